@@ -1,0 +1,168 @@
+"""Oracle time loops: forward, adjoint and gradient in FP64 (plain three-level form).
+
+Forward (box "Forward problem" with the model problem eq. model1):
+    D+^n E^{n+1} = (2 M_eps/dt^2 - A) E^n - D-^n E^{n-1} + F^n,
+    D+-^n = M_eps/dt^2 +- (M_sigma + S^n)/(2 dt),    E^0 = E^{-1} = 0.
+Traces T^n = E^n on the detector nodes for n = 1..N_t.
+
+Loss: J = 1/2 sum_n sum_detectors |T^n - E_obs^n|^2 (eq. tikhonov_functional with
+the observation indicator on the detector faces, smoothing z = 1, no
+Tikhonov term).
+
+Adjoint (box "Adjoint problem"), exact transpose of the forward recursion with
+the Lagrangian L = J + sum_n lambda^n . R^n:
+    D+^{k-1} lambda^{k-1} = -r^k + (2 M_eps/dt^2 - A^T) lambda^k - D-^{k+1} lambda^{k+1},
+    k = N_t .. 1,  lambda^{N_t} = lambda^{N_t+1} = 0,  r^k = dJ/dT^k on the detectors.
+
+Gradient (eq. gradeps and dL/deps, dL/dsigma of the optimality conditions,
+taken exactly on the discrete scheme):
+    dJ/deps_i   = sum_{n=0}^{N_t-1} [ m_i lambda^n_i . (E^{n+1} - 2E^n + E^{n-1})_i / dt^2
+                                      + sum_{K ∋ i} |K| div_K(lambda^n) (grad phi_i . E^n_i) ],
+    dJ/dsigma_i = sum_{n=0}^{N_t-1} m_i lambda^n_i . (E^{n+1} - E^{n-1})_i / (2 dt),
+on free FEM nodes (layer >= 2), zero elsewhere.  The f_1 term of eq. gradeps
+vanishes because the model problem starts from rest.
+"""
+
+from __future__ import annotations
+
+import math
+
+import numpy as np
+
+SRC_SINE1, SRC_GAUSS_SINE, SRC_DIPOLE = 1, 2, 3
+
+
+def source_time_function(src, t):
+    """P(t): eq. f (one sine period) or a Gaussian-modulated sine on [0, 2 t0]."""
+    if src.kind == SRC_SINE1:
+        return src.amp * math.sin(src.omega * t) if 0.0 < t < 2.0 * math.pi / src.omega else 0.0
+    if src.kind in (SRC_GAUSS_SINE, SRC_DIPOLE):
+        if t < 0.0 or t > 2.0 * src.t0:
+            return 0.0
+        s = (t - src.t0) / src.width
+        return src.amp * math.sin(src.omega * (t - src.t0)) * math.exp(-0.5 * s * s)
+    raise ValueError("unknown source kind")
+
+
+def forcing(d, src, n):
+    """F^n over the grid, shape (N, 3)."""
+    F = np.zeros((d.N, 3))
+    p = source_time_function(src, n * d.dt)
+    if p == 0.0:
+        return F
+    pol = np.asarray(src.pol, dtype=np.float64)
+    if src.kind == SRC_DIPOLE:
+        i, j, k = (int(v) for v in src.pos)
+        g = i + d.nvec[0] * (j + d.nvec[1] * k)
+        F[g] = p * pol
+    else:
+        if n * d.dt <= float(d.desc.t_switch):   # Gamma_{1,1}: d_n E = P on the top face
+            F += (d.face_mass[1] * p)[:, None] * pol[None, :]
+    return F
+
+
+def forward(d, src=None, n_steps=None, force=None, keep_full=False):
+    """Run the forward recursion.
+
+    ``src`` is a synth Source, or ``force`` a callable n -> F^n (N, 3).
+    Returns a dict with traces (N_t, n_det, 3), energy W^{n+1/2} (N_t,),
+    balance residual (N_t,), E on FEM nodes for levels -1..N_t (N_t+2, n_fem, 3)
+    and, if ``keep_full``, E on the whole grid for levels -1..N_t.
+    """
+    nt = int(d.desc.n_steps if n_steps is None else n_steps)
+    dt = d.dt
+    Me = d.M_eps[:, None]
+    E_prev = np.zeros((d.N, 3))
+    E_cur = np.zeros((d.N, 3))
+    traces = np.zeros((nt, len(d.det), 3))
+    energy = np.zeros(nt)
+    balance = np.zeros(nt)
+    fem_hist = np.zeros((nt + 2, d.n_fem, 3))
+    full = [E_prev.copy(), E_cur.copy()] if keep_full else None
+    w_prev = 0.0
+    for n in range(nt):
+        F = force(n) if force is not None else forcing(d, src, n)
+        C = (d.M_sig + d.damping(n))[:, None]
+        AE = d.apply_A(E_cur)
+        rhs = (2.0 * Me / dt ** 2) * E_cur - AE - (Me / dt ** 2 - C / (2 * dt)) * E_prev + F
+        E_next = rhs / (Me / dt ** 2 + C / (2 * dt))
+        traces[n] = E_next[d.det]
+        V = E_next - E_cur
+        w = 0.5 * np.sum(Me * V * V) / dt ** 2 + 0.5 * np.sum(E_next * AE)
+        D = E_next - E_prev
+        balance[n] = (w - w_prev) - 0.5 * np.sum(D * (F - C * D / (2 * dt)))
+        energy[n] = w
+        w_prev = w
+        fem_hist[n + 2] = E_next[d.fem_grid]
+        if keep_full:
+            full.append(E_next.copy())
+        E_prev, E_cur = E_cur, E_next
+    out = dict(traces=traces, energy=energy, balance=balance, fem_hist=fem_hist)
+    if keep_full:
+        out["full"] = np.stack(full)
+    return out
+
+
+def loss_and_cotangent(traces, eobs):
+    r = traces - eobs
+    return 0.5 * float(np.sum(r * r)), r
+
+
+def adjoint_gradient(d, cot, fwd, keep_lambda=False):
+    """Adjoint recursion backward in time and the eps / sigma gradient.
+
+    ``cot`` is dJ/dT with the shape of the traces; ``fwd`` the forward result
+    (its FEM history).  Returns dict(g_eps, g_sigma) over the FEM lattice, the
+    mass term in both the plain and the summed-by-parts form, and optionally
+    lambda^n (n = 0..N_t-1) on the whole grid.
+    """
+    nt = cot.shape[0]
+    dt = d.dt
+    Me = d.M_eps[:, None]
+    Eh = fwd["fem_hist"]                      # level n at index n + 1
+    m = d.m[d.fem_grid]
+    lam_next = np.zeros((d.N, 3))            # lambda^{k+1}
+    lam_cur = np.zeros((d.N, 3))             # lambda^k
+    g_mass = np.zeros(d.n_fem)
+    g_dd = np.zeros(d.n_fem)
+    g_sig = np.zeros(d.n_fem)
+    lam_f = np.zeros((nt + 1, d.n_fem, 3))   # lambda^n on FEM nodes, n = 0..N_t
+    lams = np.zeros((nt, d.N, 3)) if keep_lambda else None
+    for k in range(nt, 0, -1):
+        r = np.zeros((d.N, 3))
+        r[d.det] = cot[k - 1]
+        Cm = (d.M_sig + d.damping(k - 1))[:, None]
+        Cp = (d.M_sig + d.damping(k + 1))[:, None]
+        rhs = -r + (2.0 * Me / dt ** 2) * lam_cur - d.apply_AT(lam_cur) - (Me / dt ** 2 - Cp / (2 * dt)) * lam_next
+        lam_prev = rhs / (Me / dt ** 2 + Cm / (2 * dt))
+        n = k - 1
+        lf = lam_prev[d.fem_grid]
+        lam_f[n] = lf
+        e_p, e_c, e_m = Eh[n + 2], Eh[n + 1], Eh[n]
+        g_mass += m * np.sum(lf * (e_p - 2.0 * e_c + e_m), axis=1) / dt ** 2
+        g_sig += m * np.sum(lf * (e_p - e_m), axis=1) / (2.0 * dt)
+        # div-div term: sum_K |K| div_K(lambda^n restricted to FEM rows) (grad phi_i . E^n_i)
+        lr = lf.copy()
+        lr[~d.fem_owned] = 0.0
+        div = np.einsum("tac,tac->t", d.grad, lr[d.tets])
+        ge = np.einsum("tac,tac->ta", d.grad, e_c[d.tets])
+        g_dd += np.bincount(d.tets.ravel(), weights=((d.vol * div)[:, None] * ge).ravel(), minlength=d.n_fem)
+        if keep_lambda:
+            lams[n] = lam_prev
+        lam_next, lam_cur = lam_cur, lam_prev
+    # summation by parts of the mass term: -sum_n m (lambda^{n+1} - lambda^n) . (E^{n+1} - E^n) / dt^2
+    g_mass_sbp = np.zeros(d.n_fem)
+    for n in range(nt):
+        g_mass_sbp -= m * np.sum((lam_f[n + 1] - lam_f[n]) * (Eh[n + 2] - Eh[n + 1]), axis=1) / dt ** 2
+    free = d.fem_free
+    g_eps = np.where(free, g_mass + g_dd, 0.0)
+    g_sigma = np.where(free, g_sig, 0.0)
+    out = dict(g_eps=g_eps, g_sigma=g_sigma, g_mass=np.where(free, g_mass, 0.0),
+               g_mass_sbp=np.where(free, g_mass_sbp, 0.0), g_divdiv=np.where(free, g_dd, 0.0))
+    if keep_lambda:
+        out["lambda"] = lams
+    return out
+
+
+def energy_balance_residual(fwd):
+    return fwd["balance"]
