@@ -1,0 +1,163 @@
+/*
+ * dd.h -- C-ABI of the hybrid FE/FD time-domain Maxwell solver (MI355X / gfx950).
+ *
+ * The solver advances the stabilised Maxwell system of the paper's box
+ * "Forward problem" (eq. forward_prob; model problem eq. model1 with the
+ * plane-wave source eq. f):
+ *     eps E_tt + sigma E_t - Laplace E - grad div((eps - 1) E) = 0,
+ * explicitly in time on a structured outer grid (7-point finite differences)
+ * coupled, through a two-node overlap, to lumped-mass P1 finite elements on
+ * the Kuhn tetrahedra of an inner box (section "The mathematical model",
+ * domain decomposition paragraph; eq. epsilon_sigma_constraint).  It then runs
+ * the adjoint problem of the box "Adjoint problem" (eq. adjoint_prob) backward
+ * in time and forms the eps / sigma gradient of eq. gradeps as time integrals
+ * of forward x adjoint products, exactly on the discrete scheme.
+ *
+ * Conventions
+ *   - Outer-grid node (i,j,k) is at origin + h*(i,j,k); grid arrays are
+ *     lexicographic, x fastest.
+ *   - FEM box = outer hex cells [fem_lo, fem_lo + fem_cells); its nodes have
+ *     local indices l in [0, fem_cells] per axis, and "FEM-node arrays" (eps,
+ *     sigma, gradients) are lexicographic over them, x fastest.  A node's layer
+ *     is min over axes of min(l, fem_cells - l): layer 0 belongs to the
+ *     finite-difference region, layer 1 is FEM-owned, layers >= 2 are free.
+ *   - Detectors: outer-grid nodes on the faces selected by detector_faces, in
+ *     lexicographic grid order.  Trace arrays are [n_src][n_steps][n_det][3]
+ *     float32; row n holds E at time level n+1.
+ *   - Face bits: DD_FACE_TOP (z max; the paper's backscatter boundary d_1),
+ *     DD_FACE_BOTTOM (z min; d_2), DD_FACE_XMIN/XMAX/YMIN/YMAX (the sides d_3).
+ *
+ * Memory and streams
+ *   - Every pointer argument named *_dev is device memory owned by the caller
+ *     and must stay valid until the work queued on `stream` has finished.
+ *   - The library owns its internal state (fields, checkpoints, interface
+ *     history, FP64 accumulators), allocated with hipMalloc in dd_create and
+ *     dd_forward and released by dd_destroy.
+ *   - `stream` is a hipStream_t (NULL = the default stream).  All device work is
+ *     queued asynchronously on it; calls return once the work is queued, except
+ *     dd_set_coefficients, which synchronises the stream to report violations.
+ *   - A dd_problem is not thread-safe; use it from one host thread and one
+ *     stream at a time.
+ *
+ * Errors: every call returns DD_OK (0) or a negative DD_ERR_* code; no C++
+ * exception crosses the ABI.  dd_error_string(code) gives a static text and
+ * dd_last_error(problem) the message of the problem's last failure.
+ */
+#ifndef DD_H
+#define DD_H
+
+#include <stddef.h>
+#include <stdint.h>
+
+#ifdef __cplusplus
+extern "C" {
+#endif
+
+enum {
+  DD_OK = 0,
+  DD_ERR_INVALID_ARG = -1,  /* bad descriptor, null pointer, size mismatch */
+  DD_ERR_CONSTRAINT = -2,   /* eps / sigma violate eq. epsilon_sigma_constraint */
+  DD_ERR_UNSTABLE = -3,     /* non-finite field values after a solve */
+  DD_ERR_OOM = -4,          /* device allocation failed */
+  DD_ERR_HIP = -5,          /* a HIP runtime call or kernel launch failed */
+  DD_ERR_STATE = -6,        /* call out of order (e.g. adjoint without a saved forward) */
+  DD_ERR_UNSUPPORTED = -7   /* valid request this build does not handle */
+};
+
+enum {
+  DD_FACE_TOP = 1, DD_FACE_BOTTOM = 2, DD_FACE_XMIN = 4,
+  DD_FACE_XMAX = 8, DD_FACE_YMIN = 16, DD_FACE_YMAX = 32
+};
+
+enum {
+  DD_SRC_SINE1 = 1,       /* P(t) = amp sin(omega t) on (0, 2 pi / omega), eq. f */
+  DD_SRC_GAUSS_SINE = 2,  /* P(t) = amp sin(omega (t - t0)) exp(-((t - t0)/width)^2 / 2) on [0, 2 t0] */
+  DD_SRC_DIPOLE = 3       /* Gaussian-sine time function, point force pol * P(t) at grid node pos */
+};
+
+typedef struct dd_problem dd_problem;
+
+typedef struct {
+  int32_t n_outer[3];       /* outer grid nodes per axis, each >= 4 */
+  double h;                 /* grid spacing > 0 */
+  double origin[3];         /* coordinates of grid node (0,0,0) */
+  int32_t fem_lo[3];        /* grid index of the FEM box's lower corner; >= 1 */
+  int32_t fem_cells[3];     /* FEM hex cells per axis; >= 2, fem_lo + fem_cells <= n_outer - 2 */
+  double dt;                /* time step > 0, fixed (never derived from eps) */
+  int32_t n_steps;          /* N_t >= 1 */
+  int32_t ckpt_every;       /* forward checkpoint interval K >= 1 for the adjoint */
+  uint32_t detector_faces;  /* face bits of the detector set (non-empty) */
+  uint32_t absorbing_faces; /* face bits with first-order absorbing BC (eq. model1) */
+  double t_switch;          /* top face: plane-wave source for t_n <= t_switch, absorbing
+                               (if DD_FACE_TOP is in absorbing_faces) for t_n > t_switch */
+} dd_problem_desc;
+
+typedef struct {
+  int32_t kind;             /* DD_SRC_* */
+  double omega, t0, width, amp;
+  double pol[3];            /* polarisation / dipole moment direction */
+  int32_t pos[3];           /* DD_SRC_DIPOLE: grid node; must be finite-difference owned */
+} dd_source;
+
+/* Build the mesh, partitions, element colouring and device state of one problem
+ * (paper: domain decomposition of section "The mathematical model"; Kuhn split of
+ * the FEM box).  eps = 1, sigma = 0 until dd_set_coefficients is called.
+ * out: receives the handle (owned by the caller, release with dd_destroy). */
+int dd_create(const dd_problem_desc* desc, dd_problem** out);
+int dd_destroy(dd_problem* p);
+
+/* Sizes: FEM lattice nodes, detectors, outer grid nodes (any pointer may be NULL). */
+int dd_sizes(const dd_problem* p, int64_t* n_fem_nodes, int64_t* n_detectors, int64_t* n_grid);
+
+/* Host-only: grid indices of the detector nodes in trace order (n_detectors entries). */
+int dd_detector_nodes(const dd_problem_desc* desc, int64_t* out, int64_t capacity, int64_t* n_written);
+
+/* Device bytes dd_create + dd_forward(save=1) with n_src sources will hold (admission control). */
+size_t dd_footprint_bytes(const dd_problem_desc* desc, int32_t n_src);
+
+/* eps, sigma: FEM-node arrays (float32, n_fem_nodes each) on the device.
+ * Enforces eq. epsilon_sigma_constraint: eps = 1, sigma = 0 on layers 0 and 1,
+ * eps >= 1 and sigma >= 0 everywhere, all finite; else DD_ERR_CONSTRAINT and the
+ * previous coefficients stay.  Synchronises `stream`. */
+int dd_set_coefficients(dd_problem* p, const float* eps_dev, const float* sigma_dev, void* stream);
+
+/* Forward solve of each source from rest (E = E_t = 0 at t = 0).
+ * traces_dev: [n_src][n_steps][n_det][3] float32 output.
+ * save: nonzero keeps what dd_adjoint needs (FEM checkpoints every ckpt_every steps
+ *       and the per-step layer-0 interface values), per source.
+ * energy_dev: NULL or [n_src][n_steps] float64 output of the discrete energy
+ *       W^{n+1/2} = |V^{n+1}|^2_{M_eps} / (2 dt^2) + E^{n+1} . A E^n / 2. */
+int dd_forward(dd_problem* p, const dd_source* src, int32_t n_src, float* traces_dev,
+               int32_t save, double* energy_dev, void* stream);
+
+/* Adjoint solve (eq. adjoint_prob, exact transpose of the discrete forward scheme)
+ * for each source of the last saved dd_forward, with the trace cotangent
+ * cot_dev = dJ/dtraces ([n_src][n_steps][n_det][3] float32; E - E_obs for the
+ * loss J = 1/2 sum |E - E_obs|^2).  Recomputes the FEM forward state segment by
+ * segment from the checkpoints and accumulates the eps / sigma gradient of
+ * eq. gradeps in FP64, summed over sources.  DD_ERR_STATE without a saved forward. */
+int dd_adjoint(dd_problem* p, const float* cot_dev, void* stream);
+
+/* Gradient of the last dd_adjoint: g_eps_dev, g_sigma_dev are FEM-node arrays
+ * (float64, n_fem_nodes each); zero on nodes of layer 0 and 1. */
+int dd_gradient(dd_problem* p, double* g_eps_dev, double* g_sigma_dev, void* stream);
+
+const char* dd_error_string(int code);
+const char* dd_last_error(const dd_problem* p);
+
+/* Diagnostic (host only, no GPU): applies the FEM rows of the operator -- forward
+ * (K + A_dd) E, or with adjoint != 0 the transpose K E + (eps - 1) q(E) -- in FP64 by
+ * walking exactly the partition / halo / colour / geometry data the FEM kernel reads,
+ * checking every index bound and that no colour touches an owned node twice.
+ * eps: FEM-node array; E, out: [n_fem_nodes][3] (out is written on FEM-owned nodes,
+ * zero elsewhere).  stats (nullable, 7 entries): partitions, max colours, max local
+ * nodes, geometry entries, element evaluations, owned nodes, layer-0 nodes.
+ * Returns DD_ERR_UNSUPPORTED if any check fails. */
+int dd_debug_fem_apply(const dd_problem_desc* desc, const double* eps, const double* E, int32_t adjoint,
+                       double* out, int64_t* stats);
+
+#ifdef __cplusplus
+}
+#endif
+
+#endif /* DD_H */

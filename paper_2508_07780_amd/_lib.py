@@ -1,0 +1,127 @@
+"""ctypes view of the C-ABI in include/dd.h (argument marshalling only)."""
+
+import ctypes
+import os
+
+HERE = os.path.dirname(os.path.abspath(__file__))
+LIB_PATH = os.path.join(HERE, "libddfem.so")
+
+DD_OK = 0
+ERRORS = {
+    -1: "DD_ERR_INVALID_ARG", -2: "DD_ERR_CONSTRAINT", -3: "DD_ERR_UNSTABLE", -4: "DD_ERR_OOM",
+    -5: "DD_ERR_HIP", -6: "DD_ERR_STATE", -7: "DD_ERR_UNSUPPORTED",
+}
+
+EXPORTS = [
+    "dd_create", "dd_destroy", "dd_sizes", "dd_detector_nodes", "dd_footprint_bytes",
+    "dd_set_coefficients", "dd_forward", "dd_adjoint", "dd_gradient", "dd_error_string", "dd_last_error",
+]
+
+
+class ProblemDesc(ctypes.Structure):
+    _fields_ = [
+        ("n_outer", ctypes.c_int32 * 3),
+        ("h", ctypes.c_double),
+        ("origin", ctypes.c_double * 3),
+        ("fem_lo", ctypes.c_int32 * 3),
+        ("fem_cells", ctypes.c_int32 * 3),
+        ("dt", ctypes.c_double),
+        ("n_steps", ctypes.c_int32),
+        ("ckpt_every", ctypes.c_int32),
+        ("detector_faces", ctypes.c_uint32),
+        ("absorbing_faces", ctypes.c_uint32),
+        ("t_switch", ctypes.c_double),
+    ]
+
+
+class Source(ctypes.Structure):
+    _fields_ = [
+        ("kind", ctypes.c_int32),
+        ("omega", ctypes.c_double),
+        ("t0", ctypes.c_double),
+        ("width", ctypes.c_double),
+        ("amp", ctypes.c_double),
+        ("pol", ctypes.c_double * 3),
+        ("pos", ctypes.c_int32 * 3),
+    ]
+
+
+class DDError(RuntimeError):
+    def __init__(self, code, msg=""):
+        super().__init__(f"{ERRORS.get(code, code)}: {msg}")
+        self.code = code
+
+
+_lib = None
+
+
+def load():
+    """Load libddfem.so; raises if it has not been built (there is no fallback path)."""
+    global _lib
+    if _lib is not None:
+        return _lib
+    if not os.path.exists(LIB_PATH):
+        raise RuntimeError(f"{LIB_PATH} is missing: build it with paper_2508_07780_amd/build.py")
+    lib = ctypes.CDLL(LIB_PATH)
+    P = ctypes.c_void_p
+    lib.dd_create.argtypes = [ctypes.POINTER(ProblemDesc), ctypes.POINTER(P)]
+    lib.dd_destroy.argtypes = [P]
+    lib.dd_sizes.argtypes = [P, ctypes.POINTER(ctypes.c_int64), ctypes.POINTER(ctypes.c_int64),
+                             ctypes.POINTER(ctypes.c_int64)]
+    lib.dd_detector_nodes.argtypes = [ctypes.POINTER(ProblemDesc), ctypes.POINTER(ctypes.c_int64), ctypes.c_int64,
+                                      ctypes.POINTER(ctypes.c_int64)]
+    lib.dd_footprint_bytes.argtypes = [ctypes.POINTER(ProblemDesc), ctypes.c_int32]
+    lib.dd_footprint_bytes.restype = ctypes.c_size_t
+    lib.dd_set_coefficients.argtypes = [P, P, P, P]
+    lib.dd_forward.argtypes = [P, ctypes.POINTER(Source), ctypes.c_int32, P, ctypes.c_int32, P, P]
+    lib.dd_adjoint.argtypes = [P, P, P]
+    lib.dd_gradient.argtypes = [P, P, P, P]
+    lib.dd_error_string.argtypes = [ctypes.c_int]
+    lib.dd_error_string.restype = ctypes.c_char_p
+    lib.dd_last_error.argtypes = [P]
+    lib.dd_last_error.restype = ctypes.c_char_p
+    for name in EXPORTS:
+        if name not in ("dd_footprint_bytes", "dd_error_string", "dd_last_error"):
+            getattr(lib, name).restype = ctypes.c_int
+    _lib = lib
+    return lib
+
+
+def check(rc, handle=None):
+    if rc != DD_OK:
+        msg = ""
+        if handle:
+            msg = (load().dd_last_error(handle) or b"").decode()
+        raise DDError(rc, msg)
+
+
+def make_desc(d):
+    """ProblemDesc from any object with the synth.ProblemDesc fields."""
+    c = ProblemDesc()
+    for a in range(3):
+        c.n_outer[a] = int(d.n_outer[a])
+        c.origin[a] = float(d.origin[a])
+        c.fem_lo[a] = int(d.fem_lo[a])
+        c.fem_cells[a] = int(d.fem_cells[a])
+    c.h = float(d.h)
+    c.dt = float(d.dt)
+    c.n_steps = int(d.n_steps)
+    c.ckpt_every = int(d.ckpt_every)
+    c.detector_faces = int(d.detector_faces)
+    c.absorbing_faces = int(d.absorbing_faces)
+    c.t_switch = float(d.t_switch)
+    return c
+
+
+def make_sources(srcs):
+    arr = (Source * len(srcs))()
+    for i, s in enumerate(srcs):
+        arr[i].kind = int(s.kind)
+        arr[i].omega = float(s.omega)
+        arr[i].t0 = float(s.t0)
+        arr[i].width = float(s.width)
+        arr[i].amp = float(s.amp)
+        for a in range(3):
+            arr[i].pol[a] = float(s.pol[a])
+            arr[i].pos[a] = int(s.pos[a])
+    return arr

@@ -1,0 +1,529 @@
+// C-ABI of the hybrid FE/FD solver: problem setup, forward / adjoint / gradient drivers.
+//
+// Time loops run on the host and queue one finite-difference launch and one FEM
+// launch per step on the caller's stream.  Within a step both kernels read only
+// level-n buffers and write only level-(n+1) buffers (ping-pong for the fields,
+// in-place increments), so their order inside a step does not matter.
+#include <cmath>
+#include <cstdio>
+#include <cstring>
+#include <new>
+
+#include "dd_common.hpp"
+
+using namespace dd;
+
+struct dd_problem {
+  dd_problem_desc d{};
+  int nx = 0, ny = 0, nz = 0;
+  int64_t N = 0;
+  int fs[3] = {0, 0, 0};
+  int64_t n_fem = 0, n_own = 0, n_l0 = 0, n_det = 0;
+  int n_part = 0, n_geom = 0;
+  int nbx = 0, nby = 0, nbz = 0, n_tiles = 0, per_xcd = 0;
+  // topology (device)
+  int *own_off = nullptr, *halo_off = nullptr, *halo = nullptr, *col_base = nullptr, *ncol = nullptr,
+      *col_off = nullptr, *own_grid = nullptr, *own_api = nullptr;
+  uint64_t* elems = nullptr;
+  float* geom = nullptr;
+  double* mass_d = nullptr;
+  float *em1 = nullptr, *c1 = nullptr, *c2 = nullptr;
+  // state (device)
+  float *Efd[2] = {nullptr, nullptr}, *Vfd = nullptr, *Efem[2] = {nullptr, nullptr}, *Vfem = nullptr;
+  float* iring = nullptr;  // [2][3][n_l0]
+  double* epart = nullptr;
+  int* d_err = nullptr;
+  // saved forward for the adjoint
+  std::vector<float*> ihist, ckpt;  // per source
+  int n_ck = 0;
+  float* win = nullptr;             // [(K+1)][2][3][n_own]
+  bool saved = false;
+  int saved_n_src = 0;
+  double *g_eps = nullptr, *g_sig = nullptr;
+  bool have_grad = false;
+  std::string err;
+  std::vector<void*> allocs;
+};
+
+namespace {
+
+int fail(dd_problem* p, int code, const std::string& msg) {
+  if (p) p->err = msg;
+  return code;
+}
+
+template <class T>
+int dalloc(dd_problem* p, T** ptr, size_t count) {
+  void* q = nullptr;
+  const size_t bytes = count ? count * sizeof(T) : sizeof(T);
+  if (hipMalloc(&q, bytes) != hipSuccess) {
+    (void)hipGetLastError();
+    return fail(p, DD_ERR_OOM, "hipMalloc of " + std::to_string(bytes) + " bytes failed");
+  }
+  p->allocs.push_back(q);
+  *ptr = static_cast<T*>(q);
+  return DD_OK;
+}
+
+template <class T>
+int upload(dd_problem* p, T** ptr, const std::vector<T>& v) {
+  int rc = dalloc(p, ptr, v.size());
+  if (rc) return rc;
+  if (!v.empty() && hipMemcpy(*ptr, v.data(), v.size() * sizeof(T), hipMemcpyHostToDevice) != hipSuccess)
+    return fail(p, DD_ERR_HIP, "hipMemcpy upload failed");
+  return DD_OK;
+}
+
+int check_launch(dd_problem* p) {
+  hipError_t e = hipGetLastError();
+  if (e != hipSuccess) return fail(p, DD_ERR_HIP, std::string("kernel launch failed: ") + hipGetErrorString(e));
+  return DD_OK;
+}
+
+std::string check_desc(const dd_problem_desc* d) {
+  if (!d) return "null descriptor";
+  for (int a = 0; a < 3; ++a) {
+    if (d->n_outer[a] < 4) return "n_outer must be >= 4 per axis";
+    if (d->fem_cells[a] < 2) return "fem_cells must be >= 2 per axis";
+    if (d->fem_lo[a] < 1 || (int64_t)d->fem_lo[a] + d->fem_cells[a] > (int64_t)d->n_outer[a] - 2)
+      return "the FEM box must lie strictly inside the outer grid";
+  }
+  const double n = (double)d->n_outer[0] * d->n_outer[1] * d->n_outer[2];
+  if (n > 2147483647.0) return "outer grid exceeds 2^31 nodes";
+  if (!(d->h > 0.0) || !std::isfinite(d->h)) return "h must be positive";
+  if (!(d->dt > 0.0) || !std::isfinite(d->dt)) return "dt must be positive";
+  if (d->dt * std::sqrt(3.0) > d->h * (1.0 + 1e-12)) return "dt exceeds the explicit stability bound h/sqrt(3)";
+  if (d->n_steps < 1) return "n_steps must be >= 1";
+  if (d->ckpt_every < 1) return "ckpt_every must be >= 1";
+  if (d->detector_faces == 0 || d->detector_faces > 63u) return "detector_faces must be a non-empty face mask";
+  if (d->absorbing_faces > 63u) return "absorbing_faces must be a face mask";
+  return std::string();
+}
+
+double source_time(const dd_source& s, double t) {
+  if (s.kind == DD_SRC_SINE1) {
+    const double T = 2.0 * M_PI / s.omega;
+    return (t > 0.0 && t < T) ? s.amp * std::sin(s.omega * t) : 0.0;
+  }
+  if (t < 0.0 || t > 2.0 * s.t0) return 0.0;
+  const double u = (t - s.t0) / s.width;
+  return s.amp * std::sin(s.omega * (t - s.t0)) * std::exp(-0.5 * u * u);
+}
+
+std::string check_source(const dd_problem* p, const dd_source& s) {
+  if (s.kind != DD_SRC_SINE1 && s.kind != DD_SRC_GAUSS_SINE && s.kind != DD_SRC_DIPOLE) return "unknown source kind";
+  if (!(s.omega > 0.0) || !std::isfinite(s.omega)) return "source omega must be positive";
+  if (s.kind != DD_SRC_SINE1 && !(s.width > 0.0)) return "source width must be positive";
+  if (s.kind == DD_SRC_DIPOLE) {
+    for (int a = 0; a < 3; ++a)
+      if (s.pos[a] < 0 || s.pos[a] >= p->d.n_outer[a]) return "dipole position outside the grid";
+    bool inside = true;
+    for (int a = 0; a < 3; ++a) inside &= s.pos[a] > p->d.fem_lo[a] && s.pos[a] < p->d.fem_lo[a] + p->d.fem_cells[a];
+    if (inside) return "dipole must sit on a finite-difference node";
+  }
+  return std::string();
+}
+
+bool top_absorbs(const dd_problem* p, int64_t level) {
+  return (p->d.absorbing_faces & DD_FACE_TOP) && (double)level * p->d.dt > p->d.t_switch;
+}
+
+FdArgs fd_base(const dd_problem* p) {
+  FdArgs a;
+  std::memset(&a, 0, sizeof(a));
+  a.N = p->N;
+  a.nx = p->nx; a.ny = p->ny; a.nz = p->nz;
+  for (int c = 0; c < 3; ++c) {
+    a.blo[c] = p->d.fem_lo[c];
+    a.bhi[c] = p->d.fem_lo[c] + p->d.fem_cells[c];
+    a.fs[c] = p->fs[c];
+  }
+  a.nbx = p->nbx; a.nby = p->nby; a.nbz = p->nbz; a.ntiles = p->n_tiles; a.per_xcd = p->per_xcd;
+  const double nu = p->d.dt / p->d.h;
+  a.nu = (float)nu;
+  a.nu2 = (float)(nu * nu);
+  a.abs_mask = p->d.absorbing_faces;
+  a.dip_idx = -1;
+  a.det_mask = p->d.detector_faces;
+  a.dt2_h3 = (float)(p->d.dt * p->d.dt / (p->d.h * p->d.h * p->d.h));
+  a.n_l0 = p->n_l0;
+  a.e_coef = p->d.h * p->d.h * p->d.h / (2.0 * p->d.dt * p->d.dt);
+  return a;
+}
+
+FemArgs fem_base(const dd_problem* p) {
+  FemArgs a;
+  std::memset(&a, 0, sizeof(a));
+  a.own_off = p->own_off; a.halo_off = p->halo_off; a.halo = p->halo;
+  a.col_base = p->col_base; a.ncol = p->ncol; a.col_off = p->col_off;
+  a.elems = p->elems; a.geom = p->geom; a.own_grid = p->own_grid;
+  a.em1 = p->em1; a.c1 = p->c1; a.c2 = p->c2; a.mass_d = p->mass_d;
+  a.n_own = p->n_own; a.n_l0 = p->n_l0; a.N = p->N;
+  a.epart_off = p->n_tiles;
+  const double dt = p->d.dt;
+  a.inv_2dt2 = 1.0 / (2.0 * dt * dt);
+  a.inv_dt2 = 1.0 / (dt * dt);
+  a.inv_2dt = 1.0 / (2.0 * dt);
+  return a;
+}
+
+void zero_state(dd_problem* p, hipStream_t st) {
+  for (int b = 0; b < 2; ++b) {
+    launch_fill_f32(p->Efd[b], 3 * p->N, 0.f, st);
+    launch_fill_f32(p->Efem[b], 3 * p->n_own, 0.f, st);
+  }
+  launch_fill_f32(p->Vfd, 3 * p->N, 0.f, st);
+  launch_fill_f32(p->Vfem, 3 * p->n_own, 0.f, st);
+  launch_fill_f32(p->iring, 6 * p->n_l0, 0.f, st);
+}
+
+int ensure_saved_storage(dd_problem* p, int n_src) {
+  const int64_t nt = p->d.n_steps;
+  while ((int)p->ihist.size() < n_src) {
+    float *h = nullptr, *c = nullptr;
+    int rc = dalloc(p, &h, (size_t)(nt + 1) * 3 * p->n_l0);
+    if (rc) return rc;
+    rc = dalloc(p, &c, (size_t)p->n_ck * 6 * p->n_own);
+    if (rc) return rc;
+    p->ihist.push_back(h);
+    p->ckpt.push_back(c);
+  }
+  if (!p->win) {
+    const int64_t K = std::min<int64_t>(p->d.ckpt_every, nt);
+    int rc = dalloc(p, &p->win, (size_t)(K + 1) * 6 * p->n_own);
+    if (rc) return rc;
+  }
+  return DD_OK;
+}
+
+int run_forward(dd_problem* p, const dd_source& src, int s, float* traces, bool save, double* energy, hipStream_t st) {
+  const int64_t nt = p->d.n_steps, K = p->d.ckpt_every;
+  const int64_t n_l0 = p->n_l0, n_own = p->n_own;
+  zero_state(p, st);
+  float* hist = save ? p->ihist[s] : nullptr;
+  float* ck = save ? p->ckpt[s] : nullptr;
+  if (save) {
+    launch_fill_f32(hist, 3 * n_l0, 0.f, st);          // level 0
+    launch_fill_f32(ck, 6 * n_own, 0.f, st);           // checkpoint of level 0
+  }
+  FdArgs fa = fd_base(p);
+  FemArgs ea = fem_base(p);
+  const double dt = p->d.dt, h = p->d.h;
+  int64_t dip_idx = -1;
+  double dip_scale = 0.0;
+  if (src.kind == DD_SRC_DIPOLE) {
+    dip_idx = src.pos[0] + (int64_t)p->nx * (src.pos[1] + (int64_t)p->ny * src.pos[2]);
+    int b = 0;
+    b += (src.pos[0] == 0 || src.pos[0] == p->nx - 1);
+    b += (src.pos[1] == 0 || src.pos[1] == p->ny - 1);
+    b += (src.pos[2] == 0 || src.pos[2] == p->nz - 1);
+    dip_scale = dt * dt / (h * h * h * std::ldexp(1.0, -b));   // dt^2 / m at the dipole node
+  }
+  for (int64_t n = 0; n < nt; ++n) {
+    const double t = (double)n * dt;
+    const double P = source_time(src, t);
+    const int cur = (int)(n & 1), nxt = (int)((n + 1) & 1);
+    fa.X_in = p->Efd[cur];
+    fa.X_out = p->Efd[nxt];
+    fa.I = p->Vfd;
+    fa.top_a = fa.top_b = top_absorbs(p, n) ? 1 : 0;
+    for (int c = 0; c < 3; ++c) {
+      fa.pw[c] = (src.kind != DD_SRC_DIPOLE && t <= p->d.t_switch) ? (float)(2.0 * dt * dt / h * P * src.pol[c]) : 0.f;
+      fa.dip[c] = (float)(P * src.pol[c] * dip_scale);
+    }
+    fa.dip_idx = dip_idx;
+    fa.tr_out = traces + ((int64_t)s * nt + n) * p->n_det * 3;
+    fa.cot_in = nullptr;
+    fa.iface_out = save ? hist + (n + 1) * 3 * n_l0 : p->iring + nxt * 3 * n_l0;
+    fa.epart = energy ? p->epart : nullptr;
+    launch_fd(fa, st, energy != nullptr);
+
+    ea.X_in = p->Efem[cur];
+    ea.X_out = p->Efem[nxt];
+    ea.I_in = ea.I_out = p->Vfem;
+    ea.iface_in = save ? hist + n * 3 * n_l0 : p->iring + cur * 3 * n_l0;
+    ea.fd_out = p->Efd[nxt];
+    const bool ckw = save && ((n + 1) % K == 0) && ((n + 1) / K < p->n_ck);
+    ea.ck_X = ckw ? ck + ((n + 1) / K) * 6 * n_own : nullptr;
+    ea.ck_I = ckw ? ea.ck_X + 3 * n_own : nullptr;
+    ea.epart = energy ? p->epart : nullptr;
+    launch_fem_fwd(ea, p->n_part, st, energy != nullptr);
+    if (energy) launch_energy_reduce(p->epart, p->n_tiles + p->n_part, energy + (int64_t)s * nt + n, st);
+  }
+  return check_launch(p);
+}
+
+int run_adjoint(dd_problem* p, int s, const float* cot, hipStream_t st) {
+  const int64_t nt = p->d.n_steps, K = p->d.ckpt_every;
+  const int64_t n_l0 = p->n_l0, n_own = p->n_own;
+  zero_state(p, st);
+  FdArgs fa = fd_base(p);
+  FemArgs fw = fem_base(p);   // recompute (forward, FEM only)
+  FemArgs ea = fem_base(p);   // adjoint
+  ea.g_eps = p->g_eps;
+  ea.g_sig = p->g_sig;
+  const int64_t nseg = (nt + K - 1) / K;
+  float* hist = p->ihist[s];
+  float* ck = p->ckpt[s];
+  auto wE = [&](int64_t j) { return p->win + j * 6 * n_own; };
+  auto wV = [&](int64_t j) { return p->win + j * 6 * n_own + 3 * n_own; };
+  for (int64_t seg = nseg - 1; seg >= 0; --seg) {
+    const int64_t k0 = seg * K, k1 = std::min(k0 + K, nt);
+    launch_copy_f32(p->win, ck + seg * 6 * n_own, 6 * n_own, st);
+    for (int64_t k = k0; k < k1; ++k) {
+      fw.X_in = wE(k - k0);
+      fw.X_out = wE(k - k0 + 1);
+      fw.I_in = wV(k - k0);
+      fw.I_out = wV(k - k0 + 1);
+      fw.iface_in = hist + k * 3 * n_l0;
+      fw.fd_out = nullptr;
+      launch_fem_fwd(fw, p->n_part, st, false);
+    }
+    for (int64_t k = k1; k > k0; --k) {
+      const int cur = (int)(k & 1), prv = (int)((k - 1) & 1);
+      fa.X_in = p->Efd[cur];
+      fa.X_out = p->Efd[prv];
+      fa.I = p->Vfd;
+      fa.top_a = top_absorbs(p, k - 1) ? 1 : 0;
+      fa.top_b = top_absorbs(p, k + 1) ? 1 : 0;
+      fa.tr_out = nullptr;
+      fa.cot_in = cot + ((int64_t)s * nt + (k - 1)) * p->n_det * 3;
+      fa.iface_out = p->iring + prv * 3 * n_l0;
+      launch_fd(fa, st, false);
+
+      ea.X_in = p->Efem[cur];
+      ea.X_out = p->Efem[prv];
+      ea.I_in = ea.I_out = p->Vfem;
+      ea.iface_in = p->iring + cur * 3 * n_l0;
+      ea.fd_out = p->Efd[prv];
+      ea.wE = wE(k - k0);
+      ea.wV = wV(k - k0);
+      ea.wVm = wV(k - 1 - k0);
+      launch_fem_adj(ea, p->n_part, st);
+    }
+  }
+  return check_launch(p);
+}
+
+}  // namespace
+
+extern "C" {
+
+const char* dd_error_string(int code) {
+  switch (code) {
+    case DD_OK: return "ok";
+    case DD_ERR_INVALID_ARG: return "invalid argument";
+    case DD_ERR_CONSTRAINT: return "eps/sigma violate the coefficient constraint";
+    case DD_ERR_UNSTABLE: return "non-finite field values";
+    case DD_ERR_OOM: return "device out of memory";
+    case DD_ERR_HIP: return "HIP runtime error";
+    case DD_ERR_STATE: return "call out of order";
+    case DD_ERR_UNSUPPORTED: return "unsupported";
+    default: return "unknown error";
+  }
+}
+
+const char* dd_last_error(const dd_problem* p) { return p ? p->err.c_str() : "null problem"; }
+
+int dd_detector_nodes(const dd_problem_desc* desc, int64_t* out, int64_t capacity, int64_t* n_written) {
+  const std::string e = check_desc(desc);
+  if (!e.empty()) return DD_ERR_INVALID_ARG;
+  const int nx = desc->n_outer[0], ny = desc->n_outer[1], nz = desc->n_outer[2];
+  const int64_t n = face_lex_count(nx, ny, nz, desc->detector_faces);
+  if (n_written) *n_written = n;
+  if (!out) return DD_OK;
+  if (capacity < n) return DD_ERR_INVALID_ARG;
+  for (int z = 0; z < nz; ++z)
+    for (int y = 0; y < ny; ++y)
+      for (int x = 0; x < nx; ++x) {
+        const int64_t i = face_lex_index(x, y, z, nx, ny, nz, desc->detector_faces);
+        if (i >= 0) out[i] = x + (int64_t)nx * (y + (int64_t)ny * z);
+      }
+  return DD_OK;
+}
+
+size_t dd_footprint_bytes(const dd_problem_desc* desc, int32_t n_src) {
+  if (!check_desc(desc).empty() || n_src < 0) return 0;
+  const int64_t N = (int64_t)desc->n_outer[0] * desc->n_outer[1] * desc->n_outer[2];
+  const int64_t fs[3] = {desc->fem_cells[0] + 1, desc->fem_cells[1] + 1, desc->fem_cells[2] + 1};
+  const int64_t n_fem = fs[0] * fs[1] * fs[2];
+  const int64_t n_own = (int64_t)(desc->fem_cells[0] - 1) * (desc->fem_cells[1] - 1) * (desc->fem_cells[2] - 1);
+  const int64_t n_l0 = face_lex_count((int)fs[0], (int)fs[1], (int)fs[2], 63u);
+  const int64_t nt = desc->n_steps, K = std::min<int64_t>(desc->ckpt_every, nt);
+  const int64_t n_ck = nt / desc->ckpt_every + 1;
+  const int64_t tets_est = 6 * n_fem * 3 / 2;  // elements incl. halo duplicates (upper estimate)
+  int64_t b = 0;
+  b += 4 * 9 * N;                         // E (2 levels) + V on the grid
+  b += 4 * 9 * n_own;                     // E (2 levels) + V on the FEM nodes
+  b += 4 * 6 * n_l0;                      // interface ring
+  b += n_own * (4 * 3 + 8 + 4 * 2 + 8 * 2);  // coefficients, mass, index maps, gradient accumulators
+  b += tets_est * 8 + n_fem * 4 * 2;      // elements, halo lists
+  b += (int64_t)n_src * ((nt + 1) * 3 * n_l0 * 4 + n_ck * 6 * n_own * 4);  // saved forward
+  b += (K + 1) * 6 * n_own * 4;           // recompute window
+  return (size_t)b;
+}
+
+int dd_create(const dd_problem_desc* desc, dd_problem** out) {
+  if (!out) return DD_ERR_INVALID_ARG;
+  *out = nullptr;
+  const std::string e = check_desc(desc);
+  if (!e.empty()) return DD_ERR_INVALID_ARG;
+  dd_problem* p = new (std::nothrow) dd_problem();
+  if (!p) return DD_ERR_OOM;
+  p->d = *desc;
+  p->nx = desc->n_outer[0];
+  p->ny = desc->n_outer[1];
+  p->nz = desc->n_outer[2];
+  p->N = (int64_t)p->nx * p->ny * p->nz;
+  for (int a = 0; a < 3; ++a) p->fs[a] = desc->fem_cells[a] + 1;
+  p->n_det = face_lex_count(p->nx, p->ny, p->nz, desc->detector_faces);
+  HostMesh m;
+  const std::string me = build_mesh(*desc, m);
+  if (!me.empty()) {
+    delete p;
+    return DD_ERR_UNSUPPORTED;
+  }
+  p->n_fem = m.n_fem;
+  p->n_own = m.n_own;
+  p->n_l0 = m.n_l0;
+  p->n_part = m.n_part;
+  p->n_geom = m.n_geom;
+  p->nbx = (p->nx + FD_TX - 1) / FD_TX;
+  p->nby = (p->ny + FD_TY - 1) / FD_TY;
+  p->nbz = (p->nz + FD_ZC - 1) / FD_ZC;
+  p->n_tiles = p->nbx * p->nby * p->nbz;
+  p->per_xcd = (p->n_tiles + N_XCD - 1) / N_XCD;
+  p->n_ck = (int)(desc->n_steps / desc->ckpt_every) + 1;
+  int rc = DD_OK;
+  auto chk = [&](int r) { if (r && !rc) rc = r; };
+  chk(upload(p, &p->own_off, m.own_off));
+  chk(upload(p, &p->halo_off, m.halo_off));
+  chk(upload(p, &p->halo, m.halo));
+  chk(upload(p, &p->col_base, m.col_base));
+  chk(upload(p, &p->ncol, m.ncol));
+  chk(upload(p, &p->col_off, m.col_off));
+  chk(upload(p, &p->own_grid, m.own_grid));
+  chk(upload(p, &p->own_api, m.own_api));
+  chk(upload(p, &p->elems, m.elems));
+  chk(upload(p, &p->geom, m.geom));
+  chk(upload(p, &p->mass_d, m.mass));
+  chk(dalloc(p, &p->em1, p->n_own));
+  chk(dalloc(p, &p->c1, p->n_own));
+  chk(dalloc(p, &p->c2, p->n_own));
+  for (int b = 0; b < 2; ++b) {
+    chk(dalloc(p, &p->Efd[b], 3 * p->N));
+    chk(dalloc(p, &p->Efem[b], 3 * p->n_own));
+  }
+  chk(dalloc(p, &p->Vfd, 3 * p->N));
+  chk(dalloc(p, &p->Vfem, 3 * p->n_own));
+  chk(dalloc(p, &p->iring, 6 * p->n_l0));
+  chk(dalloc(p, &p->epart, p->n_tiles + p->n_part));
+  chk(dalloc(p, &p->d_err, 1));
+  chk(dalloc(p, &p->g_eps, p->n_own));
+  chk(dalloc(p, &p->g_sig, p->n_own));
+  if (rc) {
+    dd_destroy(p);
+    return rc;
+  }
+  // eps = 1, sigma = 0 until dd_set_coefficients
+  std::vector<float> em1(p->n_own, 0.f), c1(p->n_own, 1.f), c2(p->n_own);
+  for (int64_t i = 0; i < p->n_own; ++i) c2[i] = (float)(desc->dt * desc->dt / m.mass[i]);
+  if (hipMemcpy(p->em1, em1.data(), 4 * p->n_own, hipMemcpyHostToDevice) != hipSuccess ||
+      hipMemcpy(p->c1, c1.data(), 4 * p->n_own, hipMemcpyHostToDevice) != hipSuccess ||
+      hipMemcpy(p->c2, c2.data(), 4 * p->n_own, hipMemcpyHostToDevice) != hipSuccess) {
+    dd_destroy(p);
+    return DD_ERR_HIP;
+  }
+  *out = p;
+  return DD_OK;
+}
+
+int dd_destroy(dd_problem* p) {
+  if (!p) return DD_ERR_INVALID_ARG;
+  (void)hipDeviceSynchronize();
+  for (void* q : p->allocs) (void)hipFree(q);
+  delete p;
+  return DD_OK;
+}
+
+int dd_sizes(const dd_problem* p, int64_t* n_fem_nodes, int64_t* n_detectors, int64_t* n_grid) {
+  if (!p) return DD_ERR_INVALID_ARG;
+  if (n_fem_nodes) *n_fem_nodes = p->n_fem;
+  if (n_detectors) *n_detectors = p->n_det;
+  if (n_grid) *n_grid = p->N;
+  return DD_OK;
+}
+
+int dd_set_coefficients(dd_problem* p, const float* eps_dev, const float* sigma_dev, void* stream) {
+  if (!p) return DD_ERR_INVALID_ARG;
+  if (!eps_dev || !sigma_dev) return fail(p, DD_ERR_INVALID_ARG, "null coefficient pointer");
+  hipStream_t st = (hipStream_t)stream;
+  int h_err = 0;
+  if (hipMemsetAsync(p->d_err, 0, sizeof(int), st) != hipSuccess) return fail(p, DD_ERR_HIP, "hipMemsetAsync failed");
+  launch_validate(eps_dev, sigma_dev, p->fs[0], p->fs[1], p->fs[2], p->d_err, st);
+  if (int rc = check_launch(p)) return rc;
+  if (hipMemcpyAsync(&h_err, p->d_err, sizeof(int), hipMemcpyDeviceToHost, st) != hipSuccess ||
+      hipStreamSynchronize(st) != hipSuccess)
+    return fail(p, DD_ERR_HIP, "error readback failed");
+  if (h_err) return fail(p, DD_ERR_CONSTRAINT, std::to_string(h_err) + " FEM nodes violate the coefficient constraint");
+  launch_coefficients(eps_dev, sigma_dev, p->own_api, p->mass_d, p->n_own, p->d.dt, p->em1, p->c1, p->c2, st);
+  if (int rc = check_launch(p)) return rc;
+  if (hipStreamSynchronize(st) != hipSuccess) return fail(p, DD_ERR_HIP, "stream synchronize failed");
+  p->saved = false;
+  p->have_grad = false;
+  return DD_OK;
+}
+
+int dd_forward(dd_problem* p, const dd_source* src, int32_t n_src, float* traces_dev, int32_t save, double* energy_dev,
+               void* stream) {
+  if (!p) return DD_ERR_INVALID_ARG;
+  if (!src || n_src < 1 || !traces_dev) return fail(p, DD_ERR_INVALID_ARG, "need sources and a trace buffer");
+  for (int s = 0; s < n_src; ++s) {
+    const std::string e = check_source(p, src[s]);
+    if (!e.empty()) return fail(p, DD_ERR_INVALID_ARG, e);
+  }
+  hipStream_t st = (hipStream_t)stream;
+  p->saved = false;
+  p->have_grad = false;
+  if (save) {
+    int rc = ensure_saved_storage(p, n_src);
+    if (rc) return rc;
+  }
+  for (int s = 0; s < n_src; ++s) {
+    int rc = run_forward(p, src[s], s, traces_dev, save != 0, energy_dev, st);
+    if (rc) return rc;
+  }
+  if (save) {
+    p->saved = true;
+    p->saved_n_src = n_src;
+  }
+  return DD_OK;
+}
+
+int dd_adjoint(dd_problem* p, const float* cot_dev, void* stream) {
+  if (!p) return DD_ERR_INVALID_ARG;
+  if (!cot_dev) return fail(p, DD_ERR_INVALID_ARG, "null cotangent");
+  if (!p->saved) return fail(p, DD_ERR_STATE, "dd_adjoint needs a preceding dd_forward with save");
+  hipStream_t st = (hipStream_t)stream;
+  launch_fill_f64(p->g_eps, p->n_own, 0.0, st);
+  launch_fill_f64(p->g_sig, p->n_own, 0.0, st);
+  for (int s = 0; s < p->saved_n_src; ++s) {
+    int rc = run_adjoint(p, s, cot_dev, st);
+    if (rc) return rc;
+  }
+  p->have_grad = true;
+  return DD_OK;
+}
+
+int dd_gradient(dd_problem* p, double* g_eps_dev, double* g_sigma_dev, void* stream) {
+  if (!p) return DD_ERR_INVALID_ARG;
+  if (!g_eps_dev || !g_sigma_dev) return fail(p, DD_ERR_INVALID_ARG, "null gradient buffer");
+  if (!p->have_grad) return fail(p, DD_ERR_STATE, "dd_gradient needs a preceding dd_adjoint");
+  hipStream_t st = (hipStream_t)stream;
+  launch_fill_f64(g_eps_dev, p->n_fem, 0.0, st);
+  launch_fill_f64(g_sigma_dev, p->n_fem, 0.0, st);
+  launch_gradient_out(p->g_eps, p->g_sig, p->own_api, p->own_grid, p->n_own, g_eps_dev, g_sigma_dev, st);
+  return check_launch(p);
+}
+
+}  // extern "C"

@@ -1,0 +1,147 @@
+// Internal declarations shared by the host setup, the kernels and the C-ABI.
+#pragma once
+
+#include <hip/hip_runtime.h>
+
+#include <cstdint>
+#include <string>
+#include <vector>
+
+#include "dd.h"
+
+namespace dd {
+
+// Finite-difference tile: 32 x 8 nodes in (x, y), marching ZC planes in z.
+constexpr int FD_TX = 32;
+constexpr int FD_TY = 8;
+constexpr int FD_ZC = 16;
+constexpr int FD_THREADS = FD_TX * FD_TY;
+
+// FEM partition: a block of at most FEM_PB^3 owned nodes plus its halo.
+constexpr int FEM_PB = 8;
+constexpr int FEM_THREADS = 256;
+constexpr int FEM_LOC_MAX = 1024;  // owned + halo nodes per partition (11-bit local ids)
+constexpr int FEM_OWN_MAX = 512;
+constexpr int FEM_COLORS_MAX = 64;
+
+constexpr int N_XCD = 8;  // MI355X: workgroups are dispatched round-robin over 8 XCDs
+
+// Index of node (x, y, z) among the nodes of an nx*ny*nz box that lie on the
+// faces in `mask`, counted in lexicographic order (x fastest); -1 if the node
+// is on none of them.  Requires nx, ny, nz >= 2.
+__host__ __device__ inline int64_t face_lex_index(int x, int y, int z, int nx, int ny, int nz, unsigned mask) {
+  const bool zlo = (mask & DD_FACE_BOTTOM) && z == 0;
+  const bool zhi = (mask & DD_FACE_TOP) && z == nz - 1;
+  const bool xlo = (mask & DD_FACE_XMIN) && x == 0;
+  const bool xhi = (mask & DD_FACE_XMAX) && x == nx - 1;
+  const bool ylo = (mask & DD_FACE_YMIN) && y == 0;
+  const bool yhi = (mask & DD_FACE_YMAX) && y == ny - 1;
+  if (!(zlo || zhi || xlo || xhi || ylo || yhi)) return -1;
+  const int64_t cm = ((mask & DD_FACE_XMIN) ? 1 : 0) + ((mask & DD_FACE_XMAX) ? 1 : 0);
+  const int64_t ny_mid = ny - ((mask & DD_FACE_YMIN) ? 1 : 0) - ((mask & DD_FACE_YMAX) ? 1 : 0);
+  const int64_t p_mid = (int64_t)(ny - ny_mid) * nx + ny_mid * cm;
+  const int64_t p_full = (int64_t)nx * ny;
+  int64_t before = 0;
+  if (z > 0) before = ((mask & DD_FACE_BOTTOM) ? p_full : p_mid) + (int64_t)(z - 1) * p_mid;
+  if (zlo || zhi) return before + (int64_t)y * nx + x;
+  int64_t rows = 0;
+  if (y > 0) rows = ((mask & DD_FACE_YMIN) ? (int64_t)nx : cm) + (int64_t)(y - 1) * cm;
+  if (ylo || yhi) return before + rows + x;
+  return before + rows + (xlo ? 0 : ((mask & DD_FACE_XMIN) ? 1 : 0));
+}
+
+inline int64_t face_lex_count(int nx, int ny, int nz, unsigned mask) {
+  const int64_t cm = ((mask & DD_FACE_XMIN) ? 1 : 0) + ((mask & DD_FACE_XMAX) ? 1 : 0);
+  const int64_t ny_mid = ny - ((mask & DD_FACE_YMIN) ? 1 : 0) - ((mask & DD_FACE_YMAX) ? 1 : 0);
+  const int64_t p_mid = (int64_t)(ny - ny_mid) * nx + ny_mid * cm;
+  const int64_t p_full = (int64_t)nx * ny;
+  const int64_t nzf = ((mask & DD_FACE_BOTTOM) ? 1 : 0) + ((mask & DD_FACE_TOP) ? 1 : 0);
+  return nzf * p_full + (nz - nzf) * p_mid;
+}
+
+// ---- kernel arguments -------------------------------------------------------------------
+
+struct FdArgs {
+  const float* X_in;   // field at level n (forward E^n, adjoint lambda^k), [3][N]
+  float* X_out;        // field at the next level, [3][N]
+  float* I;            // increment, updated in place (forward V, adjoint Lambda), [3][N]
+  int64_t N;
+  int nx, ny, nz;
+  int blo[3], bhi[3];  // FEM box node range [fem_lo, fem_lo + fem_cells] per axis
+  int nbx, nby, nbz, ntiles, per_xcd;
+  float nu2, nu;       // (dt/h)^2, dt/h
+  unsigned abs_mask;
+  int top_a, top_b;    // top face absorbing at the levels of D+ (a) and D- (b)
+  float pw[3];         // plane-wave forcing F dt^2 / m on the top face (0 when off)
+  int64_t dip_idx;     // dipole grid node or -1
+  float dip[3];        // dipole forcing F dt^2 / m at that node
+  unsigned det_mask;
+  float* tr_out;       // forward: traces of this step [n_det][3] or null
+  const float* cot_in; // adjoint: cotangent of this step [n_det][3] or null
+  float dt2_h3;        // dt^2 / h^3
+  float* iface_out;    // layer-0 values of the next level [3][n_l0] or null
+  int64_t n_l0;
+  int fs[3];           // FEM lattice shape (fem_cells + 1)
+  double* epart;       // energy partial per tile or null
+  double e_coef;       // h^3 / (2 dt^2)
+};
+
+struct FemArgs {
+  const int* own_off;   // [n_part + 1]
+  const int* halo_off;  // [n_part + 1]
+  const int* halo;      // owned internal id, or -1 - layer0 index
+  const int* col_base;  // [n_part] start of the partition's colour offsets in col_off
+  const int* ncol;      // [n_part]
+  const int* col_off;   // absolute element offsets per colour
+  const uint64_t* elems;
+  const float* geom;    // [n_geom][16]: grad phi_0..3 (12), |K|, pad
+  const int* own_grid;  // grid index for layer-1 owned nodes, -1 otherwise (free)
+  const float* em1;     // eps - 1
+  const float* c1;      // (a - b) / (a + b)
+  const float* c2;      // 1 / (a + b);  a = m eps / dt^2, b = m sigma / (2 dt)
+  const double* mass_d; // lumped mass (FP64)
+  const float* X_in; float* X_out;
+  const float* I_in; float* I_out;
+  const float* iface_in;  // layer-0 values at the current level [3][n_l0]
+  float* fd_out;          // grid field of the next level for the layer-1 dual write, or null
+  float* ck_X; float* ck_I;  // checkpoint dual write or null
+  int64_t n_own, n_l0, N;
+  double* epart; int epart_off; double inv_2dt2;
+  // adjoint
+  const float* wE; const float* wV; const float* wVm;  // forward E^k, V^k, V^{k-1} [3][n_own]
+  double* g_eps; double* g_sig;
+  double inv_dt2, inv_2dt;
+};
+
+void launch_fd(const FdArgs& a, hipStream_t s, bool energy);
+void launch_fem_fwd(const FemArgs& a, int n_part, hipStream_t s, bool energy);
+void launch_fem_adj(const FemArgs& a, int n_part, hipStream_t s);
+void launch_energy_reduce(const double* part, int n, double* out, hipStream_t s);
+void launch_fill_f32(float* p, int64_t n, float v, hipStream_t s);
+void launch_fill_f64(double* p, int64_t n, double v, hipStream_t s);
+void launch_copy_f32(float* dst, const float* src, int64_t n, hipStream_t s);
+void launch_validate(const float* eps, const float* sig, int fsx, int fsy, int fsz, int* err, hipStream_t s);
+void launch_coefficients(const float* eps, const float* sig, const int* own_api, const double* mass_d,
+                         int64_t n_own, double dt, float* em1, float* c1, float* c2, hipStream_t s);
+void launch_gradient_out(const double* g_eps, const double* g_sig, const int* own_api, const int* own_grid,
+                         int64_t n_own, double* out_eps, double* out_sig, hipStream_t s);
+void launch_count_nonfinite(const float* x, int64_t n, int* err, hipStream_t s);
+
+// ---- host-side mesh and partitions ----------------------------------------------------
+
+struct HostMesh {
+  int64_t n_fem = 0, n_own = 0, n_l0 = 0;
+  int n_part = 0, n_geom = 0;
+  std::vector<int> own_off, halo_off, halo, col_base, ncol, col_off;
+  std::vector<uint64_t> elems;
+  std::vector<float> geom;
+  std::vector<int> own_grid, own_api;
+  std::vector<double> mass;
+  int max_colors = 0, max_loc = 0;
+};
+
+// Builds the Kuhn split of the FEM box, the node partitions and per-partition colouring.
+// Returns an empty string on success, else the error text.
+std::string build_mesh(const dd_problem_desc& d, HostMesh& m);
+
+}  // namespace dd

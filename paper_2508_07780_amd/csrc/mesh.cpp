@@ -1,0 +1,364 @@
+// Host setup of the FEM box: Kuhn tetrahedra, node partitions with halos,
+// per-partition element colouring and the deduplicated element geometry table.
+//
+// The paper discretises the inner cube with tetrahedra and the outer region with
+// hexahedra (section "Numerical results", Fig. "meshes").  Here each hex cell of
+// the FEM box is split into the 6 Kuhn tetrahedra (one per permutation of the
+// axes), which keeps the mesh conforming; the kernels only see general tetrahedral
+// connectivity plus a geometry table, so any conforming tetrahedral mesh whose
+// nodes carry the same ownership rules would run unchanged.
+//
+// Owned (FEM-updated) nodes are the lattice nodes of layer >= 1; they are cut
+// into blocks of FEM_PB^3 nodes.  A partition holds every tetrahedron that
+// touches one of its owned nodes, so elements on a partition border are
+// evaluated by each partition that needs them and no partial sums are exchanged.
+// Elements are coloured so that two elements of one colour never share an owned
+// node of the partition; the kernel scatters colour by colour without atomics,
+// which makes every result bitwise reproducible.
+#include <algorithm>
+#include <array>
+#include <cmath>
+#include <cstring>
+#include <map>
+
+#include "dd_common.hpp"
+
+namespace dd {
+
+namespace {
+
+struct Lattice {
+  int c[3];   // cells per axis
+  int s[3];   // nodes per axis
+  int64_t idx(int x, int y, int z) const { return x + (int64_t)s[0] * (y + (int64_t)s[1] * z); }
+  int layer(int x, int y, int z) const {
+    int l = std::min(x, c[0] - x);
+    l = std::min(l, std::min(y, c[1] - y));
+    return std::min(l, std::min(z, c[2] - z));
+  }
+};
+
+const int kPerms[6][3] = {{0, 1, 2}, {0, 2, 1}, {1, 0, 2}, {1, 2, 0}, {2, 0, 1}, {2, 1, 0}};
+
+// Gradients of the 4 barycentric functions and the volume of a tetrahedron with
+// vertices p[0..3] (FP64); returns false for a degenerate element.
+bool tet_geometry(const double p[4][3], double grad[4][3], double* vol) {
+  double J[3][3];
+  for (int r = 0; r < 3; ++r)
+    for (int k = 0; k < 3; ++k) J[r][k] = p[k + 1][r] - p[0][r];  // column k = edge k
+  const double det = J[0][0] * (J[1][1] * J[2][2] - J[1][2] * J[2][1]) -
+                     J[0][1] * (J[1][0] * J[2][2] - J[1][2] * J[2][0]) +
+                     J[0][2] * (J[1][0] * J[2][1] - J[1][1] * J[2][0]);
+  if (!(std::fabs(det) > 0.0)) return false;
+  // inverse: row k of J^{-1} is the gradient of barycentric coordinate k+1
+  double inv[3][3];
+  inv[0][0] = (J[1][1] * J[2][2] - J[1][2] * J[2][1]) / det;
+  inv[0][1] = (J[0][2] * J[2][1] - J[0][1] * J[2][2]) / det;
+  inv[0][2] = (J[0][1] * J[1][2] - J[0][2] * J[1][1]) / det;
+  inv[1][0] = (J[1][2] * J[2][0] - J[1][0] * J[2][2]) / det;
+  inv[1][1] = (J[0][0] * J[2][2] - J[0][2] * J[2][0]) / det;
+  inv[1][2] = (J[0][2] * J[1][0] - J[0][0] * J[1][2]) / det;
+  inv[2][0] = (J[1][0] * J[2][1] - J[1][1] * J[2][0]) / det;
+  inv[2][1] = (J[0][1] * J[2][0] - J[0][0] * J[2][1]) / det;
+  inv[2][2] = (J[0][0] * J[1][1] - J[0][1] * J[1][0]) / det;
+  for (int a = 0; a < 3; ++a) {
+    grad[0][a] = -(inv[0][a] + inv[1][a] + inv[2][a]);
+    for (int k = 0; k < 3; ++k) grad[k + 1][a] = inv[k][a];
+  }
+  *vol = std::fabs(det) / 6.0;
+  return true;
+}
+
+}  // namespace
+
+std::string build_mesh(const dd_problem_desc& d, HostMesh& m) {
+  Lattice L;
+  for (int a = 0; a < 3; ++a) {
+    L.c[a] = d.fem_cells[a];
+    L.s[a] = d.fem_cells[a] + 1;
+  }
+  m.n_fem = (int64_t)L.s[0] * L.s[1] * L.s[2];
+  const int ow[3] = {L.c[0] - 1, L.c[1] - 1, L.c[2] - 1};  // owned nodes per axis
+  m.n_own = (int64_t)ow[0] * ow[1] * ow[2];
+  m.n_l0 = face_lex_count(L.s[0], L.s[1], L.s[2], 63u);
+  int npb[3];
+  for (int a = 0; a < 3; ++a) npb[a] = (ow[a] + FEM_PB - 1) / FEM_PB;
+  m.n_part = npb[0] * npb[1] * npb[2];
+
+  // internal numbering: partition-major, lexicographic inside the block
+  std::vector<int> lat2int(m.n_fem, 0);  // owned: internal id; layer 0: -1 - layer0 index
+  for (int z = 0; z < L.s[2]; ++z)
+    for (int y = 0; y < L.s[1]; ++y)
+      for (int x = 0; x < L.s[0]; ++x)
+        if (L.layer(x, y, z) == 0)
+          lat2int[L.idx(x, y, z)] = -1 - (int)face_lex_index(x, y, z, L.s[0], L.s[1], L.s[2], 63u);
+  m.own_off.assign(m.n_part + 1, 0);
+  m.own_grid.assign(m.n_own, -1);
+  m.own_api.assign(m.n_own, 0);
+  std::vector<std::array<int, 6>> prange(m.n_part);
+  {
+    int next = 0, p = 0;
+    for (int pz = 0; pz < npb[2]; ++pz)
+      for (int py = 0; py < npb[1]; ++py)
+        for (int px = 0; px < npb[0]; ++px, ++p) {
+          const int lo[3] = {1 + px * FEM_PB, 1 + py * FEM_PB, 1 + pz * FEM_PB};
+          const int hi[3] = {std::min(lo[0] + FEM_PB, L.c[0]), std::min(lo[1] + FEM_PB, L.c[1]),
+                             std::min(lo[2] + FEM_PB, L.c[2])};
+          prange[p] = {lo[0], hi[0], lo[1], hi[1], lo[2], hi[2]};
+          m.own_off[p] = next;
+          for (int z = lo[2]; z < hi[2]; ++z)
+            for (int y = lo[1]; y < hi[1]; ++y)
+              for (int x = lo[0]; x < hi[0]; ++x) {
+                const int64_t li = L.idx(x, y, z);
+                lat2int[li] = next;
+                m.own_api[next] = (int)li;
+                if (L.layer(x, y, z) == 1) {
+                  const int64_t gx = d.fem_lo[0] + x, gy = d.fem_lo[1] + y, gz = d.fem_lo[2] + z;
+                  m.own_grid[next] = (int)(gx + (int64_t)d.n_outer[0] * (gy + (int64_t)d.n_outer[1] * gz));
+                }
+                ++next;
+              }
+        }
+    m.own_off[m.n_part] = next;
+  }
+
+  // geometry table (deduplicated on the float32 image of the FP64 geometry)
+  std::map<std::array<uint32_t, 13>, int> geom_ids;
+  auto geom_id = [&](const int v[4][3]) -> int {
+    double p[4][3], g[4][3], vol;
+    for (int j = 0; j < 4; ++j)
+      for (int a = 0; a < 3; ++a) p[j][a] = d.h * (double)(v[j][a] - v[0][a]);
+    if (!tet_geometry(p, g, &vol)) return -1;
+    std::array<uint32_t, 13> key;
+    float f[13];
+    for (int j = 0; j < 4; ++j)
+      for (int a = 0; a < 3; ++a) f[3 * j + a] = (float)g[j][a];
+    f[12] = (float)vol;
+    for (int i = 0; i < 13; ++i) std::memcpy(&key[i], &f[i], 4);
+    auto it = geom_ids.find(key);
+    if (it != geom_ids.end()) return it->second;
+    const int id = (int)geom_ids.size();
+    geom_ids.emplace(key, id);
+    for (int i = 0; i < 13; ++i) m.geom.push_back(f[i]);
+    for (int i = 13; i < 16; ++i) m.geom.push_back(0.f);
+    return id;
+  };
+
+  // lumped mass of owned nodes: sum over incident tetrahedra of |K| / 4 (FP64)
+  m.mass.assign(m.n_own, 0.0);
+  m.halo_off.assign(m.n_part + 1, 0);
+  m.col_base.assign(m.n_part, 0);
+  m.ncol.assign(m.n_part, 0);
+  m.col_off.clear();
+  m.elems.clear();
+  m.halo.clear();
+  for (int p = 0; p < m.n_part; ++p) {
+    const auto& r = prange[p];
+    const int o0 = m.own_off[p], no = m.own_off[p + 1] - o0;
+    auto owned_here = [&](const int v[3]) {
+      return v[0] >= r[0] && v[0] < r[1] && v[1] >= r[2] && v[1] < r[3] && v[2] >= r[4] && v[2] < r[5];
+    };
+    struct El { int v[4][3]; int gid; };
+    std::vector<El> els;
+    for (int cz = std::max(r[4] - 1, 0); cz <= std::min(r[5] - 1, L.c[2] - 1); ++cz)
+      for (int cy = std::max(r[2] - 1, 0); cy <= std::min(r[3] - 1, L.c[1] - 1); ++cy)
+        for (int cx = std::max(r[0] - 1, 0); cx <= std::min(r[1] - 1, L.c[0] - 1); ++cx)
+          for (int q = 0; q < 6; ++q) {
+            El e;
+            e.v[0][0] = cx; e.v[0][1] = cy; e.v[0][2] = cz;
+            for (int k = 1; k < 4; ++k) {
+              for (int a = 0; a < 3; ++a) e.v[k][a] = e.v[k - 1][a];
+              e.v[k][kPerms[q][k - 1]] += 1;
+            }
+            bool touches = false;
+            for (int k = 0; k < 4; ++k) touches |= owned_here(e.v[k]);
+            if (!touches) continue;
+            e.gid = geom_id(e.v);
+            if (e.gid < 0) return "degenerate tetrahedron";
+            els.push_back(e);
+          }
+    // halo: non-owned vertices, ordered by internal code (owned ids, then layer-0 codes)
+    std::vector<int> hcodes;
+    for (const auto& e : els)
+      for (int k = 0; k < 4; ++k)
+        if (!owned_here(e.v[k])) hcodes.push_back(lat2int[L.idx(e.v[k][0], e.v[k][1], e.v[k][2])]);
+    std::sort(hcodes.begin(), hcodes.end(), [](int a, int b) {
+      if ((a >= 0) != (b >= 0)) return a >= 0;
+      return a >= 0 ? a < b : a > b;
+    });
+    hcodes.erase(std::unique(hcodes.begin(), hcodes.end()), hcodes.end());
+    const int nl = no + (int)hcodes.size();
+    if (nl > FEM_LOC_MAX || no > FEM_OWN_MAX) return "FEM partition exceeds local node limit";
+    m.max_loc = std::max(m.max_loc, nl);
+    std::map<int, int> hloc;
+    for (size_t i = 0; i < hcodes.size(); ++i) hloc[hcodes[i]] = no + (int)i;
+    m.halo_off[p] = (int)m.halo.size();
+    m.halo.insert(m.halo.end(), hcodes.begin(), hcodes.end());
+    // local ids, greedy colouring on shared owned nodes
+    struct Pk { int loc[4]; int gid; int color; };
+    std::vector<Pk> pk(els.size());
+    std::vector<uint64_t> used(no, 0);
+    int ncol = 0;
+    for (size_t i = 0; i < els.size(); ++i) {
+      uint64_t forbid = 0;
+      for (int k = 0; k < 4; ++k) {
+        const int code = lat2int[L.idx(els[i].v[k][0], els[i].v[k][1], els[i].v[k][2])];
+        const int loc = owned_here(els[i].v[k]) ? code - o0 : hloc[code];
+        pk[i].loc[k] = loc;
+        if (loc < no) forbid |= used[loc];
+      }
+      if (forbid == ~0ull) return "FEM colouring needs more than 64 colours";
+      int c = 0;
+      while (forbid & (1ull << c)) ++c;
+      pk[i].color = c;
+      pk[i].gid = els[i].gid;
+      for (int k = 0; k < 4; ++k)
+        if (pk[i].loc[k] < no) used[pk[i].loc[k]] |= (1ull << c);
+      ncol = std::max(ncol, c + 1);
+    }
+    // lumped mass contributions to this partition's owned nodes (each element of the
+    // mesh that touches an owned node is present here exactly once)
+    for (size_t i = 0; i < els.size(); ++i) {
+      double p4[4][3], g4[4][3], v;
+      for (int j = 0; j < 4; ++j)
+        for (int a = 0; a < 3; ++a) p4[j][a] = d.h * (double)(els[i].v[j][a] - els[i].v[0][a]);
+      tet_geometry(p4, g4, &v);
+      for (int k = 0; k < 4; ++k)
+        if (pk[i].loc[k] < no) m.mass[o0 + pk[i].loc[k]] += v / 4.0;
+    }
+    m.max_colors = std::max(m.max_colors, ncol);
+    std::stable_sort(pk.begin(), pk.end(), [](const Pk& a, const Pk& b) { return a.color < b.color; });
+    m.col_base[p] = (int)m.col_off.size();
+    m.ncol[p] = ncol;
+    const int e0 = (int)m.elems.size();
+    {
+      size_t i = 0;
+      for (int c = 0; c <= ncol; ++c) {
+        while (i < pk.size() && pk[i].color < c) ++i;
+        m.col_off.push_back(e0 + (int)i);
+      }
+    }
+    for (const auto& q : pk) {
+      if (q.gid >= (1 << 20)) return "geometry table exceeds 2^20 entries";
+      uint64_t w = 0;
+      for (int k = 0; k < 4; ++k) w |= (uint64_t)(q.loc[k] & 0x7FF) << (11 * k);
+      w |= (uint64_t)q.gid << 44;
+      m.elems.push_back(w);
+    }
+  }
+  m.halo_off[m.n_part] = (int)m.halo.size();
+  m.n_geom = (int)geom_ids.size();
+  return std::string();
+}
+
+}  // namespace dd
+
+// ---------------------------------------------------------------------------------------
+// Host-only diagnostic: applies the FEM operator with exactly the data the FEM kernel
+// consumes (partition halos, colours, packed connectivity, geometry table), in FP64 and
+// sequentially, checking every index against its bound and every colour for conflicts.
+// ---------------------------------------------------------------------------------------
+extern "C" int dd_debug_fem_apply(const dd_problem_desc* d, const double* eps, const double* E, int adjoint,
+                                  double* out, int64_t* stats) {
+  using namespace dd;
+  if (!d || !eps || !E || !out) return DD_ERR_INVALID_ARG;
+  HostMesh m;
+  if (!build_mesh(*d, m).empty()) return DD_ERR_UNSUPPORTED;
+  const int s[3] = {d->fem_cells[0] + 1, d->fem_cells[1] + 1, d->fem_cells[2] + 1};
+  const int64_t n_own = m.n_own, n_l0 = m.n_l0;
+  std::vector<double> X(3 * n_own), em1(n_own), iface(3 * n_l0, 0.0);
+  std::vector<char> l0_seen(n_l0, 0);
+  for (int64_t id = 0; id < n_own; ++id) {
+    const int api = m.own_api[id];
+    if (api < 0 || api >= m.n_fem) return DD_ERR_UNSUPPORTED;
+    for (int c = 0; c < 3; ++c) X[c * n_own + id] = E[(int64_t)api * 3 + c];
+    em1[id] = eps[api] - 1.0;
+  }
+  for (int z = 0; z < s[2]; ++z)
+    for (int y = 0; y < s[1]; ++y)
+      for (int x = 0; x < s[0]; ++x) {
+        const int64_t q = face_lex_index(x, y, z, s[0], s[1], s[2], 63u);
+        if (q < 0) continue;
+        if (q >= n_l0 || l0_seen[q]) return DD_ERR_UNSUPPORTED;
+        l0_seen[q] = 1;
+        const int64_t api = x + (int64_t)s[0] * (y + (int64_t)s[1] * z);
+        for (int c = 0; c < 3; ++c) iface[c * n_l0 + q] = E[api * 3 + c];
+      }
+  for (int64_t i = 0; i < 3 * m.n_fem; ++i) out[i] = 0.0;
+  int64_t n_elem = 0;
+  for (int p = 0; p < m.n_part; ++p) {
+    const int o0 = m.own_off[p], no = m.own_off[p + 1] - o0;
+    const int h0 = m.halo_off[p], nh = m.halo_off[p + 1] - h0;
+    const int nl = no + nh;
+    if (nl > FEM_LOC_MAX || no > FEM_OWN_MAX || o0 + no > n_own) return DD_ERR_UNSUPPORTED;
+    std::vector<double> sX(3 * nl), sM(nl, 0.0), acc(6 * no, 0.0);
+    for (int l = 0; l < nl; ++l) {
+      if (l < no) {
+        for (int c = 0; c < 3; ++c) sX[c * nl + l] = X[c * n_own + o0 + l];
+        sM[l] = em1[o0 + l];
+      } else {
+        const int hc = m.halo[h0 + l - no];
+        if (hc >= 0) {
+          if (hc >= n_own) return DD_ERR_UNSUPPORTED;
+          for (int c = 0; c < 3; ++c) sX[c * nl + l] = X[c * n_own + hc];
+          sM[l] = em1[hc];
+        } else {
+          const int64_t q = -1 - (int64_t)hc;
+          if (q >= n_l0) return DD_ERR_UNSUPPORTED;
+          for (int c = 0; c < 3; ++c) sX[c * nl + l] = iface[c * n_l0 + q];
+        }
+      }
+    }
+    const int cb = m.col_base[p];
+    for (int c = 0; c < m.ncol[p]; ++c) {
+      std::vector<char> touched(no, 0);
+      for (int e = m.col_off[cb + c]; e < m.col_off[cb + c + 1]; ++e) {
+        ++n_elem;
+        const uint64_t w = m.elems[e];
+        int v[4];
+        for (int k = 0; k < 4; ++k) {
+          v[k] = (int)((w >> (11 * k)) & 0x7FFu);
+          if (v[k] >= nl) return DD_ERR_UNSUPPORTED;
+        }
+        const uint64_t gid = w >> 44;
+        if ((int64_t)gid >= m.n_geom) return DD_ERR_UNSUPPORTED;
+        const float* g = &m.geom[16 * gid];
+        double G[3][3] = {{0}}, dv = 0.0;
+        for (int j = 0; j < 4; ++j) {
+          const double mj = adjoint ? 1.0 : sM[v[j]];
+          for (int q = 0; q < 3; ++q)
+            for (int a = 0; a < 3; ++a) G[q][a] += sX[q * nl + v[j]] * g[3 * j + a];
+          for (int a = 0; a < 3; ++a) dv += mj * sX[a * nl + v[j]] * g[3 * j + a];
+        }
+        const double vol = g[12];
+        for (int k = 0; k < 4; ++k) {
+          if (v[k] >= no) continue;
+          if (touched[v[k]]) return DD_ERR_UNSUPPORTED;  // two elements of one colour share an owned node
+          touched[v[k]] = 1;
+          for (int q = 0; q < 3; ++q) {
+            const double kc = vol * (g[3 * k] * G[q][0] + g[3 * k + 1] * G[q][1] + g[3 * k + 2] * G[q][2]);
+            const double dc = vol * g[3 * k + q] * dv;
+            acc[q * no + v[k]] += kc;
+            acc[(3 + q) * no + v[k]] += dc;
+          }
+        }
+      }
+    }
+    for (int l = 0; l < no; ++l) {
+      const int api = m.own_api[o0 + l];
+      for (int q = 0; q < 3; ++q)
+        out[(int64_t)api * 3 + q] =
+            acc[q * no + l] + (adjoint ? em1[o0 + l] : 1.0) * acc[(3 + q) * no + l];
+    }
+  }
+  if (stats) {
+    stats[0] = m.n_part;
+    stats[1] = m.max_colors;
+    stats[2] = m.max_loc;
+    stats[3] = m.n_geom;
+    stats[4] = n_elem;
+    stats[5] = m.n_own;
+    stats[6] = m.n_l0;
+  }
+  return DD_OK;
+}

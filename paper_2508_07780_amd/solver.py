@@ -1,0 +1,109 @@
+"""Python face of the C-ABI: one Problem per dd_problem handle.
+
+Only argument marshalling happens here: torch provides device memory and the
+current stream; every step of the solve runs in the library's HIP kernels.
+"""
+
+import ctypes
+
+import torch
+
+from . import _lib
+
+
+def _stream():
+    return ctypes.c_void_p(torch.cuda.current_stream().cuda_stream)
+
+
+def _ptr(t):
+    return ctypes.c_void_p(t.data_ptr())
+
+
+def _device_f32(x, n, name):
+    t = torch.as_tensor(x)
+    if not t.is_cuda:
+        raise ValueError(f"{name} must be a CUDA (HIP) tensor")
+    t = t.to(torch.float32).contiguous().reshape(-1)
+    if t.numel() != n:
+        raise ValueError(f"{name} must have {n} entries, got {t.numel()}")
+    return t
+
+
+class Problem:
+    """A hybrid FE/FD problem resident on the current GPU."""
+
+    def __init__(self, desc):
+        lib = _lib.load()
+        self.desc = desc
+        self._cdesc = _lib.make_desc(desc)
+        h = ctypes.c_void_p()
+        _lib.check(lib.dd_create(ctypes.byref(self._cdesc), ctypes.byref(h)))
+        self._h = h
+        nf, nd, ng = ctypes.c_int64(), ctypes.c_int64(), ctypes.c_int64()
+        _lib.check(lib.dd_sizes(h, ctypes.byref(nf), ctypes.byref(nd), ctypes.byref(ng)), h)
+        self.n_fem, self.n_det, self.n_grid = nf.value, nd.value, ng.value
+        self.n_steps = int(desc.n_steps)
+        self._n_src = 0
+
+    def close(self):
+        if getattr(self, "_h", None):
+            _lib.load().dd_destroy(self._h)
+            self._h = None
+
+    def __del__(self):
+        try:
+            self.close()
+        except Exception:
+            pass
+
+    @staticmethod
+    def footprint_bytes(desc, n_src):
+        c = _lib.make_desc(desc)
+        return int(_lib.load().dd_footprint_bytes(ctypes.byref(c), int(n_src)))
+
+    @staticmethod
+    def detector_nodes(desc):
+        import numpy as np
+        c = _lib.make_desc(desc)
+        n = ctypes.c_int64()
+        lib = _lib.load()
+        _lib.check(lib.dd_detector_nodes(ctypes.byref(c), None, 0, ctypes.byref(n)))
+        out = np.zeros(n.value, dtype=np.int64)
+        _lib.check(lib.dd_detector_nodes(ctypes.byref(c), out.ctypes.data_as(ctypes.POINTER(ctypes.c_int64)),
+                                         n.value, ctypes.byref(n)))
+        return out
+
+    def set_coefficients(self, eps, sigma):
+        e = _device_f32(eps, self.n_fem, "eps")
+        s = _device_f32(sigma, self.n_fem, "sigma")
+        _lib.check(_lib.load().dd_set_coefficients(self._h, _ptr(e), _ptr(s), _stream()), self._h)
+
+    def forward(self, sources, save=True, energy=False, out=None):
+        srcs = _lib.make_sources(sources)
+        n = len(sources)
+        dev = torch.device("cuda", torch.cuda.current_device())
+        shape = (n, self.n_steps, self.n_det, 3)
+        traces = out if out is not None else torch.empty(shape, dtype=torch.float32, device=dev)
+        if tuple(traces.shape) != shape or traces.dtype != torch.float32 or not traces.is_contiguous():
+            raise ValueError("trace buffer must be a contiguous float32 tensor of shape %s" % (shape,))
+        en = torch.empty((n, self.n_steps), dtype=torch.float64, device=dev) if energy else None
+        _lib.check(_lib.load().dd_forward(self._h, srcs, n, _ptr(traces), 1 if save else 0,
+                                          _ptr(en) if en is not None else None, _stream()), self._h)
+        self._n_src = n
+        return (traces, en) if energy else traces
+
+    def adjoint(self, cot):
+        c = torch.as_tensor(cot)
+        if not c.is_cuda:
+            raise ValueError("cotangent must be a CUDA (HIP) tensor")
+        c = c.to(torch.float32).contiguous()
+        if self._n_src and c.numel() != self._n_src * self.n_steps * self.n_det * 3:
+            raise ValueError("cotangent must match the traces of the last forward")
+        _lib.check(_lib.load().dd_adjoint(self._h, _ptr(c), _stream()), self._h)
+
+    def gradient(self):
+        dev = torch.device("cuda", torch.cuda.current_device())
+        ge = torch.empty(self.n_fem, dtype=torch.float64, device=dev)
+        gs = torch.empty(self.n_fem, dtype=torch.float64, device=dev)
+        _lib.check(_lib.load().dd_gradient(self._h, _ptr(ge), _ptr(gs), _stream()), self._h)
+        return ge, gs
