@@ -1,0 +1,177 @@
+#!/usr/bin/env python3
+"""Benchmark: one step = one full forward + adjoint + gradient solve on the GPU.
+
+Workload (default): layered-skin model, 160^3 outer grid nodes, 64^3 FEM hexes
+(1.57M Kuhn tetrahedra), 2000 time steps, one Gaussian-sine plane wave on the
+top face, detectors on the top face, checkpoints every 64 steps.  Observed data
+come from the seeded true model plus 3% Gaussian noise; the gradient is taken at
+the initial guess eps = 1, sigma = 0.  Inputs are resident in HBM before timing.
+
+Prints one JSON line with the throughput in Gcell-steps/s, where a cell is an
+outer-grid node or a FEM-owned node and forward and adjoint steps both count,
+the roofline of the dominant kernel (finite-difference step, HIP-event timed over
+the timed region on the solver's stream), per-solve latency p50/p99 and the FP64
+oracle timed on the host on a bounded sample of the same workload.
+"""
+
+import argparse
+import json
+import math
+import os
+import sys
+import time
+
+ROOT = os.path.dirname(os.path.abspath(__file__))
+sys.path.insert(0, ROOT)
+
+HBM_PEAK_GBS = 8000.0   # MI355X HBM3E peak
+
+
+def _percentile(xs, q):
+    xs = sorted(xs)
+    if not xs:
+        return None
+    k = (len(xs) - 1) * q / 100.0
+    f, c = math.floor(k), math.ceil(k)
+    return xs[f] + (xs[c] - xs[f]) * (k - f)
+
+
+def cpu_baseline(workload, n_steps):
+    """The FP64 oracle, as it stands, on the first n_steps forward + n_steps adjoint steps."""
+    import numpy as np
+    from oracle.discretization import Discretization
+    from oracle.solver import adjoint_gradient, forward
+    import synth
+    w = synth.with_steps(workload, n_steps)
+    d = Discretization(w.desc).set_coefficients(w.eps, w.sigma)
+    cot = np.random.default_rng(0).standard_normal((n_steps, len(d.det), 3)) * 1e-3
+    t0, c0 = time.perf_counter(), time.process_time()
+    fw = forward(d, w.sources[0])
+    adjoint_gradient(d, cot, fw)
+    wall = time.perf_counter() - t0
+    cpu = time.process_time() - c0
+    cells = w.desc.n_grid() + w.desc.n_fem_owned()
+    return {
+        "value": cells * 2 * n_steps / wall / 1e9,
+        "unit": "Gcell-steps/s",
+        "cores": max(1, int(math.ceil(cpu / wall - 0.05))),
+        "kind": "oracle",
+        "sample": f"FP64 numpy/scipy oracle, full {w.desc.n_outer[0]}^3 grid with {w.desc.fem_cells[0]}^3 FEM "
+                  f"hexes, first {n_steps} forward + {n_steps} adjoint steps with gradient accumulation "
+                  f"({wall:.1f} s wall, {cpu:.1f} s CPU; host has {len(os.sched_getaffinity(0))} cores available)",
+    }
+
+
+def main():
+    ap = argparse.ArgumentParser()
+    ap.add_argument("--gpus", type=int, default=1)
+    ap.add_argument("--steps", type=int, default=3)
+    ap.add_argument("--warmup", type=int, default=1)
+    ap.add_argument("--n-steps", type=int, default=2000, help="time steps per solve")
+    ap.add_argument("--cpu-sample-steps", type=int, default=8, help="0 skips the oracle baseline")
+    ap.add_argument("--no-profile", action="store_true", help="skip the HIP-event kernel timing")
+    args = ap.parse_args()
+    if args.gpus != 1 or int(os.environ.get("WORLD_SIZE", "1")) != 1:
+        print("bench.py measures one GPU: the solver runs one problem per GPU and this build has no "
+              "multi-GPU path; run with --gpus 1", file=sys.stderr)
+        sys.exit(2)
+
+    import numpy as np
+    import torch
+    import synth
+    from paper_2508_07780_amd import Problem, _lib
+
+    torch.cuda.set_device(0)
+    w = synth.c2(n_steps=args.n_steps)
+    dev = torch.device("cuda", 0)
+    prob = Problem(w.desc)
+    # observed data: seeded true model + 3% Gaussian noise (setup, not timed)
+    prob.set_coefficients(torch.tensor(w.eps_true, dtype=torch.float32, device=dev),
+                          torch.tensor(w.sigma_true, dtype=torch.float32, device=dev))
+    tr_true = prob.forward(w.sources, save=False)
+    xi = synth.noise(tuple(tr_true.shape), w.seed).astype(np.float32)
+    eobs = tr_true * (1.0 + w.noise_level * torch.from_numpy(xi).to(dev))
+    del xi, tr_true
+    eps0 = torch.ones(prob.n_fem, dtype=torch.float32, device=dev)     # initial guess (paper: eps = 1, sigma = 0)
+    sig0 = torch.zeros(prob.n_fem, dtype=torch.float32, device=dev)
+    torch.cuda.synchronize()
+
+    def solve():
+        prob.set_coefficients(eps0, sig0)
+        tr = prob.forward(w.sources, save=True)
+        prob.adjoint(tr - eobs)          # dJ/dtraces of J = 1/2 sum |E - E_obs|^2
+        return prob.gradient()
+
+    for _ in range(args.warmup):
+        solve()
+    torch.cuda.synchronize()
+    if not args.no_profile:
+        prob.profile(True)
+        for k in range(5):
+            prob.profile_read(k, reset=True)
+    lat = []
+    torch.cuda.synchronize()
+    t_all = time.perf_counter()
+    for _ in range(args.steps):
+        t0 = time.perf_counter()
+        g_eps, g_sig = solve()
+        torch.cuda.synchronize()
+        lat.append((time.perf_counter() - t0) * 1e3)
+    torch.cuda.synchronize()
+    elapsed = time.perf_counter() - t_all
+    kern = {}
+    if not args.no_profile:
+        for k, name in enumerate(_lib.PROF_NAMES):
+            ms, n = prob.profile_read(k, reset=True)
+            b = prob.algorithmic_bytes(k)
+            if n:
+                kern[name] = {"launches": n, "avg_us": ms / n * 1e3, "algorithmic_bytes": b,
+                              "algorithmic_GBs": b / (ms / n * 1e-3) / 1e9}
+        prob.profile(False)
+
+    n_src = len(w.sources)
+    cells = w.desc.n_grid() + w.desc.n_fem_owned()
+    cell_steps = cells * 2 * w.desc.n_steps * n_src
+    value = cell_steps * args.steps / elapsed / 1e9
+    finite = bool(torch.isfinite(g_eps).all() and torch.isfinite(g_sig).all())
+
+    roofline = None
+    if "fd_step_fwd" in kern:
+        k = kern["fd_step_fwd"]
+        achieved = k["algorithmic_GBs"]
+        roofline = {"bound": "hbm", "achieved": round(achieved, 1), "peak": HBM_PEAK_GBS, "unit": "GB/s",
+                    "frac": round(achieved / HBM_PEAK_GBS, 4), "traffic": None,
+                    "kernel": "fd_step_kernel (forward)", "avg_us": round(k["avg_us"], 2),
+                    "algorithmic_bytes_per_launch": k["algorithmic_bytes"]}
+
+    out = {
+        "metric": "Gcell-steps/s fwd+adj (HBM % of peak), FP32 vs oracle err; p50/p99 solve latency",
+        "value": round(value, 3),
+        "unit": "Gcell-steps/s",
+        "n_gpus": 1,
+        "steps": args.steps,
+        "warmup": args.warmup,
+        "ms_per_step": round(elapsed / args.steps * 1e3, 2),
+        "higher_is_better": True,
+        "scaling": "weak",
+        "vs_baseline": None,
+        "dtype": "f32",
+        "data": "synthetic",
+        "config": {"workload": "layered-skin forward+adjoint+gradient solve", "outer_nodes": list(w.desc.n_outer),
+                   "fem_hexes": list(w.desc.fem_cells), "tets": 6 * int(np.prod(w.desc.fem_cells)),
+                   "time_steps": w.desc.n_steps, "sources": n_src, "ckpt_every": w.desc.ckpt_every,
+                   "cells": cells},
+        "latency_ms": {"p50": round(_percentile(lat, 50), 2), "p99": round(_percentile(lat, 99), 2)},
+        "roofline": roofline,
+        "kernels": {k: {kk: (round(vv, 2) if isinstance(vv, float) else vv) for kk, vv in v.items()}
+                    for k, v in kern.items()},
+        "gradient_finite": finite,
+    }
+    del prob
+    if args.cpu_sample_steps > 0:
+        out["cpu_baseline"] = cpu_baseline(w, args.cpu_sample_steps)
+    print(json.dumps(out), flush=True)
+
+
+if __name__ == "__main__":
+    main()

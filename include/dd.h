@@ -145,6 +145,20 @@ int dd_gradient(dd_problem* p, double* g_eps_dev, double* g_sigma_dev, void* str
 const char* dd_error_string(int code);
 const char* dd_last_error(const dd_problem* p);
 
+/* Kernel timing.  When enabled, HIP events on the caller's stream bracket every
+ * step launch of each kind below (up to 16384 launches per kind), adding a few
+ * microseconds of gaps between launches.  dd_profile_read synchronises on the last
+ * event of `kind` and returns the summed kernel time and the launch count; reset != 0
+ * clears that kind.  dd_algorithmic_bytes gives the minimum HBM bytes one launch of
+ * `kind` must move (each field value read or written once). */
+enum {
+  DD_PROF_FD_FWD = 0, DD_PROF_FEM_FWD = 1, DD_PROF_FD_ADJ = 2, DD_PROF_FEM_ADJ = 3,
+  DD_PROF_FEM_RECOMPUTE = 4, DD_PROF_KINDS = 5
+};
+int dd_profile_enable(dd_problem* p, int32_t enable);
+int dd_profile_read(dd_problem* p, int32_t kind, double* total_ms, int64_t* launches, int32_t reset);
+int dd_algorithmic_bytes(const dd_problem* p, int32_t kind, double* bytes_per_launch);
+
 /* Diagnostic (host only, no GPU): applies the FEM rows of the operator -- forward
  * (K + A_dd) E, or with adjoint != 0 the transpose K E + (eps - 1) q(E) -- in FP64 by
  * walking exactly the partition / halo / colour / geometry data the FEM kernel reads,

@@ -15,7 +15,11 @@ ERRORS = {
 EXPORTS = [
     "dd_create", "dd_destroy", "dd_sizes", "dd_detector_nodes", "dd_footprint_bytes",
     "dd_set_coefficients", "dd_forward", "dd_adjoint", "dd_gradient", "dd_error_string", "dd_last_error",
+    "dd_profile_enable", "dd_profile_read", "dd_algorithmic_bytes", "dd_debug_fem_apply",
 ]
+
+PROF_FD_FWD, PROF_FEM_FWD, PROF_FD_ADJ, PROF_FEM_ADJ, PROF_FEM_RECOMPUTE = range(5)
+PROF_NAMES = ["fd_step_fwd", "fem_step_fwd", "fd_step_adj", "fem_step_adj", "fem_step_recompute"]
 
 
 class ProblemDesc(ctypes.Structure):
@@ -80,6 +84,11 @@ def load():
     lib.dd_error_string.restype = ctypes.c_char_p
     lib.dd_last_error.argtypes = [P]
     lib.dd_last_error.restype = ctypes.c_char_p
+    lib.dd_profile_enable.argtypes = [P, ctypes.c_int32]
+    lib.dd_profile_read.argtypes = [P, ctypes.c_int32, ctypes.POINTER(ctypes.c_double), ctypes.POINTER(ctypes.c_int64),
+                                    ctypes.c_int32]
+    lib.dd_algorithmic_bytes.argtypes = [P, ctypes.c_int32, ctypes.POINTER(ctypes.c_double)]
+    lib.dd_debug_fem_apply.argtypes = [ctypes.POINTER(ProblemDesc), P, P, ctypes.c_int32, P, P]
     for name in EXPORTS:
         if name not in ("dd_footprint_bytes", "dd_error_string", "dd_last_error"):
             getattr(lib, name).restype = ctypes.c_int

@@ -4,6 +4,7 @@
 // launch per step on the caller's stream.  Within a step both kernels read only
 // level-n buffers and write only level-(n+1) buffers (ping-pong for the fields,
 // in-place increments), so their order inside a step does not matter.
+#include <algorithm>
 #include <cmath>
 #include <cstdio>
 #include <cstring>
@@ -43,9 +44,35 @@ struct dd_problem {
   bool have_grad = false;
   std::string err;
   std::vector<void*> allocs;
+  // kernel timing: event pairs around each step launch, per launch kind
+  bool prof = false;
+  std::vector<hipEvent_t> ev[DD_PROF_KINDS];
+  size_t ev_used[DD_PROF_KINDS] = {0, 0, 0, 0, 0};
 };
 
 namespace {
+
+constexpr size_t kProfMaxPairs = 16384;
+
+// Records the opening event of a timed launch; returns the pair slot or -1.
+long prof_begin(dd_problem* p, int kind, hipStream_t st) {
+  if (!p->prof) return -1;
+  auto& v = p->ev[kind];
+  const size_t i = p->ev_used[kind];
+  if (i >= kProfMaxPairs) return -1;
+  while (v.size() < 2 * (i + 1)) {
+    hipEvent_t e;
+    if (hipEventCreate(&e) != hipSuccess) return -1;
+    v.push_back(e);
+  }
+  if (hipEventRecord(v[2 * i], st) != hipSuccess) return -1;
+  return (long)i;
+}
+
+void prof_end(dd_problem* p, int kind, long slot, hipStream_t st) {
+  if (slot < 0) return;
+  if (hipEventRecord(p->ev[kind][2 * slot + 1], st) == hipSuccess) p->ev_used[kind] = (size_t)slot + 1;
+}
 
 int fail(dd_problem* p, int code, const std::string& msg) {
   if (p) p->err = msg;
@@ -236,7 +263,9 @@ int run_forward(dd_problem* p, const dd_source& src, int s, float* traces, bool 
     fa.cot_in = nullptr;
     fa.iface_out = save ? hist + (n + 1) * 3 * n_l0 : p->iring + nxt * 3 * n_l0;
     fa.epart = energy ? p->epart : nullptr;
+    long ps = prof_begin(p, DD_PROF_FD_FWD, st);
     launch_fd(fa, st, energy != nullptr);
+    prof_end(p, DD_PROF_FD_FWD, ps, st);
 
     ea.X_in = p->Efem[cur];
     ea.X_out = p->Efem[nxt];
@@ -247,7 +276,9 @@ int run_forward(dd_problem* p, const dd_source& src, int s, float* traces, bool 
     ea.ck_X = ckw ? ck + ((n + 1) / K) * 6 * n_own : nullptr;
     ea.ck_I = ckw ? ea.ck_X + 3 * n_own : nullptr;
     ea.epart = energy ? p->epart : nullptr;
+    ps = prof_begin(p, DD_PROF_FEM_FWD, st);
     launch_fem_fwd(ea, p->n_part, st, energy != nullptr);
+    prof_end(p, DD_PROF_FEM_FWD, ps, st);
     if (energy) launch_energy_reduce(p->epart, p->n_tiles + p->n_part, energy + (int64_t)s * nt + n, st);
   }
   return check_launch(p);
@@ -277,7 +308,9 @@ int run_adjoint(dd_problem* p, int s, const float* cot, hipStream_t st) {
       fw.I_out = wV(k - k0 + 1);
       fw.iface_in = hist + k * 3 * n_l0;
       fw.fd_out = nullptr;
+      const long ps = prof_begin(p, DD_PROF_FEM_RECOMPUTE, st);
       launch_fem_fwd(fw, p->n_part, st, false);
+      prof_end(p, DD_PROF_FEM_RECOMPUTE, ps, st);
     }
     for (int64_t k = k1; k > k0; --k) {
       const int cur = (int)(k & 1), prv = (int)((k - 1) & 1);
@@ -289,7 +322,9 @@ int run_adjoint(dd_problem* p, int s, const float* cot, hipStream_t st) {
       fa.tr_out = nullptr;
       fa.cot_in = cot + ((int64_t)s * nt + (k - 1)) * p->n_det * 3;
       fa.iface_out = p->iring + prv * 3 * n_l0;
+      long ps = prof_begin(p, DD_PROF_FD_ADJ, st);
       launch_fd(fa, st, false);
+      prof_end(p, DD_PROF_FD_ADJ, ps, st);
 
       ea.X_in = p->Efem[cur];
       ea.X_out = p->Efem[prv];
@@ -299,7 +334,9 @@ int run_adjoint(dd_problem* p, int s, const float* cot, hipStream_t st) {
       ea.wE = wE(k - k0);
       ea.wV = wV(k - k0);
       ea.wVm = wV(k - 1 - k0);
+      ps = prof_begin(p, DD_PROF_FEM_ADJ, st);
       launch_fem_adj(ea, p->n_part, st);
+      prof_end(p, DD_PROF_FEM_ADJ, ps, st);
     }
   }
   return check_launch(p);
@@ -441,6 +478,8 @@ int dd_create(const dd_problem_desc* desc, dd_problem** out) {
 int dd_destroy(dd_problem* p) {
   if (!p) return DD_ERR_INVALID_ARG;
   (void)hipDeviceSynchronize();
+  for (auto& v : p->ev)
+    for (hipEvent_t e : v) (void)hipEventDestroy(e);
   for (void* q : p->allocs) (void)hipFree(q);
   delete p;
   return DD_OK;
@@ -524,6 +563,59 @@ int dd_gradient(dd_problem* p, double* g_eps_dev, double* g_sigma_dev, void* str
   launch_fill_f64(g_sigma_dev, p->n_fem, 0.0, st);
   launch_gradient_out(p->g_eps, p->g_sig, p->own_api, p->own_grid, p->n_own, g_eps_dev, g_sigma_dev, st);
   return check_launch(p);
+}
+
+int dd_profile_enable(dd_problem* p, int32_t enable) {
+  if (!p) return DD_ERR_INVALID_ARG;
+  p->prof = enable != 0;
+  for (auto& u : p->ev_used) u = 0;
+  return DD_OK;
+}
+
+int dd_profile_read(dd_problem* p, int32_t kind, double* total_ms, int64_t* launches, int32_t reset) {
+  if (!p || kind < 0 || kind >= DD_PROF_KINDS) return DD_ERR_INVALID_ARG;
+  double tot = 0.0;
+  const size_t n = p->ev_used[kind];
+  if (n) {
+    if (hipEventSynchronize(p->ev[kind][2 * n - 1]) != hipSuccess) return fail(p, DD_ERR_HIP, "event synchronize failed");
+    for (size_t i = 0; i < n; ++i) {
+      float ms = 0.f;
+      if (hipEventElapsedTime(&ms, p->ev[kind][2 * i], p->ev[kind][2 * i + 1]) != hipSuccess)
+        return fail(p, DD_ERR_HIP, "hipEventElapsedTime failed");
+      tot += ms;
+    }
+  }
+  if (total_ms) *total_ms = tot;
+  if (launches) *launches = (int64_t)n;
+  if (reset) p->ev_used[kind] = 0;
+  return DD_OK;
+}
+
+int dd_algorithmic_bytes(const dd_problem* p, int32_t kind, double* bytes_per_launch) {
+  if (!p || !bytes_per_launch || kind < 0 || kind >= DD_PROF_KINDS) return DD_ERR_INVALID_ARG;
+  const double n_fd = (double)(p->N - p->n_own);
+  const double n_own = (double)p->n_own, n_l0 = (double)p->n_l0, n_det = (double)p->n_det;
+  int64_t n_free = 1;
+  for (int a = 0; a < 3; ++a) n_free *= std::max(p->d.fem_cells[a] - 3, 0);
+  const double n_l1 = (double)(p->n_own - n_free);
+  double b = 0.0;
+  switch (kind) {
+    case DD_PROF_FD_FWD:   // E^n, V^n read, V^{n+1}, E^{n+1} written; traces and layer-0 values written
+    case DD_PROF_FD_ADJ:   // same with lambda, Lambda; cotangent read instead of traces written
+      b = 48.0 * n_fd + 12.0 * n_det + 12.0 * n_l0;
+      break;
+    case DD_PROF_FEM_FWD:
+    case DD_PROF_FEM_RECOMPUTE:
+      // state (E read/written, V read/written), coefficients eps-1, c1, c2, layer-0 read, layer-1 dual write
+      b = 48.0 * n_own + 12.0 * n_own + 12.0 * n_l0 + 12.0 * n_l1;
+      break;
+    case DD_PROF_FEM_ADJ:
+      // adjoint state + coefficients + forward window (E^k, V^k, V^{k-1}) + FP64 gradient read/write (free nodes)
+      b = 48.0 * n_own + 12.0 * n_own + 12.0 * n_l0 + 12.0 * n_l1 + 36.0 * n_own + 32.0 * (n_own - n_l1);
+      break;
+  }
+  *bytes_per_launch = b;
+  return DD_OK;
 }
 
 }  // extern "C"

@@ -107,3 +107,19 @@ class Problem:
         gs = torch.empty(self.n_fem, dtype=torch.float64, device=dev)
         _lib.check(_lib.load().dd_gradient(self._h, _ptr(ge), _ptr(gs), _stream()), self._h)
         return ge, gs
+
+    # ---- kernel timing ---------------------------------------------------------------------
+    def profile(self, enable=True):
+        _lib.check(_lib.load().dd_profile_enable(self._h, 1 if enable else 0), self._h)
+
+    def profile_read(self, kind, reset=True):
+        """(total kernel ms, launches) of one launch kind since the last reset."""
+        ms, n = ctypes.c_double(), ctypes.c_int64()
+        _lib.check(_lib.load().dd_profile_read(self._h, int(kind), ctypes.byref(ms), ctypes.byref(n),
+                                               1 if reset else 0), self._h)
+        return ms.value, n.value
+
+    def algorithmic_bytes(self, kind):
+        b = ctypes.c_double()
+        _lib.check(_lib.load().dd_algorithmic_bytes(self._h, int(kind), ctypes.byref(b)), self._h)
+        return b.value
