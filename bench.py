@@ -68,6 +68,9 @@ def main():
     ap.add_argument("--steps", type=int, default=3)
     ap.add_argument("--warmup", type=int, default=1)
     ap.add_argument("--n-steps", type=int, default=2000, help="time steps per solve")
+    ap.add_argument("--ckpt-every", type=int, default=0,
+                    help="forward checkpoint interval K for the adjoint; 0 = store every FEM level "
+                         "(no recompute; 12.6 GB for the default workload)")
     ap.add_argument("--cpu-sample-steps", type=int, default=8, help="0 skips the oracle baseline")
     ap.add_argument("--no-profile", action="store_true", help="skip the HIP-event kernel timing")
     args = ap.parse_args()
@@ -83,6 +86,7 @@ def main():
 
     torch.cuda.set_device(0)
     w = synth.c2(n_steps=args.n_steps)
+    w.desc.ckpt_every = args.ckpt_every if args.ckpt_every > 0 else w.desc.n_steps
     dev = torch.device("cuda", 0)
     prob = Problem(w.desc)
     # observed data: seeded true model + 3% Gaussian noise (setup, not timed)

@@ -160,14 +160,16 @@ int dd_profile_read(dd_problem* p, int32_t kind, double* total_ms, int64_t* laun
 int dd_algorithmic_bytes(const dd_problem* p, int32_t kind, double* bytes_per_launch);
 
 /* Diagnostic (host only, no GPU): applies the FEM rows of the operator -- forward
- * (K + A_dd) E, or with adjoint != 0 the transpose K E + (eps - 1) q(E) -- in FP64 by
- * walking exactly the partition / halo / colour / geometry data the FEM kernel reads,
- * checking every index bound and that no colour touches an owned node twice.
+ * (K + A_dd) E, or with flags bit 0 set the transpose K E + (eps - 1) q(E) -- in FP64 by
+ * walking exactly the data a FEM kernel reads, checking every index bound: with flags
+ * bit 1 clear the element kernel's partition / halo / colour / geometry data (and that no
+ * colour touches an owned node twice), with bit 1 set the assembled-stencil kernel's
+ * partition boxes and stencil table (DD_ERR_UNSUPPORTED if the mesh has no shared stencil).
  * eps: FEM-node array; E, out: [n_fem_nodes][3] (out is written on FEM-owned nodes,
- * zero elsewhere).  stats (nullable, 7 entries): partitions, max colours, max local
- * nodes, geometry entries, element evaluations, owned nodes, layer-0 nodes.
+ * zero elsewhere).  stats (nullable, 8 entries): partitions, max colours, max local
+ * nodes, geometry entries, element evaluations, owned nodes, layer-0 nodes, stencil slots.
  * Returns DD_ERR_UNSUPPORTED if any check fails. */
-int dd_debug_fem_apply(const dd_problem_desc* desc, const double* eps, const double* E, int32_t adjoint,
+int dd_debug_fem_apply(const dd_problem_desc* desc, const double* eps, const double* E, int32_t flags,
                        double* out, int64_t* stats);
 
 #ifdef __cplusplus

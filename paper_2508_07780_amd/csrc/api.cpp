@@ -7,6 +7,7 @@
 #include <algorithm>
 #include <cmath>
 #include <cstdio>
+#include <cstdlib>
 #include <cstring>
 #include <new>
 
@@ -21,7 +22,12 @@ struct dd_problem {
   int fs[3] = {0, 0, 0};
   int64_t n_fem = 0, n_own = 0, n_l0 = 0, n_det = 0;
   int n_part = 0, n_geom = 0;
-  int nbx = 0, nby = 0, nbz = 0, n_tiles = 0, per_xcd = 0;
+  int lds_loc = 0, lds_own = 0, lds_elem = 0, lds_box = 0;
+  bool use_stencil = false;             // assembled-stencil FEM kernel instead of the element kernel
+  int n_slots = 0;
+  int *part_dims = nullptr, *box_codes = nullptr, *slot_off = nullptr;
+  float *slot_k = nullptr, *slot_b = nullptr;
+  int nbx = 0, nby = 0, nbz = 0, n_tiles = 0, per_xcd = 0, zc = FD_ZC;
   // topology (device)
   int *own_off = nullptr, *halo_off = nullptr, *halo = nullptr, *col_base = nullptr, *ncol = nullptr,
       *col_off = nullptr, *own_grid = nullptr, *own_api = nullptr;
@@ -34,10 +40,15 @@ struct dd_problem {
   float* iring = nullptr;  // [2][3][n_l0]
   double* epart = nullptr;
   int* d_err = nullptr;
-  // saved forward for the adjoint
-  std::vector<float*> ihist, ckpt;  // per source
+  // saved forward for the adjoint, per source: layer-0 history, segment-start checkpoints
+  // and the last segment's full FEM state (written by the forward, never recomputed)
+  std::vector<float*> ihist, ckpt, tail;
   int n_ck = 0;
-  float* win = nullptr;             // [(K+1)][2][3][n_own]
+  float* win = nullptr;             // recompute window [(K+1)][2][3][n_own]
+  // FD and FEM launches of one step run concurrently on the caller's stream and `aux`
+  hipStream_t aux = nullptr;
+  hipEvent_t ev_fd = nullptr, ev_fem = nullptr;
+  bool overlap = true;
   bool saved = false;
   int saved_n_src = 0;
   double *g_eps = nullptr, *g_sig = nullptr;
@@ -166,6 +177,7 @@ FdArgs fd_base(const dd_problem* p) {
     a.fs[c] = p->fs[c];
   }
   a.nbx = p->nbx; a.nby = p->nby; a.nbz = p->nbz; a.ntiles = p->n_tiles; a.per_xcd = p->per_xcd;
+  a.zc = p->zc;
   const double nu = p->d.dt / p->d.h;
   a.nu = (float)nu;
   a.nu2 = (float)(nu * nu);
@@ -183,7 +195,10 @@ FemArgs fem_base(const dd_problem* p) {
   std::memset(&a, 0, sizeof(a));
   a.own_off = p->own_off; a.halo_off = p->halo_off; a.halo = p->halo;
   a.col_base = p->col_base; a.ncol = p->ncol; a.col_off = p->col_off;
-  a.elems = p->elems; a.geom = p->geom; a.own_grid = p->own_grid;
+  a.elems = p->elems; a.geom = p->geom; a.n_geom = p->n_geom; a.own_grid = p->own_grid;
+  a.lds_loc = p->lds_loc; a.lds_own = p->lds_own; a.lds_elem = p->lds_elem;
+  a.part_dims = p->part_dims; a.box_codes = p->box_codes; a.slot_off = p->slot_off;
+  a.slot_k = p->slot_k; a.slot_b = p->slot_b; a.n_slots = p->n_slots; a.lds_box = p->lds_box;
   a.em1 = p->em1; a.c1 = p->c1; a.c2 = p->c2; a.mass_d = p->mass_d;
   a.n_own = p->n_own; a.n_l0 = p->n_l0; a.N = p->N;
   a.epart_off = p->n_tiles;
@@ -192,6 +207,20 @@ FemArgs fem_base(const dd_problem* p) {
   a.inv_dt2 = 1.0 / (dt * dt);
   a.inv_2dt = 1.0 / (2.0 * dt);
   return a;
+}
+
+void fem_fwd(const dd_problem* p, const FemArgs& a, hipStream_t st, bool energy) {
+  if (p->use_stencil)
+    launch_fem_stencil_fwd(a, p->n_part, st, energy);
+  else
+    launch_fem_fwd(a, p->n_part, st, energy);
+}
+
+void fem_adj(const dd_problem* p, const FemArgs& a, hipStream_t st) {
+  if (p->use_stencil)
+    launch_fem_stencil_adj(a, p->n_part, st);
+  else
+    launch_fem_adj(a, p->n_part, st);
 }
 
 void zero_state(dd_problem* p, hipStream_t st) {
@@ -204,23 +233,54 @@ void zero_state(dd_problem* p, hipStream_t st) {
   launch_fill_f32(p->iring, 6 * p->n_l0, 0.f, st);
 }
 
+// Segments of the adjoint: [k0, k1) per segment, K steps each, the last one shorter.
+int64_t n_segments(const dd_problem* p) {
+  const int64_t nt = p->d.n_steps, K = p->d.ckpt_every;
+  return (nt + K - 1) / K;
+}
+int64_t last_segment_start(const dd_problem* p) { return (n_segments(p) - 1) * (int64_t)p->d.ckpt_every; }
+
 int ensure_saved_storage(dd_problem* p, int n_src) {
   const int64_t nt = p->d.n_steps;
+  const int64_t tail_levels = nt - last_segment_start(p) + 1;
   while ((int)p->ihist.size() < n_src) {
-    float *h = nullptr, *c = nullptr;
+    float *h = nullptr, *c = nullptr, *t = nullptr;
     int rc = dalloc(p, &h, (size_t)(nt + 1) * 3 * p->n_l0);
     if (rc) return rc;
     rc = dalloc(p, &c, (size_t)p->n_ck * 6 * p->n_own);
     if (rc) return rc;
+    rc = dalloc(p, &t, (size_t)tail_levels * 6 * p->n_own);
+    if (rc) return rc;
     p->ihist.push_back(h);
     p->ckpt.push_back(c);
+    p->tail.push_back(t);
   }
-  if (!p->win) {
-    const int64_t K = std::min<int64_t>(p->d.ckpt_every, nt);
+  if (!p->win && n_segments(p) > 1) {
+    const int64_t K = p->d.ckpt_every;
     int rc = dalloc(p, &p->win, (size_t)(K + 1) * 6 * p->n_own);
     if (rc) return rc;
   }
   return DD_OK;
+}
+
+// Two-stream step pipeline: within a step the FD launch (main stream) and the FEM launch
+// (aux stream) are independent; across steps each waits for both of the previous step.
+void fork_streams(dd_problem* p, hipStream_t st) {
+  if (!p->overlap) return;
+  (void)hipEventRecord(p->ev_fd, st);
+  (void)hipStreamWaitEvent(p->aux, p->ev_fd, 0);
+}
+void step_barrier(dd_problem* p, hipStream_t st) {
+  if (!p->overlap) return;
+  (void)hipEventRecord(p->ev_fd, st);
+  (void)hipEventRecord(p->ev_fem, p->aux);
+  (void)hipStreamWaitEvent(st, p->ev_fem, 0);
+  (void)hipStreamWaitEvent(p->aux, p->ev_fd, 0);
+}
+void join_streams(dd_problem* p, hipStream_t st) {
+  if (!p->overlap) return;
+  (void)hipEventRecord(p->ev_fem, p->aux);
+  (void)hipStreamWaitEvent(st, p->ev_fem, 0);
 }
 
 int run_forward(dd_problem* p, const dd_source& src, int s, float* traces, bool save, double* energy, hipStream_t st) {
@@ -229,10 +289,15 @@ int run_forward(dd_problem* p, const dd_source& src, int s, float* traces, bool 
   zero_state(p, st);
   float* hist = save ? p->ihist[s] : nullptr;
   float* ck = save ? p->ckpt[s] : nullptr;
+  float* tail = save ? p->tail[s] : nullptr;
+  const int64_t k_tail = last_segment_start(p);
   if (save) {
     launch_fill_f32(hist, 3 * n_l0, 0.f, st);          // level 0
     launch_fill_f32(ck, 6 * n_own, 0.f, st);           // checkpoint of level 0
+    if (k_tail == 0) launch_fill_f32(tail, 6 * n_own, 0.f, st);
   }
+  hipStream_t sf = p->overlap ? p->aux : st;           // stream of the FEM launches
+  fork_streams(p, st);
   FdArgs fa = fd_base(p);
   FemArgs ea = fem_base(p);
   const double dt = p->d.dt, h = p->d.h;
@@ -272,15 +337,21 @@ int run_forward(dd_problem* p, const dd_source& src, int s, float* traces, bool 
     ea.I_in = ea.I_out = p->Vfem;
     ea.iface_in = save ? hist + n * 3 * n_l0 : p->iring + cur * 3 * n_l0;
     ea.fd_out = p->Efd[nxt];
-    const bool ckw = save && ((n + 1) % K == 0) && ((n + 1) / K < p->n_ck);
-    ea.ck_X = ckw ? ck + ((n + 1) / K) * 6 * n_own : nullptr;
-    ea.ck_I = ckw ? ea.ck_X + 3 * n_own : nullptr;
+    // dual write of the new FEM state: the last segment entirely, else segment-start checkpoints
+    ea.ck_X = nullptr;
+    if (save && n + 1 >= k_tail)
+      ea.ck_X = tail + (n + 1 - k_tail) * 6 * n_own;
+    else if (save && (n + 1) % K == 0 && (n + 1) / K < p->n_ck)
+      ea.ck_X = ck + ((n + 1) / K) * 6 * n_own;
+    ea.ck_I = ea.ck_X ? ea.ck_X + 3 * n_own : nullptr;
     ea.epart = energy ? p->epart : nullptr;
-    ps = prof_begin(p, DD_PROF_FEM_FWD, st);
-    launch_fem_fwd(ea, p->n_part, st, energy != nullptr);
-    prof_end(p, DD_PROF_FEM_FWD, ps, st);
+    ps = prof_begin(p, DD_PROF_FEM_FWD, sf);
+    fem_fwd(p, ea, sf, energy != nullptr);
+    prof_end(p, DD_PROF_FEM_FWD, ps, sf);
+    step_barrier(p, st);
     if (energy) launch_energy_reduce(p->epart, p->n_tiles + p->n_part, energy + (int64_t)s * nt + n, st);
   }
+  join_streams(p, st);
   return check_launch(p);
 }
 
@@ -293,24 +364,31 @@ int run_adjoint(dd_problem* p, int s, const float* cot, hipStream_t st) {
   FemArgs ea = fem_base(p);   // adjoint
   ea.g_eps = p->g_eps;
   ea.g_sig = p->g_sig;
-  const int64_t nseg = (nt + K - 1) / K;
+  const int64_t nseg = n_segments(p);
   float* hist = p->ihist[s];
   float* ck = p->ckpt[s];
-  auto wE = [&](int64_t j) { return p->win + j * 6 * n_own; };
-  auto wV = [&](int64_t j) { return p->win + j * 6 * n_own + 3 * n_own; };
+  hipStream_t sf = p->overlap ? p->aux : st;
+  fork_streams(p, st);
   for (int64_t seg = nseg - 1; seg >= 0; --seg) {
     const int64_t k0 = seg * K, k1 = std::min(k0 + K, nt);
-    launch_copy_f32(p->win, ck + seg * 6 * n_own, 6 * n_own, st);
-    for (int64_t k = k0; k < k1; ++k) {
-      fw.X_in = wE(k - k0);
-      fw.X_out = wE(k - k0 + 1);
-      fw.I_in = wV(k - k0);
-      fw.I_out = wV(k - k0 + 1);
-      fw.iface_in = hist + k * 3 * n_l0;
-      fw.fd_out = nullptr;
-      const long ps = prof_begin(p, DD_PROF_FEM_RECOMPUTE, st);
-      launch_fem_fwd(fw, p->n_part, st, false);
-      prof_end(p, DD_PROF_FEM_RECOMPUTE, ps, st);
+    // forward FEM state of levels k0..k1: stored by the forward for the last segment,
+    // recomputed from the segment-start checkpoint and the layer-0 history otherwise
+    float* win = seg == nseg - 1 ? p->tail[s] : p->win;
+    auto wE = [&](int64_t j) { return win + j * 6 * n_own; };
+    auto wV = [&](int64_t j) { return win + j * 6 * n_own + 3 * n_own; };
+    if (seg != nseg - 1) {
+      launch_copy_f32(win, ck + seg * 6 * n_own, 6 * n_own, sf);
+      for (int64_t k = k0; k < k1; ++k) {
+        fw.X_in = wE(k - k0);
+        fw.X_out = wE(k - k0 + 1);
+        fw.I_in = wV(k - k0);
+        fw.I_out = wV(k - k0 + 1);
+        fw.iface_in = hist + k * 3 * n_l0;
+        fw.fd_out = nullptr;
+        const long ps = prof_begin(p, DD_PROF_FEM_RECOMPUTE, sf);
+        fem_fwd(p, fw, sf, false);
+        prof_end(p, DD_PROF_FEM_RECOMPUTE, ps, sf);
+      }
     }
     for (int64_t k = k1; k > k0; --k) {
       const int cur = (int)(k & 1), prv = (int)((k - 1) & 1);
@@ -334,11 +412,13 @@ int run_adjoint(dd_problem* p, int s, const float* cot, hipStream_t st) {
       ea.wE = wE(k - k0);
       ea.wV = wV(k - k0);
       ea.wVm = wV(k - 1 - k0);
-      ps = prof_begin(p, DD_PROF_FEM_ADJ, st);
-      launch_fem_adj(ea, p->n_part, st);
-      prof_end(p, DD_PROF_FEM_ADJ, ps, st);
+      ps = prof_begin(p, DD_PROF_FEM_ADJ, sf);
+      fem_adj(p, ea, sf);
+      prof_end(p, DD_PROF_FEM_ADJ, ps, sf);
+      step_barrier(p, st);
     }
   }
+  join_streams(p, st);
   return check_launch(p);
 }
 
@@ -386,8 +466,9 @@ size_t dd_footprint_bytes(const dd_problem_desc* desc, int32_t n_src) {
   const int64_t n_fem = fs[0] * fs[1] * fs[2];
   const int64_t n_own = (int64_t)(desc->fem_cells[0] - 1) * (desc->fem_cells[1] - 1) * (desc->fem_cells[2] - 1);
   const int64_t n_l0 = face_lex_count((int)fs[0], (int)fs[1], (int)fs[2], 63u);
-  const int64_t nt = desc->n_steps, K = std::min<int64_t>(desc->ckpt_every, nt);
-  const int64_t n_ck = nt / desc->ckpt_every + 1;
+  const int64_t nt = desc->n_steps, K = desc->ckpt_every;
+  const int64_t nseg = (nt + K - 1) / K;
+  const int64_t n_ck = nseg, tail_levels = nt - (nseg - 1) * K + 1;
   const int64_t tets_est = 6 * n_fem * 3 / 2;  // elements incl. halo duplicates (upper estimate)
   int64_t b = 0;
   b += 4 * 9 * N;                         // E (2 levels) + V on the grid
@@ -395,8 +476,8 @@ size_t dd_footprint_bytes(const dd_problem_desc* desc, int32_t n_src) {
   b += 4 * 6 * n_l0;                      // interface ring
   b += n_own * (4 * 3 + 8 + 4 * 2 + 8 * 2);  // coefficients, mass, index maps, gradient accumulators
   b += tets_est * 8 + n_fem * 4 * 2;      // elements, halo lists
-  b += (int64_t)n_src * ((nt + 1) * 3 * n_l0 * 4 + n_ck * 6 * n_own * 4);  // saved forward
-  b += (K + 1) * 6 * n_own * 4;           // recompute window
+  b += (int64_t)n_src * ((nt + 1) * 3 * n_l0 * 4 + (n_ck + tail_levels) * 6 * n_own * 4);  // saved forward
+  if (nseg > 1) b += (K + 1) * 6 * n_own * 4;  // recompute window
   return (size_t)b;
 }
 
@@ -415,7 +496,12 @@ int dd_create(const dd_problem_desc* desc, dd_problem** out) {
   for (int a = 0; a < 3; ++a) p->fs[a] = desc->fem_cells[a] + 1;
   p->n_det = face_lex_count(p->nx, p->ny, p->nz, desc->detector_faces);
   HostMesh m;
-  const std::string me = build_mesh(*desc, m);
+  int pb[3] = {FEM_PB, FEM_PB, FEM_PB};
+  if (const char* e = std::getenv("DD_FEM_PB")) {
+    int x = 0, y = 0, z = 0;
+    if (std::sscanf(e, "%d,%d,%d", &x, &y, &z) == 3) { pb[0] = x; pb[1] = y; pb[2] = z; }
+  }
+  const std::string me = build_mesh(*desc, m, pb);
   if (!me.empty()) {
     delete p;
     return DD_ERR_UNSUPPORTED;
@@ -425,12 +511,25 @@ int dd_create(const dd_problem_desc* desc, dd_problem** out) {
   p->n_l0 = m.n_l0;
   p->n_part = m.n_part;
   p->n_geom = m.n_geom;
+  p->lds_loc = (m.max_loc + 3) & ~3;     // multiples of 4 floats keep the LDS sub-arrays 16-byte aligned
+  p->lds_own = (m.max_own + 3) & ~3;
+  p->lds_elem = (m.max_elem + 1) & ~1;
+  p->lds_box = m.max_box;
+  p->n_slots = m.n_slots;
+  p->use_stencil = m.stencil_ok && m.n_slots <= STENCIL_SLOTS_MAX;
+  if (const char* e = std::getenv("DD_FEM_PATH"))
+    if (std::strcmp(e, "element") == 0) p->use_stencil = false;
   p->nbx = (p->nx + FD_TX - 1) / FD_TX;
   p->nby = (p->ny + FD_TY - 1) / FD_TY;
-  p->nbz = (p->nz + FD_ZC - 1) / FD_ZC;
+  if (const char* zc = std::getenv("DD_FD_ZC")) {
+    const int v = std::atoi(zc);
+    if (v == 8 || v == 16 || v == 32) p->zc = v;
+  }
+  p->nbz = (p->nz + p->zc - 1) / p->zc;
   p->n_tiles = p->nbx * p->nby * p->nbz;
   p->per_xcd = (p->n_tiles + N_XCD - 1) / N_XCD;
-  p->n_ck = (int)(desc->n_steps / desc->ckpt_every) + 1;
+  p->n_ck = (int)((desc->n_steps + desc->ckpt_every - 1) / desc->ckpt_every);
+  if (const char* ov = std::getenv("DD_OVERLAP")) p->overlap = std::atoi(ov) != 0;
   int rc = DD_OK;
   auto chk = [&](int r) { if (r && !rc) rc = r; };
   chk(upload(p, &p->own_off, m.own_off));
@@ -444,6 +543,13 @@ int dd_create(const dd_problem_desc* desc, dd_problem** out) {
   chk(upload(p, &p->elems, m.elems));
   chk(upload(p, &p->geom, m.geom));
   chk(upload(p, &p->mass_d, m.mass));
+  if (m.stencil_ok) {
+    chk(upload(p, &p->part_dims, m.part_dims));
+    chk(upload(p, &p->box_codes, m.box_codes));
+    chk(upload(p, &p->slot_off, m.slot_off));
+    chk(upload(p, &p->slot_k, m.slot_k));
+    chk(upload(p, &p->slot_b, m.slot_b));
+  }
   chk(dalloc(p, &p->em1, p->n_own));
   chk(dalloc(p, &p->c1, p->n_own));
   chk(dalloc(p, &p->c2, p->n_own));
@@ -458,6 +564,10 @@ int dd_create(const dd_problem_desc* desc, dd_problem** out) {
   chk(dalloc(p, &p->d_err, 1));
   chk(dalloc(p, &p->g_eps, p->n_own));
   chk(dalloc(p, &p->g_sig, p->n_own));
+  if (!rc && (hipStreamCreateWithFlags(&p->aux, hipStreamNonBlocking) != hipSuccess ||
+              hipEventCreateWithFlags(&p->ev_fd, hipEventDisableTiming) != hipSuccess ||
+              hipEventCreateWithFlags(&p->ev_fem, hipEventDisableTiming) != hipSuccess))
+    rc = DD_ERR_HIP;
   if (rc) {
     dd_destroy(p);
     return rc;
@@ -480,6 +590,9 @@ int dd_destroy(dd_problem* p) {
   (void)hipDeviceSynchronize();
   for (auto& v : p->ev)
     for (hipEvent_t e : v) (void)hipEventDestroy(e);
+  if (p->ev_fd) (void)hipEventDestroy(p->ev_fd);
+  if (p->ev_fem) (void)hipEventDestroy(p->ev_fem);
+  if (p->aux) (void)hipStreamDestroy(p->aux);
   for (void* q : p->allocs) (void)hipFree(q);
   delete p;
   return DD_OK;

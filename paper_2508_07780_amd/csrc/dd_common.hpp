@@ -11,18 +11,24 @@
 
 namespace dd {
 
-// Finite-difference tile: 32 x 8 nodes in (x, y), marching ZC planes in z.
+// Finite-difference tile: 32 x 8 nodes in (x, y), marching zc planes in z (8, 16 or 32;
+// default FD_ZC, overridable with the DD_FD_ZC environment variable).
 constexpr int FD_TX = 32;
 constexpr int FD_TY = 8;
 constexpr int FD_ZC = 16;
 constexpr int FD_THREADS = FD_TX * FD_TY;
 
 // FEM partition: a block of at most FEM_PB^3 owned nodes plus its halo.
-constexpr int FEM_PB = 8;
+constexpr int FEM_PB = 8;          // default block edge; DD_FEM_PB="x,y,z" overrides
 constexpr int FEM_THREADS = 256;
 constexpr int FEM_LOC_MAX = 1024;  // owned + halo nodes per partition (11-bit local ids)
 constexpr int FEM_OWN_MAX = 512;
 constexpr int FEM_COLORS_MAX = 64;
+constexpr int FEM_ELEM_MAX = 4608;  // elements per partition (staged in LDS)
+constexpr int FEM_GEOM_LDS = 64;    // geometry tables up to this size are staged in LDS
+// Geometry entry: grad phi_0..3 (12 floats), |K| grad phi_0..3 (12), |K|, padding.  The
+// stride of 36 floats puts consecutive entries on different LDS banks for 16-byte reads.
+constexpr int GEOM_STRIDE = 36;
 
 constexpr int N_XCD = 8;  // MI355X: workgroups are dispatched round-robin over 8 XCDs
 
@@ -69,6 +75,7 @@ struct FdArgs {
   int nx, ny, nz;
   int blo[3], bhi[3];  // FEM box node range [fem_lo, fem_lo + fem_cells] per axis
   int nbx, nby, nbz, ntiles, per_xcd;
+  int zc;              // planes per tile in z (8, 16 or 32)
   float nu2, nu;       // (dt/h)^2, dt/h
   unsigned abs_mask;
   int top_a, top_b;    // top face absorbing at the levels of D+ (a) and D- (b)
@@ -86,6 +93,8 @@ struct FdArgs {
   double e_coef;       // h^3 / (2 dt^2)
 };
 
+constexpr int STENCIL_SLOTS_MAX = 27;
+
 struct FemArgs {
   const int* own_off;   // [n_part + 1]
   const int* halo_off;  // [n_part + 1]
@@ -94,7 +103,9 @@ struct FemArgs {
   const int* ncol;      // [n_part]
   const int* col_off;   // absolute element offsets per colour
   const uint64_t* elems;
-  const float* geom;    // [n_geom][16]: grad phi_0..3 (12), |K|, pad
+  const float* geom;    // [n_geom][GEOM_STRIDE]
+  int n_geom;
+  int lds_loc, lds_own, lds_elem;  // LDS sizing: max local nodes, owned nodes, elements (even)
   const int* own_grid;  // grid index for layer-1 owned nodes, -1 otherwise (free)
   const float* em1;     // eps - 1
   const float* c1;      // (a - b) / (a + b)
@@ -107,6 +118,9 @@ struct FemArgs {
   float* ck_X; float* ck_I;  // checkpoint dual write or null
   int64_t n_own, n_l0, N;
   double* epart; int epart_off; double inv_2dt2;
+  // assembled-stencil path
+  const int* part_dims; const int* box_codes; const int* slot_off; const float* slot_k; const float* slot_b;
+  int n_slots, lds_box;
   // adjoint
   const float* wE; const float* wV; const float* wVm;  // forward E^k, V^k, V^{k-1} [3][n_own]
   double* g_eps; double* g_sig;
@@ -114,8 +128,11 @@ struct FemArgs {
 };
 
 void launch_fd(const FdArgs& a, hipStream_t s, bool energy);
+size_t fem_lds_bytes(const FemArgs& a, bool adj);
 void launch_fem_fwd(const FemArgs& a, int n_part, hipStream_t s, bool energy);
 void launch_fem_adj(const FemArgs& a, int n_part, hipStream_t s);
+void launch_fem_stencil_fwd(const FemArgs& a, int n_part, hipStream_t s, bool energy);
+void launch_fem_stencil_adj(const FemArgs& a, int n_part, hipStream_t s);
 void launch_energy_reduce(const double* part, int n, double* out, hipStream_t s);
 void launch_fill_f32(float* p, int64_t n, float v, hipStream_t s);
 void launch_fill_f64(double* p, int64_t n, double v, hipStream_t s);
@@ -137,11 +154,21 @@ struct HostMesh {
   std::vector<float> geom;
   std::vector<int> own_grid, own_api;
   std::vector<double> mass;
-  int max_colors = 0, max_loc = 0;
+  int max_colors = 0, max_loc = 0, max_own = 0, max_elem = 0;
+  // Assembled-stencil form (used when every owned node has the same assembled stencil,
+  // as on the Kuhn lattice): per partition the owned block dims and a (dims+2)^3 box of
+  // node codes in lattice order; per stencil slot the lattice offset, K_ij and B_ij.
+  bool stencil_ok = false;
+  int n_slots = 0, max_box = 0;
+  std::vector<int> part_dims;   // [n_part][4]: owned dims x, y, z, box base
+  std::vector<int> box_codes;   // owned internal id or -1 - layer0 index
+  std::vector<int> slot_off;    // [n_slots][4]: dx, dy, dz, 0
+  std::vector<float> slot_k;    // [n_slots]
+  std::vector<float> slot_b;    // [n_slots][9], row-major 3x3
 };
 
 // Builds the Kuhn split of the FEM box, the node partitions and per-partition colouring.
 // Returns an empty string on success, else the error text.
-std::string build_mesh(const dd_problem_desc& d, HostMesh& m);
+std::string build_mesh(const dd_problem_desc& d, HostMesh& m, const int pb[3]);
 
 }  // namespace dd

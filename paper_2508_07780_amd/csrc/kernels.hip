@@ -18,21 +18,25 @@ namespace dd {
 // Finite-difference region.  eps = 1, sigma = 0 here (eq. epsilon_sigma_constraint), so
 // the update is the 7-point wave stencil with mirror (Neumann) weights on the outer box,
 // lumped absorbing damping on absorbing faces and the plane-wave / dipole forcing.
-// Tile = 32 x 8 nodes in (x, y), marching FD_ZC planes in z: the current plane sits in LDS
-// (with a one-node halo), the z-1 and z+1 values of each column stay in registers.
+// Tile = 32 x 8 nodes in (x, y), marching ZC planes in z: the current plane sits in LDS
+// (with a one-node halo, double-buffered), the z-1 / z+1 values of each column stay in a
+// register queue that is prefetched two planes ahead; increments and halo one plane ahead.
 // ---------------------------------------------------------------------------------------
-template <bool ENERGY>
+template <int ZC, bool ENERGY>
 __global__ __launch_bounds__(FD_THREADS) void fd_step_kernel(FdArgs a) {
-  __shared__ float s[3][FD_TY + 2][FD_TX + 2];
+  // two LDS planes: plane z is written while plane z-1 may still be read by slower waves,
+  // so one barrier per plane suffices
+  __shared__ float s[2][3][FD_TY + 2][FD_TX + 2];
   __shared__ double red[ENERGY ? FD_THREADS : 1];
   const int b = blockIdx.x;
   const int t = (b % N_XCD) * a.per_xcd + b / N_XCD;  // consecutive tiles share an XCD's L2
   if (t >= a.ntiles) return;
+  const int nx = a.nx, ny = a.ny, nz = a.nz;
   const int bx = t % a.nbx;
   const int by = (t / a.nbx) % a.nby;
   const int bz = t / (a.nbx * a.nby);
-  const int x0 = bx * FD_TX, y0 = by * FD_TY, z0 = bz * FD_ZC;
-  const int z1 = min(z0 + FD_ZC, a.nz);
+  const int x0 = bx * FD_TX, y0 = by * FD_TY, z0 = bz * ZC;
+  const int z1 = min(z0 + ZC, nz);
   const int tid = threadIdx.x;
   if (x0 > a.blo[0] && x0 + FD_TX - 1 < a.bhi[0] && y0 > a.blo[1] && y0 + FD_TY - 1 < a.bhi[1] &&
       z0 > a.blo[2] && z1 - 1 < a.bhi[2]) {
@@ -42,65 +46,101 @@ __global__ __launch_bounds__(FD_THREADS) void fd_step_kernel(FdArgs a) {
   }
   const int tx = tid % FD_TX, ty = tid / FD_TX;
   const int x = x0 + tx, y = y0 + ty;
-  const int nx = a.nx, ny = a.ny, nz = a.nz;
   const bool col_ok = (x < nx) && (y < ny);
-  const int64_t N = a.N;
-  const int64_t plane = (int64_t)nx * ny;
-  const int64_t col = (int64_t)y * nx + x;
-  const float* __restrict__ X = a.X_in;
+  const int plane = nx * ny;           // N < 2^31: 32-bit offsets within one component
+  const int col = y * nx + x;
+  const float* __restrict__ X0 = a.X_in;
+  const float* __restrict__ X1 = a.X_in + a.N;
+  const float* __restrict__ X2 = a.X_in + 2 * a.N;
+  float* __restrict__ I0 = a.I;
+  float* __restrict__ I1 = a.I + a.N;
+  float* __restrict__ I2 = a.I + 2 * a.N;
+
+  // halo cell of this thread (80 ring cells of the 32 x 8 tile, corners unused)
+  int hx = -1, hy = -1, hsy = 0, hsx = 0;
+  if (tid < FD_TX) { hx = x0 + tid; hy = y0 - 1; hsy = 0; hsx = tid + 1; }
+  else if (tid < 2 * FD_TX) { hx = x0 + tid - FD_TX; hy = y0 + FD_TY; hsy = FD_TY + 1; hsx = tid - FD_TX + 1; }
+  else if (tid < 2 * FD_TX + FD_TY) { hx = x0 - 1; hy = y0 + tid - 2 * FD_TX; hsy = tid - 2 * FD_TX + 1; hsx = 0; }
+  else if (tid < 2 * FD_TX + 2 * FD_TY) { hx = x0 + FD_TX; hy = y0 + tid - 2 * FD_TX - FD_TY; hsy = tid - 2 * FD_TX - FD_TY + 1; hsx = FD_TX + 1; }
+  const bool h_ok = hx >= 0 && hx < nx && hy >= 0 && hy < ny;
+  const int hcol = h_ok ? hy * nx + hx : 0;
 
   const bool bxl = x == 0, bxh = x == nx - 1, byl = y == 0, byh = y == ny - 1;
-  const float wx = (bxl || bxh) ? 2.f : 1.f;   // 2 / (neighbours along x)
+  const float wx = (bxl || bxh) ? 2.f : 1.f;   // 2 / (neighbours along x): mirror weights
   const float wy = (byl || byh) ? 2.f : 1.f;
   const bool in_box_xy = x > a.blo[0] && x < a.bhi[0] && y > a.blo[1] && y < a.bhi[1];
   const bool in_box_xy_closed = x >= a.blo[0] && x <= a.bhi[0] && y >= a.blo[1] && y <= a.bhi[1];
 
-  float cur[3] = {0.f, 0.f, 0.f}, prv[3] = {0.f, 0.f, 0.f}, nxt[3] = {0.f, 0.f, 0.f};
+  // register queue of this column: q0 = z-1, q1 = z, q2 = z+1, q3 = z+2 (in flight)
+  float q0[3] = {0.f, 0.f, 0.f}, q1[3] = {0.f, 0.f, 0.f}, q2[3] = {0.f, 0.f, 0.f}, q3[3];
+  float hv[3] = {0.f, 0.f, 0.f}, hn[3];
+  float v[3] = {0.f, 0.f, 0.f}, vn[3];
   if (col_ok) {
-#pragma unroll
-    for (int c = 0; c < 3; ++c) {
-      cur[c] = X[c * N + z0 * plane + col];
-      prv[c] = z0 > 0 ? X[c * N + (z0 - 1) * plane + col] : 0.f;
-    }
+    const int o = z0 * plane + col;
+    q1[0] = X0[o]; q1[1] = X1[o]; q1[2] = X2[o];
+    if (z0 > 0) { q0[0] = X0[o - plane]; q0[1] = X1[o - plane]; q0[2] = X2[o - plane]; }
+    if (z0 + 1 < nz) { q2[0] = X0[o + plane]; q2[1] = X1[o + plane]; q2[2] = X2[o + plane]; }
+    v[0] = I0[o]; v[1] = I1[o]; v[2] = I2[o];
+  }
+  if (h_ok) {
+    const int o = z0 * plane + hcol;
+    hv[0] = X0[o]; hv[1] = X1[o]; hv[2] = X2[o];
   }
   double eacc = 0.0;
+  int buf = 0;
   for (int z = z0; z < z1; ++z) {
-    const int64_t zoff = (int64_t)z * plane;
-#pragma unroll
-    for (int c = 0; c < 3; ++c) {
-      const float* Xc = X + c * N + zoff;
-      if (col_ok) s[c][ty + 1][tx + 1] = cur[c];
-      if (tx == 0 && x0 > 0 && y < ny) s[c][ty + 1][0] = Xc[(int64_t)y * nx + x0 - 1];
-      if (tx == FD_TX - 1 && x0 + FD_TX < nx && y < ny) s[c][ty + 1][FD_TX + 1] = Xc[(int64_t)y * nx + x0 + FD_TX];
-      if (ty == 0 && y0 > 0 && x < nx) s[c][0][tx + 1] = Xc[(int64_t)(y0 - 1) * nx + x];
-      if (ty == FD_TY - 1 && y0 + FD_TY < ny && x < nx) s[c][FD_TY + 1][tx + 1] = Xc[(int64_t)(y0 + FD_TY) * nx + x];
-      nxt[c] = (col_ok && z + 1 < nz) ? X[c * N + zoff + plane + col] : 0.f;
+    const int zoff = z * plane;
+    if (col_ok) {
+      s[buf][0][ty + 1][tx + 1] = q1[0];
+      s[buf][1][ty + 1][tx + 1] = q1[1];
+      s[buf][2][ty + 1][tx + 1] = q1[2];
+    }
+    if (h_ok) {
+      s[buf][0][hsy][hsx] = hv[0];
+      s[buf][1][hsy][hsx] = hv[1];
+      s[buf][2][hsy][hsx] = hv[2];
+    }
+    // prefetch: column two planes ahead, halo and increment one plane ahead
+    q3[0] = q3[1] = q3[2] = 0.f;
+    hn[0] = hn[1] = hn[2] = 0.f;
+    vn[0] = vn[1] = vn[2] = 0.f;
+    if (col_ok && z + 2 < nz && z + 2 <= z1) {
+      const int o = zoff + 2 * plane + col;
+      q3[0] = X0[o]; q3[1] = X1[o]; q3[2] = X2[o];
+    }
+    if (col_ok && z + 1 < z1) {
+      const int o = zoff + plane + col;
+      vn[0] = I0[o]; vn[1] = I1[o]; vn[2] = I2[o];
+    }
+    if (h_ok && z + 1 < z1) {
+      const int o = zoff + plane + hcol;
+      hn[0] = X0[o]; hn[1] = X1[o]; hn[2] = X2[o];
     }
     __syncthreads();
     const bool fem_owned = in_box_xy && z > a.blo[2] && z < a.bhi[2];
     if (col_ok && !fem_owned) {
       const bool bzl = z == 0, bzh = z == nz - 1;
       const float wz = (bzl || bzh) ? 2.f : 1.f;
-      const int64_t idx = zoff + col;
+      const int idx = zoff + col;
       float L[3];
 #pragma unroll
       for (int c = 0; c < 3; ++c) {
-        const float xc = cur[c];
+        const float xc = q1[c];
         float sx = 0.f, sy = 0.f, sz = 0.f;
-        if (!bxl) sx += xc - s[c][ty + 1][tx];
-        if (!bxh) sx += xc - s[c][ty + 1][tx + 2];
-        if (!byl) sy += xc - s[c][ty][tx + 1];
-        if (!byh) sy += xc - s[c][ty + 2][tx + 1];
-        if (!bzl) sz += xc - prv[c];
-        if (!bzh) sz += xc - nxt[c];
+        if (!bxl) sx += xc - s[buf][c][ty + 1][tx];
+        if (!bxh) sx += xc - s[buf][c][ty + 1][tx + 2];
+        if (!byl) sy += xc - s[buf][c][ty][tx + 1];
+        if (!byh) sy += xc - s[buf][c][ty + 2][tx + 1];
+        if (!bzl) sz += xc - q0[c];
+        if (!bzh) sz += xc - q2[c];
         L[c] = a.nu2 * (wx * sx + wy * sy + wz * sz);
       }
       const bool on_bnd = bxl || bxh || byl || byh || bzl || bzh;
-      const int bcount = (int)(bxl || bxh) + (int)(byl || byh) + (int)(bzl || bzh);
       float src[3] = {0.f, 0.f, 0.f};
-      int na = 0, nb = 0;
+      int na = 0, nb = 0, bcount = 0;
       int64_t det = -1;
       if (on_bnd) {
+        bcount = (int)(bxl || bxh) + (int)(byl || byh) + (int)(bzl || bzh);
         const unsigned am = a.abs_mask;
         const int fixed = ((am & DD_FACE_BOTTOM) && bzl) + ((am & DD_FACE_XMIN) && bxl) +
                           ((am & DD_FACE_XMAX) && bxh) + ((am & DD_FACE_YMIN) && byl) + ((am & DD_FACE_YMAX) && byh);
@@ -119,38 +159,52 @@ __global__ __launch_bounds__(FD_THREADS) void fd_step_kernel(FdArgs a) {
           for (int c = 0; c < 3; ++c) src[c] -= a.cot_in[det * 3 + c] * sc;
         }
       }
-      if (idx == a.dip_idx) {
+      if ((int64_t)idx == a.dip_idx) {
 #pragma unroll
         for (int c = 0; c < 3; ++c) src[c] += a.dip[c];
       }
       int64_t l0 = -1;
       if (a.iface_out && in_box_xy_closed && z >= a.blo[2] && z <= a.bhi[2])
         l0 = face_lex_index(x - a.blo[0], y - a.blo[1], z - a.blo[2], a.fs[0], a.fs[1], a.fs[2], 63u);
-      const float ba = a.nu * (float)na, bb = a.nu * (float)nb;
-      double e_node = 0.0;
+      float out[3], xn[3];
+      if (na == 0 && nb == 0) {
 #pragma unroll
-      for (int c = 0; c < 3; ++c) {
-        const float inc = a.I[c * N + idx];
-        float out;
-        if (na == 0 && nb == 0)
-          out = inc - L[c] + src[c];
-        else
-          out = ((1.f - bb) * inc - L[c] + src[c] - (ba - bb) * cur[c]) / (1.f + ba);
-        const float xn = cur[c] + out;
-        a.I[c * N + idx] = out;
-        a.X_out[c * N + idx] = xn;
-        if (det >= 0 && a.tr_out) a.tr_out[det * 3 + c] = xn;
-        if (l0 >= 0) a.iface_out[c * a.n_l0 + l0] = xn;
-        if (ENERGY) e_node += (double)out * (double)out + (double)xn * (double)L[c];
+        for (int c = 0; c < 3; ++c) out[c] = v[c] - L[c] + src[c];
+      } else {
+        const float ba = a.nu * (float)na, bb = a.nu * (float)nb;
+#pragma unroll
+        for (int c = 0; c < 3; ++c) out[c] = ((1.f - bb) * v[c] - L[c] + src[c] - (ba - bb) * q1[c]) / (1.f + ba);
       }
-      if (ENERGY) eacc += a.e_coef * ldexp(1.0, -bcount) * e_node;
+#pragma unroll
+      for (int c = 0; c < 3; ++c) xn[c] = q1[c] + out[c];
+      I0[idx] = out[0]; I1[idx] = out[1]; I2[idx] = out[2];
+      a.X_out[idx] = xn[0];
+      a.X_out[a.N + idx] = xn[1];
+      a.X_out[2 * a.N + idx] = xn[2];
+      if (det >= 0 && a.tr_out) {
+#pragma unroll
+        for (int c = 0; c < 3; ++c) a.tr_out[det * 3 + c] = xn[c];
+      }
+      if (l0 >= 0) {
+#pragma unroll
+        for (int c = 0; c < 3; ++c) a.iface_out[c * a.n_l0 + l0] = xn[c];
+      }
+      if (ENERGY) {
+        double e_node = 0.0;
+#pragma unroll
+        for (int c = 0; c < 3; ++c) e_node += (double)out[c] * (double)out[c] + (double)xn[c] * (double)L[c];
+        eacc += a.e_coef * ldexp(1.0, -bcount) * e_node;
+      }
     }
-    __syncthreads();
 #pragma unroll
     for (int c = 0; c < 3; ++c) {
-      prv[c] = cur[c];
-      cur[c] = nxt[c];
+      q0[c] = q1[c];
+      q1[c] = q2[c];
+      q2[c] = q3[c];
+      hv[c] = hn[c];
+      v[c] = vn[c];
     }
+    buf ^= 1;
   }
   if (ENERGY) {
     red[tid] = eacc;
@@ -177,128 +231,209 @@ __global__ __launch_bounds__(FD_THREADS) void fd_step_kernel(FdArgs a) {
 // Layer-0 values come from the interface buffer written by the finite-difference kernel;
 // layer-1 results are also written into the finite-difference grid (the two-node overlap).
 // ---------------------------------------------------------------------------------------
-template <bool ADJ, bool ENERGY>
+template <bool ADJ, bool ENERGY, bool GEOM_LDS>
 __global__ __launch_bounds__(FEM_THREADS) void fem_step_kernel(FemArgs a) {
-  __shared__ float sX[3][FEM_LOC_MAX];
-  __shared__ float sM[ADJ ? 1 : FEM_LOC_MAX];
-  __shared__ float sA[ADJ ? 6 : 3][FEM_OWN_MAX];
+  constexpr int NPT = FEM_OWN_MAX / FEM_THREADS;   // owned nodes per thread in the update
+  constexpr int NA4 = ADJ ? 2 : 1;                 // float4 accumulators per owned node
+  // Dynamic LDS sized from the mesh.  One float4 per node (E_x, E_y, E_z, eps - 1) and per
+  // accumulator, so a node is gathered or scattered with a single 16-byte access; each
+  // accumulator row has 32 trash slots that absorb the contributions to halo nodes.
+  extern __shared__ __align__(16) unsigned char lds[];
+  const int LOC = a.lds_loc, ROW = a.lds_own + 32;
+  float4* sX = reinterpret_cast<float4*>(lds);                // [LOC]
+  float4* sA = sX + LOC;                                      // [NA4][ROW]
+  uint64_t* sE = reinterpret_cast<uint64_t*>(sA + NA4 * ROW);  // [lds_elem] (even)
+  float* sG = reinterpret_cast<float*>(sE + a.lds_elem);       // [n_geom][GEOM_STRIDE]
+  int* sC = reinterpret_cast<int*>(sG + (GEOM_LDS ? a.n_geom * GEOM_STRIDE : 0));   // [ncl + 1]
   __shared__ double red[ENERGY ? FEM_THREADS : 1];
   const int p = blockIdx.x;
   const int tid = threadIdx.x;
   const int o0 = a.own_off[p], no = a.own_off[p + 1] - o0;
   const int h0 = a.halo_off[p], nh = a.halo_off[p + 1] - h0;
   const int nl = no + nh;
+  const int ncl = a.ncol[p], cb = a.col_base[p];
+  const int e_beg = a.col_off[cb], ne = a.col_off[cb + ncl] - e_beg;
   const int64_t n_own = a.n_own, n_l0 = a.n_l0;
 
-  for (int l = tid; l < nl; l += FEM_THREADS) {
-    float v0, v1, v2, m = 0.f;
-    if (l < no) {
-      const int id = o0 + l;
-      v0 = a.X_in[id];
-      v1 = a.X_in[n_own + id];
-      v2 = a.X_in[2 * n_own + id];
-      if (!ADJ) m = a.em1[id];
-    } else {
-      const int hc = a.halo[h0 + l - no];
-      if (hc >= 0) {
-        v0 = a.X_in[hc];
-        v1 = a.X_in[n_own + hc];
-        v2 = a.X_in[2 * n_own + hc];
-        if (!ADJ) m = a.em1[hc];
-      } else {
-        const int64_t q = -1 - (int64_t)hc;
-        v0 = a.iface_in[q];
-        v1 = a.iface_in[n_l0 + q];
-        v2 = a.iface_in[2 * n_l0 + q];
+  // ---- stage: elements, colour offsets, geometry, node values.  Loads are issued in
+  // unrolled batches so that one batch costs one memory latency, not one per iteration.
+  if (tid <= ncl) sC[tid] = a.col_off[cb + tid] - e_beg;
+  constexpr int EB = 8;
+  for (int base = 0; base < ne; base += EB * FEM_THREADS) {
+    uint64_t tmp[EB];
+#pragma unroll
+    for (int k = 0; k < EB; ++k) {
+      const int i = base + k * FEM_THREADS + tid;
+      tmp[k] = i < ne ? a.elems[e_beg + i] : 0ull;
+    }
+#pragma unroll
+    for (int k = 0; k < EB; ++k) {
+      const int i = base + k * FEM_THREADS + tid;
+      if (i < ne) sE[i] = tmp[k];
+    }
+  }
+  if (GEOM_LDS)
+    for (int i = tid; i < a.n_geom * GEOM_STRIDE; i += FEM_THREADS) sG[i] = a.geom[i];
+  constexpr int NB = 4;
+  for (int base = 0; base < nl; base += NB * FEM_THREADS) {
+    int code[NB];
+#pragma unroll
+    for (int k = 0; k < NB; ++k) {
+      const int l = base + k * FEM_THREADS + tid;
+      code[k] = l < no ? o0 + l : (l < nl ? a.halo[h0 + l - no] : 0);
+    }
+    float4 xv[NB];
+#pragma unroll
+    for (int k = 0; k < NB; ++k) {
+      const int l = base + k * FEM_THREADS + tid;
+      xv[k] = make_float4(0.f, 0.f, 0.f, 0.f);
+      if (l < nl && code[k] >= 0) {
+        const int id = code[k];
+        xv[k].x = a.X_in[id];
+        xv[k].y = a.X_in[n_own + id];
+        xv[k].z = a.X_in[2 * n_own + id];
+        if (!ADJ) xv[k].w = a.em1[id];
+      } else if (l < nl) {
+        const int64_t q = -1 - (int64_t)code[k];
+        xv[k].x = a.iface_in[q];
+        xv[k].y = a.iface_in[n_l0 + q];
+        xv[k].z = a.iface_in[2 * n_l0 + q];
       }
     }
-    sX[0][l] = v0;
-    sX[1][l] = v1;
-    sX[2][l] = v2;
-    if (!ADJ) sM[l] = m;
-  }
-  for (int l = tid; l < no; l += FEM_THREADS) {
 #pragma unroll
-    for (int c = 0; c < (ADJ ? 6 : 3); ++c) sA[c][l] = 0.f;
+    for (int k = 0; k < NB; ++k) {
+      const int l = base + k * FEM_THREADS + tid;
+      if (l < nl) sX[l] = xv[k];
+    }
+  }
+  for (int l = tid; l < ROW; l += FEM_THREADS) {
+#pragma unroll
+    for (int c = 0; c < NA4; ++c) sA[c * ROW + l] = make_float4(0.f, 0.f, 0.f, 0.f);
+  }
+  // per-node data of the update, prefetched into registers while the elements run
+  float pI[NPT][3], pc1[NPT], pc2[NPT], pem[NPT];
+  float pwE[NPT][3], pwV[NPT][3], pwVm[NPT][3];
+#pragma unroll
+  for (int j = 0; j < NPT; ++j) {
+    const int l = tid + j * FEM_THREADS;
+    if (l < no) {
+      const int id = o0 + l;
+#pragma unroll
+      for (int c = 0; c < 3; ++c) pI[j][c] = a.I_in[c * n_own + id];
+      pc1[j] = a.c1[id];
+      pc2[j] = a.c2[id];
+      pem[j] = a.em1[id];
+      if (ADJ) {
+#pragma unroll
+        for (int c = 0; c < 3; ++c) {
+          pwE[j][c] = a.wE[c * n_own + id];
+          pwV[j][c] = a.wV[c * n_own + id];
+          pwVm[j][c] = a.wVm[c * n_own + id];
+        }
+      }
+    }
   }
   __syncthreads();
 
-  const int ncl = a.ncol[p], cb = a.col_base[p];
+  // ---- elements, colour by colour (no two elements of a colour share an owned node)
+  const float* __restrict__ G = GEOM_LDS ? sG : a.geom;
+  const int trash = a.lds_own + (tid & 31);
   for (int c = 0; c < ncl; ++c) {
-    const int e0 = a.col_off[cb + c], e1 = a.col_off[cb + c + 1];
+    const int e0 = sC[c], e1 = sC[c + 1];
     for (int e = e0 + tid; e < e1; e += FEM_THREADS) {
-      const uint64_t w = a.elems[e];
-      int v[4];
+      const uint64_t w = sE[e];
+      int v[4], t[4];
 #pragma unroll
-      for (int k = 0; k < 4; ++k) v[k] = (int)((w >> (11 * k)) & 0x7FFu);
-      const float* g = a.geom + ((w >> 44) << 4);
-      float gr[4][3];
+      for (int k = 0; k < 4; ++k) {
+        v[k] = (int)((w >> (11 * k)) & 0x7FFu);
+        t[k] = v[k] < no ? v[k] : trash;
+      }
+      // accumulator reads first: their latency overlaps the element arithmetic
+      float4 acc[4], acd[4];
 #pragma unroll
-      for (int j = 0; j < 4; ++j)
+      for (int k = 0; k < 4; ++k) {
+        acc[k] = sA[t[k]];
+        if (ADJ) acd[k] = sA[ROW + t[k]];
+      }
+      const float4* g4 = reinterpret_cast<const float4*>(G + (int)(w >> 44) * GEOM_STRIDE);
+      // g4[0..2]: grad phi_0..3 (12 floats), g4[3..5]: |K| grad phi_0..3
+      float gr[12], vg[12];
 #pragma unroll
-        for (int d = 0; d < 3; ++d) gr[j][d] = g[3 * j + d];
-      const float vol = g[12];
-      float G[3][3];
+      for (int i = 0; i < 3; ++i) {
+        const float4 a4 = g4[i], b4 = g4[3 + i];
+        gr[4 * i] = a4.x; gr[4 * i + 1] = a4.y; gr[4 * i + 2] = a4.z; gr[4 * i + 3] = a4.w;
+        vg[4 * i] = b4.x; vg[4 * i + 1] = b4.y; vg[4 * i + 2] = b4.z; vg[4 * i + 3] = b4.w;
+      }
+      // Gm[q] = gradient of component q on the element; dv = div of (eps-1)E (forward) or lambda
+      float Gm[3][3];
 #pragma unroll
       for (int q = 0; q < 3; ++q)
 #pragma unroll
-        for (int d = 0; d < 3; ++d) G[q][d] = 0.f;
+        for (int d = 0; d < 3; ++d) Gm[q][d] = 0.f;
       float dv = 0.f;
 #pragma unroll
       for (int j = 0; j < 4; ++j) {
-        const float e0v = sX[0][v[j]], e1v = sX[1][v[j]], e2v = sX[2][v[j]];
+        const float4 x = sX[v[j]];
 #pragma unroll
         for (int d = 0; d < 3; ++d) {
-          G[0][d] += e0v * gr[j][d];
-          G[1][d] += e1v * gr[j][d];
-          G[2][d] += e2v * gr[j][d];
+          Gm[0][d] += x.x * gr[3 * j + d];
+          Gm[1][d] += x.y * gr[3 * j + d];
+          Gm[2][d] += x.z * gr[3 * j + d];
         }
-        const float mj = ADJ ? 1.f : sM[v[j]];
-        dv += mj * (e0v * gr[j][0] + e1v * gr[j][1] + e2v * gr[j][2]);
+        const float dj = x.x * gr[3 * j] + x.y * gr[3 * j + 1] + x.z * gr[3 * j + 2];
+        dv += ADJ ? dj : x.w * dj;
       }
+      if (!ADJ) {
+        // contribution to slot k, component q: |K| grad phi_k . (Gm[q] + dv e_q)
 #pragma unroll
-      for (int q = 0; q < 3; ++q)
+        for (int q = 0; q < 3; ++q) Gm[q][q] += dv;
 #pragma unroll
-        for (int d = 0; d < 3; ++d) G[q][d] *= vol;
-      dv *= vol;
+        for (int k = 0; k < 4; ++k) {
+          const float a0 = vg[3 * k], a1 = vg[3 * k + 1], a2 = vg[3 * k + 2];
+          acc[k].x += a0 * Gm[0][0] + a1 * Gm[0][1] + a2 * Gm[0][2];
+          acc[k].y += a0 * Gm[1][0] + a1 * Gm[1][1] + a2 * Gm[1][2];
+          acc[k].z += a0 * Gm[2][0] + a1 * Gm[2][1] + a2 * Gm[2][2];
+          sA[t[k]] = acc[k];
+        }
+      } else {
 #pragma unroll
-      for (int sl = 0; sl < 4; ++sl) {
-        const int li = v[sl];
-        if (li < no) {
-#pragma unroll
-          for (int q = 0; q < 3; ++q) {
-            const float kc = gr[sl][0] * G[q][0] + gr[sl][1] * G[q][1] + gr[sl][2] * G[q][2];
-            const float dc = gr[sl][q] * dv;
-            if (ADJ) {
-              sA[q][li] += kc;
-              sA[3 + q][li] += dc;
-            } else {
-              sA[q][li] += kc + dc;
-            }
-          }
+        for (int k = 0; k < 4; ++k) {
+          const float a0 = vg[3 * k], a1 = vg[3 * k + 1], a2 = vg[3 * k + 2];
+          acc[k].x += a0 * Gm[0][0] + a1 * Gm[0][1] + a2 * Gm[0][2];
+          acc[k].y += a0 * Gm[1][0] + a1 * Gm[1][1] + a2 * Gm[1][2];
+          acc[k].z += a0 * Gm[2][0] + a1 * Gm[2][1] + a2 * Gm[2][2];
+          acd[k].x += a0 * dv;
+          acd[k].y += a1 * dv;
+          acd[k].z += a2 * dv;
+          sA[t[k]] = acc[k];
+          sA[ROW + t[k]] = acd[k];
         }
       }
     }
     __syncthreads();
   }
 
+  // ---- owned-node update
   double eacc = 0.0;
-  for (int l = tid; l < no; l += FEM_THREADS) {
+#pragma unroll
+  for (int j = 0; j < NPT; ++j) {
+    const int l = tid + j * FEM_THREADS;
+    if (l >= no) continue;
     const int id = o0 + l;
-    const float k1 = a.c1[id], k2 = a.c2[id];
-    float xn[3], inc[3], r[3];
-    if (!ADJ) {
+    const float4 x4 = sX[l], s4 = sA[l];
+    const float4 d4 = ADJ ? sA[ROW + l] : make_float4(0.f, 0.f, 0.f, 0.f);
+    const float xo[3] = {x4.x, x4.y, x4.z};
+    const float q[3] = {d4.x, d4.y, d4.z};
+    float r[3] = {s4.x, s4.y, s4.z};
+    if (ADJ) {
 #pragma unroll
-      for (int c = 0; c < 3; ++c) r[c] = sA[c][l];
-    } else {
-      const float em = a.em1[id];
-#pragma unroll
-      for (int c = 0; c < 3; ++c) r[c] = sA[c][l] + em * sA[3 + c][l];
+      for (int c = 0; c < 3; ++c) r[c] += pem[j] * q[c];
     }
+    float xn[3], inc[3];
 #pragma unroll
     for (int c = 0; c < 3; ++c) {
-      inc[c] = k1 * a.I_in[c * n_own + id] - k2 * r[c];
-      xn[c] = sX[c][l] + inc[c];
+      inc[c] = pc1[j] * pI[j][c] - pc2[j] * r[c];
+      xn[c] = xo[c] + inc[c];
       a.I_out[c * n_own + id] = inc[c];
       a.X_out[c * n_own + id] = xn[c];
     }
@@ -317,7 +452,7 @@ __global__ __launch_bounds__(FEM_THREADS) void fem_step_kernel(FemArgs a) {
       }
     }
     if (ENERGY) {
-      const double me = a.mass_d[id] * (1.0 + (double)a.em1[id]);
+      const double me = a.mass_d[id] * (1.0 + (double)pem[j]);
       double vv = 0.0, er = 0.0;
 #pragma unroll
       for (int c = 0; c < 3; ++c) {
@@ -331,10 +466,196 @@ __global__ __launch_bounds__(FEM_THREADS) void fem_step_kernel(FemArgs a) {
       double ge = 0.0, gm = 0.0, gs = 0.0;
 #pragma unroll
       for (int c = 0; c < 3; ++c) {
-        const double wv = (double)a.wV[c * n_own + id];
-        ge += (double)sA[3 + c][l] * (double)a.wE[c * n_own + id];
+        const double wv = (double)pwV[j][c];
+        ge += (double)q[c] * (double)pwE[j][c];
         gm += (double)inc[c] * wv;
-        gs += (double)xn[c] * (wv + (double)a.wVm[c * n_own + id]);
+        gs += (double)xn[c] * (wv + (double)pwVm[j][c]);
+      }
+      a.g_eps[id] += ge + m * a.inv_dt2 * gm;
+      a.g_sig[id] += m * a.inv_2dt * gs;
+    }
+  }
+  if (ENERGY) {
+    red[tid] = eacc;
+    __syncthreads();
+    for (int w = FEM_THREADS / 2; w > 0; w >>= 1) {
+      if (tid < w) red[tid] += red[tid + w];
+      __syncthreads();
+    }
+    if (tid == 0) a.epart[a.epart_off + p] = red[0];
+  }
+}
+
+// ---------------------------------------------------------------------------------------
+// FEM region, assembled-stencil form.  When every FEM-owned node has the same assembled
+// element star (the Kuhn split of a uniform box: each owned node is surrounded by the same
+// 24 tetrahedra), the lumped-mass P1 operator of the element kernel above is one nodal
+// stencil of 3x3 blocks, assembled once on the host in FP64 from the same element
+// geometry:
+//     (A E)_i = sum_s [ K_s E_{i+o_s} + B_s ((eps - 1) E)_{i+o_s} ],
+//     K_s = sum_K |K| grad phi_i . grad phi_j,  B_s = sum_K |K| grad phi_i (grad phi_j)^T,
+// and for the adjoint (A^T l)_i = sum_s K_s l_{i+o_s} + (eps_i - 1) q_i with
+// q_i = sum_s B_s l_{i+o_s} (B_s^T is the block of the mirrored slot, so the same stencil
+// applies).  Results equal the element form up to floating-point rounding; there is no
+// scatter, hence no colouring and no barrier after the staging.
+// ---------------------------------------------------------------------------------------
+template <bool ADJ, bool ENERGY>
+__global__ __launch_bounds__(FEM_THREADS) void fem_stencil_kernel(FemArgs a) {
+  constexpr int NPT = FEM_OWN_MAX / FEM_THREADS;
+  extern __shared__ __align__(16) unsigned char lds[];
+  float4* sX = reinterpret_cast<float4*>(lds);                   // [box]: E_x, E_y, E_z, eps - 1
+  float* sKB = reinterpret_cast<float*>(sX + a.lds_box);          // [n_slots][12]: K, B (9), pad
+  int* sOff = reinterpret_cast<int*>(sKB + 12 * STENCIL_SLOTS_MAX);  // [n_slots] box offsets
+  __shared__ double red[ENERGY ? FEM_THREADS : 1];
+  const int p = blockIdx.x;
+  const int tid = threadIdx.x;
+  const int ox = a.part_dims[4 * p], oy = a.part_dims[4 * p + 1], oz = a.part_dims[4 * p + 2];
+  const int bbase = a.part_dims[4 * p + 3];
+  const int BX = ox + 2, BY = oy + 2;
+  const int nbox = BX * BY * (oz + 2);
+  const int o0 = a.own_off[p], no = ox * oy * oz;
+  const int ns = a.n_slots;
+  const int64_t n_own = a.n_own, n_l0 = a.n_l0;
+
+  if (tid < ns) {
+    const int dx = a.slot_off[4 * tid], dy = a.slot_off[4 * tid + 1], dz = a.slot_off[4 * tid + 2];
+    sOff[tid] = dx + BX * (dy + BY * dz);
+    sKB[12 * tid] = a.slot_k[tid];
+#pragma unroll
+    for (int q = 0; q < 9; ++q) sKB[12 * tid + 1 + q] = a.slot_b[9 * tid + q];
+  }
+  // stage the box of node values in batches (one memory latency per batch)
+  constexpr int NB = 4;
+  for (int base = 0; base < nbox; base += NB * FEM_THREADS) {
+    int code[NB];
+#pragma unroll
+    for (int k = 0; k < NB; ++k) {
+      const int l = base + k * FEM_THREADS + tid;
+      code[k] = l < nbox ? a.box_codes[bbase + l] : 0;
+    }
+    float4 xv[NB];
+#pragma unroll
+    for (int k = 0; k < NB; ++k) {
+      const int l = base + k * FEM_THREADS + tid;
+      xv[k] = make_float4(0.f, 0.f, 0.f, 0.f);
+      if (l < nbox && code[k] >= 0) {
+        const int id = code[k];
+        xv[k].x = a.X_in[id];
+        xv[k].y = a.X_in[n_own + id];
+        xv[k].z = a.X_in[2 * n_own + id];
+        if (!ADJ) xv[k].w = a.em1[id];
+      } else if (l < nbox) {
+        const int64_t q = -1 - (int64_t)code[k];
+        xv[k].x = a.iface_in[q];
+        xv[k].y = a.iface_in[n_l0 + q];
+        xv[k].z = a.iface_in[2 * n_l0 + q];
+      }
+    }
+#pragma unroll
+    for (int k = 0; k < NB; ++k) {
+      const int l = base + k * FEM_THREADS + tid;
+      if (l < nbox) sX[l] = xv[k];
+    }
+  }
+  // per-node data of the update, prefetched before the barrier
+  float pI[NPT][3], pc1[NPT], pc2[NPT], pem[NPT];
+  float pwE[NPT][3], pwV[NPT][3], pwVm[NPT][3];
+#pragma unroll
+  for (int j = 0; j < NPT; ++j) {
+    const int l = tid + j * FEM_THREADS;
+    if (l < no) {
+      const int id = o0 + l;
+#pragma unroll
+      for (int c = 0; c < 3; ++c) pI[j][c] = a.I_in[c * n_own + id];
+      pc1[j] = a.c1[id];
+      pc2[j] = a.c2[id];
+      pem[j] = a.em1[id];
+      if (ADJ) {
+#pragma unroll
+        for (int c = 0; c < 3; ++c) {
+          pwE[j][c] = a.wE[c * n_own + id];
+          pwV[j][c] = a.wV[c * n_own + id];
+          pwVm[j][c] = a.wVm[c * n_own + id];
+        }
+      }
+    }
+  }
+  __syncthreads();
+
+  double eacc = 0.0;
+#pragma unroll
+  for (int j = 0; j < NPT; ++j) {
+    const int l = tid + j * FEM_THREADS;
+    if (l >= no) continue;
+    const int id = o0 + l;
+    const int ix = l % ox, iy = (l / ox) % oy, iz = l / (ox * oy);
+    const int li = (ix + 1) + BX * ((iy + 1) + BY * (iz + 1));
+    float r[3] = {0.f, 0.f, 0.f}, q[3] = {0.f, 0.f, 0.f};
+    for (int s = 0; s < ns; ++s) {
+      const float4 x = sX[li + sOff[s]];
+      const float* kb = sKB + 12 * s;
+      const float K = kb[0];
+      r[0] += K * x.x;
+      r[1] += K * x.y;
+      r[2] += K * x.z;
+      if (ADJ) {
+        q[0] += kb[1] * x.x + kb[2] * x.y + kb[3] * x.z;
+        q[1] += kb[4] * x.x + kb[5] * x.y + kb[6] * x.z;
+        q[2] += kb[7] * x.x + kb[8] * x.y + kb[9] * x.z;
+      } else {
+        const float w0 = x.w * x.x, w1 = x.w * x.y, w2 = x.w * x.z;
+        r[0] += kb[1] * w0 + kb[2] * w1 + kb[3] * w2;
+        r[1] += kb[4] * w0 + kb[5] * w1 + kb[6] * w2;
+        r[2] += kb[7] * w0 + kb[8] * w1 + kb[9] * w2;
+      }
+    }
+    if (ADJ) {
+#pragma unroll
+      for (int c = 0; c < 3; ++c) r[c] += pem[j] * q[c];
+    }
+    const float4 x4 = sX[li];
+    const float xo[3] = {x4.x, x4.y, x4.z};
+    float xn[3], inc[3];
+#pragma unroll
+    for (int c = 0; c < 3; ++c) {
+      inc[c] = pc1[j] * pI[j][c] - pc2[j] * r[c];
+      xn[c] = xo[c] + inc[c];
+      a.I_out[c * n_own + id] = inc[c];
+      a.X_out[c * n_own + id] = xn[c];
+    }
+    if (a.fd_out) {
+      const int gi = a.own_grid[id];
+      if (gi >= 0) {
+#pragma unroll
+        for (int c = 0; c < 3; ++c) a.fd_out[c * a.N + gi] = xn[c];
+      }
+    }
+    if (!ADJ && a.ck_X) {
+#pragma unroll
+      for (int c = 0; c < 3; ++c) {
+        a.ck_X[c * n_own + id] = xn[c];
+        a.ck_I[c * n_own + id] = inc[c];
+      }
+    }
+    if (ENERGY) {
+      const double me = a.mass_d[id] * (1.0 + (double)pem[j]);
+      double vv = 0.0, er = 0.0;
+#pragma unroll
+      for (int c = 0; c < 3; ++c) {
+        vv += (double)inc[c] * (double)inc[c];
+        er += (double)xn[c] * (double)r[c];
+      }
+      eacc += me * a.inv_2dt2 * vv + 0.5 * er;
+    }
+    if (ADJ && a.own_grid[id] < 0) {
+      const double m = a.mass_d[id];
+      double ge = 0.0, gm = 0.0, gs = 0.0;
+#pragma unroll
+      for (int c = 0; c < 3; ++c) {
+        const double wv = (double)pwV[j][c];
+        ge += (double)q[c] * (double)pwE[j][c];
+        gm += (double)inc[c] * wv;
+        gs += (double)xn[c] * (wv + (double)pwVm[j][c]);
       }
       a.g_eps[id] += ge + m * a.inv_dt2 * gm;
       a.g_sig[id] += m * a.inv_2dt * gs;
@@ -431,23 +752,69 @@ static int grid_for(int64_t n, int block = 256, int cap = 4096) {
   return (int)g;
 }
 
-void launch_fd(const FdArgs& a, hipStream_t s, bool energy) {
+template <int ZC>
+static void launch_fd_zc(const FdArgs& a, hipStream_t s, bool energy) {
   const int grid = a.per_xcd * N_XCD;
   if (energy)
-    hipLaunchKernelGGL(fd_step_kernel<true>, dim3(grid), dim3(FD_THREADS), 0, s, a);
+    hipLaunchKernelGGL((fd_step_kernel<ZC, true>), dim3(grid), dim3(FD_THREADS), 0, s, a);
   else
-    hipLaunchKernelGGL(fd_step_kernel<false>, dim3(grid), dim3(FD_THREADS), 0, s, a);
+    hipLaunchKernelGGL((fd_step_kernel<ZC, false>), dim3(grid), dim3(FD_THREADS), 0, s, a);
+}
+
+void launch_fd(const FdArgs& a, hipStream_t s, bool energy) {
+  switch (a.zc) {
+    case 8: launch_fd_zc<8>(a, s, energy); break;
+    case 32: launch_fd_zc<32>(a, s, energy); break;
+    default: launch_fd_zc<16>(a, s, energy); break;
+  }
+}
+
+size_t fem_lds_bytes(const FemArgs& a, bool adj) {
+  const bool geom_lds = a.n_geom <= FEM_GEOM_LDS;
+  size_t f = (size_t)a.lds_loc * 4 + (size_t)(adj ? 8 : 4) * (a.lds_own + 32);
+  f += (size_t)a.lds_elem * 2 + (geom_lds ? (size_t)a.n_geom * GEOM_STRIDE : 0);
+  f += FEM_COLORS_MAX + 1;   // colour offsets
+  return f * 4;
+}
+
+template <bool ADJ, bool ENERGY>
+static void launch_fem_t(const FemArgs& a, int n_part, hipStream_t s) {
+  const size_t lds = fem_lds_bytes(a, ADJ);
+  if (lds > 65536) {
+    (void)hipFuncSetAttribute((const void*)fem_step_kernel<ADJ, ENERGY, true>,
+                              hipFuncAttributeMaxDynamicSharedMemorySize, (int)lds);
+    (void)hipFuncSetAttribute((const void*)fem_step_kernel<ADJ, ENERGY, false>,
+                              hipFuncAttributeMaxDynamicSharedMemorySize, (int)lds);
+  }
+  if (a.n_geom <= FEM_GEOM_LDS)
+    hipLaunchKernelGGL((fem_step_kernel<ADJ, ENERGY, true>), dim3(n_part), dim3(FEM_THREADS), lds, s, a);
+  else
+    hipLaunchKernelGGL((fem_step_kernel<ADJ, ENERGY, false>), dim3(n_part), dim3(FEM_THREADS), lds, s, a);
 }
 
 void launch_fem_fwd(const FemArgs& a, int n_part, hipStream_t s, bool energy) {
   if (energy)
-    hipLaunchKernelGGL((fem_step_kernel<false, true>), dim3(n_part), dim3(FEM_THREADS), 0, s, a);
+    launch_fem_t<false, true>(a, n_part, s);
   else
-    hipLaunchKernelGGL((fem_step_kernel<false, false>), dim3(n_part), dim3(FEM_THREADS), 0, s, a);
+    launch_fem_t<false, false>(a, n_part, s);
 }
 
-void launch_fem_adj(const FemArgs& a, int n_part, hipStream_t s) {
-  hipLaunchKernelGGL((fem_step_kernel<true, false>), dim3(n_part), dim3(FEM_THREADS), 0, s, a);
+void launch_fem_adj(const FemArgs& a, int n_part, hipStream_t s) { launch_fem_t<true, false>(a, n_part, s); }
+
+static size_t stencil_lds_bytes(const FemArgs& a) {
+  return (size_t)a.lds_box * 16 + 12 * 4 * STENCIL_SLOTS_MAX + 4 * STENCIL_SLOTS_MAX;
+}
+
+void launch_fem_stencil_fwd(const FemArgs& a, int n_part, hipStream_t s, bool energy) {
+  const size_t lds = stencil_lds_bytes(a);
+  if (energy)
+    hipLaunchKernelGGL((fem_stencil_kernel<false, true>), dim3(n_part), dim3(FEM_THREADS), lds, s, a);
+  else
+    hipLaunchKernelGGL((fem_stencil_kernel<false, false>), dim3(n_part), dim3(FEM_THREADS), lds, s, a);
+}
+
+void launch_fem_stencil_adj(const FemArgs& a, int n_part, hipStream_t s) {
+  hipLaunchKernelGGL((fem_stencil_kernel<true, false>), dim3(n_part), dim3(FEM_THREADS), stencil_lds_bytes(a), s, a);
 }
 
 void launch_energy_reduce(const double* part, int n, double* out, hipStream_t s) {

@@ -71,7 +71,7 @@ bool tet_geometry(const double p[4][3], double grad[4][3], double* vol) {
 
 }  // namespace
 
-std::string build_mesh(const dd_problem_desc& d, HostMesh& m) {
+std::string build_mesh(const dd_problem_desc& d, HostMesh& m, const int pb[3]) {
   Lattice L;
   for (int a = 0; a < 3; ++a) {
     L.c[a] = d.fem_cells[a];
@@ -82,7 +82,10 @@ std::string build_mesh(const dd_problem_desc& d, HostMesh& m) {
   m.n_own = (int64_t)ow[0] * ow[1] * ow[2];
   m.n_l0 = face_lex_count(L.s[0], L.s[1], L.s[2], 63u);
   int npb[3];
-  for (int a = 0; a < 3; ++a) npb[a] = (ow[a] + FEM_PB - 1) / FEM_PB;
+  for (int a = 0; a < 3; ++a) {
+    if (pb[a] < 1 || pb[0] * pb[1] * pb[2] > FEM_OWN_MAX) return "bad FEM partition block";
+    npb[a] = (ow[a] + pb[a] - 1) / pb[a];
+  }
   m.n_part = npb[0] * npb[1] * npb[2];
 
   // internal numbering: partition-major, lexicographic inside the block
@@ -101,9 +104,9 @@ std::string build_mesh(const dd_problem_desc& d, HostMesh& m) {
     for (int pz = 0; pz < npb[2]; ++pz)
       for (int py = 0; py < npb[1]; ++py)
         for (int px = 0; px < npb[0]; ++px, ++p) {
-          const int lo[3] = {1 + px * FEM_PB, 1 + py * FEM_PB, 1 + pz * FEM_PB};
-          const int hi[3] = {std::min(lo[0] + FEM_PB, L.c[0]), std::min(lo[1] + FEM_PB, L.c[1]),
-                             std::min(lo[2] + FEM_PB, L.c[2])};
+          const int lo[3] = {1 + px * pb[0], 1 + py * pb[1], 1 + pz * pb[2]};
+          const int hi[3] = {std::min(lo[0] + pb[0], L.c[0]), std::min(lo[1] + pb[1], L.c[1]),
+                             std::min(lo[2] + pb[2], L.c[2])};
           prange[p] = {lo[0], hi[0], lo[1], hi[1], lo[2], hi[2]};
           m.own_off[p] = next;
           for (int z = lo[2]; z < hi[2]; ++z)
@@ -139,8 +142,10 @@ std::string build_mesh(const dd_problem_desc& d, HostMesh& m) {
     if (it != geom_ids.end()) return it->second;
     const int id = (int)geom_ids.size();
     geom_ids.emplace(key, id);
-    for (int i = 0; i < 13; ++i) m.geom.push_back(f[i]);
-    for (int i = 13; i < 16; ++i) m.geom.push_back(0.f);
+    for (int i = 0; i < 12; ++i) m.geom.push_back(f[i]);                       // grad phi_j
+    for (int i = 0; i < 12; ++i) m.geom.push_back((float)((double)vol * g[i / 3][i % 3]));  // |K| grad phi_j
+    m.geom.push_back(f[12]);                                                     // |K|
+    for (int i = 25; i < GEOM_STRIDE; ++i) m.geom.push_back(0.f);
     return id;
   };
 
@@ -152,6 +157,12 @@ std::string build_mesh(const dd_problem_desc& d, HostMesh& m) {
   m.col_off.clear();
   m.elems.clear();
   m.halo.clear();
+  m.part_dims.assign(4 * m.n_part, 0);
+  m.box_codes.clear();
+  // assembled stencil per owned node: 27 lattice offsets x (K_ij, B_ij), FP64
+  std::vector<double> ref_st;               // stencil of the first owned node (FP64)
+  std::vector<float> ref32;
+  m.stencil_ok = true;
   for (int p = 0; p < m.n_part; ++p) {
     const auto& r = prange[p];
     const int o0 = m.own_off[p], no = m.own_off[p + 1] - o0;
@@ -189,7 +200,10 @@ std::string build_mesh(const dd_problem_desc& d, HostMesh& m) {
     hcodes.erase(std::unique(hcodes.begin(), hcodes.end()), hcodes.end());
     const int nl = no + (int)hcodes.size();
     if (nl > FEM_LOC_MAX || no > FEM_OWN_MAX) return "FEM partition exceeds local node limit";
+    if ((int)els.size() > FEM_ELEM_MAX) return "FEM partition exceeds the element limit";
     m.max_loc = std::max(m.max_loc, nl);
+    m.max_own = std::max(m.max_own, no);
+    m.max_elem = std::max(m.max_elem, (int)els.size());
     std::map<int, int> hloc;
     for (size_t i = 0; i < hcodes.size(); ++i) hloc[hcodes[i]] = no + (int)i;
     m.halo_off[p] = (int)m.halo.size();
@@ -216,15 +230,51 @@ std::string build_mesh(const dd_problem_desc& d, HostMesh& m) {
         if (pk[i].loc[k] < no) used[pk[i].loc[k]] |= (1ull << c);
       ncol = std::max(ncol, c + 1);
     }
-    // lumped mass contributions to this partition's owned nodes (each element of the
-    // mesh that touches an owned node is present here exactly once)
+    // lumped mass and assembled stencil of this partition's owned nodes (each element
+    // of the mesh that touches an owned node is present here exactly once)
+    std::vector<double> st((size_t)no * 27 * 10, 0.0);   // per node, slot: K, B00..B22
     for (size_t i = 0; i < els.size(); ++i) {
       double p4[4][3], g4[4][3], v;
       for (int j = 0; j < 4; ++j)
         for (int a = 0; a < 3; ++a) p4[j][a] = d.h * (double)(els[i].v[j][a] - els[i].v[0][a]);
       tet_geometry(p4, g4, &v);
-      for (int k = 0; k < 4; ++k)
-        if (pk[i].loc[k] < no) m.mass[o0 + pk[i].loc[k]] += v / 4.0;
+      for (int k = 0; k < 4; ++k) {
+        if (pk[i].loc[k] >= no) continue;
+        m.mass[o0 + pk[i].loc[k]] += v / 4.0;
+        for (int j = 0; j < 4; ++j) {
+          int slot = 0, mul = 1;
+          for (int a = 0; a < 3; ++a, mul *= 3) {
+            const int off = els[i].v[j][a] - els[i].v[k][a];
+            if (off < -1 || off > 1) m.stencil_ok = false;
+            slot += (std::min(std::max(off, -1), 1) + 1) * mul;
+          }
+          double* t = &st[((size_t)pk[i].loc[k] * 27 + slot) * 10];
+          t[0] += v * (g4[k][0] * g4[j][0] + g4[k][1] * g4[j][1] + g4[k][2] * g4[j][2]);
+          for (int r = 0; r < 3; ++r)
+            for (int c = 0; c < 3; ++c) t[1 + 3 * r + c] += v * g4[k][r] * g4[j][c];
+        }
+      }
+    }
+    for (int l = 0; l < no && m.stencil_ok; ++l) {
+      std::vector<float> s32(270);
+      for (int q = 0; q < 270; ++q) s32[q] = (float)st[(size_t)l * 270 + q];
+      if (ref32.empty()) {
+        ref32 = s32;
+        ref_st.assign(st.begin() + (size_t)l * 270, st.begin() + (size_t)(l + 1) * 270);
+      } else if (std::memcmp(s32.data(), ref32.data(), 270 * sizeof(float)) != 0) {
+        m.stencil_ok = false;
+      }
+    }
+    {
+      const int ox = r[1] - r[0], oy = r[3] - r[2], oz = r[5] - r[4];
+      m.part_dims[4 * p] = ox;
+      m.part_dims[4 * p + 1] = oy;
+      m.part_dims[4 * p + 2] = oz;
+      m.part_dims[4 * p + 3] = (int)m.box_codes.size();
+      for (int z = r[4] - 1; z <= r[5]; ++z)
+        for (int y = r[2] - 1; y <= r[3]; ++y)
+          for (int x = r[0] - 1; x <= r[1]; ++x) m.box_codes.push_back(lat2int[L.idx(x, y, z)]);
+      m.max_box = std::max(m.max_box, (ox + 2) * (oy + 2) * (oz + 2));
     }
     m.max_colors = std::max(m.max_colors, ncol);
     std::stable_sort(pk.begin(), pk.end(), [](const Pk& a, const Pk& b) { return a.color < b.color; });
@@ -248,6 +298,27 @@ std::string build_mesh(const dd_problem_desc& d, HostMesh& m) {
   }
   m.halo_off[m.n_part] = (int)m.halo.size();
   m.n_geom = (int)geom_ids.size();
+  // compress the shared stencil to its non-zero slots
+  m.n_slots = 0;
+  m.slot_off.clear();
+  m.slot_k.clear();
+  m.slot_b.clear();
+  if (m.stencil_ok && !ref32.empty()) {
+    for (int slot = 0; slot < 27; ++slot) {
+      bool nz = false;
+      for (int q = 0; q < 10; ++q) nz |= ref32[slot * 10 + q] != 0.f;
+      if (!nz) continue;
+      m.slot_off.push_back(slot % 3 - 1);
+      m.slot_off.push_back((slot / 3) % 3 - 1);
+      m.slot_off.push_back(slot / 9 - 1);
+      m.slot_off.push_back(0);
+      m.slot_k.push_back(ref32[slot * 10]);
+      for (int q = 1; q < 10; ++q) m.slot_b.push_back(ref32[slot * 10 + q]);
+      ++m.n_slots;
+    }
+  } else {
+    m.stencil_ok = false;
+  }
   return std::string();
 }
 
@@ -258,12 +329,14 @@ std::string build_mesh(const dd_problem_desc& d, HostMesh& m) {
 // consumes (partition halos, colours, packed connectivity, geometry table), in FP64 and
 // sequentially, checking every index against its bound and every colour for conflicts.
 // ---------------------------------------------------------------------------------------
-extern "C" int dd_debug_fem_apply(const dd_problem_desc* d, const double* eps, const double* E, int adjoint,
+extern "C" int dd_debug_fem_apply(const dd_problem_desc* d, const double* eps, const double* E, int flags,
                                   double* out, int64_t* stats) {
+  const bool adjoint = (flags & 1) != 0, stencil = (flags & 2) != 0;
   using namespace dd;
   if (!d || !eps || !E || !out) return DD_ERR_INVALID_ARG;
   HostMesh m;
-  if (!build_mesh(*d, m).empty()) return DD_ERR_UNSUPPORTED;
+  const int pb[3] = {FEM_PB, FEM_PB, FEM_PB};
+  if (!build_mesh(*d, m, pb).empty()) return DD_ERR_UNSUPPORTED;
   const int s[3] = {d->fem_cells[0] + 1, d->fem_cells[1] + 1, d->fem_cells[2] + 1};
   const int64_t n_own = m.n_own, n_l0 = m.n_l0;
   std::vector<double> X(3 * n_own), em1(n_own), iface(3 * n_l0, 0.0);
@@ -286,7 +359,41 @@ extern "C" int dd_debug_fem_apply(const dd_problem_desc* d, const double* eps, c
       }
   for (int64_t i = 0; i < 3 * m.n_fem; ++i) out[i] = 0.0;
   int64_t n_elem = 0;
-  for (int p = 0; p < m.n_part; ++p) {
+  if (stencil) {
+    if (!m.stencil_ok) return DD_ERR_UNSUPPORTED;
+    for (int p = 0; p < m.n_part; ++p) {
+      const int ox = m.part_dims[4 * p], oy = m.part_dims[4 * p + 1], oz = m.part_dims[4 * p + 2];
+      const int base = m.part_dims[4 * p + 3], BX = ox + 2, BY = oy + 2, nbox = BX * BY * (oz + 2);
+      const int o0 = m.own_off[p];
+      if (ox * oy * oz != m.own_off[p + 1] - o0 || nbox > m.max_box) return DD_ERR_UNSUPPORTED;
+      std::vector<double> bx(4 * nbox);
+      for (int l = 0; l < nbox; ++l) {
+        const int code = m.box_codes[base + l];
+        if (code >= n_own) return DD_ERR_UNSUPPORTED;
+        for (int c = 0; c < 3; ++c) bx[4 * l + c] = code >= 0 ? X[c * n_own + code] : iface[c * n_l0 + (-1 - code)];
+        bx[4 * l + 3] = code >= 0 ? em1[code] : 0.0;
+        if (code < 0 && -1 - code >= n_l0) return DD_ERR_UNSUPPORTED;
+      }
+      for (int l = 0; l < ox * oy * oz; ++l) {
+        const int ix = l % ox, iy = (l / ox) % oy, iz = l / (ox * oy);
+        const int li = (ix + 1) + BX * ((iy + 1) + BY * (iz + 1));
+        double r[3] = {0, 0, 0}, q[3] = {0, 0, 0};
+        for (int s = 0; s < m.n_slots; ++s) {
+          const int n = li + m.slot_off[4 * s] + BX * (m.slot_off[4 * s + 1] + BY * m.slot_off[4 * s + 2]);
+          if (n < 0 || n >= nbox) return DD_ERR_UNSUPPORTED;
+          const double* x = &bx[4 * n];
+          const double w = adjoint ? 1.0 : x[3];
+          for (int c = 0; c < 3; ++c) {
+            r[c] += (double)m.slot_k[s] * x[c];
+            for (int e = 0; e < 3; ++e) q[c] += (double)m.slot_b[9 * s + 3 * c + e] * w * x[e];
+          }
+        }
+        const int api = m.own_api[o0 + l];
+        for (int c = 0; c < 3; ++c) out[(int64_t)api * 3 + c] = r[c] + (adjoint ? em1[o0 + l] : 1.0) * q[c];
+      }
+    }
+  }
+  for (int p = 0; p < m.n_part && !stencil; ++p) {
     const int o0 = m.own_off[p], no = m.own_off[p + 1] - o0;
     const int h0 = m.halo_off[p], nh = m.halo_off[p + 1] - h0;
     const int nl = no + nh;
@@ -322,7 +429,7 @@ extern "C" int dd_debug_fem_apply(const dd_problem_desc* d, const double* eps, c
         }
         const uint64_t gid = w >> 44;
         if ((int64_t)gid >= m.n_geom) return DD_ERR_UNSUPPORTED;
-        const float* g = &m.geom[16 * gid];
+        const float* g = &m.geom[GEOM_STRIDE * gid];
         double G[3][3] = {{0}}, dv = 0.0;
         for (int j = 0; j < 4; ++j) {
           const double mj = adjoint ? 1.0 : sM[v[j]];
@@ -330,7 +437,7 @@ extern "C" int dd_debug_fem_apply(const dd_problem_desc* d, const double* eps, c
             for (int a = 0; a < 3; ++a) G[q][a] += sX[q * nl + v[j]] * g[3 * j + a];
           for (int a = 0; a < 3; ++a) dv += mj * sX[a * nl + v[j]] * g[3 * j + a];
         }
-        const double vol = g[12];
+        const double vol = g[24];
         for (int k = 0; k < 4; ++k) {
           if (v[k] >= no) continue;
           if (touched[v[k]]) return DD_ERR_UNSUPPORTED;  // two elements of one colour share an owned node
@@ -359,6 +466,7 @@ extern "C" int dd_debug_fem_apply(const dd_problem_desc* d, const double* eps, c
     stats[4] = n_elem;
     stats[5] = m.n_own;
     stats[6] = m.n_l0;
+    stats[7] = m.stencil_ok ? m.n_slots : 0;
   }
   return DD_OK;
 }

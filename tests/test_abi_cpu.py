@@ -27,9 +27,6 @@ def lib():
         from paper_2508_07780_amd import build
         build.build(verbose=False)
     lib = _lib.load()
-    lib.dd_debug_fem_apply.argtypes = [ctypes.POINTER(_lib.ProblemDesc), ctypes.c_void_p, ctypes.c_void_p,
-                                       ctypes.c_int32, ctypes.c_void_p, ctypes.c_void_p]
-    lib.dd_debug_fem_apply.restype = ctypes.c_int
     return lib
 
 
@@ -107,12 +104,13 @@ def test_fem_data_path_reproduces_oracle_operator(lib, name):
     E = rng.standard_normal((d.N, 3))
     Ef = np.ascontiguousarray(E[d.fem_grid])
     out = np.zeros((d.n_fem, 3))
-    st = np.zeros(7, dtype=np.int64)
+    st = np.zeros(8, dtype=np.int64)
     c = _lib.make_desc(w.desc)
     eps = np.ascontiguousarray(w.eps)
     own = d.fem_owned
-    for adj, ref in ((0, d.apply_A(E)), (1, d.apply_AT(E))):
-        rc = lib.dd_debug_fem_apply(ctypes.byref(c), eps.ctypes.data, Ef.ctypes.data, adj, out.ctypes.data,
+    # flags: bit 0 = transpose, bit 1 = assembled-stencil data instead of element data
+    for flags, ref in ((0, d.apply_A(E)), (1, d.apply_AT(E)), (2, d.apply_A(E)), (3, d.apply_AT(E))):
+        rc = lib.dd_debug_fem_apply(ctypes.byref(c), eps.ctypes.data, Ef.ctypes.data, flags, out.ctypes.data,
                                     st.ctypes.data)
         assert rc == 0
         r = ref[d.fem_grid]
@@ -121,3 +119,4 @@ def test_fem_data_path_reproduces_oracle_operator(lib, name):
         assert np.all(out[~own] == 0)
     assert st[5] == own.sum() and st[6] == (d.fem_layer == 0).sum()
     assert st[1] <= 64 and st[2] <= 1024
+    assert st[7] == 15      # Kuhn star: self + 14 edge neighbours

@@ -229,3 +229,25 @@ def test_autograd_function_matches_c_abi(torch_cuda):
     ag = adjoint_gradient(d, cot, fw)
     assert _rel(eps.grad.cpu().numpy(), ag["g_eps"]) <= GRAD_TOL
     assert _rel(sig.grad.cpu().numpy(), ag["g_sigma"]) <= GRAD_TOL
+
+
+@pytest.mark.parametrize("name", ["ragged", "skinlet"])
+def test_element_colored_fem_path(torch_cuda, name, monkeypatch):
+    """The element-colored FEM kernel (general tetrahedral meshes) against the oracle."""
+    torch = torch_cuda
+    monkeypatch.setenv("DD_FEM_PATH", "element")
+    w = synth.small(name)
+    print(f"[gpu] element path {name}", flush=True)
+    d = _oracle(w)
+    fw = forward(d, w.sources[0])
+    cot = (0.3 * fw["traces"]).astype(np.float32)
+    ag = adjoint_gradient(d, cot.astype(np.float64), fw)
+    p = _gpu_problem(torch, w)
+    tr = p.forward(w.sources, save=True)
+    p.adjoint(torch.tensor(cot[None], device="cuda"))
+    ge, gs = p.gradient()
+    e0 = _rel(tr[0].cpu().numpy(), fw["traces"])
+    e1 = _rel(ge.cpu().numpy(), ag["g_eps"])
+    e2 = _rel(gs.cpu().numpy(), ag["g_sigma"])
+    _report(check="element_path", case=name, trace_rel_l2=f"{e0:.3e}", g_eps_rel_l2=f"{e1:.3e}", g_sigma_rel_l2=f"{e2:.3e}")
+    assert e0 <= TRACE_TOL and e1 <= GRAD_TOL and e2 <= GRAD_TOL
