@@ -153,7 +153,9 @@ const char* dd_last_error(const dd_problem* p);
  * `kind` must move (each field value read or written once). */
 enum {
   DD_PROF_FD_FWD = 0, DD_PROF_FEM_FWD = 1, DD_PROF_FD_ADJ = 2, DD_PROF_FEM_ADJ = 3,
-  DD_PROF_FEM_RECOMPUTE = 4, DD_PROF_KINDS = 5
+  DD_PROF_FEM_RECOMPUTE = 4,
+  DD_PROF_STEP_FWD = 5, DD_PROF_STEP_ADJ = 6,  /* fused FD + FEM step launches */
+  DD_PROF_KINDS = 7
 };
 int dd_profile_enable(dd_problem* p, int32_t enable);
 int dd_profile_read(dd_problem* p, int32_t kind, double* total_ms, int64_t* launches, int32_t reset);

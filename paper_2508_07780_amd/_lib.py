@@ -18,8 +18,9 @@ EXPORTS = [
     "dd_profile_enable", "dd_profile_read", "dd_algorithmic_bytes", "dd_debug_fem_apply",
 ]
 
-PROF_FD_FWD, PROF_FEM_FWD, PROF_FD_ADJ, PROF_FEM_ADJ, PROF_FEM_RECOMPUTE = range(5)
-PROF_NAMES = ["fd_step_fwd", "fem_step_fwd", "fd_step_adj", "fem_step_adj", "fem_step_recompute"]
+PROF_FD_FWD, PROF_FEM_FWD, PROF_FD_ADJ, PROF_FEM_ADJ, PROF_FEM_RECOMPUTE, PROF_STEP_FWD, PROF_STEP_ADJ = range(7)
+PROF_NAMES = ["fd_step_fwd", "fem_step_fwd", "fd_step_adj", "fem_step_adj", "fem_step_recompute",
+              "step_fwd", "step_adj"]
 
 
 class ProblemDesc(ctypes.Structure):

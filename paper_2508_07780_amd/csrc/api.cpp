@@ -48,7 +48,8 @@ struct dd_problem {
   // FD and FEM launches of one step run concurrently on the caller's stream and `aux`
   hipStream_t aux = nullptr;
   hipEvent_t ev_fd = nullptr, ev_fem = nullptr;
-  bool overlap = true;
+  bool overlap = false;   // measured slower than one stream (cross-stream waits per step)
+  bool fused = true;      // one launch per step (FD tiles + stencil FEM partitions)
   bool saved = false;
   int saved_n_src = 0;
   double *g_eps = nullptr, *g_sig = nullptr;
@@ -58,7 +59,7 @@ struct dd_problem {
   // kernel timing: event pairs around each step launch, per launch kind
   bool prof = false;
   std::vector<hipEvent_t> ev[DD_PROF_KINDS];
-  size_t ev_used[DD_PROF_KINDS] = {0, 0, 0, 0, 0};
+  size_t ev_used[DD_PROF_KINDS] = {};
 };
 
 namespace {
@@ -199,6 +200,7 @@ FemArgs fem_base(const dd_problem* p) {
   a.lds_loc = p->lds_loc; a.lds_own = p->lds_own; a.lds_elem = p->lds_elem;
   a.part_dims = p->part_dims; a.box_codes = p->box_codes; a.slot_off = p->slot_off;
   a.slot_k = p->slot_k; a.slot_b = p->slot_b; a.n_slots = p->n_slots; a.lds_box = p->lds_box;
+  a.n_part = p->n_part;
   a.em1 = p->em1; a.c1 = p->c1; a.c2 = p->c2; a.mass_d = p->mass_d;
   a.n_own = p->n_own; a.n_l0 = p->n_l0; a.N = p->N;
   a.epart_off = p->n_tiles;
@@ -328,9 +330,13 @@ int run_forward(dd_problem* p, const dd_source& src, int s, float* traces, bool 
     fa.cot_in = nullptr;
     fa.iface_out = save ? hist + (n + 1) * 3 * n_l0 : p->iring + nxt * 3 * n_l0;
     fa.epart = energy ? p->epart : nullptr;
-    long ps = prof_begin(p, DD_PROF_FD_FWD, st);
-    launch_fd(fa, st, energy != nullptr);
-    prof_end(p, DD_PROF_FD_FWD, ps, st);
+    const bool fused = p->use_stencil && p->fused;
+    long ps = -1;
+    if (!fused) {
+      ps = prof_begin(p, DD_PROF_FD_FWD, st);
+      launch_fd(fa, st, energy != nullptr);
+      prof_end(p, DD_PROF_FD_FWD, ps, st);
+    }
 
     ea.X_in = p->Efem[cur];
     ea.X_out = p->Efem[nxt];
@@ -345,10 +351,16 @@ int run_forward(dd_problem* p, const dd_source& src, int s, float* traces, bool 
       ea.ck_X = ck + ((n + 1) / K) * 6 * n_own;
     ea.ck_I = ea.ck_X ? ea.ck_X + 3 * n_own : nullptr;
     ea.epart = energy ? p->epart : nullptr;
-    ps = prof_begin(p, DD_PROF_FEM_FWD, sf);
-    fem_fwd(p, ea, sf, energy != nullptr);
-    prof_end(p, DD_PROF_FEM_FWD, ps, sf);
-    step_barrier(p, st);
+    if (fused) {
+      ps = prof_begin(p, DD_PROF_STEP_FWD, st);
+      launch_step(fa, ea, st, false, energy != nullptr);
+      prof_end(p, DD_PROF_STEP_FWD, ps, st);
+    } else {
+      ps = prof_begin(p, DD_PROF_FEM_FWD, sf);
+      fem_fwd(p, ea, sf, energy != nullptr);
+      prof_end(p, DD_PROF_FEM_FWD, ps, sf);
+      step_barrier(p, st);
+    }
     if (energy) launch_energy_reduce(p->epart, p->n_tiles + p->n_part, energy + (int64_t)s * nt + n, st);
   }
   join_streams(p, st);
@@ -400,9 +412,13 @@ int run_adjoint(dd_problem* p, int s, const float* cot, hipStream_t st) {
       fa.tr_out = nullptr;
       fa.cot_in = cot + ((int64_t)s * nt + (k - 1)) * p->n_det * 3;
       fa.iface_out = p->iring + prv * 3 * n_l0;
-      long ps = prof_begin(p, DD_PROF_FD_ADJ, st);
-      launch_fd(fa, st, false);
-      prof_end(p, DD_PROF_FD_ADJ, ps, st);
+      const bool fused = p->use_stencil && p->fused;
+      long ps = -1;
+      if (!fused) {
+        ps = prof_begin(p, DD_PROF_FD_ADJ, st);
+        launch_fd(fa, st, false);
+        prof_end(p, DD_PROF_FD_ADJ, ps, st);
+      }
 
       ea.X_in = p->Efem[cur];
       ea.X_out = p->Efem[prv];
@@ -412,10 +428,16 @@ int run_adjoint(dd_problem* p, int s, const float* cot, hipStream_t st) {
       ea.wE = wE(k - k0);
       ea.wV = wV(k - k0);
       ea.wVm = wV(k - 1 - k0);
-      ps = prof_begin(p, DD_PROF_FEM_ADJ, sf);
-      fem_adj(p, ea, sf);
-      prof_end(p, DD_PROF_FEM_ADJ, ps, sf);
-      step_barrier(p, st);
+      if (fused) {
+        ps = prof_begin(p, DD_PROF_STEP_ADJ, st);
+        launch_step(fa, ea, st, true, false);
+        prof_end(p, DD_PROF_STEP_ADJ, ps, st);
+      } else {
+        ps = prof_begin(p, DD_PROF_FEM_ADJ, sf);
+        fem_adj(p, ea, sf);
+        prof_end(p, DD_PROF_FEM_ADJ, ps, sf);
+        step_barrier(p, st);
+      }
     }
   }
   join_streams(p, st);
@@ -530,6 +552,7 @@ int dd_create(const dd_problem_desc* desc, dd_problem** out) {
   p->per_xcd = (p->n_tiles + N_XCD - 1) / N_XCD;
   p->n_ck = (int)((desc->n_steps + desc->ckpt_every - 1) / desc->ckpt_every);
   if (const char* ov = std::getenv("DD_OVERLAP")) p->overlap = std::atoi(ov) != 0;
+  if (const char* fu = std::getenv("DD_FUSED")) p->fused = std::atoi(fu) != 0;
   int rc = DD_OK;
   auto chk = [&](int r) { if (r && !rc) rc = r; };
   chk(upload(p, &p->own_off, m.own_off));
@@ -725,6 +748,13 @@ int dd_algorithmic_bytes(const dd_problem* p, int32_t kind, double* bytes_per_la
     case DD_PROF_FEM_ADJ:
       // adjoint state + coefficients + forward window (E^k, V^k, V^{k-1}) + FP64 gradient read/write (free nodes)
       b = 48.0 * n_own + 12.0 * n_own + 12.0 * n_l0 + 12.0 * n_l1 + 36.0 * n_own + 32.0 * (n_own - n_l1);
+      break;
+    case DD_PROF_STEP_FWD:
+      b = 48.0 * n_fd + 12.0 * n_det + 12.0 * n_l0 + 48.0 * n_own + 12.0 * n_own + 12.0 * n_l0 + 12.0 * n_l1;
+      break;
+    case DD_PROF_STEP_ADJ:
+      b = 48.0 * n_fd + 12.0 * n_det + 12.0 * n_l0 + 48.0 * n_own + 12.0 * n_own + 12.0 * n_l0 + 12.0 * n_l1 +
+          36.0 * n_own + 32.0 * (n_own - n_l1);
       break;
   }
   *bytes_per_launch = b;

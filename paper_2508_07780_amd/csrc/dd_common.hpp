@@ -121,6 +121,7 @@ struct FemArgs {
   // assembled-stencil path
   const int* part_dims; const int* box_codes; const int* slot_off; const float* slot_k; const float* slot_b;
   int n_slots, lds_box;
+  int n_part;
   // adjoint
   const float* wE; const float* wV; const float* wVm;  // forward E^k, V^k, V^{k-1} [3][n_own]
   double* g_eps; double* g_sig;
@@ -133,6 +134,8 @@ void launch_fem_fwd(const FemArgs& a, int n_part, hipStream_t s, bool energy);
 void launch_fem_adj(const FemArgs& a, int n_part, hipStream_t s);
 void launch_fem_stencil_fwd(const FemArgs& a, int n_part, hipStream_t s, bool energy);
 void launch_fem_stencil_adj(const FemArgs& a, int n_part, hipStream_t s);
+// fused FD + FEM (assembled-stencil) step, one launch
+void launch_step(const FdArgs& fa, const FemArgs& ea, hipStream_t s, bool adj, bool energy);
 void launch_energy_reduce(const double* part, int n, double* out, hipStream_t s);
 void launch_fill_f32(float* p, int64_t n, float v, hipStream_t s);
 void launch_fill_f64(double* p, int64_t n, double v, hipStream_t s);

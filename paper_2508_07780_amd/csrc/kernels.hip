@@ -22,13 +22,14 @@ namespace dd {
 // (with a one-node halo, double-buffered), the z-1 / z+1 values of each column stay in a
 // register queue that is prefetched two planes ahead; increments and halo one plane ahead.
 // ---------------------------------------------------------------------------------------
+// b: block index within the finite-difference part of the launch; b % N_XCD must equal
+// blockIdx.x % N_XCD so that the remap below keeps consecutive tiles on one XCD.
 template <int ZC, bool ENERGY>
-__global__ __launch_bounds__(FD_THREADS) void fd_step_kernel(FdArgs a) {
+__device__ __forceinline__ void fd_tile(const FdArgs& a, const int b) {
   // two LDS planes: plane z is written while plane z-1 may still be read by slower waves,
   // so one barrier per plane suffices
   __shared__ float s[2][3][FD_TY + 2][FD_TX + 2];
   __shared__ double red[ENERGY ? FD_THREADS : 1];
-  const int b = blockIdx.x;
   const int t = (b % N_XCD) * a.per_xcd + b / N_XCD;  // consecutive tiles share an XCD's L2
   if (t >= a.ntiles) return;
   const int nx = a.nx, ny = a.ny, nz = a.nz;
@@ -215,6 +216,11 @@ __global__ __launch_bounds__(FD_THREADS) void fd_step_kernel(FdArgs a) {
     }
     if (tid == 0) a.epart[t] = red[0];
   }
+}
+
+template <int ZC, bool ENERGY>
+__global__ __launch_bounds__(FD_THREADS) void fd_step_kernel(FdArgs a) {
+  fd_tile<ZC, ENERGY>(a, blockIdx.x);
 }
 
 // ---------------------------------------------------------------------------------------
@@ -500,14 +506,13 @@ __global__ __launch_bounds__(FEM_THREADS) void fem_step_kernel(FemArgs a) {
 // scatter, hence no colouring and no barrier after the staging.
 // ---------------------------------------------------------------------------------------
 template <bool ADJ, bool ENERGY>
-__global__ __launch_bounds__(FEM_THREADS) void fem_stencil_kernel(FemArgs a) {
+__device__ __forceinline__ void fem_stencil_part(const FemArgs& a, const int p) {
   constexpr int NPT = FEM_OWN_MAX / FEM_THREADS;
   extern __shared__ __align__(16) unsigned char lds[];
   float4* sX = reinterpret_cast<float4*>(lds);                   // [box]: E_x, E_y, E_z, eps - 1
   float* sKB = reinterpret_cast<float*>(sX + a.lds_box);          // [n_slots][12]: K, B (9), pad
   int* sOff = reinterpret_cast<int*>(sKB + 12 * STENCIL_SLOTS_MAX);  // [n_slots] box offsets
   __shared__ double red[ENERGY ? FEM_THREADS : 1];
-  const int p = blockIdx.x;
   const int tid = threadIdx.x;
   const int ox = a.part_dims[4 * p], oy = a.part_dims[4 * p + 1], oz = a.part_dims[4 * p + 2];
   const int bbase = a.part_dims[4 * p + 3];
@@ -557,9 +562,9 @@ __global__ __launch_bounds__(FEM_THREADS) void fem_stencil_kernel(FemArgs a) {
       if (l < nbox) sX[l] = xv[k];
     }
   }
-  // per-node data of the update, prefetched before the barrier
+  // per-node data of the update, prefetched before the barrier (the adjoint's forward
+  // window is read after the stencil sum to keep register pressure low)
   float pI[NPT][3], pc1[NPT], pc2[NPT], pem[NPT];
-  float pwE[NPT][3], pwV[NPT][3], pwVm[NPT][3];
 #pragma unroll
   for (int j = 0; j < NPT; ++j) {
     const int l = tid + j * FEM_THREADS;
@@ -570,14 +575,6 @@ __global__ __launch_bounds__(FEM_THREADS) void fem_stencil_kernel(FemArgs a) {
       pc1[j] = a.c1[id];
       pc2[j] = a.c2[id];
       pem[j] = a.em1[id];
-      if (ADJ) {
-#pragma unroll
-        for (int c = 0; c < 3; ++c) {
-          pwE[j][c] = a.wE[c * n_own + id];
-          pwV[j][c] = a.wV[c * n_own + id];
-          pwVm[j][c] = a.wVm[c * n_own + id];
-        }
-      }
     }
   }
   __syncthreads();
@@ -652,10 +649,10 @@ __global__ __launch_bounds__(FEM_THREADS) void fem_stencil_kernel(FemArgs a) {
       double ge = 0.0, gm = 0.0, gs = 0.0;
 #pragma unroll
       for (int c = 0; c < 3; ++c) {
-        const double wv = (double)pwV[j][c];
-        ge += (double)q[c] * (double)pwE[j][c];
+        const double wv = (double)a.wV[c * n_own + id];
+        ge += (double)q[c] * (double)a.wE[c * n_own + id];
         gm += (double)inc[c] * wv;
-        gs += (double)xn[c] * (wv + (double)pwVm[j][c]);
+        gs += (double)xn[c] * (wv + (double)a.wVm[c * n_own + id]);
       }
       a.g_eps[id] += ge + m * a.inv_dt2 * gm;
       a.g_sig[id] += m * a.inv_2dt * gs;
@@ -670,6 +667,24 @@ __global__ __launch_bounds__(FEM_THREADS) void fem_stencil_kernel(FemArgs a) {
     }
     if (tid == 0) a.epart[a.epart_off + p] = red[0];
   }
+}
+
+template <bool ADJ, bool ENERGY>
+__global__ __launch_bounds__(FEM_THREADS) void fem_stencil_kernel(FemArgs a) {
+  fem_stencil_part<ADJ, ENERGY>(a, blockIdx.x);
+}
+
+// One launch per time step: blocks [0, fem_blocks) advance the FEM partitions (scheduled
+// first: their staging is latency-bound), the remaining blocks the finite-difference
+// tiles.  Both read level n and write level n+1 only, so they need no ordering.
+template <int ZC, bool ADJ, bool ENERGY>
+__global__ __launch_bounds__(FD_THREADS) void step_kernel(FdArgs fa, FemArgs ea, int fem_blocks) {
+  const int b = blockIdx.x;
+  if (b < fem_blocks) {
+    if (b < ea.n_part) fem_stencil_part<ADJ, ENERGY>(ea, b);
+    return;
+  }
+  fd_tile<ZC, ENERGY>(fa, b - fem_blocks);
 }
 
 // ---------------------------------------------------------------------------------------
@@ -815,6 +830,27 @@ void launch_fem_stencil_fwd(const FemArgs& a, int n_part, hipStream_t s, bool en
 
 void launch_fem_stencil_adj(const FemArgs& a, int n_part, hipStream_t s) {
   hipLaunchKernelGGL((fem_stencil_kernel<true, false>), dim3(n_part), dim3(FEM_THREADS), stencil_lds_bytes(a), s, a);
+}
+
+template <int ZC>
+static void launch_step_zc(const FdArgs& fa, const FemArgs& ea, hipStream_t s, bool adj, bool energy) {
+  const int fem_blocks = (ea.n_part + N_XCD - 1) / N_XCD * N_XCD;   // keeps FD blocks XCD-aligned
+  const dim3 grid(fem_blocks + fa.per_xcd * N_XCD);
+  const size_t lds = stencil_lds_bytes(ea);
+  if (adj)
+    hipLaunchKernelGGL((step_kernel<ZC, true, false>), grid, dim3(FD_THREADS), lds, s, fa, ea, fem_blocks);
+  else if (energy)
+    hipLaunchKernelGGL((step_kernel<ZC, false, true>), grid, dim3(FD_THREADS), lds, s, fa, ea, fem_blocks);
+  else
+    hipLaunchKernelGGL((step_kernel<ZC, false, false>), grid, dim3(FD_THREADS), lds, s, fa, ea, fem_blocks);
+}
+
+void launch_step(const FdArgs& fa, const FemArgs& ea, hipStream_t s, bool adj, bool energy) {
+  switch (fa.zc) {
+    case 8: launch_step_zc<8>(fa, ea, s, adj, energy); break;
+    case 32: launch_step_zc<32>(fa, ea, s, adj, energy); break;
+    default: launch_step_zc<16>(fa, ea, s, adj, energy); break;
+  }
 }
 
 void launch_energy_reduce(const double* part, int n, double* out, hipStream_t s) {
