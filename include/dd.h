@@ -145,19 +145,21 @@ int dd_gradient(dd_problem* p, double* g_eps_dev, double* g_sigma_dev, void* str
 const char* dd_error_string(int code);
 const char* dd_last_error(const dd_problem* p);
 
-/* Kernel timing.  When enabled, HIP events on the caller's stream bracket every
- * step launch of each kind below (up to 16384 launches per kind), adding a few
- * microseconds of gaps between launches.  dd_profile_read synchronises on the last
- * event of `kind` and returns the summed kernel time and the launch count; reset != 0
- * clears that kind.  dd_algorithmic_bytes gives the minimum HBM bytes one launch of
- * `kind` must move (each field value read or written once). */
+/* Kernel timing.  dd_profile_enable(p, stride): with stride k > 0, HIP events on the
+ * stream of the launch bracket every k-th step launch of each kind below (up to 16384
+ * timed launches per kind); each timed launch gains a few microseconds of gap, so a
+ * stride of 16 or more leaves the run nearly unperturbed; 0 switches timing off.
+ * dd_profile_read synchronises on the last event of `kind` and returns the summed time
+ * and the number of timed launches; reset != 0 clears that kind.  dd_algorithmic_bytes
+ * gives the minimum HBM bytes one launch of `kind` must move (each field value read or
+ * written once). */
 enum {
   DD_PROF_FD_FWD = 0, DD_PROF_FEM_FWD = 1, DD_PROF_FD_ADJ = 2, DD_PROF_FEM_ADJ = 3,
   DD_PROF_FEM_RECOMPUTE = 4,
   DD_PROF_STEP_FWD = 5, DD_PROF_STEP_ADJ = 6,  /* fused FD + FEM step launches */
   DD_PROF_KINDS = 7
 };
-int dd_profile_enable(dd_problem* p, int32_t enable);
+int dd_profile_enable(dd_problem* p, int32_t stride);
 int dd_profile_read(dd_problem* p, int32_t kind, double* total_ms, int64_t* launches, int32_t reset);
 int dd_algorithmic_bytes(const dd_problem* p, int32_t kind, double* bytes_per_launch);
 

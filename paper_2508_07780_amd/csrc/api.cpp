@@ -57,9 +57,10 @@ struct dd_problem {
   std::string err;
   std::vector<void*> allocs;
   // kernel timing: event pairs around each step launch, per launch kind
-  bool prof = false;
+  int prof_stride = 0;      // 0: off; k: time every k-th launch of each kind
   std::vector<hipEvent_t> ev[DD_PROF_KINDS];
   size_t ev_used[DD_PROF_KINDS] = {};
+  uint64_t ev_seen[DD_PROF_KINDS] = {};
 };
 
 namespace {
@@ -68,7 +69,8 @@ constexpr size_t kProfMaxPairs = 16384;
 
 // Records the opening event of a timed launch; returns the pair slot or -1.
 long prof_begin(dd_problem* p, int kind, hipStream_t st) {
-  if (!p->prof) return -1;
+  if (p->prof_stride <= 0) return -1;
+  if (p->ev_seen[kind]++ % (uint64_t)p->prof_stride != 0) return -1;
   auto& v = p->ev[kind];
   const size_t i = p->ev_used[kind];
   if (i >= kProfMaxPairs) return -1;
@@ -701,10 +703,11 @@ int dd_gradient(dd_problem* p, double* g_eps_dev, double* g_sigma_dev, void* str
   return check_launch(p);
 }
 
-int dd_profile_enable(dd_problem* p, int32_t enable) {
-  if (!p) return DD_ERR_INVALID_ARG;
-  p->prof = enable != 0;
+int dd_profile_enable(dd_problem* p, int32_t stride) {
+  if (!p || stride < 0) return DD_ERR_INVALID_ARG;
+  p->prof_stride = stride;
   for (auto& u : p->ev_used) u = 0;
+  for (auto& u : p->ev_seen) u = 0;
   return DD_OK;
 }
 
@@ -723,7 +726,10 @@ int dd_profile_read(dd_problem* p, int32_t kind, double* total_ms, int64_t* laun
   }
   if (total_ms) *total_ms = tot;
   if (launches) *launches = (int64_t)n;
-  if (reset) p->ev_used[kind] = 0;
+  if (reset) {
+    p->ev_used[kind] = 0;
+    p->ev_seen[kind] = 0;
+  }
   return DD_OK;
 }
 

@@ -109,8 +109,9 @@ class Problem:
         return ge, gs
 
     # ---- kernel timing ---------------------------------------------------------------------
-    def profile(self, enable=True):
-        _lib.check(_lib.load().dd_profile_enable(self._h, 1 if enable else 0), self._h)
+    def profile(self, stride=1):
+        """Time every `stride`-th step launch with HIP events (0 switches timing off)."""
+        _lib.check(_lib.load().dd_profile_enable(self._h, int(stride)), self._h)
 
     def profile_read(self, kind, reset=True):
         """(total kernel ms, launches) of one launch kind since the last reset."""
