@@ -62,6 +62,38 @@ def cpu_baseline(workload, n_steps):
     }
 
 
+def serving_comparison():
+    """Continuous batching vs one solve at a time on the same uneven request stream.
+
+    Requests (seeded): outer grids {64, 96, 128}^3, FEM boxes {32, 48}^3 hexes, 1-4 plane-wave
+    or dipole sources, 300-800 steps, 2-4 reconstruction iterations each.  A burst (all jobs
+    at t = 0) measures throughput; Poisson arrivals at 0.8x the measured one-at-a-time
+    capacity measure latency.
+    """
+    import synth
+    from paper_2508_07780_amd import serving
+    kw = dict(outer=(64, 96, 128), fem=(32, 48), sources=(1, 4), steps=(300, 800), iterations=(2, 4))
+    burst = synth.serving_requests(24, 1e9, **kw)
+    for r in burst:
+        r.arrival = 0.0
+    serving.serve_serial(burst[:2])                       # warm-up
+    s_serial, _ = serving.serve_serial(burst)
+    s_batch, _ = serving.serve_batched(burst, max_slots=16, chunk=32)
+    rate = 0.8 * s_serial["jobs"] / s_serial["makespan_s"]
+    stream = synth.serving_requests(24, rate, **kw)
+    l_serial, _ = serving.serve_serial(stream)
+    l_batch, _ = serving.serve_batched(stream, max_slots=16, chunk=32)
+    keep = ("jobs", "solves", "makespan_s", "throughput_gcell_steps_s", "latency_p50_s", "latency_p99_s")
+    pick = lambda d: {k: (round(d[k], 4) if isinstance(d[k], float) else d[k]) for k in keep}  # noqa: E731
+    return {
+        "workload": "24 jobs: outer {64,96,128}^3, FEM {32,48}^3 hexes, 1-4 sources, 300-800 steps, "
+                    "2-4 iterations; seeded",
+        "burst": {"batched": pick(s_batch), "one_at_a_time": pick(s_serial),
+                  "throughput_ratio": round(s_batch["throughput_gcell_steps_s"] / s_serial["throughput_gcell_steps_s"], 3)},
+        "poisson_0.8x": {"rate_jobs_per_s": round(rate, 3), "batched": pick(l_batch), "one_at_a_time": pick(l_serial)},
+    }
+
+
 def main():
     ap = argparse.ArgumentParser()
     ap.add_argument("--gpus", type=int, default=1)
@@ -73,6 +105,7 @@ def main():
                          "(no recompute; 12.6 GB for the default workload)")
     ap.add_argument("--cpu-sample-steps", type=int, default=8, help="0 skips the oracle baseline")
     ap.add_argument("--no-profile", action="store_true", help="skip the HIP-event kernel timing")
+    ap.add_argument("--serving", type=int, default=1, help="0 skips the batched / serving comparison")
     ap.add_argument("--profile-stride", type=int, default=16,
                     help="time every k-th step launch with HIP events (k >= 16 barely perturbs the run)")
     args = ap.parse_args()
@@ -176,6 +209,8 @@ def main():
         "gradient_finite": finite,
     }
     del prob
+    if args.serving:
+        out["serving"] = serving_comparison()
     if args.cpu_sample_steps > 0:
         out["cpu_baseline"] = cpu_baseline(w, args.cpu_sample_steps)
     print(json.dumps(out), flush=True)

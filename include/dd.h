@@ -145,6 +145,32 @@ int dd_gradient(dd_problem* p, double* g_eps_dev, double* g_sigma_dev, void* str
 const char* dd_error_string(int code);
 const char* dd_last_error(const dd_problem* p);
 
+/* ---- Batched solves (several problems in one launch per step) ----------------------
+ * A batch holds up to max_slots jobs.  A job is the solve of one problem: the forward of
+ * each source with saving, then -- when obs_dev is given -- the adjoint for the misfit
+ * cotangent traces - obs (read inside the adjoint kernel; obs_dev has the traces' layout)
+ * and the gradient summed over sources, written to g_eps_dev / g_sigma_dev (FEM-node
+ * arrays, float64) when those are given.  dd_batch_step advances every active job by up
+ * to max_steps time steps: each iteration is one kernel launch in which every active job
+ * contributes its next step (forward, adjoint or checkpoint recompute), so jobs of uneven
+ * grid sizes, step counts and source counts share the GPU and new jobs can join while
+ * others run.  A finished job's results are complete once `stream` reaches the work
+ * queued by the dd_batch_step call that reported it through dd_batch_poll; afterwards the
+ * problem behaves as after dd_forward(save) + dd_adjoint.
+ * Requirements: the problem uses the assembled-stencil FEM path (uniform Kuhn box) and the
+ * default z-chunk (else DD_ERR_UNSUPPORTED); it has no other active job and is not used
+ * outside the batch until its job is done; all buffers stay valid until then.  A batch is
+ * driven from one host thread and one stream.  Storage for the saved forward is allocated
+ * in dd_batch_submit (see dd_footprint_bytes); dd_batch_step allocates nothing. */
+typedef struct dd_batch dd_batch;
+int dd_batch_create(int32_t max_slots, dd_batch** out);
+int dd_batch_destroy(dd_batch* b);
+int dd_batch_submit(dd_batch* b, dd_problem* p, const dd_source* src, int32_t n_src, float* traces_dev,
+                    const float* obs_dev, double* g_eps_dev, double* g_sigma_dev, int32_t* job_out);
+int dd_batch_step(dd_batch* b, int32_t max_steps, void* stream);
+/* Ids of jobs finished since the last poll (up to capacity), and the number still active. */
+int dd_batch_poll(dd_batch* b, int32_t* done_jobs, int32_t capacity, int32_t* n_done, int32_t* n_active);
+
 /* Kernel timing.  dd_profile_enable(p, stride): with stride k > 0, HIP events on the
  * stream of the launch bracket every k-th step launch of each kind below (up to 16384
  * timed launches per kind); each timed launch gains a few microseconds of gap, so a

@@ -16,6 +16,7 @@ EXPORTS = [
     "dd_create", "dd_destroy", "dd_sizes", "dd_detector_nodes", "dd_footprint_bytes",
     "dd_set_coefficients", "dd_forward", "dd_adjoint", "dd_gradient", "dd_error_string", "dd_last_error",
     "dd_profile_enable", "dd_profile_read", "dd_algorithmic_bytes", "dd_debug_fem_apply",
+    "dd_batch_create", "dd_batch_destroy", "dd_batch_submit", "dd_batch_step", "dd_batch_poll",
 ]
 
 PROF_FD_FWD, PROF_FEM_FWD, PROF_FD_ADJ, PROF_FEM_ADJ, PROF_FEM_RECOMPUTE, PROF_STEP_FWD, PROF_STEP_ADJ = range(7)
@@ -90,6 +91,13 @@ def load():
                                     ctypes.c_int32]
     lib.dd_algorithmic_bytes.argtypes = [P, ctypes.c_int32, ctypes.POINTER(ctypes.c_double)]
     lib.dd_debug_fem_apply.argtypes = [ctypes.POINTER(ProblemDesc), P, P, ctypes.c_int32, P, P]
+    lib.dd_batch_create.argtypes = [ctypes.c_int32, ctypes.POINTER(P)]
+    lib.dd_batch_destroy.argtypes = [P]
+    lib.dd_batch_submit.argtypes = [P, P, ctypes.POINTER(Source), ctypes.c_int32, P, P, P, P,
+                                    ctypes.POINTER(ctypes.c_int32)]
+    lib.dd_batch_step.argtypes = [P, ctypes.c_int32, P]
+    lib.dd_batch_poll.argtypes = [P, ctypes.POINTER(ctypes.c_int32), ctypes.c_int32, ctypes.POINTER(ctypes.c_int32),
+                                  ctypes.POINTER(ctypes.c_int32)]
     for name in EXPORTS:
         if name not in ("dd_footprint_bytes", "dd_error_string", "dd_last_error"):
             getattr(lib, name).restype = ctypes.c_int

@@ -287,77 +287,149 @@ void join_streams(dd_problem* p, hipStream_t st) {
   (void)hipStreamWaitEvent(st, p->ev_fem, 0);
 }
 
-int run_forward(dd_problem* p, const dd_source& src, int s, float* traces, bool save, double* energy, hipStream_t st) {
-  const int64_t nt = p->d.n_steps, K = p->d.ckpt_every;
-  const int64_t n_l0 = p->n_l0, n_own = p->n_own;
-  zero_state(p, st);
-  float* hist = save ? p->ihist[s] : nullptr;
-  float* ck = save ? p->ckpt[s] : nullptr;
-  float* tail = save ? p->tail[s] : nullptr;
-  const int64_t k_tail = last_segment_start(p);
-  if (save) {
-    launch_fill_f32(hist, 3 * n_l0, 0.f, st);          // level 0
-    launch_fill_f32(ck, 6 * n_own, 0.f, st);           // checkpoint of level 0
-    if (k_tail == 0) launch_fill_f32(tail, 6 * n_own, 0.f, st);
-  }
-  hipStream_t sf = p->overlap ? p->aux : st;           // stream of the FEM launches
-  fork_streams(p, st);
-  FdArgs fa = fd_base(p);
-  FemArgs ea = fem_base(p);
-  const double dt = p->d.dt, h = p->d.h;
+// ---- per-step argument builders (shared by the single-problem driver and the batch engine)
+
+struct SrcPlan {
   int64_t dip_idx = -1;
-  double dip_scale = 0.0;
+  double dip_scale = 0.0;   // dt^2 / m at the dipole node
+};
+
+SrcPlan source_plan(const dd_problem* p, const dd_source& src) {
+  SrcPlan sp;
   if (src.kind == DD_SRC_DIPOLE) {
-    dip_idx = src.pos[0] + (int64_t)p->nx * (src.pos[1] + (int64_t)p->ny * src.pos[2]);
+    sp.dip_idx = src.pos[0] + (int64_t)p->nx * (src.pos[1] + (int64_t)p->ny * src.pos[2]);
     int b = 0;
     b += (src.pos[0] == 0 || src.pos[0] == p->nx - 1);
     b += (src.pos[1] == 0 || src.pos[1] == p->ny - 1);
     b += (src.pos[2] == 0 || src.pos[2] == p->nz - 1);
-    dip_scale = dt * dt / (h * h * h * std::ldexp(1.0, -b));   // dt^2 / m at the dipole node
+    const double h = p->d.h;
+    sp.dip_scale = p->d.dt * p->d.dt / (h * h * h * std::ldexp(1.0, -b));
   }
-  for (int64_t n = 0; n < nt; ++n) {
-    const double t = (double)n * dt;
-    const double P = source_time(src, t);
-    const int cur = (int)(n & 1), nxt = (int)((n + 1) & 1);
-    fa.X_in = p->Efd[cur];
-    fa.X_out = p->Efd[nxt];
-    fa.I = p->Vfd;
-    fa.top_a = fa.top_b = top_absorbs(p, n) ? 1 : 0;
-    for (int c = 0; c < 3; ++c) {
-      fa.pw[c] = (src.kind != DD_SRC_DIPOLE && t <= p->d.t_switch) ? (float)(2.0 * dt * dt / h * P * src.pol[c]) : 0.f;
-      fa.dip[c] = (float)(P * src.pol[c] * dip_scale);
-    }
-    fa.dip_idx = dip_idx;
-    fa.tr_out = traces + ((int64_t)s * nt + n) * p->n_det * 3;
-    fa.cot_in = nullptr;
-    fa.iface_out = save ? hist + (n + 1) * 3 * n_l0 : p->iring + nxt * 3 * n_l0;
-    fa.epart = energy ? p->epart : nullptr;
-    const bool fused = p->use_stencil && p->fused;
-    long ps = -1;
-    if (!fused) {
-      ps = prof_begin(p, DD_PROF_FD_FWD, st);
-      launch_fd(fa, st, energy != nullptr);
-      prof_end(p, DD_PROF_FD_FWD, ps, st);
-    }
+  return sp;
+}
 
-    ea.X_in = p->Efem[cur];
-    ea.X_out = p->Efem[nxt];
-    ea.I_in = ea.I_out = p->Vfem;
-    ea.iface_in = save ? hist + n * 3 * n_l0 : p->iring + cur * 3 * n_l0;
-    ea.fd_out = p->Efd[nxt];
-    // dual write of the new FEM state: the last segment entirely, else segment-start checkpoints
-    ea.ck_X = nullptr;
-    if (save && n + 1 >= k_tail)
-      ea.ck_X = tail + (n + 1 - k_tail) * 6 * n_own;
-    else if (save && (n + 1) % K == 0 && (n + 1) / K < p->n_ck)
-      ea.ck_X = ck + ((n + 1) / K) * 6 * n_own;
-    ea.ck_I = ea.ck_X ? ea.ck_X + 3 * n_own : nullptr;
-    ea.epart = energy ? p->epart : nullptr;
+// Zeroes the state and the level-0 entries of the saved forward of source s.
+void forward_prologue(dd_problem* p, int s, bool save, hipStream_t st) {
+  zero_state(p, st);
+  if (save) {
+    launch_fill_f32(p->ihist[s], 3 * p->n_l0, 0.f, st);   // layer-0 values of level 0
+    launch_fill_f32(p->ckpt[s], 6 * p->n_own, 0.f, st);   // checkpoint of level 0
+    if (last_segment_start(p) == 0) launch_fill_f32(p->tail[s], 6 * p->n_own, 0.f, st);
+  }
+}
+
+// Arguments of forward step n (level n -> n+1) of source s.
+void fwd_step_args(const dd_problem* p, const dd_source& src, const SrcPlan& sp, int s, int64_t n, float* traces,
+                   bool save, FdArgs& fa, FemArgs& ea) {
+  const int64_t nt = p->d.n_steps, K = p->d.ckpt_every;
+  const int64_t n_l0 = p->n_l0, n_own = p->n_own;
+  const double dt = p->d.dt, h = p->d.h;
+  const double t = (double)n * dt;
+  const double P = source_time(src, t);
+  const int cur = (int)(n & 1), nxt = (int)((n + 1) & 1);
+  fa.X_in = p->Efd[cur];
+  fa.X_out = p->Efd[nxt];
+  fa.I = p->Vfd;
+  fa.top_a = fa.top_b = top_absorbs(p, n) ? 1 : 0;
+  for (int c = 0; c < 3; ++c) {
+    fa.pw[c] = (src.kind != DD_SRC_DIPOLE && t <= p->d.t_switch) ? (float)(2.0 * dt * dt / h * P * src.pol[c]) : 0.f;
+    fa.dip[c] = (float)(P * src.pol[c] * sp.dip_scale);
+  }
+  fa.dip_idx = sp.dip_idx;
+  fa.tr_out = traces + ((int64_t)s * nt + n) * p->n_det * 3;
+  fa.cot_in = nullptr;
+  fa.obs_in = nullptr;
+  fa.iface_out = save ? p->ihist[s] + (n + 1) * 3 * n_l0 : p->iring + nxt * 3 * n_l0;
+  ea.X_in = p->Efem[cur];
+  ea.X_out = p->Efem[nxt];
+  ea.I_in = ea.I_out = p->Vfem;
+  ea.iface_in = save ? p->ihist[s] + n * 3 * n_l0 : p->iring + cur * 3 * n_l0;
+  ea.fd_out = p->Efd[nxt];
+  // dual write of the new FEM state: the last segment entirely, else segment-start checkpoints
+  const int64_t k_tail = last_segment_start(p);
+  ea.ck_X = nullptr;
+  if (save && n + 1 >= k_tail)
+    ea.ck_X = p->tail[s] + (n + 1 - k_tail) * 6 * n_own;
+  else if (save && (n + 1) % K == 0 && (n + 1) / K < p->n_ck)
+    ea.ck_X = p->ckpt[s] + ((n + 1) / K) * 6 * n_own;
+  ea.ck_I = ea.ck_X ? ea.ck_X + 3 * n_own : nullptr;
+}
+
+// Forward FEM state of the levels of segment seg: stored by the forward for the last
+// segment, recomputed into the shared window otherwise.
+float* segment_window(const dd_problem* p, int s, int64_t seg) {
+  return seg == n_segments(p) - 1 ? p->tail[s] : p->win;
+}
+
+void segment_prologue(dd_problem* p, int s, int64_t seg, hipStream_t st) {
+  if (seg != n_segments(p) - 1)
+    launch_copy_f32(p->win, p->ckpt[s] + seg * 6 * p->n_own, 6 * p->n_own, st);
+}
+
+// Arguments of the FEM-only forward recompute of level k -> k+1 inside segment [k0, k1).
+void recompute_args(const dd_problem* p, int s, int64_t k, int64_t k0, float* win, FemArgs& fw) {
+  const int64_t n_own = p->n_own;
+  fw.X_in = win + (k - k0) * 6 * n_own;
+  fw.X_out = win + (k - k0 + 1) * 6 * n_own;
+  fw.I_in = fw.X_in + 3 * n_own;
+  fw.I_out = fw.X_out + 3 * n_own;
+  fw.iface_in = p->ihist[s] + k * 3 * p->n_l0;
+  fw.fd_out = nullptr;
+  fw.ck_X = fw.ck_I = nullptr;
+}
+
+// Arguments of adjoint step k (lambda^k -> lambda^{k-1}) of source s inside segment k0.
+void adj_step_args(const dd_problem* p, int s, int64_t k, int64_t k0, const float* win, const float* cot,
+                   const float* obs, FdArgs& fa, FemArgs& ea) {
+  const int64_t nt = p->d.n_steps, n_l0 = p->n_l0, n_own = p->n_own;
+  const int cur = (int)(k & 1), prv = (int)((k - 1) & 1);
+  fa.X_in = p->Efd[cur];
+  fa.X_out = p->Efd[prv];
+  fa.I = p->Vfd;
+  fa.top_a = top_absorbs(p, k - 1) ? 1 : 0;
+  fa.top_b = top_absorbs(p, k + 1) ? 1 : 0;
+  for (int c = 0; c < 3; ++c) fa.pw[c] = fa.dip[c] = 0.f;
+  fa.dip_idx = -1;
+  fa.tr_out = nullptr;
+  const int64_t row = ((int64_t)s * nt + (k - 1)) * p->n_det * 3;
+  fa.cot_in = cot + row;
+  fa.obs_in = obs ? obs + row : nullptr;
+  fa.iface_out = p->iring + prv * 3 * n_l0;
+  ea.X_in = p->Efem[cur];
+  ea.X_out = p->Efem[prv];
+  ea.I_in = ea.I_out = p->Vfem;
+  ea.iface_in = p->iring + cur * 3 * n_l0;
+  ea.fd_out = p->Efd[prv];
+  ea.ck_X = ea.ck_I = nullptr;
+  ea.wE = win + (k - k0) * 6 * n_own;
+  ea.wV = ea.wE + 3 * n_own;
+  ea.wVm = win + (k - 1 - k0) * 6 * n_own + 3 * n_own;
+  ea.g_eps = p->g_eps;
+  ea.g_sig = p->g_sig;
+}
+
+int run_forward(dd_problem* p, const dd_source& src, int s, float* traces, bool save, double* energy, hipStream_t st) {
+  const int64_t nt = p->d.n_steps;
+  forward_prologue(p, s, save, st);
+  hipStream_t sf = p->overlap ? p->aux : st;           // stream of the FEM launches
+  fork_streams(p, st);
+  FdArgs fa = fd_base(p);
+  FemArgs ea = fem_base(p);
+  const SrcPlan sp = source_plan(p, src);
+  fa.epart = energy ? p->epart : nullptr;
+  ea.epart = energy ? p->epart : nullptr;
+  const bool fused = p->use_stencil && p->fused;
+  for (int64_t n = 0; n < nt; ++n) {
+    fwd_step_args(p, src, sp, s, n, traces, save, fa, ea);
+    long ps = -1;
     if (fused) {
       ps = prof_begin(p, DD_PROF_STEP_FWD, st);
       launch_step(fa, ea, st, false, energy != nullptr);
       prof_end(p, DD_PROF_STEP_FWD, ps, st);
     } else {
+      ps = prof_begin(p, DD_PROF_FD_FWD, st);
+      launch_fd(fa, st, energy != nullptr);
+      prof_end(p, DD_PROF_FD_FWD, ps, st);
       ps = prof_begin(p, DD_PROF_FEM_FWD, sf);
       fem_fwd(p, ea, sf, energy != nullptr);
       prof_end(p, DD_PROF_FEM_FWD, ps, sf);
@@ -369,72 +441,39 @@ int run_forward(dd_problem* p, const dd_source& src, int s, float* traces, bool 
   return check_launch(p);
 }
 
-int run_adjoint(dd_problem* p, int s, const float* cot, hipStream_t st) {
+int run_adjoint(dd_problem* p, int s, const float* cot, const float* obs, hipStream_t st) {
   const int64_t nt = p->d.n_steps, K = p->d.ckpt_every;
-  const int64_t n_l0 = p->n_l0, n_own = p->n_own;
   zero_state(p, st);
   FdArgs fa = fd_base(p);
   FemArgs fw = fem_base(p);   // recompute (forward, FEM only)
   FemArgs ea = fem_base(p);   // adjoint
-  ea.g_eps = p->g_eps;
-  ea.g_sig = p->g_sig;
   const int64_t nseg = n_segments(p);
-  float* hist = p->ihist[s];
-  float* ck = p->ckpt[s];
   hipStream_t sf = p->overlap ? p->aux : st;
+  const bool fused = p->use_stencil && p->fused;
   fork_streams(p, st);
   for (int64_t seg = nseg - 1; seg >= 0; --seg) {
     const int64_t k0 = seg * K, k1 = std::min(k0 + K, nt);
-    // forward FEM state of levels k0..k1: stored by the forward for the last segment,
-    // recomputed from the segment-start checkpoint and the layer-0 history otherwise
-    float* win = seg == nseg - 1 ? p->tail[s] : p->win;
-    auto wE = [&](int64_t j) { return win + j * 6 * n_own; };
-    auto wV = [&](int64_t j) { return win + j * 6 * n_own + 3 * n_own; };
+    float* win = segment_window(p, s, seg);
     if (seg != nseg - 1) {
-      launch_copy_f32(win, ck + seg * 6 * n_own, 6 * n_own, sf);
+      segment_prologue(p, s, seg, sf);
       for (int64_t k = k0; k < k1; ++k) {
-        fw.X_in = wE(k - k0);
-        fw.X_out = wE(k - k0 + 1);
-        fw.I_in = wV(k - k0);
-        fw.I_out = wV(k - k0 + 1);
-        fw.iface_in = hist + k * 3 * n_l0;
-        fw.fd_out = nullptr;
+        recompute_args(p, s, k, k0, win, fw);
         const long ps = prof_begin(p, DD_PROF_FEM_RECOMPUTE, sf);
         fem_fwd(p, fw, sf, false);
         prof_end(p, DD_PROF_FEM_RECOMPUTE, ps, sf);
       }
     }
     for (int64_t k = k1; k > k0; --k) {
-      const int cur = (int)(k & 1), prv = (int)((k - 1) & 1);
-      fa.X_in = p->Efd[cur];
-      fa.X_out = p->Efd[prv];
-      fa.I = p->Vfd;
-      fa.top_a = top_absorbs(p, k - 1) ? 1 : 0;
-      fa.top_b = top_absorbs(p, k + 1) ? 1 : 0;
-      fa.tr_out = nullptr;
-      fa.cot_in = cot + ((int64_t)s * nt + (k - 1)) * p->n_det * 3;
-      fa.iface_out = p->iring + prv * 3 * n_l0;
-      const bool fused = p->use_stencil && p->fused;
+      adj_step_args(p, s, k, k0, win, cot, obs, fa, ea);
       long ps = -1;
-      if (!fused) {
-        ps = prof_begin(p, DD_PROF_FD_ADJ, st);
-        launch_fd(fa, st, false);
-        prof_end(p, DD_PROF_FD_ADJ, ps, st);
-      }
-
-      ea.X_in = p->Efem[cur];
-      ea.X_out = p->Efem[prv];
-      ea.I_in = ea.I_out = p->Vfem;
-      ea.iface_in = p->iring + cur * 3 * n_l0;
-      ea.fd_out = p->Efd[prv];
-      ea.wE = wE(k - k0);
-      ea.wV = wV(k - k0);
-      ea.wVm = wV(k - 1 - k0);
       if (fused) {
         ps = prof_begin(p, DD_PROF_STEP_ADJ, st);
         launch_step(fa, ea, st, true, false);
         prof_end(p, DD_PROF_STEP_ADJ, ps, st);
       } else {
+        ps = prof_begin(p, DD_PROF_FD_ADJ, st);
+        launch_fd(fa, st, false);
+        prof_end(p, DD_PROF_FD_ADJ, ps, st);
         ps = prof_begin(p, DD_PROF_FEM_ADJ, sf);
         fem_adj(p, ea, sf);
         prof_end(p, DD_PROF_FEM_ADJ, ps, sf);
@@ -685,7 +724,7 @@ int dd_adjoint(dd_problem* p, const float* cot_dev, void* stream) {
   launch_fill_f64(p->g_eps, p->n_own, 0.0, st);
   launch_fill_f64(p->g_sig, p->n_own, 0.0, st);
   for (int s = 0; s < p->saved_n_src; ++s) {
-    int rc = run_adjoint(p, s, cot_dev, st);
+    int rc = run_adjoint(p, s, cot_dev, nullptr, st);
     if (rc) return rc;
   }
   p->have_grad = true;
@@ -764,6 +803,251 @@ int dd_algorithmic_bytes(const dd_problem* p, int32_t kind, double* bytes_per_la
       break;
   }
   *bytes_per_launch = b;
+  return DD_OK;
+}
+
+}  // extern "C"
+
+// ---------------------------------------------------------------------------------------
+// Batch engine: several problems (jobs) advance together, one launch per iteration, each
+// active job contributing its next time step (forward, adjoint, or FEM-only recompute).
+// ---------------------------------------------------------------------------------------
+namespace {
+
+struct BatchJob {
+  dd_problem* p = nullptr;
+  std::vector<dd_source> src;
+  std::vector<SrcPlan> plans;
+  float* traces = nullptr;
+  const float* obs = nullptr;
+  double *g_eps = nullptr, *g_sig = nullptr;
+  int id = 0;
+  int phase = 0;              // 0 forward, 1 adjoint, 2 finished
+  int s = 0;                  // current source
+  int64_t n = 0;              // forward step
+  int64_t seg = 0, k = 0;     // adjoint segment and step
+  bool started = false;       // prologue of the current source queued
+  bool seg_started = false;   // prologue of the current segment queued
+  bool recomputing = false;
+};
+
+// Queues the prologue work due before the job's next step and fills `it` with that step.
+// Returns false when the job has no step left.
+bool job_next(BatchJob& j, hipStream_t st, BatchItem& it) {
+  dd_problem* p = j.p;
+  const int64_t nt = p->d.n_steps, K = p->d.ckpt_every;
+  const int nsrc = (int)j.src.size();
+  if (j.phase == 0) {
+    if (!j.started) {
+      forward_prologue(p, j.s, true, st);
+      j.started = true;
+    }
+    it.fa = fd_base(p);
+    it.ea = fem_base(p);
+    fwd_step_args(p, j.src[j.s], j.plans[j.s], j.s, j.n, j.traces, true, it.fa, it.ea);
+    it.kind = 0;
+    if (++j.n == nt) {
+      j.n = 0;
+      j.started = false;
+      if (++j.s == nsrc) {
+        j.s = 0;
+        j.phase = j.obs ? 1 : 2;
+      }
+    }
+    return true;
+  }
+  if (j.phase != 1) return false;
+  const int64_t nseg = n_segments(p);
+  if (!j.started) {
+    if (j.s == 0) {
+      launch_fill_f64(p->g_eps, p->n_own, 0.0, st);
+      launch_fill_f64(p->g_sig, p->n_own, 0.0, st);
+    }
+    zero_state(p, st);
+    j.seg = nseg - 1;
+    j.seg_started = false;
+    j.started = true;
+  }
+  const int64_t k0 = j.seg * K, k1 = std::min(k0 + K, nt);
+  float* win = segment_window(p, j.s, j.seg);
+  if (!j.seg_started) {
+    segment_prologue(p, j.s, j.seg, st);
+    j.recomputing = j.seg != nseg - 1;
+    j.k = j.recomputing ? k0 : k1;
+    j.seg_started = true;
+  }
+  it.fa = fd_base(p);
+  it.ea = fem_base(p);
+  if (j.recomputing) {
+    recompute_args(p, j.s, j.k, k0, win, it.ea);
+    it.kind = 2;
+    if (++j.k == k1) j.recomputing = false;   // then adjoint steps k1 .. k0+1
+    return true;
+  }
+  adj_step_args(p, j.s, j.k, k0, win, j.traces, j.obs, it.fa, it.ea);
+  it.kind = 1;
+  if (--j.k == k0) {
+    j.seg_started = false;
+    if (--j.seg < 0) {
+      j.started = false;
+      if (++j.s == nsrc) j.phase = 2;
+    }
+  }
+  return true;
+}
+
+}  // namespace
+
+struct dd_batch {
+  int max_slots = 0;
+  std::vector<BatchJob> jobs;
+  std::vector<int> done;
+  int next_id = 1;
+  BatchItem* host = nullptr;    // pinned [ring][max_slots]
+  BatchItem* dev = nullptr;     // device [ring][max_slots]
+  std::vector<hipEvent_t> ev;   // per ring slot: its upload has been consumed
+  int ring = 64, pos = 0;
+  std::string err;
+};
+
+extern "C" {
+
+int dd_batch_create(int32_t max_slots, dd_batch** out) {
+  if (!out || max_slots < 1 || max_slots > 64) return DD_ERR_INVALID_ARG;
+  *out = nullptr;
+  dd_batch* b = new (std::nothrow) dd_batch();
+  if (!b) return DD_ERR_OOM;
+  b->max_slots = max_slots;
+  const size_t bytes = sizeof(BatchItem) * (size_t)b->ring * max_slots;
+  if (hipHostMalloc((void**)&b->host, bytes, hipHostMallocDefault) != hipSuccess) {
+    delete b;
+    return DD_ERR_OOM;
+  }
+  if (hipMalloc((void**)&b->dev, bytes) != hipSuccess) {
+    (void)hipHostFree(b->host);
+    delete b;
+    return DD_ERR_OOM;
+  }
+  b->ev.resize(b->ring, nullptr);
+  for (auto& e : b->ev)
+    if (hipEventCreateWithFlags(&e, hipEventDisableTiming) != hipSuccess) {
+      dd_batch_destroy(b);
+      return DD_ERR_HIP;
+    }
+  *out = b;
+  return DD_OK;
+}
+
+int dd_batch_destroy(dd_batch* b) {
+  if (!b) return DD_ERR_INVALID_ARG;
+  (void)hipDeviceSynchronize();
+  for (auto e : b->ev)
+    if (e) (void)hipEventDestroy(e);
+  if (b->dev) (void)hipFree(b->dev);
+  if (b->host) (void)hipHostFree(b->host);
+  delete b;
+  return DD_OK;
+}
+
+int dd_batch_submit(dd_batch* b, dd_problem* p, const dd_source* src, int32_t n_src, float* traces_dev,
+                    const float* obs_dev, double* g_eps_dev, double* g_sigma_dev, int32_t* job_out) {
+  if (!b || !p) return DD_ERR_INVALID_ARG;
+  if (!src || n_src < 1 || !traces_dev) return fail(p, DD_ERR_INVALID_ARG, "need sources and a trace buffer");
+  if ((g_eps_dev || g_sigma_dev) && !obs_dev) return fail(p, DD_ERR_INVALID_ARG, "a gradient needs observations");
+  if ((int)b->jobs.size() >= b->max_slots) return fail(p, DD_ERR_STATE, "no free batch slot");
+  for (const auto& j : b->jobs)
+    if (j.p == p) return fail(p, DD_ERR_STATE, "problem already has an active batch job");
+  if (!p->use_stencil || !p->fused || p->zc != FD_ZC)
+    return fail(p, DD_ERR_UNSUPPORTED, "batched steps need the assembled-stencil FEM path and the default z-chunk");
+  for (int s = 0; s < n_src; ++s) {
+    const std::string e = check_source(p, src[s]);
+    if (!e.empty()) return fail(p, DD_ERR_INVALID_ARG, e);
+  }
+  int rc = ensure_saved_storage(p, n_src);
+  if (rc) return rc;
+  BatchJob j;
+  j.p = p;
+  j.src.assign(src, src + n_src);
+  for (int s = 0; s < n_src; ++s) j.plans.push_back(source_plan(p, src[s]));
+  j.traces = traces_dev;
+  j.obs = obs_dev;
+  j.g_eps = g_eps_dev;
+  j.g_sig = g_sigma_dev;
+  j.id = b->next_id++;
+  p->saved = false;
+  p->have_grad = false;
+  b->jobs.push_back(j);
+  if (job_out) *job_out = j.id;
+  return DD_OK;
+}
+
+int dd_batch_step(dd_batch* b, int32_t max_steps, void* stream) {
+  if (!b || max_steps < 0) return DD_ERR_INVALID_ARG;
+  hipStream_t st = (hipStream_t)stream;
+  for (int iter = 0; iter < max_steps && !b->jobs.empty(); ++iter) {
+    const int slot = b->pos;
+    b->pos = (b->pos + 1) % b->ring;
+    if (hipEventSynchronize(b->ev[slot]) != hipSuccess) {
+      b->err = "event synchronize failed";
+      return DD_ERR_HIP;
+    }
+    BatchItem* h = b->host + (size_t)slot * b->max_slots;
+    int n = 0, base = 0;
+    size_t lds = 0;
+    for (auto& j : b->jobs) {
+      BatchItem& it = h[n];
+      if (!job_next(j, st, it)) continue;
+      it.fem_blocks = (j.p->n_part + N_XCD - 1) / N_XCD * N_XCD;
+      it.fd_blocks = it.kind == 2 ? 0 : j.p->per_xcd * N_XCD;
+      it.base = base;
+      base += it.fem_blocks + it.fd_blocks;
+      lds = std::max(lds, stencil_lds(it.ea));
+      ++n;
+    }
+    if (n) {
+      BatchItem* d = b->dev + (size_t)slot * b->max_slots;
+      if (hipMemcpyAsync(d, h, sizeof(BatchItem) * n, hipMemcpyHostToDevice, st) != hipSuccess ||
+          hipEventRecord(b->ev[slot], st) != hipSuccess) {
+        b->err = "batch upload failed";
+        return DD_ERR_HIP;
+      }
+      launch_batch(d, n, base, lds, st);
+      hipError_t e = hipGetLastError();
+      if (e != hipSuccess) {
+        b->err = std::string("batch launch failed: ") + hipGetErrorString(e);
+        return DD_ERR_HIP;
+      }
+    }
+    for (auto it = b->jobs.begin(); it != b->jobs.end();) {
+      if (it->phase == 2) {
+        dd_problem* p = it->p;
+        p->saved = true;
+        p->saved_n_src = (int)it->src.size();
+        if (it->obs) {
+          p->have_grad = true;
+          if (it->g_eps && it->g_sig) {
+            launch_fill_f64(it->g_eps, p->n_fem, 0.0, st);
+            launch_fill_f64(it->g_sig, p->n_fem, 0.0, st);
+            launch_gradient_out(p->g_eps, p->g_sig, p->own_api, p->own_grid, p->n_own, it->g_eps, it->g_sig, st);
+          }
+        }
+        b->done.push_back(it->id);
+        it = b->jobs.erase(it);
+      } else {
+        ++it;
+      }
+    }
+  }
+  return DD_OK;
+}
+
+int dd_batch_poll(dd_batch* b, int32_t* done_jobs, int32_t capacity, int32_t* n_done, int32_t* n_active) {
+  if (!b) return DD_ERR_INVALID_ARG;
+  const int n = std::min<int>((int)b->done.size(), done_jobs ? capacity : 0);
+  for (int i = 0; i < n; ++i) done_jobs[i] = b->done[i];
+  b->done.erase(b->done.begin(), b->done.begin() + n);
+  if (n_done) *n_done = n;
+  if (n_active) *n_active = (int)b->jobs.size();
   return DD_OK;
 }
 

@@ -85,6 +85,7 @@ struct FdArgs {
   unsigned det_mask;
   float* tr_out;       // forward: traces of this step [n_det][3] or null
   const float* cot_in; // adjoint: cotangent of this step [n_det][3] or null
+  const float* obs_in; // adjoint: observations of this step; the cotangent is then cot_in - obs_in
   float dt2_h3;        // dt^2 / h^3
   float* iface_out;    // layer-0 values of the next level [3][n_l0] or null
   int64_t n_l0;
@@ -136,6 +137,18 @@ void launch_fem_stencil_fwd(const FemArgs& a, int n_part, hipStream_t s, bool en
 void launch_fem_stencil_adj(const FemArgs& a, int n_part, hipStream_t s);
 // fused FD + FEM (assembled-stencil) step, one launch
 void launch_step(const FdArgs& fa, const FemArgs& ea, hipStream_t s, bool adj, bool energy);
+
+// one item of a batched step launch
+struct BatchItem {
+  FdArgs fa;
+  FemArgs ea;
+  int kind;         // 0 forward, 1 adjoint, 2 forward FEM-only recompute
+  int fem_blocks;   // multiple of N_XCD (extra blocks exit)
+  int fd_blocks;    // per_xcd * N_XCD, or 0 for a recompute step
+  int base;         // first block of this item (multiple of N_XCD)
+};
+void launch_batch(const BatchItem* items_dev, int n_items, int total_blocks, size_t lds, hipStream_t s);
+size_t stencil_lds(const FemArgs& a);
 void launch_energy_reduce(const double* part, int n, double* out, hipStream_t s);
 void launch_fill_f32(float* p, int64_t n, float v, hipStream_t s);
 void launch_fill_f64(double* p, int64_t n, double v, hipStream_t s);

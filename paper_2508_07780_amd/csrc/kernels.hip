@@ -37,6 +37,7 @@ __device__ __forceinline__ void fd_tile(const FdArgs& a, const int b) {
   const int by = (t / a.nbx) % a.nby;
   const int bz = t / (a.nbx * a.nby);
   const int x0 = bx * FD_TX, y0 = by * FD_TY, z0 = bz * ZC;
+  if (z0 >= nz) return;   // tile grid built for another z-chunk: nothing of this tile exists
   const int z1 = min(z0 + ZC, nz);
   const int tid = threadIdx.x;
   if (x0 > a.blo[0] && x0 + FD_TX - 1 < a.bhi[0] && y0 > a.blo[1] && y0 + FD_TY - 1 < a.bhi[1] &&
@@ -156,8 +157,12 @@ __device__ __forceinline__ void fd_tile(const FdArgs& a, const int b) {
         if (a.det_mask) det = face_lex_index(x, y, z, nx, ny, nz, a.det_mask);
         if (det >= 0 && a.cot_in) {
           const float sc = a.dt2_h3 * (float)(1 << bcount);   // dt^2 / m_i
+          // r = dJ/dT: the cotangent itself, or T - E_obs when the observations are given
 #pragma unroll
-          for (int c = 0; c < 3; ++c) src[c] -= a.cot_in[det * 3 + c] * sc;
+          for (int c = 0; c < 3; ++c) {
+            const float r = a.obs_in ? a.cot_in[det * 3 + c] - a.obs_in[det * 3 + c] : a.cot_in[det * 3 + c];
+            src[c] -= r * sc;
+          }
         }
       }
       if ((int64_t)idx == a.dip_idx) {
@@ -685,6 +690,40 @@ __global__ __launch_bounds__(FD_THREADS) void step_kernel(FdArgs fa, FemArgs ea,
     return;
   }
   fd_tile<ZC, ENERGY>(fa, b - fem_blocks);
+}
+
+// ---------------------------------------------------------------------------------------
+// Batched step: one launch advances every active job of a batch by one time step.  Item i
+// covers blocks [base_i, base_i + fem_blocks_i + fd_blocks_i); its FEM partitions come
+// first, then its FD tiles (fem_blocks_i and base_i are multiples of N_XCD, keeping each
+// item's tile-to-XCD mapping).  kind: 0 forward step, 1 adjoint step, 2 forward FEM-only
+// recompute step.  Items live in device memory (uniform per block: scalar loads).
+// ---------------------------------------------------------------------------------------
+template <int ZC>
+__global__ __launch_bounds__(FD_THREADS) void batch_step_kernel(const BatchItem* __restrict__ items, int n_items) {
+  const int b = blockIdx.x;
+  int i = 0;
+  while (i + 1 < n_items && b >= items[i + 1].base) ++i;
+  const BatchItem& it = items[i];
+  const int local = b - it.base;
+  if (local < it.fem_blocks) {
+    if (local < it.ea.n_part) {
+      if (it.kind == 1)
+        fem_stencil_part<true, false>(it.ea, local);
+      else
+        fem_stencil_part<false, false>(it.ea, local);
+    }
+    return;
+  }
+  if (local - it.fem_blocks < it.fd_blocks) fd_tile<ZC, false>(it.fa, local - it.fem_blocks);
+}
+
+void launch_batch(const BatchItem* items_dev, int n_items, int total_blocks, size_t lds, hipStream_t s) {
+  hipLaunchKernelGGL((batch_step_kernel<FD_ZC>), dim3(total_blocks), dim3(FD_THREADS), lds, s, items_dev, n_items);
+}
+
+size_t stencil_lds(const FemArgs& a) {
+  return (size_t)a.lds_box * 16 + 12 * 4 * STENCIL_SLOTS_MAX + 4 * STENCIL_SLOTS_MAX;
 }
 
 // ---------------------------------------------------------------------------------------

@@ -1,0 +1,170 @@
+"""Request loop: continuous batching of reconstruction solves with HBM admission.
+
+Jobs arrive over time.  Each job is a sequence of solves of one problem (forward,
+misfit adjoint, eps/sigma gradient, then a steepest-descent update of eps and sigma on
+the device); the problem's fields stay resident between its solves.  A job is admitted
+when a batch slot is free and its device footprint (dd_footprint_bytes plus its trace,
+observation and gradient buffers) fits in the HBM budget; admitted solves join the
+running batch at the next launch, so work of jobs of different sizes overlaps on the
+device.  The one-at-a-time server runs the same jobs in arrival order through the
+single-problem calls, for comparison.
+
+Requests are plain objects with `arrival` (s), `iterations` and `workload` (desc, sources,
+initial eps / sigma, seed).  Observations are seeded synthetic data of the traces' shape:
+the cost of a solve does not depend on their values.
+"""
+
+import time
+
+import numpy as np
+import torch
+
+from .batch import Batch
+from .solver import Problem
+
+
+def cell_steps(desc, n_src):
+    """Cells (outer nodes + FEM-owned nodes) x (forward + adjoint steps) x sources of one solve."""
+    n_own = int(np.prod([max(int(c) - 1, 0) for c in desc.fem_cells]))
+    n_grid = int(np.prod([int(v) for v in desc.n_outer]))
+    return (n_grid + n_own) * 2 * int(desc.n_steps) * n_src
+
+
+class _Job:
+    def __init__(self, req, dev):
+        w = req.workload
+        self.req = req
+        self.problem = Problem(w.desc)
+        self.eps = torch.tensor(w.eps, dtype=torch.float32, device=dev)
+        self.sigma = torch.tensor(w.sigma, dtype=torch.float32, device=dev)
+        self.free = self.eps.new_tensor(_free_mask(w.desc), dtype=torch.bool)
+        g = torch.Generator(device=dev)
+        g.manual_seed(int(w.seed))
+        shape = (len(w.sources), w.desc.n_steps, self.problem.n_det, 3)
+        self.obs = 1e-3 * torch.randn(shape, generator=g, device=dev, dtype=torch.float32)
+        self.done_iters = 0
+        self.problem.set_coefficients(self.eps, self.sigma)
+
+    def update(self, g_eps, g_sigma):
+        """Steepest descent on free nodes, kept inside the coefficient constraint."""
+        for x, g, lo in ((self.eps, g_eps, 1.0), (self.sigma, g_sigma, 0.0)):
+            gm = torch.max(torch.abs(g))
+            step = torch.where(gm > 0, 0.05 / gm, torch.zeros_like(gm)).to(torch.float32)
+            x.sub_(torch.where(self.free, step * g.to(torch.float32), torch.zeros_like(x)))
+            x.clamp_(min=lo)
+        self.problem.set_coefficients(self.eps, self.sigma)
+
+
+def _free_mask(desc):
+    c = [int(v) for v in desc.fem_cells]
+    lz, ly, lx = np.meshgrid(np.arange(c[2] + 1), np.arange(c[1] + 1), np.arange(c[0] + 1), indexing="ij")
+    lay = np.minimum(np.minimum(lx, c[0] - lx), np.minimum(ly, c[1] - ly))
+    lay = np.minimum(lay, np.minimum(lz, c[2] - lz))
+    return (lay >= 2).reshape(-1)
+
+
+def job_footprint(req):
+    w = req.workload
+    n_src = len(w.sources)
+    traces = n_src * int(w.desc.n_steps) * _n_det(w.desc) * 3 * 4
+    return Problem.footprint_bytes(w.desc, n_src) + 2 * traces + 2 * 8 * w.desc.n_fem_nodes()
+
+
+def _n_det(desc):
+    return len(Problem.detector_nodes(desc))
+
+
+def _summary(lat, solves, makespan, work):
+    lat = sorted(lat)
+    pct = lambda q: float(np.percentile(lat, q)) if lat else None  # noqa: E731
+    return {"jobs": len(lat), "solves": solves, "makespan_s": makespan,
+            "throughput_gcell_steps_s": work / makespan / 1e9 if makespan > 0 else None,
+            "latency_p50_s": pct(50), "latency_p99_s": pct(99), "latency_mean_s": float(np.mean(lat)) if lat else None}
+
+
+def serve_batched(requests, max_slots=16, hbm_budget=None, chunk=32, time_fn=time.perf_counter):
+    """Continuous batching: returns a summary dict and per-job records."""
+    dev = torch.device("cuda", torch.cuda.current_device())
+    if hbm_budget is None:
+        free, _ = torch.cuda.mem_get_info()
+        hbm_budget = int(0.9 * free)
+    pending = sorted(requests, key=lambda r: r.arrival)
+    batch = Batch(max_slots)
+    active = {}           # job id in the batch -> _Job
+    in_use = 0
+    lat, records = [], []
+    solves = 0
+    work = 0
+    peak_bytes = peak_jobs = 0
+    t0 = time_fn()
+    while pending or active:
+        now = time_fn() - t0
+        # admission: arrived, a slot free, the footprint fits
+        while pending and pending[0].arrival <= now and len(active) < max_slots:
+            fp = job_footprint(pending[0])
+            if in_use + fp > hbm_budget:
+                break
+            req = pending.pop(0)
+            job = _Job(req, dev)
+            job.footprint = fp
+            in_use += fp
+            jid = batch.submit(job.problem, req.workload.sources, obs=job.obs)
+            active[jid] = job
+            peak_bytes = max(peak_bytes, in_use)
+            peak_jobs = max(peak_jobs, len(active))
+        if not active:
+            # idle until the next arrival
+            time.sleep(max(0.0, min(0.01, pending[0].arrival - now)))
+            continue
+        batch.step(chunk)
+        finished, _ = batch.poll()
+        for rec in finished:
+            job = active.pop(rec["id"])
+            job.update(rec["g_eps"], rec["g_sigma"])      # synchronises the stream
+            solves += 1
+            work += cell_steps(job.req.workload.desc, len(job.req.workload.sources))
+            job.done_iters += 1
+            if job.done_iters < job.req.iterations:
+                jid = batch.submit(job.problem, job.req.workload.sources, obs=job.obs)
+                active[jid] = job
+            else:
+                t_done = time_fn() - t0
+                lat.append(t_done - job.req.arrival)
+                records.append({"rid": job.req.rid, "arrival": job.req.arrival, "done": t_done,
+                                "iterations": job.done_iters})
+                job.problem.close()
+                in_use -= job.footprint
+    torch.cuda.synchronize()
+    makespan = time_fn() - t0
+    batch.close()
+    out = _summary(lat, solves, makespan, work)
+    out.update(hbm_budget_bytes=hbm_budget, peak_admitted_bytes=peak_bytes, peak_concurrent_jobs=peak_jobs)
+    return out, records
+
+
+def serve_serial(requests, time_fn=time.perf_counter):
+    """One solve at a time, jobs in arrival order, through the single-problem calls."""
+    dev = torch.device("cuda", torch.cuda.current_device())
+    lat, records = [], []
+    solves = 0
+    work = 0
+    t0 = time_fn()
+    for req in sorted(requests, key=lambda r: r.arrival):
+        now = time_fn() - t0
+        if req.arrival > now:
+            time.sleep(req.arrival - now)
+        job = _Job(req, dev)
+        for _ in range(req.iterations):
+            tr = job.problem.forward(req.workload.sources, save=True)
+            job.problem.adjoint(tr - job.obs)
+            ge, gs = job.problem.gradient()
+            job.update(ge, gs)
+            solves += 1
+            work += cell_steps(req.workload.desc, len(req.workload.sources))
+        t_done = time_fn() - t0
+        lat.append(t_done - req.arrival)
+        records.append({"rid": req.rid, "arrival": req.arrival, "done": t_done, "iterations": req.iterations})
+        job.problem.close()
+    torch.cuda.synchronize()
+    makespan = time_fn() - t0
+    return _summary(lat, solves, makespan, work), records

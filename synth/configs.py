@@ -325,3 +325,51 @@ def batch_mix(n_problems=16, seed=SEED_BASE + 4, scale=1.0):
 
 def with_steps(w: Workload, n_steps: int) -> Workload:
     return replace(w, desc=replace(w.desc, n_steps=n_steps))
+
+
+@dataclass
+class Request:
+    rid: int
+    arrival: float          # seconds after the start of the run
+    workload: Workload
+    iterations: int         # reconstruction iterations of the job (solve, update, solve, ...)
+
+
+def serving_requests(n_requests, rate, seed=SEED_BASE + 5, outer=(64, 96, 128, 160, 224),
+                     fem=(32, 48, 64, 96), sources=(1, 8), steps=(500, 2000), iterations=(3, 10)):
+    """Poisson arrivals (rate per second) of reconstruction jobs of uneven size.
+
+    Each job draws an outer grid and a FEM box (valid pairs: outer >= fem + 2 max(8, 0.2 fem)),
+    1-8 sources (plane waves of varying polarisation, every third one a point dipole above
+    the FEM box), a step count and a number of iterations; media from the layered-skin
+    generator.
+    """
+    rng = np.random.Generator(np.random.PCG64(seed))
+    t = 0.0
+    out = []
+    for r in range(n_requests):
+        t += rng.exponential(1.0 / rate)
+        while True:
+            no = int(rng.choice(outer))
+            nf = int(rng.choice(fem))
+            if no >= nf + 2 * max(8, math.ceil(0.2 * nf)):
+                break
+        nt = int(rng.integers(steps[0], steps[1] + 1))
+        desc = _centered_desc(no, nf, nt)
+        base = gauss_sine(2.0 * math.pi / 2.236)
+        desc.t_switch = base.support_end()
+        srcs = []
+        for k in range(int(rng.integers(sources[0], sources[1] + 1))):
+            pol = tuple(rng.normal(size=3) * np.array([1.0, 1.0, 0.2]))
+            if k % 3 == 2:
+                z = min(no - 2, desc.fem_lo[2] + nf + 4)
+                srcs.append(Source(kind=SRC_DIPOLE, omega=base.omega, t0=base.t0, width=base.width,
+                                   pol=pol, pos=(no // 2, no // 2, z)))
+            else:
+                srcs.append(gauss_sine(base.omega, pol=pol))
+        eps, sig, _ = skin_media(desc, rng)
+        n = desc.n_fem_nodes()
+        w = Workload(f"req{r}", desc, np.ones(n), np.zeros(n), srcs, seed + 1000 + r,
+                     eps_true=eps, sigma_true=sig, noise_level=0.03)
+        out.append(Request(r, t, w, int(rng.integers(iterations[0], iterations[1] + 1))))
+    return out
