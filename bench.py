@@ -25,6 +25,22 @@ ROOT = os.path.dirname(os.path.abspath(__file__))
 sys.path.insert(0, ROOT)
 
 HBM_PEAK_GBS = 8000.0   # MI355X HBM3E peak
+TRAFFIC_FILE = os.path.join(ROOT, "profiles", "step_kernel_c2_traffic.md")
+
+
+def measured_traffic(key):
+    """HBM bytes per launch recorded from PMC counters, if they were taken on these kernel sources."""
+    from paper_2508_07780_amd.profiling import kernel_source_hash
+    try:
+        txt = open(TRAFFIC_FILE).read()
+    except OSError:
+        return None
+    vals = dict(line.split(":", 1) for line in txt.splitlines() if ":" in line and not line.startswith(("#", " ", "|")))
+    vals = {k.strip(): v.strip() for k, v in vals.items()}
+    if vals.get("kernel_source_hash") != kernel_source_hash():
+        return None
+    v = vals.get(key)
+    return float(v) if v else None
 
 
 def _percentile(xs, q):
@@ -179,8 +195,9 @@ def main():
     if dom:
         k = kern[dom]
         achieved = k["algorithmic_GBs"]
+        traffic = measured_traffic("traffic_bytes_per_launch_step_fwd") if dom == "step_fwd" else None
         roofline = {"bound": "hbm", "achieved": round(achieved, 1), "peak": HBM_PEAK_GBS, "unit": "GB/s",
-                    "frac": round(achieved / HBM_PEAK_GBS, 4), "traffic": None,
+                    "frac": round(achieved / HBM_PEAK_GBS, 4), "traffic": traffic,
                     "kernel": {"step_fwd": "step_kernel (fused FD + FEM, forward)",
                                "fd_step_fwd": "fd_step_kernel (forward)"}[dom],
                     "avg_us": round(k["avg_us"], 2), "algorithmic_bytes_per_launch": k["algorithmic_bytes"]}
