@@ -78,6 +78,54 @@ def cpu_baseline(workload, n_steps):
     }
 
 
+def batch_comparison():
+    """16 uneven problems (outer 96-224^3, FEM 32-96^3 hexes, 1000-2500 steps, plane-wave or
+    dipole source each), forward + adjoint + gradient: one batch (one launch per step for all
+    of them) vs one problem after the other through the single-problem calls."""
+    import torch
+    import synth
+    from paper_2508_07780_amd import Problem
+    from paper_2508_07780_amd.batch import Batch
+    from paper_2508_07780_amd.serving import cell_steps
+    mix = synth.batch_mix(16)
+    dev = torch.device("cuda", 0)
+    probs, obs = [], []
+    for w in mix:
+        p = Problem(w.desc)
+        p.set_coefficients(torch.tensor(w.eps, dtype=torch.float32, device=dev),
+                           torch.tensor(w.sigma, dtype=torch.float32, device=dev))
+        g = torch.Generator(device=dev)
+        g.manual_seed(w.seed)
+        obs.append(1e-3 * torch.randn((1, w.desc.n_steps, p.n_det, 3), generator=g, device=dev))
+        probs.append(p)
+    work = sum(cell_steps(w.desc, 1) for w in mix)
+    torch.cuda.synchronize()
+    t0 = time.perf_counter()
+    for p, w, o in zip(probs, mix, obs):
+        tr = p.forward(w.sources, save=True)
+        p.adjoint(tr - o)
+        p.gradient()
+    torch.cuda.synchronize()
+    t_serial = time.perf_counter() - t0
+    b = Batch(16)
+    torch.cuda.synchronize()
+    t0 = time.perf_counter()
+    for p, w, o in zip(probs, mix, obs):
+        b.submit(p, w.sources, obs=o)
+    b.run_to_completion(chunk=64)
+    torch.cuda.synchronize()
+    t_batch = time.perf_counter() - t0
+    b.close()
+    for p in probs:
+        p.close()
+    return {"workload": "16 problems: outer " + ",".join(str(w.desc.n_outer[0]) for w in mix) + "; FEM "
+                        + ",".join(str(w.desc.fem_cells[0]) for w in mix) + "; steps "
+                        + ",".join(str(w.desc.n_steps) for w in mix) + "; K = 64",
+            "batched_gcell_steps_s": round(work / t_batch / 1e9, 3), "batched_s": round(t_batch, 3),
+            "one_at_a_time_gcell_steps_s": round(work / t_serial / 1e9, 3), "one_at_a_time_s": round(t_serial, 3),
+            "ratio": round(t_serial / t_batch, 3)}
+
+
 def serving_comparison():
     """Continuous batching vs one solve at a time on the same uneven request stream.
 
@@ -122,7 +170,7 @@ def main():
     ap.add_argument("--cpu-sample-steps", type=int, default=8, help="0 skips the oracle baseline")
     ap.add_argument("--no-profile", action="store_true", help="skip the HIP-event kernel timing")
     ap.add_argument("--serving", type=int, default=1, help="0 skips the batched / serving comparison")
-    ap.add_argument("--profile-stride", type=int, default=16,
+    ap.add_argument("--profile-stride", type=int, default=64,
                     help="time every k-th step launch with HIP events (k >= 16 barely perturbs the run)")
     args = ap.parse_args()
     if args.gpus != 1 or int(os.environ.get("WORLD_SIZE", "1")) != 1:
@@ -227,6 +275,7 @@ def main():
     }
     del prob
     if args.serving:
+        out["batched_mix"] = batch_comparison()
         out["serving"] = serving_comparison()
     if args.cpu_sample_steps > 0:
         out["cpu_baseline"] = cpu_baseline(w, args.cpu_sample_steps)

@@ -172,11 +172,12 @@ int dd_batch_step(dd_batch* b, int32_t max_steps, void* stream);
 int dd_batch_poll(dd_batch* b, int32_t* done_jobs, int32_t capacity, int32_t* n_done, int32_t* n_active);
 
 /* Kernel timing.  dd_profile_enable(p, stride): with stride k > 0, HIP events on the
- * stream of the launch bracket every k-th step launch of each kind below (up to 16384
- * timed launches per kind); each timed launch gains a few microseconds of gap, so a
- * stride of 16 or more leaves the run nearly unperturbed; 0 switches timing off.
- * dd_profile_read synchronises on the last event of `kind` and returns the summed time
- * and the number of timed launches; reset != 0 clears that kind.  dd_algorithmic_bytes
+ * stream of the launch bracket, every k launches of each kind below, a window of
+ * consecutive launches (8 for the fused step kinds, which run back to back; 1 otherwise;
+ * up to 16384 windows per kind).  A window's elapsed time covers its kernels and the
+ * dispatch gaps between them; 0 switches timing off.  dd_profile_read synchronises on the
+ * last event of `kind` and returns the summed time and the number of timed launches;
+ * reset != 0 clears that kind.  dd_algorithmic_bytes
  * gives the minimum HBM bytes one launch of `kind` must move (each field value read or
  * written once). */
 enum {

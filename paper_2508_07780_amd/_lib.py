@@ -4,7 +4,7 @@ import ctypes
 import os
 
 HERE = os.path.dirname(os.path.abspath(__file__))
-LIB_PATH = os.path.join(HERE, "libddfem.so")
+LIB_PATH = os.environ.get("DD_LIB_PATH") or os.path.join(HERE, "libddfem.so")
 
 DD_OK = 0
 ERRORS = {

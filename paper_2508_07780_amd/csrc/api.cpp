@@ -67,20 +67,29 @@ namespace {
 
 constexpr size_t kProfMaxPairs = 16384;
 
-// Records the opening event of a timed launch; returns the pair slot or -1.
+// Kernel timing: a window of `prof_window(kind)` consecutive launches of one kind is
+// bracketed by one event pair every `prof_stride` launches.  Windows of several launches
+// amortise the event markers; they are used only for kinds that are launched back to back
+// (the fused step kernels), single launches otherwise.
+int prof_window(int kind) { return (kind == DD_PROF_STEP_FWD || kind == DD_PROF_STEP_ADJ) ? 8 : 1; }
+
 long prof_begin(dd_problem* p, int kind, hipStream_t st) {
   if (p->prof_stride <= 0) return -1;
-  if (p->ev_seen[kind]++ % (uint64_t)p->prof_stride != 0) return -1;
-  auto& v = p->ev[kind];
+  const uint64_t seen = p->ev_seen[kind]++;
+  const int w = prof_window(kind);
+  const uint64_t period = (uint64_t)std::max(p->prof_stride, w);
+  const uint64_t pos = seen % period;
+  if (pos >= (uint64_t)w) return -1;
   const size_t i = p->ev_used[kind];
   if (i >= kProfMaxPairs) return -1;
+  auto& v = p->ev[kind];
   while (v.size() < 2 * (i + 1)) {
     hipEvent_t e;
     if (hipEventCreate(&e) != hipSuccess) return -1;
     v.push_back(e);
   }
-  if (hipEventRecord(v[2 * i], st) != hipSuccess) return -1;
-  return (long)i;
+  if (pos == 0 && hipEventRecord(v[2 * i], st) != hipSuccess) return -1;
+  return (long)(pos == (uint64_t)(w - 1) ? i : -2);   // -2: inside a window, no closing event yet
 }
 
 void prof_end(dd_problem* p, int kind, long slot, hipStream_t st) {
@@ -753,7 +762,7 @@ int dd_profile_enable(dd_problem* p, int32_t stride) {
 int dd_profile_read(dd_problem* p, int32_t kind, double* total_ms, int64_t* launches, int32_t reset) {
   if (!p || kind < 0 || kind >= DD_PROF_KINDS) return DD_ERR_INVALID_ARG;
   double tot = 0.0;
-  const size_t n = p->ev_used[kind];
+  const size_t n = p->ev_used[kind];   // closed windows
   if (n) {
     if (hipEventSynchronize(p->ev[kind][2 * n - 1]) != hipSuccess) return fail(p, DD_ERR_HIP, "event synchronize failed");
     for (size_t i = 0; i < n; ++i) {
@@ -764,7 +773,7 @@ int dd_profile_read(dd_problem* p, int32_t kind, double* total_ms, int64_t* laun
     }
   }
   if (total_ms) *total_ms = tot;
-  if (launches) *launches = (int64_t)n;
+  if (launches) *launches = (int64_t)n * prof_window(kind);
   if (reset) {
     p->ev_used[kind] = 0;
     p->ev_seen[kind] = 0;

@@ -13,14 +13,19 @@ namespace dd {
 
 // Finite-difference tile: 32 x 8 nodes in (x, y), marching zc planes in z (8, 16 or 32;
 // default FD_ZC, overridable with the DD_FD_ZC environment variable).
+#ifndef DD_FD_TY
+#define DD_FD_TY 8
+#endif
 constexpr int FD_TX = 32;
-constexpr int FD_TY = 8;
+constexpr int FD_TY = DD_FD_TY;
 constexpr int FD_ZC = 16;
 constexpr int FD_THREADS = FD_TX * FD_TY;
 
 // FEM partition: a block of at most FEM_PB^3 owned nodes plus its halo.
 constexpr int FEM_PB = 8;          // default block edge; DD_FEM_PB="x,y,z" overrides
 constexpr int FEM_THREADS = 256;
+// the assembled-stencil FEM part shares launches with the FD tiles: same block size
+constexpr int STENCIL_THREADS = FD_THREADS;
 constexpr int FEM_LOC_MAX = 1024;  // owned + halo nodes per partition (11-bit local ids)
 constexpr int FEM_OWN_MAX = 512;
 constexpr int FEM_COLORS_MAX = 64;

@@ -512,12 +512,12 @@ __global__ __launch_bounds__(FEM_THREADS) void fem_step_kernel(FemArgs a) {
 // ---------------------------------------------------------------------------------------
 template <bool ADJ, bool ENERGY>
 __device__ __forceinline__ void fem_stencil_part(const FemArgs& a, const int p) {
-  constexpr int NPT = FEM_OWN_MAX / FEM_THREADS;
+  constexpr int NPT = FEM_OWN_MAX / STENCIL_THREADS;
   extern __shared__ __align__(16) unsigned char lds[];
   float4* sX = reinterpret_cast<float4*>(lds);                   // [box]: E_x, E_y, E_z, eps - 1
   float* sKB = reinterpret_cast<float*>(sX + a.lds_box);          // [n_slots][12]: K, B (9), pad
   int* sOff = reinterpret_cast<int*>(sKB + 12 * STENCIL_SLOTS_MAX);  // [n_slots] box offsets
-  __shared__ double red[ENERGY ? FEM_THREADS : 1];
+  __shared__ double red[ENERGY ? STENCIL_THREADS : 1];
   const int tid = threadIdx.x;
   const int ox = a.part_dims[4 * p], oy = a.part_dims[4 * p + 1], oz = a.part_dims[4 * p + 2];
   const int bbase = a.part_dims[4 * p + 3];
@@ -536,17 +536,17 @@ __device__ __forceinline__ void fem_stencil_part(const FemArgs& a, const int p) 
   }
   // stage the box of node values in batches (one memory latency per batch)
   constexpr int NB = 4;
-  for (int base = 0; base < nbox; base += NB * FEM_THREADS) {
+  for (int base = 0; base < nbox; base += NB * STENCIL_THREADS) {
     int code[NB];
 #pragma unroll
     for (int k = 0; k < NB; ++k) {
-      const int l = base + k * FEM_THREADS + tid;
+      const int l = base + k * STENCIL_THREADS + tid;
       code[k] = l < nbox ? a.box_codes[bbase + l] : 0;
     }
     float4 xv[NB];
 #pragma unroll
     for (int k = 0; k < NB; ++k) {
-      const int l = base + k * FEM_THREADS + tid;
+      const int l = base + k * STENCIL_THREADS + tid;
       xv[k] = make_float4(0.f, 0.f, 0.f, 0.f);
       if (l < nbox && code[k] >= 0) {
         const int id = code[k];
@@ -563,7 +563,7 @@ __device__ __forceinline__ void fem_stencil_part(const FemArgs& a, const int p) 
     }
 #pragma unroll
     for (int k = 0; k < NB; ++k) {
-      const int l = base + k * FEM_THREADS + tid;
+      const int l = base + k * STENCIL_THREADS + tid;
       if (l < nbox) sX[l] = xv[k];
     }
   }
@@ -572,7 +572,7 @@ __device__ __forceinline__ void fem_stencil_part(const FemArgs& a, const int p) 
   float pI[NPT][3], pc1[NPT], pc2[NPT], pem[NPT];
 #pragma unroll
   for (int j = 0; j < NPT; ++j) {
-    const int l = tid + j * FEM_THREADS;
+    const int l = tid + j * STENCIL_THREADS;
     if (l < no) {
       const int id = o0 + l;
 #pragma unroll
@@ -587,7 +587,7 @@ __device__ __forceinline__ void fem_stencil_part(const FemArgs& a, const int p) 
   double eacc = 0.0;
 #pragma unroll
   for (int j = 0; j < NPT; ++j) {
-    const int l = tid + j * FEM_THREADS;
+    const int l = tid + j * STENCIL_THREADS;
     if (l >= no) continue;
     const int id = o0 + l;
     const int ix = l % ox, iy = (l / ox) % oy, iz = l / (ox * oy);
@@ -666,7 +666,7 @@ __device__ __forceinline__ void fem_stencil_part(const FemArgs& a, const int p) 
   if (ENERGY) {
     red[tid] = eacc;
     __syncthreads();
-    for (int w = FEM_THREADS / 2; w > 0; w >>= 1) {
+    for (int w = STENCIL_THREADS / 2; w > 0; w >>= 1) {
       if (tid < w) red[tid] += red[tid + w];
       __syncthreads();
     }
@@ -675,7 +675,7 @@ __device__ __forceinline__ void fem_stencil_part(const FemArgs& a, const int p) 
 }
 
 template <bool ADJ, bool ENERGY>
-__global__ __launch_bounds__(FEM_THREADS) void fem_stencil_kernel(FemArgs a) {
+__global__ __launch_bounds__(STENCIL_THREADS) void fem_stencil_kernel(FemArgs a) {
   fem_stencil_part<ADJ, ENERGY>(a, blockIdx.x);
 }
 
@@ -862,13 +862,13 @@ static size_t stencil_lds_bytes(const FemArgs& a) {
 void launch_fem_stencil_fwd(const FemArgs& a, int n_part, hipStream_t s, bool energy) {
   const size_t lds = stencil_lds_bytes(a);
   if (energy)
-    hipLaunchKernelGGL((fem_stencil_kernel<false, true>), dim3(n_part), dim3(FEM_THREADS), lds, s, a);
+    hipLaunchKernelGGL((fem_stencil_kernel<false, true>), dim3(n_part), dim3(STENCIL_THREADS), lds, s, a);
   else
-    hipLaunchKernelGGL((fem_stencil_kernel<false, false>), dim3(n_part), dim3(FEM_THREADS), lds, s, a);
+    hipLaunchKernelGGL((fem_stencil_kernel<false, false>), dim3(n_part), dim3(STENCIL_THREADS), lds, s, a);
 }
 
 void launch_fem_stencil_adj(const FemArgs& a, int n_part, hipStream_t s) {
-  hipLaunchKernelGGL((fem_stencil_kernel<true, false>), dim3(n_part), dim3(FEM_THREADS), stencil_lds_bytes(a), s, a);
+  hipLaunchKernelGGL((fem_stencil_kernel<true, false>), dim3(n_part), dim3(STENCIL_THREADS), stencil_lds_bytes(a), s, a);
 }
 
 template <int ZC>

@@ -296,11 +296,10 @@ def small(name: str, seed_offset: int = 0) -> Workload:
     return Workload(name, desc, eps, sig, [src], seed, eps_true=eps, sigma_true=sig)
 
 
-def batch_mix(n_problems=16, seed=SEED_BASE + 4, scale=1.0):
-    """Uneven multi-problem mix: outer 96..224 nodes, FEM 32..96 cells, valid pairs.
-
-    ``scale`` < 1 shrinks every grid (for tests) while keeping the mix uneven.
-    """
+def batch_mix(n_problems=16, seed=SEED_BASE + 4, ckpt_every=64):
+    """Uneven multi-problem mix: outer 96..224 nodes, FEM 32..96 cells (valid pairs), 1000-2500
+    steps, layered-skin media; even problems get a plane wave of seeded polarisation, odd ones
+    a point dipole of seeded moment 4 nodes above the FEM box."""
     rng = np.random.Generator(np.random.PCG64(seed))
     out = []
     for p in range(n_problems):
@@ -309,15 +308,17 @@ def batch_mix(n_problems=16, seed=SEED_BASE + 4, scale=1.0):
             nf = int(rng.choice([32, 48, 64, 80, 96]))
             if no >= nf + 2 * max(8, math.ceil(0.2 * nf)):
                 break
-        if scale != 1.0:
-            nf = max(6, int(round(nf * scale)))
-            no = max(nf + 8, int(round(no * scale)))
         nt = int(rng.integers(1000, 2501))
-        if scale != 1.0:
-            nt = max(20, int(round(nt * scale)))
-        desc = _centered_desc(no, nf, nt)
-        src = gauss_sine(2.0 * math.pi / 2.236 if scale == 1.0 else 2.0 * math.pi / (18.0 / nf))
-        desc.t_switch = src.support_end()
+        desc = _centered_desc(no, nf, nt, ckpt_every=ckpt_every)
+        base = gauss_sine(2.0 * math.pi / 2.236)
+        desc.t_switch = base.support_end()
+        v = rng.normal(size=3)
+        v = tuple(v / np.linalg.norm(v))
+        if p % 2 == 0:
+            src = gauss_sine(base.omega, pol=(v[0], v[1], 0.0))
+        else:
+            src = Source(kind=SRC_DIPOLE, omega=base.omega, t0=base.t0, width=base.width, pol=v,
+                         pos=(no // 2, no // 2, desc.fem_lo[2] + nf + 4))
         eps, sig, _ = skin_media(desc, rng)
         out.append(Workload(f"mix{p}", desc, eps, sig, [src], seed + p, eps_true=eps, sigma_true=sig))
     return out
