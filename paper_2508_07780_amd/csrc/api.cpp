@@ -595,7 +595,7 @@ int dd_create(const dd_problem_desc* desc, dd_problem** out) {
   p->nby = (p->ny + FD_TY - 1) / FD_TY;
   if (const char* zc = std::getenv("DD_FD_ZC")) {
     const int v = std::atoi(zc);
-    if (v == 8 || v == 16 || v == 32) p->zc = v;
+    if (v == 8 || v == 16) p->zc = v;
   }
   p->nbz = (p->nz + p->zc - 1) / p->zc;
   p->n_tiles = p->nbx * p->nby * p->nbz;

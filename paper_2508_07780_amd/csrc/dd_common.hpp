@@ -11,14 +11,14 @@
 
 namespace dd {
 
-// Finite-difference tile: 32 x 8 nodes in (x, y), marching zc planes in z (8, 16 or 32;
+// Finite-difference tile: 32 x 8 nodes in (x, y), marching zc planes in z (8 or 16;
 // default FD_ZC, overridable with the DD_FD_ZC environment variable).
 #ifndef DD_FD_TY
 #define DD_FD_TY 8
 #endif
 constexpr int FD_TX = 32;
 constexpr int FD_TY = DD_FD_TY;
-constexpr int FD_ZC = 16;
+constexpr int FD_ZC = 8;
 constexpr int FD_THREADS = FD_TX * FD_TY;
 
 // FEM partition: a block of at most FEM_PB^3 owned nodes plus its halo.

@@ -20,15 +20,27 @@ namespace dd {
 // lumped absorbing damping on absorbing faces and the plane-wave / dipole forcing.
 // Tile = 32 x 8 nodes in (x, y), marching ZC planes in z: the current plane sits in LDS
 // (with a one-node halo, double-buffered), the z-1 / z+1 values of each column stay in a
-// register queue that is prefetched two planes ahead; increments and halo one plane ahead.
+// register queue that is prefetched three planes ahead; increments and halo two ahead.
+// The march is fully unrolled, so the queues rotate by renaming registers, and every
+// access is a 32-bit byte offset from a uniform base pointer (one offset register serves
+// the three components).  Loads never branch on a lane's position: lanes outside the grid
+// read a valid clamped address and their values are discarded.
 // ---------------------------------------------------------------------------------------
+__device__ __forceinline__ float ld_at(const char* base, uint32_t off) {
+  return *reinterpret_cast<const float*>(base + off);
+}
+__device__ __forceinline__ void st_at(char* base, uint32_t off, float v) {
+  *reinterpret_cast<float*>(base + off) = v;
+}
+
 // b: block index within the finite-difference part of the launch; b % N_XCD must equal
 // blockIdx.x % N_XCD so that the remap below keeps consecutive tiles on one XCD.
 template <int ZC, bool ENERGY>
 __device__ __forceinline__ void fd_tile(const FdArgs& a, const int b) {
   // two LDS planes: plane z is written while plane z-1 may still be read by slower waves,
   // so one barrier per plane suffices
-  __shared__ float s[2][3][FD_TY + 2][FD_TX + 2];
+  constexpr int SW = FD_TX + 2, SC = (FD_TY + 2) * SW;   // row and component strides
+  __shared__ float s[2][3 * SC];
   __shared__ double red[ENERGY ? FD_THREADS : 1];
   const int t = (b % N_XCD) * a.per_xcd + b / N_XCD;  // consecutive tiles share an XCD's L2
   if (t >= a.ntiles) return;
@@ -49,92 +61,101 @@ __device__ __forceinline__ void fd_tile(const FdArgs& a, const int b) {
   const int tx = tid % FD_TX, ty = tid / FD_TX;
   const int x = x0 + tx, y = y0 + ty;
   const bool col_ok = (x < nx) && (y < ny);
-  const int plane = nx * ny;           // N < 2^31: 32-bit offsets within one component
-  const int col = y * nx + x;
-  const float* __restrict__ X0 = a.X_in;
-  const float* __restrict__ X1 = a.X_in + a.N;
-  const float* __restrict__ X2 = a.X_in + 2 * a.N;
-  float* __restrict__ I0 = a.I;
-  float* __restrict__ I1 = a.I + a.N;
-  float* __restrict__ I2 = a.I + 2 * a.N;
+  // byte offsets within one component (the grid has fewer than 2^30 nodes)
+  const uint32_t plane4 = 4u * (uint32_t)(nx * ny);
+  const uint32_t col4 = col_ok ? 4u * (uint32_t)(y * nx + x) : 0u;
+  const size_t comp = (size_t)a.N * 4;
+  const char* X0 = reinterpret_cast<const char*>(a.X_in);
+  const char* X1 = X0 + comp;
+  const char* X2 = X1 + comp;
+  char* I0 = reinterpret_cast<char*>(a.I);
+  char* I1 = I0 + comp;
+  char* I2 = I1 + comp;
 
   // halo cell of this thread (80 ring cells of the 32 x 8 tile, corners unused)
-  int hx = -1, hy = -1, hsy = 0, hsx = 0;
-  if (tid < FD_TX) { hx = x0 + tid; hy = y0 - 1; hsy = 0; hsx = tid + 1; }
-  else if (tid < 2 * FD_TX) { hx = x0 + tid - FD_TX; hy = y0 + FD_TY; hsy = FD_TY + 1; hsx = tid - FD_TX + 1; }
-  else if (tid < 2 * FD_TX + FD_TY) { hx = x0 - 1; hy = y0 + tid - 2 * FD_TX; hsy = tid - 2 * FD_TX + 1; hsx = 0; }
-  else if (tid < 2 * FD_TX + 2 * FD_TY) { hx = x0 + FD_TX; hy = y0 + tid - 2 * FD_TX - FD_TY; hsy = tid - 2 * FD_TX - FD_TY + 1; hsx = FD_TX + 1; }
+  int hx = 0, hy = 0, hs = 0;
+  if (tid < FD_TX) { hx = x0 + tid; hy = y0 - 1; hs = tid + 1; }
+  else if (tid < 2 * FD_TX) { hx = x0 + tid - FD_TX; hy = y0 + FD_TY; hs = (FD_TY + 1) * SW + tid - FD_TX + 1; }
+  else if (tid < 2 * FD_TX + FD_TY) { hx = x0 - 1; hy = y0 + tid - 2 * FD_TX; hs = (tid - 2 * FD_TX + 1) * SW; }
+  else { hx = x0 + FD_TX; hy = y0 + tid - 2 * FD_TX - FD_TY; hs = (tid - 2 * FD_TX - FD_TY + 1) * SW + FD_TX + 1; }
+  const bool h_role = tid < 2 * FD_TX + 2 * FD_TY;
   const bool h_ok = hx >= 0 && hx < nx && hy >= 0 && hy < ny;
-  const int hcol = h_ok ? hy * nx + hx : 0;
+  const uint32_t hcol4 = (h_role && h_ok) ? 4u * (uint32_t)(hy * nx + hx) : 0u;
 
   const bool bxl = x == 0, bxh = x == nx - 1, byl = y == 0, byh = y == ny - 1;
-  const float wx = (bxl || bxh) ? 2.f : 1.f;   // 2 / (neighbours along x): mirror weights
-  const float wy = (byl || byh) ? 2.f : 1.f;
   const bool in_box_xy = x > a.blo[0] && x < a.bhi[0] && y > a.blo[1] && y < a.bhi[1];
   const bool in_box_xy_closed = x >= a.blo[0] && x <= a.bhi[0] && y >= a.blo[1] && y <= a.bhi[1];
 
-  // register queue of this column: q0 = z-1, q1 = z, q2 = z+1, q3 = z+2 (in flight)
-  float q0[3] = {0.f, 0.f, 0.f}, q1[3] = {0.f, 0.f, 0.f}, q2[3] = {0.f, 0.f, 0.f}, q3[3];
-  float hv[3] = {0.f, 0.f, 0.f}, hn[3];
-  float v[3] = {0.f, 0.f, 0.f}, vn[3];
-  if (col_ok) {
-    const int o = z0 * plane + col;
-    q1[0] = X0[o]; q1[1] = X1[o]; q1[2] = X2[o];
-    if (z0 > 0) { q0[0] = X0[o - plane]; q0[1] = X1[o - plane]; q0[2] = X2[o - plane]; }
-    if (z0 + 1 < nz) { q2[0] = X0[o + plane]; q2[1] = X1[o + plane]; q2[2] = X2[o + plane]; }
-    v[0] = I0[o]; v[1] = I1[o]; v[2] = I2[o];
+  // Register queues along z.  Column: q0 = z-1, q1 = z, q2 = z+1, q3 = z+2, q4 = z+3 (in
+  // flight); increment v = z, vn = z+1, vn2 = z+2 (in flight); halo cell hv = z, hn = z+1,
+  // hn2 = z+2 (in flight).  Planes outside the grid or past the chunk read as 0.
+  float q0[3] = {0.f, 0.f, 0.f}, q1[3], q2[3] = {0.f, 0.f, 0.f}, q3[3] = {0.f, 0.f, 0.f}, q4[3];
+  float hv[3] = {0.f, 0.f, 0.f}, hn[3] = {0.f, 0.f, 0.f}, hn2[3];
+  float v[3], vn[3] = {0.f, 0.f, 0.f}, vn2[3];
+  {
+    const uint32_t o = (uint32_t)z0 * plane4 + col4;
+    q1[0] = ld_at(X0, o); q1[1] = ld_at(X1, o); q1[2] = ld_at(X2, o);
+    if (z0 > 0) { q0[0] = ld_at(X0, o - plane4); q0[1] = ld_at(X1, o - plane4); q0[2] = ld_at(X2, o - plane4); }
+    if (z0 + 1 < nz) { q2[0] = ld_at(X0, o + plane4); q2[1] = ld_at(X1, o + plane4); q2[2] = ld_at(X2, o + plane4); }
+    if (z0 + 2 < nz && z0 + 2 <= z1) {
+      const uint32_t o2 = o + 2 * plane4;
+      q3[0] = ld_at(X0, o2); q3[1] = ld_at(X1, o2); q3[2] = ld_at(X2, o2);
+    }
+    v[0] = ld_at(I0, o); v[1] = ld_at(I1, o); v[2] = ld_at(I2, o);
+    if (z0 + 1 < z1) { vn[0] = ld_at(I0, o + plane4); vn[1] = ld_at(I1, o + plane4); vn[2] = ld_at(I2, o + plane4); }
   }
-  if (h_ok) {
-    const int o = z0 * plane + hcol;
-    hv[0] = X0[o]; hv[1] = X1[o]; hv[2] = X2[o];
+  if (h_role) {
+    const uint32_t o = (uint32_t)z0 * plane4 + hcol4;
+    hv[0] = ld_at(X0, o); hv[1] = ld_at(X1, o); hv[2] = ld_at(X2, o);
+    if (z0 + 1 < z1) { hn[0] = ld_at(X0, o + plane4); hn[1] = ld_at(X1, o + plane4); hn[2] = ld_at(X2, o + plane4); }
   }
   double eacc = 0.0;
-  int buf = 0;
-  for (int z = z0; z < z1; ++z) {
-    const int zoff = z * plane;
-    if (col_ok) {
-      s[buf][0][ty + 1][tx + 1] = q1[0];
-      s[buf][1][ty + 1][tx + 1] = q1[1];
-      s[buf][2][ty + 1][tx + 1] = q1[2];
+#pragma unroll
+  for (int k = 0; k < ZC; ++k) {
+    const int z = z0 + k;
+    if (z >= z1) break;
+    const uint32_t zo = (uint32_t)z * plane4;
+    float* sb = s[k & 1];
+    const int sc = (ty + 1) * SW + tx + 1;
+#pragma unroll
+    for (int c = 0; c < 3; ++c) sb[c * SC + sc] = q1[c];
+    if (h_role) {
+#pragma unroll
+      for (int c = 0; c < 3; ++c) sb[c * SC + hs] = hv[c];
     }
-    if (h_ok) {
-      s[buf][0][hsy][hsx] = hv[0];
-      s[buf][1][hsy][hsx] = hv[1];
-      s[buf][2][hsy][hsx] = hv[2];
+    // prefetch: column three planes ahead (up to the plane just past the chunk), halo and
+    // increment two planes ahead (within the chunk)
+    q4[0] = q4[1] = q4[2] = 0.f;
+    hn2[0] = hn2[1] = hn2[2] = 0.f;
+    vn2[0] = vn2[1] = vn2[2] = 0.f;
+    if (z + 3 < nz && z + 3 <= z1) {
+      const uint32_t o = zo + 3 * plane4 + col4;
+      q4[0] = ld_at(X0, o); q4[1] = ld_at(X1, o); q4[2] = ld_at(X2, o);
     }
-    // prefetch: column two planes ahead, halo and increment one plane ahead
-    q3[0] = q3[1] = q3[2] = 0.f;
-    hn[0] = hn[1] = hn[2] = 0.f;
-    vn[0] = vn[1] = vn[2] = 0.f;
-    if (col_ok && z + 2 < nz && z + 2 <= z1) {
-      const int o = zoff + 2 * plane + col;
-      q3[0] = X0[o]; q3[1] = X1[o]; q3[2] = X2[o];
-    }
-    if (col_ok && z + 1 < z1) {
-      const int o = zoff + plane + col;
-      vn[0] = I0[o]; vn[1] = I1[o]; vn[2] = I2[o];
-    }
-    if (h_ok && z + 1 < z1) {
-      const int o = zoff + plane + hcol;
-      hn[0] = X0[o]; hn[1] = X1[o]; hn[2] = X2[o];
+    if (z + 2 < z1) {
+      const uint32_t o = zo + 2 * plane4 + col4;
+      vn2[0] = ld_at(I0, o); vn2[1] = ld_at(I1, o); vn2[2] = ld_at(I2, o);
+      if (h_role) {
+        const uint32_t oh = zo + 2 * plane4 + hcol4;
+        hn2[0] = ld_at(X0, oh); hn2[1] = ld_at(X1, oh); hn2[2] = ld_at(X2, oh);
+      }
     }
     __syncthreads();
     const bool fem_owned = in_box_xy && z > a.blo[2] && z < a.bhi[2];
     if (col_ok && !fem_owned) {
       const bool bzl = z == 0, bzh = z == nz - 1;
+      const float wx = (bxl || bxh) ? 2.f : 1.f;   // 2 / (neighbours along x): mirror weights
+      const float wy = (byl || byh) ? 2.f : 1.f;
       const float wz = (bzl || bzh) ? 2.f : 1.f;
-      const int idx = zoff + col;
+      const uint32_t idx4 = zo + col4;
       float L[3];
 #pragma unroll
       for (int c = 0; c < 3; ++c) {
         const float xc = q1[c];
-        float sx = 0.f, sy = 0.f, sz = 0.f;
-        if (!bxl) sx += xc - s[buf][c][ty + 1][tx];
-        if (!bxh) sx += xc - s[buf][c][ty + 1][tx + 2];
-        if (!byl) sy += xc - s[buf][c][ty][tx + 1];
-        if (!byh) sy += xc - s[buf][c][ty + 2][tx + 1];
-        if (!bzl) sz += xc - q0[c];
-        if (!bzh) sz += xc - q2[c];
+        const float* p = sb + c * SC + sc;
+        const float sx = (bxl ? 0.f : xc - p[-1]) + (bxh ? 0.f : xc - p[1]);
+        const float sy = (byl ? 0.f : xc - p[-SW]) + (byh ? 0.f : xc - p[SW]);
+        const float sz = (bzl ? 0.f : xc - q0[c]) + (bzh ? 0.f : xc - q2[c]);
         L[c] = a.nu2 * (wx * sx + wy * sy + wz * sz);
       }
       const bool on_bnd = bxl || bxh || byl || byh || bzl || bzh;
@@ -156,16 +177,16 @@ __device__ __forceinline__ void fd_tile(const FdArgs& a, const int b) {
         }
         if (a.det_mask) det = face_lex_index(x, y, z, nx, ny, nz, a.det_mask);
         if (det >= 0 && a.cot_in) {
-          const float sc = a.dt2_h3 * (float)(1 << bcount);   // dt^2 / m_i
+          const float sc2 = a.dt2_h3 * (float)(1 << bcount);   // dt^2 / m_i
           // r = dJ/dT: the cotangent itself, or T - E_obs when the observations are given
 #pragma unroll
           for (int c = 0; c < 3; ++c) {
             const float r = a.obs_in ? a.cot_in[det * 3 + c] - a.obs_in[det * 3 + c] : a.cot_in[det * 3 + c];
-            src[c] -= r * sc;
+            src[c] -= r * sc2;
           }
         }
       }
-      if ((int64_t)idx == a.dip_idx) {
+      if ((int64_t)(idx4 >> 2) == a.dip_idx) {
 #pragma unroll
         for (int c = 0; c < 3; ++c) src[c] += a.dip[c];
       }
@@ -183,10 +204,9 @@ __device__ __forceinline__ void fd_tile(const FdArgs& a, const int b) {
       }
 #pragma unroll
       for (int c = 0; c < 3; ++c) xn[c] = q1[c] + out[c];
-      I0[idx] = out[0]; I1[idx] = out[1]; I2[idx] = out[2];
-      a.X_out[idx] = xn[0];
-      a.X_out[a.N + idx] = xn[1];
-      a.X_out[2 * a.N + idx] = xn[2];
+      st_at(I0, idx4, out[0]); st_at(I1, idx4, out[1]); st_at(I2, idx4, out[2]);
+      char* O0 = reinterpret_cast<char*>(a.X_out);
+      st_at(O0, idx4, xn[0]); st_at(O0 + comp, idx4, xn[1]); st_at(O0 + 2 * comp, idx4, xn[2]);
       if (det >= 0 && a.tr_out) {
 #pragma unroll
         for (int c = 0; c < 3; ++c) a.tr_out[det * 3 + c] = xn[c];
@@ -207,10 +227,12 @@ __device__ __forceinline__ void fd_tile(const FdArgs& a, const int b) {
       q0[c] = q1[c];
       q1[c] = q2[c];
       q2[c] = q3[c];
+      q3[c] = q4[c];
       hv[c] = hn[c];
+      hn[c] = hn2[c];
       v[c] = vn[c];
+      vn[c] = vn2[c];
     }
-    buf ^= 1;
   }
   if (ENERGY) {
     red[tid] = eacc;
@@ -818,7 +840,6 @@ static void launch_fd_zc(const FdArgs& a, hipStream_t s, bool energy) {
 void launch_fd(const FdArgs& a, hipStream_t s, bool energy) {
   switch (a.zc) {
     case 8: launch_fd_zc<8>(a, s, energy); break;
-    case 32: launch_fd_zc<32>(a, s, energy); break;
     default: launch_fd_zc<16>(a, s, energy); break;
   }
 }
@@ -887,7 +908,6 @@ static void launch_step_zc(const FdArgs& fa, const FemArgs& ea, hipStream_t s, b
 void launch_step(const FdArgs& fa, const FemArgs& ea, hipStream_t s, bool adj, bool energy) {
   switch (fa.zc) {
     case 8: launch_step_zc<8>(fa, ea, s, adj, energy); break;
-    case 32: launch_step_zc<32>(fa, ea, s, adj, energy); break;
     default: launch_step_zc<16>(fa, ea, s, adj, energy); break;
   }
 }
