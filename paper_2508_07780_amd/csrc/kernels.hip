@@ -681,8 +681,10 @@ __device__ __forceinline__ void fem_stencil_part(const FemArgs& a, const int p) 
         gm += (double)inc[c] * wv;
         gs += (double)xn[c] * (wv + (double)a.wVm[c * n_own + id]);
       }
-      a.g_eps[id] += ge + m * a.inv_dt2 * gm;
-      a.g_sig[id] += m * a.inv_2dt * gs;
+      // one contribution per node and launch: the device-side FP64 add (no value returned,
+      // so nothing waits for it) rounds once, exactly like a load-add-store
+      unsafeAtomicAdd(a.g_eps + id, ge + m * a.inv_dt2 * gm);
+      unsafeAtomicAdd(a.g_sig + id, m * a.inv_2dt * gs);
     }
   }
   if (ENERGY) {
