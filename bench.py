@@ -3,15 +3,18 @@
 
 Workload (default): layered-skin model, 160^3 outer grid nodes, 64^3 FEM hexes
 (1.57M Kuhn tetrahedra), 2000 time steps, one Gaussian-sine plane wave on the
-top face, detectors on the top face, checkpoints every 64 steps.  Observed data
+top face, detectors on the top face, every forward FEM level kept for the adjoint
+(no recompute; --ckpt-every K checkpoints every K steps instead).  Observed data
 come from the seeded true model plus 3% Gaussian noise; the gradient is taken at
 the initial guess eps = 1, sigma = 0.  Inputs are resident in HBM before timing.
 
 Prints one JSON line with the throughput in Gcell-steps/s, where a cell is an
 outer-grid node or a FEM-owned node and forward and adjoint steps both count,
-the roofline of the dominant kernel (finite-difference step, HIP-event timed over
-the timed region on the solver's stream), per-solve latency p50/p99 and the FP64
-oracle timed on the host on a bounded sample of the same workload.
+the roofline of the dominant kernel (the fused FD + FEM forward step, HIP-event timed
+over the timed region on the solver's stream), per-solve latency p50/p99, the same
+kernels on a 288^3 probe whose fields exceed the last-level cache, the batched and
+serving comparisons, and the FP64 oracle timed on the host on a bounded sample of the
+same workload.
 """
 
 import argparse
@@ -126,6 +129,50 @@ def batch_comparison():
             "ratio": round(t_serial / t_batch, 3)}
 
 
+def large_probe(n_steps=300, stride=16):
+    """The fused step kernels on a 288^3 outer grid (96^3 FEM hexes, layered skin), whose
+    per-step field set (860 MB) exceeds the 256 MB last-level cache, so that the achieved
+    bandwidth is HBM's and not the cache's: one forward (every level kept) + adjoint +
+    gradient, kernels timed with HIP events on the solver's stream."""
+    import torch
+    import synth
+    from paper_2508_07780_amd import Problem, _lib
+    w = synth.probe288(n_steps)
+    dev = torch.device("cuda", 0)
+    p = Problem(w.desc)
+    p.set_coefficients(torch.tensor(w.eps_true, dtype=torch.float32, device=dev),
+                       torch.tensor(w.sigma_true, dtype=torch.float32, device=dev))
+    tr = p.forward(w.sources, save=True)             # warm-up
+    cot = (1e-3 * tr).contiguous()
+    p.adjoint(cot)
+    p.gradient()
+    torch.cuda.synchronize()
+    p.profile(stride)
+    for k in range(len(_lib.PROF_NAMES)):
+        p.profile_read(k, reset=True)
+    t0 = time.perf_counter()
+    p.forward(w.sources, save=True)
+    p.adjoint(cot)
+    p.gradient()
+    torch.cuda.synchronize()
+    wall = time.perf_counter() - t0
+    out = {"workload": f"layered skin, outer {w.desc.n_outer[0]}^3, FEM {w.desc.fem_cells[0]}^3 hexes, "
+                       f"{n_steps} steps forward + adjoint",
+           "field_set_MB": round(w.desc.n_grid() * 36 / 1e6, 1),
+           "gcell_steps_s": round((w.desc.n_grid() + w.desc.n_fem_owned()) * 2 * n_steps / wall / 1e9, 3)}
+    for kind in ("step_fwd", "step_adj"):
+        k = _lib.PROF_NAMES.index(kind)
+        ms, n = p.profile_read(k, reset=True)
+        b = p.algorithmic_bytes(k)
+        if n:
+            gbs = b / (ms / n * 1e-3) / 1e9
+            out[kind] = {"avg_us": round(ms / n * 1e3, 2), "algorithmic_bytes": b,
+                         "algorithmic_GBs": round(gbs, 1), "frac": round(gbs / HBM_PEAK_GBS, 4)}
+    p.profile(0)
+    p.close()
+    return out
+
+
 def serving_comparison():
     """Continuous batching vs one solve at a time on the same uneven request stream.
 
@@ -170,6 +217,7 @@ def main():
     ap.add_argument("--cpu-sample-steps", type=int, default=8, help="0 skips the oracle baseline")
     ap.add_argument("--no-profile", action="store_true", help="skip the HIP-event kernel timing")
     ap.add_argument("--serving", type=int, default=1, help="0 skips the batched / serving comparison")
+    ap.add_argument("--probe", type=int, default=1, help="0 skips the 288^3 bandwidth probe")
     ap.add_argument("--profile-stride", type=int, default=64,
                     help="time every k-th step launch with HIP events (k >= 16 barely perturbs the run)")
     args = ap.parse_args()
@@ -274,6 +322,8 @@ def main():
         "gradient_finite": finite,
     }
     del prob
+    if args.probe:
+        out["hbm_probe"] = large_probe()
     if args.serving:
         out["batched_mix"] = batch_comparison()
         out["serving"] = serving_comparison()

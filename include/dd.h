@@ -179,7 +179,9 @@ int dd_batch_poll(dd_batch* b, int32_t* done_jobs, int32_t capacity, int32_t* n_
  * last event of `kind` and returns the summed time and the number of timed launches;
  * reset != 0 clears that kind.  dd_algorithmic_bytes
  * gives the minimum HBM bytes one launch of `kind` must move (each field value read or
- * written once). */
+ * written once); for the forward kinds it is the average over the launches of a forward
+ * that saves its state for dd_adjoint (store-every-level: each launch writes the FEM
+ * state once more). */
 enum {
   DD_PROF_FD_FWD = 0, DD_PROF_FEM_FWD = 1, DD_PROF_FD_ADJ = 2, DD_PROF_FEM_ADJ = 3,
   DD_PROF_FEM_RECOMPUTE = 4,

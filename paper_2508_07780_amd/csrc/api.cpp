@@ -785,31 +785,33 @@ int dd_algorithmic_bytes(const dd_problem* p, int32_t kind, double* bytes_per_la
   if (!p || !bytes_per_launch || kind < 0 || kind >= DD_PROF_KINDS) return DD_ERR_INVALID_ARG;
   const double n_fd = (double)(p->N - p->n_own);
   const double n_own = (double)p->n_own, n_l0 = (double)p->n_l0, n_det = (double)p->n_det;
-  int64_t n_free = 1;
-  for (int a = 0; a < 3; ++a) n_free *= std::max(p->d.fem_cells[a] - 3, 0);
-  const double n_l1 = (double)(p->n_own - n_free);
+  int64_t n_free_i = 1;
+  for (int a = 0; a < 3; ++a) n_free_i *= std::max(p->d.fem_cells[a] - 3, 0);
+  const double n_free = (double)n_free_i, n_l1 = n_own - n_free;
+  // a saving forward also writes the FEM state (E, V) of the levels the adjoint reads back:
+  // every level of the last segment and the segment-start checkpoints before it
+  const int64_t nt = p->d.n_steps, K = p->d.ckpt_every, k_tail = last_segment_start(p);
+  int64_t saved = 0;
+  for (int64_t n = 0; n < nt; ++n)
+    if (n + 1 >= k_tail || ((n + 1) % K == 0 && (n + 1) / K < p->n_ck)) ++saved;
+  const double save_fem = 24.0 * n_own * (double)saved / (double)std::max<int64_t>(nt, 1);
+  // FD: E^n, V^n read, E^{n+1}, V^{n+1} written; traces (forward) written or cotangent
+  // (adjoint) read; layer-0 values written
+  const double fd = 48.0 * n_fd + 12.0 * n_det + 12.0 * n_l0;
+  // FEM: state read and written, coefficients (eps - 1, c1, c2), layer-0 values read,
+  // layer-1 values dual-written into the FD grid
+  const double fem = 48.0 * n_own + 12.0 * n_own + 12.0 * n_l0 + 12.0 * n_l1;
+  // adjoint FEM, free nodes: forward window E^k, V^k, V^{k-1} read, FP64 gradients updated
+  const double grad = 36.0 * n_free + 32.0 * n_free;
   double b = 0.0;
   switch (kind) {
-    case DD_PROF_FD_FWD:   // E^n, V^n read, V^{n+1}, E^{n+1} written; traces and layer-0 values written
-    case DD_PROF_FD_ADJ:   // same with lambda, Lambda; cotangent read instead of traces written
-      b = 48.0 * n_fd + 12.0 * n_det + 12.0 * n_l0;
-      break;
-    case DD_PROF_FEM_FWD:
-    case DD_PROF_FEM_RECOMPUTE:
-      // state (E read/written, V read/written), coefficients eps-1, c1, c2, layer-0 read, layer-1 dual write
-      b = 48.0 * n_own + 12.0 * n_own + 12.0 * n_l0 + 12.0 * n_l1;
-      break;
-    case DD_PROF_FEM_ADJ:
-      // adjoint state + coefficients + forward window (E^k, V^k, V^{k-1}) + FP64 gradient read/write (free nodes)
-      b = 48.0 * n_own + 12.0 * n_own + 12.0 * n_l0 + 12.0 * n_l1 + 36.0 * n_own + 32.0 * (n_own - n_l1);
-      break;
-    case DD_PROF_STEP_FWD:
-      b = 48.0 * n_fd + 12.0 * n_det + 12.0 * n_l0 + 48.0 * n_own + 12.0 * n_own + 12.0 * n_l0 + 12.0 * n_l1;
-      break;
-    case DD_PROF_STEP_ADJ:
-      b = 48.0 * n_fd + 12.0 * n_det + 12.0 * n_l0 + 48.0 * n_own + 12.0 * n_own + 12.0 * n_l0 + 12.0 * n_l1 +
-          36.0 * n_own + 32.0 * (n_own - n_l1);
-      break;
+    case DD_PROF_FD_FWD:
+    case DD_PROF_FD_ADJ: b = fd; break;
+    case DD_PROF_FEM_FWD: b = fem + save_fem; break;
+    case DD_PROF_FEM_RECOMPUTE: b = 48.0 * n_own + 12.0 * n_own + 12.0 * n_l0; break;   // window to window
+    case DD_PROF_FEM_ADJ: b = fem + grad; break;
+    case DD_PROF_STEP_FWD: b = fd + fem + save_fem; break;
+    case DD_PROF_STEP_ADJ: b = fd + fem + grad; break;
   }
   *bytes_per_launch = b;
   return DD_OK;

@@ -270,6 +270,12 @@ def c3(n_steps=1500) -> Workload:
     return _skin_workload("c3", 3, 192, 96, n_steps, ckpt_every=64)
 
 
+def probe288(n_steps=300) -> Workload:
+    """Bandwidth probe: the layered-skin generator on a 288^3 outer grid (96^3 FEM hexes),
+    whose per-step field set (E twice and V, 860 MB) exceeds the 256 MB last-level cache."""
+    return _skin_workload("probe288", 6, 288, 96, n_steps, ckpt_every=n_steps)
+
+
 _SMALL = {
     # name: (n_outer, h, fem_lo, fem_cells, n_steps, detector faces, ckpt_every)
     "tiny": ((12, 11, 13), 0.05, (3, 3, 4), (5, 4, 5), 40, FACE_ALL, 8),

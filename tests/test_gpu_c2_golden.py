@@ -1,0 +1,85 @@
+"""Full-size parity: the layered-skin workload (160^3 outer nodes, 64^3 FEM hexes, 2000
+steps) on the GPU, in the launch configuration the benchmark times (fused step kernel,
+every forward level kept), against the FP64 oracle.
+
+The oracle run takes over an hour on one host core, so its result is stored:
+tests/golden/make_c2_golden.py (which calls only the oracle and the seeded input
+generators) wrote a seeded sample of 8192 trace entries and 8192 free-node gradient
+entries, the per-step trace norms, the gradient norms and the energy history of the
+true medium, for a seeded cotangent that this test regenerates from the same generator.
+
+Bars: traces rel L2 <= 1e-4 (over the sampled entries, and over the per-step norms),
+gradient rel L2 <= 1e-3 (over the sampled entries, and the norms), energy rel L2 <= 1e-4.
+"""
+
+import os
+
+import numpy as np
+import pytest
+
+import synth
+
+pytestmark = pytest.mark.gpu
+
+HERE = os.path.dirname(os.path.abspath(__file__))
+GOLDEN = os.path.join(HERE, "golden", "c2_oracle_sample_2000.npz")
+
+
+def _rel(a, b):
+    a = np.asarray(a, dtype=np.float64)
+    return float(np.linalg.norm(a - b) / np.linalg.norm(b))
+
+
+@pytest.fixture(scope="module")
+def c2_run():
+    import importlib.util
+    import torch
+    from paper_2508_07780_amd import Problem
+    spec = importlib.util.spec_from_file_location("make_c2_golden", os.path.join(HERE, "golden", "make_c2_golden.py"))
+    mk = importlib.util.module_from_spec(spec)
+    spec.loader.exec_module(mk)
+    ref = np.load(GOLDEN)
+    w = synth.c2(n_steps=int(ref["n_steps"]))
+    w.desc.ckpt_every = w.desc.n_steps          # every forward level kept, as benchmarked
+    print(f"[gpu] c2 golden: {w.desc.n_outer} fem {w.desc.fem_cells} steps {w.desc.n_steps}", flush=True)
+    p = Problem(w.desc)
+    p.set_coefficients(torch.tensor(w.eps_true, dtype=torch.float32, device="cuda"),
+                       torch.tensor(w.sigma_true, dtype=torch.float32, device="cuda"))
+    tr = p.forward(w.sources, save=True).clone()
+    cot = mk.cotangent(tuple(tr.shape[1:]), w.seed)
+    p.adjoint(torch.tensor(cot[None], device="cuda"))
+    ge, gs = (g.cpu().numpy() for g in p.gradient())
+    _, en = p.forward(w.sources, save=False, energy=True)
+    torch.cuda.synchronize()
+    out = dict(traces=tr[0].cpu().numpy(), g_eps=ge, g_sigma=gs, energy=en[0].cpu().numpy())
+    p.close()
+    return ref, out
+
+
+def test_c2_traces_match_oracle(c2_run):
+    ref, out = c2_run
+    tr = out["traces"]
+    e_sample = _rel(tr[ref["t_idx"], ref["d_idx"], :], ref["traces"])
+    e_norm = _rel(np.sqrt(np.sum(tr.astype(np.float64) ** 2, axis=(1, 2))), ref["trace_row_norm"])
+    print(f"[gpu] c2 traces: sampled rel L2 {e_sample:.3e}, per-step norms rel L2 {e_norm:.3e}", flush=True)
+    assert e_sample <= 1e-4 and e_norm <= 1e-4
+
+
+def test_c2_gradient_matches_oracle(c2_run):
+    ref, out = c2_run
+    gi = ref["g_idx"]
+    e_eps = _rel(out["g_eps"][gi], ref["g_eps"])
+    e_sig = _rel(out["g_sigma"][gi], ref["g_sigma"])
+    n_eps = abs(np.linalg.norm(out["g_eps"]) / float(ref["g_eps_norm"]) - 1.0)
+    n_sig = abs(np.linalg.norm(out["g_sigma"]) / float(ref["g_sigma_norm"]) - 1.0)
+    print(f"[gpu] c2 gradient: sampled rel L2 eps {e_eps:.3e} sigma {e_sig:.3e}; "
+          f"norm ratio - 1: eps {n_eps:.2e} sigma {n_sig:.2e}", flush=True)
+    assert e_eps <= 1e-3 and e_sig <= 1e-3
+    assert n_eps <= 1e-3 and n_sig <= 1e-3
+
+
+def test_c2_energy_matches_oracle(c2_run):
+    ref, out = c2_run
+    e = _rel(out["energy"], ref["energy"])
+    print(f"[gpu] c2 energy rel L2 {e:.3e}", flush=True)
+    assert e <= 1e-4
