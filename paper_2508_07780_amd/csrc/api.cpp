@@ -36,7 +36,8 @@ struct dd_problem {
   double* mass_d = nullptr;
   float *em1 = nullptr, *c1 = nullptr, *c2 = nullptr;
   // state (device)
-  float *Efd[2] = {nullptr, nullptr}, *Vfd = nullptr, *Efem[2] = {nullptr, nullptr}, *Vfem = nullptr;
+  // FD grid: two levels of E (three-level form); FEM: two levels of E and the increment V
+  float *Efd[2] = {nullptr, nullptr}, *Efem[2] = {nullptr, nullptr}, *Vfem = nullptr;
   float* iring = nullptr;  // [2][3][n_l0]
   double* epart = nullptr;
   int* d_err = nullptr;
@@ -241,7 +242,6 @@ void zero_state(dd_problem* p, hipStream_t st) {
     launch_fill_f32(p->Efd[b], 3 * p->N, 0.f, st);
     launch_fill_f32(p->Efem[b], 3 * p->n_own, 0.f, st);
   }
-  launch_fill_f32(p->Vfd, 3 * p->N, 0.f, st);
   launch_fill_f32(p->Vfem, 3 * p->n_own, 0.f, st);
   launch_fill_f32(p->iring, 6 * p->n_l0, 0.f, st);
 }
@@ -338,7 +338,6 @@ void fwd_step_args(const dd_problem* p, const dd_source& src, const SrcPlan& sp,
   const int cur = (int)(n & 1), nxt = (int)((n + 1) & 1);
   fa.X_in = p->Efd[cur];
   fa.X_out = p->Efd[nxt];
-  fa.I = p->Vfd;
   fa.top_a = fa.top_b = top_absorbs(p, n) ? 1 : 0;
   for (int c = 0; c < 3; ++c) {
     fa.pw[c] = (src.kind != DD_SRC_DIPOLE && t <= p->d.t_switch) ? (float)(2.0 * dt * dt / h * P * src.pol[c]) : 0.f;
@@ -394,7 +393,6 @@ void adj_step_args(const dd_problem* p, int s, int64_t k, int64_t k0, const floa
   const int cur = (int)(k & 1), prv = (int)((k - 1) & 1);
   fa.X_in = p->Efd[cur];
   fa.X_out = p->Efd[prv];
-  fa.I = p->Vfd;
   fa.top_a = top_absorbs(p, k - 1) ? 1 : 0;
   fa.top_b = top_absorbs(p, k + 1) ? 1 : 0;
   for (int c = 0; c < 3; ++c) fa.pw[c] = fa.dip[c] = 0.f;
@@ -543,7 +541,7 @@ size_t dd_footprint_bytes(const dd_problem_desc* desc, int32_t n_src) {
   const int64_t n_ck = nseg, tail_levels = nt - (nseg - 1) * K + 1;
   const int64_t tets_est = 6 * n_fem * 3 / 2;  // elements incl. halo duplicates (upper estimate)
   int64_t b = 0;
-  b += 4 * 9 * N;                         // E (2 levels) + V on the grid
+  b += 4 * 6 * N;                         // E (2 levels) on the grid
   b += 4 * 9 * n_own;                     // E (2 levels) + V on the FEM nodes
   b += 4 * 6 * n_l0;                      // interface ring
   b += n_own * (4 * 3 + 8 + 4 * 2 + 8 * 2);  // coefficients, mass, index maps, gradient accumulators
@@ -630,7 +628,6 @@ int dd_create(const dd_problem_desc* desc, dd_problem** out) {
     chk(dalloc(p, &p->Efd[b], 3 * p->N));
     chk(dalloc(p, &p->Efem[b], 3 * p->n_own));
   }
-  chk(dalloc(p, &p->Vfd, 3 * p->N));
   chk(dalloc(p, &p->Vfem, 3 * p->n_own));
   chk(dalloc(p, &p->iring, 6 * p->n_l0));
   chk(dalloc(p, &p->epart, p->n_tiles + p->n_part));
@@ -795,9 +792,9 @@ int dd_algorithmic_bytes(const dd_problem* p, int32_t kind, double* bytes_per_la
   for (int64_t n = 0; n < nt; ++n)
     if (n + 1 >= k_tail || ((n + 1) % K == 0 && (n + 1) / K < p->n_ck)) ++saved;
   const double save_fem = 24.0 * n_own * (double)saved / (double)std::max<int64_t>(nt, 1);
-  // FD: E^n, V^n read, E^{n+1}, V^{n+1} written; traces (forward) written or cotangent
-  // (adjoint) read; layer-0 values written
-  const double fd = 48.0 * n_fd + 12.0 * n_det + 12.0 * n_l0;
+  // FD (three-level form): E^n and E^{n-1} read, E^{n+1} written; traces (forward)
+  // written or cotangent (adjoint) read; layer-0 values written
+  const double fd = 36.0 * n_fd + 12.0 * n_det + 12.0 * n_l0;
   // FEM: state read and written, coefficients (eps - 1, c1, c2), layer-0 values read,
   // layer-1 values dual-written into the FD grid
   const double fem = 48.0 * n_own + 12.0 * n_own + 12.0 * n_l0 + 12.0 * n_l1;

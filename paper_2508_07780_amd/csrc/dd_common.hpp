@@ -74,13 +74,13 @@ inline int64_t face_lex_count(int nx, int ny, int nz, unsigned mask) {
 
 struct FdArgs {
   const float* X_in;   // field at level n (forward E^n, adjoint lambda^k), [3][N]
-  float* X_out;        // field at the next level, [3][N]
-  float* I;            // increment, updated in place (forward V, adjoint Lambda), [3][N]
+  float* X_out;        // field at the previous level on entry (forward E^{n-1}, adjoint
+                       // lambda^{k+1}), overwritten with the next level, [3][N]
   int64_t N;
   int nx, ny, nz;
   int blo[3], bhi[3];  // FEM box node range [fem_lo, fem_lo + fem_cells] per axis
   int nbx, nby, nbz, ntiles, per_xcd;
-  int zc;              // planes per tile in z (8, 16 or 32)
+  int zc;              // planes per tile in z (8 or 16)
   float nu2, nu;       // (dt/h)^2, dt/h
   unsigned abs_mask;
   int top_a, top_b;    // top face absorbing at the levels of D+ (a) and D- (b)

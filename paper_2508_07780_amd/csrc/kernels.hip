@@ -1,10 +1,12 @@
 // HIP kernels (gfx950) of the hybrid FE/FD leapfrog: finite-difference region,
 // FEM region, and the small helpers around them.
 //
-// Both regions advance the same explicit scheme (increment form of the
-// central-difference leapfrog for eq. forward_prob / eq. model1):
+// Both regions advance the same explicit scheme (the central-difference leapfrog for
+// eq. forward_prob / eq. model1), the FEM region in increment form
 //     V^{n+1} = [ (M/dt^2 - C/(2dt)) V^n - A E^n + F^n ] / (M/dt^2 + C/(2dt)),
 //     E^{n+1} = E^n + V^{n+1},
+// the finite-difference region (vacuum) in three-level form, V^n = E^n - E^{n-1} formed
+// from the two stored levels, so that only E is stored there (36 B per node and step),
 // and its exact transpose for the adjoint (eq. adjoint_prob) run backward:
 //     Lambda^k = [ (M/dt^2 - C^{k+1}/(2dt)) Lambda^{k+1} - A^T lambda^k - r^k
 //                  - (C^{k-1} - C^{k+1}) lambda^k / (2dt) ] / (M/dt^2 + C^{k-1}/(2dt)),
@@ -20,7 +22,8 @@ namespace dd {
 // lumped absorbing damping on absorbing faces and the plane-wave / dipole forcing.
 // Tile = 32 x 8 nodes in (x, y), marching ZC planes in z: the current plane sits in LDS
 // (with a one-node halo, double-buffered), the z-1 / z+1 values of each column stay in a
-// register queue that is prefetched three planes ahead; increments and halo two ahead.
+// register queue that is prefetched three planes ahead; the previous level and the halo
+// two ahead.
 // The march is fully unrolled, so the queues rotate by renaming registers, and every
 // access is a 32-bit byte offset from a uniform base pointer (one offset register serves
 // the three components).  Loads never branch on a lane's position: lanes outside the grid
@@ -68,9 +71,11 @@ __device__ __forceinline__ void fd_tile(const FdArgs& a, const int b) {
   const char* X0 = reinterpret_cast<const char*>(a.X_in);
   const char* X1 = X0 + comp;
   const char* X2 = X1 + comp;
-  char* I0 = reinterpret_cast<char*>(a.I);
-  char* I1 = I0 + comp;
-  char* I2 = I1 + comp;
+  // level n-1 on entry, overwritten with level n+1 node by node (only the node's own lane
+  // reads or writes its value in this array)
+  char* P0 = reinterpret_cast<char*>(a.X_out);
+  char* P1 = P0 + comp;
+  char* P2 = P1 + comp;
 
   // halo cell of this thread (80 ring cells of the 32 x 8 tile, corners unused)
   int hx = 0, hy = 0, hs = 0;
@@ -87,11 +92,11 @@ __device__ __forceinline__ void fd_tile(const FdArgs& a, const int b) {
   const bool in_box_xy_closed = x >= a.blo[0] && x <= a.bhi[0] && y >= a.blo[1] && y <= a.bhi[1];
 
   // Register queues along z.  Column: q0 = z-1, q1 = z, q2 = z+1, q3 = z+2, q4 = z+3 (in
-  // flight); increment v = z, vn = z+1, vn2 = z+2 (in flight); halo cell hv = z, hn = z+1,
+  // flight); previous level pv = z, pn = z+1, pn2 = z+2 (in flight); halo cell hv = z, hn = z+1,
   // hn2 = z+2 (in flight).  Planes outside the grid or past the chunk read as 0.
   float q0[3] = {0.f, 0.f, 0.f}, q1[3], q2[3] = {0.f, 0.f, 0.f}, q3[3] = {0.f, 0.f, 0.f}, q4[3];
   float hv[3] = {0.f, 0.f, 0.f}, hn[3] = {0.f, 0.f, 0.f}, hn2[3];
-  float v[3], vn[3] = {0.f, 0.f, 0.f}, vn2[3];
+  float pv[3], pn[3] = {0.f, 0.f, 0.f}, pn2[3];
   {
     const uint32_t o = (uint32_t)z0 * plane4 + col4;
     q1[0] = ld_at(X0, o); q1[1] = ld_at(X1, o); q1[2] = ld_at(X2, o);
@@ -101,8 +106,8 @@ __device__ __forceinline__ void fd_tile(const FdArgs& a, const int b) {
       const uint32_t o2 = o + 2 * plane4;
       q3[0] = ld_at(X0, o2); q3[1] = ld_at(X1, o2); q3[2] = ld_at(X2, o2);
     }
-    v[0] = ld_at(I0, o); v[1] = ld_at(I1, o); v[2] = ld_at(I2, o);
-    if (z0 + 1 < z1) { vn[0] = ld_at(I0, o + plane4); vn[1] = ld_at(I1, o + plane4); vn[2] = ld_at(I2, o + plane4); }
+    pv[0] = ld_at(P0, o); pv[1] = ld_at(P1, o); pv[2] = ld_at(P2, o);
+    if (z0 + 1 < z1) { pn[0] = ld_at(P0, o + plane4); pn[1] = ld_at(P1, o + plane4); pn[2] = ld_at(P2, o + plane4); }
   }
   if (h_role) {
     const uint32_t o = (uint32_t)z0 * plane4 + hcol4;
@@ -127,14 +132,14 @@ __device__ __forceinline__ void fd_tile(const FdArgs& a, const int b) {
     // increment two planes ahead (within the chunk)
     q4[0] = q4[1] = q4[2] = 0.f;
     hn2[0] = hn2[1] = hn2[2] = 0.f;
-    vn2[0] = vn2[1] = vn2[2] = 0.f;
+    pn2[0] = pn2[1] = pn2[2] = 0.f;
     if (z + 3 < nz && z + 3 <= z1) {
       const uint32_t o = zo + 3 * plane4 + col4;
       q4[0] = ld_at(X0, o); q4[1] = ld_at(X1, o); q4[2] = ld_at(X2, o);
     }
     if (z + 2 < z1) {
       const uint32_t o = zo + 2 * plane4 + col4;
-      vn2[0] = ld_at(I0, o); vn2[1] = ld_at(I1, o); vn2[2] = ld_at(I2, o);
+      pn2[0] = ld_at(P0, o); pn2[1] = ld_at(P1, o); pn2[2] = ld_at(P2, o);
       if (h_role) {
         const uint32_t oh = zo + 2 * plane4 + hcol4;
         hn2[0] = ld_at(X0, oh); hn2[1] = ld_at(X1, oh); hn2[2] = ld_at(X2, oh);
@@ -193,20 +198,21 @@ __device__ __forceinline__ void fd_tile(const FdArgs& a, const int b) {
       int64_t l0 = -1;
       if (a.iface_out && in_box_xy_closed && z >= a.blo[2] && z <= a.bhi[2])
         l0 = face_lex_index(x - a.blo[0], y - a.blo[1], z - a.blo[2], a.fs[0], a.fs[1], a.fs[2], 63u);
+      // three-level form: the increment of this level is the difference of the two stored
+      // levels, out = increment of the next level, xn = next level
       float out[3], xn[3];
       if (na == 0 && nb == 0) {
 #pragma unroll
-        for (int c = 0; c < 3; ++c) out[c] = v[c] - L[c] + src[c];
+        for (int c = 0; c < 3; ++c) out[c] = (q1[c] - pv[c]) - L[c] + src[c];
       } else {
         const float ba = a.nu * (float)na, bb = a.nu * (float)nb;
 #pragma unroll
-        for (int c = 0; c < 3; ++c) out[c] = ((1.f - bb) * v[c] - L[c] + src[c] - (ba - bb) * q1[c]) / (1.f + ba);
+        for (int c = 0; c < 3; ++c)
+          out[c] = ((1.f - bb) * (q1[c] - pv[c]) - L[c] + src[c] - (ba - bb) * q1[c]) / (1.f + ba);
       }
 #pragma unroll
       for (int c = 0; c < 3; ++c) xn[c] = q1[c] + out[c];
-      st_at(I0, idx4, out[0]); st_at(I1, idx4, out[1]); st_at(I2, idx4, out[2]);
-      char* O0 = reinterpret_cast<char*>(a.X_out);
-      st_at(O0, idx4, xn[0]); st_at(O0 + comp, idx4, xn[1]); st_at(O0 + 2 * comp, idx4, xn[2]);
+      st_at(P0, idx4, xn[0]); st_at(P1, idx4, xn[1]); st_at(P2, idx4, xn[2]);
       if (det >= 0 && a.tr_out) {
 #pragma unroll
         for (int c = 0; c < 3; ++c) a.tr_out[det * 3 + c] = xn[c];
@@ -230,8 +236,8 @@ __device__ __forceinline__ void fd_tile(const FdArgs& a, const int b) {
       q3[c] = q4[c];
       hv[c] = hn[c];
       hn[c] = hn2[c];
-      v[c] = vn[c];
-      vn[c] = vn2[c];
+      pv[c] = pn[c];
+      pn[c] = pn2[c];
     }
   }
   if (ENERGY) {
