@@ -27,7 +27,8 @@ struct dd_problem {
   int n_slots = 0;
   int *part_dims = nullptr, *box_codes = nullptr, *slot_off = nullptr;
   float *slot_k = nullptr, *slot_b = nullptr;
-  int nbx = 0, nby = 0, nbz = 0, n_tiles = 0, per_xcd = 0, zc = FD_ZC;
+  int nbx = 0, nby = 0, nbz = 0, n_tiles = 0, per_xcd = 0;
+  bool fd_nt = false;     // non-temporal own-node streams in the FD tiles (grid exceeds the LLC)
   // topology (device)
   int *own_off = nullptr, *halo_off = nullptr, *halo = nullptr, *col_base = nullptr, *ncol = nullptr,
       *col_off = nullptr, *own_grid = nullptr, *own_api = nullptr;
@@ -190,7 +191,6 @@ FdArgs fd_base(const dd_problem* p) {
     a.fs[c] = p->fs[c];
   }
   a.nbx = p->nbx; a.nby = p->nby; a.nbz = p->nbz; a.ntiles = p->n_tiles; a.per_xcd = p->per_xcd;
-  a.zc = p->zc;
   const double nu = p->d.dt / p->d.h;
   a.nu = (float)nu;
   a.nu2 = (float)(nu * nu);
@@ -245,6 +245,9 @@ void zero_state(dd_problem* p, hipStream_t st) {
   launch_fill_f32(p->Vfem, 3 * p->n_own, 0.f, st);
   launch_fill_f32(p->iring, 6 * p->n_l0, 0.f, st);
 }
+
+// Bytes of the two levels of E on the FD grid, the set every step streams through.
+double fd_field_bytes(const dd_problem* p) { return 24.0 * (double)p->N; }
 
 // Segments of the adjoint: [k0, k1) per segment, K steps each, the last one shorter.
 int64_t n_segments(const dd_problem* p) {
@@ -431,11 +434,11 @@ int run_forward(dd_problem* p, const dd_source& src, int s, float* traces, bool 
     long ps = -1;
     if (fused) {
       ps = prof_begin(p, DD_PROF_STEP_FWD, st);
-      launch_step(fa, ea, st, false, energy != nullptr);
+      launch_step(fa, ea, st, false, energy != nullptr, p->fd_nt);
       prof_end(p, DD_PROF_STEP_FWD, ps, st);
     } else {
       ps = prof_begin(p, DD_PROF_FD_FWD, st);
-      launch_fd(fa, st, energy != nullptr);
+      launch_fd(fa, st, energy != nullptr, p->fd_nt);
       prof_end(p, DD_PROF_FD_FWD, ps, st);
       ps = prof_begin(p, DD_PROF_FEM_FWD, sf);
       fem_fwd(p, ea, sf, energy != nullptr);
@@ -475,11 +478,11 @@ int run_adjoint(dd_problem* p, int s, const float* cot, const float* obs, hipStr
       long ps = -1;
       if (fused) {
         ps = prof_begin(p, DD_PROF_STEP_ADJ, st);
-        launch_step(fa, ea, st, true, false);
+        launch_step(fa, ea, st, true, false, p->fd_nt);
         prof_end(p, DD_PROF_STEP_ADJ, ps, st);
       } else {
         ps = prof_begin(p, DD_PROF_FD_ADJ, st);
-        launch_fd(fa, st, false);
+        launch_fd(fa, st, false, p->fd_nt);
         prof_end(p, DD_PROF_FD_ADJ, ps, st);
         ps = prof_begin(p, DD_PROF_FEM_ADJ, sf);
         fem_adj(p, ea, sf);
@@ -591,11 +594,9 @@ int dd_create(const dd_problem_desc* desc, dd_problem** out) {
     if (std::strcmp(e, "element") == 0) p->use_stencil = false;
   p->nbx = (p->nx + FD_TX - 1) / FD_TX;
   p->nby = (p->ny + FD_TY - 1) / FD_TY;
-  if (const char* zc = std::getenv("DD_FD_ZC")) {
-    const int v = std::atoi(zc);
-    if (v == 8 || v == 16) p->zc = v;
-  }
-  p->nbz = (p->nz + p->zc - 1) / p->zc;
+  p->nbz = (p->nz + FD_ZC - 1) / FD_ZC;
+  p->fd_nt = fd_field_bytes(p) > LLC_BYTES;
+  if (const char* e = std::getenv("DD_FD_NT")) p->fd_nt = std::atoi(e) != 0;
   p->n_tiles = p->nbx * p->nby * p->nbz;
   p->per_xcd = (p->n_tiles + N_XCD - 1) / N_XCD;
   p->n_ck = (int)((desc->n_steps + desc->ckpt_every - 1) / desc->ckpt_every);
@@ -965,8 +966,8 @@ int dd_batch_submit(dd_batch* b, dd_problem* p, const dd_source* src, int32_t n_
   if ((int)b->jobs.size() >= b->max_slots) return fail(p, DD_ERR_STATE, "no free batch slot");
   for (const auto& j : b->jobs)
     if (j.p == p) return fail(p, DD_ERR_STATE, "problem already has an active batch job");
-  if (!p->use_stencil || !p->fused || p->zc != FD_ZC)
-    return fail(p, DD_ERR_UNSUPPORTED, "batched steps need the assembled-stencil FEM path and the default z-chunk");
+  if (!p->use_stencil || !p->fused)
+    return fail(p, DD_ERR_UNSUPPORTED, "batched steps need the assembled-stencil FEM path");
   for (int s = 0; s < n_src; ++s) {
     const std::string e = check_source(p, src[s]);
     if (!e.empty()) return fail(p, DD_ERR_INVALID_ARG, e);
@@ -1002,6 +1003,7 @@ int dd_batch_step(dd_batch* b, int32_t max_steps, void* stream) {
     BatchItem* h = b->host + (size_t)slot * b->max_slots;
     int n = 0, base = 0;
     size_t lds = 0;
+    double fd_bytes = 0.0;   // the FD field sets this launch streams through
     for (auto& j : b->jobs) {
       BatchItem& it = h[n];
       if (!job_next(j, st, it)) continue;
@@ -1010,6 +1012,7 @@ int dd_batch_step(dd_batch* b, int32_t max_steps, void* stream) {
       it.base = base;
       base += it.fem_blocks + it.fd_blocks;
       lds = std::max(lds, stencil_lds(it.ea));
+      if (it.fd_blocks) fd_bytes += fd_field_bytes(j.p);
       ++n;
     }
     if (n) {
@@ -1019,7 +1022,7 @@ int dd_batch_step(dd_batch* b, int32_t max_steps, void* stream) {
         b->err = "batch upload failed";
         return DD_ERR_HIP;
       }
-      launch_batch(d, n, base, lds, st);
+      launch_batch(d, n, base, lds, st, fd_bytes > LLC_BYTES);
       hipError_t e = hipGetLastError();
       if (e != hipSuccess) {
         b->err = std::string("batch launch failed: ") + hipGetErrorString(e);

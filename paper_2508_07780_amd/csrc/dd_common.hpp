@@ -11,8 +11,7 @@
 
 namespace dd {
 
-// Finite-difference tile: 32 x 8 nodes in (x, y), marching zc planes in z (8 or 16;
-// default FD_ZC, overridable with the DD_FD_ZC environment variable).
+// Finite-difference tile: 32 x 8 nodes in (x, y), marching FD_ZC planes in z.
 #ifndef DD_FD_TY
 #define DD_FD_TY 8
 #endif
@@ -20,6 +19,9 @@ constexpr int FD_TX = 32;
 constexpr int FD_TY = DD_FD_TY;
 constexpr int FD_ZC = 8;
 constexpr int FD_THREADS = FD_TX * FD_TY;
+// Last-level cache (MI355X Infinity Cache).  A grid whose two levels of E exceed it streams
+// each node's own previous and new level with non-temporal accesses.
+constexpr double LLC_BYTES = 256.0 * 1024 * 1024;
 
 // FEM partition: a block of at most FEM_PB^3 owned nodes plus its halo.
 constexpr int FEM_PB = 8;          // default block edge; DD_FEM_PB="x,y,z" overrides
@@ -80,7 +82,6 @@ struct FdArgs {
   int nx, ny, nz;
   int blo[3], bhi[3];  // FEM box node range [fem_lo, fem_lo + fem_cells] per axis
   int nbx, nby, nbz, ntiles, per_xcd;
-  int zc;              // planes per tile in z (8 or 16)
   float nu2, nu;       // (dt/h)^2, dt/h
   unsigned abs_mask;
   int top_a, top_b;    // top face absorbing at the levels of D+ (a) and D- (b)
@@ -134,14 +135,14 @@ struct FemArgs {
   double inv_dt2, inv_2dt;
 };
 
-void launch_fd(const FdArgs& a, hipStream_t s, bool energy);
+void launch_fd(const FdArgs& a, hipStream_t s, bool energy, bool nt);
 size_t fem_lds_bytes(const FemArgs& a, bool adj);
 void launch_fem_fwd(const FemArgs& a, int n_part, hipStream_t s, bool energy);
 void launch_fem_adj(const FemArgs& a, int n_part, hipStream_t s);
 void launch_fem_stencil_fwd(const FemArgs& a, int n_part, hipStream_t s, bool energy);
 void launch_fem_stencil_adj(const FemArgs& a, int n_part, hipStream_t s);
 // fused FD + FEM (assembled-stencil) step, one launch
-void launch_step(const FdArgs& fa, const FemArgs& ea, hipStream_t s, bool adj, bool energy);
+void launch_step(const FdArgs& fa, const FemArgs& ea, hipStream_t s, bool adj, bool energy, bool nt);
 
 // one item of a batched step launch
 struct BatchItem {
@@ -152,7 +153,7 @@ struct BatchItem {
   int fd_blocks;    // per_xcd * N_XCD, or 0 for a recompute step
   int base;         // first block of this item (multiple of N_XCD)
 };
-void launch_batch(const BatchItem* items_dev, int n_items, int total_blocks, size_t lds, hipStream_t s);
+void launch_batch(const BatchItem* items_dev, int n_items, int total_blocks, size_t lds, hipStream_t s, bool nt);
 size_t stencil_lds(const FemArgs& a);
 void launch_energy_reduce(const double* part, int n, double* out, hipStream_t s);
 void launch_fill_f32(float* p, int64_t n, float v, hipStream_t s);

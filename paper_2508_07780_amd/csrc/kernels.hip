@@ -20,7 +20,7 @@ namespace dd {
 // Finite-difference region.  eps = 1, sigma = 0 here (eq. epsilon_sigma_constraint), so
 // the update is the 7-point wave stencil with mirror (Neumann) weights on the outer box,
 // lumped absorbing damping on absorbing faces and the plane-wave / dipole forcing.
-// Tile = 32 x 8 nodes in (x, y), marching ZC planes in z: the current plane sits in LDS
+// Tile = 32 x 8 nodes in (x, y), marching FD_ZC planes in z: the current plane sits in LDS
 // (with a one-node halo, double-buffered), the z-1 / z+1 values of each column stay in a
 // register queue that is prefetched three planes ahead; the previous level and the halo
 // two ahead.
@@ -32,14 +32,26 @@ namespace dd {
 __device__ __forceinline__ float ld_at(const char* base, uint32_t off) {
   return *reinterpret_cast<const float*>(base + off);
 }
-__device__ __forceinline__ void st_at(char* base, uint32_t off, float v) {
-  *reinterpret_cast<float*>(base + off) = v;
+// The node's own previous level and its new level are each touched once per step.  When
+// the grid's two levels of E do not fit in the last-level cache (NT), these two streams
+// use non-temporal accesses, which keeps the caches for the E planes that neighbouring
+// tiles re-read; when they fit, ordinary accesses let the next step find them there.
+template <bool NT>
+__device__ __forceinline__ float ld_own(const char* base, uint32_t off) {
+  if (NT) return __builtin_nontemporal_load(reinterpret_cast<const float*>(base + off));
+  return *reinterpret_cast<const float*>(base + off);
+}
+template <bool NT>
+__device__ __forceinline__ void st_own(char* base, uint32_t off, float v) {
+  if (NT) __builtin_nontemporal_store(v, reinterpret_cast<float*>(base + off));
+  else *reinterpret_cast<float*>(base + off) = v;
 }
 
 // b: block index within the finite-difference part of the launch; b % N_XCD must equal
 // blockIdx.x % N_XCD so that the remap below keeps consecutive tiles on one XCD.
-template <int ZC, bool ENERGY>
+template <bool ENERGY, bool NT>
 __device__ __forceinline__ void fd_tile(const FdArgs& a, const int b) {
+  constexpr int ZC = FD_ZC;
   // two LDS planes: plane z is written while plane z-1 may still be read by slower waves,
   // so one barrier per plane suffices
   constexpr int SW = FD_TX + 2, SC = (FD_TY + 2) * SW;   // row and component strides
@@ -106,8 +118,8 @@ __device__ __forceinline__ void fd_tile(const FdArgs& a, const int b) {
       const uint32_t o2 = o + 2 * plane4;
       q3[0] = ld_at(X0, o2); q3[1] = ld_at(X1, o2); q3[2] = ld_at(X2, o2);
     }
-    pv[0] = ld_at(P0, o); pv[1] = ld_at(P1, o); pv[2] = ld_at(P2, o);
-    if (z0 + 1 < z1) { pn[0] = ld_at(P0, o + plane4); pn[1] = ld_at(P1, o + plane4); pn[2] = ld_at(P2, o + plane4); }
+    pv[0] = ld_own<NT>(P0, o); pv[1] = ld_own<NT>(P1, o); pv[2] = ld_own<NT>(P2, o);
+    if (z0 + 1 < z1) { pn[0] = ld_own<NT>(P0, o + plane4); pn[1] = ld_own<NT>(P1, o + plane4); pn[2] = ld_own<NT>(P2, o + plane4); }
   }
   if (h_role) {
     const uint32_t o = (uint32_t)z0 * plane4 + hcol4;
@@ -139,7 +151,7 @@ __device__ __forceinline__ void fd_tile(const FdArgs& a, const int b) {
     }
     if (z + 2 < z1) {
       const uint32_t o = zo + 2 * plane4 + col4;
-      pn2[0] = ld_at(P0, o); pn2[1] = ld_at(P1, o); pn2[2] = ld_at(P2, o);
+      pn2[0] = ld_own<NT>(P0, o); pn2[1] = ld_own<NT>(P1, o); pn2[2] = ld_own<NT>(P2, o);
       if (h_role) {
         const uint32_t oh = zo + 2 * plane4 + hcol4;
         hn2[0] = ld_at(X0, oh); hn2[1] = ld_at(X1, oh); hn2[2] = ld_at(X2, oh);
@@ -212,7 +224,7 @@ __device__ __forceinline__ void fd_tile(const FdArgs& a, const int b) {
       }
 #pragma unroll
       for (int c = 0; c < 3; ++c) xn[c] = q1[c] + out[c];
-      st_at(P0, idx4, xn[0]); st_at(P1, idx4, xn[1]); st_at(P2, idx4, xn[2]);
+      st_own<NT>(P0, idx4, xn[0]); st_own<NT>(P1, idx4, xn[1]); st_own<NT>(P2, idx4, xn[2]);
       if (det >= 0 && a.tr_out) {
 #pragma unroll
         for (int c = 0; c < 3; ++c) a.tr_out[det * 3 + c] = xn[c];
@@ -251,9 +263,9 @@ __device__ __forceinline__ void fd_tile(const FdArgs& a, const int b) {
   }
 }
 
-template <int ZC, bool ENERGY>
+template <bool ENERGY, bool NT>
 __global__ __launch_bounds__(FD_THREADS) void fd_step_kernel(FdArgs a) {
-  fd_tile<ZC, ENERGY>(a, blockIdx.x);
+  fd_tile<ENERGY, NT>(a, blockIdx.x);
 }
 
 // ---------------------------------------------------------------------------------------
@@ -712,14 +724,14 @@ __global__ __launch_bounds__(STENCIL_THREADS) void fem_stencil_kernel(FemArgs a)
 // One launch per time step: blocks [0, fem_blocks) advance the FEM partitions (scheduled
 // first: their staging is latency-bound), the remaining blocks the finite-difference
 // tiles.  Both read level n and write level n+1 only, so they need no ordering.
-template <int ZC, bool ADJ, bool ENERGY>
+template <bool ADJ, bool ENERGY, bool NT>
 __global__ __launch_bounds__(FD_THREADS) void step_kernel(FdArgs fa, FemArgs ea, int fem_blocks) {
   const int b = blockIdx.x;
   if (b < fem_blocks) {
     if (b < ea.n_part) fem_stencil_part<ADJ, ENERGY>(ea, b);
     return;
   }
-  fd_tile<ZC, ENERGY>(fa, b - fem_blocks);
+  fd_tile<ENERGY, NT>(fa, b - fem_blocks);
 }
 
 // ---------------------------------------------------------------------------------------
@@ -729,7 +741,7 @@ __global__ __launch_bounds__(FD_THREADS) void step_kernel(FdArgs fa, FemArgs ea,
 // item's tile-to-XCD mapping).  kind: 0 forward step, 1 adjoint step, 2 forward FEM-only
 // recompute step.  Items live in device memory (uniform per block: scalar loads).
 // ---------------------------------------------------------------------------------------
-template <int ZC>
+template <bool NT>
 __global__ __launch_bounds__(FD_THREADS) void batch_step_kernel(const BatchItem* __restrict__ items, int n_items) {
   const int b = blockIdx.x;
   int i = 0;
@@ -745,11 +757,14 @@ __global__ __launch_bounds__(FD_THREADS) void batch_step_kernel(const BatchItem*
     }
     return;
   }
-  if (local - it.fem_blocks < it.fd_blocks) fd_tile<ZC, false>(it.fa, local - it.fem_blocks);
+  if (local - it.fem_blocks < it.fd_blocks) fd_tile<false, NT>(it.fa, local - it.fem_blocks);
 }
 
-void launch_batch(const BatchItem* items_dev, int n_items, int total_blocks, size_t lds, hipStream_t s) {
-  hipLaunchKernelGGL((batch_step_kernel<FD_ZC>), dim3(total_blocks), dim3(FD_THREADS), lds, s, items_dev, n_items);
+void launch_batch(const BatchItem* items_dev, int n_items, int total_blocks, size_t lds, hipStream_t s, bool nt) {
+  if (nt)
+    hipLaunchKernelGGL((batch_step_kernel<true>), dim3(total_blocks), dim3(FD_THREADS), lds, s, items_dev, n_items);
+  else
+    hipLaunchKernelGGL((batch_step_kernel<false>), dim3(total_blocks), dim3(FD_THREADS), lds, s, items_dev, n_items);
 }
 
 size_t stencil_lds(const FemArgs& a) {
@@ -836,20 +851,20 @@ static int grid_for(int64_t n, int block = 256, int cap = 4096) {
   return (int)g;
 }
 
-template <int ZC>
-static void launch_fd_zc(const FdArgs& a, hipStream_t s, bool energy) {
+template <bool NT>
+static void launch_fd_t(const FdArgs& a, hipStream_t s, bool energy) {
   const int grid = a.per_xcd * N_XCD;
   if (energy)
-    hipLaunchKernelGGL((fd_step_kernel<ZC, true>), dim3(grid), dim3(FD_THREADS), 0, s, a);
+    hipLaunchKernelGGL((fd_step_kernel<true, NT>), dim3(grid), dim3(FD_THREADS), 0, s, a);
   else
-    hipLaunchKernelGGL((fd_step_kernel<ZC, false>), dim3(grid), dim3(FD_THREADS), 0, s, a);
+    hipLaunchKernelGGL((fd_step_kernel<false, NT>), dim3(grid), dim3(FD_THREADS), 0, s, a);
 }
 
-void launch_fd(const FdArgs& a, hipStream_t s, bool energy) {
-  switch (a.zc) {
-    case 8: launch_fd_zc<8>(a, s, energy); break;
-    default: launch_fd_zc<16>(a, s, energy); break;
-  }
+void launch_fd(const FdArgs& a, hipStream_t s, bool energy, bool nt) {
+  if (nt)
+    launch_fd_t<true>(a, s, energy);
+  else
+    launch_fd_t<false>(a, s, energy);
 }
 
 size_t fem_lds_bytes(const FemArgs& a, bool adj) {
@@ -900,24 +915,24 @@ void launch_fem_stencil_adj(const FemArgs& a, int n_part, hipStream_t s) {
   hipLaunchKernelGGL((fem_stencil_kernel<true, false>), dim3(n_part), dim3(STENCIL_THREADS), stencil_lds_bytes(a), s, a);
 }
 
-template <int ZC>
-static void launch_step_zc(const FdArgs& fa, const FemArgs& ea, hipStream_t s, bool adj, bool energy) {
+template <bool NT>
+static void launch_step_t(const FdArgs& fa, const FemArgs& ea, hipStream_t s, bool adj, bool energy) {
   const int fem_blocks = (ea.n_part + N_XCD - 1) / N_XCD * N_XCD;   // keeps FD blocks XCD-aligned
   const dim3 grid(fem_blocks + fa.per_xcd * N_XCD);
   const size_t lds = stencil_lds_bytes(ea);
   if (adj)
-    hipLaunchKernelGGL((step_kernel<ZC, true, false>), grid, dim3(FD_THREADS), lds, s, fa, ea, fem_blocks);
+    hipLaunchKernelGGL((step_kernel<true, false, NT>), grid, dim3(FD_THREADS), lds, s, fa, ea, fem_blocks);
   else if (energy)
-    hipLaunchKernelGGL((step_kernel<ZC, false, true>), grid, dim3(FD_THREADS), lds, s, fa, ea, fem_blocks);
+    hipLaunchKernelGGL((step_kernel<false, true, NT>), grid, dim3(FD_THREADS), lds, s, fa, ea, fem_blocks);
   else
-    hipLaunchKernelGGL((step_kernel<ZC, false, false>), grid, dim3(FD_THREADS), lds, s, fa, ea, fem_blocks);
+    hipLaunchKernelGGL((step_kernel<false, false, NT>), grid, dim3(FD_THREADS), lds, s, fa, ea, fem_blocks);
 }
 
-void launch_step(const FdArgs& fa, const FemArgs& ea, hipStream_t s, bool adj, bool energy) {
-  switch (fa.zc) {
-    case 8: launch_step_zc<8>(fa, ea, s, adj, energy); break;
-    default: launch_step_zc<16>(fa, ea, s, adj, energy); break;
-  }
+void launch_step(const FdArgs& fa, const FemArgs& ea, hipStream_t s, bool adj, bool energy, bool nt) {
+  if (nt)
+    launch_step_t<true>(fa, ea, s, adj, energy);
+  else
+    launch_step_t<false>(fa, ea, s, adj, energy);
 }
 
 void launch_energy_reduce(const double* part, int n, double* out, hipStream_t s) {
