@@ -146,7 +146,7 @@ const char* dd_error_string(int code);
 const char* dd_last_error(const dd_problem* p);
 
 /* ---- Batched solves (several problems in one launch per step) ----------------------
- * A batch holds up to max_slots jobs.  A job is the solve of one problem: the forward of
+ * A batch holds up to max_slots (1..64) jobs.  A job is the solve of one problem: the forward of
  * each source with saving, then -- when obs_dev is given -- the adjoint for the misfit
  * cotangent traces - obs (read inside the adjoint kernel; obs_dev has the traces' layout)
  * and the gradient summed over sources, written to g_eps_dev / g_sigma_dev (FEM-node
@@ -158,7 +158,7 @@ const char* dd_last_error(const dd_problem* p);
  * queued by the dd_batch_step call that reported it through dd_batch_poll; afterwards the
  * problem behaves as after dd_forward(save) + dd_adjoint.
  * Requirements: the problem uses the assembled-stencil FEM path (uniform Kuhn box) and the
- * default z-chunk (else DD_ERR_UNSUPPORTED); it has no other active job and is not used
+ * fused step (else DD_ERR_UNSUPPORTED); it has no other active job and is not used
  * outside the batch until its job is done; all buffers stay valid until then.  A batch is
  * driven from one host thread and one stream.  Storage for the saved forward is allocated
  * in dd_batch_submit (see dd_footprint_bytes); dd_batch_step allocates nothing. */

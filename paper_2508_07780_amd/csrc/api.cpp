@@ -922,7 +922,7 @@ struct dd_batch {
 extern "C" {
 
 int dd_batch_create(int32_t max_slots, dd_batch** out) {
-  if (!out || max_slots < 1 || max_slots > 64) return DD_ERR_INVALID_ARG;
+  if (!out || max_slots < 1 || max_slots > BATCH_MAX) return DD_ERR_INVALID_ARG;
   *out = nullptr;
   dd_batch* b = new (std::nothrow) dd_batch();
   if (!b) return DD_ERR_OOM;
@@ -1001,6 +1001,7 @@ int dd_batch_step(dd_batch* b, int32_t max_steps, void* stream) {
       return DD_ERR_HIP;
     }
     BatchItem* h = b->host + (size_t)slot * b->max_slots;
+    BatchBases bases;
     int n = 0, base = 0;
     size_t lds = 0;
     double fd_bytes = 0.0;   // the FD field sets this launch streams through
@@ -1009,8 +1010,6 @@ int dd_batch_step(dd_batch* b, int32_t max_steps, void* stream) {
       if (!job_next(j, st, it)) continue;
       it.fem_blocks = (j.p->n_part + N_XCD - 1) / N_XCD * N_XCD;
       it.fd_blocks = it.kind == 2 ? 0 : j.p->per_xcd * N_XCD;
-      it.base = base;
-      base += it.fem_blocks + it.fd_blocks;
       lds = std::max(lds, stencil_lds(it.ea));
       if (it.fd_blocks) fd_bytes += fd_field_bytes(j.p);
       ++n;
@@ -1022,7 +1021,14 @@ int dd_batch_step(dd_batch* b, int32_t max_steps, void* stream) {
         b->err = "batch upload failed";
         return DD_ERR_HIP;
       }
-      launch_batch(d, n, base, lds, st, fd_bytes > LLC_BYTES);
+      // block ranges: each item's FEM partitions, then its FD tiles
+      bases.n = n;
+      for (int k = 0; k < n; ++k) {
+        bases.base[k] = base;
+        base += h[k].fem_blocks + h[k].fd_blocks;
+      }
+      bases.base[n] = base;
+      launch_batch(d, bases, lds, st, fd_bytes > LLC_BYTES);
       hipError_t e = hipGetLastError();
       if (e != hipSuccess) {
         b->err = std::string("batch launch failed: ") + hipGetErrorString(e);

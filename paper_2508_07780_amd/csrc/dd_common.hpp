@@ -151,9 +151,15 @@ struct BatchItem {
   int kind;         // 0 forward, 1 adjoint, 2 forward FEM-only recompute
   int fem_blocks;   // multiple of N_XCD (extra blocks exit)
   int fd_blocks;    // per_xcd * N_XCD, or 0 for a recompute step
-  int base;         // first block of this item (multiple of N_XCD)
 };
-void launch_batch(const BatchItem* items_dev, int n_items, int total_blocks, size_t lds, hipStream_t s, bool nt);
+// First block of each item of a batched launch (base[n] = total blocks), passed by value
+// so that a block finds its item among the kernel arguments.
+constexpr int BATCH_MAX = 64;
+struct BatchBases {
+  int n;
+  int base[BATCH_MAX + 1];
+};
+void launch_batch(const BatchItem* items_dev, const BatchBases& bases, size_t lds, hipStream_t s, bool nt);
 size_t stencil_lds(const FemArgs& a);
 void launch_energy_reduce(const double* part, int n, double* out, hipStream_t s);
 void launch_fill_f32(float* p, int64_t n, float v, hipStream_t s);
