@@ -218,6 +218,9 @@ def main():
     ap.add_argument("--no-profile", action="store_true", help="skip the HIP-event kernel timing")
     ap.add_argument("--serving", type=int, default=1, help="0 skips the batched / serving comparison")
     ap.add_argument("--probe", type=int, default=1, help="0 skips the 288^3 bandwidth probe")
+    ap.add_argument("--probe-only", action="store_true",
+                    help="run only the 288^3 probe (for profilers) and print its JSON")
+    ap.add_argument("--probe-steps", type=int, default=300, help="time steps of the probe")
     ap.add_argument("--profile-stride", type=int, default=64,
                     help="time every k-th step launch with HIP events (k >= 16 barely perturbs the run)")
     args = ap.parse_args()
@@ -232,6 +235,9 @@ def main():
     from paper_2508_07780_amd import Problem, _lib
 
     torch.cuda.set_device(0)
+    if args.probe_only:
+        print(json.dumps(large_probe(args.probe_steps)), flush=True)
+        return
     w = synth.c2(n_steps=args.n_steps)
     w.desc.ckpt_every = args.ckpt_every if args.ckpt_every > 0 else w.desc.n_steps
     dev = torch.device("cuda", 0)
@@ -323,7 +329,7 @@ def main():
     }
     del prob
     if args.probe:
-        out["hbm_probe"] = large_probe()
+        out["hbm_probe"] = large_probe(args.probe_steps)
     if args.serving:
         out["batched_mix"] = batch_comparison()
         out["serving"] = serving_comparison()
