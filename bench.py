@@ -115,7 +115,7 @@ def batch_comparison():
     t0 = time.perf_counter()
     for p, w, o in zip(probs, mix, obs):
         b.submit(p, w.sources, obs=o)
-    b.run_to_completion(chunk=64)
+    b.run_to_completion()
     torch.cuda.synchronize()
     t_batch = time.perf_counter() - t0
     b.close()
@@ -189,11 +189,11 @@ def serving_comparison():
         r.arrival = 0.0
     serving.serve_serial(burst[:2])                       # warm-up
     s_serial, _ = serving.serve_serial(burst)
-    s_batch, _ = serving.serve_batched(burst, max_slots=16, chunk=32)
+    s_batch, _ = serving.serve_batched(burst, max_slots=16)
     rate = 0.8 * s_serial["jobs"] / s_serial["makespan_s"]
     stream = synth.serving_requests(24, rate, **kw)
     l_serial, _ = serving.serve_serial(stream)
-    l_batch, _ = serving.serve_batched(stream, max_slots=16, chunk=32)
+    l_batch, _ = serving.serve_batched(stream, max_slots=16)
     keep = ("jobs", "solves", "makespan_s", "throughput_gcell_steps_s", "latency_p50_s", "latency_p99_s")
     pick = lambda d: {k: (round(d[k], 4) if isinstance(d[k], float) else d[k]) for k in keep}  # noqa: E731
     return {

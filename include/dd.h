@@ -154,7 +154,9 @@ const char* dd_last_error(const dd_problem* p);
  * to max_steps time steps: each iteration is one kernel launch in which every active job
  * contributes its next step (forward, adjoint or checkpoint recompute), so jobs of uneven
  * grid sizes, step counts and source counts share the GPU and new jobs can join while
- * others run.  A finished job's results are complete once `stream` reaches the work
+ * others run.  dd_batch_step returns early, after the launch in which a job completed, so
+ * that a caller can collect results and admit new jobs without waiting for the remaining
+ * steps it asked for.  A finished job's results are complete once `stream` reaches the work
  * queued by the dd_batch_step call that reported it through dd_batch_poll; afterwards the
  * problem behaves as after dd_forward(save) + dd_adjoint.
  * Requirements: the problem uses the assembled-stencil FEM path (uniform Kuhn box) and the

@@ -67,7 +67,7 @@ class Batch:
             if n.value < 64:
                 return done, act.value
 
-    def run_to_completion(self, chunk=64):
+    def run_to_completion(self, chunk=1024):
         out = []
         while True:
             self.step(chunk)

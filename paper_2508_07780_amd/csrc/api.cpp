@@ -905,6 +905,14 @@ bool job_next(BatchJob& j, hipStream_t st, BatchItem& it) {
   return true;
 }
 
+// True when the job's next job_next call queues prologue work (a source's forward or
+// adjoint start, or an adjoint segment start) ahead of its step.
+bool job_needs_prologue(const BatchJob& j) {
+  if (j.phase == 0) return !j.started;
+  if (j.phase == 1) return !j.started || !j.seg_started;
+  return false;
+}
+
 }  // namespace
 
 struct dd_batch {
@@ -914,8 +922,12 @@ struct dd_batch {
   int next_id = 1;
   BatchItem* host = nullptr;    // pinned [ring][max_slots]
   BatchItem* dev = nullptr;     // device [ring][max_slots]
-  std::vector<hipEvent_t> ev;   // per ring slot: its upload has been consumed
+  std::vector<hipEvent_t> ev;   // per ring segment: its upload has been consumed
+  // The ring holds the items of `ring` launches in segments of `seg` launches; the items of
+  // the launches of one segment are uploaded with one copy.
+  static constexpr int seg = 16;
   int ring = 64, pos = 0;
+  bool return_on_done = true;   // dd_batch_step returns after the launch in which a job finishes
   std::string err;
 };
 
@@ -937,7 +949,7 @@ int dd_batch_create(int32_t max_slots, dd_batch** out) {
     delete b;
     return DD_ERR_OOM;
   }
-  b->ev.resize(b->ring, nullptr);
+  b->ev.resize(b->ring / b->seg, nullptr);
   for (auto& e : b->ev)
     if (hipEventCreateWithFlags(&e, hipEventDisableTiming) != hipSuccess) {
       dd_batch_destroy(b);
@@ -993,66 +1005,91 @@ int dd_batch_submit(dd_batch* b, dd_problem* p, const dd_source* src, int32_t n_
 int dd_batch_step(dd_batch* b, int32_t max_steps, void* stream) {
   if (!b || max_steps < 0) return DD_ERR_INVALID_ARG;
   hipStream_t st = (hipStream_t)stream;
-  for (int iter = 0; iter < max_steps && !b->jobs.empty(); ++iter) {
-    const int slot = b->pos;
-    b->pos = (b->pos + 1) % b->ring;
-    if (hipEventSynchronize(b->ev[slot]) != hipSuccess) {
+  const size_t done0 = b->done.size();
+  int iter = 0;
+  while (iter < max_steps && !b->jobs.empty()) {
+    // Fill one ring segment with the items of up to `seg` launches, upload them with one
+    // copy and launch them.  The segment ends early before a job's prologue work (which
+    // must follow the launches before it in stream order) and after a launch in which a
+    // job takes its last step.
+    const int g = b->pos / b->seg;
+    if (hipEventSynchronize(b->ev[g]) != hipSuccess) {
       b->err = "event synchronize failed";
       return DD_ERR_HIP;
     }
-    BatchItem* h = b->host + (size_t)slot * b->max_slots;
-    BatchBases bases;
-    int n = 0, base = 0;
-    size_t lds = 0;
-    double fd_bytes = 0.0;   // the FD field sets this launch streams through
-    for (auto& j : b->jobs) {
-      BatchItem& it = h[n];
-      if (!job_next(j, st, it)) continue;
-      it.fem_blocks = (j.p->n_part + N_XCD - 1) / N_XCD * N_XCD;
-      it.fd_blocks = it.kind == 2 ? 0 : j.p->per_xcd * N_XCD;
-      lds = std::max(lds, stencil_lds(it.ea));
-      if (it.fd_blocks) fd_bytes += fd_field_bytes(j.p);
-      ++n;
+    BatchBases bases[dd_batch::seg];
+    size_t lds[dd_batch::seg];
+    bool nt[dd_batch::seg];
+    int m = 0;
+    bool finished = false;
+    while (m < b->seg && iter < max_steps && !b->jobs.empty()) {
+      if (m > 0 && std::any_of(b->jobs.begin(), b->jobs.end(), job_needs_prologue)) break;
+      BatchItem* h = b->host + (size_t)(b->pos + m) * b->max_slots;
+      int n = 0, base = 0;
+      size_t l = 0;
+      double fd_bytes = 0.0;   // the FD field sets this launch streams through
+      for (auto& j : b->jobs) {
+        BatchItem& it = h[n];
+        if (!job_next(j, st, it)) continue;
+        it.fem_blocks = (j.p->n_part + N_XCD - 1) / N_XCD * N_XCD;
+        it.fd_blocks = it.kind == 2 ? 0 : j.p->per_xcd * N_XCD;
+        l = std::max(l, stencil_lds(it.ea));
+        if (it.fd_blocks) fd_bytes += fd_field_bytes(j.p);
+        bases[m].base[n] = base;   // each item's FEM partitions, then its FD tiles
+        base += it.fem_blocks + it.fd_blocks;
+        ++n;
+      }
+      bases[m].n = n;
+      bases[m].base[n] = base;
+      lds[m] = l;
+      nt[m] = fd_bytes > LLC_BYTES;
+      ++m;
+      ++iter;
+      if (std::any_of(b->jobs.begin(), b->jobs.end(), [](const BatchJob& j) { return j.phase == 2; })) {
+        finished = true;
+        break;
+      }
     }
-    if (n) {
-      BatchItem* d = b->dev + (size_t)slot * b->max_slots;
-      if (hipMemcpyAsync(d, h, sizeof(BatchItem) * n, hipMemcpyHostToDevice, st) != hipSuccess ||
-          hipEventRecord(b->ev[slot], st) != hipSuccess) {
+    if (m) {
+      const size_t off = (size_t)b->pos * b->max_slots;
+      if (hipMemcpyAsync(b->dev + off, b->host + off, sizeof(BatchItem) * b->max_slots * m, hipMemcpyHostToDevice,
+                         st) != hipSuccess ||
+          hipEventRecord(b->ev[g], st) != hipSuccess) {
         b->err = "batch upload failed";
         return DD_ERR_HIP;
       }
-      // block ranges: each item's FEM partitions, then its FD tiles
-      bases.n = n;
-      for (int k = 0; k < n; ++k) {
-        bases.base[k] = base;
-        base += h[k].fem_blocks + h[k].fd_blocks;
-      }
-      bases.base[n] = base;
-      launch_batch(d, bases, lds, st, fd_bytes > LLC_BYTES);
+      for (int k = 0; k < m; ++k)
+        if (bases[k].n) launch_batch(b->dev + off + (size_t)k * b->max_slots, bases[k], lds[k], st, nt[k]);
       hipError_t e = hipGetLastError();
       if (e != hipSuccess) {
         b->err = std::string("batch launch failed: ") + hipGetErrorString(e);
         return DD_ERR_HIP;
       }
     }
-    for (auto it = b->jobs.begin(); it != b->jobs.end();) {
-      if (it->phase == 2) {
-        dd_problem* p = it->p;
-        p->saved = true;
-        p->saved_n_src = (int)it->src.size();
-        if (it->obs) {
-          p->have_grad = true;
-          if (it->g_eps && it->g_sig) {
-            launch_fill_f64(it->g_eps, p->n_fem, 0.0, st);
-            launch_fill_f64(it->g_sig, p->n_fem, 0.0, st);
-            launch_gradient_out(p->g_eps, p->g_sig, p->own_api, p->own_grid, p->n_own, it->g_eps, it->g_sig, st);
+    b->pos = ((g + 1) * b->seg) % b->ring;
+    if (finished) {
+      for (auto it = b->jobs.begin(); it != b->jobs.end();) {
+        if (it->phase == 2) {
+          dd_problem* p = it->p;
+          p->saved = true;
+          p->saved_n_src = (int)it->src.size();
+          if (it->obs) {
+            p->have_grad = true;
+            if (it->g_eps && it->g_sig) {
+              launch_fill_f64(it->g_eps, p->n_fem, 0.0, st);
+              launch_fill_f64(it->g_sig, p->n_fem, 0.0, st);
+              launch_gradient_out(p->g_eps, p->g_sig, p->own_api, p->own_grid, p->n_own, it->g_eps, it->g_sig, st);
+            }
           }
+          b->done.push_back(it->id);
+          it = b->jobs.erase(it);
+        } else {
+          ++it;
         }
-        b->done.push_back(it->id);
-        it = b->jobs.erase(it);
-      } else {
-        ++it;
       }
+      // a job finished: return so that the caller can collect it (and admit new work)
+      // without waiting for the rest of the requested steps
+      if (b->return_on_done && b->done.size() > done0) break;
     }
   }
   return DD_OK;

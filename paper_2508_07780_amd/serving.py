@@ -82,7 +82,7 @@ def _summary(lat, solves, makespan, work):
             "latency_p50_s": pct(50), "latency_p99_s": pct(99), "latency_mean_s": float(np.mean(lat)) if lat else None}
 
 
-def serve_batched(requests, max_slots=16, hbm_budget=None, chunk=32, time_fn=time.perf_counter):
+def serve_batched(requests, max_slots=16, hbm_budget=None, chunk=256, time_fn=time.perf_counter):
     """Continuous batching: returns a summary dict and per-job records."""
     dev = torch.device("cuda", torch.cuda.current_device())
     if hbm_budget is None:
