@@ -157,6 +157,21 @@ __device__ __forceinline__ void fd_tile(const FdArgs& a, const int b) {
         hn2[0] = ld_at(X0, oh); hn2[1] = ld_at(X1, oh); hn2[2] = ld_at(X2, oh);
       }
     }
+    // Adjoint: when the top face is the last plane of a full chunk, its trace cotangent is
+    // loaded here, before the barrier, rather than after the stencil where its latency
+    // would add to the march.  In this last unrolled iteration nothing is prefetched for
+    // later planes, so these registers come free.
+    float cr[3] = {0.f, 0.f, 0.f};
+    const bool top_pref = k == ZC - 1 && a.cot_in && (a.det_mask & DD_FACE_TOP) && z == nz - 1;
+    if (top_pref) {
+      const uint32_t o3 = 12u * (uint32_t)face_lex_index(0, 0, nz - 1, nx, ny, nz, a.det_mask) + 3u * col4;
+      const char* cot = reinterpret_cast<const char*>(a.cot_in);
+      cr[0] = ld_at(cot, o3); cr[1] = ld_at(cot, o3 + 4); cr[2] = ld_at(cot, o3 + 8);
+      if (a.obs_in) {
+        const char* obs = reinterpret_cast<const char*>(a.obs_in);
+        cr[0] -= ld_at(obs, o3); cr[1] -= ld_at(obs, o3 + 4); cr[2] -= ld_at(obs, o3 + 8);
+      }
+    }
     __syncthreads();
     const bool fem_owned = in_box_xy && z > a.blo[2] && z < a.bhi[2];
     if (col_ok && !fem_owned) {
@@ -198,7 +213,8 @@ __device__ __forceinline__ void fd_tile(const FdArgs& a, const int b) {
           // r = dJ/dT: the cotangent itself, or T - E_obs when the observations are given
 #pragma unroll
           for (int c = 0; c < 3; ++c) {
-            const float r = a.obs_in ? a.cot_in[det * 3 + c] - a.obs_in[det * 3 + c] : a.cot_in[det * 3 + c];
+            const float r = (top_pref && bzh) ? cr[c]
+                          : a.obs_in ? a.cot_in[det * 3 + c] - a.obs_in[det * 3 + c] : a.cot_in[det * 3 + c];
             src[c] -= r * sc2;
           }
         }
