@@ -78,7 +78,7 @@ enum {
 typedef struct dd_problem dd_problem;
 
 typedef struct {
-  int32_t n_outer[3];       /* outer grid nodes per axis, each >= 4 */
+  int32_t n_outer[3];       /* outer grid nodes per axis, each >= 4; product < 2^30 */
   double h;                 /* grid spacing > 0 */
   double origin[3];         /* coordinates of grid node (0,0,0) */
   int32_t fem_lo[3];        /* grid index of the FEM box's lower corner; >= 1 */

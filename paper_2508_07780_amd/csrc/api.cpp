@@ -141,7 +141,8 @@ std::string check_desc(const dd_problem_desc* d) {
       return "the FEM box must lie strictly inside the outer grid";
   }
   const double n = (double)d->n_outer[0] * d->n_outer[1] * d->n_outer[2];
-  if (n > 2147483647.0) return "outer grid exceeds 2^31 nodes";
+  // the FD kernels address one field component with 32-bit byte offsets
+  if (n >= 1073741824.0) return "outer grid must have fewer than 2^30 nodes";
   if (!(d->h > 0.0) || !std::isfinite(d->h)) return "h must be positive";
   if (!(d->dt > 0.0) || !std::isfinite(d->dt)) return "dt must be positive";
   if (d->dt * std::sqrt(3.0) > d->h * (1.0 + 1e-12)) return "dt exceeds the explicit stability bound h/sqrt(3)";

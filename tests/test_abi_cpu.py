@@ -79,6 +79,7 @@ def test_invalid_descriptors_rejected(lib):
         lambda d: setattr(d, "detector_faces", 0),
         lambda d: setattr(d, "n_steps", 0),
         lambda d: setattr(d, "fem_cells", (8, 4, 5)),   # box leaves the grid
+        lambda d: setattr(d, "n_outer", (1024, 1024, 1024)),   # 2^30 nodes: beyond 32-bit byte offsets
     ):
         w = synth.small("tiny")
         mutate(w.desc)
