@@ -732,9 +732,17 @@ __device__ __forceinline__ void fem_stencil_part(const FemArgs& a, const int p) 
   }
 }
 
+// Partition of FEM block b of a range of `blocks` (a multiple of N_XCD) blocks: blocks are
+// dealt to the XCDs round-robin, so consecutive partitions, whose staging boxes overlap,
+// are given to one XCD and share its L2.
+__device__ __forceinline__ int fem_part_of_block(int b, int blocks) {
+  return (b % N_XCD) * (blocks / N_XCD) + b / N_XCD;
+}
+
 template <bool ADJ, bool ENERGY>
 __global__ __launch_bounds__(STENCIL_THREADS) void fem_stencil_kernel(FemArgs a) {
-  fem_stencil_part<ADJ, ENERGY>(a, blockIdx.x);
+  const int p = fem_part_of_block(blockIdx.x, gridDim.x);
+  if (p < a.n_part) fem_stencil_part<ADJ, ENERGY>(a, p);
 }
 
 // One launch per time step: blocks [0, fem_blocks) advance the FEM partitions (scheduled
@@ -744,7 +752,8 @@ template <bool ADJ, bool ENERGY, bool NT>
 __global__ __launch_bounds__(FD_THREADS) void step_kernel(FdArgs fa, FemArgs ea, int fem_blocks) {
   const int b = blockIdx.x;
   if (b < fem_blocks) {
-    if (b < ea.n_part) fem_stencil_part<ADJ, ENERGY>(ea, b);
+    const int p = fem_part_of_block(b, fem_blocks);
+    if (p < ea.n_part) fem_stencil_part<ADJ, ENERGY>(ea, p);
     return;
   }
   fd_tile<ENERGY, NT>(fa, b - fem_blocks);
@@ -773,11 +782,12 @@ __global__ __launch_bounds__(FD_THREADS, 6) void batch_step_kernel(const BatchIt
   const BatchItem& it = items[lo];
   const int local = b - bb.base[lo];
   if (local < it.fem_blocks) {
-    if (local < it.ea.n_part) {
+    const int p = fem_part_of_block(local, it.fem_blocks);
+    if (p < it.ea.n_part) {
       if (it.kind == 1)
-        fem_stencil_part<true, false>(it.ea, local);
+        fem_stencil_part<true, false>(it.ea, p);
       else
-        fem_stencil_part<false, false>(it.ea, local);
+        fem_stencil_part<false, false>(it.ea, p);
     }
     return;
   }
@@ -924,6 +934,8 @@ void launch_fem_fwd(const FemArgs& a, int n_part, hipStream_t s, bool energy) {
 
 void launch_fem_adj(const FemArgs& a, int n_part, hipStream_t s) { launch_fem_t<true, false>(a, n_part, s); }
 
+static int xcd_round(int n) { return (n + N_XCD - 1) / N_XCD * N_XCD; }
+
 static size_t stencil_lds_bytes(const FemArgs& a) {
   return (size_t)a.lds_box * 16 + 12 * 4 * STENCIL_SLOTS_MAX + 4 * STENCIL_SLOTS_MAX;
 }
@@ -931,13 +943,13 @@ static size_t stencil_lds_bytes(const FemArgs& a) {
 void launch_fem_stencil_fwd(const FemArgs& a, int n_part, hipStream_t s, bool energy) {
   const size_t lds = stencil_lds_bytes(a);
   if (energy)
-    hipLaunchKernelGGL((fem_stencil_kernel<false, true>), dim3(n_part), dim3(STENCIL_THREADS), lds, s, a);
+    hipLaunchKernelGGL((fem_stencil_kernel<false, true>), dim3(xcd_round(n_part)), dim3(STENCIL_THREADS), lds, s, a);
   else
-    hipLaunchKernelGGL((fem_stencil_kernel<false, false>), dim3(n_part), dim3(STENCIL_THREADS), lds, s, a);
+    hipLaunchKernelGGL((fem_stencil_kernel<false, false>), dim3(xcd_round(n_part)), dim3(STENCIL_THREADS), lds, s, a);
 }
 
 void launch_fem_stencil_adj(const FemArgs& a, int n_part, hipStream_t s) {
-  hipLaunchKernelGGL((fem_stencil_kernel<true, false>), dim3(n_part), dim3(STENCIL_THREADS), stencil_lds_bytes(a), s, a);
+  hipLaunchKernelGGL((fem_stencil_kernel<true, false>), dim3(xcd_round(n_part)), dim3(STENCIL_THREADS), stencil_lds_bytes(a), s, a);
 }
 
 template <bool NT>
