@@ -393,9 +393,9 @@ __global__ __launch_bounds__(FEM_THREADS) void fem_step_kernel(FemArgs a) {
       if (ADJ) {
 #pragma unroll
         for (int c = 0; c < 3; ++c) {
-          pwE[j][c] = a.wE[c * n_own + id];
-          pwV[j][c] = a.wV[c * n_own + id];
-          pwVm[j][c] = a.wVm[c * n_own + id];
+          pwE[j][c] = __builtin_nontemporal_load(a.wE + c * n_own + id);
+          pwV[j][c] = __builtin_nontemporal_load(a.wV + c * n_own + id);
+          pwVm[j][c] = __builtin_nontemporal_load(a.wVm + c * n_own + id);
         }
       }
     }
@@ -511,11 +511,13 @@ __global__ __launch_bounds__(FEM_THREADS) void fem_step_kernel(FemArgs a) {
         for (int c = 0; c < 3; ++c) a.fd_out[c * a.N + gi] = xn[c];
       }
     }
+    // the saved forward state is read back only by the adjoint, much later: streamed past
+    // the caches (non-temporal), as are the adjoint's reads of it
     if (!ADJ && a.ck_X) {
 #pragma unroll
       for (int c = 0; c < 3; ++c) {
-        a.ck_X[c * n_own + id] = xn[c];
-        a.ck_I[c * n_own + id] = inc[c];
+        __builtin_nontemporal_store(xn[c], a.ck_X + c * n_own + id);
+        __builtin_nontemporal_store(inc[c], a.ck_I + c * n_own + id);
       }
     }
     if (ENERGY) {
@@ -688,11 +690,13 @@ __device__ __forceinline__ void fem_stencil_part(const FemArgs& a, const int p) 
         for (int c = 0; c < 3; ++c) a.fd_out[c * a.N + gi] = xn[c];
       }
     }
+    // the saved forward state is read back only by the adjoint, much later: streamed past
+    // the caches (non-temporal), as are the adjoint's reads of it
     if (!ADJ && a.ck_X) {
 #pragma unroll
       for (int c = 0; c < 3; ++c) {
-        a.ck_X[c * n_own + id] = xn[c];
-        a.ck_I[c * n_own + id] = inc[c];
+        __builtin_nontemporal_store(xn[c], a.ck_X + c * n_own + id);
+        __builtin_nontemporal_store(inc[c], a.ck_I + c * n_own + id);
       }
     }
     if (ENERGY) {
@@ -710,10 +714,10 @@ __device__ __forceinline__ void fem_stencil_part(const FemArgs& a, const int p) 
       double ge = 0.0, gm = 0.0, gs = 0.0;
 #pragma unroll
       for (int c = 0; c < 3; ++c) {
-        const double wv = (double)a.wV[c * n_own + id];
-        ge += (double)q[c] * (double)a.wE[c * n_own + id];
+        const double wv = (double)__builtin_nontemporal_load(a.wV + c * n_own + id);
+        ge += (double)q[c] * (double)__builtin_nontemporal_load(a.wE + c * n_own + id);
         gm += (double)inc[c] * wv;
-        gs += (double)xn[c] * (wv + (double)a.wVm[c * n_own + id]);
+        gs += (double)xn[c] * (wv + (double)__builtin_nontemporal_load(a.wVm + c * n_own + id));
       }
       // one contribution per node and launch: the device-side FP64 add (no value returned,
       // so nothing waits for it) rounds once, exactly like a load-add-store
