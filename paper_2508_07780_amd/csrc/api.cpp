@@ -1,9 +1,10 @@
 // C-ABI of the hybrid FE/FD solver: problem setup, forward / adjoint / gradient drivers.
 //
-// Time loops run on the host and queue one finite-difference launch and one FEM
-// launch per step on the caller's stream.  Within a step both kernels read only
-// level-n buffers and write only level-(n+1) buffers (ping-pong for the fields,
-// in-place increments), so their order inside a step does not matter.
+// Time loops run on the host and queue one launch per step on the caller's stream: the
+// fused step kernel (FEM partitions and FD tiles together), or one FD and one FEM launch.
+// Within a step the FD tiles read level n and write level n+1 over level n-1 node by node
+// (each node's own lane only), the FEM reads level n and writes level n+1 (ping-pong, with
+// the increment updated in place), so neither depends on the other's writes of the step.
 #include <algorithm>
 #include <cmath>
 #include <cstdio>
