@@ -12,9 +12,9 @@ Prints one JSON line with the throughput in Gcell-steps/s, where a cell is an
 outer-grid node or a FEM-owned node and forward and adjoint steps both count,
 the roofline of the dominant kernel (the fused FD + FEM forward step, HIP-event timed
 over the timed region on the solver's stream), per-solve latency p50/p99, the same
-kernels on a 288^3 probe whose fields exceed the last-level cache, the batched and
-serving comparisons, and the FP64 oracle timed on the host on a bounded sample of the
-same workload.
+kernels on a 288^3 probe whose fields exceed the last-level cache, the 192^3
+autograd workload with checkpointed recompute, the batched and serving comparisons, and
+the FP64 oracle timed on the host on a bounded sample of the same workload.
 """
 
 import argparse
@@ -173,6 +173,50 @@ def large_probe(n_steps=300, stride=16):
     return out
 
 
+def c3_autograd(reps=2):
+    """Differentiation workload: 192^3 outer nodes, 96^3 FEM hexes, 1500 steps, forward
+    checkpoints every 64 steps; one torch.autograd forward (traces) + backward (hand adjoint
+    with segment recompute) of the loss 1/2 sum |E - E_obs|^2.  Recompute steps are not
+    counted as cell-steps."""
+    import numpy as np
+    import torch
+    import synth
+    from paper_2508_07780_amd import Problem
+    from paper_2508_07780_amd.autograd import solve
+    w = synth.c3()
+    dev = torch.device("cuda", 0)
+    t_setup = time.perf_counter()
+    p = Problem(w.desc)
+    p.set_coefficients(torch.tensor(w.eps_true, dtype=torch.float32, device=dev),
+                       torch.tensor(w.sigma_true, dtype=torch.float32, device=dev))
+    eobs = p.forward(w.sources, save=False).clone()
+    t_setup = time.perf_counter() - t_setup
+    eps = torch.ones(p.n_fem, dtype=torch.float32, device=dev, requires_grad=True)
+    sig = torch.zeros(p.n_fem, dtype=torch.float32, device=dev, requires_grad=True)
+
+    def step():
+        eps.grad = sig.grad = None
+        r = (solve(p, eps, sig, w.sources) - eobs).double()
+        loss = 0.5 * torch.sum(r * r)
+        loss.backward()
+        return loss
+
+    step()
+    torch.cuda.synchronize()
+    t0 = time.perf_counter()
+    for _ in range(reps):
+        step()
+    torch.cuda.synchronize()
+    dt = (time.perf_counter() - t0) / reps
+    cells = w.desc.n_grid() + w.desc.n_fem_owned()
+    finite = bool(torch.isfinite(eps.grad).all() and torch.isfinite(sig.grad).all())
+    p.close()
+    return {"workload": f"outer {w.desc.n_outer[0]}^3, FEM {w.desc.fem_cells[0]}^3 hexes, {w.desc.n_steps} steps, "
+                        f"K = {w.desc.ckpt_every}, torch.autograd forward + backward",
+            "ms": round(dt * 1e3, 2), "gcell_steps_s": round(cells * 2 * w.desc.n_steps / dt / 1e9, 3),
+            "gradient_finite": finite, "setup_s": round(t_setup, 2)}
+
+
 def serving_comparison():
     """Continuous batching vs one solve at a time on the same uneven request stream.
 
@@ -221,6 +265,7 @@ def main():
     ap.add_argument("--probe-only", action="store_true",
                     help="run only the 288^3 probe (for profilers) and print its JSON")
     ap.add_argument("--probe-steps", type=int, default=300, help="time steps of the probe")
+    ap.add_argument("--c3", type=int, default=1, help="0 skips the 192^3 autograd measurement")
     ap.add_argument("--profile-stride", type=int, default=64,
                     help="time every k-th step launch with HIP events (k >= 16 barely perturbs the run)")
     args = ap.parse_args()
@@ -330,6 +375,8 @@ def main():
     del prob
     if args.probe:
         out["hbm_probe"] = large_probe(args.probe_steps)
+    if args.c3:
+        out["c3_autograd"] = c3_autograd()
     if args.serving:
         out["batched_mix"] = batch_comparison()
         out["serving"] = serving_comparison()
