@@ -98,6 +98,8 @@ struct FdArgs {
   int fs[3];           // FEM lattice shape (fem_cells + 1)
   double* epart;       // energy partial per tile or null
   double e_coef;       // h^3 / (2 dt^2)
+  int rev;             // 1: each XCD takes its tiles in reverse order (alternate steps of
+                       // grids larger than the last-level cache)
 };
 
 constexpr int STENCIL_SLOTS_MAX = 27;
@@ -129,6 +131,7 @@ struct FemArgs {
   const int* part_dims; const int* box_codes; const int* slot_off; const float* slot_k; const float* slot_b;
   int n_slots, lds_box;
   int n_part;
+  int rev;             // 1: each XCD takes its partitions in reverse order (alternate steps)
   // adjoint
   const float* wE; const float* wV; const float* wVm;  // forward E^k, V^k, V^{k-1} [3][n_own]
   double* g_eps; double* g_sig;

@@ -57,7 +57,10 @@ __device__ __forceinline__ void fd_tile(const FdArgs& a, const int b) {
   constexpr int SW = FD_TX + 2, SC = (FD_TY + 2) * SW;   // row and component strides
   __shared__ float s[2][3 * SC];
   __shared__ double red[ENERGY ? FD_THREADS : 1];
-  const int t = (b % N_XCD) * a.per_xcd + b / N_XCD;  // consecutive tiles share an XCD's L2
+  // consecutive tiles share an XCD's L2; on alternate steps each XCD sweeps its tiles in
+  // reverse, starting where the previous step ended, whose fields are still in the caches
+  const int kx = a.rev ? a.per_xcd - 1 - b / N_XCD : b / N_XCD;
+  const int t = (b % N_XCD) * a.per_xcd + kx;
   if (t >= a.ntiles) return;
   const int nx = a.nx, ny = a.ny, nz = a.nz;
   const int bx = t % a.nbx;
@@ -738,14 +741,15 @@ __device__ __forceinline__ void fem_stencil_part(const FemArgs& a, const int p) 
 
 // Partition of FEM block b of a range of `blocks` (a multiple of N_XCD) blocks: blocks are
 // dealt to the XCDs round-robin, so consecutive partitions, whose staging boxes overlap,
-// are given to one XCD and share its L2.
-__device__ __forceinline__ int fem_part_of_block(int b, int blocks) {
-  return (b % N_XCD) * (blocks / N_XCD) + b / N_XCD;
+// are given to one XCD and share its L2 (in reverse order on alternate steps).
+__device__ __forceinline__ int fem_part_of_block(int b, int blocks, int rev) {
+  const int per = blocks / N_XCD;
+  return (b % N_XCD) * per + (rev ? per - 1 - b / N_XCD : b / N_XCD);
 }
 
 template <bool ADJ, bool ENERGY>
 __global__ __launch_bounds__(STENCIL_THREADS) void fem_stencil_kernel(FemArgs a) {
-  const int p = fem_part_of_block(blockIdx.x, gridDim.x);
+  const int p = fem_part_of_block(blockIdx.x, gridDim.x, a.rev);
   if (p < a.n_part) fem_stencil_part<ADJ, ENERGY>(a, p);
 }
 
@@ -756,7 +760,7 @@ template <bool ADJ, bool ENERGY, bool NT>
 __global__ __launch_bounds__(FD_THREADS) void step_kernel(FdArgs fa, FemArgs ea, int fem_blocks) {
   const int b = blockIdx.x;
   if (b < fem_blocks) {
-    const int p = fem_part_of_block(b, fem_blocks);
+    const int p = fem_part_of_block(b, fem_blocks, ea.rev);
     if (p < ea.n_part) fem_stencil_part<ADJ, ENERGY>(ea, p);
     return;
   }
@@ -786,7 +790,7 @@ __global__ __launch_bounds__(FD_THREADS, 6) void batch_step_kernel(const BatchIt
   const BatchItem& it = items[lo];
   const int local = b - bb.base[lo];
   if (local < it.fem_blocks) {
-    const int p = fem_part_of_block(local, it.fem_blocks);
+    const int p = fem_part_of_block(local, it.fem_blocks, it.ea.rev);
     if (p < it.ea.n_part) {
       if (it.kind == 1)
         fem_stencil_part<true, false>(it.ea, p);
