@@ -22,6 +22,10 @@ What it computes (the discrete scheme the GPU path must reproduce):
 * Gradient (eq. gradeps and the optimality conditions dL/deps, dL/dsigma):
   the exact derivative of the discrete loss 1/2 sum |E - E_obs|^2 over
   detectors and steps with respect to nodal eps and sigma.
+* Reconstruction (box "CGA", oracle/cga.py): the conjugate gradient iteration on
+  eps and sigma with the Tikhonov terms of eq. tikhonov_functional, the step-size
+  and regularisation rules of the box and the coefficient box of
+  eq. epsilon_sigma_constraint.
 
 Parity pins live in ``tests/test_oracle_*.py``.  Parity unpinned: whether this
 discretisation is the one of the paper's companion reference (the paper defers

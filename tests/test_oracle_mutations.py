@@ -76,3 +76,67 @@ def test_dropped_divdiv_gradient_term_is_caught():
     fd = (jp - jm) / (2 * delta)
     assert abs(ag["g_eps"][i] - fd) <= 1e-4 * abs(fd)
     assert abs(ag["g_mass"][i] - fd) > 1e-2 * abs(fd)      # mass term alone is wrong
+
+
+def _cga_scalar_run(gamma0=1.0, n_iter=3):
+    from oracle.cga import cga_loop
+    w = np.array([1.0])
+    prm = dict(gamma_eps=gamma0, gamma_sig=1.0, p=0.5, alpha_eps=0.25, alpha_sig=0.25, eps_max=10.0, sig_max=5.0)
+    grad = lambda e, s: (w * (e - 3.0), np.zeros_like(s), 0.0)  # noqa: E731
+    return [h["eps"]["coef"][0] for h in cga_loop(grad, np.array([1.0]), np.array([0.0]), w, np.array([True]), prm, n_iter)]
+
+
+# hand-derived iterates of the scalar quadratic (tests/test_oracle_cga.py): gamma^0 = 1 and 2
+CGA_CLOSED_FORMS = {1.0: [1.5, 3.0, 5.0 - 2.0 * math.sqrt(2.0) / 3.0], 2.0: [1.5, 29.0 / 16.0]}
+
+
+def _cga_pins_hold():
+    return all(np.allclose(_cga_scalar_run(g0, len(x)), x, rtol=1e-12, atol=0) for g0, x in CGA_CLOSED_FORMS.items())
+
+
+def test_cga_mutations_are_caught_by_the_closed_form(monkeypatch):
+    from oracle import cga as ocga
+    assert _cga_pins_hold()
+    alpha = ocga.next_alpha
+    mutations = {
+        "beta without the squares": ("fletcher_reeves_beta",
+                                     lambda gn2, prev, m: math.sqrt(gn2 / prev) if m > 0 and prev > 0 else 0.0),
+        "inverted beta": ("fletcher_reeves_beta", lambda gn2, prev, m: prev / gn2 if m > 0 and gn2 > 0 else 0.0),
+        "direction sign": ("direction", lambda g, beta, d: g + beta * d),
+        "alpha sign": ("next_alpha", lambda w, g, d, gamma, a: -alpha(w, g, d, gamma, a)),
+        "alpha without gamma": ("next_alpha", lambda w, g, d, gamma, a: gamma * alpha(w, g, d, gamma, a)),
+        "gamma index": ("next_gamma", lambda g0, m, p: g0 / float(m + 2) ** p),
+        "gamma not decayed": ("next_gamma", lambda g0, m, p: g0),
+    }
+    for name, (fn, bad) in mutations.items():
+        with monkeypatch.context() as mp:
+            mp.setattr(ocga, fn, bad)
+            assert not _cga_pins_hold(), name
+
+
+def test_cga_unscaled_gradient_is_caught(monkeypatch):
+    from oracle import cga as ocga
+    from tests.test_oracle_cga import test_weighted_vector_quadratic_reduces_to_scalar as pin
+    pin()
+    orig = ocga.gradient_function
+    monkeypatch.setattr(ocga, "gradient_function",
+                        lambda dJ, w, c, c0, gamma, free: orig(dJ * w, w, c, c0, gamma, free))
+    try:
+        pin()
+    except AssertionError:
+        return
+    raise AssertionError("an unscaled nodal derivative passed the weighted-quadratic pin")
+
+
+def test_cga_termination_grouping_mutation_is_caught(monkeypatch):
+    from oracle import cga as ocga
+    from tests.test_oracle_cga import test_termination_grouping as pin
+    pin()
+    monkeypatch.setattr(ocga, "stop_test", lambda step, gn, prm: (step["eps"] < prm.get("eta1_eps", 0.0)
+                                                                 and gn["eps"] < prm.get("eta2_eps", 0.0))
+                        or (step["sig"] < prm.get("eta1_sig", 0.0) and gn["sig"] < prm.get("eta2_sig", 0.0)))
+    try:
+        pin()
+    except AssertionError:
+        return
+    raise AssertionError("the per-field grouping of the stop test passed the termination pin")
