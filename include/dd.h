@@ -142,6 +142,68 @@ int dd_adjoint(dd_problem* p, const float* cot_dev, void* stream);
  * (float64, n_fem_nodes each); zero on nodes of layer 0 and 1. */
 int dd_gradient(dd_problem* p, double* g_eps_dev, double* g_sigma_dev, void* stream);
 
+/* dd_adjoint for the trace misfit of eq. tikhonov_functional, J = 1/2 sum |E - E_obs|^2:
+ * the cotangent traces - obs is formed inside the adjoint kernels as they read it (no
+ * cotangent array is written).  traces_dev: the traces of the last saved dd_forward;
+ * obs_dev: observations, same layout ([n_src][n_steps][n_det][3] float32).  Same
+ * requirements and results as dd_adjoint. */
+int dd_adjoint_misfit(dd_problem* p, const float* traces_dev, const float* obs_dev, void* stream);
+
+/* ---- Conjugate gradient reconstruction (box "CGA") -----------------------------------
+ * One CGA iteration m is: dd_set_coefficients(eps^m, sigma^m), dd_forward(save),
+ * dd_adjoint_misfit, dd_gradient (step 1), then dd_cga_update (steps 2-6), which turns
+ * the gradient of J into the gradient functions of eq. gradeps,
+ *     g_i = (dJ/dc_i) / m_i + gamma^m (c_i - c^0_i)   on free nodes (layer >= 2),
+ * with m_i = h^3 the lumped mass and c^0 the initial guess (the Tikhonov centre of
+ * eq. tikhonov_functional), and updates the coefficients in place:
+ *     beta^m = |g^m|^2 / |g^{m-1}|^2 (0 at m = 0 or when |g^{m-1}| = 0),
+ *     d^m = -g^m + beta^m d^{m-1},
+ *     c^{m+1} = c^m + alpha^m d^m, kept in the box 1 <= eps <= eps_max, 0 <= sigma <= sig_max
+ *               of eq. epsilon_sigma_constraint,
+ *     alpha^{m+1} = -(g^m, d^m) / (gamma^m (d^m, d^m)) (alpha^m kept when d^m = 0),
+ *     gamma^{m+1} = gamma^0 / (m + 1)^p,
+ * where (u, v) = h^3 sum over free nodes of u_i v_i (lumped-mass L2 inner product) and
+ * |u| = (u, u)^{1/2}; eps and sigma are updated independently with their own scalars.
+ * The stop test of step 6 holds when (|eps^{m+1} - eps^m| < eta1_eps or
+ * |sigma^{m+1} - sigma^m| < eta1_sig) and (|g_eps^m| < eta2_eps or |g_sig^m| < eta2_sig).
+ * All of it runs on the device, with deterministic FP64 sums. */
+typedef struct dd_cga dd_cga;
+typedef struct {
+  double gamma_eps, gamma_sig;   /* gamma^0 > 0 */
+  double p;                      /* exponent of the gamma rule, 0 < p < 1 */
+  double alpha_eps, alpha_sig;   /* alpha^0 >= 0 */
+  double eps_max, sig_max;       /* coefficient box: eps_max > 1, sig_max > 0 */
+  double eta1_eps, eta1_sig, eta2_eps, eta2_sig;   /* tolerances of the stop test, >= 0 */
+} dd_cga_params;
+typedef struct {
+  int32_t iterations;            /* updates done (m after the last update) */
+  int32_t converged;             /* the stop test held at the last update */
+  /* of the last update, [0] = eps, [1] = sigma: */
+  double grad_norm[2];           /* |g^m| */
+  double step_norm[2];           /* |c^{m+1} - c^m| */
+  double beta[2];                /* beta^m */
+  double alpha_used[2];          /* alpha^m */
+  double alpha_next[2];          /* alpha^{m+1} */
+  double gamma_used[2];          /* gamma^m */
+  double gamma_next[2];          /* gamma^{m+1} */
+} dd_cga_info;
+
+/* Start a run on problem p from the initial guess eps0_dev, sig0_dev (FEM-node arrays,
+ * float32, copied: they are the Tikhonov centres).  The initial guess must satisfy the
+ * coefficient constraint and the box (else DD_ERR_CONSTRAINT); parameters out of range
+ * give DD_ERR_INVALID_ARG.  Synchronises `stream`.  The run keeps only the lattice sizes
+ * of p and may outlive it; release it with dd_cga_destroy. */
+int dd_cga_create(dd_problem* p, const dd_cga_params* prm, const float* eps0_dev, const float* sig0_dev, void* stream,
+                  dd_cga** out);
+int dd_cga_destroy(dd_cga* c);
+/* Steps 2-6: g_eps_dev, g_sigma_dev are dd_gradient's output at (eps^m, sigma^m);
+ * eps_dev, sigma_dev hold eps^m, sigma^m on entry and eps^{m+1}, sigma^{m+1} when the
+ * queued work is done (nodes of layers 0 and 1 are not written).  Asynchronous. */
+int dd_cga_update(dd_cga* c, const double* g_eps_dev, const double* g_sigma_dev, float* eps_dev, float* sigma_dev,
+                  void* stream);
+/* Scalars of the last update (synchronises `stream`). */
+int dd_cga_get_info(dd_cga* c, dd_cga_info* out, void* stream);
+
 const char* dd_error_string(int code);
 const char* dd_last_error(const dd_problem* p);
 

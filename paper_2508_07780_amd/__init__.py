@@ -6,3 +6,4 @@ this package only marshals arguments (torch supplies device memory and streams).
 
 from ._lib import DDError, load as load_library  # noqa: F401
 from .solver import Problem  # noqa: F401
+from .cga import CGA, CGAParams  # noqa: F401

@@ -17,6 +17,7 @@ EXPORTS = [
     "dd_set_coefficients", "dd_forward", "dd_adjoint", "dd_gradient", "dd_error_string", "dd_last_error",
     "dd_profile_enable", "dd_profile_read", "dd_algorithmic_bytes", "dd_debug_fem_apply",
     "dd_batch_create", "dd_batch_destroy", "dd_batch_submit", "dd_batch_step", "dd_batch_poll",
+    "dd_adjoint_misfit", "dd_cga_create", "dd_cga_destroy", "dd_cga_update", "dd_cga_get_info",
 ]
 
 PROF_FD_FWD, PROF_FEM_FWD, PROF_FD_ADJ, PROF_FEM_ADJ, PROF_FEM_RECOMPUTE, PROF_STEP_FWD, PROF_STEP_ADJ = range(7)
@@ -50,6 +51,18 @@ class Source(ctypes.Structure):
         ("pol", ctypes.c_double * 3),
         ("pos", ctypes.c_int32 * 3),
     ]
+
+
+class CgaParams(ctypes.Structure):
+    _fields_ = [(name, ctypes.c_double) for name in (
+        "gamma_eps", "gamma_sig", "p", "alpha_eps", "alpha_sig", "eps_max", "sig_max",
+        "eta1_eps", "eta1_sig", "eta2_eps", "eta2_sig")]
+
+
+class CgaInfo(ctypes.Structure):
+    _fields_ = [("iterations", ctypes.c_int32), ("converged", ctypes.c_int32)] + [
+        (name, ctypes.c_double * 2) for name in (
+            "grad_norm", "step_norm", "beta", "alpha_used", "alpha_next", "gamma_used", "gamma_next")]
 
 
 class DDError(RuntimeError):
@@ -98,6 +111,11 @@ def load():
     lib.dd_batch_step.argtypes = [P, ctypes.c_int32, P]
     lib.dd_batch_poll.argtypes = [P, ctypes.POINTER(ctypes.c_int32), ctypes.c_int32, ctypes.POINTER(ctypes.c_int32),
                                   ctypes.POINTER(ctypes.c_int32)]
+    lib.dd_adjoint_misfit.argtypes = [P, P, P, P]
+    lib.dd_cga_create.argtypes = [P, ctypes.POINTER(CgaParams), P, P, P, ctypes.POINTER(P)]
+    lib.dd_cga_destroy.argtypes = [P]
+    lib.dd_cga_update.argtypes = [P, P, P, P, P, P]
+    lib.dd_cga_get_info.argtypes = [P, ctypes.POINTER(CgaInfo), P]
     for name in EXPORTS:
         if name not in ("dd_footprint_bytes", "dd_error_string", "dd_last_error"):
             getattr(lib, name).restype = ctypes.c_int

@@ -1,0 +1,111 @@
+"""Conjugate gradient reconstruction of eps and sigma (box "CGA") on the device.
+
+Each iteration is the solver's step 1 (dd_set_coefficients, dd_forward with saving,
+dd_adjoint_misfit, dd_gradient) and the library's steps 2-6 (dd_cga_update: gradient
+functions of eq. gradeps with the Tikhonov terms of eq. tikhonov_functional, the
+conjugate direction, the coefficient update kept in the box of
+eq. epsilon_sigma_constraint, the step-size and regularisation rules and the stop test).
+Everything stays on the device; the host reads the run's scalars once per iteration.
+"""
+
+import ctypes
+from dataclasses import dataclass, fields
+
+import torch
+
+from . import _lib
+from .solver import _ptr, _stream
+
+
+@dataclass
+class CGAParams:
+    gamma_eps: float
+    gamma_sig: float
+    p: float
+    alpha_eps: float
+    alpha_sig: float
+    eps_max: float
+    sig_max: float
+    eta1_eps: float = 0.0
+    eta1_sig: float = 0.0
+    eta2_eps: float = 0.0
+    eta2_sig: float = 0.0
+
+    def to_c(self):
+        c = _lib.CgaParams()
+        for f in fields(self):
+            setattr(c, f.name, float(getattr(self, f.name)))
+        return c
+
+
+class CGA:
+    """A CGA run on one problem: sources, observations [n_src][n_steps][n_det][3] and the
+    initial guess (also the Tikhonov centre).  ``eps`` and ``sigma`` hold the iterate."""
+
+    def __init__(self, problem, sources, obs, eps0, sig0, params):
+        dev = torch.device("cuda", torch.cuda.current_device())
+        self.problem = problem
+        self.sources = list(sources)
+        shape = (len(self.sources), problem.n_steps, problem.n_det, 3)
+        if tuple(obs.shape) != shape or obs.dtype != torch.float32 or not obs.is_cuda:
+            raise ValueError("observations must be a float32 CUDA (HIP) tensor of shape %s" % (shape,))
+        self.obs = obs.contiguous()
+        self.eps = torch.as_tensor(eps0, dtype=torch.float32, device=dev).clone().contiguous()
+        self.sigma = torch.as_tensor(sig0, dtype=torch.float32, device=dev).clone().contiguous()
+        self.traces = torch.empty(shape, dtype=torch.float32, device=dev)
+        self.g_eps = torch.empty(problem.n_fem, dtype=torch.float64, device=dev)
+        self.g_sig = torch.empty(problem.n_fem, dtype=torch.float64, device=dev)
+        self.params = params
+        self._cp = params.to_c()
+        h = ctypes.c_void_p()
+        _lib.check(_lib.load().dd_cga_create(problem._h, ctypes.byref(self._cp), _ptr(self.eps), _ptr(self.sigma),
+                                             _stream(), ctypes.byref(h)), problem._h)
+        self._h = h
+
+    def close(self):
+        if getattr(self, "_h", None):
+            _lib.load().dd_cga_destroy(self._h)
+            self._h = None
+
+    def __del__(self):
+        try:
+            self.close()
+        except Exception:
+            pass
+
+    def solve(self):
+        """Step 1 at the current iterate: traces, misfit adjoint, gradient of J."""
+        p = self.problem
+        p.set_coefficients(self.eps, self.sigma)
+        p.forward(self.sources, save=True, out=self.traces)
+        p.adjoint_misfit(self.traces, self.obs)
+        p.gradient(out=(self.g_eps, self.g_sig))
+
+    def update(self):
+        """Steps 2-6 from the gradient of the last solve (asynchronous)."""
+        _lib.check(_lib.load().dd_cga_update(self._h, _ptr(self.g_eps), _ptr(self.g_sig), _ptr(self.eps),
+                                             _ptr(self.sigma), _stream()))
+
+    def iterate(self):
+        self.solve()
+        self.update()
+
+    def info(self):
+        """Scalars of the last update (synchronises the stream)."""
+        c = _lib.CgaInfo()
+        _lib.check(_lib.load().dd_cga_get_info(self._h, ctypes.byref(c), _stream()))
+        out = {"iterations": c.iterations, "converged": bool(c.converged)}
+        for name in ("grad_norm", "step_norm", "beta", "alpha_used", "alpha_next", "gamma_used", "gamma_next"):
+            arr = getattr(c, name)
+            out[name] = {"eps": arr[0], "sig": arr[1]}
+        return out
+
+    def run(self, n_iter):
+        """Up to n_iter iterations, stopping when the stop test holds; returns the infos."""
+        hist = []
+        for _ in range(n_iter):
+            self.iterate()
+            hist.append(self.info())
+            if hist[-1]["converged"]:
+                break
+        return hist

@@ -57,6 +57,7 @@ struct dd_problem {
   int saved_n_src = 0;
   double *g_eps = nullptr, *g_sig = nullptr;
   bool have_grad = false;
+  bool adj_obs = false;   // the last adjoint formed its cotangent as traces - observations
   std::string err;
   std::vector<void*> allocs;
   // kernel timing: event pairs around each step launch, per launch kind
@@ -730,19 +731,32 @@ int dd_forward(dd_problem* p, const dd_source* src, int32_t n_src, float* traces
   return DD_OK;
 }
 
-int dd_adjoint(dd_problem* p, const float* cot_dev, void* stream) {
-  if (!p) return DD_ERR_INVALID_ARG;
-  if (!cot_dev) return fail(p, DD_ERR_INVALID_ARG, "null cotangent");
-  if (!p->saved) return fail(p, DD_ERR_STATE, "dd_adjoint needs a preceding dd_forward with save");
-  hipStream_t st = (hipStream_t)stream;
+namespace {
+int adjoint_all(dd_problem* p, const float* cot, const float* obs, hipStream_t st) {
   launch_fill_f64(p->g_eps, p->n_own, 0.0, st);
   launch_fill_f64(p->g_sig, p->n_own, 0.0, st);
+  p->adj_obs = obs != nullptr;
   for (int s = 0; s < p->saved_n_src; ++s) {
-    int rc = run_adjoint(p, s, cot_dev, nullptr, st);
+    int rc = run_adjoint(p, s, cot, obs, st);
     if (rc) return rc;
   }
   p->have_grad = true;
   return DD_OK;
+}
+}  // namespace
+
+int dd_adjoint(dd_problem* p, const float* cot_dev, void* stream) {
+  if (!p) return DD_ERR_INVALID_ARG;
+  if (!cot_dev) return fail(p, DD_ERR_INVALID_ARG, "null cotangent");
+  if (!p->saved) return fail(p, DD_ERR_STATE, "dd_adjoint needs a preceding dd_forward with save");
+  return adjoint_all(p, cot_dev, nullptr, (hipStream_t)stream);
+}
+
+int dd_adjoint_misfit(dd_problem* p, const float* traces_dev, const float* obs_dev, void* stream) {
+  if (!p) return DD_ERR_INVALID_ARG;
+  if (!traces_dev || !obs_dev) return fail(p, DD_ERR_INVALID_ARG, "null traces or observations");
+  if (!p->saved) return fail(p, DD_ERR_STATE, "dd_adjoint_misfit needs a preceding dd_forward with save");
+  return adjoint_all(p, traces_dev, obs_dev, (hipStream_t)stream);
 }
 
 int dd_gradient(dd_problem* p, double* g_eps_dev, double* g_sigma_dev, void* stream) {
@@ -754,6 +768,147 @@ int dd_gradient(dd_problem* p, double* g_eps_dev, double* g_sigma_dev, void* str
   launch_fill_f64(g_sigma_dev, p->n_fem, 0.0, st);
   launch_gradient_out(p->g_eps, p->g_sig, p->own_api, p->own_grid, p->n_own, g_eps_dev, g_sigma_dev, st);
   return check_launch(p);
+}
+
+}  // extern "C"
+
+// ---------------------------------------------------------------------------------------
+// Conjugate gradient reconstruction (box "CGA"): device state of one run.
+// ---------------------------------------------------------------------------------------
+struct dd_cga {
+  int fs[3] = {0, 0, 0};
+  int64_t n = 0;
+  float* c0 = nullptr;      // [2][n]: eps^0, sigma^0 (Tikhonov centres)
+  double* d = nullptr;      // [2][n]: previous directions d^{m-1}
+  double* part = nullptr;   // [CGA_MAX_BLOCKS][6] block partials
+  CgaDev* st = nullptr;
+};
+
+namespace {
+bool cga_params_ok(const dd_cga_params& q, std::string& why) {
+  const double v[] = {q.gamma_eps, q.gamma_sig, q.p, q.alpha_eps, q.alpha_sig, q.eps_max, q.sig_max,
+                      q.eta1_eps, q.eta1_sig, q.eta2_eps, q.eta2_sig};
+  for (double x : v)
+    if (!std::isfinite(x)) { why = "CGA parameters must be finite"; return false; }
+  if (!(q.gamma_eps > 0.0 && q.gamma_sig > 0.0)) { why = "gamma^0 must be > 0"; return false; }
+  if (!(q.p > 0.0 && q.p < 1.0)) { why = "p must lie in (0, 1)"; return false; }
+  if (!(q.alpha_eps >= 0.0 && q.alpha_sig >= 0.0)) { why = "alpha^0 must be >= 0"; return false; }
+  if (!(q.eps_max > 1.0 && q.sig_max > 0.0)) { why = "need eps_max > 1 and sig_max > 0"; return false; }
+  if (!(q.eta1_eps >= 0.0 && q.eta1_sig >= 0.0 && q.eta2_eps >= 0.0 && q.eta2_sig >= 0.0)) {
+    why = "tolerances must be >= 0";
+    return false;
+  }
+  return true;
+}
+
+void cga_free(dd_cga* c) {
+  if (!c) return;
+  (void)hipFree(c->c0);
+  (void)hipFree(c->d);
+  (void)hipFree(c->part);
+  (void)hipFree(c->st);
+  delete c;
+}
+}  // namespace
+
+extern "C" {
+
+int dd_cga_create(dd_problem* p, const dd_cga_params* prm, const float* eps0_dev, const float* sig0_dev, void* stream,
+                  dd_cga** out) {
+  if (!p) return DD_ERR_INVALID_ARG;
+  if (!prm || !eps0_dev || !sig0_dev || !out) return fail(p, DD_ERR_INVALID_ARG, "null CGA argument");
+  *out = nullptr;
+  std::string why;
+  if (!cga_params_ok(*prm, why)) return fail(p, DD_ERR_INVALID_ARG, why);
+  hipStream_t st = (hipStream_t)stream;
+  // the initial guess must satisfy eq. epsilon_sigma_constraint, upper bounds included
+  int h_err[2] = {0, 0};
+  if (hipMemsetAsync(p->d_err, 0, sizeof(int), st) != hipSuccess) return fail(p, DD_ERR_HIP, "hipMemsetAsync failed");
+  launch_validate(eps0_dev, sig0_dev, p->fs[0], p->fs[1], p->fs[2], p->d_err, st);
+  if (hipMemcpyAsync(&h_err[0], p->d_err, sizeof(int), hipMemcpyDeviceToHost, st) != hipSuccess ||
+      hipStreamSynchronize(st) != hipSuccess)
+    return fail(p, DD_ERR_HIP, "error readback failed");
+  if (hipMemsetAsync(p->d_err, 0, sizeof(int), st) != hipSuccess) return fail(p, DD_ERR_HIP, "hipMemsetAsync failed");
+  launch_cga_upper_check(eps0_dev, sig0_dev, p->n_fem, prm->eps_max, prm->sig_max, p->d_err, st);
+  if (int rc = check_launch(p)) return rc;
+  if (hipMemcpyAsync(&h_err[1], p->d_err, sizeof(int), hipMemcpyDeviceToHost, st) != hipSuccess ||
+      hipStreamSynchronize(st) != hipSuccess)
+    return fail(p, DD_ERR_HIP, "error readback failed");
+  if (h_err[0] || h_err[1])
+    return fail(p, DD_ERR_CONSTRAINT, std::to_string(h_err[0] + h_err[1]) +
+                                          " FEM nodes of the initial guess violate the coefficient box");
+  dd_cga* c = new dd_cga();
+  for (int a = 0; a < 3; ++a) c->fs[a] = p->fs[a];
+  c->n = p->n_fem;
+  if (hipMalloc((void**)&c->c0, 2 * c->n * sizeof(float)) != hipSuccess ||
+      hipMalloc((void**)&c->d, 2 * c->n * sizeof(double)) != hipSuccess ||
+      hipMalloc((void**)&c->part, (size_t)CGA_MAX_BLOCKS * 6 * sizeof(double)) != hipSuccess ||
+      hipMalloc((void**)&c->st, sizeof(CgaDev)) != hipSuccess) {
+    cga_free(c);
+    return fail(p, DD_ERR_OOM, "CGA state allocation failed");
+  }
+  CgaDev h{};
+  h.gamma0[0] = h.gamma[0] = prm->gamma_eps;
+  h.gamma0[1] = h.gamma[1] = prm->gamma_sig;
+  h.p = prm->p;
+  h.alpha[0] = prm->alpha_eps;
+  h.alpha[1] = prm->alpha_sig;
+  h.lo[0] = 1.0;
+  h.lo[1] = 0.0;
+  h.hi[0] = prm->eps_max;
+  h.hi[1] = prm->sig_max;
+  h.eta1[0] = prm->eta1_eps;
+  h.eta1[1] = prm->eta1_sig;
+  h.eta2[0] = prm->eta2_eps;
+  h.eta2[1] = prm->eta2_sig;
+  h.w = p->d.h * p->d.h * p->d.h;
+  launch_copy_f32(c->c0, eps0_dev, c->n, st);
+  launch_copy_f32(c->c0 + c->n, sig0_dev, c->n, st);
+  launch_fill_f64(c->d, 2 * c->n, 0.0, st);
+  if (int rc = check_launch(p)) {
+    cga_free(c);
+    return rc;
+  }
+  if (hipStreamSynchronize(st) != hipSuccess || hipMemcpy(c->st, &h, sizeof(CgaDev), hipMemcpyHostToDevice) != hipSuccess) {
+    cga_free(c);
+    return fail(p, DD_ERR_HIP, "CGA state upload failed");
+  }
+  *out = c;
+  return DD_OK;
+}
+
+int dd_cga_destroy(dd_cga* c) {
+  if (!c) return DD_ERR_INVALID_ARG;
+  cga_free(c);
+  return DD_OK;
+}
+
+int dd_cga_update(dd_cga* c, const double* g_eps_dev, const double* g_sigma_dev, float* eps_dev, float* sigma_dev,
+                  void* stream) {
+  if (!c || !g_eps_dev || !g_sigma_dev || !eps_dev || !sigma_dev) return DD_ERR_INVALID_ARG;
+  launch_cga_update(g_eps_dev, g_sigma_dev, eps_dev, sigma_dev, c->c0, c->c0 + c->n, c->d, c->d + c->n, c->fs, c->st,
+                    c->part, (hipStream_t)stream);
+  return hipGetLastError() == hipSuccess ? DD_OK : DD_ERR_HIP;
+}
+
+int dd_cga_get_info(dd_cga* c, dd_cga_info* out, void* stream) {
+  if (!c || !out) return DD_ERR_INVALID_ARG;
+  CgaDev h{};
+  if (hipStreamSynchronize((hipStream_t)stream) != hipSuccess ||
+      hipMemcpy(&h, c->st, sizeof(CgaDev), hipMemcpyDeviceToHost) != hipSuccess)
+    return DD_ERR_HIP;
+  out->iterations = h.m;
+  out->converged = h.converged;
+  for (int f = 0; f < 2; ++f) {
+    out->grad_norm[f] = std::sqrt(h.gn2[f]);
+    out->step_norm[f] = std::sqrt(h.step2[f]);
+    out->beta[f] = h.beta[f];
+    out->alpha_used[f] = h.alpha_used[f];
+    out->alpha_next[f] = h.alpha[f];
+    out->gamma_used[f] = h.gamma_used[f];
+    out->gamma_next[f] = h.gamma[f];
+  }
+  return DD_OK;
 }
 
 int dd_profile_enable(dd_problem* p, int32_t stride) {
@@ -803,6 +958,7 @@ int dd_algorithmic_bytes(const dd_problem* p, int32_t kind, double* bytes_per_la
   // FD (three-level form): E^n and E^{n-1} read, E^{n+1} written; traces (forward)
   // written or cotangent (adjoint) read; layer-0 values written
   const double fd = 36.0 * n_fd + 12.0 * n_det + 12.0 * n_l0;
+  const double fd_adj = fd + (p->adj_obs ? 12.0 * n_det : 0.0);   // observations read as well
   // FEM: state read and written, coefficients (eps - 1, c1, c2), layer-0 values read,
   // layer-1 values dual-written into the FD grid
   const double fem = 48.0 * n_own + 12.0 * n_own + 12.0 * n_l0 + 12.0 * n_l1;
@@ -810,13 +966,13 @@ int dd_algorithmic_bytes(const dd_problem* p, int32_t kind, double* bytes_per_la
   const double grad = 36.0 * n_free + 32.0 * n_free;
   double b = 0.0;
   switch (kind) {
-    case DD_PROF_FD_FWD:
-    case DD_PROF_FD_ADJ: b = fd; break;
+    case DD_PROF_FD_FWD: b = fd; break;
+    case DD_PROF_FD_ADJ: b = fd_adj; break;
     case DD_PROF_FEM_FWD: b = fem + save_fem; break;
     case DD_PROF_FEM_RECOMPUTE: b = 48.0 * n_own + 12.0 * n_own + 12.0 * n_l0; break;   // window to window
     case DD_PROF_FEM_ADJ: b = fem + grad; break;
     case DD_PROF_STEP_FWD: b = fd + fem + save_fem; break;
-    case DD_PROF_STEP_ADJ: b = fd + fem + grad; break;
+    case DD_PROF_STEP_ADJ: b = fd_adj + fem + grad; break;
   }
   *bytes_per_launch = b;
   return DD_OK;
@@ -999,6 +1155,7 @@ int dd_batch_submit(dd_batch* b, dd_problem* p, const dd_source* src, int32_t n_
   for (int s = 0; s < n_src; ++s) j.plans.push_back(source_plan(p, src[s]));
   j.traces = traces_dev;
   j.obs = obs_dev;
+  p->adj_obs = obs_dev != nullptr;
   j.g_eps = g_eps_dev;
   j.g_sig = g_sigma_dev;
   j.id = b->next_id++;

@@ -1,0 +1,207 @@
+// Conjugate gradient update of the coefficients eps and sigma (box "CGA", steps 2-6) on
+// the FEM lattice, after the forward / adjoint / gradient solves of step 1.
+//
+// With the lumped-mass L2 inner product (u, v) = sum_i m_i u_i v_i (m_i = h^3 on every
+// free node, i.e. layer >= 2) the gradient function of eq. gradeps at a free node is
+//     g_i = (dJ/dc_i) / m_i + gamma^m (c_i - c^0_i),
+// the nodal derivative of the trace misfit turned into a function, plus the Tikhonov term
+// of eq. tikhonov_functional (centre = the initial guess).  One update then takes
+//     beta^m  = |g^m|^2 / |g^{m-1}|^2               (0 at m = 0 or when |g^{m-1}| = 0)
+//     d^m     = -g^m + beta^m d^{m-1}
+//     c^{m+1} = clamp(c^m + alpha^m d^m, lo, hi)     (the box of eq. epsilon_sigma_constraint)
+//     alpha^{m+1} = -(g^m, d^m) / (gamma^m (d^m, d^m))   (alpha^m kept when d^m = 0)
+//     gamma^{m+1} = gamma^0 / (m + 1)^p
+// and the stop test (|c^{m+1} - c^m| < eta1 for eps or sigma) and (|g^m| < eta2 for eps or
+// sigma).  Nodes of layers 0 and 1 are never touched (eps = 1, sigma = 0 there).
+//
+// The work is a few streaming passes over FEM-node arrays (HBM-bound, a few microseconds
+// at the paper's sizes).  Every sum is FP64 and deterministic: each block reduces its
+// grid-stride share in a fixed order, one block then adds the block partials in order.
+#include "dd_common.hpp"
+
+namespace dd {
+
+namespace {
+
+constexpr int CGA_THREADS = 256;
+
+__device__ inline bool cga_free(int64_t i, int fsx, int fsy, int fsz) {
+  const int lx = (int)(i % fsx);
+  const int64_t r = i / fsx;
+  const int ly = (int)(r % fsy);
+  const int lz = (int)(r / fsy);
+  const int lay = min(min(min(lx, fsx - 1 - lx), min(ly, fsy - 1 - ly)), min(lz, fsz - 1 - lz));
+  return lay >= 2;
+}
+
+__device__ inline double cga_g(double dJ, double w, float c, float c0, double gamma) {
+  return dJ / w + gamma * ((double)c - (double)c0);
+}
+
+// Block-wide sums of NQ values per thread, in a fixed order; thread 0 writes them to out.
+template <int NQ>
+__device__ inline void block_sums(const double (&v)[NQ], double* out) {
+  __shared__ double red[NQ][CGA_THREADS];
+  const int t = threadIdx.x;
+#pragma unroll
+  for (int q = 0; q < NQ; ++q) red[q][t] = v[q];
+  __syncthreads();
+  for (int s = CGA_THREADS / 2; s > 0; s >>= 1) {
+    if (t < s) {
+#pragma unroll
+      for (int q = 0; q < NQ; ++q) red[q][t] += red[q][t + s];
+    }
+    __syncthreads();
+  }
+  if (t == 0) {
+#pragma unroll
+    for (int q = 0; q < NQ; ++q) out[q] = red[q][0];
+  }
+}
+
+// Sums of NQ partials over nb blocks (partials laid out [nb][NQ]).
+template <int NQ>
+__device__ inline void sum_partials(const double* part, int nb, double* out) {
+  double v[NQ];
+#pragma unroll
+  for (int q = 0; q < NQ; ++q) v[q] = 0.0;
+  for (int b = threadIdx.x; b < nb; b += CGA_THREADS) {
+#pragma unroll
+    for (int q = 0; q < NQ; ++q) v[q] += part[(int64_t)b * NQ + q];
+  }
+  block_sums<NQ>(v, out);
+}
+
+// |g^m|^2 partials of eps and sigma.
+__global__ __launch_bounds__(CGA_THREADS) void cga_norm_kernel(
+    const double* __restrict__ gJe, const double* __restrict__ gJs, const float* __restrict__ eps,
+    const float* __restrict__ sig, const float* __restrict__ eps0, const float* __restrict__ sig0, int fsx, int fsy,
+    int fsz, const CgaDev* __restrict__ st, double* __restrict__ part) {
+  const int64_t n = (int64_t)fsx * fsy * fsz;
+  const double w = st->w, gam_e = st->gamma[0], gam_s = st->gamma[1];
+  double acc[2] = {0.0, 0.0};
+  for (int64_t i = (int64_t)blockIdx.x * CGA_THREADS + threadIdx.x; i < n; i += (int64_t)gridDim.x * CGA_THREADS) {
+    if (!cga_free(i, fsx, fsy, fsz)) continue;
+    const double ge = cga_g(gJe[i], w, eps[i], eps0[i], gam_e);
+    const double gs = cga_g(gJs[i], w, sig[i], sig0[i], gam_s);
+    acc[0] += ge * ge;
+    acc[1] += gs * gs;
+  }
+  block_sums<2>(acc, part + (int64_t)blockIdx.x * 2);
+}
+
+// |g^m|^2 and beta^m (one block).
+__global__ __launch_bounds__(CGA_THREADS) void cga_beta_kernel(const double* __restrict__ part, int nb,
+                                                               CgaDev* __restrict__ st) {
+  __shared__ double tot[2];
+  sum_partials<2>(part, nb, tot);
+  __syncthreads();
+  if (threadIdx.x == 0) {
+    for (int f = 0; f < 2; ++f) {
+      const double gn2 = st->w * tot[f];
+      st->gn2[f] = gn2;
+      st->beta[f] = (st->m > 0 && st->gn2_prev[f] > 0.0) ? gn2 / st->gn2_prev[f] : 0.0;
+    }
+  }
+}
+
+// d^m, c^{m+1} (in place) and the partials of (g, d), (d, d), |c^{m+1} - c^m|^2.
+__global__ __launch_bounds__(CGA_THREADS) void cga_step_kernel(
+    const double* __restrict__ gJe, const double* __restrict__ gJs, float* __restrict__ eps, float* __restrict__ sig,
+    const float* __restrict__ eps0, const float* __restrict__ sig0, double* __restrict__ d_eps,
+    double* __restrict__ d_sig, int fsx, int fsy, int fsz, const CgaDev* __restrict__ st, double* __restrict__ part) {
+  const int64_t n = (int64_t)fsx * fsy * fsz;
+  const double w = st->w;
+  const double gam[2] = {st->gamma[0], st->gamma[1]};
+  const double beta[2] = {st->beta[0], st->beta[1]};
+  const double alpha[2] = {st->alpha[0], st->alpha[1]};
+  const double lo[2] = {st->lo[0], st->lo[1]}, hi[2] = {st->hi[0], st->hi[1]};
+  double acc[6] = {0.0, 0.0, 0.0, 0.0, 0.0, 0.0};
+  for (int64_t i = (int64_t)blockIdx.x * CGA_THREADS + threadIdx.x; i < n; i += (int64_t)gridDim.x * CGA_THREADS) {
+    if (!cga_free(i, fsx, fsy, fsz)) continue;
+    {
+      const float c = eps[i];
+      const double g = cga_g(gJe[i], w, c, eps0[i], gam[0]);
+      const double d = -g + beta[0] * d_eps[i];
+      const float cn = (float)fmin(fmax((double)c + alpha[0] * d, lo[0]), hi[0]);
+      d_eps[i] = d;
+      eps[i] = cn;
+      const double dc = (double)cn - (double)c;
+      acc[0] += g * d;
+      acc[1] += d * d;
+      acc[2] += dc * dc;
+    }
+    {
+      const float c = sig[i];
+      const double g = cga_g(gJs[i], w, c, sig0[i], gam[1]);
+      const double d = -g + beta[1] * d_sig[i];
+      const float cn = (float)fmin(fmax((double)c + alpha[1] * d, lo[1]), hi[1]);
+      d_sig[i] = d;
+      sig[i] = cn;
+      const double dc = (double)cn - (double)c;
+      acc[3] += g * d;
+      acc[4] += d * d;
+      acc[5] += dc * dc;
+    }
+  }
+  block_sums<6>(acc, part + (int64_t)blockIdx.x * 6);
+}
+
+// alpha^{m+1}, gamma^{m+1}, the stop test, m -> m + 1 (one block).
+__global__ __launch_bounds__(CGA_THREADS) void cga_finish_kernel(const double* __restrict__ part, int nb,
+                                                                 CgaDev* __restrict__ st) {
+  __shared__ double tot[6];
+  sum_partials<6>(part, nb, tot);
+  __syncthreads();
+  if (threadIdx.x == 0) {
+    bool small_step = false, small_grad = false;
+    for (int f = 0; f < 2; ++f) {
+      const double gd = st->w * tot[3 * f], dd = st->w * tot[3 * f + 1], step2 = st->w * tot[3 * f + 2];
+      st->gd[f] = gd;
+      st->dd[f] = dd;
+      st->step2[f] = step2;
+      st->alpha_used[f] = st->alpha[f];
+      st->gamma_used[f] = st->gamma[f];
+      if (dd > 0.0) st->alpha[f] = -gd / (st->gamma[f] * dd);
+      st->gamma[f] = st->gamma0[f] / pow((double)(st->m + 1), st->p);
+      st->gn2_prev[f] = st->gn2[f];
+      small_step = small_step || sqrt(step2) < st->eta1[f];
+      small_grad = small_grad || sqrt(st->gn2[f]) < st->eta2[f];
+    }
+    st->converged = (small_step && small_grad) ? 1 : 0;
+    st->m += 1;
+  }
+}
+
+__global__ void cga_upper_check_kernel(const float* __restrict__ eps, const float* __restrict__ sig, int64_t n,
+                                       double eps_max, double sig_max, int* err) {
+  for (int64_t i = (int64_t)blockIdx.x * blockDim.x + threadIdx.x; i < n; i += (int64_t)gridDim.x * blockDim.x)
+    if (!((double)eps[i] <= eps_max) || !((double)sig[i] <= sig_max)) atomicAdd(err, 1);
+}
+
+}  // namespace
+
+int cga_blocks(int64_t n_fem) {
+  const int64_t b = (n_fem + CGA_THREADS - 1) / CGA_THREADS;
+  return (int)std::max<int64_t>(1, std::min<int64_t>(b, CGA_MAX_BLOCKS));
+}
+
+void launch_cga_update(const double* gJe, const double* gJs, float* eps, float* sig, const float* eps0,
+                       const float* sig0, double* d_eps, double* d_sig, const int fs[3], CgaDev* st,
+                       double* part, hipStream_t s) {
+  const int nb = cga_blocks((int64_t)fs[0] * fs[1] * fs[2]);
+  hipLaunchKernelGGL(cga_norm_kernel, dim3(nb), dim3(CGA_THREADS), 0, s, gJe, gJs, eps, sig, eps0, sig0, fs[0],
+                     fs[1], fs[2], st, part);
+  hipLaunchKernelGGL(cga_beta_kernel, dim3(1), dim3(CGA_THREADS), 0, s, part, nb, st);
+  hipLaunchKernelGGL(cga_step_kernel, dim3(nb), dim3(CGA_THREADS), 0, s, gJe, gJs, eps, sig, eps0, sig0, d_eps,
+                     d_sig, fs[0], fs[1], fs[2], st, part);
+  hipLaunchKernelGGL(cga_finish_kernel, dim3(1), dim3(CGA_THREADS), 0, s, part, nb, st);
+}
+
+void launch_cga_upper_check(const float* eps, const float* sig, int64_t n, double eps_max, double sig_max, int* err,
+                            hipStream_t s) {
+  const int nb = cga_blocks(n);
+  hipLaunchKernelGGL(cga_upper_check_kernel, dim3(nb), dim3(CGA_THREADS), 0, s, eps, sig, n, eps_max, sig_max, err);
+}
+
+}  // namespace dd

@@ -101,7 +101,23 @@ class Problem:
             raise ValueError("cotangent must match the traces of the last forward")
         _lib.check(_lib.load().dd_adjoint(self._h, _ptr(c), _stream()), self._h)
 
-    def gradient(self):
+    def adjoint_misfit(self, traces, obs):
+        """Adjoint for the misfit cotangent traces - obs, formed inside the adjoint kernels."""
+        shape = (self._n_src, self.n_steps, self.n_det, 3)
+        for name, t in (("traces", traces), ("observations", obs)):
+            if not (t.is_cuda and t.dtype == torch.float32 and t.is_contiguous()) or \
+                    (self._n_src and tuple(t.shape) != shape):
+                raise ValueError("%s must be a contiguous float32 CUDA (HIP) tensor of shape %s" % (name, shape))
+        _lib.check(_lib.load().dd_adjoint_misfit(self._h, _ptr(traces), _ptr(obs), _stream()), self._h)
+
+    def gradient(self, out=None):
+        if out is not None:
+            ge, gs = out
+            for t in (ge, gs):
+                if not (t.is_cuda and t.dtype == torch.float64 and t.is_contiguous() and t.numel() == self.n_fem):
+                    raise ValueError("gradient buffers must be contiguous float64 CUDA tensors of n_fem entries")
+            _lib.check(_lib.load().dd_gradient(self._h, _ptr(ge), _ptr(gs), _stream()), self._h)
+            return ge, gs
         dev = torch.device("cuda", torch.cuda.current_device())
         ge = torch.empty(self.n_fem, dtype=torch.float64, device=dev)
         gs = torch.empty(self.n_fem, dtype=torch.float64, device=dev)
