@@ -106,7 +106,7 @@ def batch_comparison():
     t0 = time.perf_counter()
     for p, w, o in zip(probs, mix, obs):
         tr = p.forward(w.sources, save=True)
-        p.adjoint(tr - o)
+        p.adjoint_misfit(tr, o)
         p.gradient()
     torch.cuda.synchronize()
     t_serial = time.perf_counter() - t0
@@ -217,6 +217,61 @@ def c3_autograd(reps=2):
             "gradient_finite": finite, "setup_s": round(t_setup, 2)}
 
 
+def cga_measure(prob, w, eobs, n_iter):
+    """Reconstruction iterations (box "CGA") on the main workload from the paper's initial
+    guess eps = 1, sigma = 0: each iteration is a solve (forward with saving, misfit adjoint,
+    gradient) and the device update.  The step sizes and regularisation are set from the
+    gradient at the initial guess (setup, not timed): the first update moves eps by at most
+    0.5 and sigma by at most 0.1, and gamma^0 = max|g^0| / that bound, so that alpha^1 =
+    1 / gamma^0 keeps the same scale."""
+    import numpy as np
+    import torch
+    from paper_2508_07780_amd import CGA, CGAParams
+    dev = eobs.device
+    n = prob.n_fem
+    eps0 = torch.ones(n, dtype=torch.float32, device=dev)
+    sig0 = torch.zeros(n, dtype=torch.float32, device=dev)
+    h3 = float(w.desc.h) ** 3
+    prob.set_coefficients(eps0, sig0)
+    tr = prob.forward(w.sources, save=True)
+    prob.adjoint_misfit(tr, eobs)
+    ge, gs = prob.gradient()
+    gmax = [float(torch.max(torch.abs(g)).item()) / h3 for g in (ge, gs)]
+    del tr, ge, gs
+    step = (0.5, 0.1)
+    prm = CGAParams(gamma_eps=gmax[0] / step[0], gamma_sig=gmax[1] / step[1], p=0.5,
+                    alpha_eps=step[0] / gmax[0], alpha_sig=step[1] / gmax[1], eps_max=20.0, sig_max=3.0)
+    c = CGA(prob, w.sources, eobs, eps0, sig0, prm)
+    ev = [torch.cuda.Event(enable_timing=True) for _ in range(2 * n_iter)]
+    torch.cuda.synchronize()
+    t0 = time.perf_counter()
+    hist = []
+    for m in range(n_iter):
+        c.solve()
+        ev[2 * m].record()
+        c.update()
+        ev[2 * m + 1].record()
+        hist.append(c.info())
+    torch.cuda.synchronize()
+    elapsed = time.perf_counter() - t0
+    upd_us = sum(ev[2 * m].elapsed_time(ev[2 * m + 1]) for m in range(n_iter)) / n_iter * 1e3
+    n_free = int(np.prod([max(int(x) - 3, 0) for x in w.desc.fem_cells]))
+    upd_bytes = 104.0 * n_free     # gradient, iterate, centre read twice; direction read and written; iterate written
+    cells = (w.desc.n_grid() + w.desc.n_fem_owned()) * 2 * w.desc.n_steps * len(w.sources)
+    c.close()
+    rnd = lambda x: float("%.4g" % x)  # noqa: E731
+    return {
+        "iterations": n_iter, "ms_per_iteration": round(elapsed / n_iter * 1e3, 2),
+        "gcell_steps_s": round(cells * n_iter / elapsed / 1e9, 2),
+        "update_us": round(upd_us, 2), "update_algorithmic_bytes": upd_bytes,
+        "update_GBs": round(upd_bytes / (upd_us * 1e-6) / 1e9, 1),
+        "params": {k: rnd(v) for k, v in vars(prm).items() if not k.startswith("eta")},
+        "history": [{"grad_norm": [rnd(i["grad_norm"]["eps"]), rnd(i["grad_norm"]["sig"])],
+                     "step_norm": [rnd(i["step_norm"]["eps"]), rnd(i["step_norm"]["sig"])],
+                     "beta": [rnd(i["beta"]["eps"]), rnd(i["beta"]["sig"])]} for i in hist],
+    }
+
+
 def serving_comparison():
     """Continuous batching vs one solve at a time on the same uneven request stream.
 
@@ -266,6 +321,7 @@ def main():
                     help="run only the 288^3 probe (for profilers) and print its JSON")
     ap.add_argument("--probe-steps", type=int, default=300, help="time steps of the probe")
     ap.add_argument("--c3", type=int, default=1, help="0 skips the 192^3 autograd measurement")
+    ap.add_argument("--cga", type=int, default=3, help="CGA iterations to time on the main workload (0 skips)")
     ap.add_argument("--profile-stride", type=int, default=64,
                     help="time every k-th step launch with HIP events (k >= 16 barely perturbs the run)")
     args = ap.parse_args()
@@ -298,11 +354,15 @@ def main():
     sig0 = torch.zeros(prob.n_fem, dtype=torch.float32, device=dev)
     torch.cuda.synchronize()
 
+    traces = torch.empty_like(eobs)
+    g_out = (torch.empty(prob.n_fem, dtype=torch.float64, device=dev),
+             torch.empty(prob.n_fem, dtype=torch.float64, device=dev))
+
     def solve():
         prob.set_coefficients(eps0, sig0)
-        tr = prob.forward(w.sources, save=True)
-        prob.adjoint(tr - eobs)          # dJ/dtraces of J = 1/2 sum |E - E_obs|^2
-        return prob.gradient()
+        prob.forward(w.sources, save=True, out=traces)
+        prob.adjoint_misfit(traces, eobs)     # cotangent traces - E_obs of J = 1/2 sum |E - E_obs|^2
+        return prob.gradient(out=g_out)
 
     for _ in range(args.warmup):
         solve()
@@ -372,6 +432,8 @@ def main():
                     for k, v in kern.items()},
         "gradient_finite": finite,
     }
+    if args.cga:
+        out["cga"] = cga_measure(prob, w, eobs, args.cga)
     del prob
     if args.probe:
         out["hbm_probe"] = large_probe(args.probe_steps)

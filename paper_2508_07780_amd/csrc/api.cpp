@@ -12,6 +12,7 @@
 #include <cstring>
 #include <new>
 
+#include "cga.hpp"
 #include "dd_common.hpp"
 
 using namespace dd;

@@ -17,7 +17,7 @@
 // The work is a few streaming passes over FEM-node arrays (HBM-bound, a few microseconds
 // at the paper's sizes).  Every sum is FP64 and deterministic: each block reduces its
 // grid-stride share in a fixed order, one block then adds the block partials in order.
-#include "dd_common.hpp"
+#include "cga.hpp"
 
 namespace dd {
 

@@ -1,0 +1,32 @@
+// Conjugate gradient update of eps and sigma (box "CGA", steps 2-6): device state and launch.
+#pragma once
+
+#include "dd_common.hpp"
+
+namespace dd {
+
+// ---- conjugate gradient update of eps and sigma (box "CGA", steps 2-6) ----------------
+// Index 0 = eps, 1 = sigma.  Lives in device memory; written by one thread of the
+// single-block kernels, read by all.
+struct CgaDev {
+  // parameters
+  double gamma0[2], p, lo[2], hi[2], eta1[2], eta2[2];
+  double w;                  // lumped mass of a free node (h^3): weight of the L2 inner product
+  // iteration state: gamma^m, alpha^m, |g^{m-1}|^2, m
+  double gamma[2], alpha[2], gn2_prev[2];
+  int m, converged;
+  // results of the last update
+  double gn2[2], beta[2], gd[2], dd[2], step2[2], alpha_used[2], gamma_used[2];
+};
+constexpr int CGA_MAX_BLOCKS = 1024;
+int cga_blocks(int64_t n_fem);
+// Four launches: gradient-function norms, beta, direction / update / projection, step sizes.
+// part holds CGA_MAX_BLOCKS x 6 doubles.
+void launch_cga_update(const double* gJe, const double* gJs, float* eps, float* sig, const float* eps0,
+                       const float* sig0, double* d_eps, double* d_sig, const int fs[3], CgaDev* st,
+                       double* part, hipStream_t s);
+// Counts FEM nodes with eps > eps_max or sigma > sig_max into *err.
+void launch_cga_upper_check(const float* eps, const float* sig, int64_t n, double eps_max, double sig_max, int* err,
+                            hipStream_t s);
+
+}  // namespace dd

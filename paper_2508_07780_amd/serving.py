@@ -156,7 +156,7 @@ def serve_serial(requests, time_fn=time.perf_counter):
         job = _Job(req, dev)
         for _ in range(req.iterations):
             tr = job.problem.forward(req.workload.sources, save=True)
-            job.problem.adjoint(tr - job.obs)
+            job.problem.adjoint_misfit(tr, job.obs)
             ge, gs = job.problem.gradient()
             job.update(ge, gs)
             solves += 1
