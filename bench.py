@@ -231,16 +231,12 @@ def cga_measure(prob, w, eobs, n_iter):
     n = prob.n_fem
     eps0 = torch.ones(n, dtype=torch.float32, device=dev)
     sig0 = torch.zeros(n, dtype=torch.float32, device=dev)
-    h3 = float(w.desc.h) ** 3
     prob.set_coefficients(eps0, sig0)
     tr = prob.forward(w.sources, save=True)
     prob.adjoint_misfit(tr, eobs)
     ge, gs = prob.gradient()
-    gmax = [float(torch.max(torch.abs(g)).item()) / h3 for g in (ge, gs)]
+    prm = CGAParams.from_gradient(ge, gs, w.desc.h, eps_max=20.0, sig_max=3.0)
     del tr, ge, gs
-    step = (0.5, 0.1)
-    prm = CGAParams(gamma_eps=gmax[0] / step[0], gamma_sig=gmax[1] / step[1], p=0.5,
-                    alpha_eps=step[0] / gmax[0], alpha_sig=step[1] / gmax[1], eps_max=20.0, sig_max=3.0)
     c = CGA(prob, w.sources, eobs, eps0, sig0, prm)
     ev = [torch.cuda.Event(enable_timing=True) for _ in range(2 * n_iter)]
     torch.cuda.synchronize()

@@ -31,6 +31,16 @@ class CGAParams:
     eta2_eps: float = 0.0
     eta2_sig: float = 0.0
 
+    @staticmethod
+    def from_gradient(g_eps, g_sig, h, eps_max, sig_max, step_eps=0.5, step_sig=0.1, p=0.5):
+        """Step sizes and regularisation from the gradient of J at the initial guess (a host
+        read of max|g|): the first update moves eps by at most step_eps and sigma by at most
+        step_sig, and gamma^0 = max|g| / step, so that alpha^1 = 1 / gamma^0 keeps that scale."""
+        h3 = float(h) ** 3
+        gm = [max(float(torch.max(torch.abs(g)).item()) / h3, 1e-30) for g in (g_eps, g_sig)]
+        return CGAParams(gamma_eps=gm[0] / step_eps, gamma_sig=gm[1] / step_sig, p=p, alpha_eps=step_eps / gm[0],
+                         alpha_sig=step_sig / gm[1], eps_max=eps_max, sig_max=sig_max)
+
     def to_c(self):
         c = _lib.CgaParams()
         for f in fields(self):
@@ -52,9 +62,8 @@ class CGA:
         self.obs = obs.contiguous()
         self.eps = torch.as_tensor(eps0, dtype=torch.float32, device=dev).clone().contiguous()
         self.sigma = torch.as_tensor(sig0, dtype=torch.float32, device=dev).clone().contiguous()
-        self.traces = torch.empty(shape, dtype=torch.float32, device=dev)
-        self.g_eps = torch.empty(problem.n_fem, dtype=torch.float64, device=dev)
-        self.g_sig = torch.empty(problem.n_fem, dtype=torch.float64, device=dev)
+        self._shape = shape
+        self.traces = self.g_eps = self.g_sig = None     # allocated by the first solve()
         self.params = params
         self._cp = params.to_c()
         h = ctypes.c_void_p()
@@ -76,15 +85,26 @@ class CGA:
     def solve(self):
         """Step 1 at the current iterate: traces, misfit adjoint, gradient of J."""
         p = self.problem
+        if self.traces is None:
+            dev = self.eps.device
+            self.traces = torch.empty(self._shape, dtype=torch.float32, device=dev)
+            self.g_eps = torch.empty(p.n_fem, dtype=torch.float64, device=dev)
+            self.g_sig = torch.empty(p.n_fem, dtype=torch.float64, device=dev)
         p.set_coefficients(self.eps, self.sigma)
         p.forward(self.sources, save=True, out=self.traces)
         p.adjoint_misfit(self.traces, self.obs)
         p.gradient(out=(self.g_eps, self.g_sig))
 
-    def update(self):
-        """Steps 2-6 from the gradient of the last solve (asynchronous)."""
-        _lib.check(_lib.load().dd_cga_update(self._h, _ptr(self.g_eps), _ptr(self.g_sig), _ptr(self.eps),
-                                             _ptr(self.sigma), _stream()))
+    def update(self, g_eps=None, g_sig=None):
+        """Steps 2-6 from the gradient of the last solve, or from the given gradient arrays
+        of J at the current iterate (float64, FEM nodes); asynchronous."""
+        ge = self.g_eps if g_eps is None else g_eps
+        gs = self.g_sig if g_sig is None else g_sig
+        for t in (ge, gs):
+            if t is None or not (t.is_cuda and t.dtype == torch.float64 and t.is_contiguous() and t.numel() == self.problem.n_fem):
+                raise ValueError("gradients must be contiguous float64 CUDA tensors of n_fem entries")
+        _lib.check(_lib.load().dd_cga_update(self._h, _ptr(ge), _ptr(gs), _ptr(self.eps), _ptr(self.sigma),
+                                             _stream()))
 
     def iterate(self):
         self.solve()

@@ -1,8 +1,9 @@
 """Request loop: continuous batching of reconstruction solves with HBM admission.
 
-Jobs arrive over time.  Each job is a sequence of solves of one problem (forward,
-misfit adjoint, eps/sigma gradient, then a steepest-descent update of eps and sigma on
-the device); the problem's fields stay resident between its solves.  A job is admitted
+Jobs arrive over time.  Each job is a sequence of reconstruction iterations of one
+problem (box "CGA": forward, misfit adjoint, eps/sigma gradient, then the conjugate
+gradient update of eps and sigma on the device); the problem's fields stay resident
+between its solves.  A job is admitted
 when a batch slot is free and its device footprint (dd_footprint_bytes plus its trace,
 observation and gradient buffers) fits in the HBM budget; admitted solves join the
 running batch at the next launch, so work of jobs of different sizes overlaps on the
@@ -20,7 +21,12 @@ import numpy as np
 import torch
 
 from .batch import Batch
+from .cga import CGA, CGAParams
 from .solver import Problem
+
+
+# coefficient box of the reconstruction (eq. epsilon_sigma_constraint)
+EPS_MAX, SIG_MAX = 20.0, 3.0
 
 
 def cell_steps(desc, n_src):
@@ -37,37 +43,36 @@ class _Job:
         self.problem = Problem(w.desc)
         self.eps = torch.tensor(w.eps, dtype=torch.float32, device=dev)
         self.sigma = torch.tensor(w.sigma, dtype=torch.float32, device=dev)
-        self.free = self.eps.new_tensor(_free_mask(w.desc), dtype=torch.bool)
         g = torch.Generator(device=dev)
         g.manual_seed(int(w.seed))
         shape = (len(w.sources), w.desc.n_steps, self.problem.n_det, 3)
         self.obs = 1e-3 * torch.randn(shape, generator=g, device=dev, dtype=torch.float32)
         self.done_iters = 0
+        self.cga = None
         self.problem.set_coefficients(self.eps, self.sigma)
 
     def update(self, g_eps, g_sigma):
-        """Steepest descent on free nodes, kept inside the coefficient constraint."""
-        for x, g, lo in ((self.eps, g_eps, 1.0), (self.sigma, g_sigma, 0.0)):
-            gm = torch.max(torch.abs(g))
-            step = torch.where(gm > 0, 0.05 / gm, torch.zeros_like(gm)).to(torch.float32)
-            x.sub_(torch.where(self.free, step * g.to(torch.float32), torch.zeros_like(x)))
-            x.clamp_(min=lo)
-        self.problem.set_coefficients(self.eps, self.sigma)
+        """CGA steps 2-6 on the device; the run (and its step sizes) starts at the first gradient."""
+        if self.cga is None:
+            w = self.req.workload
+            prm = CGAParams.from_gradient(g_eps, g_sigma, w.desc.h, eps_max=EPS_MAX, sig_max=SIG_MAX)
+            self.cga = CGA(self.problem, w.sources, self.obs, self.eps, self.sigma, prm)
+        self.cga.update(g_eps, g_sigma)
+        self.problem.set_coefficients(self.cga.eps, self.cga.sigma)
 
-
-def _free_mask(desc):
-    c = [int(v) for v in desc.fem_cells]
-    lz, ly, lx = np.meshgrid(np.arange(c[2] + 1), np.arange(c[1] + 1), np.arange(c[0] + 1), indexing="ij")
-    lay = np.minimum(np.minimum(lx, c[0] - lx), np.minimum(ly, c[1] - ly))
-    lay = np.minimum(lay, np.minimum(lz, c[2] - lz))
-    return (lay >= 2).reshape(-1)
+    def close(self):
+        if self.cga is not None:
+            self.cga.close()
+        self.problem.close()
 
 
 def job_footprint(req):
     w = req.workload
     n_src = len(w.sources)
     traces = n_src * int(w.desc.n_steps) * _n_det(w.desc) * 3 * 4
-    return Problem.footprint_bytes(w.desc, n_src) + 2 * traces + 2 * 8 * w.desc.n_fem_nodes()
+    # problem, traces and observations, gradients (FP64), iterate (float32) and the CGA state
+    # (Tikhonov centres float32, directions FP64)
+    return Problem.footprint_bytes(w.desc, n_src) + 2 * traces + (16 + 8 + 24) * w.desc.n_fem_nodes()
 
 
 def _n_det(desc):
@@ -82,8 +87,13 @@ def _summary(lat, solves, makespan, work):
             "latency_p50_s": pct(50), "latency_p99_s": pct(99), "latency_mean_s": float(np.mean(lat)) if lat else None}
 
 
-def serve_batched(requests, max_slots=16, hbm_budget=None, chunk=256, time_fn=time.perf_counter):
-    """Continuous batching: returns a summary dict and per-job records."""
+def _final(job):
+    return {"eps": job.cga.eps.clone(), "sigma": job.cga.sigma.clone()}
+
+
+def serve_batched(requests, max_slots=16, hbm_budget=None, chunk=256, time_fn=time.perf_counter, keep=False):
+    """Continuous batching: returns a summary dict and per-job records (with each job's final
+    eps and sigma when keep is set)."""
     dev = torch.device("cuda", torch.cuda.current_device())
     if hbm_budget is None:
         free, _ = torch.cuda.mem_get_info()
@@ -131,8 +141,8 @@ def serve_batched(requests, max_slots=16, hbm_budget=None, chunk=256, time_fn=ti
                 t_done = time_fn() - t0
                 lat.append(t_done - job.req.arrival)
                 records.append({"rid": job.req.rid, "arrival": job.req.arrival, "done": t_done,
-                                "iterations": job.done_iters})
-                job.problem.close()
+                                "iterations": job.done_iters, **(_final(job) if keep else {})})
+                job.close()
                 in_use -= job.footprint
     torch.cuda.synchronize()
     makespan = time_fn() - t0
@@ -142,7 +152,7 @@ def serve_batched(requests, max_slots=16, hbm_budget=None, chunk=256, time_fn=ti
     return out, records
 
 
-def serve_serial(requests, time_fn=time.perf_counter):
+def serve_serial(requests, time_fn=time.perf_counter, keep=False):
     """One solve at a time, jobs in arrival order, through the single-problem calls."""
     dev = torch.device("cuda", torch.cuda.current_device())
     lat, records = [], []
@@ -163,8 +173,9 @@ def serve_serial(requests, time_fn=time.perf_counter):
             work += cell_steps(req.workload.desc, len(req.workload.sources))
         t_done = time_fn() - t0
         lat.append(t_done - req.arrival)
-        records.append({"rid": req.rid, "arrival": req.arrival, "done": t_done, "iterations": req.iterations})
-        job.problem.close()
+        records.append({"rid": req.rid, "arrival": req.arrival, "done": t_done, "iterations": req.iterations,
+                        **(_final(job) if keep else {})})
+        job.close()
     torch.cuda.synchronize()
     makespan = time_fn() - t0
     return _summary(lat, solves, makespan, work), records

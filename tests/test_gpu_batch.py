@@ -126,8 +126,8 @@ def test_serving_completes_and_respects_budget():
                                   iterations=(2, 3))
     fps = sorted(serving.job_footprint(r) for r in reqs)
     budget = fps[-1] + fps[-2]          # the two largest jobs fit at once, never all six
-    s_b, rec_b = serving.serve_batched(reqs, max_slots=4, hbm_budget=budget, chunk=16)
-    s_s, rec_s = serving.serve_serial(reqs)
+    s_b, rec_b = serving.serve_batched(reqs, max_slots=4, hbm_budget=budget, chunk=16, keep=True)
+    s_s, rec_s = serving.serve_serial(reqs, keep=True)
     print(f"[gpu] serving batched {s_b}", flush=True)
     print(f"[gpu] serving serial  {s_s}", flush=True)
     assert s_b["jobs"] == len(reqs) == s_s["jobs"]
@@ -135,3 +135,11 @@ def test_serving_completes_and_respects_budget():
     assert all(r["done"] >= r["arrival"] for r in rec_b + rec_s)
     assert s_b["peak_admitted_bytes"] <= budget
     assert 2 <= s_b["peak_concurrent_jobs"] < len(reqs)
+    # both servers run the same CGA iterations per job: the same reconstruction (the
+    # gradients' FP64 sums differ only in order)
+    by_rid = {r["rid"]: r for r in rec_s}
+    for r in rec_b:
+        for f, base in (("eps", 1.0), ("sigma", 0.0)):
+            a, b = (x[f].double() - base for x in (r, by_rid[r["rid"]]))
+            assert float(torch.linalg.norm(b)) > 0
+            assert float(torch.linalg.norm(a - b)) <= 1e-4 * float(torch.linalg.norm(b)), (r["rid"], f)

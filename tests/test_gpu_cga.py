@@ -68,9 +68,7 @@ def _run_update_parity(desc, params, n_updates=4, seed=1, zero_sig_from=None):
     coef = {"eps": eps0.astype(np.float64), "sig": sig0.astype(np.float64)}
     c0 = {"eps": eps0.astype(np.float64), "sig": sig0.astype(np.float64)}
     for m, (ge, gs) in enumerate(grads):
-        c.g_eps.copy_(torch.from_numpy(ge))
-        c.g_sig.copy_(torch.from_numpy(gs))
-        c.update()
+        c.update(torch.from_numpy(ge).cuda(), torch.from_numpy(gs).cuda())
         info = c.info()
         new, oi = cga_update(st, {"eps": ge, "sig": gs}, coef, c0, w, free)
         coef = {f: new[f].astype(np.float32).astype(np.float64) for f in new}   # float32 iterate, as the product
