@@ -35,9 +35,15 @@ TOP = 1
 
 
 class Discretization:
-    def __init__(self, desc, fd_only: bool = False):
+    def __init__(self, desc, fd_only: bool = False, divdiv_form: str = "R1"):
+        """divdiv_form: "R1" (the scheme: the nodal product (eps - 1) E inside the element
+        divergence, eq. forward_prob) or "R2" (the element mean of eps - 1 outside it, a
+        symmetric variant for which eq. gradeps' div-div term is the exact gradient)."""
+        if divdiv_form not in ("R1", "R2"):
+            raise ValueError("divdiv_form must be R1 or R2")
         self.desc = desc
         self.fd_only = fd_only
+        self.divdiv_form = divdiv_form
         nvec = np.array([int(v) for v in desc.n_outer])
         self.nvec = nvec
         self.N = int(np.prod(nvec))
@@ -174,21 +180,33 @@ class Discretization:
             out[:, c] = np.bincount(idx, weights=contrib[:, :, c].ravel(), minlength=self.n_fem)
         return out
 
+    def element_mean_eps_minus_one(self):
+        """(eps - 1) averaged over the four vertices of each tetrahedron (form R2)."""
+        return (self.eps - 1.0)[self.tets].mean(axis=1)
+
     def divdiv(self, E):
-        """(A_dd E)_i = sum_K |K| grad(phi_i) div_K((eps - 1) E), FEM-owned rows only."""
-        w = (self.eps - 1.0)[:, None] * E[self.fem_grid]
-        div = np.einsum("tac,tac->t", self.grad, w[self.tets])
+        """FEM-owned rows only.  R1: (A_dd E)_i = sum_K |K| grad(phi_i) div_K((eps - 1) E);
+        R2: (A_dd E)_i = sum_K |K| (mean_K eps - 1) grad(phi_i) div_K(E)."""
+        if self.divdiv_form == "R1":
+            w = (self.eps - 1.0)[:, None] * E[self.fem_grid]
+            div = np.einsum("tac,tac->t", self.grad, w[self.tets])
+        else:
+            div = self.element_mean_eps_minus_one() * np.einsum("tac,tac->t", self.grad, E[self.fem_grid][self.tets])
         acc = self._scatter((self.vol * div)[:, None, None] * self.grad)
         acc[~self.fem_owned] = 0.0
         return acc
 
     def divdiv_T(self, L):
-        """Transpose of divdiv: (eps_j - 1) sum_K |K| grad(phi_j) div_K(L restricted to FEM rows)."""
+        """Transpose of divdiv (L restricted to the FEM rows).  R1: (eps_j - 1) sum_K |K|
+        grad(phi_j) div_K(L); R2: sum_K |K| (mean_K eps - 1) grad(phi_j) div_K(L)."""
         Lf = L[self.fem_grid].copy()
         Lf[~self.fem_owned] = 0.0
         div = np.einsum("tac,tac->t", self.grad, Lf[self.tets])
-        acc = self._scatter((self.vol * div)[:, None, None] * self.grad)
-        return (self.eps - 1.0)[:, None] * acc
+        if self.divdiv_form == "R1":
+            acc = self._scatter((self.vol * div)[:, None, None] * self.grad)
+            return (self.eps - 1.0)[:, None] * acc
+        div = self.element_mean_eps_minus_one() * div
+        return self._scatter((self.vol * div)[:, None, None] * self.grad)
 
     def apply_A(self, E):
         out = self.K @ E

@@ -21,6 +21,12 @@ taken exactly on the discrete scheme):
     dJ/dsigma_i = sum_{n=0}^{N_t-1} m_i lambda^n_i . (E^{n+1} - E^{n-1})_i / (2 dt),
 on free FEM nodes (layer >= 2), zero elsewhere.  The f_1 term of eq. gradeps
 vanishes because the model problem starts from rest.
+
+The paper's own gradient formula (eq. gradeps with div((eps~) E) ~ eps~ div E) replaces
+the div-div term by
+    sum_{n} sum_{K ∋ i} (|K| / 4) div_K(lambda^n) div_K(E^n)
+(|K|/4 = the integral of phi_i over K); it is returned as a variant.  For the symmetric
+div-div form R2 it is the exact derivative, and the R2 discretisation uses it as such.
 """
 
 from __future__ import annotations
@@ -125,6 +131,7 @@ def adjoint_gradient(d, cot, fwd, keep_lambda=False):
     lam_cur = np.zeros((d.N, 3))             # lambda^k
     g_mass = np.zeros(d.n_fem)
     g_dd = np.zeros(d.n_fem)
+    g_dd_paper = np.zeros(d.n_fem)
     g_sig = np.zeros(d.n_fem)
     lam_f = np.zeros((nt + 1, d.n_fem, 3))   # lambda^n on FEM nodes, n = 0..N_t
     lams = np.zeros((nt, d.N, 3)) if keep_lambda else None
@@ -147,6 +154,10 @@ def adjoint_gradient(d, cot, fwd, keep_lambda=False):
         div = np.einsum("tac,tac->t", d.grad, lr[d.tets])
         ge = np.einsum("tac,tac->ta", d.grad, e_c[d.tets])
         g_dd += np.bincount(d.tets.ravel(), weights=((d.vol * div)[:, None] * ge).ravel(), minlength=d.n_fem)
+        # paper formula: sum_K (|K| / 4) div_K(lambda^n) div_K(E^n) on the four vertices of K
+        div_e = np.einsum("tac,tac->t", d.grad, e_c[d.tets])
+        g_dd_paper += np.bincount(d.tets.ravel(), weights=np.repeat(0.25 * d.vol * div * div_e, 4),
+                                  minlength=d.n_fem)
         if keep_lambda:
             lams[n] = lam_prev
         lam_next, lam_cur = lam_cur, lam_prev
@@ -155,10 +166,14 @@ def adjoint_gradient(d, cot, fwd, keep_lambda=False):
     for n in range(nt):
         g_mass_sbp -= m * np.sum((lam_f[n + 1] - lam_f[n]) * (Eh[n + 2] - Eh[n + 1]), axis=1) / dt ** 2
     free = d.fem_free
+    g_eps_paper = np.where(free, g_mass + g_dd_paper, 0.0)
+    if getattr(d, "divdiv_form", "R1") == "R2":
+        g_dd = g_dd_paper           # exact for the element-mean form
     g_eps = np.where(free, g_mass + g_dd, 0.0)
     g_sigma = np.where(free, g_sig, 0.0)
     out = dict(g_eps=g_eps, g_sigma=g_sigma, g_mass=np.where(free, g_mass, 0.0),
-               g_mass_sbp=np.where(free, g_mass_sbp, 0.0), g_divdiv=np.where(free, g_dd, 0.0))
+               g_mass_sbp=np.where(free, g_mass_sbp, 0.0), g_divdiv=np.where(free, g_dd, 0.0),
+               g_eps_paper=g_eps_paper)
     if keep_lambda:
         out["lambda"] = lams
     return out
