@@ -149,6 +149,22 @@ int dd_gradient(dd_problem* p, double* g_eps_dev, double* g_sigma_dev, void* str
  * requirements and results as dd_adjoint. */
 int dd_adjoint_misfit(dd_problem* p, const float* traces_dev, const float* obs_dev, void* stream);
 
+/* Paper-formula gradient variant.  eq. gradeps writes the div-div part of g_eps as the
+ * time integral of div(lambda) div(E), having replaced div(eps~ E) by eps~ div(E); on the
+ * discrete scheme that term is sum_k sum_{K containing i} (|K|/4) div_K(lambda^k) div_K(E^k)
+ * in place of the exact sum_k sum_K |K| div_K(lambda^k) (grad phi_i . E^k_i).  (It is the
+ * exact derivative of a scheme whose div-div term carries the element mean of eps - 1
+ * outside the divergence, not of this one.)
+ * dd_paper_gradient_enable(p, 1): the following dd_adjoint / dd_adjoint_misfit calls also
+ * accumulate the difference of the two terms (two small extra launches per adjoint step;
+ * FEM-node sized buffers allocated on the first call, which synchronises the device);
+ * 0 switches it off.  DD_ERR_UNSUPPORTED when FD and FEM run on two streams.  Batched jobs
+ * never accumulate it.
+ * dd_gradient_paper: after such an adjoint, the variant's g_eps and the (unchanged) g_sigma,
+ * same layout as dd_gradient; DD_ERR_STATE if the last adjoint did not accumulate it. */
+int dd_paper_gradient_enable(dd_problem* p, int32_t on);
+int dd_gradient_paper(dd_problem* p, double* g_eps_dev, double* g_sigma_dev, void* stream);
+
 /* ---- Conjugate gradient reconstruction (box "CGA") -----------------------------------
  * One CGA iteration m is: dd_set_coefficients(eps^m, sigma^m), dd_forward(save),
  * dd_adjoint_misfit, dd_gradient (step 1), then dd_cga_update (steps 2-6), which turns

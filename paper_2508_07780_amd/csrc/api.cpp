@@ -13,6 +13,7 @@
 #include <new>
 
 #include "cga.hpp"
+#include "paper_grad.hpp"
 #include "dd_common.hpp"
 
 using namespace dd;
@@ -59,6 +60,11 @@ struct dd_problem {
   double *g_eps = nullptr, *g_sig = nullptr;
   bool have_grad = false;
   bool adj_obs = false;   // the last adjoint formed its cotangent as traces - observations
+  // paper-formula gradient variant: FEM-node -> owned id map, per-cell divergences, FP64 sum
+  bool pg_on = false, have_pg = false;
+  int* api_own = nullptr;
+  float2* pg_cells = nullptr;
+  double* pg_acc = nullptr;
   std::string err;
   std::vector<void*> allocs;
   // kernel timing: event pairs around each step launch, per launch kind
@@ -498,6 +504,9 @@ int run_adjoint(dd_problem* p, int s, const float* cot, const float* obs, hipStr
         prof_end(p, DD_PROF_FEM_ADJ, ps, sf);
         step_barrier(p, st);
       }
+      // lambda^k (ea.X_in) is overwritten two steps later, on the same stream
+      if (p->pg_on)
+        launch_paper_grad_step(ea.X_in, ea.wE, p->n_own, p->api_own, p->fs, p->d.h, p->pg_cells, p->pg_acc, st);
     }
   }
   join_streams(p, st);
@@ -703,6 +712,7 @@ int dd_set_coefficients(dd_problem* p, const float* eps_dev, const float* sigma_
   if (hipStreamSynchronize(st) != hipSuccess) return fail(p, DD_ERR_HIP, "stream synchronize failed");
   p->saved = false;
   p->have_grad = false;
+  p->have_pg = false;
   return DD_OK;
 }
 
@@ -717,6 +727,7 @@ int dd_forward(dd_problem* p, const dd_source* src, int32_t n_src, float* traces
   hipStream_t st = (hipStream_t)stream;
   p->saved = false;
   p->have_grad = false;
+  p->have_pg = false;
   if (save) {
     int rc = ensure_saved_storage(p, n_src);
     if (rc) return rc;
@@ -736,12 +747,14 @@ namespace {
 int adjoint_all(dd_problem* p, const float* cot, const float* obs, hipStream_t st) {
   launch_fill_f64(p->g_eps, p->n_own, 0.0, st);
   launch_fill_f64(p->g_sig, p->n_own, 0.0, st);
+  if (p->pg_on) launch_fill_f64(p->pg_acc, p->n_fem, 0.0, st);
   p->adj_obs = obs != nullptr;
   for (int s = 0; s < p->saved_n_src; ++s) {
     int rc = run_adjoint(p, s, cot, obs, st);
     if (rc) return rc;
   }
   p->have_grad = true;
+  p->have_pg = p->pg_on;
   return DD_OK;
 }
 }  // namespace
@@ -768,6 +781,41 @@ int dd_gradient(dd_problem* p, double* g_eps_dev, double* g_sigma_dev, void* str
   launch_fill_f64(g_eps_dev, p->n_fem, 0.0, st);
   launch_fill_f64(g_sigma_dev, p->n_fem, 0.0, st);
   launch_gradient_out(p->g_eps, p->g_sig, p->own_api, p->own_grid, p->n_own, g_eps_dev, g_sigma_dev, st);
+  return check_launch(p);
+}
+
+int dd_paper_gradient_enable(dd_problem* p, int32_t on) {
+  if (!p) return DD_ERR_INVALID_ARG;
+  if (!on) {
+    p->pg_on = false;
+    return DD_OK;
+  }
+  if (p->overlap) return fail(p, DD_ERR_UNSUPPORTED, "the paper-formula gradient needs the single-stream step order");
+  if (!p->api_own) {
+    const int64_t n_cells = std::max<int64_t>(
+        1, (int64_t)std::max(p->fs[0] - 3, 0) * std::max(p->fs[1] - 3, 0) * std::max(p->fs[2] - 3, 0));
+    int rc = dalloc(p, &p->api_own, (size_t)p->n_fem);
+    if (!rc) rc = dalloc(p, &p->pg_cells, (size_t)(6 * n_cells));
+    if (!rc) rc = dalloc(p, &p->pg_acc, (size_t)p->n_fem);
+    if (rc) return rc;
+    launch_invert_own(p->own_api, p->n_own, p->n_fem, p->api_own, nullptr);
+    if (int rc2 = check_launch(p)) return rc2;
+    if (hipStreamSynchronize(nullptr) != hipSuccess) return fail(p, DD_ERR_HIP, "stream synchronize failed");
+  }
+  p->pg_on = true;
+  return DD_OK;
+}
+
+int dd_gradient_paper(dd_problem* p, double* g_eps_dev, double* g_sigma_dev, void* stream) {
+  if (!p) return DD_ERR_INVALID_ARG;
+  if (!g_eps_dev || !g_sigma_dev) return fail(p, DD_ERR_INVALID_ARG, "null gradient buffer");
+  if (!p->have_grad || !p->have_pg)
+    return fail(p, DD_ERR_STATE, "dd_gradient_paper needs a preceding dd_adjoint with the variant enabled");
+  hipStream_t st = (hipStream_t)stream;
+  launch_fill_f64(g_eps_dev, p->n_fem, 0.0, st);
+  launch_fill_f64(g_sigma_dev, p->n_fem, 0.0, st);
+  launch_gradient_out(p->g_eps, p->g_sig, p->own_api, p->own_grid, p->n_own, g_eps_dev, g_sigma_dev, st);
+  launch_add_free(p->pg_acc, p->fs, g_eps_dev, st);
   return check_launch(p);
 }
 
@@ -1157,11 +1205,13 @@ int dd_batch_submit(dd_batch* b, dd_problem* p, const dd_source* src, int32_t n_
   j.traces = traces_dev;
   j.obs = obs_dev;
   p->adj_obs = obs_dev != nullptr;
+  p->have_pg = false;
   j.g_eps = g_eps_dev;
   j.g_sig = g_sigma_dev;
   j.id = b->next_id++;
   p->saved = false;
   p->have_grad = false;
+  p->have_pg = false;
   b->jobs.push_back(j);
   if (job_out) *job_out = j.id;
   return DD_OK;

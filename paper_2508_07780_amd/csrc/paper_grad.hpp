@@ -1,0 +1,18 @@
+// Paper-formula gradient variant (eq. gradeps with div(eps~ E) ~ eps~ div E): launches.
+#pragma once
+
+#include "dd_common.hpp"
+
+namespace dd {
+
+// api_own[i] = owned internal id of FEM node i, or -1 (built from own_api).
+void launch_invert_own(const int* own_api, int64_t n_own, int64_t n_fem, int* api_own, hipStream_t s);
+// One adjoint step's contribution: lam = lambda^k, E = forward E^k (both [3][n_own], owned
+// internal order).  acc[i] (FEM-node index, free nodes) += the paper term minus the exact
+// (R1) div-div term of node i.  cellbuf: 6 float2 per interior cell ((fs-3)^3 cells).
+void launch_paper_grad_step(const float* lam, const float* E, int64_t n_own, const int* api_own, const int fs[3],
+                            double h, float2* cellbuf, double* acc, hipStream_t s);
+// out_eps[i] += acc[i] on free nodes.
+void launch_add_free(const double* acc, const int fs[3], double* out_eps, hipStream_t s);
+
+}  // namespace dd

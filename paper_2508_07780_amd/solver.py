@@ -124,6 +124,18 @@ class Problem:
         _lib.check(_lib.load().dd_gradient(self._h, _ptr(ge), _ptr(gs), _stream()), self._h)
         return ge, gs
 
+    def paper_gradient(self, on=True):
+        """Accumulate the paper-formula gradient variant in the following adjoints."""
+        _lib.check(_lib.load().dd_paper_gradient_enable(self._h, 1 if on else 0), self._h)
+
+    def gradient_paper(self):
+        """(g_eps of the paper formula, g_sigma) after an adjoint with the variant on."""
+        dev = torch.device("cuda", torch.cuda.current_device())
+        ge = torch.empty(self.n_fem, dtype=torch.float64, device=dev)
+        gs = torch.empty(self.n_fem, dtype=torch.float64, device=dev)
+        _lib.check(_lib.load().dd_gradient_paper(self._h, _ptr(ge), _ptr(gs), _stream()), self._h)
+        return ge, gs
+
     # ---- kernel timing ---------------------------------------------------------------------
     def profile(self, stride=1):
         """Time every `stride`-th step launch with HIP events (0 switches timing off)."""
