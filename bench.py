@@ -217,6 +217,27 @@ def c3_autograd(reps=2):
             "gradient_finite": finite, "setup_s": round(t_setup, 2)}
 
 
+def paper_gradient_measure(prob, solve, eobs, t_exact):
+    """The paper-formula gradient variant (eq. gradeps with grad(eps~).E dropped) on the main
+    workload's solve: its cost on top of the exact gradient and how far it is from it."""
+    import torch
+    prob.profile(0)
+    prob.paper_gradient(True)
+    solve()
+    torch.cuda.synchronize()
+    t0 = time.perf_counter()
+    ge, gs = solve()
+    torch.cuda.synchronize()
+    t = time.perf_counter() - t0
+    gp, _ = prob.gradient_paper()
+    prob.paper_gradient(False)
+    ge, gp = ge.double(), gp.double()
+    rel = float(torch.linalg.norm(gp - ge) / torch.linalg.norm(ge))
+    cos = float(torch.dot(gp, ge) / (torch.linalg.norm(gp) * torch.linalg.norm(ge)))
+    return {"solve_ms": round(t * 1e3, 2), "extra_ms": round((t - t_exact) * 1e3, 2),
+            "rel_l2_vs_exact": round(rel, 4), "cosine_vs_exact": round(cos, 4)}
+
+
 def cga_measure(prob, w, eobs, n_iter):
     """Reconstruction iterations (box "CGA") on the main workload from the paper's initial
     guess eps = 1, sigma = 0: each iteration is a solve (forward with saving, misfit adjoint,
@@ -318,6 +339,8 @@ def main():
     ap.add_argument("--probe-steps", type=int, default=300, help="time steps of the probe")
     ap.add_argument("--c3", type=int, default=1, help="0 skips the 192^3 autograd measurement")
     ap.add_argument("--cga", type=int, default=3, help="CGA iterations to time on the main workload (0 skips)")
+    ap.add_argument("--paper-gradient", type=int, default=1,
+                    help="0 skips the paper-formula gradient variant's measurement")
     ap.add_argument("--profile-stride", type=int, default=64,
                     help="time every k-th step launch with HIP events (k >= 16 barely perturbs the run)")
     args = ap.parse_args()
@@ -428,6 +451,8 @@ def main():
                     for k, v in kern.items()},
         "gradient_finite": finite,
     }
+    if args.paper_gradient:
+        out["paper_formula_gradient"] = paper_gradient_measure(prob, solve, eobs, elapsed / args.steps)
     if args.cga:
         out["cga"] = cga_measure(prob, w, eobs, args.cga)
     del prob

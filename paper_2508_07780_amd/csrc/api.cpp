@@ -60,10 +60,9 @@ struct dd_problem {
   double *g_eps = nullptr, *g_sig = nullptr;
   bool have_grad = false;
   bool adj_obs = false;   // the last adjoint formed its cotangent as traces - observations
-  // paper-formula gradient variant: FEM-node -> owned id map, per-cell divergences, FP64 sum
+  // paper-formula gradient variant: FEM-node -> owned id map, FP64 sum
   bool pg_on = false, have_pg = false;
   int* api_own = nullptr;
-  float2* pg_cells = nullptr;
   double* pg_acc = nullptr;
   std::string err;
   std::vector<void*> allocs;
@@ -506,7 +505,7 @@ int run_adjoint(dd_problem* p, int s, const float* cot, const float* obs, hipStr
       }
       // lambda^k (ea.X_in) is overwritten two steps later, on the same stream
       if (p->pg_on)
-        launch_paper_grad_step(ea.X_in, ea.wE, p->n_own, p->api_own, p->fs, p->d.h, p->pg_cells, p->pg_acc, st);
+        launch_paper_grad_step(ea.X_in, ea.wE, p->n_own, p->api_own, p->fs, p->d.h, p->pg_acc, st);
     }
   }
   join_streams(p, st);
@@ -792,10 +791,7 @@ int dd_paper_gradient_enable(dd_problem* p, int32_t on) {
   }
   if (p->overlap) return fail(p, DD_ERR_UNSUPPORTED, "the paper-formula gradient needs the single-stream step order");
   if (!p->api_own) {
-    const int64_t n_cells = std::max<int64_t>(
-        1, (int64_t)std::max(p->fs[0] - 3, 0) * std::max(p->fs[1] - 3, 0) * std::max(p->fs[2] - 3, 0));
     int rc = dalloc(p, &p->api_own, (size_t)p->n_fem);
-    if (!rc) rc = dalloc(p, &p->pg_cells, (size_t)(6 * n_cells));
     if (!rc) rc = dalloc(p, &p->pg_acc, (size_t)p->n_fem);
     if (rc) return rc;
     launch_invert_own(p->own_api, p->n_own, p->n_fem, p->api_own, nullptr);

@@ -18,9 +18,11 @@
 // A free node (layer >= 2) only touches cells whose corners are all FEM-owned, so lambda
 // needs no restriction and only those interior cells are visited.
 //
-// Pass 1 (one thread per interior cell) stores (dl, de) of its six tetrahedra; pass 2 (one
-// thread per free node) gathers its 24 tetrahedra over the 8 cells around it and adds to an
-// FP64 accumulator: no atomics, a fixed order.
+// One launch per adjoint step: a block takes an 8 x 8 x 4 tile of free nodes, stages
+// lambda^k and E^k of the 10 x 10 x 6 nodes around it in LDS, computes (dl, de) of the six
+// tetrahedra of the 9 x 9 x 5 cells the tile touches into LDS, and each thread then gathers
+// its node's 24 tetrahedra over the 8 cells around it and adds to an FP64 accumulator: no
+// atomics, a fixed order.
 #include "paper_grad.hpp"
 
 namespace dd {
@@ -39,75 +41,75 @@ __global__ void fill_i32_kernel(int* p, int64_t n, int v) {
   for (int64_t i = (int64_t)blockIdx.x * blockDim.x + threadIdx.x; i < n; i += (int64_t)gridDim.x * blockDim.x) p[i] = v;
 }
 
-__global__ __launch_bounds__(256) void pg_cell_kernel(const float* __restrict__ lam, const float* __restrict__ E,
-                                                      int64_t n_own, const int* __restrict__ api_own, int fsx,
-                                                      int fsy, int fsz, float2* __restrict__ cellbuf) {
-  const int ncx = fsx - 3, ncy = fsy - 3, ncz = fsz - 3;
-  const int64_t n_cells = (int64_t)ncx * ncy * ncz;
-  for (int64_t ci = (int64_t)blockIdx.x * blockDim.x + threadIdx.x; ci < n_cells;
-       ci += (int64_t)gridDim.x * blockDim.x) {
-    const int cx = 1 + (int)(ci % ncx);
-    const int cy = 1 + (int)((ci / ncx) % ncy);
-    const int cz = 1 + (int)(ci / ((int64_t)ncx * ncy));
-    float L[8][3], X[8][3];
-#pragma unroll
-    for (int o = 0; o < 8; ++o) {
-      const int64_t api = (int64_t)(cx + (o & 1)) + fsx * ((int64_t)(cy + ((o >> 1) & 1)) + (int64_t)fsy * (cz + (o >> 2)));
-      const int64_t id = api_own[api];
-#pragma unroll
-      for (int c = 0; c < 3; ++c) {
-        L[o][c] = lam[c * n_own + id];
-        X[o][c] = E[c * n_own + id];
-      }
-    }
-#pragma unroll
-    for (int t = 0; t < 6; ++t) {
-      const int a = kPerm[t][0], b = kPerm[t][1], c = kPerm[t][2];
-      const int v1 = 1 << a, v2 = v1 | (1 << b);
-      const float dl = (L[v1][a] - L[0][a]) + (L[v2][b] - L[v1][b]) + (L[7][c] - L[v2][c]);
-      const float de = (X[v1][a] - X[0][a]) + (X[v2][b] - X[v1][b]) + (X[7][c] - X[v2][c]);
-      cellbuf[ci * 6 + t] = make_float2(dl, de);
-    }
-  }
-}
+constexpr int PG_TX = 8, PG_TY = 8, PG_TZ = 4;                 // free nodes per block
+constexpr int PG_NX = PG_TX + 2, PG_NY = PG_TY + 2, PG_NZ = PG_TZ + 2;  // staged nodes
+constexpr int PG_CX = PG_TX + 1, PG_CY = PG_TY + 1, PG_CZ = PG_TZ + 1;  // cells touched
 
-__global__ __launch_bounds__(256) void pg_node_kernel(const float* __restrict__ E, int64_t n_own,
-                                                      const int* __restrict__ api_own, int fsx, int fsy, int fsz,
-                                                      double h, const float2* __restrict__ cellbuf,
-                                                      double* __restrict__ acc) {
-  // free nodes: lattice coordinates in [2, fs - 3] per axis
-  const int nx = fsx - 4, ny = fsy - 4, nz = fsz - 4;
-  const int ncx = fsx - 3, ncy = fsy - 3;
-  const int64_t n_free = (int64_t)nx * ny * nz;
-  for (int64_t q = (int64_t)blockIdx.x * blockDim.x + threadIdx.x; q < n_free; q += (int64_t)gridDim.x * blockDim.x) {
-    const int lx = 2 + (int)(q % nx);
-    const int ly = 2 + (int)((q / nx) % ny);
-    const int lz = 2 + (int)(q / ((int64_t)nx * ny));
-    const int64_t api = (int64_t)lx + fsx * ((int64_t)ly + (int64_t)fsy * lz);
-    const int64_t id = api_own[api];
-    const float Ei[3] = {E[id], E[n_own + id], E[2 * n_own + id]};
-    double s = 0.0;
+__global__ __launch_bounds__(256) void pg_step_kernel(const float* __restrict__ lam, const float* __restrict__ E,
+                                                      int64_t n_own, const int* __restrict__ api_own, int fsx,
+                                                      int fsy, int fsz, double h, double* __restrict__ acc) {
+  __shared__ float sl[3][PG_NZ][PG_NY][PG_NX];
+  __shared__ float se[3][PG_NZ][PG_NY][PG_NX];
+  __shared__ float2 sc[6][PG_CZ][PG_CY][PG_CX];
+  // free nodes: lattice coordinates 2 .. fs - 3 per axis
+  const int nfx = fsx - 4, nfy = fsy - 4, nfz = fsz - 4;
+  const int tbx = (nfx + PG_TX - 1) / PG_TX, tby = (nfy + PG_TY - 1) / PG_TY;
+  const int b = blockIdx.x;
+  const int x0 = 2 + (b % tbx) * PG_TX, y0 = 2 + ((b / tbx) % tby) * PG_TY, z0 = 2 + (b / (tbx * tby)) * PG_TZ;
+  const int t = threadIdx.x;
+  // stage nodes x0-1 .. x0+TX (clamped to the last owned node; values past it are unused)
+  for (int i = t; i < PG_NX * PG_NY * PG_NZ; i += 256) {
+    const int ix = i % PG_NX, iy = (i / PG_NX) % PG_NY, iz = i / (PG_NX * PG_NY);
+    const int gx = min(x0 - 1 + ix, fsx - 2), gy = min(y0 - 1 + iy, fsy - 2), gz = min(z0 - 1 + iz, fsz - 2);
+    const int64_t id = api_own[(int64_t)gx + fsx * ((int64_t)gy + (int64_t)fsy * gz)];
 #pragma unroll
-    for (int o = 0; o < 8; ++o) {
-      // the cell whose corner o is this node; its interior index
-      const int cx = lx - (o & 1), cy = ly - ((o >> 1) & 1), cz = lz - (o >> 2);
-      const int64_t ci = (int64_t)(cx - 1) + ncx * ((int64_t)(cy - 1) + (int64_t)ncy * (cz - 1));
-#pragma unroll
-      for (int t = 0; t < 6; ++t) {
-        const int a = kPerm[t][0], b = kPerm[t][1], c = kPerm[t][2];
-        const int v1 = 1 << a, v2 = v1 | (1 << b);
-        float gE;   // h grad phi . E_i for the vertex this node is
-        if (o == 0) gE = -Ei[a];
-        else if (o == v1) gE = Ei[a] - Ei[b];
-        else if (o == v2) gE = Ei[b] - Ei[c];
-        else if (o == 7) gE = Ei[c];
-        else continue;
-        const float2 v = cellbuf[ci * 6 + t];
-        s += (double)v.x * ((double)v.y - 4.0 * (double)gE);
-      }
+    for (int c = 0; c < 3; ++c) {
+      sl[c][iz][iy][ix] = lam[c * n_own + id];
+      se[c][iz][iy][ix] = E[c * n_own + id];
     }
-    acc[api] += s * (h / 24.0);
   }
+  __syncthreads();
+  // cells with lower corner x0-1+cx ...: corner (cx + ox) in the staged box
+  for (int i = t; i < PG_CX * PG_CY * PG_CZ; i += 256) {
+    const int cx = i % PG_CX, cy = (i / PG_CX) % PG_CY, cz = i / (PG_CX * PG_CY);
+#pragma unroll
+    for (int k = 0; k < 6; ++k) {
+      const int a = kPerm[k][0], bb = kPerm[k][1], c = kPerm[k][2];
+      const int v1 = 1 << a, v2 = v1 | (1 << bb);
+#define PG_AT(arr, comp, o) arr[comp][cz + ((o) >> 2)][cy + (((o) >> 1) & 1)][cx + ((o) & 1)]
+      const float dl = (PG_AT(sl, a, v1) - PG_AT(sl, a, 0)) + (PG_AT(sl, bb, v2) - PG_AT(sl, bb, v1)) +
+                       (PG_AT(sl, c, 7) - PG_AT(sl, c, v2));
+      const float de = (PG_AT(se, a, v1) - PG_AT(se, a, 0)) + (PG_AT(se, bb, v2) - PG_AT(se, bb, v1)) +
+                       (PG_AT(se, c, 7) - PG_AT(se, c, v2));
+#undef PG_AT
+      sc[k][cz][cy][cx] = make_float2(dl, de);
+    }
+  }
+  __syncthreads();
+  const int tx = t % PG_TX, ty = (t / PG_TX) % PG_TY, tz = t / (PG_TX * PG_TY);
+  const int lx = x0 + tx, ly = y0 + ty, lz = z0 + tz;
+  if (lx > fsx - 3 || ly > fsy - 3 || lz > fsz - 3) return;
+  const float Ei[3] = {se[0][tz + 1][ty + 1][tx + 1], se[1][tz + 1][ty + 1][tx + 1], se[2][tz + 1][ty + 1][tx + 1]};
+  double s = 0.0;
+#pragma unroll
+  for (int o = 0; o < 8; ++o) {
+    // the cell whose corner o is this node: staged cell (tx + 1 - ox, ...)
+    const int cx = tx + 1 - (o & 1), cy = ty + 1 - ((o >> 1) & 1), cz = tz + 1 - (o >> 2);
+#pragma unroll
+    for (int k = 0; k < 6; ++k) {
+      const int a = kPerm[k][0], bb = kPerm[k][1], c = kPerm[k][2];
+      const int v1 = 1 << a, v2 = v1 | (1 << bb);
+      float gE;   // h grad phi . E_i for the vertex this node is
+      if (o == 0) gE = -Ei[a];
+      else if (o == v1) gE = Ei[a] - Ei[bb];
+      else if (o == v2) gE = Ei[bb] - Ei[c];
+      else if (o == 7) gE = Ei[c];
+      else continue;
+      const float2 v = sc[k][cz][cy][cx];
+      s += (double)v.x * ((double)v.y - 4.0 * (double)gE);
+    }
+  }
+  acc[(int64_t)lx + fsx * ((int64_t)ly + (int64_t)fsy * lz)] += s * (h / 24.0);
 }
 
 __global__ void add_free_kernel(const double* __restrict__ acc, int fsx, int fsy, int fsz, double* __restrict__ out) {
@@ -129,14 +131,12 @@ void launch_invert_own(const int* own_api, int64_t n_own, int64_t n_fem, int* ap
 }
 
 void launch_paper_grad_step(const float* lam, const float* E, int64_t n_own, const int* api_own, const int fs[3],
-                            double h, float2* cellbuf, double* acc, hipStream_t s) {
+                            double h, double* acc, hipStream_t s) {
   if (fs[0] < 5 || fs[1] < 5 || fs[2] < 5) return;   // no free node
-  const int64_t n_cells = (int64_t)(fs[0] - 3) * (fs[1] - 3) * (fs[2] - 3);
-  const int64_t n_free = (int64_t)(fs[0] - 4) * (fs[1] - 4) * (fs[2] - 4);
-  hipLaunchKernelGGL(pg_cell_kernel, dim3(blocks_for(n_cells)), dim3(256), 0, s, lam, E, n_own, api_own, fs[0], fs[1],
-                     fs[2], cellbuf);
-  hipLaunchKernelGGL(pg_node_kernel, dim3(blocks_for(n_free)), dim3(256), 0, s, E, n_own, api_own, fs[0], fs[1], fs[2],
-                     h, cellbuf, acc);
+  const int tbx = (fs[0] - 4 + PG_TX - 1) / PG_TX, tby = (fs[1] - 4 + PG_TY - 1) / PG_TY;
+  const int tbz = (fs[2] - 4 + PG_TZ - 1) / PG_TZ;
+  hipLaunchKernelGGL(pg_step_kernel, dim3(tbx * tby * tbz), dim3(256), 0, s, lam, E, n_own, api_own, fs[0], fs[1],
+                     fs[2], h, acc);
 }
 
 void launch_add_free(const double* acc, const int fs[3], double* out_eps, hipStream_t s) {

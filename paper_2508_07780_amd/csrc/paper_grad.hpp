@@ -9,9 +9,9 @@ namespace dd {
 void launch_invert_own(const int* own_api, int64_t n_own, int64_t n_fem, int* api_own, hipStream_t s);
 // One adjoint step's contribution: lam = lambda^k, E = forward E^k (both [3][n_own], owned
 // internal order).  acc[i] (FEM-node index, free nodes) += the paper term minus the exact
-// (R1) div-div term of node i.  cellbuf: 6 float2 per interior cell ((fs-3)^3 cells).
+// (R1) div-div term of node i.
 void launch_paper_grad_step(const float* lam, const float* E, int64_t n_own, const int* api_own, const int fs[3],
-                            double h, float2* cellbuf, double* acc, hipStream_t s);
+                            double h, double* acc, hipStream_t s);
 // out_eps[i] += acc[i] on free nodes.
 void launch_add_free(const double* acc, const int fs[3], double* out_eps, hipStream_t s);
 

@@ -7,7 +7,10 @@ GPU test regenerates from the same input generator.  Stores a seeded sample of
 trace entries and gradient entries plus per-step trace norms and the gradient
 norms, so the GPU result at full size can be compared without the full arrays.
 
-Usage: python tests/golden/make_c2_golden.py [n_steps]   (about 70 min, 20 GB RAM)
+Also stores the paper-formula variant of the eps gradient (eq. gradeps with the
+grad(eps~).E term dropped) at the same sampled nodes, and its norm.
+
+Usage: python tests/golden/make_c2_golden.py [n_steps [out_path]]   (about 80 min, 20 GB RAM)
 """
 
 import os
@@ -52,12 +55,14 @@ def main():
     ds = rng.integers(0, tr.shape[1], N_SAMPLE)
     free = np.nonzero(d.fem_free)[0]
     gs = np.sort(rng.choice(free, N_SAMPLE, replace=False))
-    out = os.path.join(os.path.dirname(os.path.abspath(__file__)), f"c2_oracle_sample_{n_steps}.npz")
+    out = sys.argv[2] if len(sys.argv) > 2 else \
+        os.path.join(os.path.dirname(os.path.abspath(__file__)), f"c2_oracle_sample_{n_steps}.npz")
     np.savez_compressed(
         out, n_steps=n_steps, t_idx=ts, d_idx=ds, traces=tr[ts, ds, :],
         trace_row_norm=np.sqrt(np.sum(tr * tr, axis=(1, 2))),
         g_idx=gs, g_eps=ag["g_eps"][gs], g_sigma=ag["g_sigma"][gs],
         g_eps_norm=np.linalg.norm(ag["g_eps"]), g_sigma_norm=np.linalg.norm(ag["g_sigma"]),
+        g_eps_paper=ag["g_eps_paper"][gs], g_eps_paper_norm=np.linalg.norm(ag["g_eps_paper"]),
         energy=fw["energy"])
     print("wrote", out, flush=True)
 
