@@ -46,9 +46,9 @@ def _mix():
 
 
 def _obs(torch, p, n_src, seed):
-    g = torch.Generator(device="cuda")
-    g.manual_seed(seed)
-    return 1e-2 * torch.randn((n_src, p.n_steps, p.n_det, 3), generator=g, device="cuda")
+    """Seeded synthetic observations (host generator), on the device."""
+    return torch.tensor(1e-2 * synth.noise((n_src, p.n_steps, p.n_det, 3), seed), dtype=torch.float32,
+                        device="cuda")
 
 
 def _alone(torch, w, obs):
@@ -103,16 +103,17 @@ def test_batched_solve_matches_oracle():
     p = Problem(w.desc)
     p.set_coefficients(torch.tensor(w.eps, dtype=torch.float32, device="cuda"),
                        torch.tensor(w.sigma, dtype=torch.float32, device="cuda"))
-    ob = _obs(torch, p, 1, 11)
-    b = Batch(4)
-    b.submit(p, w.sources, obs=ob)
-    rec = b.run_to_completion(chunk=8)[0]
     d = Discretization(w.desc).set_coefficients(w.eps.astype(np.float32).astype(np.float64),
                                                 w.sigma.astype(np.float32).astype(np.float64))
     fw = forward(d, w.sources[0])
+    # observations from the oracle's traces: a coherent misfit, as in a reconstruction
+    ob = torch.tensor((0.9 * fw["traces"])[None].astype(np.float32), device="cuda")
+    b = Batch(4)
+    b.submit(p, w.sources, obs=ob)
+    rec = b.run_to_completion(chunk=8)[0]
     tr = rec["traces"][0].cpu().numpy()
     assert np.linalg.norm(tr - fw["traces"]) <= 1e-4 * np.linalg.norm(fw["traces"])
-    cot = tr.astype(np.float64) - ob[0].cpu().numpy()
+    cot = fw["traces"] - ob[0].cpu().numpy().astype(np.float64)
     ag = adjoint_gradient(d, cot, fw)
     ge = rec["g_eps"].cpu().numpy()
     assert np.linalg.norm(ge - ag["g_eps"]) <= 1e-3 * np.linalg.norm(ag["g_eps"])

@@ -216,17 +216,18 @@ def test_autograd_function_matches_c_abi(torch_cuda):
     from paper_2508_07780_amd import Problem
     from paper_2508_07780_amd.autograd import solve
     w = synth.small("skinlet")
+    d = _oracle(w)
+    fw = forward(d, w.sources[0])
+    # observations from the oracle's traces (the loss's cotangent is then the oracle's own)
+    eobs_np = (0.9 * fw["traces"]).astype(np.float32)
+    ag = adjoint_gradient(d, fw["traces"] - eobs_np.astype(np.float64), fw)
     p = Problem(w.desc)
     eps = torch.tensor(w.eps, dtype=torch.float32, device="cuda", requires_grad=True)
     sig = torch.tensor(w.sigma, dtype=torch.float32, device="cuda", requires_grad=True)
     tr = solve(p, eps, sig, w.sources)
-    eobs = (tr.detach() * 0.9).contiguous()
+    eobs = torch.tensor(eobs_np[None], device="cuda")
     loss = 0.5 * ((tr - eobs) ** 2).sum()
     loss.backward()
-    d = _oracle(w)
-    fw = forward(d, w.sources[0])
-    cot = (tr.detach()[0] - eobs[0]).cpu().numpy().astype(np.float64)
-    ag = adjoint_gradient(d, cot, fw)
     assert _rel(eps.grad.cpu().numpy(), ag["g_eps"]) <= GRAD_TOL
     assert _rel(sig.grad.cpu().numpy(), ag["g_sigma"]) <= GRAD_TOL
 
