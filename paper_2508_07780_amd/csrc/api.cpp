@@ -609,13 +609,9 @@ int dd_create(const dd_problem_desc* desc, dd_problem** out) {
   p->use_stencil = m.stencil_ok && m.n_slots <= STENCIL_SLOTS_MAX;
   if (const char* e = std::getenv("DD_FEM_PATH"))
     if (std::strcmp(e, "element") == 0) p->use_stencil = false;
-  p->nbx = (p->nx + FD_TX - 1) / FD_TX;
-  p->nby = (p->ny + FD_TY - 1) / FD_TY;
-  p->nbz = (p->nz + FD_ZC - 1) / FD_ZC;
   p->fd_nt = fd_field_bytes(p) > LLC_BYTES;
   if (const char* e = std::getenv("DD_FD_NT")) p->fd_nt = std::atoi(e) != 0;
-  p->n_tiles = p->nbx * p->nby * p->nbz;
-  p->per_xcd = (p->n_tiles + N_XCD - 1) / N_XCD;
+  fd_tile_grid(p->nx, p->ny, p->nz, p->fd_nt, p->nbx, p->nby, p->nbz, p->n_tiles, p->per_xcd);
   p->n_ck = (int)((desc->n_steps + desc->ckpt_every - 1) / desc->ckpt_every);
   if (const char* ov = std::getenv("DD_OVERLAP")) p->overlap = std::atoi(ov) != 0;
   if (const char* fu = std::getenv("DD_FUSED")) p->fused = std::atoi(fu) != 0;
@@ -1239,21 +1235,32 @@ int dd_batch_step(dd_batch* b, int32_t max_steps, void* stream) {
       int n = 0, base = 0;
       size_t l = 0;
       double fd_bytes = 0.0;   // the FD field sets this launch streams through
+      const dd_problem* owner[BATCH_MAX];
       for (auto& j : b->jobs) {
-        BatchItem& it = h[n];
-        if (!job_next(j, st, it)) continue;
-        it.fem_blocks = (j.p->n_part + N_XCD - 1) / N_XCD * N_XCD;
-        it.fd_blocks = it.kind == 2 ? 0 : j.p->per_xcd * N_XCD;
+        if (!job_next(j, st, h[n])) continue;
+        if (h[n].kind != 2) fd_bytes += fd_field_bytes(j.p);
+        owner[n++] = j.p;
+      }
+      // the launch's variant (and with it the z-chunk) follows the FD fields it streams;
+      // each item's tile grid is laid out for that chunk
+      const bool use_nt = fd_bytes > LLC_BYTES;
+      for (int i = 0; i < n; ++i) {
+        BatchItem& it = h[i];
+        const dd_problem* q = owner[i];
+        it.fem_blocks = (q->n_part + N_XCD - 1) / N_XCD * N_XCD;
+        it.fd_blocks = 0;
+        if (it.kind != 2) {
+          fd_tile_grid(q->nx, q->ny, q->nz, use_nt, it.fa.nbx, it.fa.nby, it.fa.nbz, it.fa.ntiles, it.fa.per_xcd);
+          it.fd_blocks = it.fa.per_xcd * N_XCD;
+        }
         l = std::max(l, stencil_lds(it.ea));
-        if (it.fd_blocks) fd_bytes += fd_field_bytes(j.p);
-        bases[m].base[n] = base;   // each item's FEM partitions, then its FD tiles
+        bases[m].base[i] = base;   // each item's FEM partitions, then its FD tiles
         base += it.fem_blocks + it.fd_blocks;
-        ++n;
       }
       bases[m].n = n;
       bases[m].base[n] = base;
       lds[m] = l;
-      nt[m] = fd_bytes > LLC_BYTES;
+      nt[m] = use_nt;
       ++m;
       ++iter;
       if (std::any_of(b->jobs.begin(), b->jobs.end(), [](const BatchJob& j) { return j.phase == 2; })) {

@@ -11,13 +11,22 @@
 
 namespace dd {
 
-// Finite-difference tile: 32 x 8 nodes in (x, y), marching FD_ZC planes in z.
+// Finite-difference tile: 32 x 8 nodes in (x, y), marching a chunk of planes in z.
 #ifndef DD_FD_TY
 #define DD_FD_TY 8
 #endif
 constexpr int FD_TX = 32;
 constexpr int FD_TY = DD_FD_TY;
-constexpr int FD_ZC = 8;
+// z-chunk length.  Where the grid's fields fit the last-level cache, short chunks: more and
+// smaller blocks fill the GPU more evenly, and the extra reads of the planes that
+// neighbouring chunks share hit the cache.  Where the fields stream from HBM (the
+// non-temporal variant), long chunks, which read those shared planes less often.
+#ifndef DD_FD_ZC_CACHED
+#define DD_FD_ZC_CACHED 2
+#endif
+constexpr int FD_ZC_CACHED = DD_FD_ZC_CACHED;
+constexpr int FD_ZC_STREAM = 8;
+__host__ __device__ constexpr int fd_zc(bool nt) { return nt ? FD_ZC_STREAM : FD_ZC_CACHED; }
 constexpr int FD_THREADS = FD_TX * FD_TY;
 // Last-level cache (MI355X Infinity Cache).  A grid whose two levels of E exceed it streams
 // each node's own previous and new level with non-temporal accesses.
@@ -70,6 +79,17 @@ inline int64_t face_lex_count(int nx, int ny, int nz, unsigned mask) {
   const int64_t p_full = (int64_t)nx * ny;
   const int64_t nzf = ((mask & DD_FACE_BOTTOM) ? 1 : 0) + ((mask & DD_FACE_TOP) ? 1 : 0);
   return nzf * p_full + (nz - nzf) * p_mid;
+}
+
+// Tile grid of an nx * ny * nz grid for the z-chunk of the streaming (nt) or cached variant;
+// per_xcd = tiles each XCD takes.
+inline void fd_tile_grid(int nx, int ny, int nz, bool nt, int& nbx, int& nby, int& nbz, int& ntiles, int& per_xcd) {
+  const int zc = fd_zc(nt);
+  nbx = (nx + FD_TX - 1) / FD_TX;
+  nby = (ny + FD_TY - 1) / FD_TY;
+  nbz = (nz + zc - 1) / zc;
+  ntiles = nbx * nby * nbz;
+  per_xcd = (ntiles + N_XCD - 1) / N_XCD;
 }
 
 // ---- kernel arguments -------------------------------------------------------------------

@@ -20,7 +20,7 @@ namespace dd {
 // Finite-difference region.  eps = 1, sigma = 0 here (eq. epsilon_sigma_constraint), so
 // the update is the 7-point wave stencil with mirror (Neumann) weights on the outer box,
 // lumped absorbing damping on absorbing faces and the plane-wave / dipole forcing.
-// Tile = 32 x 8 nodes in (x, y), marching FD_ZC planes in z: the current plane sits in LDS
+// Tile = 32 x 8 nodes in (x, y), marching a chunk of fd_zc(NT) planes in z: the current plane sits in LDS
 // (with a one-node halo, double-buffered), the z-1 / z+1 values of each column stay in a
 // register queue that is prefetched three planes ahead; the previous level and the halo
 // two ahead.
@@ -51,7 +51,7 @@ __device__ __forceinline__ void st_own(char* base, uint32_t off, float v) {
 // blockIdx.x % N_XCD so that the remap below keeps consecutive tiles on one XCD.
 template <bool ENERGY, bool NT>
 __device__ __forceinline__ void fd_tile(const FdArgs& a, const int b) {
-  constexpr int ZC = FD_ZC;
+  constexpr int ZC = fd_zc(NT);
   // two LDS planes: plane z is written while plane z-1 may still be read by slower waves,
   // so one barrier per plane suffices
   constexpr int SW = FD_TX + 2, SC = (FD_TY + 2) * SW;   // row and component strides
