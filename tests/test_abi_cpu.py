@@ -53,6 +53,48 @@ def test_error_strings(lib):
         assert lib.dd_error_string(code)
 
 
+def test_null_handles_rejected_without_device_work(lib):
+    """Every entry point added for the reconstruction checks its handles before touching the
+    device (no GPU here): a null problem or run gives DD_ERR_INVALID_ARG."""
+    from paper_2508_07780_amd import _lib
+    L = _lib.load()
+    prm = _lib.CgaParams(gamma_eps=1.0, gamma_sig=1.0, p=0.5, alpha_eps=0.1, alpha_sig=0.1, eps_max=5.0,
+                         sig_max=1.0)
+    out = ctypes.c_void_p()
+    info = _lib.CgaInfo()
+    assert L.dd_cga_create(None, ctypes.byref(prm), None, None, None, ctypes.byref(out)) == -1
+    assert L.dd_cga_update(None, None, None, None, None, None) == -1
+    assert L.dd_cga_get_info(None, ctypes.byref(info), None) == -1
+    assert L.dd_cga_destroy(None) == -1
+    assert L.dd_adjoint_misfit(None, None, None, None) == -1
+    assert L.dd_paper_gradient_enable(None, 1) == -1
+    assert L.dd_gradient_paper(None, None, None, None) == -1
+
+
+def test_struct_layouts_match_the_header(tmp_path):
+    """The ctypes mirrors of the header's structs have the C compiler's sizes and offsets."""
+    import shutil
+    import subprocess
+    from paper_2508_07780_amd import _lib
+    if shutil.which("gcc") is None:
+        pytest.skip("no C compiler")
+    src = tmp_path / "layout.c"
+    src.write_text(
+        '#include <stdio.h>\n#include <stddef.h>\n#include "dd.h"\n'
+        "int main(void) {\n"
+        '  printf("%zu %zu %zu %zu\\n", sizeof(dd_problem_desc), sizeof(dd_source), sizeof(dd_cga_params), '
+        "sizeof(dd_cga_info));\n"
+        '  printf("%zu %zu %zu\\n", offsetof(dd_problem_desc, t_switch), offsetof(dd_cga_info, grad_norm), '
+        "offsetof(dd_cga_info, gamma_next));\n"
+        "  return 0;\n}\n")
+    exe = tmp_path / "layout"
+    subprocess.run(["gcc", "-I", os.path.join(ROOT, "include"), str(src), "-o", str(exe)], check=True)
+    out = subprocess.run([str(exe)], check=True, capture_output=True, text=True).stdout.split()
+    sizes = [ctypes.sizeof(t) for t in (_lib.ProblemDesc, _lib.Source, _lib.CgaParams, _lib.CgaInfo)]
+    offs = [_lib.ProblemDesc.t_switch.offset, _lib.CgaInfo.grad_norm.offset, _lib.CgaInfo.gamma_next.offset]
+    assert [int(v) for v in out] == sizes + offs
+
+
 @pytest.mark.parametrize("mask", range(1, 64))
 def test_detector_order_matches_oracle(lib, mask):
     from paper_2508_07780_amd import _lib
