@@ -352,7 +352,7 @@ void fwd_step_args(const dd_problem* p, const dd_source& src, const SrcPlan& sp,
   fa.X_out = p->Efd[nxt];
   // grids larger than the last-level cache: alternate steps sweep in reverse, starting where
   // the previous step ended (whose fields the cache still holds)
-  fa.rev = ea.rev = p->fd_nt ? (int)(n & 1) : 0;
+  fa.rev = ea.rev = (int)(n & 1);
   fa.top_a = fa.top_b = top_absorbs(p, n) ? 1 : 0;
   for (int c = 0; c < 3; ++c) {
     fa.pw[c] = (src.kind != DD_SRC_DIPOLE && t <= p->d.t_switch) ? (float)(2.0 * dt * dt / h * P * src.pol[c]) : 0.f;
@@ -397,7 +397,7 @@ void recompute_args(const dd_problem* p, int s, int64_t k, int64_t k0, float* wi
   fw.I_in = fw.X_in + 3 * n_own;
   fw.I_out = fw.X_out + 3 * n_own;
   fw.iface_in = p->ihist[s] + k * 3 * p->n_l0;
-  fw.rev = p->fd_nt ? (int)(k & 1) : 0;
+  fw.rev = (int)(k & 1);
   fw.fd_out = nullptr;
   fw.ck_X = fw.ck_I = nullptr;
 }
@@ -409,7 +409,7 @@ void adj_step_args(const dd_problem* p, int s, int64_t k, int64_t k0, const floa
   const int cur = (int)(k & 1), prv = (int)((k - 1) & 1);
   fa.X_in = p->Efd[cur];
   fa.X_out = p->Efd[prv];
-  fa.rev = ea.rev = p->fd_nt ? (int)(k & 1) : 0;
+  fa.rev = ea.rev = (int)(k & 1);
   fa.top_a = top_absorbs(p, k - 1) ? 1 : 0;
   fa.top_b = top_absorbs(p, k + 1) ? 1 : 0;
   for (int c = 0; c < 3; ++c) fa.pw[c] = fa.dip[c] = 0.f;

@@ -118,8 +118,8 @@ struct FdArgs {
   int fs[3];           // FEM lattice shape (fem_cells + 1)
   double* epart;       // energy partial per tile or null
   double e_coef;       // h^3 / (2 dt^2)
-  int rev;             // 1: each XCD takes its tiles in reverse order (alternate steps of
-                       // grids larger than the last-level cache)
+  int rev;             // 1: each XCD takes its tiles in reverse order (alternate steps: a
+                       // step starts where the previous one ended, whose data the caches hold)
 };
 
 constexpr int STENCIL_SLOTS_MAX = 27;
