@@ -49,10 +49,14 @@ struct dd_problem {
   // and the last segment's full FEM state (written by the forward, never recomputed)
   std::vector<float*> ihist, ckpt, tail;
   int n_ck = 0;
-  float* win = nullptr;             // recompute window [(K+1)][2][3][n_own]
+  float* win = nullptr;             // recompute windows [(K+1)][2][3][n_own], for even and
+  float* win_b = nullptr;           // odd segments (one segment is recomputed while another runs)
   // FD and FEM launches of one step run concurrently on the caller's stream and `aux`
   hipStream_t aux = nullptr;
   hipEvent_t ev_fd = nullptr, ev_fem = nullptr;
+  // adjoint segment pipeline: a segment's recompute (on `aux`) is done; a segment's adjoint
+  // steps (on the caller's stream) are done
+  hipEvent_t ev_rec[2] = {nullptr, nullptr}, ev_adj = nullptr;
   bool overlap = false;   // measured slower than one stream (cross-stream waits per step)
   bool fused = true;      // one launch per step (FD tiles + stencil FEM partitions)
   bool saved = false;
@@ -280,9 +284,13 @@ int ensure_saved_storage(dd_problem* p, int n_src) {
     p->ckpt.push_back(c);
     p->tail.push_back(t);
   }
+  const int64_t K = p->d.ckpt_every;
   if (!p->win && n_segments(p) > 1) {
-    const int64_t K = p->d.ckpt_every;
     int rc = dalloc(p, &p->win, (size_t)(K + 1) * 6 * p->n_own);
+    if (rc) return rc;
+  }
+  if (!p->win_b && n_segments(p) > 2) {
+    int rc = dalloc(p, &p->win_b, (size_t)(K + 1) * 6 * p->n_own);
     if (rc) return rc;
   }
   return DD_OK;
@@ -381,12 +389,13 @@ void fwd_step_args(const dd_problem* p, const dd_source& src, const SrcPlan& sp,
 // Forward FEM state of the levels of segment seg: stored by the forward for the last
 // segment, recomputed into the shared window otherwise.
 float* segment_window(const dd_problem* p, int s, int64_t seg) {
-  return seg == n_segments(p) - 1 ? p->tail[s] : p->win;
+  if (seg == n_segments(p) - 1) return p->tail[s];
+  return (seg & 1) ? p->win_b : p->win;
 }
 
 void segment_prologue(dd_problem* p, int s, int64_t seg, hipStream_t st) {
   if (seg != n_segments(p) - 1)
-    launch_copy_f32(p->win, p->ckpt[s] + seg * 6 * p->n_own, 6 * p->n_own, st);
+    launch_copy_f32(segment_window(p, s, seg), p->ckpt[s] + seg * 6 * p->n_own, 6 * p->n_own, st);
 }
 
 // Arguments of the FEM-only forward recompute of level k -> k+1 inside segment [k0, k1).
@@ -474,18 +483,37 @@ int run_adjoint(dd_problem* p, int s, const float* cot, const float* obs, hipStr
   const int64_t nseg = n_segments(p);
   hipStream_t sf = p->overlap ? p->aux : st;
   const bool fused = p->use_stencil && p->fused;
-  fork_streams(p, st);
+  // Segment pipeline (single-stream steps): the FEM recompute of a segment runs on `aux`,
+  // into its own window, while the adjoint steps of the segment after it run on st.  A
+  // segment's steps wait for its recompute; a recompute reuses the window of the segment
+  // two later, after that segment's steps.
+  const bool pipe = !p->overlap;
+  auto recompute = [&](int64_t seg, hipStream_t rs) {
+    const int64_t k0 = seg * K, k1 = std::min(k0 + K, nt);
+    float* win = segment_window(p, s, seg);
+    segment_prologue(p, s, seg, rs);
+    for (int64_t k = k0; k < k1; ++k) {
+      recompute_args(p, s, k, k0, win, fw);
+      const long ps = prof_begin(p, DD_PROF_FEM_RECOMPUTE, rs);
+      fem_fwd(p, fw, rs, false);
+      prof_end(p, DD_PROF_FEM_RECOMPUTE, ps, rs);
+    }
+    if (pipe) (void)hipEventRecord(p->ev_rec[seg & 1], rs);
+  };
+  if (pipe) {
+    // aux starts after the work already queued on st (the forward's checkpoints)
+    (void)hipEventRecord(p->ev_adj, st);
+    (void)hipStreamWaitEvent(p->aux, p->ev_adj, 0);
+    if (nseg >= 2) recompute(nseg - 2, p->aux);
+  } else {
+    fork_streams(p, st);
+  }
   for (int64_t seg = nseg - 1; seg >= 0; --seg) {
     const int64_t k0 = seg * K, k1 = std::min(k0 + K, nt);
     float* win = segment_window(p, s, seg);
     if (seg != nseg - 1) {
-      segment_prologue(p, s, seg, sf);
-      for (int64_t k = k0; k < k1; ++k) {
-        recompute_args(p, s, k, k0, win, fw);
-        const long ps = prof_begin(p, DD_PROF_FEM_RECOMPUTE, sf);
-        fem_fwd(p, fw, sf, false);
-        prof_end(p, DD_PROF_FEM_RECOMPUTE, ps, sf);
-      }
+      if (pipe) (void)hipStreamWaitEvent(st, p->ev_rec[seg & 1], 0);
+      else recompute(seg, sf);
     }
     for (int64_t k = k1; k > k0; --k) {
       adj_step_args(p, s, k, k0, win, cot, obs, fa, ea);
@@ -507,8 +535,14 @@ int run_adjoint(dd_problem* p, int s, const float* cot, const float* obs, hipStr
       if (p->pg_on)
         launch_paper_grad_step(ea.X_in, ea.wE, p->n_own, p->api_own, p->fs, p->d.h, p->pg_acc, st);
     }
+    if (pipe && seg >= 2) {
+      (void)hipEventRecord(p->ev_adj, st);
+      (void)hipStreamWaitEvent(p->aux, p->ev_adj, 0);
+      recompute(seg - 2, p->aux);
+    }
   }
-  join_streams(p, st);
+  // pipelined: every recompute queued on aux has been waited for by a segment on st
+  if (!pipe) join_streams(p, st);
   return check_launch(p);
 }
 
@@ -568,6 +602,7 @@ size_t dd_footprint_bytes(const dd_problem_desc* desc, int32_t n_src) {
   b += tets_est * 8 + n_fem * 4 * 2;      // elements, halo lists
   b += (int64_t)n_src * ((nt + 1) * 3 * n_l0 * 4 + (n_ck + tail_levels) * 6 * n_own * 4);  // saved forward
   if (nseg > 1) b += (K + 1) * 6 * n_own * 4;  // recompute window
+  if (nseg > 2) b += (K + 1) * 6 * n_own * 4;  // the second one (two segments in flight)
   return (size_t)b;
 }
 
@@ -650,7 +685,10 @@ int dd_create(const dd_problem_desc* desc, dd_problem** out) {
   chk(dalloc(p, &p->g_sig, p->n_own));
   if (!rc && (hipStreamCreateWithFlags(&p->aux, hipStreamNonBlocking) != hipSuccess ||
               hipEventCreateWithFlags(&p->ev_fd, hipEventDisableTiming) != hipSuccess ||
-              hipEventCreateWithFlags(&p->ev_fem, hipEventDisableTiming) != hipSuccess))
+              hipEventCreateWithFlags(&p->ev_fem, hipEventDisableTiming) != hipSuccess ||
+              hipEventCreateWithFlags(&p->ev_rec[0], hipEventDisableTiming) != hipSuccess ||
+              hipEventCreateWithFlags(&p->ev_rec[1], hipEventDisableTiming) != hipSuccess ||
+              hipEventCreateWithFlags(&p->ev_adj, hipEventDisableTiming) != hipSuccess))
     rc = DD_ERR_HIP;
   if (rc) {
     dd_destroy(p);
@@ -676,6 +714,8 @@ int dd_destroy(dd_problem* p) {
     for (hipEvent_t e : v) (void)hipEventDestroy(e);
   if (p->ev_fd) (void)hipEventDestroy(p->ev_fd);
   if (p->ev_fem) (void)hipEventDestroy(p->ev_fem);
+  for (hipEvent_t e : {p->ev_rec[0], p->ev_rec[1], p->ev_adj})
+    if (e) (void)hipEventDestroy(e);
   if (p->aux) (void)hipStreamDestroy(p->aux);
   for (void* q : p->allocs) (void)hipFree(q);
   delete p;
