@@ -34,5 +34,5 @@ the discretisation to it and prints no discrete values).
 
 from .discretization import Discretization  # noqa: F401
 from .solver import (  # noqa: F401
-    source_time_function, forward, adjoint_gradient, loss_and_cotangent, energy_balance_residual,
+    source_time_function, forward, adjoint_gradient, loss_and_cotangent, energy_balance_residual, taper,
 )

@@ -168,8 +168,9 @@ def cga_loop(grad_fn, eps0, sig0, w, free, params, n_iter):
     return hist
 
 
-def solve_gradient(d, sources, eobs):
-    """Step 1 on the discrete scheme: gradient of J summed over sources, and J."""
+def solve_gradient(d, sources, eobs, z=None):
+    """Step 1 on the discrete scheme: gradient of J summed over sources, and J (z: the
+    smoothing function of eq. tikhonov_functional at the trace rows, or None for z = 1)."""
     def grad_fn(eps, sig):
         d.set_coefficients(eps, sig)
         ge = np.zeros(d.n_fem)
@@ -177,7 +178,7 @@ def solve_gradient(d, sources, eobs):
         J = 0.0
         for s, src in enumerate(sources):
             fw = forward(d, src)
-            Js, r = loss_and_cotangent(fw["traces"], eobs[s])
+            Js, r = loss_and_cotangent(fw["traces"], eobs[s], z)
             ag = adjoint_gradient(d, r, fw)
             ge += ag["g_eps"]
             gs += ag["g_sigma"]
@@ -186,7 +187,7 @@ def solve_gradient(d, sources, eobs):
     return grad_fn
 
 
-def cga(d, sources, eobs, eps0, sig0, params, n_iter):
+def cga(d, sources, eobs, eps0, sig0, params, n_iter, z=None):
     """The CGA on the discretisation d: eobs is [n_src][n_steps][n_det][3]."""
     w = d.m[d.fem_grid]
-    return cga_loop(solve_gradient(d, sources, eobs), eps0, sig0, w, d.fem_free, params, n_iter)
+    return cga_loop(solve_gradient(d, sources, eobs, z), eps0, sig0, w, d.fem_free, params, n_iter)

@@ -109,9 +109,26 @@ def forward(d, src=None, n_steps=None, force=None, keep_full=False):
     return out
 
 
-def loss_and_cotangent(traces, eobs):
+def taper(n_steps, dt, delta):
+    """Smoothing function z of eq. tikhonov_functional at the trace rows (row n holds time
+    level n + 1, t = (n + 1) dt): 1 up to T - delta, then a cosine ramp to 0 at T = n_steps dt,
+    z(t) = (1 + cos(pi (t - T + delta) / delta)) / 2.  delta <= 0 gives z = 1."""
+    T = n_steps * dt
+    t = dt * np.arange(1, n_steps + 1)
+    if delta <= 0:
+        return np.ones(n_steps)
+    s = np.clip((t - (T - delta)) / delta, 0.0, 1.0)
+    return 0.5 * (1.0 + np.cos(np.pi * s))
+
+
+def loss_and_cotangent(traces, eobs, z=None):
+    """J = 1/2 sum_n z_n sum_det |T^n - E_obs^n|^2 (z = 1 when not given) and dJ/dT.
+    traces / eobs: [n_steps][n_det][3], or with a leading source axis."""
     r = traces - eobs
-    return 0.5 * float(np.sum(r * r)), r
+    if z is None:
+        return 0.5 * float(np.sum(r * r)), r
+    w = np.asarray(z, dtype=np.float64).reshape((-1, 1, 1))
+    return 0.5 * float(np.sum(w * r * r)), w * r
 
 
 def adjoint_gradient(d, cot, fwd, keep_lambda=False):

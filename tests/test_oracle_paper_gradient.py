@@ -15,6 +15,12 @@ eps - 1 outside the divergence.  So:
   (this is what pins the formula's code, weights |K|/4 and restriction included);
 * under R1 the paper formula is a different vector from the exact gradient (it is reported
   against it, not used in its place).
+
+The smoothing function z of eq. tikhonov_functional (the misfit weighted in time):
+* the taper is 1 up to T - delta, 0 at T (the last trace row is time level N_t), monotone and
+  C1 at both ends of its ramp;
+* brute force: with z the adjoint source z_n r^n gives the gradient of the weighted J
+  (central differences), and the unweighted source does not.
 """
 
 import numpy as np
@@ -108,3 +114,49 @@ def test_paper_formula_differs_from_the_exact_r1_gradient():
     assert np.all(np.abs(ag["g_eps"][free] - fd[free]) <= 1e-4 * np.abs(fd[free]))
     rel = np.linalg.norm(ag["g_eps_paper"] - ag["g_eps"]) / np.linalg.norm(ag["g_eps"])
     assert rel > 1e-3
+
+
+# ---- the smoothing function z of eq. tikhonov_functional -----------------------------------
+
+def test_taper_shape():
+    from oracle.solver import taper
+    dt, nt, delta = 0.01, 200, 0.5
+    z = taper(nt, dt, delta)
+    t = dt * np.arange(1, nt + 1)
+    T = nt * dt
+    assert np.all(z[t <= T - delta + 1e-12] == 1.0) and z[-1] == 0.0
+    assert np.all(np.diff(z) <= 0) and np.all((z >= 0) & (z <= 1))
+    # C1 at both ends of the ramp: one-sided slopes vanish (second order in dt)
+    assert abs(z[-1] - z[-2]) <= 2 * (np.pi / delta) ** 2 * dt ** 2
+    k = int(np.searchsorted(t, T - delta + 1e-12))
+    assert abs(z[k] - z[k - 1]) <= 2 * (np.pi / delta) ** 2 * dt ** 2
+    np.testing.assert_array_equal(taper(nt, dt, 0.0), np.ones(nt))
+
+
+def test_weighted_misfit_gradient_matches_central_differences():
+    """With z the adjoint source is z_n r^n: the gradient matches differences of the weighted J."""
+    from oracle.solver import taper
+    w, d = _tiny("R1")
+    src = w.sources[0]
+    eobs = forward(d, src)["traces"] * 0.9
+    z = taper(w.desc.n_steps, w.desc.dt, 0.4 * w.desc.n_steps * w.desc.dt)
+    fw = forward(d, src)
+    J0, cot = loss_and_cotangent(fw["traces"], eobs, z)
+    J1, _ = loss_and_cotangent(fw["traces"], eobs)
+    assert J0 < J1
+    ag = adjoint_gradient(d, cot, fw)
+
+    def J(eps):
+        dd = Discretization(w.desc).set_coefficients(eps, w.sigma)
+        return loss_and_cotangent(forward(dd, src)["traces"], eobs, z)[0]
+
+    for i in np.nonzero(d.fem_free)[0][:3]:
+        e = w.eps.copy()
+        e[i] += 1e-5
+        jp = J(e)
+        e[i] -= 2e-5
+        fd = (jp - J(e)) / 2e-5
+        assert abs(ag["g_eps"][i] - fd) <= 1e-4 * abs(fd)
+    # unweighted cotangent would not match the weighted J
+    ag1 = adjoint_gradient(d, loss_and_cotangent(fw["traces"], eobs)[1], fw)
+    assert np.linalg.norm(ag1["g_eps"] - ag["g_eps"]) > 1e-2 * np.linalg.norm(ag["g_eps"])
