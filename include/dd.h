@@ -149,6 +149,19 @@ int dd_gradient(dd_problem* p, double* g_eps_dev, double* g_sigma_dev, void* str
  * requirements and results as dd_adjoint. */
 int dd_adjoint_misfit(dd_problem* p, const float* traces_dev, const float* obs_dev, void* stream);
 
+/* Trace misfit of eq. tikhonov_functional with its smoothing function z, on the device:
+ * traces_dev, obs_dev: [n_src][n_steps][n_det][3] float32; z_host: NULL (z = 1) or n_steps
+ * float64 weights >= 0 on the host, entry n for trace row n (time level n + 1).
+ *   cot_dev (nullable): z_n (traces - obs), float32, same layout (may be traces_dev itself);
+ *     dd_adjoint(p, cot_dev) then gives the gradient of the weighted misfit;
+ *   j_dev (nullable): J = 1/2 sum_n z_n sum |traces - obs|^2, one float64 (a deterministic
+ *     FP64 sum).
+ * Queued on `stream`; z_host is read before the call returns (weights that differ from the
+ * last call's are uploaded, synchronising `stream`).  Calls on different streams must not
+ * overlap. */
+int dd_misfit(dd_problem* p, const float* traces_dev, const float* obs_dev, int32_t n_src, const double* z_host,
+              float* cot_dev, double* j_dev, void* stream);
+
 /* Paper-formula gradient variant.  eq. gradeps writes the div-div part of g_eps as the
  * time integral of div(lambda) div(E), having replaced div(eps~ E) by eps~ div(E); on the
  * discrete scheme that term is sum_k sum_{K containing i} (|K|/4) div_K(lambda^k) div_K(E^k)

@@ -9,12 +9,29 @@ Everything stays on the device; the host reads the run's scalars once per iterat
 """
 
 import ctypes
+import math
 from dataclasses import dataclass, fields
 
+import numpy as np
 import torch
 
 from . import _lib
 from .solver import _ptr, _stream
+
+
+def taper_weights(n_steps, dt, delta):
+    """A smoothing function z of eq. tikhonov_functional for the trace rows (row n is time level
+    n + 1): 1 until delta before the end time T = n_steps dt, then (1 + cos(pi s)) / 2 with s
+    running from 0 to 1 over that last stretch (z = 0 at T), so that the misfit fades out
+    smoothly instead of being cut at T.  delta <= 0: z = 1."""
+    z = np.ones(n_steps)
+    if delta > 0:
+        t_end = n_steps * dt
+        for n in range(n_steps):
+            s = ((n + 1) * dt - (t_end - delta)) / delta
+            if s > 0:
+                z[n] = 0.5 * (1.0 + math.cos(math.pi * min(s, 1.0)))
+    return z
 
 
 @dataclass
@@ -52,7 +69,9 @@ class CGA:
     """A CGA run on one problem: sources, observations [n_src][n_steps][n_det][3] and the
     initial guess (also the Tikhonov centre).  ``eps`` and ``sigma`` hold the iterate."""
 
-    def __init__(self, problem, sources, obs, eps0, sig0, params):
+    def __init__(self, problem, sources, obs, eps0, sig0, params, z=None, track_loss=False):
+        """z: time weights of the misfit (numpy, one per step; None = 1); track_loss: also form
+        J of every solve on the device (read by info())."""
         dev = torch.device("cuda", torch.cuda.current_device())
         self.problem = problem
         self.sources = list(sources)
@@ -63,7 +82,10 @@ class CGA:
         self.eps = torch.as_tensor(eps0, dtype=torch.float32, device=dev).clone().contiguous()
         self.sigma = torch.as_tensor(sig0, dtype=torch.float32, device=dev).clone().contiguous()
         self._shape = shape
-        self.traces = self.g_eps = self.g_sig = None     # allocated by the first solve()
+        self.traces = self.g_eps = self.g_sig = self.cot = None     # allocated by the first solve()
+        self.z = None if z is None else np.ascontiguousarray(z, dtype=np.float64)
+        self.track_loss = bool(track_loss)
+        self.J = None
         self.params = params
         self._cp = params.to_c()
         h = ctypes.c_void_p()
@@ -92,7 +114,15 @@ class CGA:
             self.g_sig = torch.empty(p.n_fem, dtype=torch.float64, device=dev)
         p.set_coefficients(self.eps, self.sigma)
         p.forward(self.sources, save=True, out=self.traces)
-        p.adjoint_misfit(self.traces, self.obs)
+        if self.z is None:
+            if self.track_loss:
+                self.J, _ = p.misfit(self.traces, self.obs, cotangent=False)
+            p.adjoint_misfit(self.traces, self.obs)
+        else:
+            if self.cot is None:
+                self.cot = torch.empty_like(self.traces)
+            self.J, _ = p.misfit(self.traces, self.obs, self.z, loss=self.track_loss, out=self.cot)
+            p.adjoint(self.cot)
         p.gradient(out=(self.g_eps, self.g_sig))
 
     def update(self, g_eps=None, g_sig=None):
@@ -115,6 +145,8 @@ class CGA:
         c = _lib.CgaInfo()
         _lib.check(_lib.load().dd_cga_get_info(self._h, ctypes.byref(c), _stream()))
         out = {"iterations": c.iterations, "converged": bool(c.converged)}
+        if self.track_loss and self.J is not None:
+            out["J"] = float(self.J.item())     # J at the iterate the last update started from
         for name in ("grad_norm", "step_norm", "beta", "alpha_used", "alpha_next", "gamma_used", "gamma_next"):
             arr = getattr(c, name)
             out[name] = {"eps": arr[0], "sig": arr[1]}

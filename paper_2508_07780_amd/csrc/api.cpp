@@ -64,6 +64,9 @@ struct dd_problem {
   double *g_eps = nullptr, *g_sig = nullptr;
   bool have_grad = false;
   bool adj_obs = false;   // the last adjoint formed its cotangent as traces - observations
+  // dd_misfit: time weights (n_steps; a host copy of the last upload) and FP64 block partials
+  double *mis_z = nullptr, *mis_part = nullptr;
+  std::vector<double> mis_z_host;
   // paper-formula gradient variant: FEM-node -> owned id map, FP64 sum
   bool pg_on = false, have_pg = false;
   int* api_own = nullptr;
@@ -816,6 +819,35 @@ int dd_gradient(dd_problem* p, double* g_eps_dev, double* g_sigma_dev, void* str
   launch_fill_f64(g_eps_dev, p->n_fem, 0.0, st);
   launch_fill_f64(g_sigma_dev, p->n_fem, 0.0, st);
   launch_gradient_out(p->g_eps, p->g_sig, p->own_api, p->own_grid, p->n_own, g_eps_dev, g_sigma_dev, st);
+  return check_launch(p);
+}
+
+int dd_misfit(dd_problem* p, const float* traces_dev, const float* obs_dev, int32_t n_src, const double* z_host,
+              float* cot_dev, double* j_dev, void* stream) {
+  if (!p) return DD_ERR_INVALID_ARG;
+  if (!traces_dev || !obs_dev || n_src < 1) return fail(p, DD_ERR_INVALID_ARG, "need traces, observations, n_src >= 1");
+  hipStream_t st = (hipStream_t)stream;
+  const int64_t nt = p->d.n_steps;
+  if (!p->mis_part) {
+    int rc = dalloc(p, &p->mis_part, (size_t)CGA_MAX_BLOCKS);
+    if (!rc) rc = dalloc(p, &p->mis_z, (size_t)nt);
+    if (rc) return rc;
+  }
+  if (z_host) {
+    for (int64_t n = 0; n < nt; ++n)
+      if (!std::isfinite(z_host[n]) || z_host[n] < 0.0) return fail(p, DD_ERR_INVALID_ARG, "weights must be finite, >= 0");
+    // upload only new weights; the copy completes before the call returns, and it is ordered
+    // after the work already queued on the stream that reads the previous weights
+    if (p->mis_z_host.size() != (size_t)nt || !std::equal(p->mis_z_host.begin(), p->mis_z_host.end(), z_host)) {
+      if (hipMemcpyAsync(p->mis_z, z_host, (size_t)nt * sizeof(double), hipMemcpyHostToDevice, st) != hipSuccess ||
+          hipStreamSynchronize(st) != hipSuccess)
+        return fail(p, DD_ERR_HIP, "weight upload failed");
+      p->mis_z_host.assign(z_host, z_host + nt);
+    }
+  }
+  const int64_t row = p->n_det * 3;
+  launch_misfit(traces_dev, obs_dev, (int64_t)n_src * nt * row, row, nt, z_host ? p->mis_z : nullptr, cot_dev,
+                p->mis_part, j_dev, st);
   return check_launch(p);
 }
 

@@ -173,6 +173,32 @@ __global__ __launch_bounds__(CGA_THREADS) void cga_finish_kernel(const double* _
   }
 }
 
+// One pass over traces and observations: the weighted cotangent and the FP64 partials of J.
+// The difference of two float32 values is exact in FP64, so cot is that difference times z,
+// rounded once.
+__global__ __launch_bounds__(CGA_THREADS) void misfit_kernel(const float* __restrict__ traces,
+                                                             const float* __restrict__ obs, int64_t n,
+                                                             int64_t row_len, int64_t n_rows,
+                                                             const double* __restrict__ z, float* cot,
+                                                             double* __restrict__ part) {
+  double acc[1] = {0.0};
+  for (int64_t i = (int64_t)blockIdx.x * CGA_THREADS + threadIdx.x; i < n; i += (int64_t)gridDim.x * CGA_THREADS) {
+    const double r = (double)traces[i] - (double)obs[i];
+    const double w = z ? z[(i / row_len) % n_rows] : 1.0;
+    if (cot) cot[i] = (float)(w * r);
+    acc[0] += w * r * r;
+  }
+  block_sums<1>(acc, part + blockIdx.x);
+}
+
+__global__ __launch_bounds__(CGA_THREADS) void misfit_finish_kernel(const double* __restrict__ part, int nb,
+                                                                    double* __restrict__ j) {
+  __shared__ double tot[1];
+  sum_partials<1>(part, nb, tot);
+  __syncthreads();
+  if (threadIdx.x == 0) *j = 0.5 * tot[0];
+}
+
 __global__ void cga_upper_check_kernel(const float* __restrict__ eps, const float* __restrict__ sig, int64_t n,
                                        double eps_max, double sig_max, int* err) {
   for (int64_t i = (int64_t)blockIdx.x * blockDim.x + threadIdx.x; i < n; i += (int64_t)gridDim.x * blockDim.x)
@@ -196,6 +222,13 @@ void launch_cga_update(const double* gJe, const double* gJs, float* eps, float* 
   hipLaunchKernelGGL(cga_step_kernel, dim3(nb), dim3(CGA_THREADS), 0, s, gJe, gJs, eps, sig, eps0, sig0, d_eps,
                      d_sig, fs[0], fs[1], fs[2], st, part);
   hipLaunchKernelGGL(cga_finish_kernel, dim3(1), dim3(CGA_THREADS), 0, s, part, nb, st);
+}
+
+void launch_misfit(const float* traces, const float* obs, int64_t n, int64_t row_len, int64_t n_rows,
+                   const double* z, float* cot, double* part, double* j, hipStream_t s) {
+  const int nb = cga_blocks(n);
+  hipLaunchKernelGGL(misfit_kernel, dim3(nb), dim3(CGA_THREADS), 0, s, traces, obs, n, row_len, n_rows, z, cot, part);
+  if (j) hipLaunchKernelGGL(misfit_finish_kernel, dim3(1), dim3(CGA_THREADS), 0, s, part, nb, j);
 }
 
 void launch_cga_upper_check(const float* eps, const float* sig, int64_t n, double eps_max, double sig_max, int* err,

@@ -29,4 +29,10 @@ void launch_cga_update(const double* gJe, const double* gJs, float* eps, float* 
 void launch_cga_upper_check(const float* eps, const float* sig, int64_t n, double eps_max, double sig_max, int* err,
                             hipStream_t s);
 
+// Trace misfit of eq. tikhonov_functional with time weights z (null: z = 1) at the trace rows:
+// cot (nullable) = z_row (traces - obs) in float32; j (nullable) = 1/2 sum z_row |traces - obs|^2
+// in FP64 (block partials in part[CGA_MAX_BLOCKS], summed in order by one block).
+void launch_misfit(const float* traces, const float* obs, int64_t n, int64_t row_len, int64_t n_rows,
+                   const double* z, float* cot, double* part, double* j, hipStream_t s);
+
 }  // namespace dd

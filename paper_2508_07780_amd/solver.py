@@ -124,6 +124,31 @@ class Problem:
         _lib.check(_lib.load().dd_gradient(self._h, _ptr(ge), _ptr(gs), _stream()), self._h)
         return ge, gs
 
+    def misfit(self, traces, obs, z=None, cotangent=True, loss=True, out=None):
+        """(J, cot) of the trace misfit with time weights z (numpy, n_steps, or None for z = 1):
+        cot = z_n (traces - obs) (float32, into `out` when given, or None), J a float64 device
+        scalar (or None)."""
+        import numpy as np
+        n = traces.shape[0]
+        shape = (n, self.n_steps, self.n_det, 3)
+        for name, t in (("traces", traces), ("observations", obs)):
+            if not (t.is_cuda and t.dtype == torch.float32 and t.is_contiguous() and tuple(t.shape) == shape):
+                raise ValueError("%s must be a contiguous float32 CUDA (HIP) tensor of shape %s" % (name, shape))
+        zz = None
+        if z is not None:
+            zz = np.ascontiguousarray(z, dtype=np.float64)
+            if zz.shape != (self.n_steps,):
+                raise ValueError("z must have one weight per time step")
+        cot = (out if out is not None else torch.empty_like(traces)) if cotangent else None
+        if cot is not None and (cot.shape != traces.shape or cot.dtype != torch.float32 or not cot.is_contiguous()):
+            raise ValueError("cotangent buffer must match the traces")
+        J = torch.empty((), dtype=torch.float64, device=traces.device) if loss else None
+        _lib.check(_lib.load().dd_misfit(self._h, _ptr(traces), _ptr(obs), n,
+                                         zz.ctypes.data_as(ctypes.c_void_p) if zz is not None else None,
+                                         _ptr(cot) if cot is not None else None,
+                                         _ptr(J) if J is not None else None, _stream()), self._h)
+        return J, cot
+
     def paper_gradient(self, on=True):
         """Accumulate the paper-formula gradient variant in the following adjoints."""
         _lib.check(_lib.load().dd_paper_gradient_enable(self._h, 1 if on else 0), self._h)

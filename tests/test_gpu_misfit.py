@@ -1,0 +1,124 @@
+"""The trace misfit with the smoothing function z of eq. tikhonov_functional, on the GPU,
+against the FP64 oracle.
+
+* dd_misfit on seeded synthetic traces and observations (two sources, z = a taper and z = 1):
+  the cotangent z_n (T - E_obs) bit for bit (the float32 difference is exact in FP64 and is
+  rounded once, as the oracle's FP64 value cast to float32), J within 1e-12 (FP64 sums in
+  another order); the product's taper equals the oracle's.
+* The gradient of the weighted misfit (dd_misfit's cotangent into dd_adjoint) against the
+  oracle on a coherent misfit: rel L2 <= 1e-3.
+* Two CGA iterations with the taper and J tracked on the device against the oracle's CGA:
+  coefficient change rel L2 <= 2e-3; J within what the trace bar allows: with traces off by
+  at most 1e-4 |T|_z (z-weighted norm), |J_gpu - J| <= sqrt(2 J) 1e-4 |T|_z + (1e-4 |T|_z)^2 / 2
+  (the misfit is small against the traces here, so a relative bar on J would amplify the
+  FP32 trace error).
+* Negative or non-finite weights are rejected.
+"""
+
+import math
+
+import numpy as np
+import pytest
+
+import synth
+from oracle.discretization import Discretization
+from oracle.solver import adjoint_gradient, forward, loss_and_cotangent, taper
+
+pytestmark = pytest.mark.gpu
+
+
+def _rel(a, b):
+    return float(np.linalg.norm(np.asarray(a, dtype=np.float64) - b) / np.linalg.norm(b))
+
+
+def test_misfit_matches_oracle():
+    import torch
+    from paper_2508_07780_amd import Problem
+    from paper_2508_07780_amd.cga import taper_weights
+    w = synth.small("ragged")
+    p = Problem(w.desc)
+    nt = w.desc.n_steps
+    shape = (2, nt, p.n_det, 3)
+    tr = synth.noise(shape, 31).astype(np.float32)
+    ob = (0.7 * tr + 0.1 * synth.noise(shape, 32)).astype(np.float32)
+    zo = taper(nt, w.desc.dt, 0.3 * nt * w.desc.dt)
+    zp = taper_weights(nt, w.desc.dt, 0.3 * nt * w.desc.dt)
+    np.testing.assert_array_equal(zp, zo)
+    T, O = torch.tensor(tr, device="cuda"), torch.tensor(ob, device="cuda")
+    for z in (zo, None):
+        J, cot = p.misfit(T, O, z)
+        Jo = 0.0
+        for s in range(2):
+            js, cs = loss_and_cotangent(tr[s].astype(np.float64), ob[s].astype(np.float64), z)
+            Jo += js
+            np.testing.assert_array_equal(cot[s].cpu().numpy(), cs.astype(np.float32))
+        assert float(J.item()) == pytest.approx(Jo, rel=1e-12)
+    from paper_2508_07780_amd import DDError
+    bad = zo.copy()
+    bad[3] = -1.0
+    with pytest.raises(DDError):
+        p.misfit(T, O, bad)
+    bad[3] = math.nan
+    with pytest.raises(DDError):
+        p.misfit(T, O, bad)
+    p.close()
+
+
+def test_weighted_misfit_gradient_matches_oracle():
+    import torch
+    from paper_2508_07780_amd import Problem
+    w = synth.small("ragged")
+    src = w.sources[0]
+    eobs = forward(Discretization(w.desc).set_coefficients(w.eps, w.sigma), src)["traces"].astype(np.float32)
+    eps_m = 1.0 + 0.5 * (w.eps - 1.0)
+    sig_m = 0.5 * w.sigma
+    d = Discretization(w.desc).set_coefficients(eps_m.astype(np.float32).astype(np.float64),
+                                                sig_m.astype(np.float32).astype(np.float64))
+    fw = forward(d, src)
+    z = taper(w.desc.n_steps, w.desc.dt, 0.4 * w.desc.n_steps * w.desc.dt)
+    _, cot = loss_and_cotangent(fw["traces"], eobs.astype(np.float64), z)
+    ag = adjoint_gradient(d, cot, fw)
+    p = Problem(w.desc)
+    p.set_coefficients(torch.tensor(eps_m, dtype=torch.float32, device="cuda"),
+                       torch.tensor(sig_m, dtype=torch.float32, device="cuda"))
+    tr = p.forward([src], save=True)
+    _, c = p.misfit(tr, torch.tensor(eobs[None], device="cuda"), z, loss=False)
+    p.adjoint(c)
+    ge, gs = (g.cpu().numpy() for g in p.gradient())
+    e1, e2 = _rel(ge, ag["g_eps"]), _rel(gs, ag["g_sigma"])
+    print(f"[gpu] weighted misfit gradient: eps {e1:.2e} sigma {e2:.2e}", flush=True)
+    assert e1 <= 1e-3 and e2 <= 1e-3
+    p.close()
+
+
+def test_cga_with_taper_and_loss_matches_oracle():
+    import torch
+    from oracle.cga import cga
+    from paper_2508_07780_amd import CGA, CGAParams, Problem
+    w = synth.small("ragged")
+    src = w.sources[0]
+    eobs = forward(Discretization(w.desc).set_coefficients(w.eps, w.sigma), src)["traces"][None]
+    n = len(w.eps)
+    eps0, sig0 = np.ones(n), np.zeros(n)
+    z = taper(w.desc.n_steps, w.desc.dt, 0.4 * w.desc.n_steps * w.desc.dt)
+    prm = dict(gamma_eps=0.5, gamma_sig=0.5, p=0.5, alpha_eps=3.0, alpha_sig=0.3, eps_max=8.0, sig_max=2.0)
+    ref = cga(Discretization(w.desc), [src], eobs, eps0, sig0, prm, 2, z=z)
+    p = Problem(w.desc)
+    c = CGA(p, [src], torch.tensor(eobs, dtype=torch.float32, device="cuda"), torch.tensor(eps0, device="cuda"),
+            torch.tensor(sig0, device="cuda"), CGAParams(**prm), z=z, track_loss=True)
+    starts = [(eps0, sig0), (ref[0]["eps"]["coef"], ref[0]["sig"]["coef"])]
+    for m in range(2):
+        c.iterate()
+        info = c.info()
+        tr = forward(Discretization(w.desc).set_coefficients(*starts[m]), src)["traces"]
+        tz = 1e-4 * math.sqrt(float(np.sum(z[:, None, None] * tr * tr)))
+        bound = math.sqrt(2.0 * ref[m]["J"]) * tz + 0.5 * tz * tz
+        print(f"[gpu] J m={m}: gpu {info['J']:.6e} oracle {ref[m]['J']:.6e} bound {bound:.2e}", flush=True)
+        assert abs(info["J"] - ref[m]["J"]) <= bound
+        for f, t, base in (("eps", c.eps, eps0), ("sig", c.sigma, sig0)):
+            err = _rel(t.cpu().numpy().astype(np.float64) - base, ref[m][f]["coef"] - base)
+            print(f"[gpu] cga with taper m={m} {f}: change rel L2 {err:.2e}, J {info['J']:.6e} vs {ref[m]['J']:.6e}",
+                  flush=True)
+            assert err <= 2e-3
+    c.close()
+    p.close()
