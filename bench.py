@@ -240,8 +240,8 @@ def paper_gradient_measure(prob, solve, eobs, t_exact):
 
 def cga_measure(prob, w, eobs, n_iter):
     """Reconstruction iterations (box "CGA") on the main workload from the paper's initial
-    guess eps = 1, sigma = 0: each iteration is a solve (forward with saving, misfit adjoint,
-    gradient) and the device update.  The step sizes and regularisation are set from the
+    guess eps = 1, sigma = 0: each iteration is a solve (forward with saving, the misfit J on
+    the device, misfit adjoint, gradient) and the device update.  The step sizes and regularisation are set from the
     gradient at the initial guess (setup, not timed): the first update moves eps by at most
     0.5 and sigma by at most 0.1, and gamma^0 = max|g^0| / that bound, so that alpha^1 =
     1 / gamma^0 keeps the same scale."""
@@ -258,7 +258,7 @@ def cga_measure(prob, w, eobs, n_iter):
     ge, gs = prob.gradient()
     prm = CGAParams.from_gradient(ge, gs, w.desc.h, eps_max=20.0, sig_max=3.0)
     del tr, ge, gs
-    c = CGA(prob, w.sources, eobs, eps0, sig0, prm)
+    c = CGA(prob, w.sources, eobs, eps0, sig0, prm, track_loss=True)
     ev = [torch.cuda.Event(enable_timing=True) for _ in range(2 * n_iter)]
     torch.cuda.synchronize()
     t0 = time.perf_counter()
@@ -283,7 +283,7 @@ def cga_measure(prob, w, eobs, n_iter):
         "update_us": round(upd_us, 2), "update_algorithmic_bytes": upd_bytes,
         "update_GBs": round(upd_bytes / (upd_us * 1e-6) / 1e9, 1),
         "params": {k: rnd(v) for k, v in vars(prm).items() if not k.startswith("eta")},
-        "history": [{"grad_norm": [rnd(i["grad_norm"]["eps"]), rnd(i["grad_norm"]["sig"])],
+        "history": [{"J": rnd(i["J"]), "grad_norm": [rnd(i["grad_norm"]["eps"]), rnd(i["grad_norm"]["sig"])],
                      "step_norm": [rnd(i["step_norm"]["eps"]), rnd(i["step_norm"]["sig"])],
                      "beta": [rnd(i["beta"]["eps"]), rnd(i["beta"]["sig"])]} for i in hist],
     }
