@@ -175,18 +175,35 @@ __global__ __launch_bounds__(CGA_THREADS) void cga_finish_kernel(const double* _
 
 // One pass over traces and observations: the weighted cotangent and the FP64 partials of J.
 // The difference of two float32 values is exact in FP64, so cot is that difference times z,
-// rounded once.
+// rounded once.  VEC: 16-byte accesses, four values of one row each (row_len a multiple of 4).
+template <bool VEC>
 __global__ __launch_bounds__(CGA_THREADS) void misfit_kernel(const float* __restrict__ traces,
                                                              const float* __restrict__ obs, int64_t n,
                                                              int64_t row_len, int64_t n_rows,
                                                              const double* __restrict__ z, float* cot,
                                                              double* __restrict__ part) {
   double acc[1] = {0.0};
-  for (int64_t i = (int64_t)blockIdx.x * CGA_THREADS + threadIdx.x; i < n; i += (int64_t)gridDim.x * CGA_THREADS) {
-    const double r = (double)traces[i] - (double)obs[i];
-    const double w = z ? z[(i / row_len) % n_rows] : 1.0;
-    if (cot) cot[i] = (float)(w * r);
-    acc[0] += w * r * r;
+  const int64_t stride = (int64_t)gridDim.x * CGA_THREADS;
+  if (VEC) {
+    const int64_t n4 = n / 4;
+    const float4* t4 = reinterpret_cast<const float4*>(traces);
+    const float4* o4 = reinterpret_cast<const float4*>(obs);
+    for (int64_t i = (int64_t)blockIdx.x * CGA_THREADS + threadIdx.x; i < n4; i += stride) {
+      const float4 tv = t4[i], ov = o4[i];
+      const double w = z ? z[(4 * i / row_len) % n_rows] : 1.0;
+      const double r0 = (double)tv.x - (double)ov.x, r1 = (double)tv.y - (double)ov.y;
+      const double r2 = (double)tv.z - (double)ov.z, r3 = (double)tv.w - (double)ov.w;
+      if (cot) reinterpret_cast<float4*>(cot)[i] = make_float4((float)(w * r0), (float)(w * r1), (float)(w * r2),
+                                                               (float)(w * r3));
+      acc[0] += w * (r0 * r0 + r1 * r1 + r2 * r2 + r3 * r3);
+    }
+  } else {
+    for (int64_t i = (int64_t)blockIdx.x * CGA_THREADS + threadIdx.x; i < n; i += stride) {
+      const double r = (double)traces[i] - (double)obs[i];
+      const double w = z ? z[(i / row_len) % n_rows] : 1.0;
+      if (cot) cot[i] = (float)(w * r);
+      acc[0] += w * r * r;
+    }
   }
   block_sums<1>(acc, part + blockIdx.x);
 }
@@ -227,7 +244,13 @@ void launch_cga_update(const double* gJe, const double* gJs, float* eps, float* 
 void launch_misfit(const float* traces, const float* obs, int64_t n, int64_t row_len, int64_t n_rows,
                    const double* z, float* cot, double* part, double* j, hipStream_t s) {
   const int nb = cga_blocks(n);
-  hipLaunchKernelGGL(misfit_kernel, dim3(nb), dim3(CGA_THREADS), 0, s, traces, obs, n, row_len, n_rows, z, cot, part);
+  const bool vec = row_len % 4 == 0 && ((uintptr_t)traces | (uintptr_t)obs | (uintptr_t)cot) % 16 == 0;
+  if (vec)
+    hipLaunchKernelGGL((misfit_kernel<true>), dim3(nb), dim3(CGA_THREADS), 0, s, traces, obs, n, row_len, n_rows, z,
+                       cot, part);
+  else
+    hipLaunchKernelGGL((misfit_kernel<false>), dim3(nb), dim3(CGA_THREADS), 0, s, traces, obs, n, row_len, n_rows, z,
+                       cot, part);
   if (j) hipLaunchKernelGGL(misfit_finish_kernel, dim3(1), dim3(CGA_THREADS), 0, s, part, nb, j);
 }
 

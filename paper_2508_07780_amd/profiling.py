@@ -51,7 +51,7 @@ def _rows(path_or_dir, suffix):
 
 
 def _short(name):
-    name = name.split("(")[0]
+    name = name.replace("(anonymous namespace)::", "").split("(")[0]
     return name.replace("void ", "").strip()
 
 

@@ -31,11 +31,13 @@ def _rel(a, b):
     return float(np.linalg.norm(np.asarray(a, dtype=np.float64) - b) / np.linalg.norm(b))
 
 
-def test_misfit_matches_oracle():
+@pytest.mark.parametrize("name", ["ragged", "skinlet"])   # trace rows of 3 * 4135 and 3 * 2304 floats
+def test_misfit_matches_oracle(name):
+    """Both the scalar pass and the 16-byte pass (rows a multiple of four floats)."""
     import torch
     from paper_2508_07780_amd import Problem
     from paper_2508_07780_amd.cga import taper_weights
-    w = synth.small("ragged")
+    w = synth.small(name)
     p = Problem(w.desc)
     nt = w.desc.n_steps
     shape = (2, nt, p.n_det, 3)
