@@ -10,6 +10,8 @@ true medium, for a seeded cotangent that this test regenerates from the same gen
 
 Bars: traces rel L2 <= 1e-4 (over the sampled entries, and over the per-step norms),
 gradient rel L2 <= 1e-3 (over the sampled entries, and the norms), energy rel L2 <= 1e-4.
+The paper-formula variant of the eps gradient (eq. gradeps with grad(eps~).E dropped),
+accumulated in the same adjoint, is held to the gradient bar too.
 """
 
 import os
@@ -47,11 +49,13 @@ def c2_run():
                        torch.tensor(w.sigma_true, dtype=torch.float32, device="cuda"))
     tr = p.forward(w.sources, save=True).clone()
     cot = mk.cotangent(tuple(tr.shape[1:]), w.seed)
+    p.paper_gradient(True)      # leaves the exact gradient bit for bit unchanged
     p.adjoint(torch.tensor(cot[None], device="cuda"))
     ge, gs = (g.cpu().numpy() for g in p.gradient())
+    gp = p.gradient_paper()[0].cpu().numpy()
     _, en = p.forward(w.sources, save=False, energy=True)
     torch.cuda.synchronize()
-    out = dict(traces=tr[0].cpu().numpy(), g_eps=ge, g_sigma=gs, energy=en[0].cpu().numpy())
+    out = dict(traces=tr[0].cpu().numpy(), g_eps=ge, g_sigma=gs, g_eps_paper=gp, energy=en[0].cpu().numpy())
     p.close()
     return ref, out
 
@@ -83,3 +87,12 @@ def test_c2_energy_matches_oracle(c2_run):
     e = _rel(out["energy"], ref["energy"])
     print(f"[gpu] c2 energy rel L2 {e:.3e}", flush=True)
     assert e <= 1e-4
+
+
+def test_c2_paper_gradient_matches_oracle(c2_run):
+    ref, out = c2_run
+    gi = ref["g_idx"]
+    e = _rel(out["g_eps_paper"][gi], ref["g_eps_paper"])
+    n = abs(np.linalg.norm(out["g_eps_paper"]) / float(ref["g_eps_paper_norm"]) - 1.0)
+    print(f"[gpu] c2 paper-formula gradient: sampled rel L2 {e:.3e}, norm ratio - 1 {n:.2e}", flush=True)
+    assert e <= 1e-3 and n <= 1e-3
