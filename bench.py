@@ -238,6 +238,21 @@ def paper_gradient_measure(prob, solve, eobs, t_exact):
             "rel_l2_vs_exact": round(rel, 4), "cosine_vs_exact": round(cos, 4)}
 
 
+def r2_measure(prob, solve, t_r1):
+    """The main workload's solve with the symmetric div-div form R2 (element mean of eps - 1
+    outside the divergence; the paper's gradient formula is then exact), against the R1 solve."""
+    import torch
+    prob.set_divdiv_form("R2")
+    solve()
+    torch.cuda.synchronize()
+    t0 = time.perf_counter()
+    solve()
+    torch.cuda.synchronize()
+    t = time.perf_counter() - t0
+    prob.set_divdiv_form("R1")
+    return {"solve_ms": round(t * 1e3, 2), "r1_solve_ms": round(t_r1 * 1e3, 2)}
+
+
 def cga_measure(prob, w, eobs, n_iter):
     """Reconstruction iterations (box "CGA") on the main workload from the paper's initial
     guess eps = 1, sigma = 0: each iteration is a solve (forward with saving, the misfit J on
@@ -453,6 +468,8 @@ def main():
     }
     if args.paper_gradient:
         out["paper_formula_gradient"] = paper_gradient_measure(prob, solve, eobs, elapsed / args.steps)
+    if args.paper_gradient:
+        out["r2_form"] = r2_measure(prob, solve, elapsed / args.steps)
     if args.cga:
         out["cga"] = cga_measure(prob, w, eobs, args.cga)
     del prob

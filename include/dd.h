@@ -162,6 +162,17 @@ int dd_adjoint_misfit(dd_problem* p, const float* traces_dev, const float* obs_d
 int dd_misfit(dd_problem* p, const float* traces_dev, const float* obs_dev, int32_t n_src, const double* z_host,
               float* cot_dev, double* j_dev, void* stream);
 
+/* Div-div form of the FEM rows.  DD_DIVDIV_R1 (default): the nodal product (eps - 1) E inside
+ * the element divergence, as eq. forward_prob writes it.  DD_DIVDIV_R2: the element mean of
+ * eps - 1 outside it, sum_K |K| (mean_K eps - 1) grad phi_i div_K(E) (symmetric); for this form
+ * the paper's gradient formula (eq. gradeps with grad(eps~).E dropped) is the exact gradient,
+ * and dd_gradient returns it.  R2 needs the assembled-stencil path (uniform Kuhn box;
+ * DD_ERR_UNSUPPORTED otherwise) and runs the FD and FEM parts of a step as separate launches
+ * (batched jobs then report DD_ERR_UNSUPPORTED).  Switching the form discards a saved forward.
+ * The first switch to R2 allocates FEM-node sized buffers and synchronises the device. */
+enum { DD_DIVDIV_R1 = 1, DD_DIVDIV_R2 = 2 };
+int dd_set_divdiv_form(dd_problem* p, int32_t form);
+
 /* Paper-formula gradient variant.  eq. gradeps writes the div-div part of g_eps as the
  * time integral of div(lambda) div(E), having replaced div(eps~ E) by eps~ div(E); on the
  * discrete scheme that term is sum_k sum_{K containing i} (|K|/4) div_K(lambda^k) div_K(E^k)

@@ -69,6 +69,7 @@ struct dd_problem {
   std::vector<double> mis_z_host;
   // paper-formula gradient variant: FEM-node -> owned id map, FP64 sum
   bool pg_on = false, have_pg = false;
+  bool r2 = false;        // div-div form R2 (FEM kernels in separate launches)
   int* api_own = nullptr;
   double* pg_acc = nullptr;
   std::string err;
@@ -232,6 +233,8 @@ FemArgs fem_base(const dd_problem* p) {
   a.em1 = p->em1; a.c1 = p->c1; a.c2 = p->c2; a.mass_d = p->mass_d;
   a.n_own = p->n_own; a.n_l0 = p->n_l0; a.N = p->N;
   a.epart_off = p->n_tiles;
+  a.r2 = p->r2 ? 1 : 0;
+  a.h = (float)p->d.h;
   const double dt = p->d.dt;
   a.inv_2dt2 = 1.0 / (2.0 * dt * dt);
   a.inv_dt2 = 1.0 / (dt * dt);
@@ -535,8 +538,8 @@ int run_adjoint(dd_problem* p, int s, const float* cot, const float* obs, hipStr
         step_barrier(p, st);
       }
       // lambda^k (ea.X_in) is overwritten two steps later, on the same stream
-      if (p->pg_on)
-        launch_paper_grad_step(ea.X_in, ea.wE, p->n_own, p->api_own, p->fs, p->d.h, p->pg_acc, st);
+      if (p->pg_on || p->r2)
+        launch_paper_grad_step(ea.X_in, ea.wE, p->n_own, p->api_own, p->fs, p->d.h, !p->r2, p->pg_acc, st);
     }
     if (pipe && seg >= 2) {
       (void)hipEventRecord(p->ev_adj, st);
@@ -785,14 +788,14 @@ namespace {
 int adjoint_all(dd_problem* p, const float* cot, const float* obs, hipStream_t st) {
   launch_fill_f64(p->g_eps, p->n_own, 0.0, st);
   launch_fill_f64(p->g_sig, p->n_own, 0.0, st);
-  if (p->pg_on) launch_fill_f64(p->pg_acc, p->n_fem, 0.0, st);
+  if (p->pg_on || p->r2) launch_fill_f64(p->pg_acc, p->n_fem, 0.0, st);
   p->adj_obs = obs != nullptr;
   for (int s = 0; s < p->saved_n_src; ++s) {
     int rc = run_adjoint(p, s, cot, obs, st);
     if (rc) return rc;
   }
   p->have_grad = true;
-  p->have_pg = p->pg_on;
+  p->have_pg = p->pg_on || p->r2;
   return DD_OK;
 }
 }  // namespace
@@ -819,6 +822,7 @@ int dd_gradient(dd_problem* p, double* g_eps_dev, double* g_sigma_dev, void* str
   launch_fill_f64(g_eps_dev, p->n_fem, 0.0, st);
   launch_fill_f64(g_sigma_dev, p->n_fem, 0.0, st);
   launch_gradient_out(p->g_eps, p->g_sig, p->own_api, p->own_grid, p->n_own, g_eps_dev, g_sigma_dev, st);
+  if (p->r2) launch_add_free(p->pg_acc, p->fs, g_eps_dev, st);   // R2: the div-div part is the paper term
   return check_launch(p);
 }
 
@@ -851,12 +855,8 @@ int dd_misfit(dd_problem* p, const float* traces_dev, const float* obs_dev, int3
   return check_launch(p);
 }
 
-int dd_paper_gradient_enable(dd_problem* p, int32_t on) {
-  if (!p) return DD_ERR_INVALID_ARG;
-  if (!on) {
-    p->pg_on = false;
-    return DD_OK;
-  }
+namespace {
+int pg_setup(dd_problem* p) {
   if (p->overlap) return fail(p, DD_ERR_UNSUPPORTED, "the paper-formula gradient needs the single-stream step order");
   if (!p->api_own) {
     int rc = dalloc(p, &p->api_own, (size_t)p->n_fem);
@@ -866,7 +866,35 @@ int dd_paper_gradient_enable(dd_problem* p, int32_t on) {
     if (int rc2 = check_launch(p)) return rc2;
     if (hipStreamSynchronize(nullptr) != hipSuccess) return fail(p, DD_ERR_HIP, "stream synchronize failed");
   }
+  return DD_OK;
+}
+}  // namespace
+
+int dd_paper_gradient_enable(dd_problem* p, int32_t on) {
+  if (!p) return DD_ERR_INVALID_ARG;
+  if (!on) {
+    p->pg_on = false;
+    return DD_OK;
+  }
+  if (int rc = pg_setup(p)) return rc;
   p->pg_on = true;
+  return DD_OK;
+}
+
+int dd_set_divdiv_form(dd_problem* p, int32_t form) {
+  if (!p) return DD_ERR_INVALID_ARG;
+  if (form != DD_DIVDIV_R1 && form != DD_DIVDIV_R2) return fail(p, DD_ERR_INVALID_ARG, "unknown div-div form");
+  const bool r2 = form == DD_DIVDIV_R2;
+  if (r2 == p->r2) return DD_OK;
+  if (r2) {
+    if (!p->use_stencil) return fail(p, DD_ERR_UNSUPPORTED, "the R2 form needs the assembled-stencil FEM path");
+    if (int rc = pg_setup(p)) return rc;
+  }
+  p->r2 = r2;
+  p->fused = !r2;          // R2 runs the FD tiles and the FEM partitions in separate launches
+  p->saved = false;        // a saved forward of the other form no longer matches
+  p->have_grad = false;
+  p->have_pg = false;
   return DD_OK;
 }
 

@@ -152,6 +152,8 @@ struct FemArgs {
   int n_slots, lds_box;
   int n_part;
   int rev;             // 1: each XCD takes its partitions in reverse order (alternate steps)
+  int r2;              // div-div form R2 (element mean of eps - 1 outside the divergence)
+  float h;             // grid spacing (the R2 term is evaluated element by element)
   // adjoint
   const float* wE; const float* wV; const float* wVm;  // forward E^k, V^k, V^{k-1} [3][n_own]
   double* g_eps; double* g_sig;

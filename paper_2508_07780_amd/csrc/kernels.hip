@@ -571,7 +571,48 @@ __global__ __launch_bounds__(FEM_THREADS) void fem_step_kernel(FemArgs a) {
 // applies).  Results equal the element form up to floating-point rounding; there is no
 // scatter, hence no colouring and no barrier after the staging.
 // ---------------------------------------------------------------------------------------
-template <bool ADJ, bool ENERGY>
+// The div-div form R2, sum_K |K| (mean_K eps - 1) grad phi_i div_K(u), is symmetric and has
+// no fixed stencil (its coefficient varies by element), so it is evaluated element by
+// element from the staged box: a Kuhn cell holds one tetrahedron per axis permutation
+// (a, b, c) with v1 = e_a, v2 = e_a + e_b, v3 = (1,1,1); h grad phi of its vertices is -e_a,
+// e_a - e_b, e_b - e_c, e_c, |K| = h^3 / 6, and h div_K(u) = (u_v1 - u_v0)_a + (u_v2 - u_v1)_b
+// + (u_v3 - u_v2)_c.  Cells touching layer 0 have mean eps - 1 = 0, so the same form serves
+// the forward and (restricted to the FEM rows) the adjoint.
+__device__ __forceinline__ float f4c(const float4& v, int c) { return c == 0 ? v.x : (c == 1 ? v.y : v.z); }
+
+// (h / 6) sum over the 24 tetrahedra around box node (bx, by, bz) of mean(w) (h grad phi_i) (h div u)
+__device__ __forceinline__ void r2_term(const float4* sX, int BX, int BY, int bx, int by, int bz, float h, float r[3]) {
+  // axis permutations (a, b, c); a compile-time table, so that the unrolled loops index
+  // registers, not memory
+  constexpr int kKuhnPerm[6][3] = {{0, 1, 2}, {0, 2, 1}, {1, 0, 2}, {1, 2, 0}, {2, 0, 1}, {2, 1, 0}};
+  float d[3] = {0.f, 0.f, 0.f};
+#pragma unroll
+  for (int o = 0; o < 8; ++o) {
+    const int cb = (bx - (o & 1)) + BX * ((by - ((o >> 1) & 1)) + BY * (bz - (o >> 2)));
+    float4 v[8];
+#pragma unroll
+    for (int u = 0; u < 8; ++u) v[u] = sX[cb + (u & 1) + BX * (((u >> 1) & 1) + BY * (u >> 2))];
+#pragma unroll
+    for (int t = 0; t < 6; ++t) {
+      const int ax = kKuhnPerm[t][0], bx2 = kKuhnPerm[t][1], cx = kKuhnPerm[t][2];
+      const int v1 = 1 << ax, v2 = v1 | (1 << bx2);
+      if (o != 0 && o != v1 && o != v2 && o != 7) continue;
+      const float eb = 0.25f * (v[0].w + v[v1].w + v[v2].w + v[7].w);
+      const float dl = (f4c(v[v1], ax) - f4c(v[0], ax)) + (f4c(v[v2], bx2) - f4c(v[v1], bx2)) +
+                       (f4c(v[7], cx) - f4c(v[v2], cx));
+      const float f = eb * dl;
+      if (o == 0) d[ax] -= f;
+      else if (o == v1) { d[ax] += f; d[bx2] -= f; }
+      else if (o == v2) { d[bx2] += f; d[cx] -= f; }
+      else d[cx] += f;
+    }
+  }
+  const float k = h * (1.f / 6.f);
+#pragma unroll
+  for (int c = 0; c < 3; ++c) r[c] += k * d[c];
+}
+
+template <bool ADJ, bool ENERGY, bool R2 = false>
 __device__ __forceinline__ void fem_stencil_part(const FemArgs& a, const int p) {
   constexpr int NPT = FEM_OWN_MAX / STENCIL_THREADS;
   extern __shared__ __align__(16) unsigned char lds[];
@@ -614,7 +655,7 @@ __device__ __forceinline__ void fem_stencil_part(const FemArgs& a, const int p) 
         xv[k].x = a.X_in[id];
         xv[k].y = a.X_in[n_own + id];
         xv[k].z = a.X_in[2 * n_own + id];
-        if (!ADJ) xv[k].w = a.em1[id];
+        if (!ADJ || R2) xv[k].w = a.em1[id];
       } else if (l < nbox) {
         const int64_t q = -1 - (int64_t)code[k];
         xv[k].x = a.iface_in[q];
@@ -661,7 +702,9 @@ __device__ __forceinline__ void fem_stencil_part(const FemArgs& a, const int p) 
       r[0] += K * x.x;
       r[1] += K * x.y;
       r[2] += K * x.z;
-      if (ADJ) {
+      if (R2) {
+        // the div-div term follows below, element by element
+      } else if (ADJ) {
         q[0] += kb[1] * x.x + kb[2] * x.y + kb[3] * x.z;
         q[1] += kb[4] * x.x + kb[5] * x.y + kb[6] * x.z;
         q[2] += kb[7] * x.x + kb[8] * x.y + kb[9] * x.z;
@@ -672,7 +715,8 @@ __device__ __forceinline__ void fem_stencil_part(const FemArgs& a, const int p) 
         r[2] += kb[7] * w0 + kb[8] * w1 + kb[9] * w2;
       }
     }
-    if (ADJ) {
+    if (R2) r2_term(sX, BX, BY, ix + 1, iy + 1, iz + 1, a.h, r);
+    else if (ADJ) {
 #pragma unroll
       for (int c = 0; c < 3; ++c) r[c] += pem[j] * q[c];
     }
@@ -718,7 +762,8 @@ __device__ __forceinline__ void fem_stencil_part(const FemArgs& a, const int p) 
 #pragma unroll
       for (int c = 0; c < 3; ++c) {
         const double wv = (double)__builtin_nontemporal_load(a.wV + c * n_own + id);
-        ge += (double)q[c] * (double)__builtin_nontemporal_load(a.wE + c * n_own + id);
+        // R2: the div-div part of the eps gradient is added by the paper-formula kernel
+        if (!R2) ge += (double)q[c] * (double)__builtin_nontemporal_load(a.wE + c * n_own + id);
         gm += (double)inc[c] * wv;
         gs += (double)xn[c] * (wv + (double)__builtin_nontemporal_load(a.wVm + c * n_own + id));
       }
@@ -747,10 +792,10 @@ __device__ __forceinline__ int fem_part_of_block(int b, int blocks, int rev) {
   return (b % N_XCD) * per + (rev ? per - 1 - b / N_XCD : b / N_XCD);
 }
 
-template <bool ADJ, bool ENERGY>
+template <bool ADJ, bool ENERGY, bool R2>
 __global__ __launch_bounds__(STENCIL_THREADS) void fem_stencil_kernel(FemArgs a) {
   const int p = fem_part_of_block(blockIdx.x, gridDim.x, a.rev);
-  if (p < a.n_part) fem_stencil_part<ADJ, ENERGY>(a, p);
+  if (p < a.n_part) fem_stencil_part<ADJ, ENERGY, R2>(a, p);
 }
 
 // One launch per time step: blocks [0, fem_blocks) advance the FEM partitions (scheduled
@@ -948,16 +993,27 @@ static size_t stencil_lds_bytes(const FemArgs& a) {
   return (size_t)a.lds_box * 16 + 12 * 4 * STENCIL_SLOTS_MAX + 4 * STENCIL_SLOTS_MAX;
 }
 
-void launch_fem_stencil_fwd(const FemArgs& a, int n_part, hipStream_t s, bool energy) {
+template <bool R2>
+static void launch_fem_stencil_fwd_t(const FemArgs& a, int n_part, hipStream_t s, bool energy) {
   const size_t lds = stencil_lds_bytes(a);
   if (energy)
-    hipLaunchKernelGGL((fem_stencil_kernel<false, true>), dim3(xcd_round(n_part)), dim3(STENCIL_THREADS), lds, s, a);
+    hipLaunchKernelGGL((fem_stencil_kernel<false, true, R2>), dim3(xcd_round(n_part)), dim3(STENCIL_THREADS), lds, s, a);
   else
-    hipLaunchKernelGGL((fem_stencil_kernel<false, false>), dim3(xcd_round(n_part)), dim3(STENCIL_THREADS), lds, s, a);
+    hipLaunchKernelGGL((fem_stencil_kernel<false, false, R2>), dim3(xcd_round(n_part)), dim3(STENCIL_THREADS), lds, s, a);
+}
+
+void launch_fem_stencil_fwd(const FemArgs& a, int n_part, hipStream_t s, bool energy) {
+  if (a.r2) launch_fem_stencil_fwd_t<true>(a, n_part, s, energy);
+  else launch_fem_stencil_fwd_t<false>(a, n_part, s, energy);
 }
 
 void launch_fem_stencil_adj(const FemArgs& a, int n_part, hipStream_t s) {
-  hipLaunchKernelGGL((fem_stencil_kernel<true, false>), dim3(xcd_round(n_part)), dim3(STENCIL_THREADS), stencil_lds_bytes(a), s, a);
+  if (a.r2)
+    hipLaunchKernelGGL((fem_stencil_kernel<true, false, true>), dim3(xcd_round(n_part)), dim3(STENCIL_THREADS),
+                       stencil_lds_bytes(a), s, a);
+  else
+    hipLaunchKernelGGL((fem_stencil_kernel<true, false, false>), dim3(xcd_round(n_part)), dim3(STENCIL_THREADS),
+                       stencil_lds_bytes(a), s, a);
 }
 
 template <bool NT>

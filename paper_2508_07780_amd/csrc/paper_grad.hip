@@ -47,7 +47,8 @@ constexpr int PG_CX = PG_TX + 1, PG_CY = PG_TY + 1, PG_CZ = PG_TZ + 1;  // cells
 
 __global__ __launch_bounds__(256) void pg_step_kernel(const float* __restrict__ lam, const float* __restrict__ E,
                                                       int64_t n_own, const int* __restrict__ api_own, int fsx,
-                                                      int fsy, int fsz, double h, double* __restrict__ acc) {
+                                                      int fsy, int fsz, double h, int sub_exact,
+                                                      double* __restrict__ acc) {
   __shared__ float sl[3][PG_NZ][PG_NY][PG_NX];
   __shared__ float se[3][PG_NZ][PG_NY][PG_NX];
   __shared__ float2 sc[6][PG_CZ][PG_CY][PG_CX];
@@ -106,7 +107,7 @@ __global__ __launch_bounds__(256) void pg_step_kernel(const float* __restrict__ 
       else if (o == 7) gE = Ei[c];
       else continue;
       const float2 v = sc[k][cz][cy][cx];
-      s += (double)v.x * ((double)v.y - 4.0 * (double)gE);
+      s += (double)v.x * ((double)v.y - (sub_exact ? 4.0 * (double)gE : 0.0));
     }
   }
   acc[(int64_t)lx + fsx * ((int64_t)ly + (int64_t)fsy * lz)] += s * (h / 24.0);
@@ -131,12 +132,12 @@ void launch_invert_own(const int* own_api, int64_t n_own, int64_t n_fem, int* ap
 }
 
 void launch_paper_grad_step(const float* lam, const float* E, int64_t n_own, const int* api_own, const int fs[3],
-                            double h, double* acc, hipStream_t s) {
+                            double h, bool sub_exact, double* acc, hipStream_t s) {
   if (fs[0] < 5 || fs[1] < 5 || fs[2] < 5) return;   // no free node
   const int tbx = (fs[0] - 4 + PG_TX - 1) / PG_TX, tby = (fs[1] - 4 + PG_TY - 1) / PG_TY;
   const int tbz = (fs[2] - 4 + PG_TZ - 1) / PG_TZ;
   hipLaunchKernelGGL(pg_step_kernel, dim3(tbx * tby * tbz), dim3(256), 0, s, lam, E, n_own, api_own, fs[0], fs[1],
-                     fs[2], h, acc);
+                     fs[2], h, sub_exact ? 1 : 0, acc);
 }
 
 void launch_add_free(const double* acc, const int fs[3], double* out_eps, hipStream_t s) {

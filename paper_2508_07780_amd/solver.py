@@ -149,6 +149,12 @@ class Problem:
                                          _ptr(J) if J is not None else None, _stream()), self._h)
         return J, cot
 
+    def set_divdiv_form(self, form):
+        """"R1" (the scheme of eq. forward_prob) or "R2" (element mean of eps - 1 outside the
+        divergence; the paper's gradient formula is then exact)."""
+        code = {"R1": 1, "R2": 2}[form]
+        _lib.check(_lib.load().dd_set_divdiv_form(self._h, code), self._h)
+
     def paper_gradient(self, on=True):
         """Accumulate the paper-formula gradient variant in the following adjoints."""
         _lib.check(_lib.load().dd_paper_gradient_enable(self._h, 1 if on else 0), self._h)
