@@ -2,7 +2,12 @@
 
 Forward (box "Forward problem" with the model problem eq. model1):
     D+^n E^{n+1} = (2 M_eps/dt^2 - A) E^n - D-^n E^{n-1} + F^n,
-    D+-^n = M_eps/dt^2 +- (M_sigma + S^n)/(2 dt),    E^0 = E^{-1} = 0.
+    D+-^n = M_eps/dt^2 +- (M_sigma + S^n)/(2 dt).
+The model problem starts from rest, E^0 = E^{-1} = 0.  General initial data (eq.
+forward_initial_cond, E(0) = f_0, dE/dt(0) = f_1) gives the two starting levels
+E^0 = f_0 and E^{-1} = f_0 - dt f_1 (the one-sided difference of dE/dt at t = 0), so the
+starting increment is V^0 = E^0 - E^{-1} = dt f_1; both levels are independent of eps and
+sigma.
 Traces T^n = E^n on the detector nodes for n = 1..N_t.
 
 Loss: J = 1/2 sum_n sum_detectors |T^n - E_obs^n|^2 (eq. tikhonov_functional with
@@ -19,8 +24,13 @@ taken exactly on the discrete scheme):
     dJ/deps_i   = sum_{n=0}^{N_t-1} [ m_i lambda^n_i . (E^{n+1} - 2E^n + E^{n-1})_i / dt^2
                                       + sum_{K ∋ i} |K| div_K(lambda^n) (grad phi_i . E^n_i) ],
     dJ/dsigma_i = sum_{n=0}^{N_t-1} m_i lambda^n_i . (E^{n+1} - E^{n-1})_i / (2 dt),
-on free FEM nodes (layer >= 2), zero elsewhere.  The f_1 term of eq. gradeps
-vanishes because the model problem starts from rest.
+on free FEM nodes (layer >= 2), zero elsewhere.  The -lambda(x, 0) f_1 term of eq. gradeps
+is the n = 0 row of the mass term, where E^{-1} = E^0 - V^0 with V^0 = dt f_1: summed by
+parts,
+    sum_n lambda^n . (V^{n+1} - V^n) = -sum_n (lambda^{n+1} - lambda^n) . V^{n+1} - lambda^0 . V^0
+(lambda^{N_t} = 0), the discrete -int lambda_t . E_t plus the boundary term
+-lambda^0 . V^0 = -dt lambda^0 . f_1.
+It vanishes when the problem starts from rest.
 
 The paper's own gradient formula (eq. gradeps with div((eps~) E) ~ eps~ div E) replaces
 the div-div term by
@@ -67,10 +77,12 @@ def forcing(d, src, n):
     return F
 
 
-def forward(d, src=None, n_steps=None, force=None, keep_full=False):
+def forward(d, src=None, n_steps=None, force=None, keep_full=False, initial=None):
     """Run the forward recursion.
 
-    ``src`` is a synth Source, or ``force`` a callable n -> F^n (N, 3).
+    ``src`` is a synth Source, or ``force`` a callable n -> F^n (N, 3).  ``initial`` is
+    None (start from rest) or (f_0, f_1), each (N, 3) over the grid: E^0 = f_0,
+    E^{-1} = f_0 - dt f_1.
     Returns a dict with traces (N_t, n_det, 3), energy W^{n+1/2} (N_t,),
     balance residual (N_t,), E on FEM nodes for levels -1..N_t (N_t+2, n_fem, 3)
     and, if ``keep_full``, E on the whole grid for levels -1..N_t.
@@ -80,12 +92,20 @@ def forward(d, src=None, n_steps=None, force=None, keep_full=False):
     Me = d.M_eps[:, None]
     E_prev = np.zeros((d.N, 3))
     E_cur = np.zeros((d.N, 3))
+    w_prev = 0.0
+    if initial is not None:
+        E_cur = np.array(initial[0], dtype=np.float64).reshape(d.N, 3)
+        V0 = dt * np.asarray(initial[1], dtype=np.float64).reshape(d.N, 3)
+        E_prev = E_cur - V0
+        # W^{-1/2}: the energy of the starting pair, in the form of W^{n+1/2} below
+        w_prev = 0.5 * np.sum(Me * V0 * V0) / dt ** 2 + 0.5 * np.sum(E_cur * d.apply_A(E_prev))
     traces = np.zeros((nt, len(d.det), 3))
     energy = np.zeros(nt)
     balance = np.zeros(nt)
     fem_hist = np.zeros((nt + 2, d.n_fem, 3))
+    fem_hist[0] = E_prev[d.fem_grid]
+    fem_hist[1] = E_cur[d.fem_grid]
     full = [E_prev.copy(), E_cur.copy()] if keep_full else None
-    w_prev = 0.0
     for n in range(nt):
         F = force(n) if force is not None else forcing(d, src, n)
         C = (d.M_sig + d.damping(n))[:, None]
@@ -179,9 +199,11 @@ def adjoint_gradient(d, cot, fwd, keep_lambda=False):
             lams[n] = lam_prev
         lam_next, lam_cur = lam_cur, lam_prev
     # summation by parts of the mass term: -sum_n m (lambda^{n+1} - lambda^n) . (E^{n+1} - E^n) / dt^2
+    # plus the boundary term -m lambda^0 . V^0 / dt^2 of the starting levels (zero from rest)
     g_mass_sbp = np.zeros(d.n_fem)
     for n in range(nt):
         g_mass_sbp -= m * np.sum((lam_f[n + 1] - lam_f[n]) * (Eh[n + 2] - Eh[n + 1]), axis=1) / dt ** 2
+    g_mass_sbp -= m * np.sum(lam_f[0] * (Eh[1] - Eh[0]), axis=1) / dt ** 2
     free = d.fem_free
     g_eps_paper = np.where(free, g_mass + g_dd_paper, 0.0)
     if getattr(d, "divdiv_form", "R1") == "R2":

@@ -229,6 +229,32 @@ def random_media(desc, rng, eps_max=5.0, sig_max=1.0):
     return eps, sig
 
 
+def initial_pulses(desc: ProblemDesc, seed: int, n_pulses: int = 3):
+    """Seeded smooth initial data (f_0, f_1) over the whole grid, each (N, 3), node index
+    x + Nx (y + Ny z): sums of Gaussian bumps of width 3h..6h with random centres (inside the
+    grid, several within the FEM box) and random polarisations; f_1 has its own bumps."""
+    rng = np.random.Generator(np.random.PCG64(seed))
+    nx, ny, nz = (int(v) for v in desc.n_outer)
+    lz, ly, lx = np.meshgrid(np.arange(nz), np.arange(ny), np.arange(nx), indexing="ij")
+    pts = np.stack([lx, ly, lz], axis=-1).reshape(-1, 3).astype(np.float64)
+    lo = np.asarray(desc.fem_lo, dtype=np.float64)
+    hi = lo + np.asarray(desc.fem_cells, dtype=np.float64)
+    out = []
+    for _ in range(2):
+        f = np.zeros((pts.shape[0], 3))
+        for b in range(n_pulses):
+            if b % 2 == 0:
+                c = rng.uniform(lo, hi)
+            else:
+                c = rng.uniform(0.0, 1.0, 3) * (np.array([nx, ny, nz]) - 1.0)
+            w = rng.uniform(3.0, 6.0)
+            pol = rng.standard_normal(3)
+            r2 = np.sum((pts - c) ** 2, axis=1)
+            f += np.exp(-0.5 * r2 / (w * w))[:, None] * pol[None, :]
+        out.append(f)
+    return out[0], out[1]
+
+
 def noise(shape, seed):
     """Standard normal noise, PCG64 seeded."""
     return np.random.Generator(np.random.PCG64(seed)).standard_normal(shape)
