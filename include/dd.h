@@ -121,7 +121,8 @@ size_t dd_footprint_bytes(const dd_problem_desc* desc, int32_t n_src);
  * previous coefficients stay.  Synchronises `stream`. */
 int dd_set_coefficients(dd_problem* p, const float* eps_dev, const float* sigma_dev, void* stream);
 
-/* Forward solve of each source from rest (E = E_t = 0 at t = 0).
+/* Forward solve of each source from rest (E = E_t = 0 at t = 0), or from the initial data
+ * set by dd_set_initial_data.
  * traces_dev: [n_src][n_steps][n_det][3] float32 output.
  * save: nonzero keeps what dd_adjoint needs (FEM checkpoints every ckpt_every steps
  *       and the per-step layer-0 interface values), per source.
@@ -129,6 +130,23 @@ int dd_set_coefficients(dd_problem* p, const float* eps_dev, const float* sigma_
  *       W^{n+1/2} = |V^{n+1}|^2_{M_eps} / (2 dt^2) + E^{n+1} . A E^n / 2. */
 int dd_forward(dd_problem* p, const dd_source* src, int32_t n_src, float* traces_dev,
                int32_t save, double* energy_dev, void* stream);
+
+/* General initial data of the forward problem (eq. forward_initial_cond): E(x, 0) = f_0,
+ * dE/dt(x, 0) = f_1.  f0_dev, f1_dev: [n_grid][3] float32 on the device, node index
+ * x + Nx (y + Ny z), copied into library-owned buffers on `stream` (the caller's arrays may
+ * be freed once that stream has passed the call).  The scheme starts from the levels
+ * E^0 = f_0 and E^{-1} = f_0 - dt f_1 (the one-sided difference of dE/dt at t = 0), for every
+ * source of the following dd_forward calls; values are used as given (non-finite data shows
+ * up as DD_ERR_UNSTABLE only where the solver checks its fields).  The gradient of the
+ * following adjoints is the exact derivative with both levels held fixed: its level-0 rows
+ * hold the -lambda(x, 0) f_1 term of eq. gradeps (as -m_i lambda^0 . dt f_1 / dt^2) and the
+ * level-0 div-div term, for either div-div form and for dd_gradient_paper.
+ * Both NULL: start from rest again.  One NULL: DD_ERR_INVALID_ARG.  Setting or clearing the
+ * data discards a saved forward.  The first call allocates 24 n_grid + 12 n_fem_nodes bytes
+ * and may synchronise the device; DD_ERR_UNSUPPORTED when FD and FEM run on two streams.
+ * Batched jobs (dd_batch_submit) always start from rest and are refused (DD_ERR_UNSUPPORTED)
+ * while initial data is set. */
+int dd_set_initial_data(dd_problem* p, const float* f0_dev, const float* f1_dev, void* stream);
 
 /* Adjoint solve (eq. adjoint_prob, exact transpose of the discrete forward scheme)
  * for each source of the last saved dd_forward, with the trace cotangent

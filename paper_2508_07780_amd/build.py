@@ -8,7 +8,7 @@ HERE = os.path.dirname(os.path.abspath(__file__))
 ROOT = os.path.dirname(HERE)
 CSRC = os.path.join(HERE, "csrc")
 LIB = os.path.join(HERE, "libddfem.so")
-SOURCES = ["kernels.hip", "cga.hip", "paper_grad.hip", "mesh.cpp", "api.cpp"]
+SOURCES = ["kernels.hip", "cga.hip", "paper_grad.hip", "initial.hip", "mesh.cpp", "api.cpp"]
 ARCH = os.environ.get("DD_OFFLOAD_ARCH", "gfx950")
 
 

@@ -13,6 +13,7 @@
 #include <new>
 
 #include "cga.hpp"
+#include "initial.hpp"
 #include "paper_grad.hpp"
 #include "dd_common.hpp"
 
@@ -72,6 +73,11 @@ struct dd_problem {
   bool r2 = false;        // div-div form R2 (FEM kernels in separate launches)
   int* api_own = nullptr;
   double* pg_acc = nullptr;
+  // general initial data (dd_set_initial_data): f_0, f_1 [N][3]; the level-0 div-div rows of
+  // the exact R1 gradient (FEM-node index), added by dd_gradient when the last adjoint set them
+  bool init_on = false, ic_used = false;
+  float *init_f0 = nullptr, *init_f1 = nullptr;
+  double* ic_acc = nullptr;
   std::string err;
   std::vector<void*> allocs;
   // kernel timing: event pairs around each step launch, per launch kind
@@ -343,13 +349,23 @@ SrcPlan source_plan(const dd_problem* p, const dd_source& src) {
   return sp;
 }
 
-// Zeroes the state and the level-0 entries of the saved forward of source s.
-void forward_prologue(dd_problem* p, int s, bool save, hipStream_t st) {
+// Starting state (rest, or the levels of the initial data when `initial`) and the level-0
+// entries of the saved forward of source s.
+void forward_prologue(dd_problem* p, int s, bool save, bool initial, hipStream_t st) {
   zero_state(p, st);
   if (save) {
     launch_fill_f32(p->ihist[s], 3 * p->n_l0, 0.f, st);   // layer-0 values of level 0
     launch_fill_f32(p->ckpt[s], 6 * p->n_own, 0.f, st);   // checkpoint of level 0
     if (last_segment_start(p) == 0) launch_fill_f32(p->tail[s], 6 * p->n_own, 0.f, st);
+  }
+  if (initial && p->init_on) {
+    // level 0 in Efd[0] / Efem[0], level -1 in Efd[1], the increment V^0 in Vfem
+    const int blo[3] = {p->d.fem_lo[0], p->d.fem_lo[1], p->d.fem_lo[2]};
+    launch_init_grid(p->init_f0, p->init_f1, p->d.dt, p->nx, p->ny, p->nz, blo, p->fs, p->n_l0, p->Efd[0], p->Efd[1],
+                     save ? p->ihist[s] : p->iring, st);
+    launch_init_own(p->init_f0, p->init_f1, p->d.dt, p->own_api, p->n_own, p->nx, p->ny, blo, p->fs, p->Efem[0],
+                    p->Vfem, save ? p->ckpt[s] : nullptr,
+                    (save && last_segment_start(p) == 0) ? p->tail[s] : nullptr, st);
   }
 }
 
@@ -449,7 +465,7 @@ void adj_step_args(const dd_problem* p, int s, int64_t k, int64_t k0, const floa
 
 int run_forward(dd_problem* p, const dd_source& src, int s, float* traces, bool save, double* energy, hipStream_t st) {
   const int64_t nt = p->d.n_steps;
-  forward_prologue(p, s, save, st);
+  forward_prologue(p, s, save, true, st);
   hipStream_t sf = p->overlap ? p->aux : st;           // stream of the FEM launches
   fork_streams(p, st);
   FdArgs fa = fd_base(p);
@@ -549,6 +565,21 @@ int run_adjoint(dd_problem* p, int s, const float* cot, const float* obs, hipStr
   }
   // pipelined: every recompute queued on aux has been waited for by a segment on st
   if (!pipe) join_streams(p, st);
+  if (p->init_on) {
+    // level-0 rows of the gradient: lambda^0 (the last step's output, Efem[0]) against the
+    // stored level 0 (E^0, V^0) of this source
+    const float* lam0 = p->Efem[0];
+    const float* lvl0 = (nseg == 1) ? p->tail[s] : p->ckpt[s];
+    launch_init_mass_row(lam0, lvl0 + 3 * p->n_own, p->own_grid, p->mass_d, p->n_own, 1.0 / (p->d.dt * p->d.dt),
+                         p->g_eps, st);
+    if (p->r2) {
+      launch_divdiv_grad_terms(lam0, lvl0, p->n_own, p->api_own, p->fs, p->d.h, 1.0, 0.0, p->pg_acc, st);
+    } else {
+      launch_divdiv_grad_terms(lam0, lvl0, p->n_own, p->api_own, p->fs, p->d.h, 0.0, -1.0, p->ic_acc, st);
+      if (p->pg_on)
+        launch_divdiv_grad_terms(lam0, lvl0, p->n_own, p->api_own, p->fs, p->d.h, 1.0, 1.0, p->pg_acc, st);
+    }
+  }
   return check_launch(p);
 }
 
@@ -789,6 +820,8 @@ int adjoint_all(dd_problem* p, const float* cot, const float* obs, hipStream_t s
   launch_fill_f64(p->g_eps, p->n_own, 0.0, st);
   launch_fill_f64(p->g_sig, p->n_own, 0.0, st);
   if (p->pg_on || p->r2) launch_fill_f64(p->pg_acc, p->n_fem, 0.0, st);
+  p->ic_used = p->init_on && !p->r2;
+  if (p->ic_used) launch_fill_f64(p->ic_acc, p->n_fem, 0.0, st);
   p->adj_obs = obs != nullptr;
   for (int s = 0; s < p->saved_n_src; ++s) {
     int rc = run_adjoint(p, s, cot, obs, st);
@@ -823,6 +856,7 @@ int dd_gradient(dd_problem* p, double* g_eps_dev, double* g_sigma_dev, void* str
   launch_fill_f64(g_sigma_dev, p->n_fem, 0.0, st);
   launch_gradient_out(p->g_eps, p->g_sig, p->own_api, p->own_grid, p->n_own, g_eps_dev, g_sigma_dev, st);
   if (p->r2) launch_add_free(p->pg_acc, p->fs, g_eps_dev, st);   // R2: the div-div part is the paper term
+  if (p->ic_used) launch_add_free(p->ic_acc, p->fs, g_eps_dev, st);   // level-0 div-div rows (initial data)
   return check_launch(p);
 }
 
@@ -908,7 +942,39 @@ int dd_gradient_paper(dd_problem* p, double* g_eps_dev, double* g_sigma_dev, voi
   launch_fill_f64(g_sigma_dev, p->n_fem, 0.0, st);
   launch_gradient_out(p->g_eps, p->g_sig, p->own_api, p->own_grid, p->n_own, g_eps_dev, g_sigma_dev, st);
   launch_add_free(p->pg_acc, p->fs, g_eps_dev, st);
+  if (p->ic_used) launch_add_free(p->ic_acc, p->fs, g_eps_dev, st);
   return check_launch(p);
+}
+
+int dd_set_initial_data(dd_problem* p, const float* f0_dev, const float* f1_dev, void* stream) {
+  if (!p) return DD_ERR_INVALID_ARG;
+  if (!f0_dev && !f1_dev) {
+    if (p->init_on) {
+      p->init_on = false;
+      p->saved = false;
+      p->have_grad = false;
+      p->have_pg = false;
+    }
+    return DD_OK;
+  }
+  if (!f0_dev || !f1_dev) return fail(p, DD_ERR_INVALID_ARG, "initial data needs both f_0 and f_1 (or neither)");
+  if (int rc = pg_setup(p)) return rc;   // FEM-node -> owned map of the level-0 div-div rows
+  if (!p->init_f0) {
+    int rc = dalloc(p, &p->init_f0, (size_t)3 * p->N);
+    if (!rc) rc = dalloc(p, &p->init_f1, (size_t)3 * p->N);
+    if (!rc) rc = dalloc(p, &p->ic_acc, (size_t)p->n_fem);
+    if (rc) return rc;
+  }
+  hipStream_t st = (hipStream_t)stream;
+  const size_t bytes = (size_t)3 * p->N * sizeof(float);
+  if (hipMemcpyAsync(p->init_f0, f0_dev, bytes, hipMemcpyDeviceToDevice, st) != hipSuccess ||
+      hipMemcpyAsync(p->init_f1, f1_dev, bytes, hipMemcpyDeviceToDevice, st) != hipSuccess)
+    return fail(p, DD_ERR_HIP, "initial data copy failed");
+  p->init_on = true;
+  p->saved = false;
+  p->have_grad = false;
+  p->have_pg = false;
+  return DD_OK;
 }
 
 }  // extern "C"
@@ -1152,7 +1218,7 @@ bool job_next(BatchJob& j, hipStream_t st, BatchItem& it) {
   const int nsrc = (int)j.src.size();
   if (j.phase == 0) {
     if (!j.started) {
-      forward_prologue(p, j.s, true, st);
+      forward_prologue(p, j.s, true, false, st);   // batched jobs start from rest
       j.started = true;
     }
     it.fa = fd_base(p);
@@ -1284,6 +1350,7 @@ int dd_batch_submit(dd_batch* b, dd_problem* p, const dd_source* src, int32_t n_
     if (j.p == p) return fail(p, DD_ERR_STATE, "problem already has an active batch job");
   if (!p->use_stencil || !p->fused)
     return fail(p, DD_ERR_UNSUPPORTED, "batched steps need the assembled-stencil FEM path");
+  if (p->init_on) return fail(p, DD_ERR_UNSUPPORTED, "batched jobs start from rest (the problem has initial data)");
   for (int s = 0; s < n_src; ++s) {
     const std::string e = check_source(p, src[s]);
     if (!e.empty()) return fail(p, DD_ERR_INVALID_ARG, e);
@@ -1304,6 +1371,7 @@ int dd_batch_submit(dd_batch* b, dd_problem* p, const dd_source* src, int32_t n_
   p->saved = false;
   p->have_grad = false;
   p->have_pg = false;
+  p->ic_used = false;
   b->jobs.push_back(j);
   if (job_out) *job_out = j.id;
   return DD_OK;

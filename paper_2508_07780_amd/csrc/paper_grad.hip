@@ -7,6 +7,9 @@
 //     Q_i = sum_k sum_{K ∋ i} |K| div_K(lambda^k) (grad phi_i|_K . E^k_i).
 // The solver's adjoint accumulates the exact gradient; with the variant on, these kernels
 // add P_i - Q_i per adjoint step, so that the variant is the exact gradient plus that sum.
+// The kernel adds any weighted pair wp P_i - wx Q_i of one level's terms: (1, 1) for the
+// variant, (1, 0) for the paper term alone, (0, -1) for the exact term alone (the level-0
+// row of a solve that starts from initial data, which the adjoint steps do not visit).
 //
 // Geometry of the Kuhn split: the cell with lower corner c (spacing h) holds one
 // tetrahedron per axis permutation (a, b, c): v0 = c, v1 = v0 + e_a, v2 = v1 + e_b,
@@ -47,7 +50,7 @@ constexpr int PG_CX = PG_TX + 1, PG_CY = PG_TY + 1, PG_CZ = PG_TZ + 1;  // cells
 
 __global__ __launch_bounds__(256) void pg_step_kernel(const float* __restrict__ lam, const float* __restrict__ E,
                                                       int64_t n_own, const int* __restrict__ api_own, int fsx,
-                                                      int fsy, int fsz, double h, int sub_exact,
+                                                      int fsy, int fsz, double h, double wp, double wx,
                                                       double* __restrict__ acc) {
   __shared__ float sl[3][PG_NZ][PG_NY][PG_NX];
   __shared__ float se[3][PG_NZ][PG_NY][PG_NX];
@@ -107,7 +110,7 @@ __global__ __launch_bounds__(256) void pg_step_kernel(const float* __restrict__ 
       else if (o == 7) gE = Ei[c];
       else continue;
       const float2 v = sc[k][cz][cy][cx];
-      s += (double)v.x * ((double)v.y - (sub_exact ? 4.0 * (double)gE : 0.0));
+      s += (double)v.x * (wp * (double)v.y - wx * 4.0 * (double)gE);
     }
   }
   acc[(int64_t)lx + fsx * ((int64_t)ly + (int64_t)fsy * lz)] += s * (h / 24.0);
@@ -131,13 +134,18 @@ void launch_invert_own(const int* own_api, int64_t n_own, int64_t n_fem, int* ap
   if (n_own > 0) hipLaunchKernelGGL(invert_own_kernel, dim3(blocks_for(n_own)), dim3(256), 0, s, own_api, n_own, api_own);
 }
 
-void launch_paper_grad_step(const float* lam, const float* E, int64_t n_own, const int* api_own, const int fs[3],
-                            double h, bool sub_exact, double* acc, hipStream_t s) {
+void launch_divdiv_grad_terms(const float* lam, const float* E, int64_t n_own, const int* api_own, const int fs[3],
+                              double h, double wp, double wx, double* acc, hipStream_t s) {
   if (fs[0] < 5 || fs[1] < 5 || fs[2] < 5) return;   // no free node
   const int tbx = (fs[0] - 4 + PG_TX - 1) / PG_TX, tby = (fs[1] - 4 + PG_TY - 1) / PG_TY;
   const int tbz = (fs[2] - 4 + PG_TZ - 1) / PG_TZ;
   hipLaunchKernelGGL(pg_step_kernel, dim3(tbx * tby * tbz), dim3(256), 0, s, lam, E, n_own, api_own, fs[0], fs[1],
-                     fs[2], h, sub_exact ? 1 : 0, acc);
+                     fs[2], h, wp, wx, acc);
+}
+
+void launch_paper_grad_step(const float* lam, const float* E, int64_t n_own, const int* api_own, const int fs[3],
+                            double h, bool sub_exact, double* acc, hipStream_t s) {
+  launch_divdiv_grad_terms(lam, E, n_own, api_own, fs, h, 1.0, sub_exact ? 1.0 : 0.0, acc, s);
 }
 
 void launch_add_free(const double* acc, const int fs[3], double* out_eps, hipStream_t s) {

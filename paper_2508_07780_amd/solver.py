@@ -155,6 +155,20 @@ class Problem:
         code = {"R1": 1, "R2": 2}[form]
         _lib.check(_lib.load().dd_set_divdiv_form(self._h, code), self._h)
 
+    def set_initial_data(self, f0=None, f1=None):
+        """E(0) = f0, dE/dt(0) = f1 (eq. forward_initial_cond) for the following forwards:
+        CUDA tensors of n_grid x 3 values (node-major, node index x + Nx (y + Ny z)).  Both None:
+        start from rest again."""
+        lib = _lib.load()
+        if f0 is None and f1 is None:
+            _lib.check(lib.dd_set_initial_data(self._h, None, None, _stream()), self._h)
+            return
+        if f0 is None or f1 is None:
+            raise ValueError("initial data needs both f0 and f1")
+        a = _device_f32(f0, 3 * self.n_grid, "f0")
+        b = _device_f32(f1, 3 * self.n_grid, "f1")
+        _lib.check(lib.dd_set_initial_data(self._h, _ptr(a), _ptr(b), _stream()), self._h)
+
     def paper_gradient(self, on=True):
         """Accumulate the paper-formula gradient variant in the following adjoints."""
         _lib.check(_lib.load().dd_paper_gradient_enable(self._h, 1 if on else 0), self._h)

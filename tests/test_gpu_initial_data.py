@@ -1,0 +1,118 @@
+"""General initial data (eq. forward_initial_cond: E(0) = f_0, dE/dt(0) = f_1) on the GPU
+against the FP64 oracle started from the same levels E^0 = f_0, E^{-1} = f_0 - dt f_1.
+
+On the same float32 inputs: traces and energy rel L2 <= 1e-4, gradient <= 1e-3, with
+checkpoint recompute (K < N_t, the level-0 state from the first checkpoint) and with every
+level kept (one segment, the level-0 state from the kept tail); under both div-div forms and
+for the paper-formula variant (the level-0 rows of the gradient are added after the last
+adjoint step).  Clearing the data reproduces the start from rest bit for bit; batched jobs
+and a single null argument are refused.
+"""
+
+import numpy as np
+import pytest
+
+import synth
+from oracle.discretization import Discretization
+from oracle.solver import adjoint_gradient, forward
+
+pytestmark = pytest.mark.gpu
+
+
+def _rel(a, b):
+    return float(np.linalg.norm(np.asarray(a, dtype=np.float64) - b) / np.linalg.norm(b))
+
+
+def _setup(name, form="R1", store_all=False, seed=71):
+    import torch
+    from paper_2508_07780_amd import Problem
+    w = synth.small(name)
+    if store_all:
+        w.desc.ckpt_every = w.desc.n_steps
+    f0, f1 = (f.astype(np.float32) for f in synth.initial_pulses(w.desc, synth.configs.SEED_BASE + seed))
+    e32 = w.eps.astype(np.float32).astype(np.float64)
+    s32 = w.sigma.astype(np.float32).astype(np.float64)
+    d = Discretization(w.desc, divdiv_form=form).set_coefficients(e32, s32)
+    p = Problem(w.desc)
+    p.set_coefficients(torch.tensor(w.eps, dtype=torch.float32, device="cuda"),
+                       torch.tensor(w.sigma, dtype=torch.float32, device="cuda"))
+    if form != "R1":
+        p.set_divdiv_form(form)
+    return w, d, p, f0, f1
+
+
+def _solve(p, w, cot, torch):
+    tr, en = p.forward(w.sources, save=True, energy=True)
+    p.adjoint(torch.tensor(cot[None], device="cuda"))
+    ge, gs = (g.cpu().numpy() for g in p.gradient())
+    return tr[0].cpu().numpy(), en[0].cpu().numpy(), ge, gs
+
+
+@pytest.mark.parametrize("name,form,store_all", [("tiny", "R1", False), ("ragged", "R1", False),
+                                                 ("skinlet", "R1", True), ("ragged", "R2", False),
+                                                 ("tiny", "R2", True)])
+def test_initial_data_matches_oracle(name, form, store_all):
+    import torch
+    w, d, p, f0, f1 = _setup(name, form, store_all)
+    src = w.sources[0]
+    fw = forward(d, src, initial=(f0.astype(np.float64), f1.astype(np.float64)))
+    cot = (0.5 * fw["traces"] + 1e-3 * synth.noise(fw["traces"].shape, 72)).astype(np.float32)
+    ag = adjoint_gradient(d, cot.astype(np.float64), fw)
+    print(f"[gpu] initial data {name} {form}: K {w.desc.ckpt_every}, steps {w.desc.n_steps}", flush=True)
+    rest = _solve(p, w, cot, torch)
+    p.set_initial_data(torch.tensor(f0, device="cuda"), torch.tensor(f1, device="cuda"))
+    tr, en, ge, gs = _solve(p, w, cot, torch)
+    errs = (_rel(tr, fw["traces"]), _rel(en, fw["energy"]), _rel(ge, ag["g_eps"]), _rel(gs, ag["g_sigma"]))
+    print("[gpu]   traces %.2e energy %.2e g_eps %.2e g_sigma %.2e" % errs, flush=True)
+    assert errs[0] <= 1e-4 and errs[1] <= 1e-4 and errs[2] <= 1e-3 and errs[3] <= 1e-3
+    assert np.all(ge[~d.fem_free] == 0) and np.all(gs[~d.fem_free] == 0)
+    # the data changes the solve (not a start from rest in disguise)
+    assert _rel(tr, rest[0]) > 1e-2 and _rel(ge, rest[2]) > 1e-3
+    p.set_initial_data(None, None)
+    back = _solve(p, w, cot, torch)
+    for a, b in zip(back, rest):
+        np.testing.assert_array_equal(a, b)
+    p.close()
+
+
+def test_initial_data_paper_gradient_variant():
+    import torch
+    w, d, p, f0, f1 = _setup("ragged")
+    src = w.sources[0]
+    fw = forward(d, src, initial=(f0.astype(np.float64), f1.astype(np.float64)))
+    cot = (0.5 * fw["traces"] + 1e-3 * synth.noise(fw["traces"].shape, 73)).astype(np.float32)
+    ag = adjoint_gradient(d, cot.astype(np.float64), fw)
+    p.set_initial_data(torch.tensor(f0, device="cuda"), torch.tensor(f1, device="cuda"))
+    p.paper_gradient(True)
+    p.forward(w.sources, save=True)
+    p.adjoint(torch.tensor(cot[None], device="cuda"))
+    ge = p.gradient()[0].cpu().numpy()
+    gp = p.gradient_paper()[0].cpu().numpy()
+    e1, e2 = _rel(ge, ag["g_eps"]), _rel(gp, ag["g_eps_paper"])
+    print(f"[gpu] initial data, paper variant: exact {e1:.2e} paper {e2:.2e}", flush=True)
+    assert e1 <= 1e-3 and e2 <= 1e-3
+    p.close()
+
+
+def test_initial_data_refusals():
+    import torch
+    from paper_2508_07780_amd import DDError
+    from paper_2508_07780_amd.batch import Batch
+    w, d, p, f0, f1 = _setup("tiny")
+    F0 = torch.tensor(f0, device="cuda")
+    from paper_2508_07780_amd import _lib
+    lib = _lib.load()
+    rc = lib.dd_set_initial_data(p._h, ctypes_ptr(F0), None, None)
+    assert rc == -1
+    p.set_initial_data(F0, torch.tensor(f1, device="cuda"))
+    b = Batch(2)
+    with pytest.raises(DDError) as e:
+        b.submit(p, w.sources)
+    assert e.value.code == -7
+    b.close()
+    p.close()
+
+
+def ctypes_ptr(t):
+    import ctypes
+    return ctypes.c_void_p(t.data_ptr())
