@@ -24,7 +24,8 @@ import pytest
 
 import synth
 from oracle.discretization import Discretization
-from oracle.solver import adjoint_gradient, forward, loss_and_cotangent
+from oracle import solver as osolver
+from oracle.solver import forward, loss_and_cotangent
 
 
 def _closed_box(name="tiny", n_steps=120):
@@ -35,7 +36,9 @@ def _closed_box(name="tiny", n_steps=120):
     return w, d
 
 
-def test_cosine_mode_closed_form():
+def cosine_mode_errors(solver=None):
+    """(max trace error / scale, energy spread / max, balance / max) of the closed-form case."""
+    solver = solver or osolver
     w, d = _closed_box()
     desc = w.desc
     nx, ny, nz = desc.n_outer
@@ -50,17 +53,22 @@ def test_cosine_mode_closed_form():
     dt = desc.dt
     phi = math.acos(1.0 - 0.5 * dt * dt * mu)
     B = (A * math.cos(phi) - (A - dt * b)) / math.sin(phi)
-    fw = forward(d, force=lambda n: np.zeros((d.N, 3)), initial=(f0, f1))
+    fw = solver.forward(d, force=lambda n: np.zeros((d.N, 3)), initial=(f0, f1))
     n = np.arange(1, desc.n_steps + 1)
     amp = np.cos(n * phi)[:, None] * A[None, :] + np.sin(n * phi)[:, None] * B[None, :]
     expect = mode[d.det][None, :, None] * amp[:, None, :]
     scale = np.abs(expect).max()
     assert scale > 0.1
-    assert np.abs(fw["traces"] - expect).max() <= 1e-11 * scale
-    # the energy of the starting pair is carried unchanged
     W = fw["energy"]
-    assert W.min() > 0 and (W.max() - W.min()) <= 1e-12 * W.max()
-    assert np.abs(fw["balance"]).max() <= 1e-12 * W.max()
+    return (float(np.abs(fw["traces"] - expect).max() / scale), float((W.max() - W.min()) / W.max()),
+            float(np.abs(fw["balance"]).max() / W.max()))
+
+
+def test_cosine_mode_closed_form():
+    tr, spread, bal = cosine_mode_errors()
+    assert tr <= 1e-11
+    # the energy of the starting pair is carried unchanged
+    assert spread <= 1e-12 and bal <= 1e-12
 
 
 def test_energy_balance_with_initial_data_damping_and_source():
@@ -85,21 +93,24 @@ def test_zero_initial_data_is_start_from_rest():
         np.testing.assert_array_equal(a[k], b[k])
 
 
-@pytest.mark.parametrize("form", ["R1", "R2"])
-def test_gradient_with_initial_data_matches_central_differences(form):
+def gradient_fd_errors(form, solver=None):
+    """Worst relative error of g_eps, g_sigma against central differences of J (tiny grid,
+    f_0, f_1 != 0), over a fifth of the free nodes."""
+    solver = solver or osolver
     w = synth.small("tiny")
     src = w.sources[0]
     init = synth.initial_pulses(w.desc, synth.configs.SEED_BASE + 62)
     d = Discretization(w.desc, divdiv_form=form).set_coefficients(w.eps, w.sigma)
-    eobs = 0.8 * forward(d, src)["traces"]          # data of the problem started from rest
-    fw = forward(d, src, initial=init)
+    eobs = 0.8 * solver.forward(d, src)["traces"]          # data of the problem started from rest
+    fw = solver.forward(d, src, initial=init)
     _, cot = loss_and_cotangent(fw["traces"], eobs)
-    ag = adjoint_gradient(d, cot, fw)
+    ag = solver.adjoint_gradient(d, cot, fw)
 
     def J(eps, sig):
         dd = Discretization(w.desc, divdiv_form=form).set_coefficients(eps, sig)
-        return loss_and_cotangent(forward(dd, src, initial=init)["traces"], eobs)[0]
+        return loss_and_cotangent(solver.forward(dd, src, initial=init)["traces"], eobs)[0]
 
+    worst = 0.0
     free = np.nonzero(d.fem_free)[0]
     for i in free[:: max(1, len(free) // 5)]:
         for which in ("eps", "sig"):
@@ -110,20 +121,33 @@ def test_gradient_with_initial_data_matches_central_differences(form):
             c[i] -= 2e-5
             fd = (jp - J(e, s)) / 2e-5
             g = ag["g_eps" if which == "eps" else "g_sigma"][i]
-            assert abs(g - fd) <= 1e-4 * abs(fd), (form, i, which, g, fd)
+            worst = max(worst, abs(g - fd) / abs(fd))
+    return worst
 
 
-def test_mass_term_summation_by_parts_with_boundary_term():
+@pytest.mark.parametrize("form", ["R1", "R2"])
+def test_gradient_with_initial_data_matches_central_differences(form):
+    assert gradient_fd_errors(form) <= 1e-4
+
+
+def sbp_errors(solver=None):
+    """(|g_mass - g_mass_sbp| / scale, boundary term / scale) with f_0, f_1 != 0."""
+    solver = solver or osolver
     w = synth.small("ragged")
     d = Discretization(w.desc).set_coefficients(w.eps, w.sigma)
     init = synth.initial_pulses(w.desc, synth.configs.SEED_BASE + 63)
-    fw = forward(d, w.sources[0], initial=init)
+    fw = solver.forward(d, w.sources[0], initial=init)
     cot = synth.noise(fw["traces"].shape, 7) * 1e-3
-    ag = adjoint_gradient(d, cot, fw, keep_lambda=True)
+    ag = solver.adjoint_gradient(d, cot, fw, keep_lambda=True)
     scale = np.abs(ag["g_mass"]).max()
-    assert np.abs(ag["g_mass"] - ag["g_mass_sbp"]).max() <= 1e-12 * scale
-    # the boundary term -m lambda^0 . V^0 / dt^2 is not negligible here
     lam0 = ag["lambda"][0][d.fem_grid]
     V0 = w.desc.dt * init[1][d.fem_grid]
     bt = np.where(d.fem_free, d.m[d.fem_grid] * np.sum(lam0 * V0, axis=1) / w.desc.dt ** 2, 0.0)
-    assert np.abs(bt).max() >= 1e-3 * scale
+    return float(np.abs(ag["g_mass"] - ag["g_mass_sbp"]).max() / scale), float(np.abs(bt).max() / scale)
+
+
+def test_mass_term_summation_by_parts_with_boundary_term():
+    err, bt = sbp_errors()
+    assert err <= 1e-12
+    # the boundary term -m lambda^0 . V^0 / dt^2 is not negligible here
+    assert bt >= 1e-3

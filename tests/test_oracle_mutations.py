@@ -140,3 +140,39 @@ def test_cga_termination_grouping_mutation_is_caught(monkeypatch):
     except AssertionError:
         return
     raise AssertionError("the per-field grouping of the stop test passed the termination pin")
+
+
+# ---- general initial data: mistakes planted in the oracle's source text ---------------------
+
+_INIT_MUTATIONS = {
+    # E^{-1} = f_0 + dt f_1 (sign of the one-sided difference)
+    "sign of the starting increment": ("E_prev = E_cur - V0", "E_prev = E_cur + V0"),
+    # f_1 taken as the increment itself
+    "dt missing from V^0": ("V0 = dt * np.asarray", "V0 = np.asarray"),
+    # level -1 of the FEM history left at rest
+    "level -1 not stored": ("fem_hist[0] = E_prev[d.fem_grid]", "fem_hist[0] = 0.0 * E_prev[d.fem_grid]"),
+    # W^{-1/2} without its stiffness half
+    "starting energy": ("/ dt ** 2 + 0.5 * np.sum(E_cur * d.apply_A(E_prev))", "/ dt ** 2"),
+    # summation by parts without its boundary row
+    "boundary row dropped": ("g_mass_sbp -= m * np.sum(lam_f[0]", "g_mass_sbp -= 0.0 * m * np.sum(lam_f[0]"),
+}
+
+
+def _mutated_solver(old, new):
+    import types
+    src = open(osolver.__file__).read()
+    assert src.count(old) == 1, old
+    mod = types.ModuleType("oracle_solver_mutant")
+    exec(compile(src.replace(old, new), "oracle_solver_mutant", "exec"), mod.__dict__)
+    return mod
+
+
+def test_initial_data_mutations_are_caught():
+    from tests.test_oracle_initial_data import cosine_mode_errors, gradient_fd_errors, sbp_errors
+    assert max(cosine_mode_errors()) < 1e-11 and sbp_errors()[0] < 1e-12
+    for name, (old, new) in _INIT_MUTATIONS.items():
+        m = _mutated_solver(old, new)
+        caught = max(cosine_mode_errors(m)) > 1e-6 or sbp_errors(m)[0] > 1e-6
+        if not caught:
+            caught = gradient_fd_errors("R1", m) > 1e-3
+        assert caught, name
