@@ -5,6 +5,9 @@
 * Stiffness and div-div are second-order consistent with -Laplace(E) and
   -grad div((eps - 1) E) (the spatial part of the box "Forward problem",
   eq. forward_prob) on smooth fields: the error drops by 4 per halving of h.
+* With a constant eps, M_eps^{-1} A moves longitudinal plane waves at speed 1 and
+  transverse ones at 1/sqrt(eps) (closed form of eq. forward_prob), to second order, for
+  both div-div forms: this also fixes the eps in the mass matrix.
 * The transposed operator used by the adjoint is the exact transpose.
 * Lumped masses and face masses add up to the box volume and face areas.
 """
@@ -126,3 +129,37 @@ def test_coefficient_constraint_enforced():
     bad[d.fem_free] = 0.5
     with pytest.raises(ValueError):
         d.set_coefficients(bad, w.sigma)
+
+
+def _wave_speed_errors(nc, eps_c=4.0, form="R1"):
+    """Closed form: in a constant medium eps, eps E_tt - Laplace E - (eps - 1) grad div E = 0 has
+    longitudinal plane waves at speed 1 (omega^2 = |k|^2) and transverse ones at 1/sqrt(eps)
+    (omega^2 = |k|^2 / eps).  On free FEM rows, M_eps^{-1} A applied to cos(k.x + 0.3) times
+    the unit vector along k (or across it) must give omega^2 times the field."""
+    d = Discretization(_desc(nc), divdiv_form=form)
+    n = d.n_fem
+    d.set_coefficients(np.ones(n), np.zeros(n))
+    d.eps = np.full(n, eps_c)              # operator-only test: eps constant on every FEM node
+    eg = np.ones(d.N)
+    eg[d.fem_grid] = eps_c
+    M = d.m * eg
+    k = np.array([0.9, -0.5, 0.7])
+    kk = float(k @ k)
+    kh = k / math.sqrt(kk)
+    t = np.cross(kh, [0.0, 0.0, 1.0])
+    t /= np.linalg.norm(t)
+    ph = np.cos(d.x @ k + 0.3)
+    rows = d.fem_grid[d.fem_layer >= 2]
+    out = []
+    for u, w2 in ((ph[:, None] * kh[None, :], kk), (ph[:, None] * t[None, :], kk / eps_c)):
+        r = d.apply_A(u)[rows] / M[rows][:, None]
+        out.append(float(np.abs(r - w2 * u[rows]).max() / (w2 * np.abs(u[rows]).max())))
+    return out
+
+
+def test_longitudinal_and_transverse_wave_speeds():
+    for form in ("R1", "R2"):
+        e8, e16 = _wave_speed_errors(8, form=form), _wave_speed_errors(16, form=form)
+        for a, b in zip(e8, e16):
+            assert 3.6 < a / b < 4.4, (form, a, b)
+        assert max(e16) < 3e-3, (form, e16)
