@@ -185,8 +185,9 @@ int dd_misfit(dd_problem* p, const float* traces_dev, const float* obs_dev, int3
  * eps - 1 outside it, sum_K |K| (mean_K eps - 1) grad phi_i div_K(E) (symmetric); for this form
  * the paper's gradient formula (eq. gradeps with grad(eps~).E dropped) is the exact gradient,
  * and dd_gradient returns it.  R2 needs the assembled-stencil path (uniform Kuhn box;
- * DD_ERR_UNSUPPORTED otherwise) and runs the FD and FEM parts of a step as separate launches
- * (batched jobs then report DD_ERR_UNSUPPORTED).  Switching the form discards a saved forward.
+ * DD_ERR_UNSUPPORTED otherwise); its steps are fused launches of their own (one more
+ * launch per adjoint step adds the div-div gradient term); batched jobs run R1 only and
+ * report DD_ERR_UNSUPPORTED for an R2 problem.  Switching the form discards a saved forward.
  * The first switch to R2 allocates FEM-node sized buffers and synchronises the device. */
 enum { DD_DIVDIV_R1 = 1, DD_DIVDIV_R2 = 2 };
 int dd_set_divdiv_form(dd_problem* p, int32_t form);

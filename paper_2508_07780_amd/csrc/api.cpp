@@ -70,7 +70,7 @@ struct dd_problem {
   std::vector<double> mis_z_host;
   // paper-formula gradient variant: FEM-node -> owned id map, FP64 sum
   bool pg_on = false, have_pg = false;
-  bool r2 = false;        // div-div form R2 (FEM kernels in separate launches)
+  bool r2 = false;        // div-div form R2 (its own step kernel instantiations)
   int* api_own = nullptr;
   double* pg_acc = nullptr;
   // general initial data (dd_set_initial_data): f_0, f_1 [N][3]; the level-0 div-div rows of
@@ -925,7 +925,6 @@ int dd_set_divdiv_form(dd_problem* p, int32_t form) {
     if (int rc = pg_setup(p)) return rc;
   }
   p->r2 = r2;
-  p->fused = !r2;          // R2 runs the FD tiles and the FEM partitions in separate launches
   p->saved = false;        // a saved forward of the other form no longer matches
   p->have_grad = false;
   p->have_pg = false;
@@ -1350,6 +1349,7 @@ int dd_batch_submit(dd_batch* b, dd_problem* p, const dd_source* src, int32_t n_
     if (j.p == p) return fail(p, DD_ERR_STATE, "problem already has an active batch job");
   if (!p->use_stencil || !p->fused)
     return fail(p, DD_ERR_UNSUPPORTED, "batched steps need the assembled-stencil FEM path");
+  if (p->r2) return fail(p, DD_ERR_UNSUPPORTED, "batched steps run the div-div form R1 only");
   if (p->init_on) return fail(p, DD_ERR_UNSUPPORTED, "batched jobs start from rest (the problem has initial data)");
   for (int s = 0; s < n_src; ++s) {
     const std::string e = check_source(p, src[s]);

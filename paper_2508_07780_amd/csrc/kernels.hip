@@ -812,6 +812,21 @@ __global__ __launch_bounds__(FD_THREADS) void step_kernel(FdArgs fa, FemArgs ea,
   fd_tile<ENERGY, NT>(fa, b - fem_blocks);
 }
 
+// The same step with the FEM rows in the div-div form R2.  Unbounded, its FEM part takes
+// about 117 VGPRs and the whole launch runs at 4 waves per SIMD; held to 5 (96 VGPRs, 12-20
+// bytes of spill) the main workload's R2 solve took 172.9 ms against 186.2 ms (and 173.8 ms
+// at 6 waves, 80 VGPRs with 88-104 bytes of spill).
+template <bool ADJ, bool ENERGY, bool NT>
+__global__ __launch_bounds__(FD_THREADS, 5) void step_kernel_r2(FdArgs fa, FemArgs ea, int fem_blocks) {
+  const int b = blockIdx.x;
+  if (b < fem_blocks) {
+    const int p = fem_part_of_block(b, fem_blocks, ea.rev);
+    if (p < ea.n_part) fem_stencil_part<ADJ, ENERGY, true>(ea, p);
+    return;
+  }
+  fd_tile<ENERGY, NT>(fa, b - fem_blocks);
+}
+
 // ---------------------------------------------------------------------------------------
 // Batched step: one launch advances every active job of a batch by one time step.  Item i
 // covers blocks [base_i, base_{i+1}): its FEM partitions first, then its FD tiles
@@ -1021,7 +1036,14 @@ static void launch_step_t(const FdArgs& fa, const FemArgs& ea, hipStream_t s, bo
   const int fem_blocks = (ea.n_part + N_XCD - 1) / N_XCD * N_XCD;   // keeps FD blocks XCD-aligned
   const dim3 grid(fem_blocks + fa.per_xcd * N_XCD);
   const size_t lds = stencil_lds_bytes(ea);
-  if (adj)
+  if (ea.r2) {
+    if (adj)
+      hipLaunchKernelGGL((step_kernel_r2<true, false, NT>), grid, dim3(FD_THREADS), lds, s, fa, ea, fem_blocks);
+    else if (energy)
+      hipLaunchKernelGGL((step_kernel_r2<false, true, NT>), grid, dim3(FD_THREADS), lds, s, fa, ea, fem_blocks);
+    else
+      hipLaunchKernelGGL((step_kernel_r2<false, false, NT>), grid, dim3(FD_THREADS), lds, s, fa, ea, fem_blocks);
+  } else if (adj)
     hipLaunchKernelGGL((step_kernel<true, false, NT>), grid, dim3(FD_THREADS), lds, s, fa, ea, fem_blocks);
   else if (energy)
     hipLaunchKernelGGL((step_kernel<false, true, NT>), grid, dim3(FD_THREADS), lds, s, fa, ea, fem_blocks);
