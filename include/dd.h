@@ -133,17 +133,17 @@ int dd_forward(dd_problem* p, const dd_source* src, int32_t n_src, float* traces
 
 /* General initial data of the forward problem (eq. forward_initial_cond): E(x, 0) = f_0,
  * dE/dt(x, 0) = f_1.  f0_dev, f1_dev: [n_grid][3] float32 on the device, node index
- * x + Nx (y + Ny z), copied into library-owned buffers on `stream` (the caller's arrays may
- * be freed once that stream has passed the call).  The scheme starts from the levels
+ * x + Nx (y + Ny z), checked (any non-finite value: DD_ERR_CONSTRAINT, and the data set
+ * before stay) and copied into library-owned buffers; synchronises `stream`, so the caller's
+ * arrays may be freed when the call returns.  The scheme starts from the levels
  * E^0 = f_0 and E^{-1} = f_0 - dt f_1 (the one-sided difference of dE/dt at t = 0), for every
- * source of the following dd_forward calls; values are used as given (non-finite data shows
- * up as DD_ERR_UNSTABLE only where the solver checks its fields).  The gradient of the
+ * source of the following dd_forward calls.  The gradient of the
  * following adjoints is the exact derivative with both levels held fixed: its level-0 rows
  * hold the -lambda(x, 0) f_1 term of eq. gradeps (as -m_i lambda^0 . dt f_1 / dt^2) and the
  * level-0 div-div term, for either div-div form and for dd_gradient_paper.
  * Both NULL: start from rest again.  One NULL: DD_ERR_INVALID_ARG.  Setting or clearing the
  * data discards a saved forward.  The first call allocates 24 n_grid + 12 n_fem_nodes bytes
- * and may synchronise the device; DD_ERR_UNSUPPORTED when FD and FEM run on two streams.
+ * and synchronises the device; DD_ERR_UNSUPPORTED when FD and FEM run on two streams.
  * Batched jobs (dd_batch_submit) always start from rest and are refused (DD_ERR_UNSUPPORTED)
  * while initial data is set. */
 int dd_set_initial_data(dd_problem* p, const float* f0_dev, const float* f1_dev, void* stream);

@@ -168,16 +168,17 @@ def cga_loop(grad_fn, eps0, sig0, w, free, params, n_iter):
     return hist
 
 
-def solve_gradient(d, sources, eobs, z=None):
+def solve_gradient(d, sources, eobs, z=None, initial=None):
     """Step 1 on the discrete scheme: gradient of J summed over sources, and J (z: the
-    smoothing function of eq. tikhonov_functional at the trace rows, or None for z = 1)."""
+    smoothing function of eq. tikhonov_functional at the trace rows, or None for z = 1;
+    initial: (f_0, f_1) of eq. forward_initial_cond for every source, or None for rest)."""
     def grad_fn(eps, sig):
         d.set_coefficients(eps, sig)
         ge = np.zeros(d.n_fem)
         gs = np.zeros(d.n_fem)
         J = 0.0
         for s, src in enumerate(sources):
-            fw = forward(d, src)
+            fw = forward(d, src, initial=initial)
             Js, r = loss_and_cotangent(fw["traces"], eobs[s], z)
             ag = adjoint_gradient(d, r, fw)
             ge += ag["g_eps"]
@@ -187,7 +188,7 @@ def solve_gradient(d, sources, eobs, z=None):
     return grad_fn
 
 
-def cga(d, sources, eobs, eps0, sig0, params, n_iter, z=None):
+def cga(d, sources, eobs, eps0, sig0, params, n_iter, z=None, initial=None):
     """The CGA on the discretisation d: eobs is [n_src][n_steps][n_det][3]."""
     w = d.m[d.fem_grid]
-    return cga_loop(solve_gradient(d, sources, eobs, z), eps0, sig0, w, d.fem_free, params, n_iter)
+    return cga_loop(solve_gradient(d, sources, eobs, z, initial), eps0, sig0, w, d.fem_free, params, n_iter)

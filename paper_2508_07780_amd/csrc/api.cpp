@@ -957,6 +957,16 @@ int dd_set_initial_data(dd_problem* p, const float* f0_dev, const float* f1_dev,
     return DD_OK;
   }
   if (!f0_dev || !f1_dev) return fail(p, DD_ERR_INVALID_ARG, "initial data needs both f_0 and f_1 (or neither)");
+  hipStream_t st = (hipStream_t)stream;
+  int h_err = 0;
+  if (hipMemsetAsync(p->d_err, 0, sizeof(int), st) != hipSuccess) return fail(p, DD_ERR_HIP, "hipMemsetAsync failed");
+  launch_count_nonfinite(f0_dev, 3 * p->N, p->d_err, st);
+  launch_count_nonfinite(f1_dev, 3 * p->N, p->d_err, st);
+  if (int rc = check_launch(p)) return rc;
+  if (hipMemcpyAsync(&h_err, p->d_err, sizeof(int), hipMemcpyDeviceToHost, st) != hipSuccess ||
+      hipStreamSynchronize(st) != hipSuccess)
+    return fail(p, DD_ERR_HIP, "error readback failed");
+  if (h_err) return fail(p, DD_ERR_CONSTRAINT, std::to_string(h_err) + " non-finite initial data values");
   if (int rc = pg_setup(p)) return rc;   // FEM-node -> owned map of the level-0 div-div rows
   if (!p->init_f0) {
     int rc = dalloc(p, &p->init_f0, (size_t)3 * p->N);
@@ -964,7 +974,6 @@ int dd_set_initial_data(dd_problem* p, const float* f0_dev, const float* f1_dev,
     if (!rc) rc = dalloc(p, &p->ic_acc, (size_t)p->n_fem);
     if (rc) return rc;
   }
-  hipStream_t st = (hipStream_t)stream;
   const size_t bytes = (size_t)3 * p->N * sizeof(float);
   if (hipMemcpyAsync(p->init_f0, f0_dev, bytes, hipMemcpyDeviceToDevice, st) != hipSuccess ||
       hipMemcpyAsync(p->init_f1, f1_dev, bytes, hipMemcpyDeviceToDevice, st) != hipSuccess)

@@ -5,8 +5,8 @@ On the same float32 inputs: traces and energy rel L2 <= 1e-4, gradient <= 1e-3, 
 checkpoint recompute (K < N_t, the level-0 state from the first checkpoint) and with every
 level kept (one segment, the level-0 state from the kept tail); under both div-div forms and
 for the paper-formula variant (the level-0 rows of the gradient are added after the last
-adjoint step).  Clearing the data reproduces the start from rest bit for bit; batched jobs
-and a single null argument are refused.
+adjoint step).  Clearing the data reproduces the start from rest bit for bit; batched jobs,
+a single null argument and non-finite data are refused (the data set before stay).
 """
 
 import numpy as np
@@ -104,7 +104,16 @@ def test_initial_data_refusals():
     lib = _lib.load()
     rc = lib.dd_set_initial_data(p._h, ctypes_ptr(F0), None, None)
     assert rc == -1
-    p.set_initial_data(F0, torch.tensor(f1, device="cuda"))
+    F1 = torch.tensor(f1, device="cuda")
+    p.set_initial_data(F0, F1)
+    t_ok = p.forward(w.sources, save=False).cpu().numpy()
+    # a non-finite value is rejected and the data set before stay
+    bad = F1.clone()
+    bad[5, 1] = float("nan")
+    with pytest.raises(DDError) as e:
+        p.set_initial_data(F0, bad)
+    assert e.value.code == -2
+    np.testing.assert_array_equal(p.forward(w.sources, save=False).cpu().numpy(), t_ok)
     b = Batch(2)
     with pytest.raises(DDError) as e:
         b.submit(p, w.sources)
@@ -156,4 +165,38 @@ def test_initial_data_edge_cases(n_steps, ckpt_every, n_src):
         errs.append(_rel(g, go) if np.linalg.norm(go) > 0 else float(np.abs(g).max()))
     print("[gpu]   " + " ".join("%.2e" % e for e in errs), flush=True)
     assert max(errs[:n_src]) <= 1e-4 and errs[-2] <= 1e-3 and errs[-1] <= 1e-3
+    p.close()
+
+
+def test_cga_with_initial_data_matches_oracle():
+    """Two CGA iterations (box "CGA") of a problem with initial data, against the oracle's CGA
+    from the same levels; step sizes from the oracle's gradient at the initial guess (the first
+    update moves eps by at most 0.5 and sigma by at most 0.1)."""
+    import torch
+    from oracle.cga import cga, solve_gradient
+    from paper_2508_07780_amd import CGA, CGAParams, Problem
+    w = synth.small("ragged")
+    src = w.sources[0]
+    f0, f1 = (f.astype(np.float32) for f in synth.initial_pulses(w.desc, synth.configs.SEED_BASE + 76))
+    init = (f0.astype(np.float64), f1.astype(np.float64))
+    eobs = forward(Discretization(w.desc).set_coefficients(w.eps, w.sigma), src, initial=init)["traces"][None]
+    n = len(w.eps)
+    eps0, sig0 = np.ones(n), np.zeros(n)
+    ge, gs, _ = solve_gradient(Discretization(w.desc), [src], eobs, None, init)(eps0, sig0)
+    m = w.desc.h ** 3
+    ae, asg = 0.5 / (np.abs(ge).max() / m), 0.1 / (np.abs(gs).max() / m)
+    prm = dict(gamma_eps=1.0 / ae, gamma_sig=1.0 / asg, p=0.5, alpha_eps=ae, alpha_sig=asg, eps_max=8.0,
+               sig_max=2.0)
+    ref = cga(Discretization(w.desc), [src], eobs, eps0, sig0, prm, 2, initial=init)
+    p = Problem(w.desc)
+    p.set_initial_data(torch.tensor(f0, device="cuda"), torch.tensor(f1, device="cuda"))
+    c = CGA(p, [src], torch.tensor(eobs, dtype=torch.float32, device="cuda"), torch.tensor(eps0, device="cuda"),
+            torch.tensor(sig0, device="cuda"), CGAParams(**prm))
+    for it in range(2):
+        c.iterate()
+        for f, t, base in (("eps", c.eps, eps0), ("sig", c.sigma, sig0)):
+            err = _rel(t.cpu().numpy().astype(np.float64) - base, ref[it][f]["coef"] - base)
+            print(f"[gpu] cga with initial data m={it} {f}: change rel L2 {err:.2e}", flush=True)
+            assert err <= 2e-3
+    c.close()
     p.close()
