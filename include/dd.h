@@ -142,8 +142,9 @@ int dd_forward(dd_problem* p, const dd_source* src, int32_t n_src, float* traces
  * hold the -lambda(x, 0) f_1 term of eq. gradeps (as -m_i lambda^0 . dt f_1 / dt^2) and the
  * level-0 div-div term, for either div-div form and for dd_gradient_paper.
  * Both NULL: start from rest again.  One NULL: DD_ERR_INVALID_ARG.  Setting or clearing the
- * data discards a saved forward.  The first call allocates 24 n_grid + 12 n_fem_nodes bytes
- * and synchronises the device; DD_ERR_UNSUPPORTED when FD and FEM run on two streams.
+ * data discards a saved forward.  The first call allocates up to 24 n_grid + 20 n_fem_nodes
+ * bytes (not counted by dd_footprint_bytes) and synchronises the device; DD_ERR_UNSUPPORTED
+ * when FD and FEM run on two streams.
  * Batched jobs (dd_batch_submit) always start from rest and are refused (DD_ERR_UNSUPPORTED)
  * while initial data is set. */
 int dd_set_initial_data(dd_problem* p, const float* f0_dev, const float* f1_dev, void* stream);
