@@ -22,6 +22,11 @@ What it computes (the discrete scheme the GPU path must reproduce):
 * Gradient (eq. gradeps and the optimality conditions dL/deps, dL/dsigma):
   the exact derivative of the discrete loss 1/2 sum |E - E_obs|^2 over
   detectors and steps with respect to nodal eps and sigma.
+* General initial data (eq. forward_initial_cond): the starting levels E^0 = f_0,
+  E^{-1} = f_0 - dt f_1 (start from rest by default), with the level-0 rows of the
+  gradient that carry the -lambda(x, 0) f_1 term of eq. gradeps.
+* Variants: the paper's own gradient formula, and the symmetric div-div form R2 for
+  which that formula is the exact gradient (oracle/discretization.py).
 * Reconstruction (box "CGA", oracle/cga.py): the conjugate gradient iteration on
   eps and sigma with the Tikhonov terms of eq. tikhonov_functional, the step-size
   and regularisation rules of the box and the coefficient box of
