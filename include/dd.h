@@ -268,13 +268,14 @@ const char* dd_error_string(int code);
 const char* dd_last_error(const dd_problem* p);
 
 /* ---- Batched solves (several problems in one launch per step) ----------------------
- * A batch holds up to max_slots (1..64) jobs.  A job is the solve of one problem: the forward of
+ * A batch holds up to max_slots (1..32) jobs.  A job is the solve of one problem: the forward of
  * each source with saving, then -- when obs_dev is given -- the adjoint for the misfit
  * cotangent traces - obs (read inside the adjoint kernel; obs_dev has the traces' layout)
  * and the gradient summed over sources, written to g_eps_dev / g_sigma_dev (FEM-node
  * arrays, float64) when those are given.  dd_batch_step advances every active job by up
  * to max_steps time steps: each iteration is one kernel launch in which every active job
- * contributes its next step (forward, adjoint or checkpoint recompute), so jobs of uneven
+ * contributes its next step (a forward step, or an adjoint step together with the next
+ * checkpoint recompute step of the segment before it, which uses the other window), so jobs of uneven
  * grid sizes, step counts and source counts share the GPU and new jobs can join while
  * others run.  dd_batch_step returns early, after the launch in which a job completed, so
  * that a caller can collect results and admit new jobs without waiting for the remaining

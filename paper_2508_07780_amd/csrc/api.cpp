@@ -1213,26 +1213,42 @@ struct BatchJob {
   int s = 0;                  // current source
   int64_t n = 0;              // forward step
   int64_t seg = 0, k = 0;     // adjoint segment and step
+  int64_t rseg = -1, rk = 0;  // segment whose FEM states are being recomputed, its next step
   bool started = false;       // prologue of the current source queued
-  bool seg_started = false;   // prologue of the current segment queued
-  bool recomputing = false;
+  bool seg_started = false;   // current adjoint segment started (and the recompute of the one before it)
 };
 
-// Queues the prologue work due before the job's next step and fills `it` with that step.
-// Returns false when the job has no step left.
-bool job_next(BatchJob& j, hipStream_t st, BatchItem& it) {
+// Adjoint segment [k0, k1) of segment seg.
+int64_t seg_k0(const dd_problem* p, int64_t seg) { return seg * (int64_t)p->d.ckpt_every; }
+int64_t seg_k1(const dd_problem* p, int64_t seg) {
+  return std::min(seg_k0(p, seg) + (int64_t)p->d.ckpt_every, (int64_t)p->d.n_steps);
+}
+
+// The job's adjoint segment can start: the last segment (stored by the forward), or one whose
+// recompute has taken all its steps.
+bool seg_ready(const BatchJob& j) {
+  return j.seg == n_segments(j.p) - 1 || (j.rseg == j.seg && j.rk == seg_k1(j.p, j.seg));
+}
+
+// Queues the prologue work due before the job's next launch and writes the items the job
+// contributes to it into `it` (returns how many: 0 when the job has no step left).  In the
+// adjoint, a launch carries the adjoint step of segment seg and, as a second item, the next
+// FEM recompute step of segment seg - 1 (into the other window), as the single-problem
+// path overlaps them on two streams; a segment whose recompute is still short of its last
+// step (after a shorter last segment) first takes recompute-only launches.
+int job_items(BatchJob& j, hipStream_t st, BatchItem* it) {
   dd_problem* p = j.p;
-  const int64_t nt = p->d.n_steps, K = p->d.ckpt_every;
+  const int64_t nt = p->d.n_steps;
   const int nsrc = (int)j.src.size();
   if (j.phase == 0) {
     if (!j.started) {
       forward_prologue(p, j.s, true, false, st);   // batched jobs start from rest
       j.started = true;
     }
-    it.fa = fd_base(p);
-    it.ea = fem_base(p);
-    fwd_step_args(p, j.src[j.s], j.plans[j.s], j.s, j.n, j.traces, true, it.fa, it.ea);
-    it.kind = 0;
+    it[0].fa = fd_base(p);
+    it[0].ea = fem_base(p);
+    fwd_step_args(p, j.src[j.s], j.plans[j.s], j.s, j.n, j.traces, true, it[0].fa, it[0].ea);
+    it[0].kind = 0;
     if (++j.n == nt) {
       j.n = 0;
       j.started = false;
@@ -1241,9 +1257,9 @@ bool job_next(BatchJob& j, hipStream_t st, BatchItem& it) {
         j.phase = j.obs ? 1 : 2;
       }
     }
-    return true;
+    return 1;
   }
-  if (j.phase != 1) return false;
+  if (j.phase != 1) return 0;
   const int64_t nseg = n_segments(p);
   if (!j.started) {
     if (j.s == 0) {
@@ -1253,26 +1269,40 @@ bool job_next(BatchJob& j, hipStream_t st, BatchItem& it) {
     zero_state(p, st);
     j.seg = nseg - 1;
     j.seg_started = false;
+    j.rseg = -1;
     j.started = true;
   }
-  const int64_t k0 = j.seg * K, k1 = std::min(k0 + K, nt);
-  float* win = segment_window(p, j.s, j.seg);
+  int n = 0;
+  auto recompute_item = [&]() {
+    it[n].fa = fd_base(p);
+    it[n].ea = fem_base(p);
+    recompute_args(p, j.s, j.rk, seg_k0(p, j.rseg), segment_window(p, j.s, j.rseg), it[n].ea);
+    it[n].kind = 2;
+    ++j.rk;
+    ++n;
+  };
   if (!j.seg_started) {
-    segment_prologue(p, j.s, j.seg, st);
-    j.recomputing = j.seg != nseg - 1;
-    j.k = j.recomputing ? k0 : k1;
+    if (!seg_ready(j)) {
+      recompute_item();          // the rest of this segment's recompute, alone
+      return n;
+    }
+    j.k = seg_k1(p, j.seg);
     j.seg_started = true;
+    if (j.seg >= 1) {
+      // the recompute of the segment before starts now, into the window whose last readers
+      // (the adjoint steps of segment seg + 1) are already queued
+      j.rseg = j.seg - 1;
+      j.rk = seg_k0(p, j.rseg);
+      segment_prologue(p, j.s, j.rseg, st);
+    }
   }
-  it.fa = fd_base(p);
-  it.ea = fem_base(p);
-  if (j.recomputing) {
-    recompute_args(p, j.s, j.k, k0, win, it.ea);
-    it.kind = 2;
-    if (++j.k == k1) j.recomputing = false;   // then adjoint steps k1 .. k0+1
-    return true;
-  }
-  adj_step_args(p, j.s, j.k, k0, win, j.traces, j.obs, it.fa, it.ea);
-  it.kind = 1;
+  const int64_t k0 = seg_k0(p, j.seg);
+  it[n].fa = fd_base(p);
+  it[n].ea = fem_base(p);
+  adj_step_args(p, j.s, j.k, k0, segment_window(p, j.s, j.seg), j.traces, j.obs, it[n].fa, it[n].ea);
+  it[n].kind = 1;
+  ++n;
+  if (j.rseg == j.seg - 1 && j.rseg >= 0 && j.rk < seg_k1(p, j.rseg)) recompute_item();
   if (--j.k == k0) {
     j.seg_started = false;
     if (--j.seg < 0) {
@@ -1280,14 +1310,15 @@ bool job_next(BatchJob& j, hipStream_t st, BatchItem& it) {
       if (++j.s == nsrc) j.phase = 2;
     }
   }
-  return true;
+  return n;
 }
 
-// True when the job's next job_next call queues prologue work (a source's forward or
-// adjoint start, or an adjoint segment start) ahead of its step.
+// True when the job's next job_items call queues prologue work (a source's forward or
+// adjoint start, or an adjoint segment start with the next segment's recompute prologue)
+// ahead of its items.
 bool job_needs_prologue(const BatchJob& j) {
   if (j.phase == 0) return !j.started;
-  if (j.phase == 1) return !j.started || !j.seg_started;
+  if (j.phase == 1) return !j.started || (!j.seg_started && seg_ready(j));
   return false;
 }
 
@@ -1295,11 +1326,12 @@ bool job_needs_prologue(const BatchJob& j) {
 
 struct dd_batch {
   int max_slots = 0;
+  int width = 0;                // items per launch: two per job (an adjoint step and a recompute step)
   std::vector<BatchJob> jobs;
   std::vector<int> done;
   int next_id = 1;
-  BatchItem* host = nullptr;    // pinned [ring][max_slots]
-  BatchItem* dev = nullptr;     // device [ring][max_slots]
+  BatchItem* host = nullptr;    // pinned [ring][width]
+  BatchItem* dev = nullptr;     // device [ring][width]
   std::vector<hipEvent_t> ev;   // per ring segment: its upload has been consumed
   // The ring holds the items of `ring` launches in segments of `seg` launches; the items of
   // the launches of one segment are uploaded with one copy.
@@ -1312,12 +1344,13 @@ struct dd_batch {
 extern "C" {
 
 int dd_batch_create(int32_t max_slots, dd_batch** out) {
-  if (!out || max_slots < 1 || max_slots > BATCH_MAX) return DD_ERR_INVALID_ARG;
+  if (!out || max_slots < 1 || 2 * max_slots > BATCH_MAX) return DD_ERR_INVALID_ARG;
   *out = nullptr;
   dd_batch* b = new (std::nothrow) dd_batch();
   if (!b) return DD_ERR_OOM;
   b->max_slots = max_slots;
-  const size_t bytes = sizeof(BatchItem) * (size_t)b->ring * max_slots;
+  b->width = 2 * max_slots;
+  const size_t bytes = sizeof(BatchItem) * (size_t)b->ring * b->width;
   if (hipHostMalloc((void**)&b->host, bytes, hipHostMallocDefault) != hipSuccess) {
     delete b;
     return DD_ERR_OOM;
@@ -1408,15 +1441,17 @@ int dd_batch_step(dd_batch* b, int32_t max_steps, void* stream) {
     bool finished = false;
     while (m < b->seg && iter < max_steps && !b->jobs.empty()) {
       if (m > 0 && std::any_of(b->jobs.begin(), b->jobs.end(), job_needs_prologue)) break;
-      BatchItem* h = b->host + (size_t)(b->pos + m) * b->max_slots;
+      BatchItem* h = b->host + (size_t)(b->pos + m) * b->width;
       int n = 0, base = 0;
       size_t l = 0;
       double fd_bytes = 0.0;   // the FD field sets this launch streams through
       const dd_problem* owner[BATCH_MAX];
       for (auto& j : b->jobs) {
-        if (!job_next(j, st, h[n])) continue;
-        if (h[n].kind != 2) fd_bytes += fd_field_bytes(j.p);
-        owner[n++] = j.p;
+        const int c = job_items(j, st, h + n);
+        for (int i = 0; i < c; ++i) {
+          if (h[n].kind != 2) fd_bytes += fd_field_bytes(j.p);
+          owner[n++] = j.p;
+        }
       }
       // the launch's variant (and with it the z-chunk) follows the FD fields it streams;
       // each item's tile grid is laid out for that chunk
@@ -1446,15 +1481,15 @@ int dd_batch_step(dd_batch* b, int32_t max_steps, void* stream) {
       }
     }
     if (m) {
-      const size_t off = (size_t)b->pos * b->max_slots;
-      if (hipMemcpyAsync(b->dev + off, b->host + off, sizeof(BatchItem) * b->max_slots * m, hipMemcpyHostToDevice,
+      const size_t off = (size_t)b->pos * b->width;
+      if (hipMemcpyAsync(b->dev + off, b->host + off, sizeof(BatchItem) * b->width * m, hipMemcpyHostToDevice,
                          st) != hipSuccess ||
           hipEventRecord(b->ev[g], st) != hipSuccess) {
         b->err = "batch upload failed";
         return DD_ERR_HIP;
       }
       for (int k = 0; k < m; ++k)
-        if (bases[k].n) launch_batch(b->dev + off + (size_t)k * b->max_slots, bases[k], lds[k], st, nt[k]);
+        if (bases[k].n) launch_batch(b->dev + off + (size_t)k * b->width, bases[k], lds[k], st, nt[k]);
       hipError_t e = hipGetLastError();
       if (e != hipSuccess) {
         b->err = std::string("batch launch failed: ") + hipGetErrorString(e);
