@@ -540,9 +540,20 @@ int run_adjoint(dd_problem* p, int s, const float* cot, const float* obs, hipStr
     for (int64_t k = k1; k > k0; --k) {
       adj_step_args(p, s, k, k0, win, cot, obs, fa, ea);
       long ps = -1;
+      // the div-div gradient terms of lambda^k (the R2 div-div gradient, or the R1 variant's
+      // difference): inside the fused step, which reads but does not write lambda^k and E^k,
+      // else a launch of their own after the step (lambda^k, ea.X_in, is overwritten two
+      // steps later, on the same stream)
+      const bool pg_fused = fused && (p->r2 || p->pg_on);
       if (fused) {
+        PgArgs pga{};
+        if (pg_fused) {
+          pga.lam = ea.X_in; pga.E = ea.wE; pga.n_own = p->n_own; pga.api_own = p->api_own;
+          for (int c = 0; c < 3; ++c) pga.fs[c] = p->fs[c];
+          pga.h = p->d.h; pga.wp = 1.0; pga.wx = p->r2 ? 0.0 : 1.0; pga.acc = p->pg_acc;
+        }
         ps = prof_begin(p, DD_PROF_STEP_ADJ, st);
-        launch_step(fa, ea, st, true, false, p->fd_nt);
+        launch_step(fa, ea, st, true, false, p->fd_nt, pg_fused ? &pga : nullptr);
         prof_end(p, DD_PROF_STEP_ADJ, ps, st);
       } else {
         ps = prof_begin(p, DD_PROF_FD_ADJ, st);
@@ -553,8 +564,7 @@ int run_adjoint(dd_problem* p, int s, const float* cot, const float* obs, hipStr
         prof_end(p, DD_PROF_FEM_ADJ, ps, sf);
         step_barrier(p, st);
       }
-      // lambda^k (ea.X_in) is overwritten two steps later, on the same stream
-      if (p->pg_on || p->r2)
+      if ((p->pg_on || p->r2) && !pg_fused)
         launch_paper_grad_step(ea.X_in, ea.wE, p->n_own, p->api_own, p->fs, p->d.h, !p->r2, p->pg_acc, st);
     }
     if (pipe && seg >= 2) {

@@ -167,7 +167,20 @@ void launch_fem_adj(const FemArgs& a, int n_part, hipStream_t s);
 void launch_fem_stencil_fwd(const FemArgs& a, int n_part, hipStream_t s, bool energy);
 void launch_fem_stencil_adj(const FemArgs& a, int n_part, hipStream_t s);
 // fused FD + FEM (assembled-stencil) step, one launch
-void launch_step(const FdArgs& fa, const FemArgs& ea, hipStream_t s, bool adj, bool energy, bool nt);
+// Arguments of the paper-formula div-div gradient terms of one level (pg_tile.hpp).
+struct PgArgs {
+  const float* lam;     // lambda^k, [3][n_own] (owned order)
+  const float* E;       // forward E^k, [3][n_own]
+  int64_t n_own;
+  const int* api_own;   // FEM-node -> owned id
+  int fs[3];            // FEM nodes per axis
+  double h, wp, wx;
+  double* acc;          // [n_fem] FP64, free nodes
+};
+// pg: the div-div gradient terms of the step's input level, fused into an adjoint step of
+// the form R2 (nullable).
+void launch_step(const FdArgs& fa, const FemArgs& ea, hipStream_t s, bool adj, bool energy, bool nt,
+                 const PgArgs* pg = nullptr);
 
 // one item of a batched step launch
 struct BatchItem {

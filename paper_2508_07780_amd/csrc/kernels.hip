@@ -13,6 +13,7 @@
 //     lambda^{k-1} = lambda^k + Lambda^k.
 // Field state is FP32; the energy and gradient sums are FP64.
 #include "dd_common.hpp"
+#include "pg_tile.hpp"
 
 namespace dd {
 
@@ -812,19 +813,45 @@ __global__ __launch_bounds__(FD_THREADS) void step_kernel(FdArgs fa, FemArgs ea,
   fd_tile<ENERGY, NT>(fa, b - fem_blocks);
 }
 
+// The adjoint step of the form R1 with the paper-formula variant on: it also carries the
+// variant's div-div gradient terms of its input level (blocks [fem_blocks, fem_blocks +
+// pg_blocks), pg_tile), which read lambda^k and the saved E^k that the step does not write.
+template <bool NT>
+__global__ __launch_bounds__(FD_THREADS) void step_kernel_pg(FdArgs fa, FemArgs ea, int fem_blocks, PgArgs pg,
+                                                             int pg_blocks) {
+  const int b = blockIdx.x;
+  if (b < fem_blocks) {
+    const int p = fem_part_of_block(b, fem_blocks, ea.rev);
+    if (p < ea.n_part) fem_stencil_part<true, false>(ea, p);
+    return;
+  }
+  if (b < fem_blocks + pg_blocks) {
+    if (b - fem_blocks < pg_tiles(pg.fs)) pg_tile(pg, b - fem_blocks);
+    return;
+  }
+  fd_tile<false, NT>(fa, b - fem_blocks - pg_blocks);
+}
+
 // The same step with the FEM rows in the div-div form R2.  Unbounded, its FEM part takes
 // about 117 VGPRs and the whole launch runs at 4 waves per SIMD; held to 5 (96 VGPRs, 12-20
 // bytes of spill) the main workload's R2 solve took 172.9 ms against 186.2 ms (and 173.8 ms
-// at 6 waves, 80 VGPRs with 88-104 bytes of spill).
+// at 6 waves, 80 VGPRs with 88-104 bytes of spill).  An adjoint step also carries the
+// div-div gradient terms of its input level (blocks [fem_blocks, fem_blocks + pg_blocks),
+// pg_tile): they read lambda^k and the saved E^k, which the step does not write.
 template <bool ADJ, bool ENERGY, bool NT>
-__global__ __launch_bounds__(FD_THREADS, 5) void step_kernel_r2(FdArgs fa, FemArgs ea, int fem_blocks) {
+__global__ __launch_bounds__(FD_THREADS, 5) void step_kernel_r2(FdArgs fa, FemArgs ea, int fem_blocks, PgArgs pg,
+                                                                  int pg_blocks) {
   const int b = blockIdx.x;
   if (b < fem_blocks) {
     const int p = fem_part_of_block(b, fem_blocks, ea.rev);
     if (p < ea.n_part) fem_stencil_part<ADJ, ENERGY, true>(ea, p);
     return;
   }
-  fd_tile<ENERGY, NT>(fa, b - fem_blocks);
+  if (ADJ && b < fem_blocks + pg_blocks) {
+    if (b - fem_blocks < pg_tiles(pg.fs)) pg_tile(pg, b - fem_blocks);
+    return;
+  }
+  fd_tile<ENERGY, NT>(fa, b - fem_blocks - pg_blocks);
 }
 
 // ---------------------------------------------------------------------------------------
@@ -1032,17 +1059,33 @@ void launch_fem_stencil_adj(const FemArgs& a, int n_part, hipStream_t s) {
 }
 
 template <bool NT>
-static void launch_step_t(const FdArgs& fa, const FemArgs& ea, hipStream_t s, bool adj, bool energy) {
+static void launch_step_t(const FdArgs& fa, const FemArgs& ea, hipStream_t s, bool adj, bool energy,
+                          const PgArgs* pg) {
   const int fem_blocks = (ea.n_part + N_XCD - 1) / N_XCD * N_XCD;   // keeps FD blocks XCD-aligned
   const dim3 grid(fem_blocks + fa.per_xcd * N_XCD);
   const size_t lds = stencil_lds_bytes(ea);
   if (ea.r2) {
+    PgArgs g{};
+    int pg_blocks = 0;
+    if (adj && pg) {
+      g = *pg;
+      pg_blocks = (pg_tiles(g.fs) + N_XCD - 1) / N_XCD * N_XCD;
+    }
+    const dim3 grid_r2(fem_blocks + pg_blocks + fa.per_xcd * N_XCD);
+    const size_t lds_r2 = pg_blocks ? std::max(lds, PG_LDS_BYTES) : lds;
     if (adj)
-      hipLaunchKernelGGL((step_kernel_r2<true, false, NT>), grid, dim3(FD_THREADS), lds, s, fa, ea, fem_blocks);
+      hipLaunchKernelGGL((step_kernel_r2<true, false, NT>), grid_r2, dim3(FD_THREADS), lds_r2, s, fa, ea, fem_blocks, g,
+                         pg_blocks);
     else if (energy)
-      hipLaunchKernelGGL((step_kernel_r2<false, true, NT>), grid, dim3(FD_THREADS), lds, s, fa, ea, fem_blocks);
+      hipLaunchKernelGGL((step_kernel_r2<false, true, NT>), grid_r2, dim3(FD_THREADS), lds_r2, s, fa, ea, fem_blocks,
+                         g, 0);
     else
-      hipLaunchKernelGGL((step_kernel_r2<false, false, NT>), grid, dim3(FD_THREADS), lds, s, fa, ea, fem_blocks);
+      hipLaunchKernelGGL((step_kernel_r2<false, false, NT>), grid_r2, dim3(FD_THREADS), lds_r2, s, fa, ea, fem_blocks,
+                         g, 0);
+  } else if (adj && pg) {
+    const int pg_blocks = (pg_tiles(pg->fs) + N_XCD - 1) / N_XCD * N_XCD;
+    hipLaunchKernelGGL((step_kernel_pg<NT>), dim3(fem_blocks + pg_blocks + fa.per_xcd * N_XCD), dim3(FD_THREADS),
+                       std::max(lds, PG_LDS_BYTES), s, fa, ea, fem_blocks, *pg, pg_blocks);
   } else if (adj)
     hipLaunchKernelGGL((step_kernel<true, false, NT>), grid, dim3(FD_THREADS), lds, s, fa, ea, fem_blocks);
   else if (energy)
@@ -1051,11 +1094,12 @@ static void launch_step_t(const FdArgs& fa, const FemArgs& ea, hipStream_t s, bo
     hipLaunchKernelGGL((step_kernel<false, false, NT>), grid, dim3(FD_THREADS), lds, s, fa, ea, fem_blocks);
 }
 
-void launch_step(const FdArgs& fa, const FemArgs& ea, hipStream_t s, bool adj, bool energy, bool nt) {
+void launch_step(const FdArgs& fa, const FemArgs& ea, hipStream_t s, bool adj, bool energy, bool nt,
+                 const PgArgs* pg) {
   if (nt)
-    launch_step_t<true>(fa, ea, s, adj, energy);
+    launch_step_t<true>(fa, ea, s, adj, energy, pg);
   else
-    launch_step_t<false>(fa, ea, s, adj, energy);
+    launch_step_t<false>(fa, ea, s, adj, energy, pg);
 }
 
 void launch_energy_reduce(const double* part, int n, double* out, hipStream_t s) {
