@@ -186,9 +186,9 @@ int dd_misfit(dd_problem* p, const float* traces_dev, const float* obs_dev, int3
  * eps - 1 outside it, sum_K |K| (mean_K eps - 1) grad phi_i div_K(E) (symmetric); for this form
  * the paper's gradient formula (eq. gradeps with grad(eps~).E dropped) is the exact gradient,
  * and dd_gradient returns it.  R2 needs the assembled-stencil path (uniform Kuhn box;
- * DD_ERR_UNSUPPORTED otherwise); its steps are fused launches of their own (one more
- * launch per adjoint step adds the div-div gradient term); batched jobs run R1 only and
- * report DD_ERR_UNSUPPORTED for an R2 problem.  Switching the form discards a saved forward.
+ * DD_ERR_UNSUPPORTED otherwise); its steps are fused launches of their own, the adjoint
+ * ones carrying the div-div gradient terms; batched jobs run R1 only and report
+ * DD_ERR_UNSUPPORTED for an R2 problem.  Switching the form discards a saved forward.
  * The first switch to R2 allocates FEM-node sized buffers and synchronises the device. */
 enum { DD_DIVDIV_R1 = 1, DD_DIVDIV_R2 = 2 };
 int dd_set_divdiv_form(dd_problem* p, int32_t form);
@@ -200,8 +200,9 @@ int dd_set_divdiv_form(dd_problem* p, int32_t form);
  * exact derivative of a scheme whose div-div term carries the element mean of eps - 1
  * outside the divergence, not of this one.)
  * dd_paper_gradient_enable(p, 1): the following dd_adjoint / dd_adjoint_misfit calls also
- * accumulate the difference of the two terms (two small extra launches per adjoint step;
- * FEM-node sized buffers allocated on the first call, which synchronises the device);
+ * accumulate the difference of the two terms (inside the fused adjoint step launches, a
+ * launch of its own after each step otherwise; FEM-node sized buffers allocated on the
+ * first call, which synchronises the device);
  * 0 switches it off.  DD_ERR_UNSUPPORTED when FD and FEM run on two streams.  Batched jobs
  * never accumulate it.
  * dd_gradient_paper: after such an adjoint, the variant's g_eps and the (unchanged) g_sigma,
