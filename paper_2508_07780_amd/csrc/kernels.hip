@@ -587,7 +587,11 @@ __device__ __forceinline__ void r2_term(const float4* sX, int BX, int BY, int bx
   // registers, not memory
   constexpr int kKuhnPerm[6][3] = {{0, 1, 2}, {0, 2, 1}, {1, 0, 2}, {1, 2, 0}, {2, 0, 1}, {2, 1, 0}};
   float d[3] = {0.f, 0.f, 0.f};
-#pragma unroll
+  // four cells at a time: fully unrolled, the compiler hoists the 64 staged loads of all
+  // eight cells (117 VGPRs, 4 waves per SIMD for the launch); four at a time keeps the
+  // launch at 6 waves with no spill (73 VGPRs; the R2 solve 158.9 -> 148.8 ms, one cell at
+  // a time 155.8 ms)
+#pragma unroll 4
   for (int o = 0; o < 8; ++o) {
     const int cb = (bx - (o & 1)) + BX * ((by - ((o >> 1) & 1)) + BY * (bz - (o >> 2)));
     float4 v[8];
@@ -832,14 +836,12 @@ __global__ __launch_bounds__(FD_THREADS) void step_kernel_pg(FdArgs fa, FemArgs 
   fd_tile<false, NT>(fa, b - fem_blocks - pg_blocks);
 }
 
-// The same step with the FEM rows in the div-div form R2.  Unbounded, its FEM part takes
-// about 117 VGPRs and the whole launch runs at 4 waves per SIMD; held to 5 (96 VGPRs, 12-20
-// bytes of spill) the main workload's R2 solve took 172.9 ms against 186.2 ms (and 173.8 ms
-// at 6 waves, 80 VGPRs with 88-104 bytes of spill).  An adjoint step also carries the
+// The same step with the FEM rows in the div-div form R2 (about 73 VGPRs, 6 waves per SIMD,
+// with r2_term's cell loop unrolled four at a time).  An adjoint step also carries the
 // div-div gradient terms of its input level (blocks [fem_blocks, fem_blocks + pg_blocks),
 // pg_tile): they read lambda^k and the saved E^k, which the step does not write.
 template <bool ADJ, bool ENERGY, bool NT>
-__global__ __launch_bounds__(FD_THREADS, 5) void step_kernel_r2(FdArgs fa, FemArgs ea, int fem_blocks, PgArgs pg,
+__global__ __launch_bounds__(FD_THREADS) void step_kernel_r2(FdArgs fa, FemArgs ea, int fem_blocks, PgArgs pg,
                                                                   int pg_blocks) {
   const int b = blockIdx.x;
   if (b < fem_blocks) {
