@@ -57,7 +57,7 @@ enum {
   DD_OK = 0,
   DD_ERR_INVALID_ARG = -1,  /* bad descriptor, null pointer, size mismatch */
   DD_ERR_CONSTRAINT = -2,   /* eps / sigma violate eq. epsilon_sigma_constraint */
-  DD_ERR_UNSTABLE = -3,     /* non-finite field values after a solve */
+  DD_ERR_UNSTABLE = -3,     /* non-finite field values after a solve (dd_check_finite) */
   DD_ERR_OOM = -4,          /* device allocation failed */
   DD_ERR_HIP = -5,          /* a HIP runtime call or kernel launch failed */
   DD_ERR_STATE = -6,        /* call out of order (e.g. adjoint without a saved forward) */
@@ -130,6 +130,14 @@ int dd_set_coefficients(dd_problem* p, const float* eps_dev, const float* sigma_
  *       W^{n+1/2} = |V^{n+1}|^2_{M_eps} / (2 dt^2) + E^{n+1} . A E^n / 2. */
 int dd_forward(dd_problem* p, const dd_source* src, int32_t n_src, float* traces_dev,
                int32_t save, double* energy_dev, void* stream);
+
+/* Scans the current field state (both FD levels, the FEM levels and increment: after
+ * dd_forward the last forward state, after dd_adjoint the adjoint's) for non-finite values:
+ * DD_ERR_UNSTABLE when there are any, else DD_OK.  Synchronises `stream`.  The solve calls
+ * do not check by themselves (they stay asynchronous): with a time step within the CFL
+ * bound and coefficients that pass dd_set_coefficients the scheme is stable, so non-finite
+ * fields come from non-finite inputs that are not checked (cotangents, observations). */
+int dd_check_finite(dd_problem* p, void* stream);
 
 /* General initial data of the forward problem (eq. forward_initial_cond): E(x, 0) = f_0,
  * dE/dt(x, 0) = f_1.  f0_dev, f1_dev: [n_grid][3] float32 on the device, node index

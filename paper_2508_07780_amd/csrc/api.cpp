@@ -955,6 +955,24 @@ int dd_gradient_paper(dd_problem* p, double* g_eps_dev, double* g_sigma_dev, voi
   return check_launch(p);
 }
 
+int dd_check_finite(dd_problem* p, void* stream) {
+  if (!p) return DD_ERR_INVALID_ARG;
+  hipStream_t st = (hipStream_t)stream;
+  int h_err = 0;
+  if (hipMemsetAsync(p->d_err, 0, sizeof(int), st) != hipSuccess) return fail(p, DD_ERR_HIP, "hipMemsetAsync failed");
+  for (int b = 0; b < 2; ++b) {
+    launch_count_nonfinite(p->Efd[b], 3 * p->N, p->d_err, st);
+    launch_count_nonfinite(p->Efem[b], 3 * p->n_own, p->d_err, st);
+  }
+  launch_count_nonfinite(p->Vfem, 3 * p->n_own, p->d_err, st);
+  if (int rc = check_launch(p)) return rc;
+  if (hipMemcpyAsync(&h_err, p->d_err, sizeof(int), hipMemcpyDeviceToHost, st) != hipSuccess ||
+      hipStreamSynchronize(st) != hipSuccess)
+    return fail(p, DD_ERR_HIP, "error readback failed");
+  if (h_err) return fail(p, DD_ERR_UNSTABLE, std::to_string(h_err) + " non-finite field values");
+  return DD_OK;
+}
+
 int dd_set_initial_data(dd_problem* p, const float* f0_dev, const float* f1_dev, void* stream) {
   if (!p) return DD_ERR_INVALID_ARG;
   if (!f0_dev && !f1_dev) {

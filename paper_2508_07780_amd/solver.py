@@ -155,6 +155,10 @@ class Problem:
         code = {"R1": 1, "R2": 2}[form]
         _lib.check(_lib.load().dd_set_divdiv_form(self._h, code), self._h)
 
+    def check_finite(self):
+        """Raise DDError (DD_ERR_UNSTABLE) if the current fields hold non-finite values."""
+        _lib.check(_lib.load().dd_check_finite(self._h, _stream()), self._h)
+
     def set_initial_data(self, f0=None, f1=None):
         """E(0) = f0, dE/dt(0) = f1 (eq. forward_initial_cond) for the following forwards:
         CUDA tensors of n_grid x 3 values (node-major, node index x + Nx (y + Ny z)).  Both None:

@@ -96,3 +96,26 @@ def test_edge_case_matches_oracle(name):
     else:
         assert not np.any(ge) and not np.any(gs)
     p.close()
+
+
+def test_check_finite_reports_non_finite_fields():
+    """dd_check_finite: clean fields after a forward; a NaN in the (unchecked) cotangent
+    reaches the adjoint's fields and is reported as DD_ERR_UNSTABLE; a clean solve after it
+    starts from fresh state again."""
+    import torch
+    from paper_2508_07780_amd import DDError, Problem
+    w = synth.small("tiny")
+    p = Problem(w.desc)
+    p.set_coefficients(torch.tensor(w.eps, dtype=torch.float32, device="cuda"),
+                       torch.tensor(w.sigma, dtype=torch.float32, device="cuda"))
+    tr = p.forward(w.sources, save=True)
+    p.check_finite()
+    cot = tr.clone()
+    cot[0, w.desc.n_steps - 1, 0, 1] = float("nan")
+    p.adjoint(cot)
+    with pytest.raises(DDError) as e:
+        p.check_finite()
+    assert e.value.code == -3
+    p.forward(w.sources, save=True)
+    p.check_finite()
+    p.close()
