@@ -1516,8 +1516,16 @@ int dd_batch_step(dd_batch* b, int32_t max_steps, void* stream) {
         b->err = "batch upload failed";
         return DD_ERR_HIP;
       }
-      for (int k = 0; k < m; ++k)
-        if (bases[k].n) launch_batch(b->dev + off + (size_t)k * b->width, bases[k], lds[k], st, nt[k]);
+      for (int k = 0; k < m; ++k) {
+        if (!bases[k].n) continue;
+        const BatchItem& one = b->host[off + (size_t)k * b->width];
+        if (bases[k].n == 1 && one.kind != 2)
+          // a single forward or adjoint step: the fused step kernel, arguments by value (the
+          // same device code on the same arguments, without the item lookup)
+          launch_step(one.fa, one.ea, st, one.kind == 1, false, nt[k]);
+        else
+          launch_batch(b->dev + off + (size_t)k * b->width, bases[k], lds[k], st, nt[k]);
+      }
       hipError_t e = hipGetLastError();
       if (e != hipSuccess) {
         b->err = std::string("batch launch failed: ") + hipGetErrorString(e);
