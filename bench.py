@@ -46,6 +46,11 @@ def measured_traffic(key):
     return float(v) if v else None
 
 
+def progress(msg):
+    """One line on stderr as each part of the run completes (the JSON result goes to stdout)."""
+    print("[bench] " + msg, file=sys.stderr, flush=True)
+
+
 def _percentile(xs, q):
     xs = sorted(xs)
     if not xs:
@@ -304,32 +309,41 @@ def cga_measure(prob, w, eobs, n_iter):
     }
 
 
-def serving_comparison():
+def serving_comparison(n_jobs=24, ranges="small"):
     """Continuous batching vs one solve at a time on the same uneven request stream.
 
-    Requests (seeded): outer grids {64, 96, 128}^3, FEM boxes {32, 48}^3 hexes, 1-4 plane-wave
-    or dipole sources, 300-800 steps, 2-4 reconstruction iterations each.  A burst (all jobs
-    at t = 0) measures throughput; Poisson arrivals at 0.8x the measured one-at-a-time
-    capacity measure latency.
+    Requests (seeded), ranges "small": outer grids {64, 96, 128}^3, FEM boxes {32, 48}^3 hexes,
+    1-4 plane-wave or dipole sources, 300-800 steps, 2-4 reconstruction iterations each;
+    "full": outer {64, 96, 128, 160, 224}^3, FEM {32, 48, 64, 96}^3, 1-8 sources, 500-2000
+    steps, 3-10 iterations.  A burst (all jobs at t = 0) measures throughput; Poisson
+    arrivals at 0.8x the measured one-at-a-time capacity measure latency.
     """
     import synth
     from paper_2508_07780_amd import serving
-    kw = dict(outer=(64, 96, 128), fem=(32, 48), sources=(1, 4), steps=(300, 800), iterations=(2, 4))
-    burst = synth.serving_requests(24, 1e9, **kw)
+    if ranges == "full":
+        kw = {}
+        label = "outer {64,96,128,160,224}^3, FEM {32,48,64,96}^3 hexes, 1-8 sources, 500-2000 steps, 3-10 iterations"
+    else:
+        kw = dict(outer=(64, 96, 128), fem=(32, 48), sources=(1, 4), steps=(300, 800), iterations=(2, 4))
+        label = "outer {64,96,128}^3, FEM {32,48}^3 hexes, 1-4 sources, 300-800 steps, 2-4 iterations"
+    burst = synth.serving_requests(n_jobs, 1e9, **kw)
     for r in burst:
         r.arrival = 0.0
     serving.serve_serial(burst[:2])                       # warm-up
     s_serial, _ = serving.serve_serial(burst)
+    progress("serving: burst, one at a time")
     s_batch, _ = serving.serve_batched(burst, max_slots=16)
+    progress("serving: burst, batched")
     rate = 0.8 * s_serial["jobs"] / s_serial["makespan_s"]
-    stream = synth.serving_requests(24, rate, **kw)
+    stream = synth.serving_requests(n_jobs, rate, **kw)
     l_serial, _ = serving.serve_serial(stream)
+    progress("serving: Poisson stream, one at a time")
     l_batch, _ = serving.serve_batched(stream, max_slots=16)
+    progress("serving: Poisson stream, batched")
     keep = ("jobs", "solves", "makespan_s", "throughput_gcell_steps_s", "latency_p50_s", "latency_p99_s")
     pick = lambda d: {k: (round(d[k], 4) if isinstance(d[k], float) else d[k]) for k in keep}  # noqa: E731
     return {
-        "workload": "24 jobs: outer {64,96,128}^3, FEM {32,48}^3 hexes, 1-4 sources, 300-800 steps, "
-                    "2-4 iterations; seeded",
+        "workload": "%d jobs: %s; seeded" % (n_jobs, label),
         "burst": {"batched": pick(s_batch), "one_at_a_time": pick(s_serial),
                   "throughput_ratio": round(s_batch["throughput_gcell_steps_s"] / s_serial["throughput_gcell_steps_s"], 3)},
         "poisson_0.8x": {"rate_jobs_per_s": round(rate, 3), "batched": pick(l_batch), "one_at_a_time": pick(l_serial)},
@@ -348,6 +362,9 @@ def main():
     ap.add_argument("--cpu-sample-steps", type=int, default=8, help="0 skips the oracle baseline")
     ap.add_argument("--no-profile", action="store_true", help="skip the HIP-event kernel timing")
     ap.add_argument("--serving", type=int, default=1, help="0 skips the batched / serving comparison")
+    ap.add_argument("--serving-jobs", type=int, default=24, help="requests of the serving comparison")
+    ap.add_argument("--serving-ranges", choices=("small", "full"), default="small",
+                    help="request size ranges of the serving comparison")
     ap.add_argument("--probe", type=int, default=1, help="0 skips the 288^3 bandwidth probe")
     ap.add_argument("--probe-only", action="store_true",
                     help="run only the 288^3 probe (for profilers) and print its JSON")
@@ -473,15 +490,20 @@ def main():
     if args.cga:
         out["cga"] = cga_measure(prob, w, eobs, args.cga)
     del prob
+    progress("main workload")
     if args.probe:
         out["hbm_probe"] = large_probe(args.probe_steps)
+        progress("288^3 probe")
     if args.c3:
         out["c3_autograd"] = c3_autograd()
+        progress("192^3 autograd")
     if args.serving:
         out["batched_mix"] = batch_comparison()
-        out["serving"] = serving_comparison()
+        progress("batched mix")
+        out["serving"] = serving_comparison(args.serving_jobs, args.serving_ranges)
     if args.cpu_sample_steps > 0:
         out["cpu_baseline"] = cpu_baseline(w, args.cpu_sample_steps)
+        progress("oracle baseline")
     print(json.dumps(out), flush=True)
 
 
