@@ -7,7 +7,10 @@ between its solves.  A job is admitted
 when a batch slot is free and its device footprint (dd_footprint_bytes plus its trace,
 observation and gradient buffers) fits in the HBM budget; admitted solves join the
 running batch at the next launch, so work of jobs of different sizes overlaps on the
-device.  The one-at-a-time server runs the same jobs in arrival order through the
+device.  A job whose single step already fills the GPU (at least `solo_cells` cells per
+step) gains nothing from sharing launches and is slower through the batch kernel: it waits
+until the batch is empty and then runs alone through the single-problem calls, in arrival
+order like every other job.  The one-at-a-time server runs the same jobs in arrival order through the
 single-problem calls, for comparison.
 
 Requests are plain objects with `arrival` (s), `iterations` and `workload` (desc, sources,
@@ -91,9 +94,27 @@ def _final(job):
     return {"eps": job.cga.eps.clone(), "sigma": job.cga.sigma.clone()}
 
 
-def serve_batched(requests, max_slots=16, hbm_budget=None, chunk=256, time_fn=time.perf_counter, keep=False):
+def step_cells(desc):
+    """Cells (outer nodes + FEM-owned nodes) one time step of the problem advances."""
+    return cell_steps(desc, 1) // (2 * int(desc.n_steps))
+
+
+def _run_alone(job):
+    """All iterations of one job through the single-problem calls."""
+    req = job.req
+    for _ in range(req.iterations):
+        tr = job.problem.forward(req.workload.sources, save=True)
+        job.problem.adjoint_misfit(tr, job.obs)
+        ge, gs = job.problem.gradient()
+        job.update(ge, gs)
+        job.done_iters += 1
+
+
+def serve_batched(requests, max_slots=16, hbm_budget=None, chunk=256, time_fn=time.perf_counter, keep=False,
+                  solo_cells=3_000_000):
     """Continuous batching: returns a summary dict and per-job records (with each job's final
-    eps and sigma when keep is set)."""
+    eps and sigma when keep is set).  Jobs of at least solo_cells cells per step run alone
+    through the single-problem calls (None: every job is batched)."""
     dev = torch.device("cuda", torch.cuda.current_device())
     if hbm_budget is None:
         free, _ = torch.cuda.mem_get_info()
@@ -112,6 +133,25 @@ def serve_batched(requests, max_slots=16, hbm_budget=None, chunk=256, time_fn=ti
         # admission: arrived, a slot free, the footprint fits
         while pending and pending[0].arrival <= now and len(active) < max_slots:
             fp = job_footprint(pending[0])
+            if fp > hbm_budget:
+                raise ValueError(f"request {pending[0].rid} needs {fp} bytes, over the HBM budget of {hbm_budget}")
+            if solo_cells is not None and step_cells(pending[0].workload.desc) >= solo_cells:
+                if active:
+                    break                # the batch drains first (arrival order is kept)
+                req = pending.pop(0)
+                peak_bytes = max(peak_bytes, fp)
+                peak_jobs = max(peak_jobs, 1)
+                job = _Job(req, dev)
+                _run_alone(job)
+                solves += req.iterations
+                work += cell_steps(req.workload.desc, len(req.workload.sources)) * req.iterations
+                t_done = time_fn() - t0
+                lat.append(t_done - req.arrival)
+                records.append({"rid": req.rid, "arrival": req.arrival, "done": t_done, "iterations": req.iterations,
+                                **(_final(job) if keep else {})})
+                job.close()
+                now = time_fn() - t0
+                continue
             if in_use + fp > hbm_budget:
                 break
             req = pending.pop(0)
@@ -123,6 +163,8 @@ def serve_batched(requests, max_slots=16, hbm_budget=None, chunk=256, time_fn=ti
             peak_bytes = max(peak_bytes, in_use)
             peak_jobs = max(peak_jobs, len(active))
         if not active:
+            if not pending:
+                break            # the last jobs ran alone
             # idle until the next arrival
             time.sleep(max(0.0, min(0.01, pending[0].arrival - now)))
             continue

@@ -144,3 +144,29 @@ def test_serving_completes_and_respects_budget():
             a, b = (x[f].double() - base for x in (r, by_rid[r["rid"]]))
             assert float(torch.linalg.norm(b)) > 0
             assert float(torch.linalg.norm(a - b)) <= 1e-4 * float(torch.linalg.norm(b)), (r["rid"], f)
+
+
+def test_serving_runs_large_jobs_alone():
+    """Jobs at or above the solo threshold wait for the batch to drain and run alone through
+    the single-problem calls (the one-at-a-time server's calls: the same reconstruction bit
+    for bit); the others are batched; every job completes in arrival order of admission."""
+    import torch
+    from paper_2508_07780_amd import serving
+    reqs = synth.serving_requests(6, 20.0, outer=(40, 48), fem=(16, 24), sources=(1, 3), steps=(40, 90),
+                                  iterations=(2, 3))
+    cells = sorted(serving.step_cells(r.workload.desc) for r in reqs)
+    thr = cells[len(cells) // 2]
+    solo = {r.rid for r in reqs if serving.step_cells(r.workload.desc) >= thr}
+    assert 0 < len(solo) < len(reqs)
+    s_b, rec_b = serving.serve_batched(reqs, max_slots=4, chunk=16, keep=True, solo_cells=thr)
+    s_s, rec_s = serving.serve_serial(reqs, keep=True)
+    print(f"[gpu] serving with {len(solo)} solo jobs: {s_b}", flush=True)
+    assert s_b["jobs"] == len(reqs) and s_b["solves"] == s_s["solves"]
+    by_rid = {r["rid"]: r for r in rec_s}
+    for r in rec_b:
+        for f, base in (("eps", 1.0), ("sigma", 0.0)):
+            a, b = (x[f].double() - base for x in (r, by_rid[r["rid"]]))
+            if r["rid"] in solo:
+                assert torch.equal(a, b), (r["rid"], f)
+            else:
+                assert float(torch.linalg.norm(a - b)) <= 1e-4 * float(torch.linalg.norm(b)), (r["rid"], f)
