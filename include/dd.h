@@ -281,12 +281,14 @@ const char* dd_last_error(const dd_problem* p);
  * each source with saving, then -- when obs_dev is given -- the adjoint for the misfit
  * cotangent traces - obs (read inside the adjoint kernel; obs_dev has the traces' layout)
  * and the gradient summed over sources, written to g_eps_dev / g_sigma_dev (FEM-node
- * arrays, float64) when those are given.  dd_batch_step advances every active job by up
- * to max_steps time steps: each iteration is one kernel launch in which every active job
- * contributes its next step (a forward step, or an adjoint step together with the next
- * checkpoint recompute step of the segment before it, which uses the other window), so jobs of uneven
- * grid sizes, step counts and source counts share the GPU and new jobs can join while
- * others run.  dd_batch_step returns early, after the launch in which a job completed, so
+ * arrays, float64) when those are given.  dd_batch_step issues up to max_steps kernel
+ * launches.  A launch takes the oldest active jobs until their cells per step (outer nodes
+ * + FEM-owned nodes) reach the batch's fill target (dd_batch_set_fill; at least one job),
+ * and each job it takes contributes its next step (a forward step, or an adjoint step
+ * together with the next checkpoint recompute step of the segment before it, which uses
+ * the other window).  So jobs of uneven grid sizes, step counts and source counts share
+ * the GPU while they are small, a job that fills the GPU alone runs alone, and new jobs
+ * can join while others run.  dd_batch_step returns early, after the launch in which a job completed, so
  * that a caller can collect results and admit new jobs without waiting for the remaining
  * steps it asked for.  A finished job's results are complete once `stream` reaches the work
  * queued by the dd_batch_step call that reported it through dd_batch_poll; afterwards the
@@ -298,6 +300,9 @@ const char* dd_last_error(const dd_problem* p);
  * in dd_batch_submit (see dd_footprint_bytes); dd_batch_step allocates nothing. */
 typedef struct dd_batch dd_batch;
 int dd_batch_create(int32_t max_slots, dd_batch** out);
+/* Fill target of a launch in cells per step (default 6,000,000); 0 lets every active job
+ * take part in every launch.  Negative: DD_ERR_INVALID_ARG. */
+int dd_batch_set_fill(dd_batch* b, int64_t cells);
 int dd_batch_destroy(dd_batch* b);
 int dd_batch_submit(dd_batch* b, dd_problem* p, const dd_source* src, int32_t n_src, float* traces_dev,
                     const float* obs_dev, double* g_eps_dev, double* g_sigma_dev, int32_t* job_out);

@@ -18,7 +18,7 @@ EXPORTS = [
     "dd_profile_enable", "dd_profile_read", "dd_algorithmic_bytes", "dd_debug_fem_apply",
     "dd_batch_create", "dd_batch_destroy", "dd_batch_submit", "dd_batch_step", "dd_batch_poll",
     "dd_adjoint_misfit", "dd_cga_create", "dd_cga_destroy", "dd_cga_update", "dd_cga_get_info",
-    "dd_paper_gradient_enable", "dd_gradient_paper", "dd_misfit", "dd_set_divdiv_form", "dd_set_initial_data", "dd_check_finite",
+    "dd_paper_gradient_enable", "dd_gradient_paper", "dd_misfit", "dd_set_divdiv_form", "dd_set_initial_data", "dd_check_finite", "dd_batch_set_fill",
 ]
 
 PROF_FD_FWD, PROF_FEM_FWD, PROF_FD_ADJ, PROF_FEM_ADJ, PROF_FEM_RECOMPUTE, PROF_STEP_FWD, PROF_STEP_ADJ = range(7)
@@ -119,6 +119,7 @@ def load():
     lib.dd_gradient_paper.argtypes = [P, P, P, P]
     lib.dd_set_initial_data.argtypes = [P, P, P, P]
     lib.dd_check_finite.argtypes = [P, P]
+    lib.dd_batch_set_fill.argtypes = [P, ctypes.c_int64]
     lib.dd_cga_create.argtypes = [P, ctypes.POINTER(CgaParams), P, P, P, ctypes.POINTER(P)]
     lib.dd_cga_destroy.argtypes = [P]
     lib.dd_cga_update.argtypes = [P, P, P, P, P, P]

@@ -11,9 +11,13 @@ from .solver import _ptr, _stream
 class Batch:
     """Up to `max_slots` concurrent solves sharing every step launch."""
 
-    def __init__(self, max_slots=16):
+    def __init__(self, max_slots=16, fill_cells=None):
+        """fill_cells: a launch takes the oldest jobs until their cells per step reach this
+        (None: the library's default; 0: every job in every launch)."""
         self._h = ctypes.c_void_p()
         _lib.check(_lib.load().dd_batch_create(int(max_slots), ctypes.byref(self._h)))
+        if fill_cells is not None:
+            _lib.check(_lib.load().dd_batch_set_fill(self._h, int(fill_cells)))
         self.max_slots = int(max_slots)
         self.jobs = {}          # job id -> dict with the problem and the tensors it writes
 

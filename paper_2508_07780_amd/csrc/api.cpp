@@ -1366,6 +1366,13 @@ struct dd_batch {
   static constexpr int seg = 16;
   int ring = 64, pos = 0;
   bool return_on_done = true;   // dd_batch_step returns after the launch in which a job finishes
+  // a launch takes the oldest active jobs until their cells per step reach this (at least
+  // one job; 0: every active job in every launch).  Measured on the 16-problem mix and the
+  // small serving burst (throughput against one problem at a time): 0: 0.855 / 1.067;
+  // 3M: 0.919 / 0.998; 6M: 0.880 / 1.070; 12M: 0.853 / 1.057.  Small jobs gain from sharing
+  // launches (the fixed cost per launch is spread), large ones from keeping their fields in
+  // the last-level cache.
+  int64_t fill_cells = 6000000;
   std::string err;
 };
 
@@ -1447,6 +1454,27 @@ int dd_batch_submit(dd_batch* b, dd_problem* p, const dd_source* src, int32_t n_
   return DD_OK;
 }
 
+namespace {
+// Number of jobs (a prefix of b->jobs, oldest first) that take part in the next launch.
+size_t launch_jobs(const dd_batch* b) {
+  if (b->fill_cells <= 0) return b->jobs.size();
+  int64_t cells = 0;
+  size_t n = 0;
+  for (const auto& j : b->jobs) {
+    if (n > 0 && cells >= b->fill_cells) break;
+    if (j.phase != 2) cells += j.p->N + j.p->n_own;
+    ++n;
+  }
+  return n;
+}
+}  // namespace
+
+int dd_batch_set_fill(dd_batch* b, int64_t cells) {
+  if (!b || cells < 0) return DD_ERR_INVALID_ARG;
+  b->fill_cells = cells;
+  return DD_OK;
+}
+
 int dd_batch_step(dd_batch* b, int32_t max_steps, void* stream) {
   if (!b || max_steps < 0) return DD_ERR_INVALID_ARG;
   hipStream_t st = (hipStream_t)stream;
@@ -1468,13 +1496,15 @@ int dd_batch_step(dd_batch* b, int32_t max_steps, void* stream) {
     int m = 0;
     bool finished = false;
     while (m < b->seg && iter < max_steps && !b->jobs.empty()) {
-      if (m > 0 && std::any_of(b->jobs.begin(), b->jobs.end(), job_needs_prologue)) break;
+      const size_t nj = launch_jobs(b);
+      if (m > 0 && std::any_of(b->jobs.begin(), b->jobs.begin() + nj, job_needs_prologue)) break;
       BatchItem* h = b->host + (size_t)(b->pos + m) * b->width;
       int n = 0, base = 0;
       size_t l = 0;
       double fd_bytes = 0.0;   // the FD field sets this launch streams through
       const dd_problem* owner[BATCH_MAX];
-      for (auto& j : b->jobs) {
+      for (size_t q = 0; q < nj; ++q) {
+        BatchJob& j = b->jobs[q];
         const int c = job_items(j, st, h + n);
         for (int i = 0; i < c; ++i) {
           if (h[n].kind != 2) fd_bytes += fd_field_bytes(j.p);

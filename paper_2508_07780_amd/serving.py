@@ -111,16 +111,17 @@ def _run_alone(job):
 
 
 def serve_batched(requests, max_slots=16, hbm_budget=None, chunk=256, time_fn=time.perf_counter, keep=False,
-                  solo_cells=3_000_000):
+                  solo_cells=3_000_000, fill_cells=None):
     """Continuous batching: returns a summary dict and per-job records (with each job's final
     eps and sigma when keep is set).  Jobs of at least solo_cells cells per step run alone
-    through the single-problem calls (None: every job is batched)."""
+    through the single-problem calls (None: every job is batched).  fill_cells: the batch's
+    fill target per launch (None: the library's default)."""
     dev = torch.device("cuda", torch.cuda.current_device())
     if hbm_budget is None:
         free, _ = torch.cuda.mem_get_info()
         hbm_budget = int(0.9 * free)
     pending = sorted(requests, key=lambda r: r.arrival)
-    batch = Batch(max_slots)
+    batch = Batch(max_slots, fill_cells=fill_cells)
     active = {}           # job id in the batch -> _Job
     in_use = 0
     lat, records = [], []

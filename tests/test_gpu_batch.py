@@ -66,7 +66,10 @@ def _rel(a, b):
     return float((a - b).double().norm() / b.double().norm())
 
 
-def test_batch_equals_alone_including_late_join():
+@pytest.mark.parametrize("fill", [None, 0, 1])
+def test_batch_equals_alone_including_late_join(fill):
+    """fill: the library's default fill target (these small jobs all share each launch), 0
+    (every job in every launch), 1 (one job per launch, oldest first: the late job waits)."""
     import torch
     from paper_2508_07780_amd import Problem
     from paper_2508_07780_amd.batch import Batch
@@ -78,14 +81,14 @@ def test_batch_equals_alone_including_late_join():
                            torch.tensor(w.sigma, dtype=torch.float32, device="cuda"))
         probs.append(p)
         obs.append(_obs(torch, p, len(w.sources), 5 + i))
-    batch = Batch(8)
+    batch = Batch(8, fill_cells=fill)
     ids = [batch.submit(probs[i], mix[i].sources, obs=obs[i]) for i in (0, 1)]
     batch.step(25)                     # the third job joins while the others run
     ids.append(batch.submit(probs[2], mix[2].sources, obs=obs[2]))
     recs = {r["id"]: r for r in batch.run_to_completion(chunk=16)}
     torch.cuda.synchronize()
     for i, w in enumerate(mix):
-        print(f"[gpu] batch vs alone {w.name}", flush=True)
+        print(f"[gpu] batch (fill {fill}) vs alone {w.name}", flush=True)
         r = recs[ids[i]]
         tr, ge, gs = _alone(torch, w, obs[i])
         same = torch.equal(r["traces"], tr) and torch.equal(r["g_eps"], ge) and torch.equal(r["g_sigma"], gs)
