@@ -168,3 +168,14 @@ def test_fem_data_path_reproduces_oracle_operator(lib, name):
     assert st[5] == own.sum() and st[6] == (d.fem_layer == 0).sum()
     assert st[1] <= 64 and st[2] <= 1024
     assert st[7] == 15      # Kuhn star: self + 14 edge neighbours
+
+
+def test_bench_refuses_several_gpus():
+    """bench.py measures one GPU: --gpus above 1 exits with a message before touching a GPU."""
+    import subprocess
+    import sys
+    root = os.path.dirname(os.path.dirname(os.path.abspath(__file__)))
+    r = subprocess.run([sys.executable, os.path.join(root, "bench.py"), "--gpus", "2"], capture_output=True,
+                       text=True, timeout=120)
+    assert r.returncode != 0
+    assert "one GPU" in (r.stdout + r.stderr)
