@@ -82,3 +82,56 @@ def test_r2_differs_from_r1_and_batch_refuses():
     assert e.value.code == -7
     b.close()
     p.close()
+
+
+def test_r2_gradient_at_full_size_against_directional_differences():
+    """The form R2 at the main workload's size (160^3 outer nodes, 64^3 FEM hexes, 2000 steps),
+    where the oracle is too slow: the gradient (the paper formula, exact for R2) against
+    central differences of the GPU loss along the gradient and a smooth field, for eps and
+    sigma; steps 1e-2 and 2e-2 agree to 1 %, and their Richardson extrapolation matches the
+    adjoint directional derivative to 1e-3.  Observations: the noise-free R2 traces of the
+    true medium; evaluation point far from it (as in the 192^3 autograd test)."""
+    import torch
+    from paper_2508_07780_amd import Problem
+    w = synth.c2()
+    dev = torch.device("cuda", 0)
+    print("[gpu] R2 at full size: 160^3, 2000 steps", flush=True)
+    p = Problem(w.desc)
+    p.set_divdiv_form("R2")
+    f32 = lambda a: torch.tensor(a, dtype=torch.float32, device=dev)  # noqa: E731
+    p.set_coefficients(f32(w.eps_true), f32(w.sigma_true))
+    eobs = p.forward(w.sources, save=False).clone()
+    free = synth.fem_layers(w.desc) >= 2
+    eps0 = np.where(free, 1.05 + 0.2 * (w.eps_true - 1.0), 1.0)
+    sig0 = np.where(free, 0.5 * w.sigma_true + 0.05, 0.0)
+
+    def loss(e, s):
+        p.set_coefficients(f32(e), f32(s))
+        r = (p.forward(w.sources, save=False) - eobs).double()
+        return float(0.5 * torch.sum(r * r))
+
+    p.set_coefficients(f32(eps0), f32(sig0))
+    tr = p.forward(w.sources, save=True)
+    p.adjoint_misfit(tr, eobs)
+    g_eps, g_sig = (g.cpu().numpy() for g in p.gradient())
+    np.testing.assert_array_equal(p.gradient_paper()[0].cpu().numpy(), g_eps)
+    x = synth.fem_node_coords(w.desc)
+    rng = np.random.Generator(np.random.PCG64(w.seed + 7))
+    k = rng.normal(size=3) * 2.0 * np.pi
+    smooth = np.where(free, 1.0 + 0.5 * np.sin(x @ k + rng.uniform(0, 2 * np.pi)), 0.0)
+    for which, g, base in (("eps", g_eps, eps0), ("sigma", g_sig, sig0)):
+        for name, d in (("gradient", np.where(free, g, 0.0)), ("smooth", smooth)):
+            d = d / np.abs(d).max()
+            pred = float(g @ d)
+            fds = []
+            for delta in (1e-2, 2e-2):
+                vals = [loss(base + sg * delta * d if which == "eps" else eps0,
+                             base + sg * delta * d if which == "sigma" else sig0) for sg in (1.0, -1.0)]
+                fds.append((vals[0] - vals[1]) / (2 * delta))
+            rich = (4.0 * fds[0] - fds[1]) / 3.0
+            rel = abs(pred - rich) / abs(rich)
+            print(f"[gpu]   R2 {which}/{name}: adjoint {pred:.8e} fd {fds[0]:.8e} / {fds[1]:.8e} "
+                  f"richardson {rich:.8e} rel {rel:.2e}", flush=True)
+            assert abs(fds[0] - fds[1]) <= 1e-2 * abs(fds[0]), "finite differences not converged"
+            assert rel <= 1e-3
+    p.close()
