@@ -124,3 +124,28 @@ def test_cga_with_taper_and_loss_matches_oracle():
             assert err <= 2e-3
     c.close()
     p.close()
+
+
+def test_misfit_at_full_size():
+    """dd_misfit on the main workload's trace size (2000 steps x 25 600 top-face detectors x 3,
+    614 MB per array) with the taper: the cotangent equals z_n (T - E_obs) rounded once from
+    FP64 (bit for bit), and J the FP64 sum of its definition to 1e-12 (another order)."""
+    import torch
+    from paper_2508_07780_amd import Problem
+    w = synth.c2()
+    nt = w.desc.n_steps
+    p = Problem(w.desc)
+    g = torch.Generator(device="cuda")
+    g.manual_seed(11)
+    T = torch.randn((1, nt, p.n_det, 3), generator=g, device="cuda", dtype=torch.float32)
+    O = (0.9 * T + 0.05 * torch.randn(T.shape, generator=g, device="cuda", dtype=torch.float32)).contiguous()
+    z = taper(nt, w.desc.dt, 0.25 * nt * w.desc.dt)
+    print(f"[gpu] misfit at full size: {tuple(T.shape)}", flush=True)
+    J, cot = p.misfit(T, O, z)
+    zt = torch.tensor(z, dtype=torch.float64, device="cuda").view(1, nt, 1, 1)
+    r = T.double() - O.double()
+    assert torch.equal(cot, (zt * r).float())
+    Jref = float(0.5 * torch.sum(zt * r * r))
+    print(f"[gpu]   J {float(J.item()):.12e} reference {Jref:.12e}", flush=True)
+    assert float(J.item()) == pytest.approx(Jref, rel=1e-12)
+    p.close()
