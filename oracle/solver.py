@@ -204,6 +204,12 @@ def adjoint_gradient(d, cot, fwd, keep_lambda=False):
     for n in range(nt):
         g_mass_sbp -= m * np.sum((lam_f[n + 1] - lam_f[n]) * (Eh[n + 2] - Eh[n + 1]), axis=1) / dt ** 2
     g_mass_sbp -= m * np.sum(lam_f[0] * (Eh[1] - Eh[0]), axis=1) / dt ** 2
+    # the sigma term summed by parts: sum_n m (lambda^n + lambda^{n+1}) . (E^{n+1} - E^n) / (2 dt)
+    # plus the boundary row m lambda^0 . V^0 / (2 dt) of the starting levels (zero from rest)
+    g_sig_sbp = np.zeros(d.n_fem)
+    for n in range(nt):
+        g_sig_sbp += m * np.sum((lam_f[n] + lam_f[n + 1]) * (Eh[n + 2] - Eh[n + 1]), axis=1) / (2.0 * dt)
+    g_sig_sbp += m * np.sum(lam_f[0] * (Eh[1] - Eh[0]), axis=1) / (2.0 * dt)
     free = d.fem_free
     g_eps_paper = np.where(free, g_mass + g_dd_paper, 0.0)
     if getattr(d, "divdiv_form", "R1") == "R2":
@@ -211,7 +217,8 @@ def adjoint_gradient(d, cot, fwd, keep_lambda=False):
     g_eps = np.where(free, g_mass + g_dd, 0.0)
     g_sigma = np.where(free, g_sig, 0.0)
     out = dict(g_eps=g_eps, g_sigma=g_sigma, g_mass=np.where(free, g_mass, 0.0),
-               g_mass_sbp=np.where(free, g_mass_sbp, 0.0), g_divdiv=np.where(free, g_dd, 0.0),
+               g_mass_sbp=np.where(free, g_mass_sbp, 0.0), g_sigma_sbp=np.where(free, g_sig_sbp, 0.0),
+               g_divdiv=np.where(free, g_dd, 0.0),
                g_eps_paper=g_eps_paper)
     if keep_lambda:
         out["lambda"] = lams

@@ -143,6 +143,8 @@ def sbp_errors(solver=None):
     lam0 = ag["lambda"][0][d.fem_grid]
     V0 = w.desc.dt * init[1][d.fem_grid]
     bt = np.where(d.fem_free, d.m[d.fem_grid] * np.sum(lam0 * V0, axis=1) / w.desc.dt ** 2, 0.0)
+    ss = np.abs(ag["g_sigma"]).max()
+    assert np.abs(ag["g_sigma"] - ag["g_sigma_sbp"]).max() <= 1e-12 * ss   # with its lambda^0 . V^0 row
     return float(np.abs(ag["g_mass"] - ag["g_mass_sbp"]).max() / scale), float(np.abs(bt).max() / scale)
 
 
