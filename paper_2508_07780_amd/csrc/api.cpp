@@ -458,6 +458,7 @@ void adj_step_args(const dd_problem* p, int s, int64_t k, int64_t k0, const floa
   ea.ck_X = ea.ck_I = nullptr;
   ea.wE = win + (k - k0) * 6 * n_own;
   ea.wV = ea.wE + 3 * n_own;
+  ea.wVm = win + (k - 1 - k0) * 6 * n_own + 3 * n_own;
   ea.g_eps = p->g_eps;
   ea.g_sig = p->g_sig;
 }
@@ -580,7 +581,7 @@ int run_adjoint(dd_problem* p, int s, const float* cot, const float* obs, hipStr
     const float* lam0 = p->Efem[0];
     const float* lvl0 = (nseg == 1) ? p->tail[s] : p->ckpt[s];
     launch_init_mass_row(lam0, lvl0 + 3 * p->n_own, p->own_grid, p->mass_d, p->n_own, 1.0 / (p->d.dt * p->d.dt),
-                         1.0 / (2.0 * p->d.dt), p->g_eps, p->g_sig, st);
+                         p->g_eps, st);
     if (p->r2) {
       launch_divdiv_grad_terms(lam0, lvl0, p->n_own, p->api_own, p->fs, p->d.h, 1.0, 0.0, p->pg_acc, st);
     } else {
@@ -1204,8 +1205,8 @@ int dd_algorithmic_bytes(const dd_problem* p, int32_t kind, double* bytes_per_la
   // FEM: state read and written, coefficients (eps - 1, c1, c2), layer-0 values read,
   // layer-1 values dual-written into the FD grid
   const double fem = 48.0 * n_own + 12.0 * n_own + 12.0 * n_l0 + 12.0 * n_l1;
-  // adjoint FEM, free nodes: forward window E^k, V^k read, FP64 gradients updated
-  const double grad = 24.0 * n_free + 32.0 * n_free;
+  // adjoint FEM, free nodes: forward window E^k, V^k, V^{k-1} read, FP64 gradients updated
+  const double grad = 36.0 * n_free + 32.0 * n_free;
   double b = 0.0;
   switch (kind) {
     case DD_PROF_FD_FWD: b = fd; break;

@@ -155,10 +155,7 @@ struct FemArgs {
   int r2;              // div-div form R2 (element mean of eps - 1 outside the divergence)
   float h;             // grid spacing (the R2 term is evaluated element by element)
   // adjoint
-  // forward E^k, V^k [3][n_own].  The sigma gradient is summed by parts,
-  // sum_n lambda^n . (V^{n+1} + V^n) = sum_n (lambda^n + lambda^{n+1}) . V^{n+1} + lambda^0 . V^0,
-  // so an adjoint step needs V^k only (the lambda^0 row is added with initial data)
-  const float* wE; const float* wV;
+  const float* wE; const float* wV; const float* wVm;  // forward E^k, V^k, V^{k-1} [3][n_own]
   double* g_eps; double* g_sig;
   double inv_dt2, inv_2dt;
 };

@@ -5,9 +5,7 @@
 // surface values of E^0.  Both levels are independent of eps and sigma, so the exact
 // gradient differs from the start from rest only by level-0 rows: the adjoint steps
 // accumulate the mass term summed by parts, sum_n (lambda^n - lambda^{n+1}) . V^{n+1}, whose
-// boundary row -lambda^0 . V^0 (the discrete -lambda(x, 0) f_1 of eq. gradeps) is added here,
-// and the sigma term summed by parts, sum_n (lambda^n + lambda^{n+1}) . V^{n+1}, whose
-// boundary row is +lambda^0 . V^0.
+// boundary row -lambda^0 . V^0 (the discrete -lambda(x, 0) f_1 of eq. gradeps) is added here.
 #include <algorithm>
 
 #include "initial.hpp"
@@ -67,8 +65,7 @@ __global__ void init_own_kernel(const float* __restrict__ f0, const float* __res
 
 __global__ void init_mass_row_kernel(const float* __restrict__ lam0, const float* __restrict__ V0,
                                      const int* __restrict__ own_grid, const double* __restrict__ mass_d,
-                                     int64_t n_own, double inv_dt2, double inv_2dt, double* __restrict__ g_eps,
-                                     double* __restrict__ g_sig) {
+                                     int64_t n_own, double inv_dt2, double* __restrict__ g_eps) {
   for (int64_t id = (int64_t)blockIdx.x * blockDim.x + threadIdx.x; id < n_own;
        id += (int64_t)gridDim.x * blockDim.x) {
     if (own_grid[id] >= 0) continue;   // layer-1 nodes carry no gradient
@@ -76,7 +73,6 @@ __global__ void init_mass_row_kernel(const float* __restrict__ lam0, const float
 #pragma unroll
     for (int c = 0; c < 3; ++c) s += (double)lam0[c * n_own + id] * (double)V0[c * n_own + id];
     g_eps[id] -= mass_d[id] * inv_dt2 * s;
-    g_sig[id] += mass_d[id] * inv_2dt * s;
   }
 }
 
@@ -98,11 +94,10 @@ void launch_init_own(const float* f0, const float* f1, double dt, const int* own
 }
 
 void launch_init_mass_row(const float* lam0, const float* V0, const int* own_grid, const double* mass_d,
-                          int64_t n_own, double inv_dt2, double inv_2dt, double* g_eps, double* g_sig,
-                          hipStream_t s) {
+                          int64_t n_own, double inv_dt2, double* g_eps, hipStream_t s) {
   if (n_own <= 0) return;
   hipLaunchKernelGGL(init_mass_row_kernel, dim3(blocks_of(n_own)), dim3(256), 0, s, lam0, V0, own_grid, mass_d, n_own,
-                     inv_dt2, inv_2dt, g_eps, g_sig);
+                     inv_dt2, g_eps);
 }
 
 }  // namespace dd

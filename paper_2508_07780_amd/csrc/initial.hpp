@@ -16,11 +16,9 @@ void launch_init_grid(const float* f0, const float* f1, double dt, int nx, int n
 // [3][n_own]); the same pair into each non-null ck ([2][3][n_own]: E, then V).
 void launch_init_own(const float* f0, const float* f1, double dt, const int* own_api, int64_t n_own, int nx, int ny,
                      const int blo[3], const int fs[3], float* E0, float* V0, float* ck_a, float* ck_b, hipStream_t s);
-// The boundary rows of the summed-by-parts mass and sigma terms on free owned nodes
-// (own_grid < 0): g_eps[id] -= m_id lambda^0 . V^0 / dt^2, g_sig[id] += m_id lambda^0 . V^0 /
-// (2 dt); lam0, V0 [3][n_own].
+// The boundary row of the summed-by-parts mass term: g_eps[id] -= m_id lambda^0 . V^0 / dt^2
+// on free owned nodes (own_grid < 0); lam0, V0 [3][n_own].
 void launch_init_mass_row(const float* lam0, const float* V0, const int* own_grid, const double* mass_d,
-                          int64_t n_own, double inv_dt2, double inv_2dt, double* g_eps, double* g_sig,
-                          hipStream_t s);
+                          int64_t n_own, double inv_dt2, double* g_eps, hipStream_t s);
 
 }  // namespace dd

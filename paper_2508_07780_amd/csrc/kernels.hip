@@ -383,7 +383,7 @@ __global__ __launch_bounds__(FEM_THREADS) void fem_step_kernel(FemArgs a) {
   }
   // per-node data of the update, prefetched into registers while the elements run
   float pI[NPT][3], pc1[NPT], pc2[NPT], pem[NPT];
-  float pwE[NPT][3], pwV[NPT][3];
+  float pwE[NPT][3], pwV[NPT][3], pwVm[NPT][3];
 #pragma unroll
   for (int j = 0; j < NPT; ++j) {
     const int l = tid + j * FEM_THREADS;
@@ -399,6 +399,7 @@ __global__ __launch_bounds__(FEM_THREADS) void fem_step_kernel(FemArgs a) {
         for (int c = 0; c < 3; ++c) {
           pwE[j][c] = __builtin_nontemporal_load(a.wE + c * n_own + id);
           pwV[j][c] = __builtin_nontemporal_load(a.wV + c * n_own + id);
+          pwVm[j][c] = __builtin_nontemporal_load(a.wVm + c * n_own + id);
         }
       }
     }
@@ -541,7 +542,7 @@ __global__ __launch_bounds__(FEM_THREADS) void fem_step_kernel(FemArgs a) {
         const double wv = (double)pwV[j][c];
         ge += (double)q[c] * (double)pwE[j][c];
         gm += (double)inc[c] * wv;
-        gs += ((double)xn[c] + (double)xo[c]) * wv;   // (lambda^{k-1} + lambda^k) . V^k
+        gs += (double)xn[c] * (wv + (double)pwVm[j][c]);
       }
       a.g_eps[id] += ge + m * a.inv_dt2 * gm;
       a.g_sig[id] += m * a.inv_2dt * gs;
@@ -769,7 +770,7 @@ __device__ __forceinline__ void fem_stencil_part(const FemArgs& a, const int p) 
         // R2: the div-div part of the eps gradient is added by the paper-formula kernel
         if (!R2) ge += (double)q[c] * (double)__builtin_nontemporal_load(a.wE + c * n_own + id);
         gm += (double)inc[c] * wv;
-        gs += ((double)xn[c] + (double)xo[c]) * wv;   // (lambda^{k-1} + lambda^k) . V^k
+        gs += (double)xn[c] * (wv + (double)__builtin_nontemporal_load(a.wVm + c * n_own + id));
       }
       // one contribution per node and launch: the device-side FP64 add (no value returned,
       // so nothing waits for it) rounds once, exactly like a load-add-store
