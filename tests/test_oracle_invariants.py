@@ -165,7 +165,7 @@ def test_mass_term_summation_by_parts():
     scale = np.abs(ag["g_mass"]).max()
     assert scale > 0
     assert np.abs(ag["g_mass"] - ag["g_mass_sbp"]).max() <= 1e-12 * scale
-    # the sigma term likewise (the form the GPU accumulates: lambda^{k-1} + lambda^k against V^k)
+    # the sigma term likewise: sum_n (lambda^n + lambda^{n+1}) . V^{n+1} (no boundary row from rest)
     ss = np.abs(ag["g_sigma"]).max()
     assert ss > 0 and np.abs(ag["g_sigma"] - ag["g_sigma_sbp"]).max() <= 1e-12 * ss
 
