@@ -173,3 +173,18 @@ def test_serving_runs_large_jobs_alone():
                 assert torch.equal(a, b), (r["rid"], f)
             else:
                 assert float(torch.linalg.norm(a - b)) <= 1e-4 * float(torch.linalg.norm(b)), (r["rid"], f)
+
+
+def test_batch_and_serving_refusals():
+    """A negative fill target is rejected; a request larger than the whole HBM budget raises
+    instead of waiting for room that never comes."""
+    from paper_2508_07780_amd import DDError, serving
+    from paper_2508_07780_amd.batch import Batch
+    with pytest.raises(DDError) as e:
+        Batch(2, fill_cells=-1)
+    assert e.value.code == -1
+    reqs = synth.serving_requests(2, 20.0, outer=(40, 48), fem=(16, 24), sources=(1, 2), steps=(40, 60),
+                                  iterations=(2, 2))
+    small = min(serving.job_footprint(r) for r in reqs) // 2
+    with pytest.raises(ValueError):
+        serving.serve_batched(reqs, max_slots=2, hbm_budget=small, chunk=16)
