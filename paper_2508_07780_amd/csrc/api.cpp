@@ -1373,6 +1373,9 @@ struct dd_batch {
   // launches (the fixed cost per launch is spread), large ones from keeping their fields in
   // the last-level cache.
   int64_t fill_cells = 6000000;
+  // FD tile variant of the launches: -1 by the launch's combined FD fields against the
+  // last-level cache, 0 / 1 forced cached / streaming (DD_FD_NT at dd_batch_create)
+  int nt_mode = -1;
   std::string err;
 };
 
@@ -1385,6 +1388,7 @@ int dd_batch_create(int32_t max_slots, dd_batch** out) {
   if (!b) return DD_ERR_OOM;
   b->max_slots = max_slots;
   b->width = 2 * max_slots;
+  if (const char* e = std::getenv("DD_FD_NT")) b->nt_mode = std::atoi(e) != 0 ? 1 : 0;
   const size_t bytes = sizeof(BatchItem) * (size_t)b->ring * b->width;
   if (hipHostMalloc((void**)&b->host, bytes, hipHostMallocDefault) != hipSuccess) {
     delete b;
@@ -1513,7 +1517,7 @@ int dd_batch_step(dd_batch* b, int32_t max_steps, void* stream) {
       }
       // the launch's variant (and with it the z-chunk) follows the FD fields it streams;
       // each item's tile grid is laid out for that chunk
-      const bool use_nt = fd_bytes > LLC_BYTES;
+      const bool use_nt = b->nt_mode < 0 ? fd_bytes > LLC_BYTES : b->nt_mode != 0;
       for (int i = 0; i < n; ++i) {
         BatchItem& it = h[i];
         const dd_problem* q = owner[i];

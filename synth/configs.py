@@ -406,3 +406,23 @@ def serving_requests(n_requests, rate, seed=SEED_BASE + 5, outer=(64, 96, 128, 1
                      eps_true=eps, sigma_true=sig, noise_level=0.03)
         out.append(Request(r, t, w, int(rng.integers(iterations[0], iterations[1] + 1))))
     return out
+
+
+def stream224(n_steps=420) -> Workload:
+    """Streaming-regime parity case: the layered-skin generator on a 224^3 outer grid with a
+    96^3-hex FEM box, whose two levels of E (270 MB) exceed the 256 MB last-level cache, so the
+    finite-difference tiles take their streaming variant by default.  One point dipole of seeded
+    moment 4 nodes above the FEM box with a short pulse (period 16 h), so that within a few
+    hundred steps the wave reaches both the FEM box and the top-face detectors; K = 64."""
+    seed = SEED_BASE + 7
+    rng = np.random.Generator(np.random.PCG64(seed))
+    desc = _centered_desc(224, 96, n_steps, ckpt_every=64)
+    h = desc.h
+    base = gauss_sine(2.0 * math.pi / (16.0 * h))
+    desc.t_switch = base.support_end()
+    v = rng.normal(size=3)
+    v = tuple(v / np.linalg.norm(v))
+    src = Source(kind=SRC_DIPOLE, omega=base.omega, t0=base.t0, width=base.width, pol=v,
+                 pos=(112, 100, desc.fem_lo[2] + 96 + 4))
+    eps, sig, info = skin_media(desc, rng)
+    return Workload("stream224", desc, eps, sig, [src], seed, eps_true=eps, sigma_true=sig, extra=info)

@@ -66,11 +66,15 @@ def _rel(a, b):
     return float((a - b).double().norm() / b.double().norm())
 
 
+@pytest.mark.parametrize("fd_nt", ["0", "1"])
 @pytest.mark.parametrize("fill", [None, 0, 1])
-def test_batch_equals_alone_including_late_join(fill):
+def test_batch_equals_alone_including_late_join(fill, fd_nt, monkeypatch):
     """fill: the library's default fill target (these small jobs all share each launch), 0
-    (every job in every launch), 1 (one job per launch, oldest first: the late job waits)."""
+    (every job in every launch), 1 (one job per launch, oldest first: the late job waits).
+    fd_nt: the finite-difference tiles' cached (0) or streaming (1) variant, for the batch's
+    launches (the batched kernel's streaming instantiation) and the problems alone."""
     import torch
+    monkeypatch.setenv("DD_FD_NT", fd_nt)
     from paper_2508_07780_amd import Problem
     from paper_2508_07780_amd.batch import Batch
     mix = _mix()
@@ -88,7 +92,7 @@ def test_batch_equals_alone_including_late_join(fill):
     recs = {r["id"]: r for r in batch.run_to_completion(chunk=16)}
     torch.cuda.synchronize()
     for i, w in enumerate(mix):
-        print(f"[gpu] batch (fill {fill}) vs alone {w.name}", flush=True)
+        print(f"[gpu] batch (fill {fill}, fd_nt {fd_nt}) vs alone {w.name}", flush=True)
         r = recs[ids[i]]
         tr, ge, gs = _alone(torch, w, obs[i])
         same = torch.equal(r["traces"], tr) and torch.equal(r["g_eps"], ge) and torch.equal(r["g_sigma"], gs)

@@ -96,3 +96,35 @@ def test_c2_paper_gradient_matches_oracle(c2_run):
     n = abs(np.linalg.norm(out["g_eps_paper"]) / float(ref["g_eps_paper_norm"]) - 1.0)
     print(f"[gpu] c2 paper-formula gradient: sampled rel L2 {e:.3e}, norm ratio - 1 {n:.2e}", flush=True)
     assert e <= 1e-3 and n <= 1e-3
+
+
+def test_c2_streaming_variant_is_bitwise_identical(c2_run, monkeypatch):
+    """The full-size workload with its finite-difference tiles forced onto the streaming variant
+    (8-plane z-chunks, non-temporal own-node accesses; its fields fit the last-level cache, so it
+    runs the cached variant by default): traces and gradients equal the default run bit for bit,
+    since no node's arithmetic depends on the chunking."""
+    import importlib.util
+    import torch
+    from paper_2508_07780_amd import Problem
+    ref, out = c2_run
+    spec = importlib.util.spec_from_file_location("make_c2_golden", os.path.join(HERE, "golden", "make_c2_golden.py"))
+    mk = importlib.util.module_from_spec(spec)
+    spec.loader.exec_module(mk)
+    monkeypatch.setenv("DD_FD_NT", "1")
+    w = synth.c2(n_steps=int(ref["n_steps"]))
+    w.desc.ckpt_every = w.desc.n_steps
+    print("[gpu] c2 with the streaming tile variant", flush=True)
+    p = Problem(w.desc)
+    p.set_coefficients(torch.tensor(w.eps_true, dtype=torch.float32, device="cuda"),
+                       torch.tensor(w.sigma_true, dtype=torch.float32, device="cuda"))
+    tr = p.forward(w.sources, save=True).clone()
+    cot = mk.cotangent(tuple(tr.shape[1:]), w.seed)
+    p.adjoint(torch.tensor(cot[None], device="cuda"))
+    ge, gs = (g.cpu().numpy() for g in p.gradient())
+    torch.cuda.synchronize()
+    same_tr = np.array_equal(tr[0].cpu().numpy(), out["traces"])
+    print(f"[gpu] c2 streaming variant: traces equal {same_tr}, g_eps equal {np.array_equal(ge, out['g_eps'])}, "
+          f"g_sigma equal {np.array_equal(gs, out['g_sigma'])}", flush=True)
+    p.close()
+    assert same_tr
+    assert np.array_equal(ge, out["g_eps"]) and np.array_equal(gs, out["g_sigma"])

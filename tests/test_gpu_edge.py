@@ -65,14 +65,18 @@ def _rel(a, b):
     return float(np.linalg.norm(np.asarray(a, dtype=np.float64) - b) / nb) if nb > 0 else float(np.linalg.norm(a))
 
 
+@pytest.mark.parametrize("fd_nt", ["0", "1"])
 @pytest.mark.parametrize("name", sorted(CASES))
-def test_edge_case_matches_oracle(name):
+def test_edge_case_matches_oracle(name, fd_nt, monkeypatch):
+    """fd_nt: the finite-difference tiles' cached (0) or streaming (1) variant."""
     import torch
     from paper_2508_07780_amd import Problem
+    monkeypatch.setenv("DD_FD_NT", fd_nt)
     n_outer, lo, cells, nt, det, ck, kind = CASES[name]
     desc, eps, sig = _case(n_outer, lo, cells, nt, det, ck, seed=sorted(CASES).index(name))
     srcs = _sources(desc, kind)
-    print(f"[gpu] edge case {name}: outer {n_outer} fem {lo}+{cells} steps {nt} K {ck} source {kind}", flush=True)
+    print(f"[gpu] edge case {name}: outer {n_outer} fem {lo}+{cells} steps {nt} K {ck} source {kind} "
+          f"fd_nt {fd_nt}", flush=True)
     e32 = eps.astype(np.float32).astype(np.float64)
     s32 = sig.astype(np.float32).astype(np.float64)
     d = Discretization(desc).set_coefficients(e32, s32)

@@ -66,11 +66,21 @@ def _workload(name):
     return synth.c1() if name == "c1" else synth.small(name)
 
 
+# DD_FD_NT: the finite-difference tiles' cached variant (2-plane z-chunks, ordinary accesses) and
+# their streaming variant (8-plane z-chunks, non-temporal own-node accesses, the adjoint's top-face
+# cotangent loaded ahead when the top face closes a full chunk), which grids whose two E levels
+# exceed the last-level cache take by default
+FD_VARIANTS = ["0", "1"]
+
+
+@pytest.mark.parametrize("fd_nt", FD_VARIANTS)
 @pytest.mark.parametrize("name", CASES)
-def test_forward_traces_and_energy(torch_cuda, name):
+def test_forward_traces_and_energy(torch_cuda, name, fd_nt, monkeypatch):
     torch = torch_cuda
+    monkeypatch.setenv("DD_FD_NT", fd_nt)
     w = _workload(name)
-    print(f"[gpu] forward parity {name} {w.desc.n_outer} fem {w.desc.fem_cells} steps {w.desc.n_steps}", flush=True)
+    print(f"[gpu] forward parity {name} {w.desc.n_outer} fem {w.desc.fem_cells} steps {w.desc.n_steps} "
+          f"fd_nt {fd_nt}", flush=True)
     p = _gpu_problem(torch, w)
     tr, en = p.forward(w.sources, save=False, energy=True)
     torch.cuda.synchronize()
@@ -78,16 +88,18 @@ def test_forward_traces_and_energy(torch_cuda, name):
     ref = forward(d, w.sources[0])
     err = _rel(tr[0].cpu().numpy(), ref["traces"])
     eerr = _rel(en[0].cpu().numpy(), ref["energy"])
-    _report(check="forward", case=name, trace_rel_l2=f"{err:.3e}", energy_rel_l2=f"{eerr:.3e}")
+    _report(check="forward", case=name, fd_nt=fd_nt, trace_rel_l2=f"{err:.3e}", energy_rel_l2=f"{eerr:.3e}")
     assert err <= TRACE_TOL, err
     assert eerr <= 1e-4, eerr
 
 
+@pytest.mark.parametrize("fd_nt", FD_VARIANTS)
 @pytest.mark.parametrize("name", CASES)
-def test_gradient(torch_cuda, name):
+def test_gradient(torch_cuda, name, fd_nt, monkeypatch):
     torch = torch_cuda
+    monkeypatch.setenv("DD_FD_NT", fd_nt)
     w = _workload(name)
-    print(f"[gpu] gradient parity {name}", flush=True)
+    print(f"[gpu] gradient parity {name} fd_nt {fd_nt}", flush=True)
     d = _oracle(w)
     fw = forward(d, w.sources[0])
     rng = np.random.default_rng(7)
@@ -101,10 +113,38 @@ def test_gradient(torch_cuda, name):
     ge, gs = ge.cpu().numpy(), gs.cpu().numpy()
     e1 = _rel(ge, ag["g_eps"])
     e2 = _rel(gs, ag["g_sigma"]) if np.any(ag["g_sigma"]) else 0.0
-    _report(check="gradient", case=name, g_eps_rel_l2=f"{e1:.3e}", g_sigma_rel_l2=f"{e2:.3e}")
+    _report(check="gradient", case=name, fd_nt=fd_nt, g_eps_rel_l2=f"{e1:.3e}", g_sigma_rel_l2=f"{e2:.3e}")
     assert e1 <= GRAD_TOL and e2 <= GRAD_TOL, (e1, e2)
     free = d.fem_free
     assert np.all(ge[~free] == 0) and np.all(gs[~free] == 0)
+
+
+@pytest.mark.parametrize("name", CASES)
+def test_streaming_variant_is_bitwise_identical(torch_cuda, name, monkeypatch):
+    """The two finite-difference tile variants differ in z-chunk length and access kind only, not
+    in any node's arithmetic: a saving forward and the misfit adjoint (cotangent traces - obs
+    formed in the tiles, through the top-face prefetch where the top face closes a full chunk)
+    give the same traces and gradients bit for bit; the energy sums (per-tile partials) agree to
+    rounding."""
+    torch = torch_cuda
+    w = _workload(name)
+    out = {}
+    for fd_nt in FD_VARIANTS:
+        monkeypatch.setenv("DD_FD_NT", fd_nt)
+        print(f"[gpu] tile variant {fd_nt} on {name}", flush=True)
+        p = _gpu_problem(torch, w)
+        tr, en = p.forward(w.sources, save=True, energy=True)
+        tr = tr.clone()
+        obs = (0.7 * tr + 1e-3).contiguous()
+        p.adjoint_misfit(tr, obs)
+        ge, gs = p.gradient()
+        torch.cuda.synchronize()
+        out[fd_nt] = (tr.cpu(), en.cpu(), ge.cpu(), gs.cpu())
+        p.close()
+    a, b = out["0"], out["1"]
+    assert torch.equal(a[0], b[0]), "traces differ between the tile variants"
+    assert torch.equal(a[2], b[2]) and torch.equal(a[3], b[3]), "gradients differ between the tile variants"
+    assert float((a[1] - b[1]).norm() / a[1].norm()) <= 1e-12
 
 
 def test_checkpoint_interval_does_not_change_gradient_bits(torch_cuda):
