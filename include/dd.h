@@ -189,6 +189,14 @@ int dd_adjoint_misfit(dd_problem* p, const float* traces_dev, const float* obs_d
 int dd_misfit(dd_problem* p, const float* traces_dev, const float* obs_dev, int32_t n_src, const double* z_host,
               float* cot_dev, double* j_dev, void* stream);
 
+/* Host-only: a smoothing function z of eq. tikhonov_functional as time weights for dd_misfit
+ * (the paper names it without a formula): z_out[n] (trace row n, time level n + 1,
+ * t = (n + 1) dt) is 1 up to T - delta and (1 + cos(pi s)) / 2 with s = (t - (T - delta)) / delta
+ * over the last delta, so the misfit fades out smoothly to 0 at the end time T = n_steps dt;
+ * delta <= 0 gives z = 1.  z_out: n_steps doubles (caller-owned host memory).
+ * DD_ERR_INVALID_ARG for n_steps < 1, a null z_out, dt <= 0 or non-finite dt, delta. */
+int dd_misfit_taper(int32_t n_steps, double dt, double delta, double* z_out);
+
 /* Div-div form of the FEM rows.  DD_DIVDIV_R1 (default): the nodal product (eps - 1) E inside
  * the element divergence, as eq. forward_prob writes it.  DD_DIVDIV_R2: the element mean of
  * eps - 1 outside it, sum_K |K| (mean_K eps - 1) grad phi_i div_K(E) (symmetric); for this form

@@ -46,6 +46,7 @@ class Batch:
                 ge = torch.empty(problem.n_fem, dtype=torch.float64, device=dev)
                 gs = torch.empty(problem.n_fem, dtype=torch.float64, device=dev)
         job = ctypes.c_int32()
+        problem.generation += 1
         _lib.check(_lib.load().dd_batch_submit(
             self._h, problem._h, _lib.make_sources(sources), n, _ptr(traces),
             _ptr(obs) if obs is not None else None, _ptr(ge) if ge is not None else None,

@@ -9,7 +9,6 @@ Everything stays on the device; the host reads the run's scalars once per iterat
 """
 
 import ctypes
-import math
 from dataclasses import dataclass, fields
 
 import numpy as np
@@ -20,17 +19,10 @@ from .solver import _ptr, _stream
 
 
 def taper_weights(n_steps, dt, delta):
-    """A smoothing function z of eq. tikhonov_functional for the trace rows (row n is time level
-    n + 1): 1 until delta before the end time T = n_steps dt, then (1 + cos(pi s)) / 2 with s
-    running from 0 to 1 over that last stretch (z = 0 at T), so that the misfit fades out
-    smoothly instead of being cut at T.  delta <= 0: z = 1."""
-    z = np.ones(n_steps)
-    if delta > 0:
-        t_end = n_steps * dt
-        for n in range(n_steps):
-            s = ((n + 1) * dt - (t_end - delta)) / delta
-            if s > 0:
-                z[n] = 0.5 * (1.0 + math.cos(math.pi * min(s, 1.0)))
+    """The library's smoothing function z of eq. tikhonov_functional at the trace rows
+    (dd_misfit_taper: 1 until delta before the end time, then a cosine ramp to 0)."""
+    z = np.empty(int(n_steps), dtype=np.float64)
+    _lib.check(_lib.load().dd_misfit_taper(int(n_steps), float(dt), float(delta), z.ctypes.data_as(ctypes.c_void_p)))
     return z
 
 

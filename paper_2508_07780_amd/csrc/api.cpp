@@ -899,6 +899,20 @@ int dd_misfit(dd_problem* p, const float* traces_dev, const float* obs_dev, int3
   return check_launch(p);
 }
 
+int dd_misfit_taper(int32_t n_steps, double dt, double delta, double* z_host) {
+  if (n_steps < 1 || !z_host || !(dt > 0.0) || !std::isfinite(dt) || !std::isfinite(delta)) return DD_ERR_INVALID_ARG;
+  const double t_end = (double)n_steps * dt;
+  for (int32_t n = 0; n < n_steps; ++n) {
+    z_host[n] = 1.0;
+    if (delta > 0.0) {
+      // s runs from 0 at t = T - delta to 1 at the end time T (trace row n is time level n + 1)
+      const double s = ((double)(n + 1) * dt - (t_end - delta)) / delta;
+      if (s > 0.0) z_host[n] = 0.5 * (1.0 + std::cos(M_PI * std::min(s, 1.0)));
+    }
+  }
+  return DD_OK;
+}
+
 namespace {
 int pg_setup(dd_problem* p) {
   if (p->overlap) return fail(p, DD_ERR_UNSUPPORTED, "the paper-formula gradient needs the single-stream step order");

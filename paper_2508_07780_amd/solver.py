@@ -44,6 +44,9 @@ class Problem:
         self.n_fem, self.n_det, self.n_grid = nf.value, nd.value, ng.value
         self.n_steps = int(desc.n_steps)
         self._n_src = 0
+        # bumped by every call that replaces the saved forward state (coefficients, forward,
+        # div-div form, initial data, a batched job): an autograd node checks it in backward
+        self.generation = 0
 
     def close(self):
         if getattr(self, "_h", None):
@@ -76,6 +79,7 @@ class Problem:
     def set_coefficients(self, eps, sigma):
         e = _device_f32(eps, self.n_fem, "eps")
         s = _device_f32(sigma, self.n_fem, "sigma")
+        self.generation += 1
         _lib.check(_lib.load().dd_set_coefficients(self._h, _ptr(e), _ptr(s), _stream()), self._h)
 
     def forward(self, sources, save=True, energy=False, out=None):
@@ -87,6 +91,7 @@ class Problem:
         if tuple(traces.shape) != shape or traces.dtype != torch.float32 or not traces.is_contiguous():
             raise ValueError("trace buffer must be a contiguous float32 tensor of shape %s" % (shape,))
         en = torch.empty((n, self.n_steps), dtype=torch.float64, device=dev) if energy else None
+        self.generation += 1
         _lib.check(_lib.load().dd_forward(self._h, srcs, n, _ptr(traces), 1 if save else 0,
                                           _ptr(en) if en is not None else None, _stream()), self._h)
         self._n_src = n
@@ -153,6 +158,7 @@ class Problem:
         """"R1" (the scheme of eq. forward_prob) or "R2" (element mean of eps - 1 outside the
         divergence; the paper's gradient formula is then exact)."""
         code = {"R1": 1, "R2": 2}[form]
+        self.generation += 1
         _lib.check(_lib.load().dd_set_divdiv_form(self._h, code), self._h)
 
     def check_finite(self):
@@ -164,6 +170,7 @@ class Problem:
         CUDA tensors of n_grid x 3 values (node-major, node index x + Nx (y + Ny z)).  Both None:
         start from rest again."""
         lib = _lib.load()
+        self.generation += 1
         if f0 is None and f1 is None:
             _lib.check(lib.dd_set_initial_data(self._h, None, None, _stream()), self._h)
             return

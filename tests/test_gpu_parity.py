@@ -272,6 +272,36 @@ def test_autograd_function_matches_c_abi(torch_cuda):
     assert _rel(sig.grad.cpu().numpy(), ag["g_sigma"]) <= GRAD_TOL
 
 
+def test_autograd_refuses_a_stale_saved_forward(torch_cuda):
+    """Two solves on one Problem before backward: the first node's saved forward was replaced,
+    so its backward raises instead of returning the other solve's gradient.  One Problem per
+    solve works, and eps given on the FEM lattice's 3-D shape gets a gradient of that shape."""
+    torch = torch_cuda
+    from paper_2508_07780_amd import Problem
+    from paper_2508_07780_amd.autograd import solve
+    w = synth.small("tiny")
+    shape = tuple(int(c) + 1 for c in w.desc.fem_cells)[::-1]
+    eps = torch.tensor(w.eps.reshape(shape), dtype=torch.float32, device="cuda", requires_grad=True)
+    sig = torch.tensor(w.sigma, dtype=torch.float32, device="cuda", requires_grad=True)
+    p = Problem(w.desc)
+    a = solve(p, eps, sig, w.sources)
+    b = solve(p, eps.detach() * 1.0, sig.detach(), w.sources)
+    with pytest.raises(RuntimeError):
+        (a.sum() + b.sum()).backward()
+    q = Problem(w.desc)
+    a = solve(q, eps, sig, w.sources)
+    b = solve(p, eps, sig, w.sources)
+    (0.5 * (a ** 2).sum() + 0.5 * (b ** 2).sum()).backward()
+    assert eps.grad.shape == eps.shape and sig.grad.shape == sig.shape
+    # both solves are the same, so the summed gradient is twice one of them
+    ref = Problem(w.desc)
+    eps1 = eps.detach().clone().requires_grad_(True)
+    sig1 = sig.detach().clone().requires_grad_(True)
+    (0.5 * (solve(ref, eps1, sig1, w.sources) ** 2).sum()).backward()
+    assert torch.allclose(eps.grad, 2 * eps1.grad, rtol=1e-6, atol=0)
+    assert torch.allclose(sig.grad, 2 * sig1.grad, rtol=1e-6, atol=0)
+
+
 @pytest.mark.parametrize("name", ["ragged", "skinlet"])
 def test_element_colored_fem_path(torch_cuda, name, monkeypatch):
     """The element-colored FEM kernel (general tetrahedral meshes) against the oracle."""
