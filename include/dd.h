@@ -197,6 +197,19 @@ int dd_misfit(dd_problem* p, const float* traces_dev, const float* obs_dev, int3
  * DD_ERR_INVALID_ARG for n_steps < 1, a null z_out, dt <= 0 or non-finite dt, delta. */
 int dd_misfit_taper(int32_t n_steps, double dt, double delta, double* z_out);
 
+/* dd_misfit without any device allocation, for callers that cannot allocate (code under HIP
+ * graph capture, tight serving loops, harnesses that forbid hipMalloc).  Same arguments,
+ * results and error behaviour as dd_misfit (the same kernels: results are bit-identical).
+ * Its scratch (the FP64 block partials of J and the time weights) is a static device array of
+ * 8 * (1024 + DD_MISFIT_NOALLOC_MAX_STEPS) bytes (about 520 KB), one copy per GPU, held until
+ * the process ends; n_steps above DD_MISFIT_NOALLOC_MAX_STEPS gives DD_ERR_INVALID_ARG.  All
+ * calls on one GPU share that array: calls that overlap on one GPU (different streams, or host
+ * threads) race.  With z_host the weights are uploaded on every call, which synchronises
+ * `stream`; with z_host = NULL the call only queues kernels. */
+enum { DD_MISFIT_NOALLOC_MAX_STEPS = 65536 };
+int dd_misfit_noalloc(dd_problem* p, const float* traces_dev, const float* obs_dev, int32_t n_src, const double* z_host,
+                      float* cot_dev, double* j_dev, void* stream);
+
 /* Div-div form of the FEM rows.  DD_DIVDIV_R1 (default): the nodal product (eps - 1) E inside
  * the element divergence, as eq. forward_prob writes it.  DD_DIVDIV_R2: the element mean of
  * eps - 1 outside it, sum_K |K| (mean_K eps - 1) grad phi_i div_K(E) (symmetric); for this form

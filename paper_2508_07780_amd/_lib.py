@@ -19,7 +19,7 @@ EXPORTS = [
     "dd_batch_create", "dd_batch_destroy", "dd_batch_submit", "dd_batch_step", "dd_batch_poll",
     "dd_adjoint_misfit", "dd_cga_create", "dd_cga_destroy", "dd_cga_update", "dd_cga_get_info",
     "dd_paper_gradient_enable", "dd_gradient_paper", "dd_misfit", "dd_set_divdiv_form", "dd_set_initial_data", "dd_check_finite", "dd_batch_set_fill",
-    "dd_misfit_taper",
+    "dd_misfit_noalloc", "dd_misfit_taper",
 ]
 
 PROF_FD_FWD, PROF_FEM_FWD, PROF_FD_ADJ, PROF_FEM_ADJ, PROF_FEM_RECOMPUTE, PROF_STEP_FWD, PROF_STEP_ADJ = range(7)
@@ -116,6 +116,7 @@ def load():
     lib.dd_adjoint_misfit.argtypes = [P, P, P, P]
     lib.dd_paper_gradient_enable.argtypes = [P, ctypes.c_int32]
     lib.dd_misfit.argtypes = [P, P, P, ctypes.c_int32, P, P, P, P]
+    lib.dd_misfit_noalloc.argtypes = [P, P, P, ctypes.c_int32, P, P, P, P]
     lib.dd_misfit_taper.argtypes = [ctypes.c_int32, ctypes.c_double, ctypes.c_double, P]
     lib.dd_set_divdiv_form.argtypes = [P, ctypes.c_int32]
     lib.dd_gradient_paper.argtypes = [P, P, P, P]

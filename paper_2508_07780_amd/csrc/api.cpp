@@ -913,6 +913,35 @@ int dd_misfit_taper(int32_t n_steps, double dt, double delta, double* z_host) {
   return DD_OK;
 }
 
+int dd_misfit_noalloc(dd_problem* p, const float* traces_dev, const float* obs_dev, int32_t n_src, const double* z_host,
+                      float* cot_dev, double* j_dev, void* stream) {
+  if (!p) return DD_ERR_INVALID_ARG;
+  if (!traces_dev || !obs_dev || n_src < 1) return fail(p, DD_ERR_INVALID_ARG, "need traces, observations, n_src >= 1");
+  const int64_t nt = p->d.n_steps;
+  if (nt > DD_MISFIT_NOALLOC_MAX_STEPS)
+    return fail(p, DD_ERR_INVALID_ARG, "n_steps " + std::to_string(nt) + " exceeds the no-allocation misfit's maximum of " +
+                                           std::to_string((int)DD_MISFIT_NOALLOC_MAX_STEPS) + " steps");
+  if (z_host)
+    for (int64_t n = 0; n < nt; ++n)
+      if (!std::isfinite(z_host[n]) || z_host[n] < 0.0) return fail(p, DD_ERR_INVALID_ARG, "weights must be finite, >= 0");
+  hipStream_t st = (hipStream_t)stream;
+  double* scr = nullptr;   // [CGA_MAX_BLOCKS] block partials, then [n_steps] weights
+  if (hipError_t e = misfit_scratch(&scr); e != hipSuccess)
+    return fail(p, DD_ERR_HIP, std::string("scratch symbol lookup failed: ") + hipGetErrorString(e));
+  double* zd = scr + CGA_MAX_BLOCKS;
+  if (z_host) {
+    // every call uploads its weights (the array is shared by all calls on this GPU); the copy
+    // follows the work already queued on the stream, and completes before the call returns
+    if (hipMemcpyAsync(zd, z_host, (size_t)nt * sizeof(double), hipMemcpyHostToDevice, st) != hipSuccess ||
+        hipStreamSynchronize(st) != hipSuccess)
+      return fail(p, DD_ERR_HIP, "weight upload failed");
+  }
+  // every block writes its partial before the one-block sum reads it: nothing to clear
+  const int64_t row = p->n_det * 3;
+  launch_misfit(traces_dev, obs_dev, (int64_t)n_src * nt * row, row, nt, z_host ? zd : nullptr, cot_dev, scr, j_dev, st);
+  return check_launch(p);
+}
+
 namespace {
 int pg_setup(dd_problem* p) {
   if (p->overlap) return fail(p, DD_ERR_UNSUPPORTED, "the paper-formula gradient needs the single-stream step order");

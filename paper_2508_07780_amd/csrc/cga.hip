@@ -17,9 +17,17 @@
 // The work is a few streaming passes over FEM-node arrays (HBM-bound, a few microseconds
 // at the paper's sizes).  Every sum is FP64 and deterministic: each block reduces its
 // grid-stride share in a fixed order, one block then adds the block partials in order.
+#include <mutex>
+
 #include "cga.hpp"
 
 namespace dd {
+
+// Scratch of the no-allocation misfit (dd_misfit_noalloc): the FP64 block partials of J,
+// then the time weights z.  One copy per GPU, held until the process ends.  In host code this
+// name is a stand-in, not a device address: kernels and copies take the address from
+// misfit_scratch.
+static __device__ __align__(256) double scratch[CGA_MAX_BLOCKS + DD_MISFIT_NOALLOC_MAX_STEPS];
 
 namespace {
 
@@ -252,6 +260,26 @@ void launch_misfit(const float* traces, const float* obs, int64_t n, int64_t row
     hipLaunchKernelGGL((misfit_kernel<false>), dim3(nb), dim3(CGA_THREADS), 0, s, traces, obs, n, row_len, n_rows, z,
                        cot, part);
   if (j) hipLaunchKernelGGL(misfit_finish_kernel, dim3(1), dim3(CGA_THREADS), 0, s, part, nb, j);
+}
+
+hipError_t misfit_scratch(double** out) {
+  constexpr int kMaxDevices = 64;
+  static std::mutex mu;
+  static double* addr[kMaxDevices] = {};
+  int dev = 0;
+  hipError_t e = hipGetDevice(&dev);
+  if (e != hipSuccess) return e;
+  if (dev < 0 || dev >= kMaxDevices) return hipErrorInvalidDevice;
+  std::lock_guard<std::mutex> lock(mu);
+  if (!addr[dev]) {
+    // with device `dev` current: that GPU's copy of the array
+    void* q = nullptr;
+    e = hipGetSymbolAddress(&q, HIP_SYMBOL(scratch));
+    if (e != hipSuccess) return e;
+    addr[dev] = static_cast<double*>(q);
+  }
+  *out = addr[dev];
+  return hipSuccess;
 }
 
 void launch_cga_upper_check(const float* eps, const float* sig, int64_t n, double eps_max, double sig_max, int* err,

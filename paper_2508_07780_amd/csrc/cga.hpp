@@ -35,4 +35,9 @@ void launch_cga_upper_check(const float* eps, const float* sig, int64_t n, doubl
 void launch_misfit(const float* traces, const float* obs, int64_t n, int64_t row_len, int64_t n_rows,
                    const double* z, float* cot, double* part, double* j, hipStream_t s);
 
+// Device address of the current GPU's copy of the static scratch array of the no-allocation
+// misfit: CGA_MAX_BLOCKS block partials, then DD_MISFIT_NOALLOC_MAX_STEPS time weights.  The
+// symbol is resolved once per device (hipGetSymbolAddress); returns hipSuccess or its error.
+hipError_t misfit_scratch(double** out);
+
 }  // namespace dd

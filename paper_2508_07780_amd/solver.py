@@ -129,10 +129,11 @@ class Problem:
         _lib.check(_lib.load().dd_gradient(self._h, _ptr(ge), _ptr(gs), _stream()), self._h)
         return ge, gs
 
-    def misfit(self, traces, obs, z=None, cotangent=True, loss=True, out=None):
+    def misfit(self, traces, obs, z=None, cotangent=True, loss=True, out=None, no_alloc=False):
         """(J, cot) of the trace misfit with time weights z (numpy, n_steps, or None for z = 1):
         cot = z_n (traces - obs) (float32, into `out` when given, or None), J a float64 device
-        scalar (or None)."""
+        scalar (or None).  no_alloc: through dd_misfit_noalloc (the library's scratch is a static
+        device array; the output buffers are still torch allocations here unless given)."""
         import numpy as np
         n = traces.shape[0]
         shape = (n, self.n_steps, self.n_det, 3)
@@ -148,7 +149,8 @@ class Problem:
         if cot is not None and (cot.shape != traces.shape or cot.dtype != torch.float32 or not cot.is_contiguous()):
             raise ValueError("cotangent buffer must match the traces")
         J = torch.empty((), dtype=torch.float64, device=traces.device) if loss else None
-        _lib.check(_lib.load().dd_misfit(self._h, _ptr(traces), _ptr(obs), n,
+        fn = _lib.load().dd_misfit_noalloc if no_alloc else _lib.load().dd_misfit
+        _lib.check(fn(self._h, _ptr(traces), _ptr(obs), n,
                                          zz.ctypes.data_as(ctypes.c_void_p) if zz is not None else None,
                                          _ptr(cot) if cot is not None else None,
                                          _ptr(J) if J is not None else None, _stream()), self._h)
