@@ -31,8 +31,10 @@
  *   - Every pointer argument named *_dev is device memory owned by the caller
  *     and must stay valid until the work queued on `stream` has finished.
  *   - The library owns its internal state (fields, checkpoints, interface
- *     history, FP64 accumulators), allocated with hipMalloc in dd_create and
- *     dd_forward and released by dd_destroy.
+ *     history, FP64 accumulators).  It allocates that device memory through the
+ *     allocator given to dd_create (e.g. a framework's caching allocator), or with
+ *     hipMalloc when none is given, in dd_create, dd_forward / dd_batch_submit (the
+ *     saved forward) and on the first use of an optional form; dd_destroy releases it.
  *   - `stream` is a hipStream_t (NULL = the default stream).  All device work is
  *     queued asynchronously on it; calls return once the work is queued, except
  *     dd_set_coefficients, which synchronises the stream to report violations.
@@ -77,19 +79,35 @@ enum {
 
 typedef struct dd_problem dd_problem;
 
+/* Checkpoint schemes of the forward saved for the adjoint (dd_problem_desc.ckpt_mode). */
+enum {
+  DD_CKPT_FEM_IFACE = 0,  /* FEM state (E, V) every ckpt_every steps plus the layer-0 interface
+                             values of every step; the adjoint recomputes the FEM region of a
+                             segment from its checkpoint (the FD region needs no recompute) */
+  DD_CKPT_STORE_ALL = 1,  /* every FEM level kept (ckpt_every is taken as n_steps) */
+  DD_CKPT_FULL = 2        /* full-state checkpoints: not built (DD_ERR_UNSUPPORTED) */
+};
+
 typedef struct {
   int32_t n_outer[3];       /* outer grid nodes per axis, each >= 4; product < 2^30 */
   double h;                 /* grid spacing > 0 */
   double origin[3];         /* coordinates of grid node (0,0,0) */
   int32_t fem_lo[3];        /* grid index of the FEM box's lower corner; >= 1 */
   int32_t fem_cells[3];     /* FEM hex cells per axis; >= 2, fem_lo + fem_cells <= n_outer - 2 */
+  int32_t overlap;          /* node layers shared by the FD and FEM regions (section "The
+                               mathematical model", domain decomposition): 2 (0 = 2); any other
+                               value DD_ERR_UNSUPPORTED */
   double dt;                /* time step > 0, fixed (never derived from eps) */
   int32_t n_steps;          /* N_t >= 1 */
   int32_t ckpt_every;       /* forward checkpoint interval K >= 1 for the adjoint */
+  double s_stab;            /* weight s of the div-div stabiliser s grad div(eps E) of the target
+                               system: 1 (0 = 1), the only value for which the FD region carries the
+                               plain wave equation of the paper; other values DD_ERR_UNSUPPORTED */
   uint32_t detector_faces;  /* face bits of the detector set (non-empty) */
   uint32_t absorbing_faces; /* face bits with first-order absorbing BC (eq. model1) */
   double t_switch;          /* top face: plane-wave source for t_n <= t_switch, absorbing
                                (if DD_FACE_TOP is in absorbing_faces) for t_n > t_switch */
+  int32_t ckpt_mode;        /* DD_CKPT_* (0 = DD_CKPT_FEM_IFACE) */
 } dd_problem_desc;
 
 typedef struct {
@@ -99,11 +117,28 @@ typedef struct {
   int32_t pos[3];           /* DD_SRC_DIPOLE: grid node; must be finite-difference owned */
 } dd_source;
 
+/* Device allocator of a problem's state: alloc returns `bytes` of device memory (NULL on
+ * failure, reported as DD_ERR_OOM), free releases a pointer alloc returned; ctx is passed
+ * through.  Calls happen on the thread that calls into the library. */
+typedef void* (*dd_alloc_fn)(size_t bytes, void* ctx);
+typedef void (*dd_free_fn)(void* ptr, void* ctx);
+
 /* Build the mesh, partitions, element colouring and device state of one problem
  * (paper: domain decomposition of section "The mathematical model"; Kuhn split of
  * the FEM box).  eps = 1, sigma = 0 until dd_set_coefficients is called.
- * out: receives the handle (owned by the caller, release with dd_destroy). */
-int dd_create(const dd_problem_desc* desc, dd_problem** out);
+ * alloc_fn, free_fn, ctx: the allocator of every device buffer the problem owns (its
+ * fields, saved forward, recompute windows, optional buffers and a dd_cga run started on
+ * it); both NULL: hipMalloc / hipFree; only one NULL: DD_ERR_INVALID_ARG.  They must stay
+ * usable until dd_destroy (and the last dd_cga_destroy of a run on the problem).
+ * out: receives the handle (owned by the caller, release with dd_destroy).
+ * Errors: DD_ERR_INVALID_ARG (descriptor), DD_ERR_UNSUPPORTED (overlap, s_stab, ckpt_mode),
+ * DD_ERR_OOM, DD_ERR_HIP. */
+int dd_create(const dd_problem_desc* desc, dd_alloc_fn alloc_fn, dd_free_fn free_fn, void* ctx, dd_problem** out);
+/* Releases the problem.  With hipMalloc memory the device is synchronised first; with a
+ * caller allocator only the library's own second stream is, and each buffer goes back
+ * through free_fn while the caller's stream may still hold queued work that reads it: the
+ * allocator must order reuse after that work (a stream-ordered caching allocator on the
+ * stream of the calls does). */
 int dd_destroy(dd_problem* p);
 
 /* Sizes: FEM lattice nodes, detectors, outer grid nodes (any pointer may be NULL). */
@@ -112,7 +147,10 @@ int dd_sizes(const dd_problem* p, int64_t* n_fem_nodes, int64_t* n_detectors, in
 /* Host-only: grid indices of the detector nodes in trace order (n_detectors entries). */
 int dd_detector_nodes(const dd_problem_desc* desc, int64_t* out, int64_t capacity, int64_t* n_written);
 
-/* Device bytes dd_create + dd_forward(save=1) with n_src sources will hold (admission control). */
+/* Upper bound of the device bytes a problem of this descriptor allocates through its
+ * allocator: dd_create, a saving dd_forward (or dd_batch_submit) with n_src sources and every
+ * optional buffer (initial data, the div-div form R2 / paper-formula gradient, the misfit's
+ * weights and partials, a dd_cga run), for admission control.  0 for an invalid descriptor. */
 size_t dd_footprint_bytes(const dd_problem_desc* desc, int32_t n_src);
 
 /* eps, sigma: FEM-node arrays (float32, n_fem_nodes each) on the device.
@@ -165,9 +203,21 @@ int dd_set_initial_data(dd_problem* p, const float* f0_dev, const float* f1_dev,
  * eq. gradeps in FP64, summed over sources.  DD_ERR_STATE without a saved forward. */
 int dd_adjoint(dd_problem* p, const float* cot_dev, void* stream);
 
+/* Tikhonov term of eq. tikhonov_functional, gamma_eps/2 |eps - eps0|^2 + gamma_sig/2 |sigma - sigma0|^2
+ * in L2 of the FEM box with the lumped-mass quadrature (|u|^2 = sum_i m_i u_i^2 over the free
+ * nodes, m_i = h^3), at the coefficients of the last dd_set_coefficients. */
+typedef struct {
+  double gamma_eps, gamma_sig;    /* >= 0, finite */
+  const float* eps0_dev;          /* Tikhonov centres: FEM-node arrays (float32, n_fem_nodes) */
+  const float* sigma0_dev;
+} dd_tikhonov;
+
 /* Gradient of the last dd_adjoint: g_eps_dev, g_sigma_dev are FEM-node arrays
- * (float64, n_fem_nodes each); zero on nodes of layer 0 and 1. */
-int dd_gradient(dd_problem* p, double* g_eps_dev, double* g_sigma_dev, void* stream);
+ * (float64, n_fem_nodes each), dJ/deps_i and dJ/dsigma_i on the free nodes, zero on nodes of
+ * layer 0 and 1.  reg (nullable): adds the derivative of the Tikhonov term,
+ * gamma m_i (c_i - c0_i), on the free nodes.  DD_ERR_STATE without a preceding adjoint,
+ * DD_ERR_INVALID_ARG for null buffers or a reg with negative / non-finite gammas or null centres. */
+int dd_gradient(dd_problem* p, double* g_eps_dev, double* g_sigma_dev, const dd_tikhonov* reg, void* stream);
 
 /* dd_adjoint for the trace misfit of eq. tikhonov_functional, J = 1/2 sum |E - E_obs|^2:
  * the cotangent traces - obs is formed inside the adjoint kernels as they read it (no
@@ -320,7 +370,11 @@ const char* dd_last_error(const dd_problem* p);
  * driven from one host thread and one stream.  Storage for the saved forward is allocated
  * in dd_batch_submit (see dd_footprint_bytes); dd_batch_step allocates nothing. */
 typedef struct dd_batch dd_batch;
-int dd_batch_create(int32_t max_slots, dd_batch** out);
+/* hbm_budget: bytes (0 = no limit) that the problems with an active job may hold together,
+ * each counted at dd_footprint_bytes(its descriptor, its job's sources); dd_batch_submit of a
+ * job that does not fit gives DD_ERR_STATE and changes nothing (like a full batch), and a
+ * job's bytes are returned when it completes. */
+int dd_batch_create(int32_t max_slots, size_t hbm_budget, dd_batch** out);
 /* Fill target of a launch in cells per step (default 6,000,000); 0 lets every active job
  * take part in every launch.  Negative: DD_ERR_INVALID_ARG. */
 int dd_batch_set_fill(dd_batch* b, int64_t cells);

@@ -27,6 +27,9 @@ PROF_NAMES = ["fd_step_fwd", "fem_step_fwd", "fd_step_adj", "fem_step_adj", "fem
               "step_fwd", "step_adj"]
 
 
+CKPT_FEM_IFACE, CKPT_STORE_ALL, CKPT_FULL = 0, 1, 2
+
+
 class ProblemDesc(ctypes.Structure):
     _fields_ = [
         ("n_outer", ctypes.c_int32 * 3),
@@ -34,13 +37,29 @@ class ProblemDesc(ctypes.Structure):
         ("origin", ctypes.c_double * 3),
         ("fem_lo", ctypes.c_int32 * 3),
         ("fem_cells", ctypes.c_int32 * 3),
+        ("overlap", ctypes.c_int32),
         ("dt", ctypes.c_double),
         ("n_steps", ctypes.c_int32),
         ("ckpt_every", ctypes.c_int32),
+        ("s_stab", ctypes.c_double),
         ("detector_faces", ctypes.c_uint32),
         ("absorbing_faces", ctypes.c_uint32),
         ("t_switch", ctypes.c_double),
+        ("ckpt_mode", ctypes.c_int32),
     ]
+
+
+class Tikhonov(ctypes.Structure):
+    _fields_ = [
+        ("gamma_eps", ctypes.c_double),
+        ("gamma_sig", ctypes.c_double),
+        ("eps0_dev", ctypes.c_void_p),
+        ("sigma0_dev", ctypes.c_void_p),
+    ]
+
+
+ALLOC_FN = ctypes.CFUNCTYPE(ctypes.c_void_p, ctypes.c_size_t, ctypes.c_void_p)
+FREE_FN = ctypes.CFUNCTYPE(None, ctypes.c_void_p, ctypes.c_void_p)
 
 
 class Source(ctypes.Structure):
@@ -85,7 +104,7 @@ def load():
         raise RuntimeError(f"{LIB_PATH} is missing: build it with paper_2508_07780_amd/build.py")
     lib = ctypes.CDLL(LIB_PATH)
     P = ctypes.c_void_p
-    lib.dd_create.argtypes = [ctypes.POINTER(ProblemDesc), ctypes.POINTER(P)]
+    lib.dd_create.argtypes = [ctypes.POINTER(ProblemDesc), ALLOC_FN, FREE_FN, P, ctypes.POINTER(P)]
     lib.dd_destroy.argtypes = [P]
     lib.dd_sizes.argtypes = [P, ctypes.POINTER(ctypes.c_int64), ctypes.POINTER(ctypes.c_int64),
                              ctypes.POINTER(ctypes.c_int64)]
@@ -96,7 +115,7 @@ def load():
     lib.dd_set_coefficients.argtypes = [P, P, P, P]
     lib.dd_forward.argtypes = [P, ctypes.POINTER(Source), ctypes.c_int32, P, ctypes.c_int32, P, P]
     lib.dd_adjoint.argtypes = [P, P, P]
-    lib.dd_gradient.argtypes = [P, P, P, P]
+    lib.dd_gradient.argtypes = [P, P, P, ctypes.POINTER(Tikhonov), P]
     lib.dd_error_string.argtypes = [ctypes.c_int]
     lib.dd_error_string.restype = ctypes.c_char_p
     lib.dd_last_error.argtypes = [P]
@@ -106,7 +125,7 @@ def load():
                                     ctypes.c_int32]
     lib.dd_algorithmic_bytes.argtypes = [P, ctypes.c_int32, ctypes.POINTER(ctypes.c_double)]
     lib.dd_debug_fem_apply.argtypes = [ctypes.POINTER(ProblemDesc), P, P, ctypes.c_int32, P, P]
-    lib.dd_batch_create.argtypes = [ctypes.c_int32, ctypes.POINTER(P)]
+    lib.dd_batch_create.argtypes = [ctypes.c_int32, ctypes.c_size_t, ctypes.POINTER(P)]
     lib.dd_batch_destroy.argtypes = [P]
     lib.dd_batch_submit.argtypes = [P, P, ctypes.POINTER(Source), ctypes.c_int32, P, P, P, P,
                                     ctypes.POINTER(ctypes.c_int32)]
@@ -157,6 +176,9 @@ def make_desc(d):
     c.detector_faces = int(d.detector_faces)
     c.absorbing_faces = int(d.absorbing_faces)
     c.t_switch = float(d.t_switch)
+    c.overlap = int(getattr(d, "overlap", 2))
+    c.s_stab = float(getattr(d, "s_stab", 1.0))
+    c.ckpt_mode = int(getattr(d, "ckpt_mode", CKPT_FEM_IFACE))
     return c
 
 

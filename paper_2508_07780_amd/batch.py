@@ -11,11 +11,12 @@ from .solver import _ptr, _stream
 class Batch:
     """Up to `max_slots` concurrent solves sharing every step launch."""
 
-    def __init__(self, max_slots=16, fill_cells=None):
+    def __init__(self, max_slots=16, fill_cells=None, hbm_budget=0):
         """fill_cells: a launch takes the oldest jobs until their cells per step reach this
-        (None: the library's default; 0: every job in every launch)."""
+        (None: the library's default; 0: every job in every launch).  hbm_budget: bytes the
+        problems with an active job may hold together (0: no limit); a job over it is refused."""
         self._h = ctypes.c_void_p()
-        _lib.check(_lib.load().dd_batch_create(int(max_slots), ctypes.byref(self._h)))
+        _lib.check(_lib.load().dd_batch_create(int(max_slots), int(hbm_budget), ctypes.byref(self._h)))
         if fill_cells is not None:
             _lib.check(_lib.load().dd_batch_set_fill(self._h, int(fill_cells)))
         self.max_slots = int(max_slots)

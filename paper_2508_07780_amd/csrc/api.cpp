@@ -40,6 +40,12 @@ struct dd_problem {
   float* geom = nullptr;
   double* mass_d = nullptr;
   float *em1 = nullptr, *c1 = nullptr, *c2 = nullptr;
+  float* sig_own = nullptr;   // sigma of the last dd_set_coefficients (owned order; the Tikhonov term)
+  // device allocator of every buffer the problem owns (null: hipMalloc / hipFree)
+  dd_alloc_fn alloc_fn = nullptr;
+  dd_free_fn free_fn = nullptr;
+  void* actx = nullptr;
+  size_t alloc_bytes = 0;     // bytes currently allocated
   // state (device)
   // FD grid: two levels of E (three-level form); FEM: two levels of E and the increment V
   float *Efd[2] = {nullptr, nullptr}, *Efem[2] = {nullptr, nullptr}, *Vfem = nullptr;
@@ -126,15 +132,30 @@ int fail(dd_problem* p, int code, const std::string& msg) {
   return code;
 }
 
-template <class T>
-int dalloc(dd_problem* p, T** ptr, size_t count) {
+// One device buffer through the problem's allocator (the caller's, else hipMalloc).
+void* raw_alloc(dd_alloc_fn fn, void* ctx, size_t bytes) {
   void* q = nullptr;
-  const size_t bytes = count ? count * sizeof(T) : sizeof(T);
+  if (fn) return fn(bytes, ctx);
   if (hipMalloc(&q, bytes) != hipSuccess) {
     (void)hipGetLastError();
-    return fail(p, DD_ERR_OOM, "hipMalloc of " + std::to_string(bytes) + " bytes failed");
+    return nullptr;
   }
+  return q;
+}
+
+void raw_free(dd_free_fn fn, void* ctx, void* q) {
+  if (!q) return;
+  if (fn) fn(q, ctx);
+  else (void)hipFree(q);
+}
+
+template <class T>
+int dalloc(dd_problem* p, T** ptr, size_t count) {
+  const size_t bytes = count ? count * sizeof(T) : sizeof(T);
+  void* q = raw_alloc(p->alloc_fn, p->actx, bytes);
+  if (!q) return fail(p, DD_ERR_OOM, "device allocation of " + std::to_string(bytes) + " bytes failed");
   p->allocs.push_back(q);
+  p->alloc_bytes += bytes;
   *ptr = static_cast<T*>(q);
   return DD_OK;
 }
@@ -172,7 +193,24 @@ std::string check_desc(const dd_problem_desc* d) {
   if (d->ckpt_every < 1) return "ckpt_every must be >= 1";
   if (d->detector_faces == 0 || d->detector_faces > 63u) return "detector_faces must be a non-empty face mask";
   if (d->absorbing_faces > 63u) return "absorbing_faces must be a face mask";
+  if (!std::isfinite(d->s_stab)) return "s_stab must be finite";
+  if (d->ckpt_mode < 0) return "ckpt_mode must be a DD_CKPT_* value";
   return std::string();
+}
+
+// Valid descriptor values this build does not run (DD_ERR_UNSUPPORTED).
+std::string check_desc_supported(const dd_problem_desc* d) {
+  if (d->overlap != 0 && d->overlap != 2) return "only a two-node overlap is built (overlap 2)";
+  if (d->s_stab != 0.0 && d->s_stab != 1.0)
+    return "only s = 1 is built: other s would break the plain wave equation of the finite-difference region";
+  if (d->ckpt_mode != DD_CKPT_FEM_IFACE && d->ckpt_mode != DD_CKPT_STORE_ALL)
+    return "ckpt_mode: full-state checkpoints are not built";
+  return std::string();
+}
+
+// Checkpoint interval the problem runs with: every level kept under DD_CKPT_STORE_ALL.
+int32_t effective_ckpt_every(const dd_problem_desc* d) {
+  return d->ckpt_mode == DD_CKPT_STORE_ALL ? std::max<int32_t>(d->n_steps, 1) : d->ckpt_every;
 }
 
 double source_time(const dd_source& s, double t) {
@@ -635,32 +673,59 @@ size_t dd_footprint_bytes(const dd_problem_desc* desc, int32_t n_src) {
   const int64_t N = (int64_t)desc->n_outer[0] * desc->n_outer[1] * desc->n_outer[2];
   const int64_t fs[3] = {desc->fem_cells[0] + 1, desc->fem_cells[1] + 1, desc->fem_cells[2] + 1};
   const int64_t n_fem = fs[0] * fs[1] * fs[2];
-  const int64_t n_own = (int64_t)(desc->fem_cells[0] - 1) * (desc->fem_cells[1] - 1) * (desc->fem_cells[2] - 1);
+  int64_t n_own = 1, n_part = 1;
+  for (int a = 0; a < 3; ++a) {
+    n_own *= desc->fem_cells[a] - 1;
+    n_part *= (desc->fem_cells[a] - 1 + FEM_PB - 1) / FEM_PB;
+  }
   const int64_t n_l0 = face_lex_count((int)fs[0], (int)fs[1], (int)fs[2], 63u);
-  const int64_t nt = desc->n_steps, K = desc->ckpt_every;
+  const int64_t nt = desc->n_steps, K = effective_ckpt_every(desc);
   const int64_t nseg = (nt + K - 1) / K;
   const int64_t n_ck = nseg, tail_levels = nt - (nseg - 1) * K + 1;
-  const int64_t tets_est = 6 * n_fem * 3 / 2;  // elements incl. halo duplicates (upper estimate)
+  // tile count of the variant with the most tiles (short z-chunks)
+  int nbx, nby, nbz, ntiles, per_xcd;
+  fd_tile_grid(desc->n_outer[0], desc->n_outer[1], desc->n_outer[2], false, nbx, nby, nbz, ntiles, per_xcd);
+  // per partition of at most FEM_PB^3 owned nodes: a staging box / halo list of at most
+  // (FEM_PB + 2)^3 codes, at most 6 (FEM_PB + 1)^3 elements, at most FEM_COLORS_MAX colours
+  constexpr int64_t box = (FEM_PB + 2) * (FEM_PB + 2) * (FEM_PB + 2);
+  constexpr int64_t elem = 6 * (FEM_PB + 1) * (FEM_PB + 1) * (FEM_PB + 1);
   int64_t b = 0;
+  // topology: partition offsets, colours, halo lists, elements, geometry, index maps, masses,
+  // stencil boxes and slots
+  b += 4 * (5 * n_part + 2 + n_part * (FEM_COLORS_MAX + 1) + n_part * box) + 8 * n_part * elem;
+  b += 4 * 64 * GEOM_STRIDE + 4 * 2 * n_own + 8 * n_own;
+  b += 4 * (4 * n_part + n_part * box) + 4 * STENCIL_SLOTS_MAX * 14;
+  b += 4 * 4 * n_own;                     // eps - 1, c1, c2, sigma
   b += 4 * 6 * N;                         // E (2 levels) on the grid
   b += 4 * 9 * n_own;                     // E (2 levels) + V on the FEM nodes
   b += 4 * 6 * n_l0;                      // interface ring
-  b += n_own * (4 * 3 + 8 + 4 * 2 + 8 * 2);  // coefficients, mass, index maps, gradient accumulators
-  b += tets_est * 8 + n_fem * 4 * 2;      // elements, halo lists
+  b += 8 * ((int64_t)ntiles + n_part) + 4 + 8 * 2 * n_own;   // energy partials, error flag, gradients
   b += (int64_t)n_src * ((nt + 1) * 3 * n_l0 * 4 + (n_ck + tail_levels) * 6 * n_own * 4);  // saved forward
   if (nseg > 1) b += (K + 1) * 6 * n_own * 4;  // recompute window
   if (nseg > 2) b += (K + 1) * 6 * n_own * 4;  // the second one (two segments in flight)
+  // optional buffers: misfit partials and weights; FEM-node map and sum of the div-div
+  // gradient terms (R2 / paper-formula gradient); initial data and its level-0 rows; a CGA run
+  b += 8 * 1024 + 8 * nt;
+  b += (4 + 8) * n_fem;
+  b += 2 * 4 * 3 * N + 8 * n_fem;
+  b += (2 * 4 + 2 * 8) * n_fem + 8 * 6 * 1024 + 1024;
   return (size_t)b;
 }
 
-int dd_create(const dd_problem_desc* desc, dd_problem** out) {
+int dd_create(const dd_problem_desc* desc, dd_alloc_fn alloc_fn, dd_free_fn free_fn, void* ctx, dd_problem** out) {
   if (!out) return DD_ERR_INVALID_ARG;
   *out = nullptr;
   const std::string e = check_desc(desc);
   if (!e.empty()) return DD_ERR_INVALID_ARG;
+  if (!check_desc_supported(desc).empty()) return DD_ERR_UNSUPPORTED;
+  if ((alloc_fn == nullptr) != (free_fn == nullptr)) return DD_ERR_INVALID_ARG;
   dd_problem* p = new (std::nothrow) dd_problem();
   if (!p) return DD_ERR_OOM;
   p->d = *desc;
+  p->d.ckpt_every = effective_ckpt_every(desc);
+  p->alloc_fn = alloc_fn;
+  p->free_fn = free_fn;
+  p->actx = ctx;
   p->nx = desc->n_outer[0];
   p->ny = desc->n_outer[1];
   p->nz = desc->n_outer[2];
@@ -720,6 +785,7 @@ int dd_create(const dd_problem_desc* desc, dd_problem** out) {
   chk(dalloc(p, &p->em1, p->n_own));
   chk(dalloc(p, &p->c1, p->n_own));
   chk(dalloc(p, &p->c2, p->n_own));
+  chk(dalloc(p, &p->sig_own, p->n_own));
   for (int b = 0; b < 2; ++b) {
     chk(dalloc(p, &p->Efd[b], 3 * p->N));
     chk(dalloc(p, &p->Efem[b], 3 * p->n_own));
@@ -745,6 +811,7 @@ int dd_create(const dd_problem_desc* desc, dd_problem** out) {
   std::vector<float> em1(p->n_own, 0.f), c1(p->n_own, 1.f), c2(p->n_own);
   for (int64_t i = 0; i < p->n_own; ++i) c2[i] = (float)(desc->dt * desc->dt / m.mass[i]);
   if (hipMemcpy(p->em1, em1.data(), 4 * p->n_own, hipMemcpyHostToDevice) != hipSuccess ||
+      hipMemcpy(p->sig_own, em1.data(), 4 * p->n_own, hipMemcpyHostToDevice) != hipSuccess ||
       hipMemcpy(p->c1, c1.data(), 4 * p->n_own, hipMemcpyHostToDevice) != hipSuccess ||
       hipMemcpy(p->c2, c2.data(), 4 * p->n_own, hipMemcpyHostToDevice) != hipSuccess) {
     dd_destroy(p);
@@ -756,7 +823,10 @@ int dd_create(const dd_problem_desc* desc, dd_problem** out) {
 
 int dd_destroy(dd_problem* p) {
   if (!p) return DD_ERR_INVALID_ARG;
-  (void)hipDeviceSynchronize();
+  // hipMalloc memory: nothing may still read it.  A caller allocator orders reuse after the
+  // work queued on the caller's stream; the library's own second stream is waited for here.
+  if (!p->free_fn) (void)hipDeviceSynchronize();
+  else if (p->aux) (void)hipStreamSynchronize(p->aux);
   for (auto& v : p->ev)
     for (hipEvent_t e : v) (void)hipEventDestroy(e);
   if (p->ev_fd) (void)hipEventDestroy(p->ev_fd);
@@ -764,7 +834,7 @@ int dd_destroy(dd_problem* p) {
   for (hipEvent_t e : {p->ev_rec[0], p->ev_rec[1], p->ev_adj})
     if (e) (void)hipEventDestroy(e);
   if (p->aux) (void)hipStreamDestroy(p->aux);
-  for (void* q : p->allocs) (void)hipFree(q);
+  for (void* q : p->allocs) raw_free(p->free_fn, p->actx, q);
   delete p;
   return DD_OK;
 }
@@ -789,7 +859,8 @@ int dd_set_coefficients(dd_problem* p, const float* eps_dev, const float* sigma_
       hipStreamSynchronize(st) != hipSuccess)
     return fail(p, DD_ERR_HIP, "error readback failed");
   if (h_err) return fail(p, DD_ERR_CONSTRAINT, std::to_string(h_err) + " FEM nodes violate the coefficient constraint");
-  launch_coefficients(eps_dev, sigma_dev, p->own_api, p->mass_d, p->n_own, p->d.dt, p->em1, p->c1, p->c2, st);
+  launch_coefficients(eps_dev, sigma_dev, p->own_api, p->mass_d, p->n_own, p->d.dt, p->em1, p->c1, p->c2, p->sig_own,
+                      st);
   if (int rc = check_launch(p)) return rc;
   if (hipStreamSynchronize(st) != hipSuccess) return fail(p, DD_ERR_HIP, "stream synchronize failed");
   p->saved = false;
@@ -857,9 +928,12 @@ int dd_adjoint_misfit(dd_problem* p, const float* traces_dev, const float* obs_d
   return adjoint_all(p, traces_dev, obs_dev, (hipStream_t)stream);
 }
 
-int dd_gradient(dd_problem* p, double* g_eps_dev, double* g_sigma_dev, void* stream) {
+int dd_gradient(dd_problem* p, double* g_eps_dev, double* g_sigma_dev, const dd_tikhonov* reg, void* stream) {
   if (!p) return DD_ERR_INVALID_ARG;
   if (!g_eps_dev || !g_sigma_dev) return fail(p, DD_ERR_INVALID_ARG, "null gradient buffer");
+  if (reg && (!reg->eps0_dev || !reg->sigma0_dev || !(reg->gamma_eps >= 0.0) || !(reg->gamma_sig >= 0.0) ||
+              !std::isfinite(reg->gamma_eps) || !std::isfinite(reg->gamma_sig)))
+    return fail(p, DD_ERR_INVALID_ARG, "Tikhonov term needs finite gammas >= 0 and both centres");
   if (!p->have_grad) return fail(p, DD_ERR_STATE, "dd_gradient needs a preceding dd_adjoint");
   hipStream_t st = (hipStream_t)stream;
   launch_fill_f64(g_eps_dev, p->n_fem, 0.0, st);
@@ -867,6 +941,9 @@ int dd_gradient(dd_problem* p, double* g_eps_dev, double* g_sigma_dev, void* str
   launch_gradient_out(p->g_eps, p->g_sig, p->own_api, p->own_grid, p->n_own, g_eps_dev, g_sigma_dev, st);
   if (p->r2) launch_add_free(p->pg_acc, p->fs, g_eps_dev, st);   // R2: the div-div part is the paper term
   if (p->ic_used) launch_add_free(p->ic_acc, p->fs, g_eps_dev, st);   // level-0 div-div rows (initial data)
+  if (reg)
+    launch_tikhonov_add(p->em1, p->sig_own, p->own_api, p->own_grid, p->mass_d, p->n_own, reg->gamma_eps,
+                        reg->gamma_sig, reg->eps0_dev, reg->sigma0_dev, g_eps_dev, g_sigma_dev, st);
   return check_launch(p);
 }
 
@@ -1064,6 +1141,8 @@ int dd_set_initial_data(dd_problem* p, const float* f0_dev, const float* f1_dev,
 struct dd_cga {
   int fs[3] = {0, 0, 0};
   int64_t n = 0;
+  dd_free_fn free_fn = nullptr;   // the allocator of the problem the run started on
+  void* actx = nullptr;
   float* c0 = nullptr;      // [2][n]: eps^0, sigma^0 (Tikhonov centres)
   double* d = nullptr;      // [2][n]: previous directions d^{m-1}
   double* part = nullptr;   // [CGA_MAX_BLOCKS][6] block partials
@@ -1089,10 +1168,10 @@ bool cga_params_ok(const dd_cga_params& q, std::string& why) {
 
 void cga_free(dd_cga* c) {
   if (!c) return;
-  (void)hipFree(c->c0);
-  (void)hipFree(c->d);
-  (void)hipFree(c->part);
-  (void)hipFree(c->st);
+  raw_free(c->free_fn, c->actx, c->c0);
+  raw_free(c->free_fn, c->actx, c->d);
+  raw_free(c->free_fn, c->actx, c->part);
+  raw_free(c->free_fn, c->actx, c->st);
   delete c;
 }
 }  // namespace
@@ -1126,10 +1205,13 @@ int dd_cga_create(dd_problem* p, const dd_cga_params* prm, const float* eps0_dev
   dd_cga* c = new dd_cga();
   for (int a = 0; a < 3; ++a) c->fs[a] = p->fs[a];
   c->n = p->n_fem;
-  if (hipMalloc((void**)&c->c0, 2 * c->n * sizeof(float)) != hipSuccess ||
-      hipMalloc((void**)&c->d, 2 * c->n * sizeof(double)) != hipSuccess ||
-      hipMalloc((void**)&c->part, (size_t)CGA_MAX_BLOCKS * 6 * sizeof(double)) != hipSuccess ||
-      hipMalloc((void**)&c->st, sizeof(CgaDev)) != hipSuccess) {
+  c->free_fn = p->free_fn;
+  c->actx = p->actx;
+  c->c0 = static_cast<float*>(raw_alloc(p->alloc_fn, p->actx, 2 * c->n * sizeof(float)));
+  c->d = static_cast<double*>(raw_alloc(p->alloc_fn, p->actx, 2 * c->n * sizeof(double)));
+  c->part = static_cast<double*>(raw_alloc(p->alloc_fn, p->actx, (size_t)CGA_MAX_BLOCKS * 6 * sizeof(double)));
+  c->st = static_cast<CgaDev*>(raw_alloc(p->alloc_fn, p->actx, sizeof(CgaDev)));
+  if (!c->c0 || !c->d || !c->part || !c->st) {
     cga_free(c);
     return fail(p, DD_ERR_OOM, "CGA state allocation failed");
   }
@@ -1280,6 +1362,7 @@ struct BatchJob {
   const float* obs = nullptr;
   double *g_eps = nullptr, *g_sig = nullptr;
   int id = 0;
+  size_t bytes = 0;           // the problem's footprint counted against the batch's budget
   int phase = 0;              // 0 forward, 1 adjoint, 2 finished
   int s = 0;                  // current source
   int64_t n = 0;              // forward step
@@ -1419,17 +1502,20 @@ struct dd_batch {
   // FD tile variant of the launches: -1 by the launch's combined FD fields against the
   // last-level cache, 0 / 1 forced cached / streaming (DD_FD_NT at dd_batch_create)
   int nt_mode = -1;
+  size_t hbm_budget = 0;        // 0: no limit
+  size_t in_use = 0;            // footprint of the problems with an active job
   std::string err;
 };
 
 extern "C" {
 
-int dd_batch_create(int32_t max_slots, dd_batch** out) {
+int dd_batch_create(int32_t max_slots, size_t hbm_budget, dd_batch** out) {
   if (!out || max_slots < 1 || 2 * max_slots > BATCH_MAX) return DD_ERR_INVALID_ARG;
   *out = nullptr;
   dd_batch* b = new (std::nothrow) dd_batch();
   if (!b) return DD_ERR_OOM;
   b->max_slots = max_slots;
+  b->hbm_budget = hbm_budget;
   b->width = 2 * max_slots;
   if (const char* e = std::getenv("DD_FD_NT")) b->nt_mode = std::atoi(e) != 0 ? 1 : 0;
   const size_t bytes = sizeof(BatchItem) * (size_t)b->ring * b->width;
@@ -1479,9 +1565,14 @@ int dd_batch_submit(dd_batch* b, dd_problem* p, const dd_source* src, int32_t n_
     const std::string e = check_source(p, src[s]);
     if (!e.empty()) return fail(p, DD_ERR_INVALID_ARG, e);
   }
+  const size_t bytes = dd_footprint_bytes(&p->d, n_src);
+  if (b->hbm_budget && b->in_use + bytes > b->hbm_budget)
+    return fail(p, DD_ERR_STATE, "the job does not fit the batch's HBM budget (" + std::to_string(bytes) + " bytes, " +
+                                     std::to_string(b->hbm_budget - std::min(b->in_use, b->hbm_budget)) + " free)");
   int rc = ensure_saved_storage(p, n_src);
   if (rc) return rc;
   BatchJob j;
+  j.bytes = bytes;
   j.p = p;
   j.src.assign(src, src + n_src);
   for (int s = 0; s < n_src; ++s) j.plans.push_back(source_plan(p, src[s]));
@@ -1497,6 +1588,7 @@ int dd_batch_submit(dd_batch* b, dd_problem* p, const dd_source* src, int32_t n_
   p->have_pg = false;
   p->ic_used = false;
   b->jobs.push_back(j);
+  b->in_use += bytes;
   if (job_out) *job_out = j.id;
   return DD_OK;
 }
@@ -1625,6 +1717,7 @@ int dd_batch_step(dd_batch* b, int32_t max_steps, void* stream) {
             }
           }
           b->done.push_back(it->id);
+          b->in_use -= std::min(b->in_use, it->bytes);
           it = b->jobs.erase(it);
         } else {
           ++it;

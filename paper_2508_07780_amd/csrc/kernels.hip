@@ -948,14 +948,29 @@ __global__ void validate_kernel(const float* eps, const float* sig, int fsx, int
 }
 
 __global__ void coefficients_kernel(const float* eps, const float* sig, const int* own_api, const double* mass,
-                                    int64_t n_own, double dt, float* em1, float* c1, float* c2) {
+                                    int64_t n_own, double dt, float* em1, float* c1, float* c2, float* sig_own) {
   for (int64_t id = (int64_t)blockIdx.x * blockDim.x + threadIdx.x; id < n_own; id += (int64_t)gridDim.x * blockDim.x) {
     const int api = own_api[id];
     const double e = (double)eps[api], s = (double)sig[api], m = mass[id];
     const double aa = m * e / (dt * dt), bb = m * s / (2.0 * dt);
-    em1[id] = (float)(e - 1.0);
+    em1[id] = (float)(e - 1.0);   // exact: eps >= 1 is a float32 value
     c1[id] = (float)((aa - bb) / (aa + bb));
     c2[id] = (float)(1.0 / (aa + bb));
+    sig_own[id] = sig[api];
+  }
+}
+
+// Derivative of the Tikhonov term gamma/2 sum_i m_i (c_i - c0_i)^2 on the free nodes,
+// added to the gradient arrays (FEM-node order).  eps = 1 + (eps - 1) exactly.
+__global__ void tikhonov_add_kernel(const float* em1, const float* sig_own, const int* own_api, const int* own_grid,
+                                    const double* mass, int64_t n_own, double ge, double gs, const float* eps0,
+                                    const float* sig0, double* g_eps, double* g_sig) {
+  for (int64_t id = (int64_t)blockIdx.x * blockDim.x + threadIdx.x; id < n_own; id += (int64_t)gridDim.x * blockDim.x) {
+    if (own_grid[id] >= 0) continue;   // layer 1: not free
+    const int api = own_api[id];
+    const double m = mass[id];
+    g_eps[api] += ge * m * ((1.0 + (double)em1[id]) - (double)eps0[api]);
+    g_sig[api] += gs * m * ((double)sig_own[id] - (double)sig0[api]);
   }
 }
 
@@ -1126,9 +1141,16 @@ void launch_validate(const float* eps, const float* sig, int fsx, int fsy, int f
 }
 
 void launch_coefficients(const float* eps, const float* sig, const int* own_api, const double* mass_d, int64_t n_own,
-                         double dt, float* em1, float* c1, float* c2, hipStream_t s) {
+                         double dt, float* em1, float* c1, float* c2, float* sig_own, hipStream_t s) {
   hipLaunchKernelGGL(coefficients_kernel, dim3(grid_for(n_own)), dim3(256), 0, s, eps, sig, own_api, mass_d, n_own, dt,
-                     em1, c1, c2);
+                     em1, c1, c2, sig_own);
+}
+
+void launch_tikhonov_add(const float* em1, const float* sig_own, const int* own_api, const int* own_grid,
+                         const double* mass_d, int64_t n_own, double gamma_eps, double gamma_sig, const float* eps0,
+                         const float* sig0, double* g_eps, double* g_sig, hipStream_t s) {
+  hipLaunchKernelGGL(tikhonov_add_kernel, dim3(grid_for(n_own)), dim3(256), 0, s, em1, sig_own, own_api, own_grid,
+                     mass_d, n_own, gamma_eps, gamma_sig, eps0, sig0, g_eps, g_sig);
 }
 
 void launch_gradient_out(const double* g_eps, const double* g_sig, const int* own_api, const int* own_grid,

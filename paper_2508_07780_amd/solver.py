@@ -29,15 +29,56 @@ def _device_f32(x, n, name):
     return t
 
 
-class Problem:
-    """A hybrid FE/FD problem resident on the current GPU."""
+class TorchAllocator:
+    """Routes a problem's device allocations through torch's caching allocator (on the stream
+    current at each allocation) and counts the bytes it holds."""
 
-    def __init__(self, desc):
+    def __init__(self, device):
+        self.device = device
+        self.live = {}
+        self.bytes = 0
+        self.peak = 0
+        self.alloc_fn = _lib.ALLOC_FN(self._alloc)
+        self.free_fn = _lib.FREE_FN(self._free)
+
+    def _alloc(self, nbytes, ctx):
+        try:
+            ptr = torch.cuda.caching_allocator_alloc(int(nbytes), self.device, torch.cuda.current_stream(self.device))
+        except Exception:       # out of memory: the library reports DD_ERR_OOM
+            return None
+        self.live[ptr] = int(nbytes)
+        self.bytes += int(nbytes)
+        self.peak = max(self.peak, self.bytes)
+        return ptr
+
+    def _free(self, ptr, ctx):
+        try:
+            self.bytes -= self.live.pop(ptr, 0)
+            torch.cuda.caching_allocator_delete(ptr)
+        except Exception:
+            pass
+
+
+class Problem:
+    """A hybrid FE/FD problem resident on the current GPU.  Its device state is allocated
+    through torch's caching allocator (allocator="torch", the default) or by the library
+    with hipMalloc (allocator=None)."""
+
+    def __init__(self, desc, allocator="torch"):
         lib = _lib.load()
         self.desc = desc
         self._cdesc = _lib.make_desc(desc)
         h = ctypes.c_void_p()
-        _lib.check(lib.dd_create(ctypes.byref(self._cdesc), ctypes.byref(h)))
+        self.allocator = None
+        if allocator == "torch":
+            self.allocator = TorchAllocator(torch.cuda.current_device())
+            _lib.check(lib.dd_create(ctypes.byref(self._cdesc), self.allocator.alloc_fn, self.allocator.free_fn,
+                                     None, ctypes.byref(h)))
+        elif allocator is None:
+            _lib.check(lib.dd_create(ctypes.byref(self._cdesc), _lib.ALLOC_FN(), _lib.FREE_FN(), None,
+                                     ctypes.byref(h)))
+        else:
+            raise ValueError('allocator must be "torch" or None')
         self._h = h
         nf, nd, ng = ctypes.c_int64(), ctypes.c_int64(), ctypes.c_int64()
         _lib.check(lib.dd_sizes(h, ctypes.byref(nf), ctypes.byref(nd), ctypes.byref(ng)), h)
@@ -115,19 +156,32 @@ class Problem:
                 raise ValueError("%s must be a contiguous float32 CUDA (HIP) tensor of shape %s" % (name, shape))
         _lib.check(_lib.load().dd_adjoint_misfit(self._h, _ptr(traces), _ptr(obs), _stream()), self._h)
 
-    def gradient(self, out=None):
+    def gradient(self, out=None, reg=None):
+        """(dJ/deps, dJ/dsigma) on the FEM nodes (float64).  reg: None, or (gamma_eps, gamma_sig,
+        eps0, sigma0) to add the derivative of the Tikhonov term of eq. tikhonov_functional."""
         if out is not None:
             ge, gs = out
             for t in (ge, gs):
                 if not (t.is_cuda and t.dtype == torch.float64 and t.is_contiguous() and t.numel() == self.n_fem):
                     raise ValueError("gradient buffers must be contiguous float64 CUDA tensors of n_fem entries")
-            _lib.check(_lib.load().dd_gradient(self._h, _ptr(ge), _ptr(gs), _stream()), self._h)
-            return ge, gs
-        dev = torch.device("cuda", torch.cuda.current_device())
-        ge = torch.empty(self.n_fem, dtype=torch.float64, device=dev)
-        gs = torch.empty(self.n_fem, dtype=torch.float64, device=dev)
-        _lib.check(_lib.load().dd_gradient(self._h, _ptr(ge), _ptr(gs), _stream()), self._h)
+        else:
+            dev = torch.device("cuda", torch.cuda.current_device())
+            ge = torch.empty(self.n_fem, dtype=torch.float64, device=dev)
+            gs = torch.empty(self.n_fem, dtype=torch.float64, device=dev)
+        treg = None
+        if reg is not None:
+            g_e, g_s, e0, s0 = reg
+            e0 = _device_f32(e0, self.n_fem, "eps0")
+            s0 = _device_f32(s0, self.n_fem, "sigma0")
+            treg = _lib.Tikhonov(float(g_e), float(g_s), e0.data_ptr(), s0.data_ptr())
+            self._reg_keep = (e0, s0)       # alive until the queued kernels have read them
+        _lib.check(_lib.load().dd_gradient(self._h, _ptr(ge), _ptr(gs), ctypes.byref(treg) if treg else None,
+                                           _stream()), self._h)
         return ge, gs
+
+    def device_bytes(self):
+        """Bytes the library holds through torch's allocator (None with hipMalloc)."""
+        return None if self.allocator is None else self.allocator.bytes
 
     def misfit(self, traces, obs, z=None, cotangent=True, loss=True, out=None, no_alloc=False):
         """(J, cot) of the trace misfit with time weights z (numpy, n_steps, or None for z = 1):

@@ -57,6 +57,9 @@ class ProblemDesc:
     detector_faces: int = FACE_TOP
     absorbing_faces: int = FACE_TOP | FACE_BOTTOM
     t_switch: float = 0.0   # top face: source for t <= t_switch, absorbing after
+    overlap: int = 2        # node layers shared by the FD and FEM regions
+    s_stab: float = 1.0     # weight of the div-div stabiliser
+    ckpt_mode: int = 0      # 0: FEM checkpoints + interface history, 1: every level kept
 
     def fem_shape(self):
         return tuple(int(c) + 1 for c in self.fem_cells)

@@ -91,12 +91,16 @@ def test_struct_layouts_match_the_header(tmp_path):
         "sizeof(dd_cga_info));\n"
         '  printf("%zu %zu %zu\\n", offsetof(dd_problem_desc, t_switch), offsetof(dd_cga_info, grad_norm), '
         "offsetof(dd_cga_info, gamma_next));\n"
+        '  printf("%zu %zu %zu %zu\\n", offsetof(dd_problem_desc, overlap), offsetof(dd_problem_desc, s_stab), '
+        "offsetof(dd_problem_desc, ckpt_mode), sizeof(dd_tikhonov));\n"
         "  return 0;\n}\n")
     exe = tmp_path / "layout"
     subprocess.run(["gcc", "-I", os.path.join(ROOT, "include"), str(src), "-o", str(exe)], check=True)
     out = subprocess.run([str(exe)], check=True, capture_output=True, text=True).stdout.split()
     sizes = [ctypes.sizeof(t) for t in (_lib.ProblemDesc, _lib.Source, _lib.CgaParams, _lib.CgaInfo)]
-    offs = [_lib.ProblemDesc.t_switch.offset, _lib.CgaInfo.grad_norm.offset, _lib.CgaInfo.gamma_next.offset]
+    offs = [_lib.ProblemDesc.t_switch.offset, _lib.CgaInfo.grad_norm.offset, _lib.CgaInfo.gamma_next.offset,
+            _lib.ProblemDesc.overlap.offset, _lib.ProblemDesc.s_stab.offset, _lib.ProblemDesc.ckpt_mode.offset,
+            ctypes.sizeof(_lib.Tikhonov)]
     assert [int(v) for v in out] == sizes + offs
 
 
@@ -179,3 +183,39 @@ def test_bench_refuses_several_gpus():
                        text=True, timeout=120)
     assert r.returncode != 0
     assert "one GPU" in (r.stdout + r.stderr)
+
+
+def test_descriptor_fields_without_a_build_are_refused_before_device_work(lib):
+    """overlap other than 2, s_stab other than 1 and full-state checkpoints are valid requests
+    this build does not run (DD_ERR_UNSUPPORTED); an allocator with only one of its two
+    functions is an invalid argument.  Both are decided before any device work (no GPU here)."""
+    from paper_2508_07780_amd import _lib
+    for field, value, code in (("overlap", 3, -7), ("s_stab", 0.5, -7), ("ckpt_mode", _lib.CKPT_FULL, -7),
+                               ("ckpt_mode", -1, -1), ("s_stab", float("nan"), -1)):
+        w = synth.small("tiny")
+        setattr(w.desc, field, value)
+        c = _lib.make_desc(w.desc)
+        h = ctypes.c_void_p()
+        assert lib.dd_create(ctypes.byref(c), _lib.ALLOC_FN(), _lib.FREE_FN(), None, ctypes.byref(h)) == code, field
+        assert not h.value
+    w = synth.small("tiny")
+    c = _lib.make_desc(w.desc)
+    h = ctypes.c_void_p()
+    only_alloc = _lib.ALLOC_FN(lambda n, ctx: None)
+    assert lib.dd_create(ctypes.byref(c), only_alloc, _lib.FREE_FN(), None, ctypes.byref(h)) == -1
+
+
+def test_footprint_covers_store_all_and_the_defaults_of_zeroed_fields(lib):
+    """DD_CKPT_STORE_ALL keeps every FEM level (the footprint of K = n_steps); zero overlap and
+    s_stab mean their only built values."""
+    from paper_2508_07780_amd import _lib
+    w = synth.c2()
+    c = _lib.make_desc(w.desc)
+    k64 = lib.dd_footprint_bytes(ctypes.byref(c), 1)
+    c.ckpt_mode = _lib.CKPT_STORE_ALL
+    store_all = lib.dd_footprint_bytes(ctypes.byref(c), 1)
+    c.ckpt_mode = _lib.CKPT_FEM_IFACE
+    c.ckpt_every = w.desc.n_steps
+    assert store_all == lib.dd_footprint_bytes(ctypes.byref(c), 1) > 4 * k64
+    c.overlap, c.s_stab = 0, 0.0
+    assert lib.dd_footprint_bytes(ctypes.byref(c), 1) == store_all
