@@ -60,20 +60,54 @@ def source_time_function(src, t):
     raise ValueError("unknown source kind")
 
 
+def incidence(src):
+    """Unit direction k of a plane wave's travel, or None for normal incidence (k = -e_z, the
+    model problem of eq. model1): src.dir, normalised; zero (or absent) means normal incidence.
+    The wave enters through the top face, so k_z < 0."""
+    v = np.asarray(getattr(src, "dir", (0.0, 0.0, 0.0)), dtype=np.float64)
+    nv = float(np.linalg.norm(v))
+    if nv == 0.0:
+        return None
+    k = v / nv
+    if not k[2] < 0.0:
+        raise ValueError("a plane wave enters through the top face: dir must point down (dir_z < 0)")
+    return k
+
+
+def arrival_delays(d, k):
+    """tau_i = k . (x_i - x_ref) on the top-face nodes, with x_ref the top-face node the wave
+    front reaches first (the smallest k . x), so every delay is >= 0."""
+    top = d.face_mass[1] > 0.0
+    proj = d.x[top] @ k
+    return top, proj - proj.min()
+
+
 def forcing(d, src, n):
     """F^n over the grid, shape (N, 3)."""
     F = np.zeros((d.N, 3))
-    p = source_time_function(src, n * d.dt)
-    if p == 0.0:
-        return F
+    t = n * d.dt
     pol = np.asarray(src.pol, dtype=np.float64)
     if src.kind == SRC_DIPOLE:
+        p = source_time_function(src, t)
+        if p == 0.0:
+            return F
         i, j, k = (int(v) for v in src.pos)
         g = i + d.nvec[0] * (j + d.nvec[1] * k)
         F[g] = p * pol
-    else:
-        if n * d.dt <= float(d.desc.t_switch):   # Gamma_{1,1}: d_n E = P on the top face
+        return F
+    if t > float(d.desc.t_switch):
+        return F
+    # Gamma_{1,1}: d_n E = P on the top face; a wave arriving from direction k reaches top-face
+    # node i at the delay tau_i, so there d_n E = P(t - tau_i)
+    k = incidence(src)
+    if k is None:
+        p = source_time_function(src, t)
+        if p != 0.0:
             F += (d.face_mass[1] * p)[:, None] * pol[None, :]
+        return F
+    top, tau = arrival_delays(d, k)
+    pv = np.array([source_time_function(src, t - ti) for ti in tau])
+    F[top] += (d.face_mass[1][top] * pv)[:, None] * pol[None, :]
     return F
 
 

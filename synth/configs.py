@@ -97,6 +97,7 @@ class Source:
     amp: float = 1.0
     pol: tuple = (0.0, 1.0, 0.0)
     pos: tuple = (0, 0, 0)   # dipole: outer-grid node index
+    dir: tuple = (0.0, 0.0, 0.0)   # plane wave: direction of travel (zero: normal incidence, -z)
 
     def support_end(self):
         """End of the pulse's time support (used as the top-face switch time)."""
