@@ -113,6 +113,14 @@ typedef struct {
 typedef struct {
   int32_t kind;             /* DD_SRC_* */
   double omega, t0, width, amp;
+  double dir[3];            /* plane waves: direction of travel k (normalised by the library);
+                               all zero = normal incidence (k = -e_z, the model problem of
+                               eq. model1).  Otherwise k_z < 0 is required: the wave enters
+                               through the top face, reaching top-face node i at the delay
+                               tau_i = k . (x_i - x_ref) (x_ref: the top-face node it reaches
+                               first), where the forcing is P(t - tau_i) instead of P(t); the
+                               source stays on while t_n <= t_switch, which should cover
+                               max tau_i plus the pulse.  Ignored for DD_SRC_DIPOLE. */
   double pol[3];            /* polarisation / dipole moment direction */
   int32_t pos[3];           /* DD_SRC_DIPOLE: grid node; must be finite-difference owned */
 } dd_source;

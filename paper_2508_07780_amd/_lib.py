@@ -69,6 +69,7 @@ class Source(ctypes.Structure):
         ("t0", ctypes.c_double),
         ("width", ctypes.c_double),
         ("amp", ctypes.c_double),
+        ("dir", ctypes.c_double * 3),
         ("pol", ctypes.c_double * 3),
         ("pos", ctypes.c_int32 * 3),
     ]
@@ -190,7 +191,9 @@ def make_sources(srcs):
         arr[i].t0 = float(s.t0)
         arr[i].width = float(s.width)
         arr[i].amp = float(s.amp)
+        d = getattr(s, "dir", (0.0, 0.0, 0.0))
         for a in range(3):
+            arr[i].dir[a] = float(d[a])
             arr[i].pol[a] = float(s.pol[a])
             arr[i].pos[a] = int(s.pos[a])
     return arr

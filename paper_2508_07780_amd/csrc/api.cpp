@@ -227,6 +227,11 @@ std::string check_source(const dd_problem* p, const dd_source& s) {
   if (s.kind != DD_SRC_SINE1 && s.kind != DD_SRC_GAUSS_SINE && s.kind != DD_SRC_DIPOLE) return "unknown source kind";
   if (!(s.omega > 0.0) || !std::isfinite(s.omega)) return "source omega must be positive";
   if (s.kind != DD_SRC_SINE1 && !(s.width > 0.0)) return "source width must be positive";
+  if (s.kind != DD_SRC_DIPOLE) {
+    const double n2 = s.dir[0] * s.dir[0] + s.dir[1] * s.dir[1] + s.dir[2] * s.dir[2];
+    if (!std::isfinite(n2)) return "plane-wave direction must be finite";
+    if (n2 > 0.0 && !(s.dir[2] < 0.0)) return "a plane wave enters through the top face: dir must have dir_z < 0";
+  }
   if (s.kind == DD_SRC_DIPOLE) {
     for (int a = 0; a < 3; ++a)
       if (s.pos[a] < 0 || s.pos[a] >= p->d.n_outer[a]) return "dipole position outside the grid";
@@ -371,10 +376,26 @@ void join_streams(dd_problem* p, hipStream_t st) {
 struct SrcPlan {
   int64_t dip_idx = -1;
   double dip_scale = 0.0;   // dt^2 / m at the dipole node
+  // obliquely incident plane wave: unit direction's in-face components (time per unit length,
+  // the wave speed being 1) and the top-face node of delay 0
+  bool oblique = false;
+  double kx = 0.0, ky = 0.0;
+  int x0 = 0, y0 = 0;
 };
 
 SrcPlan source_plan(const dd_problem* p, const dd_source& src) {
   SrcPlan sp;
+  if (src.kind != DD_SRC_DIPOLE) {
+    const double n = std::sqrt(src.dir[0] * src.dir[0] + src.dir[1] * src.dir[1] + src.dir[2] * src.dir[2]);
+    if (n > 0.0 && (src.dir[0] != 0.0 || src.dir[1] != 0.0)) {
+      sp.oblique = true;
+      sp.kx = src.dir[0] / n;
+      sp.ky = src.dir[1] / n;
+      // the node the wave front reaches first: the smallest k . x over the top face
+      sp.x0 = sp.kx < 0.0 ? p->nx - 1 : 0;
+      sp.y0 = sp.ky < 0.0 ? p->ny - 1 : 0;
+    }
+  }
   if (src.kind == DD_SRC_DIPOLE) {
     sp.dip_idx = src.pos[0] + (int64_t)p->nx * (src.pos[1] + (int64_t)p->ny * src.pos[2]);
     int b = 0;
@@ -422,11 +443,31 @@ void fwd_step_args(const dd_problem* p, const dd_source& src, const SrcPlan& sp,
   // the previous step ended (whose fields the cache still holds)
   fa.rev = ea.rev = (int)(n & 1);
   fa.top_a = fa.top_b = top_absorbs(p, n) ? 1 : 0;
+  const bool plane_on = src.kind != DD_SRC_DIPOLE && t <= p->d.t_switch;
   for (int c = 0; c < 3; ++c) {
-    fa.pw[c] = (src.kind != DD_SRC_DIPOLE && t <= p->d.t_switch) ? (float)(2.0 * dt * dt / h * P * src.pol[c]) : 0.f;
+    fa.pw[c] = (plane_on && !sp.oblique) ? (float)(2.0 * dt * dt / h * P * src.pol[c]) : 0.f;
     fa.dip[c] = (float)(P * src.pol[c] * sp.dip_scale);
   }
   fa.dip_idx = sp.dip_idx;
+  // oblique incidence: the kernel evaluates the delayed pulse per top-face node
+  fa.pw_kind = (plane_on && sp.oblique) ? src.kind : 0;
+  if (fa.pw_kind) {
+    for (int c = 0; c < 3; ++c) fa.pw_amp[c] = (float)(2.0 * dt * dt / h * src.amp * src.pol[c]);
+    fa.pw_kx = (float)(sp.kx * h);
+    fa.pw_ky = (float)(sp.ky * h);
+    fa.pw_x0 = sp.x0;
+    fa.pw_y0 = sp.y0;
+    fa.pw_omega = (float)src.omega;
+    if (src.kind == DD_SRC_GAUSS_SINE) {
+      fa.pw_t = (float)(t - src.t0);
+      fa.pw_iw = (float)(1.0 / src.width);
+      fa.pw_sup = (float)src.t0;
+    } else {
+      fa.pw_t = (float)t;
+      fa.pw_iw = 0.f;
+      fa.pw_sup = (float)(2.0 * M_PI / src.omega);
+    }
+  }
   fa.tr_out = traces + ((int64_t)s * nt + n) * p->n_det * 3;
   fa.cot_in = nullptr;
   fa.obs_in = nullptr;
@@ -1631,7 +1672,7 @@ int dd_batch_step(dd_batch* b, int32_t max_steps, void* stream) {
     }
     BatchBases bases[dd_batch::seg];
     size_t lds[dd_batch::seg];
-    bool nt[dd_batch::seg];
+    bool nt[dd_batch::seg], obl[dd_batch::seg];
     int m = 0;
     bool finished = false;
     while (m < b->seg && iter < max_steps && !b->jobs.empty()) {
@@ -1653,6 +1694,8 @@ int dd_batch_step(dd_batch* b, int32_t max_steps, void* stream) {
       // the launch's variant (and with it the z-chunk) follows the FD fields it streams;
       // each item's tile grid is laid out for that chunk
       const bool use_nt = b->nt_mode < 0 ? fd_bytes > LLC_BYTES : b->nt_mode != 0;
+      bool use_obl = false;
+      for (int i = 0; i < n; ++i) use_obl |= h[i].fa.pw_kind != 0;
       for (int i = 0; i < n; ++i) {
         BatchItem& it = h[i];
         const dd_problem* q = owner[i];
@@ -1670,6 +1713,7 @@ int dd_batch_step(dd_batch* b, int32_t max_steps, void* stream) {
       bases[m].base[n] = base;
       lds[m] = l;
       nt[m] = use_nt;
+      obl[m] = use_obl;
       ++m;
       ++iter;
       if (std::any_of(b->jobs.begin(), b->jobs.end(), [](const BatchJob& j) { return j.phase == 2; })) {
@@ -1693,7 +1737,7 @@ int dd_batch_step(dd_batch* b, int32_t max_steps, void* stream) {
           // same device code on the same arguments, without the item lookup)
           launch_step(one.fa, one.ea, st, one.kind == 1, false, nt[k]);
         else
-          launch_batch(b->dev + off + (size_t)k * b->width, bases[k], lds[k], st, nt[k]);
+          launch_batch(b->dev + off + (size_t)k * b->width, bases[k], lds[k], st, nt[k], obl[k]);
       }
       hipError_t e = hipGetLastError();
       if (e != hipSuccess) {

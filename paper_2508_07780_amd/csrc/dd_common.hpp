@@ -106,6 +106,16 @@ struct FdArgs {
   unsigned abs_mask;
   int top_a, top_b;    // top face absorbing at the levels of D+ (a) and D- (b)
   float pw[3];         // plane-wave forcing F dt^2 / m on the top face (0 when off)
+  // obliquely incident plane wave, while on (pw_kind != 0; pw is 0 then): top-face node (x, y)
+  // takes pw_amp * P(t_n - tau), tau = pw_kx (x - pw_x0) + pw_ky (y - pw_y0)
+  int pw_kind;         // 0, DD_SRC_SINE1 or DD_SRC_GAUSS_SINE
+  float pw_amp[3];     // 2 dt^2 / h * amp * pol
+  float pw_t;          // t_n (SINE1) or t_n - t0 (GAUSS_SINE)
+  float pw_kx, pw_ky;  // delay per node step along x and y (k_x h, k_y h)
+  int pw_x0, pw_y0;    // top-face node of delay 0
+  float pw_omega;      // omega
+  float pw_iw;         // 1 / width (GAUSS_SINE)
+  float pw_sup;        // support: |t - tau - t0| <= pw_sup (GAUSS_SINE: t0), 0 < t - tau < pw_sup (SINE1: period)
   int64_t dip_idx;     // dipole grid node or -1
   float dip[3];        // dipole forcing F dt^2 / m at that node
   unsigned det_mask;
@@ -197,7 +207,8 @@ struct BatchBases {
   int n;
   int base[BATCH_MAX + 1];
 };
-void launch_batch(const BatchItem* items_dev, const BatchBases& bases, size_t lds, hipStream_t s, bool nt);
+// obl: some item carries an obliquely incident plane wave (pw_kind != 0)
+void launch_batch(const BatchItem* items_dev, const BatchBases& bases, size_t lds, hipStream_t s, bool nt, bool obl);
 size_t stencil_lds(const FemArgs& a);
 void launch_energy_reduce(const double* part, int n, double* out, hipStream_t s);
 void launch_fill_f32(float* p, int64_t n, float v, hipStream_t s);

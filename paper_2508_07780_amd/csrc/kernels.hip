@@ -48,9 +48,28 @@ __device__ __forceinline__ void st_own(char* base, uint32_t off, float v) {
   else *reinterpret_cast<float*>(base + off) = v;
 }
 
+// The time function of an obliquely incident plane wave at top-face node (x, y): the pulse of
+// the source kind delayed by tau = pw_kx (x - pw_x0) + pw_ky (y - pw_y0).  Inside the pulse's
+// support the sine's argument stays within 3 pi (the Gaussian-modulated sine: |omega u| <=
+// omega t0 = 3 pi; one sine period: < 2 pi), where the hardware sine and exponential are
+// accurate to about 1e-6, well inside the trace tolerance, and need no argument reduction.
+__device__ __forceinline__ float oblique_pulse(const FdArgs& a, int x, int y) {
+  const float tau = a.pw_kx * (float)(x - a.pw_x0) + a.pw_ky * (float)(y - a.pw_y0);
+  const float u = a.pw_t - tau;
+  if (a.pw_kind == DD_SRC_GAUSS_SINE) {
+    if (!(fabsf(u) <= a.pw_sup)) return 0.f;
+    const float v = u * a.pw_iw;
+    return __sinf(a.pw_omega * u) * __expf(-0.5f * v * v);
+  }
+  if (!(u > 0.f && u < a.pw_sup)) return 0.f;
+  return __sinf(a.pw_omega * u);
+}
+
 // b: block index within the finite-difference part of the launch; b % N_XCD must equal
 // blockIdx.x % N_XCD so that the remap below keeps consecutive tiles on one XCD.
-template <bool ENERGY, bool NT>
+// OBL: the top face may carry an obliquely incident plane wave (a separate instantiation, so
+// that the kernels of normal incidence keep their register allocation).
+template <bool ENERGY, bool NT, bool OBL = false>
 __device__ __forceinline__ void fd_tile(const FdArgs& a, const int b) {
   constexpr int ZC = fd_zc(NT);
   // two LDS planes: plane z is written while plane z-1 may still be read by slower waves,
@@ -210,6 +229,12 @@ __device__ __forceinline__ void fd_tile(const FdArgs& a, const int b) {
           src[0] += a.pw[0];
           src[1] += a.pw[1];
           src[2] += a.pw[2];
+          if (OBL && a.pw_kind) {
+            const float pv = oblique_pulse(a, x, y);
+            src[0] += a.pw_amp[0] * pv;
+            src[1] += a.pw_amp[1] * pv;
+            src[2] += a.pw_amp[2] * pv;
+          }
         }
         if (a.det_mask) det = face_lex_index(x, y, z, nx, ny, nz, a.det_mask);
         if (det >= 0 && a.cot_in) {
@@ -283,9 +308,9 @@ __device__ __forceinline__ void fd_tile(const FdArgs& a, const int b) {
   }
 }
 
-template <bool ENERGY, bool NT>
+template <bool ENERGY, bool NT, bool OBL>
 __global__ __launch_bounds__(FD_THREADS) void fd_step_kernel(FdArgs a) {
-  fd_tile<ENERGY, NT>(a, blockIdx.x);
+  fd_tile<ENERGY, NT, OBL>(a, blockIdx.x);
 }
 
 // ---------------------------------------------------------------------------------------
@@ -806,7 +831,7 @@ __global__ __launch_bounds__(STENCIL_THREADS) void fem_stencil_kernel(FemArgs a)
 // One launch per time step: blocks [0, fem_blocks) advance the FEM partitions (scheduled
 // first: their staging is latency-bound), the remaining blocks the finite-difference
 // tiles.  Both read level n and write level n+1 only, so they need no ordering.
-template <bool ADJ, bool ENERGY, bool NT>
+template <bool ADJ, bool ENERGY, bool NT, bool OBL = false>
 __global__ __launch_bounds__(FD_THREADS) void step_kernel(FdArgs fa, FemArgs ea, int fem_blocks) {
   const int b = blockIdx.x;
   if (b < fem_blocks) {
@@ -814,7 +839,7 @@ __global__ __launch_bounds__(FD_THREADS) void step_kernel(FdArgs fa, FemArgs ea,
     if (p < ea.n_part) fem_stencil_part<ADJ, ENERGY>(ea, p);
     return;
   }
-  fd_tile<ENERGY, NT>(fa, b - fem_blocks);
+  fd_tile<ENERGY, NT, OBL>(fa, b - fem_blocks);
 }
 
 // The adjoint step of the form R1 with the paper-formula variant on: it also carries the
@@ -840,7 +865,7 @@ __global__ __launch_bounds__(FD_THREADS) void step_kernel_pg(FdArgs fa, FemArgs 
 // with r2_term's cell loop unrolled four at a time).  An adjoint step also carries the
 // div-div gradient terms of its input level (blocks [fem_blocks, fem_blocks + pg_blocks),
 // pg_tile): they read lambda^k and the saved E^k, which the step does not write.
-template <bool ADJ, bool ENERGY, bool NT>
+template <bool ADJ, bool ENERGY, bool NT, bool OBL = false>
 __global__ __launch_bounds__(FD_THREADS) void step_kernel_r2(FdArgs fa, FemArgs ea, int fem_blocks, PgArgs pg,
                                                                   int pg_blocks) {
   const int b = blockIdx.x;
@@ -853,7 +878,7 @@ __global__ __launch_bounds__(FD_THREADS) void step_kernel_r2(FdArgs fa, FemArgs 
     if (b - fem_blocks < pg_tiles(pg.fs)) pg_tile(pg, b - fem_blocks);
     return;
   }
-  fd_tile<ENERGY, NT>(fa, b - fem_blocks - pg_blocks);
+  fd_tile<ENERGY, NT, OBL>(fa, b - fem_blocks - pg_blocks);
 }
 
 // ---------------------------------------------------------------------------------------
@@ -867,7 +892,7 @@ __global__ __launch_bounds__(FD_THREADS) void step_kernel_r2(FdArgs fa, FemArgs 
 // kernel; without the occupancy bound the compiler allocates registers for their union
 // (93 VGPRs, 5 waves per SIMD instead of 6).
 // ---------------------------------------------------------------------------------------
-template <bool NT>
+template <bool NT, bool OBL>
 __global__ __launch_bounds__(FD_THREADS, 6) void batch_step_kernel(const BatchItem* __restrict__ items, BatchBases bb) {
   const int b = blockIdx.x;
   // the item whose block range holds b: binary search over the bases in the arguments
@@ -888,15 +913,19 @@ __global__ __launch_bounds__(FD_THREADS, 6) void batch_step_kernel(const BatchIt
     }
     return;
   }
-  if (local - it.fem_blocks < it.fd_blocks) fd_tile<false, NT>(it.fa, local - it.fem_blocks);
+  if (local - it.fem_blocks < it.fd_blocks) fd_tile<false, NT, OBL>(it.fa, local - it.fem_blocks);
 }
 
-void launch_batch(const BatchItem* items_dev, const BatchBases& bases, size_t lds, hipStream_t s, bool nt) {
+void launch_batch(const BatchItem* items_dev, const BatchBases& bases, size_t lds, hipStream_t s, bool nt, bool obl) {
   const dim3 grid(bases.base[bases.n]);
-  if (nt)
-    hipLaunchKernelGGL((batch_step_kernel<true>), grid, dim3(FD_THREADS), lds, s, items_dev, bases);
+  if (nt && obl)
+    hipLaunchKernelGGL((batch_step_kernel<true, true>), grid, dim3(FD_THREADS), lds, s, items_dev, bases);
+  else if (nt)
+    hipLaunchKernelGGL((batch_step_kernel<true, false>), grid, dim3(FD_THREADS), lds, s, items_dev, bases);
+  else if (obl)
+    hipLaunchKernelGGL((batch_step_kernel<false, true>), grid, dim3(FD_THREADS), lds, s, items_dev, bases);
   else
-    hipLaunchKernelGGL((batch_step_kernel<false>), grid, dim3(FD_THREADS), lds, s, items_dev, bases);
+    hipLaunchKernelGGL((batch_step_kernel<false, false>), grid, dim3(FD_THREADS), lds, s, items_dev, bases);
 }
 
 size_t stencil_lds(const FemArgs& a) {
@@ -1001,10 +1030,15 @@ static int grid_for(int64_t n, int block = 256, int cap = 4096) {
 template <bool NT>
 static void launch_fd_t(const FdArgs& a, hipStream_t s, bool energy) {
   const int grid = a.per_xcd * N_XCD;
-  if (energy)
-    hipLaunchKernelGGL((fd_step_kernel<true, NT>), dim3(grid), dim3(FD_THREADS), 0, s, a);
+  const bool obl = a.pw_kind != 0;
+  if (energy && obl)
+    hipLaunchKernelGGL((fd_step_kernel<true, NT, true>), dim3(grid), dim3(FD_THREADS), 0, s, a);
+  else if (energy)
+    hipLaunchKernelGGL((fd_step_kernel<true, NT, false>), dim3(grid), dim3(FD_THREADS), 0, s, a);
+  else if (obl)
+    hipLaunchKernelGGL((fd_step_kernel<false, NT, true>), dim3(grid), dim3(FD_THREADS), 0, s, a);
   else
-    hipLaunchKernelGGL((fd_step_kernel<false, NT>), dim3(grid), dim3(FD_THREADS), 0, s, a);
+    hipLaunchKernelGGL((fd_step_kernel<false, NT, false>), dim3(grid), dim3(FD_THREADS), 0, s, a);
 }
 
 void launch_fd(const FdArgs& a, hipStream_t s, bool energy, bool nt) {
@@ -1093,6 +1127,12 @@ static void launch_step_t(const FdArgs& fa, const FemArgs& ea, hipStream_t s, bo
     if (adj)
       hipLaunchKernelGGL((step_kernel_r2<true, false, NT>), grid_r2, dim3(FD_THREADS), lds_r2, s, fa, ea, fem_blocks, g,
                          pg_blocks);
+    else if (fa.pw_kind && energy)
+      hipLaunchKernelGGL((step_kernel_r2<false, true, NT, true>), grid_r2, dim3(FD_THREADS), lds_r2, s, fa, ea,
+                         fem_blocks, g, 0);
+    else if (fa.pw_kind)
+      hipLaunchKernelGGL((step_kernel_r2<false, false, NT, true>), grid_r2, dim3(FD_THREADS), lds_r2, s, fa, ea,
+                         fem_blocks, g, 0);
     else if (energy)
       hipLaunchKernelGGL((step_kernel_r2<false, true, NT>), grid_r2, dim3(FD_THREADS), lds_r2, s, fa, ea, fem_blocks,
                          g, 0);
@@ -1105,6 +1145,10 @@ static void launch_step_t(const FdArgs& fa, const FemArgs& ea, hipStream_t s, bo
                        std::max(lds, PG_LDS_BYTES), s, fa, ea, fem_blocks, *pg, pg_blocks);
   } else if (adj)
     hipLaunchKernelGGL((step_kernel<true, false, NT>), grid, dim3(FD_THREADS), lds, s, fa, ea, fem_blocks);
+  else if (fa.pw_kind && energy)
+    hipLaunchKernelGGL((step_kernel<false, true, NT, true>), grid, dim3(FD_THREADS), lds, s, fa, ea, fem_blocks);
+  else if (fa.pw_kind)
+    hipLaunchKernelGGL((step_kernel<false, false, NT, true>), grid, dim3(FD_THREADS), lds, s, fa, ea, fem_blocks);
   else if (energy)
     hipLaunchKernelGGL((step_kernel<false, true, NT>), grid, dim3(FD_THREADS), lds, s, fa, ea, fem_blocks);
   else

@@ -125,6 +125,32 @@ def gauss_sine(omega, amp=1.0, pol=(0.0, 1.0, 0.0)):
     return Source(kind=SRC_GAUSS_SINE, omega=omega, t0=1.5 * tp, width=0.5 * tp, amp=amp, pol=pol)
 
 
+def oblique_wave(omega, theta, phi, psi=0.0, amp=1.0):
+    """Gaussian-modulated sine plane wave travelling along k = (sin theta cos phi, sin theta sin phi,
+    -cos theta) (theta from the downward normal of the top face), polarised perpendicular to k
+    at the angle psi from the incidence plane."""
+    k = np.array([math.sin(theta) * math.cos(phi), math.sin(theta) * math.sin(phi), -math.cos(theta)])
+    e_perp = np.array([-math.sin(phi), math.cos(phi), 0.0])        # perpendicular to the incidence plane
+    e_par = np.cross(e_perp, k)                                     # in the incidence plane, perpendicular to k
+    pol = math.cos(psi) * e_par + math.sin(psi) * e_perp
+    src = gauss_sine(omega, amp=amp, pol=tuple(float(v) for v in pol))
+    src.dir = tuple(float(v) for v in k)
+    return src
+
+
+def plane_wave_switch(desc: ProblemDesc, src: Source) -> float:
+    """Top-face switch time that keeps a plane-wave source on until it has crossed the whole face:
+    the pulse's support plus the largest arrival delay over the top face."""
+    v = np.asarray(src.dir, dtype=np.float64)
+    nv = float(np.linalg.norm(v))
+    tau = 0.0
+    if nv > 0:
+        k = v / nv
+        span = desc.h * (np.asarray(desc.n_outer[:2], dtype=np.float64) - 1.0)
+        tau = float(abs(k[0]) * span[0] + abs(k[1]) * span[1])
+    return src.support_end() + tau
+
+
 def fem_layers(desc: ProblemDesc) -> np.ndarray:
     """Layer index of every FEM node (lexicographic, x fastest)."""
     nx, ny, nz = desc.fem_shape()
@@ -334,8 +360,10 @@ def small(name: str, seed_offset: int = 0) -> Workload:
 
 def batch_mix(n_problems=16, seed=SEED_BASE + 4, ckpt_every=64):
     """Uneven multi-problem mix: outer 96..224 nodes, FEM 32..96 cells (valid pairs), 1000-2500
-    steps, layered-skin media; even problems get a plane wave of seeded polarisation, odd ones
-    a point dipole of seeded moment 4 nodes above the FEM box."""
+    steps, layered-skin media; even problems get a plane wave of seeded incidence (theta ~
+    U[0, 30] degrees from the downward normal, phi ~ U[0, 360)) polarised perpendicular to its
+    direction, the top face switching once it has crossed the face; odd ones a point dipole of
+    seeded moment 4 nodes above the FEM box."""
     rng = np.random.Generator(np.random.PCG64(seed))
     out = []
     for p in range(n_problems):
@@ -351,7 +379,9 @@ def batch_mix(n_problems=16, seed=SEED_BASE + 4, ckpt_every=64):
         v = rng.normal(size=3)
         v = tuple(v / np.linalg.norm(v))
         if p % 2 == 0:
-            src = gauss_sine(base.omega, pol=(v[0], v[1], 0.0))
+            theta, phi, psi = rng.uniform(0.0, math.pi / 6), rng.uniform(0.0, 2 * math.pi), rng.uniform(0, math.pi)
+            src = oblique_wave(base.omega, theta, phi, psi)
+            desc.t_switch = plane_wave_switch(desc, src)
         else:
             src = Source(kind=SRC_DIPOLE, omega=base.omega, t0=base.t0, width=base.width, pol=v,
                          pos=(no // 2, no // 2, desc.fem_lo[2] + nf + 4))
