@@ -167,6 +167,15 @@ size_t dd_footprint_bytes(const dd_problem_desc* desc, int32_t n_src);
  * previous coefficients stay.  Synchronises `stream`. */
 int dd_set_coefficients(dd_problem* p, const float* eps_dev, const float* sigma_dev, void* stream);
 
+/* dd_set_coefficients without the wait: the check of eq. epsilon_sigma_constraint runs on the
+ * device, and the coefficients are applied only if it passes (else the previous ones stay);
+ * nothing is read back, so the call only queues work on `stream`.  dd_coefficients_status
+ * (synchronises `stream`) gives DD_ERR_CONSTRAINT if the last dd_set_coefficients_async was
+ * refused, else DD_OK.  For callers whose coefficients are valid by construction (e.g. the
+ * iterate of dd_cga_update, kept in the coefficient box) and who must not wait. */
+int dd_set_coefficients_async(dd_problem* p, const float* eps_dev, const float* sigma_dev, void* stream);
+int dd_coefficients_status(dd_problem* p, void* stream);
+
 /* Forward solve of each source from rest (E = E_t = 0 at t = 0), or from the initial data
  * set by dd_set_initial_data.
  * traces_dev: [n_src][n_steps][n_det][3] float32 output.
@@ -344,6 +353,13 @@ typedef struct {
 int dd_cga_create(dd_problem* p, const dd_cga_params* prm, const float* eps0_dev, const float* sig0_dev, void* stream,
                   dd_cga** out);
 int dd_cga_destroy(dd_cga* c);
+/* Step sizes of a run from the gradient of J at the initial guess, on the device (no host
+ * read): with G = max over the free nodes of |dJ/dc_i| / h^3 (at least 1e-30), per field,
+ * gamma^0 = gamma^m = G / step and alpha^m = step / G, so that the first update moves eps by at
+ * most step_eps and sigma by at most step_sig.  Call before the first dd_cga_update; replaces
+ * those values of the parameters given to dd_cga_create.  Asynchronous. */
+int dd_cga_steps_from_gradient(dd_cga* c, const double* g_eps_dev, const double* g_sigma_dev, double step_eps,
+                               double step_sig, void* stream);
 /* Steps 2-6: g_eps_dev, g_sigma_dev are dd_gradient's output at (eps^m, sigma^m);
  * eps_dev, sigma_dev hold eps^m, sigma^m on entry and eps^{m+1}, sigma^{m+1} when the
  * queued work is done (nodes of layers 0 and 1 are not written).  Asynchronous. */

@@ -19,7 +19,8 @@ EXPORTS = [
     "dd_batch_create", "dd_batch_destroy", "dd_batch_submit", "dd_batch_step", "dd_batch_poll",
     "dd_adjoint_misfit", "dd_cga_create", "dd_cga_destroy", "dd_cga_update", "dd_cga_get_info",
     "dd_paper_gradient_enable", "dd_gradient_paper", "dd_misfit", "dd_set_divdiv_form", "dd_set_initial_data", "dd_check_finite", "dd_batch_set_fill",
-    "dd_misfit_noalloc", "dd_misfit_taper",
+    "dd_misfit_noalloc", "dd_misfit_taper", "dd_set_coefficients_async", "dd_coefficients_status",
+    "dd_cga_steps_from_gradient",
 ]
 
 PROF_FD_FWD, PROF_FEM_FWD, PROF_FD_ADJ, PROF_FEM_ADJ, PROF_FEM_RECOMPUTE, PROF_STEP_FWD, PROF_STEP_ADJ = range(7)
@@ -114,6 +115,9 @@ def load():
     lib.dd_footprint_bytes.argtypes = [ctypes.POINTER(ProblemDesc), ctypes.c_int32]
     lib.dd_footprint_bytes.restype = ctypes.c_size_t
     lib.dd_set_coefficients.argtypes = [P, P, P, P]
+    lib.dd_set_coefficients_async.argtypes = [P, P, P, P]
+    lib.dd_coefficients_status.argtypes = [P, P]
+    lib.dd_cga_steps_from_gradient.argtypes = [P, P, P, ctypes.c_double, ctypes.c_double, P]
     lib.dd_forward.argtypes = [P, ctypes.POINTER(Source), ctypes.c_int32, P, ctypes.c_int32, P, P]
     lib.dd_adjoint.argtypes = [P, P, P]
     lib.dd_gradient.argtypes = [P, P, P, ctypes.POINTER(Tikhonov), P]

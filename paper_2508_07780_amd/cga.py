@@ -117,6 +117,16 @@ class CGA:
             p.adjoint(self.cot)
         p.gradient(out=(self.g_eps, self.g_sig))
 
+    def steps_from_gradient(self, g_eps, g_sig, step_eps=0.5, step_sig=0.1):
+        """gamma^0 and alpha^0 from the gradient of J at the initial guess, on the device (the
+        first update moves eps by at most step_eps and sigma by at most step_sig); before the
+        first update."""
+        for t in (g_eps, g_sig):
+            if not (t.is_cuda and t.dtype == torch.float64 and t.is_contiguous() and t.numel() == self.problem.n_fem):
+                raise ValueError("gradients must be contiguous float64 CUDA tensors of n_fem entries")
+        _lib.check(_lib.load().dd_cga_steps_from_gradient(self._h, _ptr(g_eps), _ptr(g_sig), float(step_eps),
+                                                          float(step_sig), _stream()))
+
     def update(self, g_eps=None, g_sig=None):
         """Steps 2-6 from the gradient of the last solve, or from the given gradient arrays
         of J at the current iterate (float64, FEM nodes); asynchronous."""

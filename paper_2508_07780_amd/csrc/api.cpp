@@ -740,7 +740,7 @@ size_t dd_footprint_bytes(const dd_problem_desc* desc, int32_t n_src) {
   b += 4 * 6 * N;                         // E (2 levels) on the grid
   b += 4 * 9 * n_own;                     // E (2 levels) + V on the FEM nodes
   b += 4 * 6 * n_l0;                      // interface ring
-  b += 8 * ((int64_t)ntiles + n_part) + 4 + 8 * 2 * n_own;   // energy partials, error flag, gradients
+  b += 8 * ((int64_t)ntiles + n_part) + 8 + 8 * 2 * n_own;   // energy partials, error flags, gradients
   b += (int64_t)n_src * ((nt + 1) * 3 * n_l0 * 4 + (n_ck + tail_levels) * 6 * n_own * 4);  // saved forward
   if (nseg > 1) b += (K + 1) * 6 * n_own * 4;  // recompute window
   if (nseg > 2) b += (K + 1) * 6 * n_own * 4;  // the second one (two segments in flight)
@@ -834,7 +834,7 @@ int dd_create(const dd_problem_desc* desc, dd_alloc_fn alloc_fn, dd_free_fn free
   chk(dalloc(p, &p->Vfem, 3 * p->n_own));
   chk(dalloc(p, &p->iring, 6 * p->n_l0));
   chk(dalloc(p, &p->epart, p->n_tiles + p->n_part));
-  chk(dalloc(p, &p->d_err, 1));
+  chk(dalloc(p, &p->d_err, 2));   // [0]: synchronous checks, [1]: the last dd_set_coefficients_async
   chk(dalloc(p, &p->g_eps, p->n_own));
   chk(dalloc(p, &p->g_sig, p->n_own));
   if (!rc && (hipStreamCreateWithFlags(&p->aux, hipStreamNonBlocking) != hipSuccess ||
@@ -851,8 +851,10 @@ int dd_create(const dd_problem_desc* desc, dd_alloc_fn alloc_fn, dd_free_fn free
   // eps = 1, sigma = 0 until dd_set_coefficients
   std::vector<float> em1(p->n_own, 0.f), c1(p->n_own, 1.f), c2(p->n_own);
   for (int64_t i = 0; i < p->n_own; ++i) c2[i] = (float)(desc->dt * desc->dt / m.mass[i]);
+  const int zeros[2] = {0, 0};
   if (hipMemcpy(p->em1, em1.data(), 4 * p->n_own, hipMemcpyHostToDevice) != hipSuccess ||
       hipMemcpy(p->sig_own, em1.data(), 4 * p->n_own, hipMemcpyHostToDevice) != hipSuccess ||
+      hipMemcpy(p->d_err, zeros, sizeof(zeros), hipMemcpyHostToDevice) != hipSuccess ||
       hipMemcpy(p->c1, c1.data(), 4 * p->n_own, hipMemcpyHostToDevice) != hipSuccess ||
       hipMemcpy(p->c2, c2.data(), 4 * p->n_own, hipMemcpyHostToDevice) != hipSuccess) {
     dd_destroy(p);
@@ -901,12 +903,38 @@ int dd_set_coefficients(dd_problem* p, const float* eps_dev, const float* sigma_
     return fail(p, DD_ERR_HIP, "error readback failed");
   if (h_err) return fail(p, DD_ERR_CONSTRAINT, std::to_string(h_err) + " FEM nodes violate the coefficient constraint");
   launch_coefficients(eps_dev, sigma_dev, p->own_api, p->mass_d, p->n_own, p->d.dt, p->em1, p->c1, p->c2, p->sig_own,
-                      st);
+                      nullptr, st);
   if (int rc = check_launch(p)) return rc;
   if (hipStreamSynchronize(st) != hipSuccess) return fail(p, DD_ERR_HIP, "stream synchronize failed");
   p->saved = false;
   p->have_grad = false;
   p->have_pg = false;
+  return DD_OK;
+}
+
+int dd_set_coefficients_async(dd_problem* p, const float* eps_dev, const float* sigma_dev, void* stream) {
+  if (!p) return DD_ERR_INVALID_ARG;
+  if (!eps_dev || !sigma_dev) return fail(p, DD_ERR_INVALID_ARG, "null coefficient pointer");
+  hipStream_t st = (hipStream_t)stream;
+  int* flag = p->d_err + 1;
+  launch_fill_i32(flag, 1, 0, st);
+  launch_validate(eps_dev, sigma_dev, p->fs[0], p->fs[1], p->fs[2], flag, st);
+  launch_coefficients(eps_dev, sigma_dev, p->own_api, p->mass_d, p->n_own, p->d.dt, p->em1, p->c1, p->c2, p->sig_own,
+                      flag, st);
+  if (int rc = check_launch(p)) return rc;
+  p->saved = false;
+  p->have_grad = false;
+  p->have_pg = false;
+  return DD_OK;
+}
+
+int dd_coefficients_status(dd_problem* p, void* stream) {
+  if (!p) return DD_ERR_INVALID_ARG;
+  int h = 0;
+  if (hipMemcpyAsync(&h, p->d_err + 1, sizeof(int), hipMemcpyDeviceToHost, (hipStream_t)stream) != hipSuccess ||
+      hipStreamSynchronize((hipStream_t)stream) != hipSuccess)
+    return fail(p, DD_ERR_HIP, "status readback failed");
+  if (h) return fail(p, DD_ERR_CONSTRAINT, std::to_string(h) + " FEM nodes violated the coefficient constraint");
   return DD_OK;
 }
 
@@ -1284,6 +1312,15 @@ int dd_cga_create(dd_problem* p, const dd_cga_params* prm, const float* eps0_dev
   }
   *out = c;
   return DD_OK;
+}
+
+int dd_cga_steps_from_gradient(dd_cga* c, const double* g_eps_dev, const double* g_sigma_dev, double step_eps,
+                               double step_sig, void* stream) {
+  if (!c || !g_eps_dev || !g_sigma_dev || !(step_eps > 0.0) || !(step_sig > 0.0) || !std::isfinite(step_eps) ||
+      !std::isfinite(step_sig))
+    return DD_ERR_INVALID_ARG;
+  launch_cga_steps(g_eps_dev, g_sigma_dev, c->fs, step_eps, step_sig, c->st, c->part, (hipStream_t)stream);
+  return hipGetLastError() == hipSuccess ? DD_OK : DD_ERR_HIP;
 }
 
 int dd_cga_destroy(dd_cga* c) {

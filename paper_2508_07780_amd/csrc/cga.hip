@@ -230,7 +230,76 @@ __global__ void cga_upper_check_kernel(const float* __restrict__ eps, const floa
     if (!((double)eps[i] <= eps_max) || !((double)sig[i] <= sig_max)) atomicAdd(err, 1);
 }
 
+// Step sizes from the gradient of J at the initial guess: per block, the largest |dJ/dc| over
+// the free nodes of eps and of sigma.
+__global__ __launch_bounds__(CGA_THREADS) void cga_gmax_kernel(const double* __restrict__ gJe,
+                                                               const double* __restrict__ gJs, int fsx, int fsy,
+                                                               int fsz, double* __restrict__ part) {
+  __shared__ double red[2][CGA_THREADS];
+  const int64_t n = (int64_t)fsx * fsy * fsz;
+  double m[2] = {0.0, 0.0};
+  for (int64_t i = (int64_t)blockIdx.x * CGA_THREADS + threadIdx.x; i < n; i += (int64_t)gridDim.x * CGA_THREADS) {
+    if (!cga_free(i, fsx, fsy, fsz)) continue;
+    m[0] = fmax(m[0], fabs(gJe[i]));
+    m[1] = fmax(m[1], fabs(gJs[i]));
+  }
+  const int t = threadIdx.x;
+  red[0][t] = m[0];
+  red[1][t] = m[1];
+  __syncthreads();
+  for (int w = CGA_THREADS / 2; w > 0; w >>= 1) {
+    if (t < w) {
+      red[0][t] = fmax(red[0][t], red[0][t + w]);
+      red[1][t] = fmax(red[1][t], red[1][t + w]);
+    }
+    __syncthreads();
+  }
+  if (t == 0) {
+    part[2 * (int64_t)blockIdx.x] = red[0][0];
+    part[2 * (int64_t)blockIdx.x + 1] = red[1][0];
+  }
+}
+
+// gamma^0 = gamma^m = G / step and alpha^m = step / G per field, G = max(max|dJ/dc| / w, 1e-30)
+// (w: the lumped mass of a free node): the first update then moves the field by at most `step`.
+__global__ __launch_bounds__(CGA_THREADS) void cga_steps_finish_kernel(const double* __restrict__ part, int nb,
+                                                                       double step_e, double step_s,
+                                                                       CgaDev* __restrict__ st) {
+  __shared__ double red[2][CGA_THREADS];
+  const int t = threadIdx.x;
+  double m[2] = {0.0, 0.0};
+  for (int b = t; b < nb; b += CGA_THREADS) {
+    m[0] = fmax(m[0], part[2 * (int64_t)b]);
+    m[1] = fmax(m[1], part[2 * (int64_t)b + 1]);
+  }
+  red[0][t] = m[0];
+  red[1][t] = m[1];
+  __syncthreads();
+  for (int w = CGA_THREADS / 2; w > 0; w >>= 1) {
+    if (t < w) {
+      red[0][t] = fmax(red[0][t], red[0][t + w]);
+      red[1][t] = fmax(red[1][t], red[1][t + w]);
+    }
+    __syncthreads();
+  }
+  if (t == 0) {
+    const double step[2] = {step_e, step_s};
+    for (int f = 0; f < 2; ++f) {
+      const double g = fmax(red[f][0] / st->w, 1e-30);
+      st->gamma0[f] = st->gamma[f] = g / step[f];
+      st->alpha[f] = step[f] / g;
+    }
+  }
+}
+
 }  // namespace
+
+void launch_cga_steps(const double* gJe, const double* gJs, const int fs[3], double step_eps, double step_sig,
+                      CgaDev* st, double* part, hipStream_t s) {
+  const int nb = cga_blocks((int64_t)fs[0] * fs[1] * fs[2]);
+  hipLaunchKernelGGL(cga_gmax_kernel, dim3(nb), dim3(CGA_THREADS), 0, s, gJe, gJs, fs[0], fs[1], fs[2], part);
+  hipLaunchKernelGGL(cga_steps_finish_kernel, dim3(1), dim3(CGA_THREADS), 0, s, part, nb, step_eps, step_sig, st);
+}
 
 int cga_blocks(int64_t n_fem) {
   const int64_t b = (n_fem + CGA_THREADS - 1) / CGA_THREADS;

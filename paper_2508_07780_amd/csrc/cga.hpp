@@ -25,6 +25,10 @@ int cga_blocks(int64_t n_fem);
 void launch_cga_update(const double* gJe, const double* gJs, float* eps, float* sig, const float* eps0,
                        const float* sig0, double* d_eps, double* d_sig, const int fs[3], CgaDev* st,
                        double* part, hipStream_t s);
+// gamma^0 = gamma^m = G / step and alpha^m = step / G for eps and sigma, G = max|dJ/dc| / h^3 over
+// the free nodes (two launches; part holds CGA_MAX_BLOCKS x 2 doubles).
+void launch_cga_steps(const double* gJe, const double* gJs, const int fs[3], double step_eps, double step_sig,
+                      CgaDev* st, double* part, hipStream_t s);
 // Counts FEM nodes with eps > eps_max or sigma > sig_max into *err.
 void launch_cga_upper_check(const float* eps, const float* sig, int64_t n, double eps_max, double sig_max, int* err,
                             hipStream_t s);

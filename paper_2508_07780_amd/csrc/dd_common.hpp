@@ -216,7 +216,9 @@ void launch_fill_f64(double* p, int64_t n, double v, hipStream_t s);
 void launch_copy_f32(float* dst, const float* src, int64_t n, hipStream_t s);
 void launch_validate(const float* eps, const float* sig, int fsx, int fsy, int fsz, int* err, hipStream_t s);
 void launch_coefficients(const float* eps, const float* sig, const int* own_api, const double* mass_d,
-                         int64_t n_own, double dt, float* em1, float* c1, float* c2, float* sig_own, hipStream_t s);
+                         int64_t n_own, double dt, float* em1, float* c1, float* c2, float* sig_own,
+                         const int* guard, hipStream_t s);
+void launch_fill_i32(int* p, int n, int v, hipStream_t s);
 void launch_tikhonov_add(const float* em1, const float* sig_own, const int* own_api, const int* own_grid,
                          const double* mass_d, int64_t n_own, double gamma_eps, double gamma_sig, const float* eps0,
                          const float* sig0, double* g_eps, double* g_sig, hipStream_t s);

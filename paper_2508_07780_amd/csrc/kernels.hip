@@ -976,8 +976,12 @@ __global__ void validate_kernel(const float* eps, const float* sig, int fsx, int
   }
 }
 
+// guard (nullable): the validation count of these coefficients; nothing is written when it is
+// nonzero (the previous coefficients stay)
 __global__ void coefficients_kernel(const float* eps, const float* sig, const int* own_api, const double* mass,
-                                    int64_t n_own, double dt, float* em1, float* c1, float* c2, float* sig_own) {
+                                    int64_t n_own, double dt, float* em1, float* c1, float* c2, float* sig_own,
+                                    const int* guard) {
+  if (guard && *guard) return;
   for (int64_t id = (int64_t)blockIdx.x * blockDim.x + threadIdx.x; id < n_own; id += (int64_t)gridDim.x * blockDim.x) {
     const int api = own_api[id];
     const double e = (double)eps[api], s = (double)sig[api], m = mass[id];
@@ -1185,9 +1189,17 @@ void launch_validate(const float* eps, const float* sig, int fsx, int fsy, int f
 }
 
 void launch_coefficients(const float* eps, const float* sig, const int* own_api, const double* mass_d, int64_t n_own,
-                         double dt, float* em1, float* c1, float* c2, float* sig_own, hipStream_t s) {
+                         double dt, float* em1, float* c1, float* c2, float* sig_own, const int* guard, hipStream_t s) {
   hipLaunchKernelGGL(coefficients_kernel, dim3(grid_for(n_own)), dim3(256), 0, s, eps, sig, own_api, mass_d, n_own, dt,
-                     em1, c1, c2, sig_own);
+                     em1, c1, c2, sig_own, guard);
+}
+
+__global__ void fill_i32_kernel(int* p, int n, int v) {
+  for (int i = threadIdx.x; i < n; i += blockDim.x) p[i] = v;
+}
+
+void launch_fill_i32(int* p, int n, int v, hipStream_t s) {
+  if (n > 0) hipLaunchKernelGGL(fill_i32_kernel, dim3(1), dim3(64), 0, s, p, n, v);
 }
 
 void launch_tikhonov_add(const float* em1, const float* sig_own, const int* own_api, const int* own_grid,

@@ -117,11 +117,20 @@ class Problem:
                                          n.value, ctypes.byref(n)))
         return out
 
-    def set_coefficients(self, eps, sigma):
+    def set_coefficients(self, eps, sigma, wait=True):
+        """eps, sigma on the FEM nodes.  wait=False: checked and applied on the device without a
+        host round trip (refused coefficients leave the previous ones; coefficients_status tells)."""
         e = _device_f32(eps, self.n_fem, "eps")
         s = _device_f32(sigma, self.n_fem, "sigma")
         self.generation += 1
-        _lib.check(_lib.load().dd_set_coefficients(self._h, _ptr(e), _ptr(s), _stream()), self._h)
+        fn = _lib.load().dd_set_coefficients if wait else _lib.load().dd_set_coefficients_async
+        _lib.check(fn(self._h, _ptr(e), _ptr(s), _stream()), self._h)
+        if not wait:
+            self._coef_keep = (e, s)        # alive until the queued kernels have read them
+
+    def coefficients_status(self):
+        """Raise DDError (DD_ERR_CONSTRAINT) if the last set_coefficients(wait=False) was refused."""
+        _lib.check(_lib.load().dd_coefficients_status(self._h, _stream()), self._h)
 
     def forward(self, sources, save=True, energy=False, out=None):
         srcs = _lib.make_sources(sources)

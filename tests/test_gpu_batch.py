@@ -192,3 +192,79 @@ def test_batch_and_serving_refusals():
     small = min(serving.job_footprint(r) for r in reqs) // 2
     with pytest.raises(ValueError):
         serving.serve_batched(reqs, max_slots=2, hbm_budget=small, chunk=16)
+
+
+def _small_requests(n, seed_shift=0):
+    return synth.serving_requests(n, 20.0, seed=synth.configs.SEED_BASE + 5 + seed_shift, outer=(40, 48),
+                                  fem=(16, 24), sources=(1, 2), steps=(40, 70), iterations=(2, 3))
+
+
+def test_serving_failures_release_budget_and_requeue_or_reject(monkeypatch):
+    """Failures injected on the host (no device fault): a submit that fails once is queued again
+    and completes; a job whose submit always fails is rejected after its retry; a batch step that
+    fails sends every job of the batch back to the queue.  Every byte of the budget comes back and
+    the other jobs finish."""
+    from paper_2508_07780_amd import DDError, serving
+    from paper_2508_07780_amd.batch import Batch
+    reqs = _small_requests(6)
+    doomed, flaky = reqs[1].workload.desc, reqs[3].workload.desc
+    calls = {"flaky": 0, "step": 0}
+    real_submit, real_step = Batch.submit, Batch.step
+
+    def submit(self, problem, sources, obs=None, gradient=True):
+        if problem.desc is doomed:
+            raise DDError(-4, "injected")
+        if problem.desc is flaky and calls["flaky"] == 0:
+            calls["flaky"] += 1
+            raise DDError(-4, "injected once")
+        return real_submit(self, problem, sources, obs=obs, gradient=gradient)
+
+    def step(self, max_steps):
+        calls["step"] += 1
+        if calls["step"] == 3:
+            raise DDError(-5, "injected step failure")
+        return real_step(self, max_steps)
+
+    monkeypatch.setattr(Batch, "submit", submit)
+    monkeypatch.setattr(Batch, "step", step)
+    s, rec = serving.serve_batched(reqs, max_slots=4, chunk=16, solo_cells=None)
+    print(f"[gpu] serving with injected failures: {s}", flush=True)
+    assert s["rejected"] == 1 and s["jobs"] == len(reqs) - 1
+    assert s["in_use_end_bytes"] == 0
+    done = {r["rid"] for r in rec if not r.get("rejected")}
+    assert reqs[1].rid not in done and reqs[3].rid in done
+    assert s["solves"] == sum(r.iterations for r in reqs if r.rid != reqs[1].rid)
+
+
+def test_served_job_matches_the_oracle_cga():
+    """One request through the batched server: its reconstruction after its iterations equals the
+    oracle's CGA from the same start, data and step-size rule (step sizes from the first gradient:
+    the first update moves eps by at most 0.5 and sigma by at most 0.1)."""
+    import torch
+    from oracle.cga import cga, solve_gradient
+    from paper_2508_07780_amd import serving
+    w = synth.small("tiny")
+    w.desc.n_steps = 60
+    h3 = w.desc.h ** 3
+    d = Discretization(w.desc).set_coefficients(w.eps.astype(np.float32).astype(np.float64),
+                                                w.sigma.astype(np.float32).astype(np.float64))
+    eobs = forward(d, w.sources[0])["traces"][None].astype(np.float32)      # data of the true medium
+    n = w.desc.n_fem_nodes()
+    start = synth.Workload("served", w.desc, np.ones(n), np.zeros(n), w.sources, 7, extra={"obs": eobs})
+    req = synth.Request(0, 0.0, start, 2)
+    s, rec = serving.serve_batched([req], max_slots=2, chunk=16, keep=True, solo_cells=None)
+    torch.cuda.synchronize()
+    assert s["jobs"] == 1
+    do = Discretization(w.desc)
+    grad_fn = solve_gradient(do, w.sources, eobs.astype(np.float64))
+    ge, gs, _ = grad_fn(np.ones(n), np.zeros(n))
+    G = [max(np.abs(g).max() / h3, 1e-30) for g in (ge, gs)]
+    prm = dict(gamma_eps=G[0] / 0.5, gamma_sig=G[1] / 0.1, p=0.5, alpha_eps=0.5 / G[0], alpha_sig=0.1 / G[1],
+               eps_max=20.0, sig_max=3.0)
+    hist = cga(do, w.sources, eobs.astype(np.float64), np.ones(n), np.zeros(n), prm, 2)
+    for f, key, base in (("eps", "eps", 1.0), ("sig", "sigma", 0.0)):
+        ref = hist[-1][f]["coef"] - base
+        got = rec[0][key].double().cpu().numpy() - base
+        e = float(np.linalg.norm(got - ref) / np.linalg.norm(ref))
+        print(f"[gpu] served job vs oracle CGA, {f}: change rel L2 {e:.2e}", flush=True)
+        assert e <= 2e-3
