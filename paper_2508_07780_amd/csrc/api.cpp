@@ -779,7 +779,10 @@ int dd_create(const dd_problem_desc* desc, dd_alloc_fn alloc_fn, dd_free_fn free
     int x = 0, y = 0, z = 0;
     if (std::sscanf(e, "%d,%d,%d", &x, &y, &z) == 3) { pb[0] = x; pb[1] = y; pb[2] = z; }
   }
-  const std::string me = build_mesh(*desc, m, pb);
+  bool element_path = false;   // the element-coloured FEM kernel instead of the assembled stencil
+  if (const char* e = std::getenv("DD_FEM_PATH"))
+    if (std::strcmp(e, "element") == 0) element_path = true;
+  const std::string me = build_mesh(*desc, m, pb, element_path);
   if (!me.empty()) {
     delete p;
     return DD_ERR_UNSUPPORTED;
@@ -794,9 +797,11 @@ int dd_create(const dd_problem_desc* desc, dd_alloc_fn alloc_fn, dd_free_fn free
   p->lds_elem = (m.max_elem + 1) & ~1;
   p->lds_box = m.max_box;
   p->n_slots = m.n_slots;
-  p->use_stencil = m.stencil_ok && m.n_slots <= STENCIL_SLOTS_MAX;
-  if (const char* e = std::getenv("DD_FEM_PATH"))
-    if (std::strcmp(e, "element") == 0) p->use_stencil = false;
+  p->use_stencil = m.stencil_ok && m.n_slots <= STENCIL_SLOTS_MAX && !element_path;
+  if (!p->use_stencil && !element_path) {
+    delete p;
+    return DD_ERR_UNSUPPORTED;
+  }
   p->fd_nt = fd_field_bytes(p) > LLC_BYTES;
   if (const char* e = std::getenv("DD_FD_NT")) p->fd_nt = std::atoi(e) != 0;
   fd_tile_grid(p->nx, p->ny, p->nz, p->fd_nt, p->nbx, p->nby, p->nbz, p->n_tiles, p->per_xcd);

@@ -249,8 +249,10 @@ struct HostMesh {
   std::vector<float> slot_b;    // [n_slots][9], row-major 3x3
 };
 
-// Builds the Kuhn split of the FEM box, the node partitions and per-partition colouring.
-// Returns an empty string on success, else the error text.
-std::string build_mesh(const dd_problem_desc& d, HostMesh& m, const int pb[3]);
+// Builds the Kuhn split of the FEM box: node partitions, the assembled stencil, masses and
+// the staging boxes of the stencil kernel, and with `elements` the element kernel's data
+// (per-partition elements, halos and colouring).  Returns an empty string on success, else
+// the error text.
+std::string build_mesh(const dd_problem_desc& d, HostMesh& m, const int pb[3], bool elements);
 
 }  // namespace dd

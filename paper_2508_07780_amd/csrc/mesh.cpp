@@ -71,7 +71,7 @@ bool tet_geometry(const double p[4][3], double grad[4][3], double* vol) {
 
 }  // namespace
 
-std::string build_mesh(const dd_problem_desc& d, HostMesh& m, const int pb[3]) {
+std::string build_mesh(const dd_problem_desc& d, HostMesh& m, const int pb[3], bool elements) {
   Lattice L;
   for (int a = 0; a < 3; ++a) {
     L.c[a] = d.fem_cells[a];
@@ -149,8 +149,64 @@ std::string build_mesh(const dd_problem_desc& d, HostMesh& m, const int pb[3]) {
     return id;
   };
 
-  // lumped mass of owned nodes: sum over incident tetrahedra of |K| / 4 (FP64)
-  m.mass.assign(m.n_own, 0.0);
+  // Every tetrahedron of the Kuhn split is a translate of one of six shapes (one per axis
+  // permutation), so its geometry id, gradients and volume are computed once per shape.
+  int shape_gid[6];
+  double shape_g[6][4][3], shape_vol[6];
+  int shape_v[6][4][3];
+  for (int q = 0; q < 6; ++q) {
+    for (int a = 0; a < 3; ++a) shape_v[q][0][a] = 0;
+    for (int k = 1; k < 4; ++k) {
+      for (int a = 0; a < 3; ++a) shape_v[q][k][a] = shape_v[q][k - 1][a];
+      shape_v[q][k][kPerms[q][k - 1]] += 1;
+    }
+    shape_gid[q] = geom_id(shape_v[q]);
+    if (shape_gid[q] < 0) return "degenerate tetrahedron";
+    double p4[4][3];
+    for (int j = 0; j < 4; ++j)
+      for (int a = 0; a < 3; ++a) p4[j][a] = d.h * (double)shape_v[q][j][a];
+    tet_geometry(p4, shape_g[q], &shape_vol[q]);
+  }
+
+  // Every owned node (layer >= 1) has all 8 cells around it in the box, so its element star is
+  // a translate of one star of 24 tetrahedra: its lumped mass (the sum of |K| / 4) and its
+  // assembled stencil of 3x3 blocks, 27 lattice offsets x (K_ij, B_ij), are those of that star,
+  // accumulated in FP64 (cells z, y, x, then shape, as everywhere else).
+  double star[27][10] = {};
+  double star_mass = 0.0;
+  for (int cz = -1; cz <= 0; ++cz)
+    for (int cy = -1; cy <= 0; ++cy)
+      for (int cx = -1; cx <= 0; ++cx)
+        for (int q = 0; q < 6; ++q) {
+          int v[4][3];
+          int k = -1;
+          for (int j = 0; j < 4; ++j) {
+            v[j][0] = cx + shape_v[q][j][0];
+            v[j][1] = cy + shape_v[q][j][1];
+            v[j][2] = cz + shape_v[q][j][2];
+            if (v[j][0] == 0 && v[j][1] == 0 && v[j][2] == 0) k = j;
+          }
+          if (k < 0) continue;
+          const double(&g4)[4][3] = shape_g[q];
+          const double vol = shape_vol[q];
+          star_mass += vol / 4.0;
+          for (int j = 0; j < 4; ++j) {
+            const int slot = (v[j][0] + 1) + 3 * (v[j][1] + 1) + 9 * (v[j][2] + 1);
+            double* t = star[slot];
+            t[0] += vol * (g4[k][0] * g4[j][0] + g4[k][1] * g4[j][1] + g4[k][2] * g4[j][2]);
+            for (int r = 0; r < 3; ++r)
+              for (int c = 0; c < 3; ++c) t[1 + 3 * r + c] += vol * g4[k][r] * g4[j][c];
+          }
+        }
+  m.mass.assign(m.n_own, star_mass);
+  m.stencil_ok = m.n_own > 0;
+  std::vector<float> ref32(270);
+  for (int slot = 0; slot < 27; ++slot)
+    for (int q = 0; q < 10; ++q) ref32[slot * 10 + q] = (float)star[slot][q];
+
+  // local id of a halo node of the current partition, by lattice index (stamped per partition)
+  std::vector<int> hloc_of(elements ? m.n_fem : 0, 0), hloc_stamp(elements ? m.n_fem : 0, -1);
+
   m.halo_off.assign(m.n_part + 1, 0);
   m.col_base.assign(m.n_part, 0);
   m.ncol.assign(m.n_part, 0);
@@ -159,13 +215,25 @@ std::string build_mesh(const dd_problem_desc& d, HostMesh& m, const int pb[3]) {
   m.halo.clear();
   m.part_dims.assign(4 * m.n_part, 0);
   m.box_codes.clear();
-  // assembled stencil per owned node: 27 lattice offsets x (K_ij, B_ij), FP64
-  std::vector<double> ref_st;               // stencil of the first owned node (FP64)
-  std::vector<float> ref32;
-  m.stencil_ok = true;
   for (int p = 0; p < m.n_part; ++p) {
     const auto& r = prange[p];
     const int o0 = m.own_off[p], no = m.own_off[p + 1] - o0;
+    m.max_own = std::max(m.max_own, no);
+    {
+      // staging box of the assembled-stencil kernel: the owned block and a one-node rim
+      const int ox = r[1] - r[0], oy = r[3] - r[2], oz = r[5] - r[4];
+      m.part_dims[4 * p] = ox;
+      m.part_dims[4 * p + 1] = oy;
+      m.part_dims[4 * p + 2] = oz;
+      m.part_dims[4 * p + 3] = (int)m.box_codes.size();
+      for (int z = r[4] - 1; z <= r[5]; ++z)
+        for (int y = r[2] - 1; y <= r[3]; ++y)
+          for (int x = r[0] - 1; x <= r[1]; ++x) m.box_codes.push_back(lat2int[L.idx(x, y, z)]);
+      m.max_box = std::max(m.max_box, (ox + 2) * (oy + 2) * (oz + 2));
+    }
+    m.halo_off[p] = (int)m.halo.size();
+    if (!elements) continue;
+    // element kernel data: every tetrahedron touching an owned node, its halo and colouring
     auto owned_here = [&](const int v[3]) {
       return v[0] >= r[0] && v[0] < r[1] && v[1] >= r[2] && v[1] < r[3] && v[2] >= r[4] && v[2] < r[5];
     };
@@ -176,37 +244,43 @@ std::string build_mesh(const dd_problem_desc& d, HostMesh& m, const int pb[3]) {
         for (int cx = std::max(r[0] - 1, 0); cx <= std::min(r[1] - 1, L.c[0] - 1); ++cx)
           for (int q = 0; q < 6; ++q) {
             El e;
-            e.v[0][0] = cx; e.v[0][1] = cy; e.v[0][2] = cz;
-            for (int k = 1; k < 4; ++k) {
-              for (int a = 0; a < 3; ++a) e.v[k][a] = e.v[k - 1][a];
-              e.v[k][kPerms[q][k - 1]] += 1;
+            for (int k = 0; k < 4; ++k) {
+              e.v[k][0] = cx + shape_v[q][k][0];
+              e.v[k][1] = cy + shape_v[q][k][1];
+              e.v[k][2] = cz + shape_v[q][k][2];
             }
             bool touches = false;
             for (int k = 0; k < 4; ++k) touches |= owned_here(e.v[k]);
             if (!touches) continue;
-            e.gid = geom_id(e.v);
-            if (e.gid < 0) return "degenerate tetrahedron";
+            e.gid = shape_gid[q];
             els.push_back(e);
           }
     // halo: non-owned vertices, ordered by internal code (owned ids, then layer-0 codes)
+    auto code_less = [](int a, int b) {
+      if ((a >= 0) != (b >= 0)) return a >= 0;
+      return a >= 0 ? a < b : a > b;
+    };
     std::vector<int> hcodes;
     for (const auto& e : els)
       for (int k = 0; k < 4; ++k)
         if (!owned_here(e.v[k])) hcodes.push_back(lat2int[L.idx(e.v[k][0], e.v[k][1], e.v[k][2])]);
-    std::sort(hcodes.begin(), hcodes.end(), [](int a, int b) {
-      if ((a >= 0) != (b >= 0)) return a >= 0;
-      return a >= 0 ? a < b : a > b;
-    });
+    std::sort(hcodes.begin(), hcodes.end(), code_less);
     hcodes.erase(std::unique(hcodes.begin(), hcodes.end()), hcodes.end());
     const int nl = no + (int)hcodes.size();
     if (nl > FEM_LOC_MAX || no > FEM_OWN_MAX) return "FEM partition exceeds local node limit";
     if ((int)els.size() > FEM_ELEM_MAX) return "FEM partition exceeds the element limit";
     m.max_loc = std::max(m.max_loc, nl);
-    m.max_own = std::max(m.max_own, no);
     m.max_elem = std::max(m.max_elem, (int)els.size());
-    std::map<int, int> hloc;
-    for (size_t i = 0; i < hcodes.size(); ++i) hloc[hcodes[i]] = no + (int)i;
-    m.halo_off[p] = (int)m.halo.size();
+    for (const auto& e : els)
+      for (int k = 0; k < 4; ++k)
+        if (!owned_here(e.v[k])) {
+          const int64_t li = L.idx(e.v[k][0], e.v[k][1], e.v[k][2]);
+          if (hloc_stamp[li] != p) {
+            hloc_stamp[li] = p;
+            hloc_of[li] = no + (int)(std::lower_bound(hcodes.begin(), hcodes.end(), lat2int[li], code_less) -
+                                     hcodes.begin());
+          }
+        }
     m.halo.insert(m.halo.end(), hcodes.begin(), hcodes.end());
     // local ids, greedy colouring on shared owned nodes
     struct Pk { int loc[4]; int gid; int color; };
@@ -216,8 +290,8 @@ std::string build_mesh(const dd_problem_desc& d, HostMesh& m, const int pb[3]) {
     for (size_t i = 0; i < els.size(); ++i) {
       uint64_t forbid = 0;
       for (int k = 0; k < 4; ++k) {
-        const int code = lat2int[L.idx(els[i].v[k][0], els[i].v[k][1], els[i].v[k][2])];
-        const int loc = owned_here(els[i].v[k]) ? code - o0 : hloc[code];
+        const int64_t li = L.idx(els[i].v[k][0], els[i].v[k][1], els[i].v[k][2]);
+        const int loc = owned_here(els[i].v[k]) ? lat2int[li] - o0 : hloc_of[li];
         pk[i].loc[k] = loc;
         if (loc < no) forbid |= used[loc];
       }
@@ -229,52 +303,6 @@ std::string build_mesh(const dd_problem_desc& d, HostMesh& m, const int pb[3]) {
       for (int k = 0; k < 4; ++k)
         if (pk[i].loc[k] < no) used[pk[i].loc[k]] |= (1ull << c);
       ncol = std::max(ncol, c + 1);
-    }
-    // lumped mass and assembled stencil of this partition's owned nodes (each element
-    // of the mesh that touches an owned node is present here exactly once)
-    std::vector<double> st((size_t)no * 27 * 10, 0.0);   // per node, slot: K, B00..B22
-    for (size_t i = 0; i < els.size(); ++i) {
-      double p4[4][3], g4[4][3], v;
-      for (int j = 0; j < 4; ++j)
-        for (int a = 0; a < 3; ++a) p4[j][a] = d.h * (double)(els[i].v[j][a] - els[i].v[0][a]);
-      tet_geometry(p4, g4, &v);
-      for (int k = 0; k < 4; ++k) {
-        if (pk[i].loc[k] >= no) continue;
-        m.mass[o0 + pk[i].loc[k]] += v / 4.0;
-        for (int j = 0; j < 4; ++j) {
-          int slot = 0, mul = 1;
-          for (int a = 0; a < 3; ++a, mul *= 3) {
-            const int off = els[i].v[j][a] - els[i].v[k][a];
-            if (off < -1 || off > 1) m.stencil_ok = false;
-            slot += (std::min(std::max(off, -1), 1) + 1) * mul;
-          }
-          double* t = &st[((size_t)pk[i].loc[k] * 27 + slot) * 10];
-          t[0] += v * (g4[k][0] * g4[j][0] + g4[k][1] * g4[j][1] + g4[k][2] * g4[j][2]);
-          for (int r = 0; r < 3; ++r)
-            for (int c = 0; c < 3; ++c) t[1 + 3 * r + c] += v * g4[k][r] * g4[j][c];
-        }
-      }
-    }
-    for (int l = 0; l < no && m.stencil_ok; ++l) {
-      std::vector<float> s32(270);
-      for (int q = 0; q < 270; ++q) s32[q] = (float)st[(size_t)l * 270 + q];
-      if (ref32.empty()) {
-        ref32 = s32;
-        ref_st.assign(st.begin() + (size_t)l * 270, st.begin() + (size_t)(l + 1) * 270);
-      } else if (std::memcmp(s32.data(), ref32.data(), 270 * sizeof(float)) != 0) {
-        m.stencil_ok = false;
-      }
-    }
-    {
-      const int ox = r[1] - r[0], oy = r[3] - r[2], oz = r[5] - r[4];
-      m.part_dims[4 * p] = ox;
-      m.part_dims[4 * p + 1] = oy;
-      m.part_dims[4 * p + 2] = oz;
-      m.part_dims[4 * p + 3] = (int)m.box_codes.size();
-      for (int z = r[4] - 1; z <= r[5]; ++z)
-        for (int y = r[2] - 1; y <= r[3]; ++y)
-          for (int x = r[0] - 1; x <= r[1]; ++x) m.box_codes.push_back(lat2int[L.idx(x, y, z)]);
-      m.max_box = std::max(m.max_box, (ox + 2) * (oy + 2) * (oz + 2));
     }
     m.max_colors = std::max(m.max_colors, ncol);
     std::stable_sort(pk.begin(), pk.end(), [](const Pk& a, const Pk& b) { return a.color < b.color; });
@@ -336,7 +364,7 @@ extern "C" int dd_debug_fem_apply(const dd_problem_desc* d, const double* eps, c
   if (!d || !eps || !E || !out) return DD_ERR_INVALID_ARG;
   HostMesh m;
   const int pb[3] = {FEM_PB, FEM_PB, FEM_PB};
-  if (!build_mesh(*d, m, pb).empty()) return DD_ERR_UNSUPPORTED;
+  if (!build_mesh(*d, m, pb, !stencil).empty()) return DD_ERR_UNSUPPORTED;
   const int s[3] = {d->fem_cells[0] + 1, d->fem_cells[1] + 1, d->fem_cells[2] + 1};
   const int64_t n_own = m.n_own, n_l0 = m.n_l0;
   std::vector<double> X(3 * n_own), em1(n_own), iface(3 * n_l0, 0.0);

@@ -132,6 +132,8 @@ def test_serving_completes_and_respects_budget():
     from paper_2508_07780_amd import serving
     reqs = synth.serving_requests(6, 20.0, outer=(40, 48), fem=(16, 24), sources=(1, 3), steps=(40, 90),
                                   iterations=(2, 3))
+    for r in reqs:
+        r.arrival = 0.0                 # a burst: admission is bound by the budget alone
     fps = sorted(serving.job_footprint(r) for r in reqs)
     budget = fps[-1] + fps[-2]          # the two largest jobs fit at once, never all six
     s_b, rec_b = serving.serve_batched(reqs, max_slots=4, hbm_budget=budget, chunk=16, keep=True)
