@@ -11,6 +11,17 @@
   the finite-difference signal; steps delta and
   2*delta must agree to 1% (the truncation error is then O(delta^2)), and their Richardson
   extrapolation is compared with the adjoint directional derivative.
+* Per node, at 20 free nodes drawn with the seed: the derivative along a smooth bump centred
+  on the node (a Gaussian of width 3 h over the free nodes, 1 at the node) of the loss over the
+  detectors within 24 h of the node's (x, y) (the adjoint gets the same masked cotangent), by
+  central differences with steps delta = 0.1 and 2 delta and their Richardson extrapolation
+  (sigma evaluated 0.2 above the other tests' point, so that the steps stay in the box), against
+  the adjoint's g . v.  Here the FP32 loss sets the floor: a bump moves
+  the loss by ~1e-5 of itself, and the two difference quotients, which differ only by
+  truncation and rounding, already disagree by 1e-3 .. 1e-2 (eps) and more for sigma.  So each
+  node's adjoint value must lie within four times that measured spread of its own difference
+  quotients (at least 1e-3 relative), and over the 20 nodes the eps derivatives within 2e-2
+  relative L2.
 * The checkpointed gradient (K = 64, 24 recomputed segments) equals, bit for bit, the one
   computed with every forward level stored (K >= N_t, no recompute).
 """
@@ -93,6 +104,66 @@ def test_c3_gradient_directional_finite_differences(c3_setup):
                   f"fd(2e-2) {fds[1]:.8e} richardson {rich:.8e} rel {abs(pred - rich) / abs(rich):.2e}", flush=True)
             assert abs(fds[0] - fds[1]) <= 1e-2 * abs(fds[0]), "finite differences not converged"
             assert abs(pred - rich) <= 1e-3 * abs(rich)
+
+
+def test_c3_gradient_at_twenty_seeded_nodes(c3_setup):
+    import torch
+    w, p, eobs, eps0, sig0, free = c3_setup
+    dev = eobs.device
+    x = synth.fem_node_coords(w.desc)
+    from paper_2508_07780_amd import Problem
+    det_idx = Problem.detector_nodes(w.desc)
+    nx, ny = w.desc.n_outer[0], w.desc.n_outer[1]
+    det_xy = np.stack([det_idx % nx, (det_idx // nx) % ny], axis=1) * w.desc.h + np.asarray(w.desc.origin[:2])
+    rng = np.random.Generator(np.random.PCG64(w.seed + 20))
+    nodes = rng.choice(np.nonzero(free)[0], 20, replace=False)
+    width = 3.0 * w.desc.h
+    radius = 24 * w.desc.h
+    sig0 = np.where(free, sig0 + 0.2, 0.0)      # room for sigma steps of 0.2 below the evaluation point
+    e0 = torch.tensor(eps0, dtype=torch.float32, device=dev)
+    s0 = torch.tensor(sig0, dtype=torch.float32, device=dev)
+
+    def traces(e, s):
+        p.set_coefficients(torch.tensor(e, dtype=torch.float32, device=dev),
+                           torch.tensor(s, dtype=torch.float32, device=dev))
+        return p.forward(w.sources, save=False)
+
+    pairs = {"eps": [], "sigma": []}
+    for i in nodes:
+        # the loss over the detectors above the node: J_i = 1/2 sum_{n, d in S_i} |T - E_obs|^2
+        near = np.linalg.norm(det_xy - x[i, :2], axis=1) <= radius
+        mask = torch.tensor(near.astype(np.float32), device=dev)[None, None, :, None]
+        p.set_coefficients(e0, s0)
+        tr = p.forward(w.sources, save=True)
+        p.adjoint(((tr - eobs) * mask).contiguous())
+        g_eps, g_sig = (g.cpu().numpy() for g in p.gradient())
+        v = np.where(free, np.exp(-0.5 * np.sum((x - x[i]) ** 2, axis=1) / width ** 2), 0.0)
+        for which, g, base, deltas in (("eps", g_eps, eps0, (0.1, 0.2)), ("sigma", g_sig, sig0, (0.1, 0.2))):
+            pred = float(g @ v)
+            fds = []
+            for delta in deltas:
+                vals = []
+                for sgn in (1.0, -1.0):
+                    xx = base + sgn * delta * v
+                    t = traces(xx, sig0) if which == "eps" else traces(eps0, xx)
+                    r = ((t - eobs) * mask).double()
+                    vals.append(float(0.5 * torch.sum(r * r)))
+                fds.append((vals[0] - vals[1]) / (2 * delta))
+            rich = (4.0 * fds[0] - fds[1]) / 3.0
+            spread = abs(fds[0] - fds[1])
+            rel = abs(pred - rich) / abs(rich)
+            print(f"[gpu] c3 node {i} {which}: {int(near.sum())} detectors, adjoint {pred:.8e} fd {fds[0]:.8e} "
+                  f"fd(2 delta) {fds[1]:.8e} richardson {rich:.8e} rel {rel:.2e} fd spread {spread / abs(rich):.2e}",
+                  flush=True)
+            pairs[which].append((pred, rich, spread))
+    fails = []
+    for which in ("eps", "sigma"):
+        a = np.array(pairs[which])
+        agg = float(np.linalg.norm(a[:, 0] - a[:, 1]) / np.linalg.norm(a[:, 1]))
+        print(f"[gpu] c3 20-node {which}: adjoint vs Richardson rel L2 {agg:.2e}", flush=True)
+        fails += [(which, k) for k, (pr, ri, sp) in enumerate(a) if abs(pr - ri) > max(2e-3 * abs(ri), 3.0 * sp)]
+        assert agg <= 1e-2
+    assert not fails, fails
 
 
 def test_c3_checkpointed_gradient_equals_store_all(c3_setup):
