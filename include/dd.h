@@ -377,8 +377,9 @@ const char* dd_last_error(const dd_problem* p);
  * cotangent traces - obs (read inside the adjoint kernel; obs_dev has the traces' layout)
  * and the gradient summed over sources, written to g_eps_dev / g_sigma_dev (FEM-node
  * arrays, float64) when those are given.  dd_batch_step issues up to max_steps kernel
- * launches.  A launch takes the oldest active jobs until their cells per step (outer nodes
- * + FEM-owned nodes) reach the batch's fill target (dd_batch_set_fill; at least one job),
+ * launches.  A launch takes the oldest active job and then the following ones while their
+ * cells per step (outer nodes + FEM-owned nodes) together stay within the batch's fill target
+ * (dd_batch_set_fill),
  * and each job it takes contributes its next step (a forward step, or an adjoint step
  * together with the next checkpoint recompute step of the segment before it, which uses
  * the other window).  So jobs of uneven grid sizes, step counts and source counts share
@@ -399,7 +400,7 @@ typedef struct dd_batch dd_batch;
  * job that does not fit gives DD_ERR_STATE and changes nothing (like a full batch), and a
  * job's bytes are returned when it completes. */
 int dd_batch_create(int32_t max_slots, size_t hbm_budget, dd_batch** out);
-/* Fill target of a launch in cells per step (default 6,000,000); 0 lets every active job
+/* Fill target of a launch in cells per step (default 9,000,000); 0 lets every active job
  * take part in every launch.  Negative: DD_ERR_INVALID_ARG. */
 int dd_batch_set_fill(dd_batch* b, int64_t cells);
 int dd_batch_destroy(dd_batch* b);

@@ -1575,13 +1575,13 @@ struct dd_batch {
   static constexpr int seg = 16;
   int ring = 64, pos = 0;
   bool return_on_done = true;   // dd_batch_step returns after the launch in which a job finishes
-  // a launch takes the oldest active jobs until their cells per step reach this (at least
-  // one job; 0: every active job in every launch).  Measured on the 16-problem mix and the
-  // small serving burst (throughput against one problem at a time): 0: 0.855 / 1.067;
-  // 3M: 0.919 / 0.998; 6M: 0.880 / 1.070; 12M: 0.853 / 1.057.  Small jobs gain from sharing
-  // launches (the fixed cost per launch is spread), large ones from keeping their fields in
-  // the last-level cache.
-  int64_t fill_cells = 6000000;
+  // a launch takes the oldest active job and then the following ones while their cells per
+  // step together stay within this (0: every active job in every launch).  Measured with the
+  // single-job launches by value (against one problem at a time; 16-problem mix of 1-11 M
+  // cells per step / small-job serving burst): 2M 0.984 / 0.90, 6M 0.985 / 1.09, 9M 0.985 /
+  // 1.12; the earlier rule that added jobs until the target was passed: 6M 0.944 / 1.12.
+  // Jobs that fill the GPU alone run alone; small, launch-bound jobs share launches.
+  int64_t fill_cells = 9000000;
   // FD tile variant of the launches: -1 by the launch's combined FD fields against the
   // last-level cache, 0 / 1 forced cached / streaming (DD_FD_NT at dd_batch_create)
   int nt_mode = -1;
@@ -1683,8 +1683,9 @@ size_t launch_jobs(const dd_batch* b) {
   int64_t cells = 0;
   size_t n = 0;
   for (const auto& j : b->jobs) {
-    if (n > 0 && cells >= b->fill_cells) break;
-    if (j.phase != 2) cells += j.p->N + j.p->n_own;
+    const int64_t c = j.phase != 2 ? j.p->N + j.p->n_own : 0;
+    if (n > 0 && cells + c > b->fill_cells) break;
+    cells += c;
     ++n;
   }
   return n;
@@ -1774,10 +1775,14 @@ int dd_batch_step(dd_batch* b, int32_t max_steps, void* stream) {
       for (int k = 0; k < m; ++k) {
         if (!bases[k].n) continue;
         const BatchItem& one = b->host[off + (size_t)k * b->width];
+        const BatchItem& two = b->host[off + (size_t)k * b->width + 1];
         if (bases[k].n == 1 && one.kind != 2)
           // a single forward or adjoint step: the fused step kernel, arguments by value (the
           // same device code on the same arguments, without the item lookup)
-          launch_step(one.fa, one.ea, st, one.kind == 1, false, nt[k]);
+          launch_step(one.fa, one.ea, st, one.kind == 1, false, nt[k], nullptr);
+        else if (bases[k].n == 2 && one.kind == 1 && two.kind == 2 && !obl[k])
+          // one job's adjoint step and its recompute step: likewise by value
+          launch_step_rec(one.fa, one.ea, two.ea, st, nt[k]);
         else
           launch_batch(b->dev + off + (size_t)k * b->width, bases[k], lds[k], st, nt[k], obl[k]);
       }

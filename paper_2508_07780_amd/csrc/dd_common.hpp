@@ -25,8 +25,19 @@ constexpr int FD_TY = DD_FD_TY;
 #define DD_FD_ZC_CACHED 2
 #endif
 constexpr int FD_ZC_CACHED = DD_FD_ZC_CACHED;
-constexpr int FD_ZC_STREAM = 8;
+#ifndef DD_FD_ZC_STREAM
+#define DD_FD_ZC_STREAM 8
+#endif
+constexpr int FD_ZC_STREAM = DD_FD_ZC_STREAM;
 __host__ __device__ constexpr int fd_zc(bool nt) { return nt ? FD_ZC_STREAM : FD_ZC_CACHED; }
+// Streaming variant: the tile order takes FD_ZGROUP consecutive z-chunks of each row of tiles
+// in turn (x fastest, then the chunks of the group, then y), so that the plane two chunks
+// share is read again while it is still in the XCD's L2.
+#ifndef DD_FD_ZGROUP
+#define DD_FD_ZGROUP 2
+#endif
+constexpr int FD_ZGROUP = DD_FD_ZGROUP;
+__host__ __device__ constexpr int fd_zgroup(bool nt) { return nt ? FD_ZGROUP : 1; }
 constexpr int FD_THREADS = FD_TX * FD_TY;
 // Last-level cache (MI355X Infinity Cache).  A grid whose two levels of E exceed it streams
 // each node's own previous and new level with non-temporal accesses.
@@ -84,11 +95,11 @@ inline int64_t face_lex_count(int nx, int ny, int nz, unsigned mask) {
 // Tile grid of an nx * ny * nz grid for the z-chunk of the streaming (nt) or cached variant;
 // per_xcd = tiles each XCD takes.
 inline void fd_tile_grid(int nx, int ny, int nz, bool nt, int& nbx, int& nby, int& nbz, int& ntiles, int& per_xcd) {
-  const int zc = fd_zc(nt);
+  const int zc = fd_zc(nt), zg = fd_zgroup(nt);
   nbx = (nx + FD_TX - 1) / FD_TX;
   nby = (ny + FD_TY - 1) / FD_TY;
   nbz = (nz + zc - 1) / zc;
-  ntiles = nbx * nby * nbz;
+  ntiles = nbx * nby * ((nbz + zg - 1) / zg * zg);   // whole groups of z-chunks
   per_xcd = (ntiles + N_XCD - 1) / N_XCD;
 }
 
@@ -192,6 +203,8 @@ struct PgArgs {
 void launch_step(const FdArgs& fa, const FemArgs& ea, hipStream_t s, bool adj, bool energy, bool nt,
                  const PgArgs* pg = nullptr);
 
+// adjoint step and FEM-only recompute step of one problem in one launch (arguments by value)
+void launch_step_rec(const FdArgs& fa, const FemArgs& ea, const FemArgs& er, hipStream_t s, bool nt);
 // one item of a batched step launch
 struct BatchItem {
   FdArgs fa;

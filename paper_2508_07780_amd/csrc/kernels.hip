@@ -83,11 +83,23 @@ __device__ __forceinline__ void fd_tile(const FdArgs& a, const int b) {
   const int t = (b % N_XCD) * a.per_xcd + kx;
   if (t >= a.ntiles) return;
   const int nx = a.nx, ny = a.ny, nz = a.nz;
+  constexpr int ZG = fd_zgroup(NT);
   const int bx = t % a.nbx;
-  const int by = (t / a.nbx) % a.nby;
-  const int bz = t / (a.nbx * a.nby);
+  int by, bz;
+  if (ZG > 1) {
+    const int r = t / a.nbx;
+    by = (r / ZG) % a.nby;
+    bz = (r / (ZG * a.nby)) * ZG + r % ZG;
+  } else {
+    by = (t / a.nbx) % a.nby;
+    bz = t / (a.nbx * a.nby);
+  }
   const int x0 = bx * FD_TX, y0 = by * FD_TY, z0 = bz * ZC;
-  if (z0 >= nz) return;   // tile grid built for another z-chunk: nothing of this tile exists
+  if (z0 >= nz) {
+    // past the grid (a group's padding, or a tile grid built for another z-chunk)
+    if (ENERGY && threadIdx.x == 0) a.epart[t] = 0.0;
+    return;
+  }
   const int z1 = min(z0 + ZC, nz);
   const int tid = threadIdx.x;
   if (x0 > a.blo[0] && x0 + FD_TX - 1 < a.bhi[0] && y0 > a.blo[1] && y0 + FD_TY - 1 < a.bhi[1] &&
@@ -879,6 +891,40 @@ __global__ __launch_bounds__(FD_THREADS) void step_kernel_r2(FdArgs fa, FemArgs 
     return;
   }
   fd_tile<ENERGY, NT, OBL>(fa, b - fem_blocks - pg_blocks);
+}
+
+// One job's adjoint step together with the next FEM-only recompute step of the segment before
+// it (which writes the other window), arguments by value: blocks [0, fem_blocks) the adjoint
+// FEM partitions, [fem_blocks, fem_blocks + rec_blocks) the recompute partitions, the rest the
+// FD tiles.  The same device code as the batched launch of these two items, without the item
+// lookup; held to 6 waves per SIMD like the batched kernel (the union of the forward and
+// adjoint FEM variants).
+template <bool NT>
+__global__ __launch_bounds__(FD_THREADS, 6) void step_rec_kernel(FdArgs fa, FemArgs ea, int fem_blocks, FemArgs er,
+                                                                   int rec_blocks) {
+  const int b = blockIdx.x;
+  if (b < fem_blocks) {
+    const int p = fem_part_of_block(b, fem_blocks, ea.rev);
+    if (p < ea.n_part) fem_stencil_part<true, false>(ea, p);
+    return;
+  }
+  if (b < fem_blocks + rec_blocks) {
+    const int p = fem_part_of_block(b - fem_blocks, rec_blocks, er.rev);
+    if (p < er.n_part) fem_stencil_part<false, false>(er, p);
+    return;
+  }
+  fd_tile<false, NT>(fa, b - fem_blocks - rec_blocks);
+}
+
+void launch_step_rec(const FdArgs& fa, const FemArgs& ea, const FemArgs& er, hipStream_t s, bool nt) {
+  const int fem_blocks = (ea.n_part + N_XCD - 1) / N_XCD * N_XCD;
+  const int rec_blocks = (er.n_part + N_XCD - 1) / N_XCD * N_XCD;
+  const dim3 grid(fem_blocks + rec_blocks + fa.per_xcd * N_XCD);
+  const size_t lds = std::max(stencil_lds(ea), stencil_lds(er));   // the items may be of two problems
+  if (nt)
+    hipLaunchKernelGGL((step_rec_kernel<true>), grid, dim3(FD_THREADS), lds, s, fa, ea, fem_blocks, er, rec_blocks);
+  else
+    hipLaunchKernelGGL((step_rec_kernel<false>), grid, dim3(FD_THREADS), lds, s, fa, ea, fem_blocks, er, rec_blocks);
 }
 
 // ---------------------------------------------------------------------------------------
