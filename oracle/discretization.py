@@ -18,6 +18,12 @@ the discrete scheme; this module writes out the reading used throughout:
   FEM rows, so the coupling is a two-node overlap;
 * first-order absorbing faces (eq. forward_absorbing_bc / model1) use the
   lumped face mass h^2 * 2^-(in-face boundary coordinates).
+
+A general (e.g. locally refined) mesh of the FEM box can replace the Kuhn split: its
+nodes are the box's lattice nodes plus extra nodes strictly inside the box, its
+tetrahedra any conforming set that covers the box (``mesh=(extra_xyz, tets)``, tets in
+FEM-node indices: lattice nodes first, lexicographic, then the extra nodes).  Extra
+nodes are free FEM-owned nodes; the ownership rules of the lattice nodes are unchanged.
 """
 
 from __future__ import annotations
@@ -35,10 +41,12 @@ TOP = 1
 
 
 class Discretization:
-    def __init__(self, desc, fd_only: bool = False, divdiv_form: str = "R1"):
+    def __init__(self, desc, fd_only: bool = False, divdiv_form: str = "R1", mesh=None):
         """divdiv_form: "R1" (the scheme: the nodal product (eps - 1) E inside the element
         divergence, eq. forward_prob) or "R2" (the element mean of eps - 1 outside it, a
-        symmetric variant for which eq. gradeps' div-div term is the exact gradient)."""
+        symmetric variant for which eq. gradeps' div-div term is the exact gradient).
+        mesh: None (the Kuhn split of the box) or (extra_xyz (n_extra, 3), tets (n_tets, 4)) in
+        FEM-node indices, lattice nodes first; every lattice node must be a vertex."""
         if divdiv_form not in ("R1", "R2"):
             raise ValueError("divdiv_form must be R1 or R2")
         self.desc = desc
@@ -46,16 +54,19 @@ class Discretization:
         self.divdiv_form = divdiv_form
         nvec = np.array([int(v) for v in desc.n_outer])
         self.nvec = nvec
-        self.N = int(np.prod(nvec))
+        self.N_grid = int(np.prod(nvec))
+        extra = np.zeros((0, 3)) if mesh is None else np.asarray(mesh[0], dtype=np.float64).reshape(-1, 3)
+        self.n_extra = len(extra)
+        self.N = self.N_grid + self.n_extra          # grid nodes, then the mesh's extra nodes
         h = float(desc.h)
         self.h = h
         self.dt = float(desc.dt)
         k, j, i = np.meshgrid(np.arange(nvec[2]), np.arange(nvec[1]), np.arange(nvec[0]), indexing="ij")
         ijk = np.stack([i, j, k], axis=-1).reshape(-1, 3)
         self.ijk = ijk
-        self.x = np.asarray(desc.origin, dtype=np.float64) + h * ijk
+        self.x = np.concatenate([np.asarray(desc.origin, dtype=np.float64) + h * ijk, extra])
         on_bnd = (ijk == 0) | (ijk == nvec - 1)
-        self.bcount = on_bnd.sum(axis=1)
+        self.bcount = np.concatenate([on_bnd.sum(axis=1), np.zeros(self.n_extra, dtype=np.int64)])
 
         # ---- FEM lattice and layers --------------------------------------------------
         lo = np.array([int(v) for v in desc.fem_lo])
@@ -64,8 +75,12 @@ class Discretization:
         lz, ly, lx = np.meshgrid(np.arange(fshape[2]), np.arange(fshape[1]), np.arange(fshape[0]), indexing="ij")
         lat = np.stack([lx, ly, lz], axis=-1).reshape(-1, 3)
         g = lat + lo
-        self.fem_grid = g[:, 0] + nvec[0] * (g[:, 1] + nvec[1] * g[:, 2])
-        self.fem_layer = np.minimum(lat, cells - lat).min(axis=1)
+        n_lat = len(lat)
+        # FEM node -> global node: lattice nodes to their grid node, extra nodes after the grid
+        self.fem_grid = np.concatenate([g[:, 0] + nvec[0] * (g[:, 1] + nvec[1] * g[:, 2]),
+                                        self.N_grid + np.arange(self.n_extra)])
+        big = int(cells.max())           # extra nodes lie strictly inside: layer >= 2 (free)
+        self.fem_layer = np.concatenate([np.minimum(lat, cells - lat).min(axis=1), np.full(self.n_extra, big)])
         self.n_fem = len(self.fem_grid)
         self.fem_owned = self.fem_layer >= 1
         self.fem_free = self.fem_layer >= 2
@@ -81,17 +96,29 @@ class Discretization:
         def lat_index(p):
             return p[:, 0] + fshape[0] * (p[:, 1] + fshape[1] * p[:, 2])
 
-        tets = []
-        eye = np.eye(3, dtype=np.int64)
-        for perm in itertools.permutations(range(3)):
-            v = [corner]
-            for a in perm:
-                v.append(v[-1] + eye[a])
-            tets.append(np.stack([lat_index(p) for p in v], axis=1))
-        self.tets = np.concatenate(tets, axis=0)
+        if mesh is None:
+            tets = []
+            eye = np.eye(3, dtype=np.int64)
+            for perm in itertools.permutations(range(3)):
+                v = [corner]
+                for a in perm:
+                    v.append(v[-1] + eye[a])
+                tets.append(np.stack([lat_index(p) for p in v], axis=1))
+            self.tets = np.concatenate(tets, axis=0)
+        else:
+            self.tets = np.asarray(mesh[1], dtype=np.int64).reshape(-1, 4)
+            if self.tets.min() < 0 or self.tets.max() >= self.n_fem:
+                raise ValueError("mesh tetrahedra reference a node that does not exist")
+            if n_lat != int(np.prod(fshape)):
+                raise ValueError("lattice size mismatch")
         X = self.x[self.fem_grid][self.tets]                       # (T, 4, 3)
         J = np.stack([X[:, 1] - X[:, 0], X[:, 2] - X[:, 0], X[:, 3] - X[:, 0]], axis=-1)
         self.vol = np.abs(np.linalg.det(J)) / 6.0
+        if not np.all(self.vol > 0):
+            raise ValueError("degenerate tetrahedron")
+        box = float(np.prod(cells)) * h ** 3
+        if abs(self.vol.sum() - box) > 1e-9 * box:
+            raise ValueError("the tetrahedra do not fill the FEM box")
         Jinv = np.linalg.inv(J)                                     # row k = grad of barycentric k
         G = np.empty((len(self.tets), 4, 3))
         G[:, 1:, :] = Jinv
@@ -102,6 +129,9 @@ class Discretization:
         m_fem = np.bincount(self.tets.ravel(), weights=np.repeat(self.vol / 4.0, 4), minlength=self.n_fem)
         self.m_fem_lumped = m_fem
         m = h ** 3 * 2.0 ** (-self.bcount.astype(np.float64))
+        m[self.N_grid:] = 0.0
+        if np.any(m_fem[self.fem_layer >= 1] <= 0):
+            raise ValueError("a FEM-owned node lies on no tetrahedron")
         if not fd_only:
             own = self.fem_owned
             m[self.fem_grid[own]] = m_fem[own]
@@ -110,7 +140,7 @@ class Discretization:
         # ---- stiffness -----------------------------------------------------------------
         rows, cols, vals = [], [], []
         for a in range(3):
-            sel = ijk[:, a] < nvec[a] - 1
+            sel = ijk[:, a] < nvec[a] - 1   # grid nodes only (the first N_grid global indices)
             p = np.nonzero(sel)[0]
             q = p + int(np.prod(nvec[:a]))
             cnt = np.ones(len(p))
@@ -138,14 +168,15 @@ class Discretization:
         # ---- faces: lumped face masses, detectors ----------------------------------------
         self.face_mass = {}
         for bit, (a, s) in FACES.items():
-            on = ijk[:, a] == (0 if s == 0 else nvec[a] - 1)
+            on = np.zeros(self.N, dtype=bool)
+            on[:self.N_grid] = ijk[:, a] == (0 if s == 0 else nvec[a] - 1)
             fm = np.zeros(self.N)
             fm[on] = h ** 2 * 2.0 ** (-(self.bcount[on] - 1).astype(np.float64))
             self.face_mass[bit] = fm
         det_mask = np.zeros(self.N, dtype=bool)
         for bit, (a, s) in FACES.items():
             if int(desc.detector_faces) & bit:
-                det_mask |= ijk[:, a] == (0 if s == 0 else nvec[a] - 1)
+                det_mask[:self.N_grid] |= ijk[:, a] == (0 if s == 0 else nvec[a] - 1)
         self.det = np.nonzero(det_mask)[0]          # lexicographic order
         self.eps = None
 

@@ -11,5 +11,6 @@ from .configs import (  # noqa: F401
     SRC_SINE1, SRC_GAUSS_SINE, SRC_DIPOLE,
     ProblemDesc, Source, Workload,
     fem_layers, fem_node_coords,
-    c1, c2, c3, probe288, stream224, small, batch_mix, noise, initial_pulses, with_steps, gauss_sine, oblique_wave, plane_wave_switch, Request, serving_requests,
+    c1, c2, c3, probe288, stream224, small, batch_mix, noise, initial_pulses, with_steps, gauss_sine, oblique_wave,
+    plane_wave_switch, Request, serving_requests, meshref_marks, refined_mesh, refined_values,
 )

@@ -460,3 +460,73 @@ def stream224(n_steps=420) -> Workload:
                  pos=(112, 100, desc.fem_lo[2] + 96 + 4))
     eps, sig, info = skin_media(desc, rng)
     return Workload("stream224", desc, eps, sig, [src], seed, eps_true=eps, sigma_true=sig, extra=info)
+
+
+def meshref_marks(desc: ProblemDesc, eps: np.ndarray, beta: float) -> np.ndarray:
+    """Cells of the FEM box (lexicographic, x fastest) marked for refinement by the rule of the
+    paper's eq. meshref on the uniform starting mesh: |h eps| >= beta max |h eps| at any of the
+    cell's corners (h the same everywhere, so the rule compares |eps|), among cells whose corners
+    are all FEM-owned (layer >= 1), so that the overlap layers keep their lattice elements."""
+    cx, cy, cz = (int(c) for c in desc.fem_cells)
+    fx, fy = cx + 1, cy + 1
+    e = np.abs(np.asarray(eps, dtype=np.float64))
+    lay = fem_layers(desc)
+    thr = beta * e.max()
+    marks = np.zeros(cx * cy * cz, dtype=bool)
+    for k in range(cz):
+        for j in range(cy):
+            for i in range(cx):
+                corners = [(i + a) + fx * ((j + b) + fy * (k + c)) for c in (0, 1) for b in (0, 1) for a in (0, 1)]
+                if lay[corners].min() >= 1 and e[corners].max() >= thr:
+                    marks[i + cx * (j + cy * k)] = True
+    return marks
+
+
+def refined_mesh(desc: ProblemDesc, marks: np.ndarray):
+    """A conforming tetrahedral mesh of the FEM box: the Kuhn split (six tetrahedra per cell, one per
+    axis permutation, from the cell's lowest corner to its highest), where every marked cell gets
+    its centre as a new node and each of its six tetrahedra is bisected across the cell's main
+    diagonal into two (the cell's faces are not split, so neighbours stay conforming).  Returns
+    (extra_xyz, tets): the centres (in the order of the marked cells) and the tetrahedra in
+    FEM-node indices (lattice nodes first, lexicographic; then the centres)."""
+    cx, cy, cz = (int(c) for c in desc.fem_cells)
+    fx, fy, fz = cx + 1, cy + 1, cz + 1
+    n_lat = fx * fy * fz
+    lo = np.asarray(desc.origin, dtype=np.float64) + desc.h * np.asarray(desc.fem_lo, dtype=np.float64)
+    perms = [(0, 1, 2), (0, 2, 1), (1, 0, 2), (1, 2, 0), (2, 0, 1), (2, 1, 0)]
+    extra, tets = [], []
+    for k in range(cz):
+        for j in range(cy):
+            for i in range(cx):
+                marked = bool(marks[i + cx * (j + cy * k)])
+                if marked:
+                    c_id = n_lat + len(extra)
+                    extra.append(lo + desc.h * np.array([i + 0.5, j + 0.5, k + 0.5]))
+                for perm in perms:
+                    p = [i, j, k]
+                    v = [p[0] + fx * (p[1] + fy * p[2])]
+                    for a in perm:
+                        p[a] += 1
+                        v.append(p[0] + fx * (p[1] + fy * p[2]))
+                    if marked:
+                        tets.append((v[0], v[1], v[2], c_id))
+                        tets.append((c_id, v[1], v[2], v[3]))
+                    else:
+                        tets.append(tuple(v))
+    return np.asarray(extra, dtype=np.float64).reshape(-1, 3), np.asarray(tets, dtype=np.int32)
+
+
+def refined_values(desc: ProblemDesc, marks: np.ndarray, lattice_values: np.ndarray) -> np.ndarray:
+    """Nodal values on the refined mesh: the lattice values, then at each centre the mean of its
+    cell's eight corners (the trilinear value there)."""
+    cx, cy, cz = (int(c) for c in desc.fem_cells)
+    fx, fy = cx + 1, cy + 1
+    v = np.asarray(lattice_values, dtype=np.float64)
+    out = [v]
+    add = []
+    for idx in np.nonzero(marks)[0]:
+        i, j, k = idx % cx, (idx // cx) % cy, idx // (cx * cy)
+        corners = [(i + a) + fx * ((j + b) + fy * (k + c)) for c in (0, 1) for b in (0, 1) for a in (0, 1)]
+        add.append(v[corners].mean())
+    out.append(np.asarray(add, dtype=np.float64))
+    return np.concatenate(out)
