@@ -142,6 +142,25 @@ typedef void (*dd_free_fn)(void* ptr, void* ctx);
  * Errors: DD_ERR_INVALID_ARG (descriptor), DD_ERR_UNSUPPORTED (overlap, s_stab, ckpt_mode),
  * DD_ERR_OOM, DD_ERR_HIP. */
 int dd_create(const dd_problem_desc* desc, dd_alloc_fn alloc_fn, dd_free_fn free_fn, void* ctx, dd_problem** out);
+/* dd_create on a general tetrahedral mesh of the FEM box (the locally refined meshes of
+ * eq. meshref: the FEM region of section "Numerical results" on a mesh refined where the
+ * reconstructed |eps| is large).  The FEM nodes are the box's (fem_cells + 1)^3 lattice nodes,
+ * lexicographic (x fastest), followed by n_extra nodes at extra_xyz (host, [n_extra][3] physical
+ * coordinates, each strictly inside the box); tets (host, [n_tets][4]) lists the tetrahedra by
+ * FEM-node index.  The tetrahedra must fill the box (volume sum within 1e-9), none degenerate,
+ * every node of lattice layer >= 1 and every extra node on at least one of them.  The lattice
+ * nodes of layers 0 and 1 keep their roles (finite-difference data; the dual-written layer) and
+ * the extra nodes are free.  FEM-node arrays (coefficients, gradients) then hold n_fem_nodes =
+ * (fem_cells + 1)^3 + n_extra entries.  The FEM rows run on the element-coloured kernel with
+ * the div-div form R1; the form R2, the paper-formula gradient, initial data, dd_cga runs and
+ * batched jobs report DD_ERR_UNSUPPORTED for such a problem.  The arrays are read during the
+ * call only.  The explicit step is stable for dt up to 2 / sqrt(lambda_max(M_eps^-1 A)),
+ * which a refined mesh lowers: the caller chooses dt accordingly.
+ * Errors: DD_ERR_INVALID_ARG (descriptor, or a mesh that breaks the rules above),
+ * DD_ERR_UNSUPPORTED (as dd_create, or a mesh too dense for the kernel's partitions of
+ * at most 512 owned / 1024 local nodes and 4608 elements), DD_ERR_OOM, DD_ERR_HIP. */
+int dd_create_mesh(const dd_problem_desc* desc, int64_t n_extra, const double* extra_xyz, int64_t n_tets,
+                   const int32_t* tets, dd_alloc_fn alloc_fn, dd_free_fn free_fn, void* ctx, dd_problem** out);
 /* Releases the problem.  With hipMalloc memory the device is synchronised first; with a
  * caller allocator only the library's own second stream is, and each buffer goes back
  * through free_fn while the caller's stream may still hold queued work that reads it: the
@@ -149,7 +168,8 @@ int dd_create(const dd_problem_desc* desc, dd_alloc_fn alloc_fn, dd_free_fn free
  * stream of the calls does). */
 int dd_destroy(dd_problem* p);
 
-/* Sizes: FEM lattice nodes, detectors, outer grid nodes (any pointer may be NULL). */
+/* Sizes: FEM nodes (lattice, plus a general mesh's extra nodes), detectors, outer grid
+ * nodes (any pointer may be NULL). */
 int dd_sizes(const dd_problem* p, int64_t* n_fem_nodes, int64_t* n_detectors, int64_t* n_grid);
 
 /* Host-only: grid indices of the detector nodes in trace order (n_detectors entries). */
@@ -443,6 +463,12 @@ int dd_algorithmic_bytes(const dd_problem* p, int32_t kind, double* bytes_per_la
  * Returns DD_ERR_UNSUPPORTED if any check fails. */
 int dd_debug_fem_apply(const dd_problem_desc* desc, const double* eps, const double* E, int32_t flags,
                        double* out, int64_t* stats);
+/* dd_debug_fem_apply on the element data that dd_create_mesh builds from a general mesh (same
+ * arguments as there; flags bit 1 must be clear: a general mesh has no assembled stencil).
+ * eps, E, out: over the n_fem_nodes = (fem_cells + 1)^3 + n_extra FEM nodes. */
+int dd_debug_fem_apply_mesh(const dd_problem_desc* desc, int64_t n_extra, const double* extra_xyz, int64_t n_tets,
+                            const int32_t* tets, const double* eps, const double* E, int32_t flags, double* out,
+                            int64_t* stats);
 
 #ifdef __cplusplus
 }

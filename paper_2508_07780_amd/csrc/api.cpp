@@ -25,6 +25,8 @@ struct dd_problem {
   int64_t N = 0;
   int fs[3] = {0, 0, 0};
   int64_t n_fem = 0, n_own = 0, n_l0 = 0, n_det = 0;
+  bool general = false;   // a caller mesh (dd_create_mesh): n_extra nodes beyond the lattice
+  int64_t n_extra = 0;
   int n_part = 0, n_geom = 0;
   int lds_loc = 0, lds_own = 0, lds_elem = 0, lds_box = 0;
   bool use_stencil = false;             // assembled-stencil FEM kernel instead of the element kernel
@@ -753,7 +755,16 @@ size_t dd_footprint_bytes(const dd_problem_desc* desc, int32_t n_src) {
   return (size_t)b;
 }
 
-int dd_create(const dd_problem_desc* desc, dd_alloc_fn alloc_fn, dd_free_fn free_fn, void* ctx, dd_problem** out) {
+namespace {
+// A general mesh of the FEM box (dd_create_mesh); null for the Kuhn split.
+struct MeshInput {
+  int64_t n_extra, n_tets;
+  const double* xyz;
+  const int32_t* tets;
+};
+
+int create_problem(const dd_problem_desc* desc, const MeshInput* gm, dd_alloc_fn alloc_fn, dd_free_fn free_fn,
+                   void* ctx, dd_problem** out) {
   if (!out) return DD_ERR_INVALID_ARG;
   *out = nullptr;
   const std::string e = check_desc(desc);
@@ -779,14 +790,19 @@ int dd_create(const dd_problem_desc* desc, dd_alloc_fn alloc_fn, dd_free_fn free
     int x = 0, y = 0, z = 0;
     if (std::sscanf(e, "%d,%d,%d", &x, &y, &z) == 3) { pb[0] = x; pb[1] = y; pb[2] = z; }
   }
-  bool element_path = false;   // the element-coloured FEM kernel instead of the assembled stencil
+  bool element_path = gm != nullptr;   // the element-coloured FEM kernel instead of the assembled stencil
   if (const char* e = std::getenv("DD_FEM_PATH"))
     if (std::strcmp(e, "element") == 0) element_path = true;
-  const std::string me = build_mesh(*desc, m, pb, element_path);
+  const std::string me = gm ? build_mesh_general(*desc, gm->n_extra, gm->xyz, gm->n_tets, gm->tets, m)
+                            : build_mesh(*desc, m, pb, element_path);
   if (!me.empty()) {
     delete p;
-    return DD_ERR_UNSUPPORTED;
+    // a caller mesh that is malformed is an argument error; one the kernel cannot partition is not
+    return gm && me.find("too dense") == std::string::npos && me.find("exceeds") == std::string::npos
+               ? DD_ERR_INVALID_ARG : DD_ERR_UNSUPPORTED;
   }
+  p->general = gm != nullptr;
+  p->n_extra = gm ? gm->n_extra : 0;
   p->n_fem = m.n_fem;
   p->n_own = m.n_own;
   p->n_l0 = m.n_l0;
@@ -868,6 +884,21 @@ int dd_create(const dd_problem_desc* desc, dd_alloc_fn alloc_fn, dd_free_fn free
   *out = p;
   return DD_OK;
 }
+}  // namespace
+
+int dd_create(const dd_problem_desc* desc, dd_alloc_fn alloc_fn, dd_free_fn free_fn, void* ctx, dd_problem** out) {
+  return create_problem(desc, nullptr, alloc_fn, free_fn, ctx, out);
+}
+
+int dd_create_mesh(const dd_problem_desc* desc, int64_t n_extra, const double* extra_xyz, int64_t n_tets,
+                   const int32_t* tets, dd_alloc_fn alloc_fn, dd_free_fn free_fn, void* ctx, dd_problem** out) {
+  if (n_extra < 0 || n_tets < 1 || !tets || (n_extra > 0 && !extra_xyz)) {
+    if (out) *out = nullptr;
+    return DD_ERR_INVALID_ARG;
+  }
+  const MeshInput gm{n_extra, n_tets, extra_xyz, tets};
+  return create_problem(desc, &gm, alloc_fn, free_fn, ctx, out);
+}
 
 int dd_destroy(dd_problem* p) {
   if (!p) return DD_ERR_INVALID_ARG;
@@ -901,7 +932,7 @@ int dd_set_coefficients(dd_problem* p, const float* eps_dev, const float* sigma_
   hipStream_t st = (hipStream_t)stream;
   int h_err = 0;
   if (hipMemsetAsync(p->d_err, 0, sizeof(int), st) != hipSuccess) return fail(p, DD_ERR_HIP, "hipMemsetAsync failed");
-  launch_validate(eps_dev, sigma_dev, p->fs[0], p->fs[1], p->fs[2], p->d_err, st);
+  launch_validate(eps_dev, sigma_dev, p->fs[0], p->fs[1], p->fs[2], p->n_extra, p->d_err, st);
   if (int rc = check_launch(p)) return rc;
   if (hipMemcpyAsync(&h_err, p->d_err, sizeof(int), hipMemcpyDeviceToHost, st) != hipSuccess ||
       hipStreamSynchronize(st) != hipSuccess)
@@ -923,7 +954,7 @@ int dd_set_coefficients_async(dd_problem* p, const float* eps_dev, const float* 
   hipStream_t st = (hipStream_t)stream;
   int* flag = p->d_err + 1;
   launch_fill_i32(flag, 1, 0, st);
-  launch_validate(eps_dev, sigma_dev, p->fs[0], p->fs[1], p->fs[2], flag, st);
+  launch_validate(eps_dev, sigma_dev, p->fs[0], p->fs[1], p->fs[2], p->n_extra, flag, st);
   launch_coefficients(eps_dev, sigma_dev, p->own_api, p->mass_d, p->n_own, p->d.dt, p->em1, p->c1, p->c2, p->sig_own,
                       flag, st);
   if (int rc = check_launch(p)) return rc;
@@ -1114,6 +1145,7 @@ int dd_paper_gradient_enable(dd_problem* p, int32_t on) {
     p->pg_on = false;
     return DD_OK;
   }
+  if (p->general) return fail(p, DD_ERR_UNSUPPORTED, "the paper-formula gradient needs the Kuhn split of the FEM box");
   if (int rc = pg_setup(p)) return rc;
   p->pg_on = true;
   return DD_OK;
@@ -1179,6 +1211,7 @@ int dd_set_initial_data(dd_problem* p, const float* f0_dev, const float* f1_dev,
     return DD_OK;
   }
   if (!f0_dev || !f1_dev) return fail(p, DD_ERR_INVALID_ARG, "initial data needs both f_0 and f_1 (or neither)");
+  if (p->general) return fail(p, DD_ERR_UNSUPPORTED, "initial data needs the Kuhn split of the FEM box");
   hipStream_t st = (hipStream_t)stream;
   int h_err = 0;
   if (hipMemsetAsync(p->d_err, 0, sizeof(int), st) != hipSuccess) return fail(p, DD_ERR_HIP, "hipMemsetAsync failed");
@@ -1256,6 +1289,7 @@ int dd_cga_create(dd_problem* p, const dd_cga_params* prm, const float* eps0_dev
                   dd_cga** out) {
   if (!p) return DD_ERR_INVALID_ARG;
   if (!prm || !eps0_dev || !sig0_dev || !out) return fail(p, DD_ERR_INVALID_ARG, "null CGA argument");
+  if (p->general) return fail(p, DD_ERR_UNSUPPORTED, "CGA runs on the Kuhn split of the FEM box");
   *out = nullptr;
   std::string why;
   if (!cga_params_ok(*prm, why)) return fail(p, DD_ERR_INVALID_ARG, why);
@@ -1263,7 +1297,7 @@ int dd_cga_create(dd_problem* p, const dd_cga_params* prm, const float* eps0_dev
   // the initial guess must satisfy eq. epsilon_sigma_constraint, upper bounds included
   int h_err[2] = {0, 0};
   if (hipMemsetAsync(p->d_err, 0, sizeof(int), st) != hipSuccess) return fail(p, DD_ERR_HIP, "hipMemsetAsync failed");
-  launch_validate(eps0_dev, sig0_dev, p->fs[0], p->fs[1], p->fs[2], p->d_err, st);
+  launch_validate(eps0_dev, sig0_dev, p->fs[0], p->fs[1], p->fs[2], p->n_extra, p->d_err, st);
   if (hipMemcpyAsync(&h_err[0], p->d_err, sizeof(int), hipMemcpyDeviceToHost, st) != hipSuccess ||
       hipStreamSynchronize(st) != hipSuccess)
     return fail(p, DD_ERR_HIP, "error readback failed");

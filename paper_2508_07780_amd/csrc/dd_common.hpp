@@ -227,7 +227,8 @@ void launch_energy_reduce(const double* part, int n, double* out, hipStream_t s)
 void launch_fill_f32(float* p, int64_t n, float v, hipStream_t s);
 void launch_fill_f64(double* p, int64_t n, double v, hipStream_t s);
 void launch_copy_f32(float* dst, const float* src, int64_t n, hipStream_t s);
-void launch_validate(const float* eps, const float* sig, int fsx, int fsy, int fsz, int* err, hipStream_t s);
+void launch_validate(const float* eps, const float* sig, int fsx, int fsy, int fsz, int64_t n_extra, int* err,
+                     hipStream_t s);
 void launch_coefficients(const float* eps, const float* sig, const int* own_api, const double* mass_d,
                          int64_t n_own, double dt, float* em1, float* c1, float* c2, float* sig_own,
                          const int* guard, hipStream_t s);
@@ -267,5 +268,10 @@ struct HostMesh {
 // (per-partition elements, halos and colouring).  Returns an empty string on success, else
 // the error text.
 std::string build_mesh(const dd_problem_desc& d, HostMesh& m, const int pb[3], bool elements);
+// General tetrahedral mesh of the FEM box (lattice nodes, then n_extra nodes at xyz strictly
+// inside the box; n_tets tetrahedra in those indices), for the element kernel.  Empty string on
+// success, else the error text.
+std::string build_mesh_general(const dd_problem_desc& d, int64_t n_extra, const double* xyz, int64_t n_tets,
+                               const int32_t* tets, HostMesh& m);
 
 }  // namespace dd

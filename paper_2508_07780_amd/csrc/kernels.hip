@@ -1006,15 +1006,20 @@ __global__ void copy_f32_kernel(float* __restrict__ d, const float* __restrict__
   for (int64_t i = (int64_t)blockIdx.x * blockDim.x + threadIdx.x; i < n; i += (int64_t)gridDim.x * blockDim.x) d[i] = s[i];
 }
 
-// eq. epsilon_sigma_constraint on the FEM lattice: eps = 1, sigma = 0 on layers 0-1,
-// eps >= 1, sigma >= 0 and finite everywhere.
-__global__ void validate_kernel(const float* eps, const float* sig, int fsx, int fsy, int fsz, int* err) {
-  const int64_t n = (int64_t)fsx * fsy * fsz;
+// eq. epsilon_sigma_constraint on the FEM nodes: eps = 1, sigma = 0 on lattice layers 0-1,
+// eps >= 1, sigma >= 0 and finite everywhere.  The n_extra nodes after the lattice (a caller
+// mesh) lie strictly inside layer 1's shell and are free.
+__global__ void validate_kernel(const float* eps, const float* sig, int fsx, int fsy, int fsz, int64_t n_extra,
+                                int* err) {
+  const int64_t n_lat = (int64_t)fsx * fsy * fsz, n = n_lat + n_extra;
   for (int64_t i = (int64_t)blockIdx.x * blockDim.x + threadIdx.x; i < n; i += (int64_t)gridDim.x * blockDim.x) {
-    const int x = (int)(i % fsx), y = (int)((i / fsx) % fsy), z = (int)(i / ((int64_t)fsx * fsy));
-    int lay = min(x, fsx - 1 - x);
-    lay = min(lay, min(y, fsy - 1 - y));
-    lay = min(lay, min(z, fsz - 1 - z));
+    int lay = 2;
+    if (i < n_lat) {
+      const int x = (int)(i % fsx), y = (int)((i / fsx) % fsy), z = (int)(i / ((int64_t)fsx * fsy));
+      lay = min(x, fsx - 1 - x);
+      lay = min(lay, min(y, fsy - 1 - y));
+      lay = min(lay, min(z, fsz - 1 - z));
+    }
     const float e = eps[i], s = sig[i];
     bool bad = !(isfinite(e) && isfinite(s)) || e < 1.f || s < 0.f;
     if (lay <= 1 && (e != 1.f || s != 0.f)) bad = true;
@@ -1229,9 +1234,10 @@ void launch_copy_f32(float* dst, const float* src, int64_t n, hipStream_t s) {
   if (n > 0) hipLaunchKernelGGL(copy_f32_kernel, dim3(grid_for(n)), dim3(256), 0, s, dst, src, n);
 }
 
-void launch_validate(const float* eps, const float* sig, int fsx, int fsy, int fsz, int* err, hipStream_t s) {
-  hipLaunchKernelGGL(validate_kernel, dim3(grid_for((int64_t)fsx * fsy * fsz)), dim3(256), 0, s, eps, sig, fsx, fsy,
-                     fsz, err);
+void launch_validate(const float* eps, const float* sig, int fsx, int fsy, int fsz, int64_t n_extra, int* err,
+                     hipStream_t s) {
+  hipLaunchKernelGGL(validate_kernel, dim3(grid_for((int64_t)fsx * fsy * fsz + n_extra)), dim3(256), 0, s, eps, sig,
+                     fsx, fsy, fsz, n_extra, err);
 }
 
 void launch_coefficients(const float* eps, const float* sig, const int* own_api, const double* mass_d, int64_t n_own,

@@ -357,14 +357,11 @@ std::string build_mesh(const dd_problem_desc& d, HostMesh& m, const int pb[3], b
 // consumes (partition halos, colours, packed connectivity, geometry table), in FP64 and
 // sequentially, checking every index against its bound and every colour for conflicts.
 // ---------------------------------------------------------------------------------------
-extern "C" int dd_debug_fem_apply(const dd_problem_desc* d, const double* eps, const double* E, int flags,
-                                  double* out, int64_t* stats) {
+namespace {
+int debug_apply(const dd_problem_desc* d, const dd::HostMesh& m, const double* eps, const double* E, int flags,
+                double* out, int64_t* stats) {
   const bool adjoint = (flags & 1) != 0, stencil = (flags & 2) != 0;
   using namespace dd;
-  if (!d || !eps || !E || !out) return DD_ERR_INVALID_ARG;
-  HostMesh m;
-  const int pb[3] = {FEM_PB, FEM_PB, FEM_PB};
-  if (!build_mesh(*d, m, pb, !stencil).empty()) return DD_ERR_UNSUPPORTED;
   const int s[3] = {d->fem_cells[0] + 1, d->fem_cells[1] + 1, d->fem_cells[2] + 1};
   const int64_t n_own = m.n_own, n_l0 = m.n_l0;
   std::vector<double> X(3 * n_own), em1(n_own), iface(3 * n_l0, 0.0);
@@ -498,3 +495,277 @@ extern "C" int dd_debug_fem_apply(const dd_problem_desc* d, const double* eps, c
   }
   return DD_OK;
 }
+}  // namespace
+
+extern "C" int dd_debug_fem_apply(const dd_problem_desc* d, const double* eps, const double* E, int flags,
+                                  double* out, int64_t* stats) {
+  if (!d || !eps || !E || !out) return DD_ERR_INVALID_ARG;
+  dd::HostMesh m;
+  const int pb[3] = {dd::FEM_PB, dd::FEM_PB, dd::FEM_PB};
+  if (!dd::build_mesh(*d, m, pb, (flags & 2) == 0).empty()) return DD_ERR_UNSUPPORTED;
+  return debug_apply(d, m, eps, E, flags, out, stats);
+}
+
+extern "C" int dd_debug_fem_apply_mesh(const dd_problem_desc* d, int64_t n_extra, const double* extra_xyz,
+                                       int64_t n_tets, const int32_t* tets, const double* eps, const double* E,
+                                       int flags, double* out, int64_t* stats) {
+  if (!d || !eps || !E || !out || (flags & 2)) return DD_ERR_INVALID_ARG;
+  dd::HostMesh m;
+  if (!dd::build_mesh_general(*d, n_extra, extra_xyz, n_tets, tets, m).empty()) return DD_ERR_UNSUPPORTED;
+  return debug_apply(d, m, eps, E, flags, out, stats);
+}
+
+namespace dd {
+
+// General tetrahedral mesh of the FEM box: the box's lattice nodes (lexicographic) and n_extra
+// extra nodes strictly inside it, and n_tets tetrahedra in those node indices.  Owned nodes
+// (lattice layer >= 1, every extra node) are grouped by lattice blocks of pb^3 (an extra node
+// joins the block of the cell it lies in); the block edge shrinks until every partition fits
+// the element kernel's limits.  Everything else is built as for the Kuhn split's element path.
+std::string build_mesh_general(const dd_problem_desc& d, int64_t n_extra, const double* xyz, int64_t n_tets,
+                               const int32_t* tv, HostMesh& m) {
+  Lattice L;
+  for (int a = 0; a < 3; ++a) {
+    L.c[a] = d.fem_cells[a];
+    L.s[a] = d.fem_cells[a] + 1;
+  }
+  const int64_t n_lat = (int64_t)L.s[0] * L.s[1] * L.s[2];
+  const int64_t n_fem = n_lat + n_extra;
+  if (n_extra < 0 || n_tets < 1 || (n_extra > 0 && !xyz) || !tv) return "null or empty mesh";
+  if (n_fem >= (1ll << 31)) return "mesh too large";
+  // node coordinates relative to the box's lower corner, in units of h
+  std::vector<std::array<double, 3>> P(n_fem);
+  for (int z = 0; z < L.s[2]; ++z)
+    for (int y = 0; y < L.s[1]; ++y)
+      for (int x = 0; x < L.s[0]; ++x) P[L.idx(x, y, z)] = {(double)x, (double)y, (double)z};
+  for (int64_t e = 0; e < n_extra; ++e)
+    for (int a = 0; a < 3; ++a) {
+      const double u = (xyz[3 * e + a] - d.origin[a]) / d.h - d.fem_lo[a];
+      if (!(u > 0.0 && u < L.c[a])) return "an extra node lies outside the FEM box's interior";
+      P[n_lat + e][a] = u;
+    }
+  auto layer_of = [&](int64_t i) -> int {
+    if (i >= n_lat) return 2;   // extra nodes are free
+    const int x = (int)(i % L.s[0]), y = (int)((i / L.s[0]) % L.s[1]), z = (int)(i / ((int64_t)L.s[0] * L.s[1]));
+    return L.layer(x, y, z);
+  };
+  // geometry (FP64, lengths in h scaled back to physical units), volumes, node -> tets
+  std::vector<int> deg(n_fem + 1, 0);
+  double vol_sum = 0.0;
+  for (int64_t t = 0; t < n_tets; ++t) {
+    double p[4][3], g[4][3], vol;
+    for (int k = 0; k < 4; ++k) {
+      const int64_t v = tv[4 * t + k];
+      if (v < 0 || v >= n_fem) return "a tetrahedron references a node that does not exist";
+      for (int a = 0; a < 3; ++a) p[k][a] = d.h * (P[v][a] - P[tv[4 * t]][a]);
+      ++deg[v];
+    }
+    if (!tet_geometry(p, g, &vol)) return "degenerate tetrahedron";
+    vol_sum += vol;
+  }
+  const double box = d.h * d.h * d.h * (double)L.c[0] * L.c[1] * L.c[2];
+  if (std::fabs(vol_sum - box) > 1e-9 * box) return "the tetrahedra do not fill the FEM box";
+  std::vector<int> adj_off(n_fem + 1, 0), adj(4 * n_tets);
+  for (int64_t i = 0; i < n_fem; ++i) adj_off[i + 1] = adj_off[i] + deg[i];
+  {
+    std::vector<int> fill(adj_off.begin(), adj_off.end() - 1);
+    for (int64_t t = 0; t < n_tets; ++t)
+      for (int k = 0; k < 4; ++k) adj[fill[tv[4 * t + k]]++] = (int)t;
+  }
+  for (int64_t i = 0; i < n_fem; ++i)
+    if (layer_of(i) >= 1 && deg[i] == 0) return "a FEM-owned node lies on no tetrahedron";
+
+  // the geometry table, deduplicated on the float32 image of the FP64 geometry
+  std::map<std::array<uint32_t, 13>, int> geom_ids;
+  m.geom.clear();
+  std::vector<int> tgid(n_tets);
+  for (int64_t t = 0; t < n_tets; ++t) {
+    double p[4][3], g[4][3], vol;
+    for (int k = 0; k < 4; ++k)
+      for (int a = 0; a < 3; ++a) p[k][a] = d.h * (P[tv[4 * t + k]][a] - P[tv[4 * t]][a]);
+    tet_geometry(p, g, &vol);
+    std::array<uint32_t, 13> key;
+    float f[13];
+    for (int j = 0; j < 4; ++j)
+      for (int a = 0; a < 3; ++a) f[3 * j + a] = (float)g[j][a];
+    f[12] = (float)vol;
+    for (int i = 0; i < 13; ++i) std::memcpy(&key[i], &f[i], 4);
+    auto it = geom_ids.find(key);
+    if (it == geom_ids.end()) {
+      const int id = (int)geom_ids.size();
+      if (id >= (1 << 20)) return "geometry table exceeds 2^20 entries";
+      it = geom_ids.emplace(key, id).first;
+      for (int i = 0; i < 12; ++i) m.geom.push_back(f[i]);
+      for (int i = 0; i < 12; ++i) m.geom.push_back((float)(vol * g[i / 3][i % 3]));
+      m.geom.push_back(f[12]);
+      for (int i = 25; i < GEOM_STRIDE; ++i) m.geom.push_back(0.f);
+    }
+    tgid[t] = it->second;
+  }
+  m.n_geom = (int)geom_ids.size();
+  m.n_fem = n_fem;
+  m.n_l0 = face_lex_count(L.s[0], L.s[1], L.s[2], 63u);
+  m.stencil_ok = false;
+  m.n_slots = 0;
+
+  // partitions: owned nodes by lattice block; try block edges 8, 6, 4, 3, 2
+  for (int pb : {8, 6, 4, 3, 2}) {
+    const int ow[3] = {L.c[0] - 1, L.c[1] - 1, L.c[2] - 1};
+    int npb[3];
+    for (int a = 0; a < 3; ++a) npb[a] = (ow[a] + pb - 1) / pb;
+    const int n_part = npb[0] * npb[1] * npb[2];
+    auto block_of = [&](const std::array<double, 3>& q) {
+      int b[3];
+      for (int a = 0; a < 3; ++a) {
+        // lattice owned coordinate 1..c-1 -> block; an extra node takes its cell's lower corner
+        int c = (int)std::floor(q[a]);
+        c = std::min(std::max(c, 1), L.c[a] - 1);
+        b[a] = (c - 1) / pb;
+      }
+      return b[0] + npb[0] * (b[1] + npb[1] * b[2]);
+    };
+    std::vector<std::vector<int64_t>> members(n_part);
+    for (int64_t i = 0; i < n_fem; ++i)
+      if (layer_of(i) >= 1) members[block_of(P[i])].push_back(i);   // lattice first, then extra: index order
+    // internal numbering: partition-major
+    std::vector<int> code(n_fem);
+    for (int z = 0; z < L.s[2]; ++z)
+      for (int y = 0; y < L.s[1]; ++y)
+        for (int x = 0; x < L.s[0]; ++x)
+          if (L.layer(x, y, z) == 0)
+            code[L.idx(x, y, z)] = -1 - (int)face_lex_index(x, y, z, L.s[0], L.s[1], L.s[2], 63u);
+    HostMesh q;
+    q.n_fem = n_fem;
+    q.n_l0 = m.n_l0;
+    q.n_part = n_part;
+    q.own_off.assign(n_part + 1, 0);
+    int next = 0;
+    for (int p = 0; p < n_part; ++p) {
+      q.own_off[p] = next;
+      for (int64_t i : members[p]) code[i] = next++;
+    }
+    q.own_off[n_part] = next;
+    q.n_own = next;
+    q.own_grid.assign(next, -1);
+    q.own_api.assign(next, 0);
+    q.mass.assign(next, 0.0);
+    for (int p = 0; p < n_part; ++p)
+      for (int64_t i : members[p]) {
+        const int id = code[i];
+        q.own_api[id] = (int)i;
+        if (i < n_lat && layer_of(i) == 1) {
+          const int x = (int)(i % L.s[0]), y = (int)((i / L.s[0]) % L.s[1]), z = (int)(i / ((int64_t)L.s[0] * L.s[1]));
+          const int64_t gx = d.fem_lo[0] + x, gy = d.fem_lo[1] + y, gz = d.fem_lo[2] + z;
+          q.own_grid[id] = (int)(gx + (int64_t)d.n_outer[0] * (gy + (int64_t)d.n_outer[1] * gz));
+        }
+        double ms = 0.0;   // lumped mass: |K| / 4 over the incident tetrahedra, in index order
+        for (int a = adj_off[i]; a < adj_off[i + 1]; ++a) {
+          const int t = adj[a];
+          double pp[4][3], g[4][3], vol;
+          for (int k = 0; k < 4; ++k)
+            for (int c = 0; c < 3; ++c) pp[k][c] = d.h * (P[tv[4 * t + k]][c] - P[tv[4 * t]][c]);
+          tet_geometry(pp, g, &vol);
+          ms += vol / 4.0;
+        }
+        q.mass[id] = ms;
+      }
+    q.halo_off.assign(n_part + 1, 0);
+    q.col_base.assign(n_part, 0);
+    q.ncol.assign(n_part, 0);
+    std::vector<int> stamp(n_tets, -1), loc_of(n_fem, 0), loc_stamp(n_fem, -1);
+    bool fits = true;
+    for (int p = 0; p < n_part && fits; ++p) {
+      const int o0 = q.own_off[p], no = q.own_off[p + 1] - o0;
+      std::vector<int> els;
+      for (int64_t i : members[p])
+        for (int a = adj_off[i]; a < adj_off[i + 1]; ++a)
+          if (stamp[adj[a]] != p) {
+            stamp[adj[a]] = p;
+            els.push_back(adj[a]);
+          }
+      std::sort(els.begin(), els.end());
+      auto owned_here = [&](int64_t v) { return layer_of(v) >= 1 && code[v] >= o0 && code[v] < o0 + no; };
+      auto code_less = [](int a, int b) {
+        if ((a >= 0) != (b >= 0)) return a >= 0;
+        return a >= 0 ? a < b : a > b;
+      };
+      std::vector<int> hcodes;
+      for (int t : els)
+        for (int k = 0; k < 4; ++k)
+          if (!owned_here(tv[4 * t + k])) hcodes.push_back(code[tv[4 * t + k]]);
+      std::sort(hcodes.begin(), hcodes.end(), code_less);
+      hcodes.erase(std::unique(hcodes.begin(), hcodes.end()), hcodes.end());
+      const int nl = no + (int)hcodes.size();
+      if (nl > FEM_LOC_MAX || no > FEM_OWN_MAX || (int)els.size() > FEM_ELEM_MAX) {
+        fits = false;
+        break;
+      }
+      q.max_loc = std::max(q.max_loc, nl);
+      q.max_own = std::max(q.max_own, no);
+      q.max_elem = std::max(q.max_elem, (int)els.size());
+      for (int t : els)
+        for (int k = 0; k < 4; ++k) {
+          const int64_t v = tv[4 * t + k];
+          if (owned_here(v)) continue;
+          if (loc_stamp[v] != p) {
+            loc_stamp[v] = p;
+            loc_of[v] = no + (int)(std::lower_bound(hcodes.begin(), hcodes.end(), code[v], code_less) - hcodes.begin());
+          }
+        }
+      q.halo_off[p] = (int)q.halo.size();
+      q.halo.insert(q.halo.end(), hcodes.begin(), hcodes.end());
+      struct Pk { int loc[4]; int gid; int color; };
+      std::vector<Pk> pk(els.size());
+      std::vector<uint64_t> used(no, 0);
+      int ncol = 0;
+      for (size_t e = 0; e < els.size(); ++e) {
+        const int t = els[e];
+        uint64_t forbid = 0;
+        for (int k = 0; k < 4; ++k) {
+          const int64_t v = tv[4 * t + k];
+          const int loc = owned_here(v) ? code[v] - o0 : loc_of[v];
+          pk[e].loc[k] = loc;
+          if (loc < no) forbid |= used[loc];
+        }
+        if (forbid == ~0ull) {
+          fits = false;
+          break;
+        }
+        int c = 0;
+        while (forbid & (1ull << c)) ++c;
+        pk[e].color = c;
+        pk[e].gid = tgid[t];
+        for (int k = 0; k < 4; ++k)
+          if (pk[e].loc[k] < no) used[pk[e].loc[k]] |= (1ull << c);
+        ncol = std::max(ncol, c + 1);
+      }
+      if (!fits) break;
+      q.max_colors = std::max(q.max_colors, ncol);
+      std::stable_sort(pk.begin(), pk.end(), [](const Pk& a, const Pk& b) { return a.color < b.color; });
+      q.col_base[p] = (int)q.col_off.size();
+      q.ncol[p] = ncol;
+      const int e0 = (int)q.elems.size();
+      size_t i = 0;
+      for (int c = 0; c <= ncol; ++c) {
+        while (i < pk.size() && pk[i].color < c) ++i;
+        q.col_off.push_back(e0 + (int)i);
+      }
+      for (const auto& r : pk) {
+        uint64_t w = 0;
+        for (int k = 0; k < 4; ++k) w |= (uint64_t)(r.loc[k] & 0x7FF) << (11 * k);
+        w |= (uint64_t)r.gid << 44;
+        q.elems.push_back(w);
+      }
+    }
+    if (!fits) continue;
+    q.halo_off[n_part] = (int)q.halo.size();
+    q.geom.swap(m.geom);
+    q.n_geom = m.n_geom;
+    q.stencil_ok = false;
+    m = std::move(q);
+    return std::string();
+  }
+  return "the mesh is too dense for the FEM kernel's partitions";
+}
+
+}  // namespace dd

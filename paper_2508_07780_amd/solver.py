@@ -6,6 +6,8 @@ current stream; every step of the solve runs in the library's HIP kernels.
 
 import ctypes
 
+import numpy as np
+
 import torch
 
 from . import _lib
@@ -62,9 +64,13 @@ class TorchAllocator:
 class Problem:
     """A hybrid FE/FD problem resident on the current GPU.  Its device state is allocated
     through torch's caching allocator (allocator="torch", the default) or by the library
-    with hipMalloc (allocator=None)."""
+    with hipMalloc (allocator=None).
 
-    def __init__(self, desc, allocator="torch"):
+    mesh: None (the Kuhn split of the FEM box) or (extra_xyz, tets), a general tetrahedral mesh
+    of the box: extra nodes (n_extra x 3, physical coordinates, strictly inside the box) after
+    the lattice nodes, tetrahedra (n_tets x 4) in FEM-node indices (dd_create_mesh)."""
+
+    def __init__(self, desc, allocator="torch", mesh=None):
         lib = _lib.load()
         self.desc = desc
         self._cdesc = _lib.make_desc(desc)
@@ -72,13 +78,20 @@ class Problem:
         self.allocator = None
         if allocator == "torch":
             self.allocator = TorchAllocator(torch.cuda.current_device())
-            _lib.check(lib.dd_create(ctypes.byref(self._cdesc), self.allocator.alloc_fn, self.allocator.free_fn,
-                                     None, ctypes.byref(h)))
+            fns = (self.allocator.alloc_fn, self.allocator.free_fn)
         elif allocator is None:
-            _lib.check(lib.dd_create(ctypes.byref(self._cdesc), _lib.ALLOC_FN(), _lib.FREE_FN(), None,
-                                     ctypes.byref(h)))
+            fns = (_lib.ALLOC_FN(), _lib.FREE_FN())
         else:
             raise ValueError('allocator must be "torch" or None')
+        if mesh is None:
+            _lib.check(lib.dd_create(ctypes.byref(self._cdesc), *fns, None, ctypes.byref(h)))
+        else:
+            xyz = np.ascontiguousarray(np.asarray(mesh[0], dtype=np.float64).reshape(-1, 3))
+            tets = np.ascontiguousarray(np.asarray(mesh[1], dtype=np.int32).reshape(-1, 4))
+            _lib.check(lib.dd_create_mesh(ctypes.byref(self._cdesc), len(xyz),
+                                          xyz.ctypes.data_as(ctypes.POINTER(ctypes.c_double)), len(tets),
+                                          tets.ctypes.data_as(ctypes.POINTER(ctypes.c_int32)), *fns, None,
+                                          ctypes.byref(h)))
         self._h = h
         nf, nd, ng = ctypes.c_int64(), ctypes.c_int64(), ctypes.c_int64()
         _lib.check(lib.dd_sizes(h, ctypes.byref(nf), ctypes.byref(nd), ctypes.byref(ng)), h)

@@ -219,3 +219,79 @@ def test_footprint_covers_store_all_and_the_defaults_of_zeroed_fields(lib):
     assert store_all == lib.dd_footprint_bytes(ctypes.byref(c), 1) > 4 * k64
     c.overlap, c.s_stab = 0, 0.0
     assert lib.dd_footprint_bytes(ctypes.byref(c), 1) == store_all
+
+
+def _refined_case(name, beta=0.5):
+    w = synth.small(name)
+    marks = synth.meshref_marks(w.desc, w.eps, beta)
+    mesh = synth.refined_mesh(w.desc, marks)
+    eps = synth.refined_values(w.desc, marks, w.eps)
+    return w, marks, mesh, eps
+
+
+@pytest.mark.parametrize("name,beta", [("tiny", 0.5), ("skinlet", 0.3), ("ragged", 0.0)])
+def test_general_mesh_data_path_reproduces_oracle_operator(lib, name, beta):
+    """The element data dd_create_mesh builds from a refined mesh (eq. meshref: marked cells get
+    their centre and bisected Kuhn tetrahedra) reproduce the oracle's FEM rows of A and A^T on
+    that mesh; beta = 0 marks every cell whose corners are FEM-owned."""
+    from paper_2508_07780_amd import _lib
+    w, marks, (xyz, tets), eps = _refined_case(name, beta)
+    assert marks.sum() > 0
+    d = Discretization(w.desc, mesh=(xyz, tets)).set_coefficients(eps, np.zeros_like(eps))
+    E = np.random.default_rng(5).standard_normal((d.N, 3))
+    Ef = np.ascontiguousarray(E[d.fem_grid])
+    out = np.zeros((d.n_fem, 3))
+    st = np.zeros(8, dtype=np.int64)
+    c = _lib.make_desc(w.desc)
+    xyz = np.ascontiguousarray(xyz, dtype=np.float64)
+    tets = np.ascontiguousarray(tets, dtype=np.int32)
+    eps = np.ascontiguousarray(eps)
+    own = d.fem_owned
+    for flags, ref in ((0, d.apply_A(E)), (1, d.apply_AT(E))):
+        rc = lib.dd_debug_fem_apply_mesh(ctypes.byref(c), len(xyz), xyz.ctypes.data, len(tets), tets.ctypes.data,
+                                         eps.ctypes.data, Ef.ctypes.data, flags, out.ctypes.data, st.ctypes.data)
+        assert rc == 0
+        r = ref[d.fem_grid]
+        assert np.abs(out[own] - r[own]).max() <= 2e-7 * np.abs(r[own]).max()
+        assert np.all(out[~own] == 0)
+    assert st[5] == own.sum() and st[6] == (d.fem_layer == 0).sum()
+    assert st[1] <= 64 and st[2] <= 1024
+    assert lib.dd_debug_fem_apply_mesh(ctypes.byref(c), len(xyz), xyz.ctypes.data, len(tets), tets.ctypes.data,
+                                       eps.ctypes.data, Ef.ctypes.data, 2, out.ctypes.data, None) == -1
+
+
+def test_malformed_general_meshes_are_refused(lib):
+    """A mesh that does not fill the box, a node outside it, an index out of range and a
+    degenerate tetrahedron are refused by the builder before any device work."""
+    from paper_2508_07780_amd import _lib
+    w, marks, (xyz, tets), eps = _refined_case("tiny")
+    c = _lib.make_desc(w.desc)
+
+    def rc(x, t):
+        x = np.ascontiguousarray(x, dtype=np.float64)
+        t = np.ascontiguousarray(t, dtype=np.int32)
+        e = np.ones(int(np.prod(np.asarray(w.desc.fem_cells) + 1)) + len(x))
+        ee = np.zeros((len(e), 3))
+        res = np.zeros_like(ee)
+        return lib.dd_debug_fem_apply_mesh(ctypes.byref(c), len(x), x.ctypes.data if len(x) else None, len(t),
+                                           t.ctypes.data, e.ctypes.data, ee.ctypes.data, 0, res.ctypes.data, None)
+
+    assert rc(xyz, tets) == 0
+    assert rc(xyz, tets[:-1]) == -7                      # does not fill the box
+    bad = xyz.copy()
+    bad[0, 2] = w.desc.origin[2] + w.desc.h * (w.desc.fem_lo[2] - 0.5)
+    assert rc(bad, tets) == -7                           # extra node outside the box
+    t2 = tets.copy()
+    t2[0, 1] = len(eps) + 3
+    assert rc(xyz, t2) == -7                             # index out of range
+    t3 = tets.copy()
+    t3[0, 1] = t3[0, 0]
+    assert rc(xyz, t3) == -7                             # degenerate
+    h = ctypes.c_void_p()
+    x = np.ascontiguousarray(xyz, dtype=np.float64)
+    t = np.ascontiguousarray(tets[:-1], dtype=np.int32)
+    # dd_create_mesh reports a malformed mesh as an argument error, before any device work
+    assert lib.dd_create_mesh(ctypes.byref(c), len(x), x.ctypes.data_as(ctypes.POINTER(ctypes.c_double)), len(t),
+                              t.ctypes.data_as(ctypes.POINTER(ctypes.c_int32)), _lib.ALLOC_FN(), _lib.FREE_FN(),
+                              None, ctypes.byref(h)) == -1
+    assert not h.value

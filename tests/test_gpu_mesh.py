@@ -1,0 +1,164 @@
+"""General (locally refined) FEM meshes on the GPU (dd_create_mesh) against the FP64 oracle.
+
+The meshes are those of eq. meshref after one refinement of the uniform starting mesh: cells
+where |eps| >= beta max |eps| at a corner get their centre as a node and their six Kuhn
+tetrahedra bisected across the main diagonal (synth.refined_mesh).  The FEM rows then run on
+the element-coloured kernel with the library's partitions of the caller's tetrahedra; dt is
+0.8 times the explicit scheme's limit on the refined mesh (power iteration on the oracle's
+operator), which the refined cells push below the uniform mesh's h / sqrt(3).  Bars as everywhere: traces rel L2 <= 1e-4, gradient rel L2 <= 1e-3 (over every FEM
+node, the inserted centres included).  Also: the Kuhn split passed as a general mesh against
+the default path, the constraint check with free extra nodes, and the refused forms.
+"""
+
+import math
+
+import numpy as np
+import pytest
+
+import synth
+from oracle.discretization import Discretization
+from oracle.solver import adjoint_gradient, forward
+pytestmark = pytest.mark.gpu
+
+TRACE_TOL, GRAD_TOL = 1e-4, 1e-3
+
+
+def _rel(a, b):
+    return float(np.linalg.norm(np.asarray(a, dtype=np.float64) - b) / np.linalg.norm(b))
+
+
+def _f32(x):
+    return np.asarray(x, dtype=np.float32).astype(np.float64)
+
+
+def step_limit(d, iters=300, seed=0):
+    """The explicit scheme's step limit 2 / sqrt(lambda_max(M_eps^-1 A)) on the oracle's
+    operator (power iteration, which approaches lambda_max from below)."""
+    v = np.random.default_rng(seed).standard_normal((d.N, 3))
+    lam = 0.0
+    for _ in range(iters):
+        u = d.apply_A(v) / d.M_eps[:, None]
+        lam = float(np.linalg.norm(u) / np.linalg.norm(v))
+        v = u / np.linalg.norm(u)
+    return 2.0 / math.sqrt(lam)
+
+
+def _refined(name, beta):
+    w = synth.small(name)
+    marks = synth.meshref_marks(w.desc, w.eps, beta)
+    mesh = synth.refined_mesh(w.desc, marks)
+    eps = _f32(synth.refined_values(w.desc, marks, w.eps))
+    sig = _f32(synth.refined_values(w.desc, marks, w.sigma))
+    # the refined cells lower the limit below the uniform mesh's h / sqrt(3): they set dt
+    lim = step_limit(Discretization(w.desc, mesh=mesh).set_coefficients(eps, sig))
+    assert lim < w.desc.h / math.sqrt(3.0)
+    w.desc.dt = 0.8 * lim
+    return w, marks, mesh, eps, sig
+
+
+def _problem(torch, w, mesh, eps, sig):
+    from paper_2508_07780_amd import Problem
+    p = Problem(w.desc, mesh=mesh)
+    p.set_coefficients(torch.tensor(eps, dtype=torch.float32, device="cuda"),
+                       torch.tensor(sig, dtype=torch.float32, device="cuda"))
+    return p
+
+
+@pytest.mark.parametrize("name,beta", [("tiny", 0.5), ("skinlet", 0.3), ("ragged", 0.6)])
+def test_refined_mesh_matches_oracle(name, beta):
+    import torch
+    w, marks, mesh, eps, sig = _refined(name, beta)
+    print(f"[gpu] refined mesh {name} beta {beta}: {int(marks.sum())} cells refined, "
+          f"{len(mesh[0])} centres, {len(mesh[1])} tets, dt {w.desc.dt:.4g}, steps {w.desc.n_steps}", flush=True)
+    d = Discretization(w.desc, mesh=mesh).set_coefficients(eps, sig)
+    fw = forward(d, w.sources[0])
+    eobs = (0.6 * fw["traces"]).astype(np.float32)
+    ag = adjoint_gradient(d, fw["traces"] - eobs.astype(np.float64), fw)
+    p = _problem(torch, w, mesh, eps, sig)
+    assert p.n_fem == d.n_fem
+    tr = p.forward(w.sources, save=True)
+    p.adjoint_misfit(tr, torch.tensor(eobs[None], device="cuda"))
+    ge, gs = (g.cpu().numpy() for g in p.gradient())
+    et = _rel(tr[0].cpu().numpy(), fw["traces"])
+    e1, e2 = _rel(ge, ag["g_eps"]), _rel(gs, ag["g_sigma"])
+    c = slice(d.n_fem - d.n_extra, d.n_fem)
+    ec = _rel(ge[c], ag["g_eps"][c])
+    print(f"[gpu]   traces {et:.2e} g_eps {e1:.2e} (centres {ec:.2e}) g_sigma {e2:.2e}", flush=True)
+    assert et <= TRACE_TOL and e1 <= GRAD_TOL and e2 <= GRAD_TOL and ec <= GRAD_TOL
+    # the energy of the refined mesh's scheme (FD + FEM masses of the caller's mesh)
+    _, en = p.forward(w.sources, save=False, energy=True)
+    ee = _rel(en[0].cpu().numpy(), fw["energy"])
+    print(f"[gpu]   energy {ee:.2e}", flush=True)
+    assert ee <= TRACE_TOL
+    p.close()
+
+
+def test_kuhn_split_as_a_general_mesh_matches_the_default_path():
+    """No cell marked: the caller's mesh is the Kuhn split, so traces and gradient equal those of
+    the default problem up to the order of the float32 sums (other partitions and colours)."""
+    import torch
+    from paper_2508_07780_amd import Problem
+    w = synth.small("ragged")
+    none = np.zeros(int(np.prod(w.desc.fem_cells)), dtype=bool)
+    mesh = synth.refined_mesh(w.desc, none)
+    eps, sig = _f32(w.eps), _f32(w.sigma)
+    q = Problem(w.desc)
+    q.set_coefficients(torch.tensor(eps, dtype=torch.float32, device="cuda"),
+                       torch.tensor(sig, dtype=torch.float32, device="cuda"))
+    p = _problem(torch, w, mesh, eps, sig)
+    obs = torch.tensor(1e-3 * synth.noise((1, w.desc.n_steps, q.n_det, 3), 7), dtype=torch.float32, device="cuda")
+    out = []
+    for r in (q, p):
+        tr = r.forward(w.sources, save=True).clone()
+        r.adjoint_misfit(tr, obs)
+        out.append((tr.cpu().numpy(), *(g.cpu().numpy() for g in r.gradient())))
+    print(f"[gpu] Kuhn split as a general mesh: traces {_rel(out[1][0], out[0][0]):.2e} "
+          f"g_eps {_rel(out[1][1], out[0][1]):.2e}", flush=True)
+    assert _rel(out[1][0], out[0][0]) <= 1e-5
+    assert _rel(out[1][1], out[0][1]) <= 1e-4 and _rel(out[1][2], out[0][2]) <= 1e-4
+    p.close()
+    q.close()
+
+
+def test_constraints_and_refused_forms_on_a_general_mesh():
+    """Extra nodes are free (eps > 1 accepted there); layer-1 lattice nodes still must hold
+    eps = 1.  R2, the paper-formula gradient, initial data, CGA and batched jobs are refused."""
+    import torch
+    from paper_2508_07780_amd import DDError
+    from paper_2508_07780_amd.batch import Batch
+    from paper_2508_07780_amd.cga import CGA, CGAParams
+    w, marks, mesh, eps, sig = _refined("tiny", 0.5)
+    p = _problem(torch, w, mesh, eps, sig)
+    n_lat = int(np.prod(np.asarray(w.desc.fem_cells) + 1))
+    e2 = eps.copy()
+    e2[n_lat:] = 2.5
+    p.set_coefficients(torch.tensor(e2, dtype=torch.float32, device="cuda"),
+                       torch.tensor(sig, dtype=torch.float32, device="cuda"))
+    lay = synth.fem_layers(w.desc)
+    e3 = eps.copy()
+    e3[int(np.nonzero(lay == 1)[0][0])] = 1.5
+    with pytest.raises(DDError) as e:
+        p.set_coefficients(torch.tensor(e3, dtype=torch.float32, device="cuda"),
+                           torch.tensor(sig, dtype=torch.float32, device="cuda"))
+    assert e.value.code == -2
+    for call in (lambda: p.set_divdiv_form("R2"), lambda: p.paper_gradient(True),
+                 lambda: p.set_initial_data(torch.zeros(3 * p.n_grid, device="cuda"),
+                                            torch.zeros(3 * p.n_grid, device="cuda"))):
+        with pytest.raises(DDError) as e:
+            call()
+        assert e.value.code == -7
+    obs = torch.zeros((1, w.desc.n_steps, p.n_det, 3), dtype=torch.float32, device="cuda")
+    with pytest.raises(DDError) as e:
+        CGA(p, w.sources, obs, torch.tensor(eps, dtype=torch.float32, device="cuda"),
+            torch.tensor(sig, dtype=torch.float32, device="cuda"),
+            CGAParams(gamma_eps=1.0, gamma_sig=1.0, p=0.5, alpha_eps=1.0, alpha_sig=1.0, eps_max=10.0, sig_max=1.0))
+    assert e.value.code == -7
+    b = Batch(2)
+    with pytest.raises(DDError) as e:
+        b.submit(p, w.sources, obs=obs)
+    assert e.value.code == -7
+    b.close()
+    # still usable after the refusals
+    tr = p.forward(w.sources, save=False)
+    assert torch.isfinite(tr).all()
+    p.close()
