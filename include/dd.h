@@ -445,7 +445,12 @@ enum {
   DD_PROF_FD_FWD = 0, DD_PROF_FEM_FWD = 1, DD_PROF_FD_ADJ = 2, DD_PROF_FEM_ADJ = 3,
   DD_PROF_FEM_RECOMPUTE = 4,
   DD_PROF_STEP_FWD = 5, DD_PROF_STEP_ADJ = 6,  /* fused FD + FEM step launches */
-  DD_PROF_KINDS = 7
+  /* two-step launches (temporal blocking of the FD region, switched on by the environment
+   * variable DD_TB=1 at dd_create; forwards without energy and adjoints of the form R1 without
+   * the paper-formula variant or initial data take them): the first launch of a pair (FD
+   * tiles away from the FEM box two steps, the rest one) and the second (near tiles and FEM) */
+  DD_PROF_PAIR_FWD = 7, DD_PROF_PAIR_ADJ = 8, DD_PROF_PAIR2_FWD = 9, DD_PROF_PAIR2_ADJ = 10,
+  DD_PROF_KINDS = 11
 };
 int dd_profile_enable(dd_problem* p, int32_t stride);
 int dd_profile_read(dd_problem* p, int32_t kind, double* total_ms, int64_t* launches, int32_t reset);

@@ -23,9 +23,10 @@ EXPORTS = [
     "dd_cga_steps_from_gradient", "dd_create_mesh", "dd_debug_fem_apply_mesh",
 ]
 
-PROF_FD_FWD, PROF_FEM_FWD, PROF_FD_ADJ, PROF_FEM_ADJ, PROF_FEM_RECOMPUTE, PROF_STEP_FWD, PROF_STEP_ADJ = range(7)
+(PROF_FD_FWD, PROF_FEM_FWD, PROF_FD_ADJ, PROF_FEM_ADJ, PROF_FEM_RECOMPUTE, PROF_STEP_FWD, PROF_STEP_ADJ,
+ PROF_PAIR_FWD, PROF_PAIR_ADJ, PROF_PAIR2_FWD, PROF_PAIR2_ADJ) = range(11)
 PROF_NAMES = ["fd_step_fwd", "fem_step_fwd", "fd_step_adj", "fem_step_adj", "fem_step_recompute",
-              "step_fwd", "step_adj"]
+              "step_fwd", "step_adj", "pair_fwd", "pair_adj", "pair2_fwd", "pair2_adj"]
 
 
 CKPT_FEM_IFACE, CKPT_STORE_ALL, CKPT_FULL = 0, 1, 2

@@ -50,7 +50,13 @@ struct dd_problem {
   size_t alloc_bytes = 0;     // bytes currently allocated
   // state (device)
   // FD grid: two levels of E (three-level form); FEM: two levels of E and the increment V
-  float *Efd[2] = {nullptr, nullptr}, *Efem[2] = {nullptr, nullptr}, *Vfem = nullptr;
+  float *Efd[4] = {nullptr, nullptr, nullptr, nullptr}, *Efem[2] = {nullptr, nullptr}, *Vfem = nullptr;
+  // temporal blocking (two FD steps per launch for the tiles away from the FEM box): level n
+  // of the FD grid in Efd[n & 3]; the two-step tile grid, its near-tile list and node counts
+  bool tb = false, tb_nt = false;
+  int tb_nbz = 0, tb_ntiles = 0, tb_per_xcd = 0, tb_nlist = 0;
+  int* tb_list = nullptr;
+  int64_t tb_far = 0, tb_near = 0;   // FD-updated nodes of far / near tiles
   float* iring = nullptr;  // [2][3][n_l0]
   double* epart = nullptr;
   int* d_err = nullptr;
@@ -102,7 +108,7 @@ constexpr size_t kProfMaxPairs = 16384;
 // Kernel timing: a window of `prof_window(kind)` consecutive launches of one kind is
 // bracketed by one event pair every `prof_stride` launches.  Windows of several launches
 // amortise the event markers; they are used only for kinds that are launched back to back
-// (the fused step kernels), single launches otherwise.
+// (the fused one-step kernels), single launches otherwise (the two launches of a pair alternate).
 int prof_window(int kind) { return (kind == DD_PROF_STEP_FWD || kind == DD_PROF_STEP_ADJ) ? 8 : 1; }
 
 long prof_begin(dd_problem* p, int kind, hipStream_t st) {
@@ -268,6 +274,8 @@ FdArgs fd_base(const dd_problem* p) {
   a.dt2_h3 = (float)(p->d.dt * p->d.dt / (p->d.h * p->d.h * p->d.h));
   a.n_l0 = p->n_l0;
   a.e_coef = p->d.h * p->d.h * p->d.h / (2.0 * p->d.dt * p->d.dt);
+  a.tb_nbz = p->tb_nbz; a.tb_ntiles = p->tb_ntiles; a.tb_per_xcd = p->tb_per_xcd;
+  a.tb_list = p->tb_list; a.tb_nlist = p->tb_nlist;
   return a;
 }
 
@@ -308,10 +316,9 @@ void fem_adj(const dd_problem* p, const FemArgs& a, hipStream_t st) {
 }
 
 void zero_state(dd_problem* p, hipStream_t st) {
-  for (int b = 0; b < 2; ++b) {
-    launch_fill_f32(p->Efd[b], 3 * p->N, 0.f, st);
-    launch_fill_f32(p->Efem[b], 3 * p->n_own, 0.f, st);
-  }
+  for (int b = 0; b < 4; ++b)
+    if (p->Efd[b]) launch_fill_f32(p->Efd[b], 3 * p->N, 0.f, st);
+  for (int b = 0; b < 2; ++b) launch_fill_f32(p->Efem[b], 3 * p->n_own, 0.f, st);
   launch_fill_f32(p->Vfem, 3 * p->n_own, 0.f, st);
   launch_fill_f32(p->iring, 6 * p->n_l0, 0.f, st);
 }
@@ -544,6 +551,39 @@ void adj_step_args(const dd_problem* p, int s, int64_t k, int64_t k0, const floa
   ea.g_sig = p->g_sig;
 }
 
+// The per-step data of a step's FD arguments (the second step of a two-step launch).
+FdStepData step_data(const FdArgs& f) {
+  FdStepData d;
+  for (int c = 0; c < 3; ++c) {
+    d.pw[c] = f.pw[c];
+    d.dip[c] = f.dip[c];
+  }
+  d.top_a = f.top_a; d.top_b = f.top_b; d.pw_kind = f.pw_kind; d.pw_t = f.pw_t;
+  d.tr_out = f.tr_out; d.cot_in = f.cot_in; d.obs_in = f.obs_in;
+  return d;
+}
+
+// Temporal blocking: FD levels in four rotating buffers, level m in Efd[m & 3].  A step from
+// level `from` to level `to` (= from + 1 forward, from - 1 adjoint) reads `from` and the level
+// on the other side of it, and writes `to`; the FEM dual-writes layer 1 of `to`.
+void tb_levels(const dd_problem* p, int64_t from, int64_t to, FdArgs& fa, FemArgs& ea) {
+  const int64_t other = 2 * from - to;
+  fa.X_in = p->Efd[from & 3];
+  fa.X_prev = p->Efd[other & 3];
+  fa.X_out = p->Efd[to & 3];
+  ea.fd_out = p->Efd[to & 3];
+}
+
+// Whether the forward / adjoint of this problem takes two-step launches: the fused one-stream
+// path with the div-div form R1, no energy, no initial data (and, for the adjoint, without the
+// paper-formula variant's extra terms).
+bool tb_forward(const dd_problem* p, bool energy) {
+  return p->tb && p->use_stencil && p->fused && !p->overlap && !p->r2 && !p->init_on && !energy;
+}
+bool tb_adjoint(const dd_problem* p) {
+  return p->tb && p->use_stencil && p->fused && !p->overlap && !p->r2 && !p->pg_on && !p->init_on;
+}
+
 int run_forward(dd_problem* p, const dd_source& src, int s, float* traces, bool save, double* energy, hipStream_t st) {
   const int64_t nt = p->d.n_steps;
   forward_prologue(p, s, save, true, st);
@@ -555,10 +595,33 @@ int run_forward(dd_problem* p, const dd_source& src, int s, float* traces, bool 
   fa.epart = energy ? p->epart : nullptr;
   ea.epart = energy ? p->epart : nullptr;
   const bool fused = p->use_stencil && p->fused;
+  const bool tb = tb_forward(p, energy != nullptr);
   for (int64_t n = 0; n < nt; ++n) {
     fwd_step_args(p, src, sp, s, n, traces, save, fa, ea);
     long ps = -1;
-    if (fused) {
+    if (tb) {
+      tb_levels(p, n, n + 1, fa, ea);
+      if ((n & 1) == 0 && n + 1 < nt) {
+        // first launch of a pair: far tiles also take step n + 1
+        FdArgs f2 = fa;
+        FemArgs e2 = ea;
+        fwd_step_args(p, src, sp, s, n + 1, traces, save, f2, e2);
+        fa.s2 = step_data(f2);
+        fa.X_out2 = p->Efd[(n + 2) & 3];
+        ps = prof_begin(p, DD_PROF_PAIR_FWD, st);
+        launch_step_pair(fa, ea, st, false, p->tb_nt, 1);
+        prof_end(p, DD_PROF_PAIR_FWD, ps, st);
+      } else if (n & 1) {
+        ps = prof_begin(p, DD_PROF_PAIR2_FWD, st);
+        launch_step_pair(fa, ea, st, false, p->tb_nt, 0);
+        prof_end(p, DD_PROF_PAIR2_FWD, ps, st);
+      } else {
+        // the last step of an odd count: one whole step
+        ps = prof_begin(p, DD_PROF_STEP_FWD, st);
+        launch_step(fa, ea, st, false, false, p->fd_nt);
+        prof_end(p, DD_PROF_STEP_FWD, ps, st);
+      }
+    } else if (fused) {
       ps = prof_begin(p, DD_PROF_STEP_FWD, st);
       launch_step(fa, ea, st, false, energy != nullptr, p->fd_nt);
       prof_end(p, DD_PROF_STEP_FWD, ps, st);
@@ -586,6 +649,7 @@ int run_adjoint(dd_problem* p, int s, const float* cot, const float* obs, hipStr
   const int64_t nseg = n_segments(p);
   hipStream_t sf = p->overlap ? p->aux : st;
   const bool fused = p->use_stencil && p->fused;
+  const bool tb = tb_adjoint(p);
   // Segment pipeline (single-stream steps): the FEM recompute of a segment runs on `aux`,
   // into its own window, while the adjoint steps of the segment after it run on st.  A
   // segment's steps wait for its recompute; a recompute reuses the window of the segment
@@ -621,6 +685,30 @@ int run_adjoint(dd_problem* p, int s, const float* cot, const float* obs, hipStr
     for (int64_t k = k1; k > k0; --k) {
       adj_step_args(p, s, k, k0, win, cot, obs, fa, ea);
       long ps = -1;
+      if (tb) {
+        // pairs (k, k - 1) from the last step down; a launch-B step may open the next segment
+        tb_levels(p, k, k - 1, fa, ea);
+        const bool first = ((nt - k) & 1) == 0;
+        if (first && k > 1) {
+          FdArgs f2 = fa;
+          FemArgs e2 = ea;
+          adj_step_args(p, s, k - 1, k0, win, cot, obs, f2, e2);
+          fa.s2 = step_data(f2);
+          fa.X_out2 = p->Efd[(k - 2) & 3];
+          ps = prof_begin(p, DD_PROF_PAIR_ADJ, st);
+          launch_step_pair(fa, ea, st, true, p->tb_nt, 1);
+          prof_end(p, DD_PROF_PAIR_ADJ, ps, st);
+        } else if (!first) {
+          ps = prof_begin(p, DD_PROF_PAIR2_ADJ, st);
+          launch_step_pair(fa, ea, st, true, p->tb_nt, 0);
+          prof_end(p, DD_PROF_PAIR2_ADJ, ps, st);
+        } else {
+          ps = prof_begin(p, DD_PROF_STEP_ADJ, st);
+          launch_step(fa, ea, st, true, false, p->fd_nt, nullptr);
+          prof_end(p, DD_PROF_STEP_ADJ, ps, st);
+        }
+        continue;
+      }
       // the div-div gradient terms of lambda^k (the R2 div-div gradient, or the R1 variant's
       // difference): inside the fused step, which reads but does not write lambda^k and E^k,
       // else a launch of their own after the step (lambda^k, ea.X_in, is overwritten two
@@ -740,6 +828,7 @@ size_t dd_footprint_bytes(const dd_problem_desc* desc, int32_t n_src) {
   b += 4 * (4 * n_part + n_part * box) + 4 * STENCIL_SLOTS_MAX * 14;
   b += 4 * 4 * n_own;                     // eps - 1, c1, c2, sigma
   b += 4 * 6 * N;                         // E (2 levels) on the grid
+  b += 4 * 6 * N + 4 * (int64_t)ntiles;   // two more levels and the near-tile list (two-step launches)
   b += 4 * 9 * n_own;                     // E (2 levels) + V on the FEM nodes
   b += 4 * 6 * n_l0;                      // interface ring
   b += 8 * ((int64_t)ntiles + n_part) + 8 + 8 * 2 * n_own;   // energy partials, error flags, gradients
@@ -821,6 +910,45 @@ int create_problem(const dd_problem_desc* desc, const MeshInput* gm, dd_alloc_fn
   p->fd_nt = fd_field_bytes(p) > LLC_BYTES;
   if (const char* e = std::getenv("DD_FD_NT")) p->fd_nt = std::atoi(e) != 0;
   fd_tile_grid(p->nx, p->ny, p->nz, p->fd_nt, p->nbx, p->nby, p->nbz, p->n_tiles, p->per_xcd);
+  // temporal blocking (two-step launches), an option of the fused single-stream stencil path:
+  // DD_TB=1 switches it on
+  p->tb = false;
+  if (const char* e = std::getenv("DD_TB")) p->tb = p->use_stencil && std::atoi(e) != 0;
+  std::vector<int> tb_list;
+  if (p->tb) {
+    // four levels stream through a two-step launch
+    p->tb_nt = 2.0 * fd_field_bytes(p) > LLC_BYTES;
+    if (const char* e = std::getenv("DD_FD_NT")) p->tb_nt = std::atoi(e) != 0;
+    const int zc = tb_zc(p->tb_nt);
+    p->tb_nbz = (p->nz + zc - 1) / zc;
+    p->tb_ntiles = p->nbx * p->nby * p->tb_nbz;
+    p->tb_per_xcd = (p->tb_ntiles + N_XCD - 1) / N_XCD;
+    int blo[3], bhi[3];
+    for (int a = 0; a < 3; ++a) {
+      blo[a] = desc->fem_lo[a];
+      bhi[a] = desc->fem_lo[a] + desc->fem_cells[a];
+    }
+    for (int t = 0; t < p->tb_ntiles; ++t) {
+      const int c = tb_tile_class(t, p->nbx, p->nby, p->nx, p->ny, p->nz, zc, blo, bhi);
+      if (c == 0) continue;
+      // FD-updated nodes of the tile: its nodes in the grid minus those of the open box
+      const int bx = t % p->nbx, by = (t / p->nbx) % p->nby, bz = t / (p->nbx * p->nby);
+      const int lo[3] = {bx * FD_TX, by * FD_TY, bz * zc};
+      const int hi[3] = {std::min(lo[0] + FD_TX, p->nx), std::min(lo[1] + FD_TY, p->ny), std::min(lo[2] + zc, p->nz)};
+      int64_t all = 1, inner = 1;
+      for (int a = 0; a < 3; ++a) {
+        all *= hi[a] - lo[a];
+        inner *= std::max(0, std::min(hi[a], bhi[a]) - std::max(lo[a], blo[a] + 1));
+      }
+      if (c == 1) {
+        tb_list.push_back(t);
+        p->tb_near += all - inner;
+      } else {
+        p->tb_far += all - inner;
+      }
+    }
+    p->tb_nlist = (int)tb_list.size();
+  }
   p->n_ck = (int)((desc->n_steps + desc->ckpt_every - 1) / desc->ckpt_every);
   if (const char* ov = std::getenv("DD_OVERLAP")) p->overlap = std::atoi(ov) != 0;
   if (const char* fu = std::getenv("DD_FUSED")) p->fused = std::atoi(fu) != 0;
@@ -851,6 +979,11 @@ int create_problem(const dd_problem_desc* desc, const MeshInput* gm, dd_alloc_fn
   for (int b = 0; b < 2; ++b) {
     chk(dalloc(p, &p->Efd[b], 3 * p->N));
     chk(dalloc(p, &p->Efem[b], 3 * p->n_own));
+  }
+  if (p->tb) {
+    chk(dalloc(p, &p->Efd[2], 3 * p->N));
+    chk(dalloc(p, &p->Efd[3], 3 * p->N));
+    if (!tb_list.empty()) chk(upload(p, &p->tb_list, tb_list));
   }
   chk(dalloc(p, &p->Vfem, 3 * p->n_own));
   chk(dalloc(p, &p->iring, 6 * p->n_l0));
@@ -1186,10 +1319,9 @@ int dd_check_finite(dd_problem* p, void* stream) {
   hipStream_t st = (hipStream_t)stream;
   int h_err = 0;
   if (hipMemsetAsync(p->d_err, 0, sizeof(int), st) != hipSuccess) return fail(p, DD_ERR_HIP, "hipMemsetAsync failed");
-  for (int b = 0; b < 2; ++b) {
-    launch_count_nonfinite(p->Efd[b], 3 * p->N, p->d_err, st);
-    launch_count_nonfinite(p->Efem[b], 3 * p->n_own, p->d_err, st);
-  }
+  for (int b = 0; b < 4; ++b)
+    if (p->Efd[b]) launch_count_nonfinite(p->Efd[b], 3 * p->N, p->d_err, st);
+  for (int b = 0; b < 2; ++b) launch_count_nonfinite(p->Efem[b], 3 * p->n_own, p->d_err, st);
   launch_count_nonfinite(p->Vfem, 3 * p->n_own, p->d_err, st);
   if (int rc = check_launch(p)) return rc;
   if (hipMemcpyAsync(&h_err, p->d_err, sizeof(int), hipMemcpyDeviceToHost, st) != hipSuccess ||
@@ -1458,6 +1590,19 @@ int dd_algorithmic_bytes(const dd_problem* p, int32_t kind, double* bytes_per_la
     case DD_PROF_FEM_ADJ: b = fem + grad; break;
     case DD_PROF_STEP_FWD: b = fd + fem + save_fem; break;
     case DD_PROF_STEP_ADJ: b = fd_adj + fem + grad; break;
+    // two-step launches: far-tile nodes read levels n-1, n and write n+1, n+2 (48 B), near-tile
+    // nodes take one step (36 B); traces / cotangents of both steps, layer-0 values of one
+    case DD_PROF_PAIR_FWD:
+    case DD_PROF_PAIR_ADJ: {
+      const double fdp = 48.0 * (double)p->tb_far + 36.0 * (double)p->tb_near + 24.0 * n_det + 12.0 * n_l0 +
+                         (kind == DD_PROF_PAIR_ADJ && p->adj_obs ? 24.0 * n_det : 0.0);
+      b = fdp + fem + (kind == DD_PROF_PAIR_FWD ? save_fem : grad);
+      break;
+    }
+    case DD_PROF_PAIR2_FWD:
+    case DD_PROF_PAIR2_ADJ:
+      b = 36.0 * (double)p->tb_near + 12.0 * n_l0 + fem + (kind == DD_PROF_PAIR2_FWD ? save_fem : grad);
+      break;
   }
   *bytes_per_launch = b;
   return DD_OK;

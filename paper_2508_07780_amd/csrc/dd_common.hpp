@@ -105,6 +105,43 @@ inline void fd_tile_grid(int nx, int ny, int nz, bool nt, int& nbx, int& nby, in
 
 // ---- kernel arguments -------------------------------------------------------------------
 
+// The data of one finite-difference step that change from step to step.
+struct FdStepData {
+  float pw[3];
+  int top_a, top_b;
+  float dip[3];
+  int pw_kind;
+  float pw_t;
+  float* tr_out;
+  const float* cot_in;
+  const float* obs_in;
+};
+
+// Temporal blocking: two-step tiles march z-chunks of tb_zc planes (the level n+1 is
+// recomputed on one extra plane at each end of the chunk, so longer chunks waste less).
+__host__ __device__ constexpr int tb_zc(bool nt) { return nt ? 16 : 8; }
+// LDS of a two-step tile: four planes of level n on the tile plus two rings (36 x 12), three
+// planes of level n+1 on the tile plus one ring (34 x 10), three components each
+constexpr int TB_LX = FD_TX + 4, TB_LY = FD_TY + 4, TB_EX = FD_TX + 2, TB_EY = FD_TY + 2;
+constexpr int TB_RING1 = TB_EX * TB_EY - FD_TX * FD_TY;   // lanes with a ring-1 node
+constexpr int TB_RING2 = TB_LX * TB_LY - TB_EX * TB_EY;   // lanes with a ring-2 node, after those
+constexpr size_t TB_LDS_BYTES = (size_t)(4 * 3 * TB_LX * TB_LY + 3 * 3 * TB_EX * TB_EY) * 4;
+// Class of two-step tile t: 0 nothing to do (past the grid, or every node FEM-owned), 1 near
+// (the tile holds a node of the closed FEM box: one step per launch, the FEM's level n+1 is
+// needed), 2 far (two steps per launch).
+__host__ __device__ inline int tb_tile_class(int t, int nbx, int nby, int nx, int ny, int nz, int zc, const int blo[3],
+                                             const int bhi[3]) {
+  const int bx = t % nbx, by = (t / nbx) % nby, bz = t / (nbx * nby);
+  const int x0 = bx * FD_TX, y0 = by * FD_TY, z0 = bz * zc;
+  if (z0 >= nz) return 0;
+  const int x1 = x0 + FD_TX - 1 < nx - 1 ? x0 + FD_TX - 1 : nx - 1;
+  const int y1 = y0 + FD_TY - 1 < ny - 1 ? y0 + FD_TY - 1 : ny - 1;
+  const int z1 = z0 + zc - 1 < nz - 1 ? z0 + zc - 1 : nz - 1;
+  if (x0 > blo[0] && x1 < bhi[0] && y0 > blo[1] && y1 < bhi[1] && z0 > blo[2] && z1 < bhi[2]) return 0;
+  if (x1 >= blo[0] && x0 <= bhi[0] && y1 >= blo[1] && y0 <= bhi[1] && z1 >= blo[2] && z0 <= bhi[2]) return 1;
+  return 2;
+}
+
 struct FdArgs {
   const float* X_in;   // field at level n (forward E^n, adjoint lambda^k), [3][N]
   float* X_out;        // field at the previous level on entry (forward E^{n-1}, adjoint
@@ -141,6 +178,16 @@ struct FdArgs {
   double e_coef;       // h^3 / (2 dt^2)
   int rev;             // 1: each XCD takes its tiles in reverse order (alternate steps: a
                        // step starts where the previous one ended, whose data the caches hold)
+  const float* X_prev; // the previous level when it is not X_out (two-step launches: four
+                       // rotating buffers, none read and written in one launch); null: X_out
+  // Two-step launches (temporal blocking): the second step's level and per-step data, the
+  // two-step tile grid (z-chunks of tb_zc(NT) planes) and the list of near tiles (those with
+  // a FEM box node) that a one-step launch covers
+  float* X_out2;
+  FdStepData s2;
+  int tb_nbz, tb_ntiles, tb_per_xcd;
+  const int* tb_list;
+  int tb_nlist;
 };
 
 constexpr int STENCIL_SLOTS_MAX = 27;
@@ -200,6 +247,9 @@ struct PgArgs {
 };
 // pg: the div-div gradient terms of the step's input level, fused into an adjoint step of
 // the form R2 (nullable).
+// Two-step launches: pair_a = 1 the first launch of a pair (far tiles two steps, near tiles
+// and the FEM partitions one), 0 the second (near tiles from fa.tb_list and the FEM, one step).
+void launch_step_pair(const FdArgs& fa, const FemArgs& ea, hipStream_t s, bool adj, bool nt, int pair_a);
 void launch_step(const FdArgs& fa, const FemArgs& ea, hipStream_t s, bool adj, bool energy, bool nt,
                  const PgArgs* pg = nullptr);
 

@@ -53,10 +53,11 @@ __device__ __forceinline__ void st_own(char* base, uint32_t off, float v) {
 // support the sine's argument stays within 3 pi (the Gaussian-modulated sine: |omega u| <=
 // omega t0 = 3 pi; one sine period: < 2 pi), where the hardware sine and exponential are
 // accurate to about 1e-6, well inside the trace tolerance, and need no argument reduction.
-__device__ __forceinline__ float oblique_pulse(const FdArgs& a, int x, int y) {
+// kind, tn: the step's source kind and time (t_n, or t_n - t0 for the Gaussian-modulated sine).
+__device__ __forceinline__ float oblique_pulse_at(const FdArgs& a, int kind, float tn, int x, int y) {
   const float tau = a.pw_kx * (float)(x - a.pw_x0) + a.pw_ky * (float)(y - a.pw_y0);
-  const float u = a.pw_t - tau;
-  if (a.pw_kind == DD_SRC_GAUSS_SINE) {
+  const float u = tn - tau;
+  if (kind == DD_SRC_GAUSS_SINE) {
     if (!(fabsf(u) <= a.pw_sup)) return 0.f;
     const float v = u * a.pw_iw;
     return __sinf(a.pw_omega * u) * __expf(-0.5f * v * v);
@@ -64,13 +65,21 @@ __device__ __forceinline__ float oblique_pulse(const FdArgs& a, int x, int y) {
   if (!(u > 0.f && u < a.pw_sup)) return 0.f;
   return __sinf(a.pw_omega * u);
 }
+__device__ __forceinline__ float oblique_pulse(const FdArgs& a, int x, int y) {
+  return oblique_pulse_at(a, a.pw_kind, a.pw_t, x, y);
+}
 
 // b: block index within the finite-difference part of the launch; b % N_XCD must equal
 // blockIdx.x % N_XCD so that the remap below keeps consecutive tiles on one XCD.
 // OBL: the top face may carry an obliquely incident plane wave (a separate instantiation, so
 // that the kernels of normal incidence keep their register allocation).
+// The node update, here and in the two-step tiles, is written with explicit fused multiply-adds
+// and no other contraction, so every path rounds alike: S = wz sz + (wy sy + wx sx) (mirror
+// weights 1 inside), E^{n+1} = E^n + [(E^n - E^{n-1}) - nu^2 S + F] (damped faces: the divided
+// form).  With unit weights and no forcing it is the interior update of the two-step tiles.
 template <bool ENERGY, bool NT, bool OBL = false>
 __device__ __forceinline__ void fd_tile(const FdArgs& a, const int b) {
+#pragma clang fp contract(off)
   constexpr int ZC = fd_zc(NT);
   // two LDS planes: plane z is written while plane z-1 may still be read by slower waves,
   // so one barrier per plane suffices
@@ -119,10 +128,13 @@ __device__ __forceinline__ void fd_tile(const FdArgs& a, const int b) {
   const char* X1 = X0 + comp;
   const char* X2 = X1 + comp;
   // level n-1 on entry, overwritten with level n+1 node by node (only the node's own lane
-  // reads or writes its value in this array)
+  // reads or writes its value in this array); or level n-1 read from X_prev when it is set
   char* P0 = reinterpret_cast<char*>(a.X_out);
   char* P1 = P0 + comp;
   char* P2 = P1 + comp;
+  const char* V0 = a.X_prev ? reinterpret_cast<const char*>(a.X_prev) : P0;
+  const char* V1 = V0 + comp;
+  const char* V2 = V1 + comp;
 
   // halo cell of this thread (80 ring cells of the 32 x 8 tile, corners unused)
   int hx = 0, hy = 0, hs = 0;
@@ -153,8 +165,8 @@ __device__ __forceinline__ void fd_tile(const FdArgs& a, const int b) {
       const uint32_t o2 = o + 2 * plane4;
       q3[0] = ld_at(X0, o2); q3[1] = ld_at(X1, o2); q3[2] = ld_at(X2, o2);
     }
-    pv[0] = ld_own<NT>(P0, o); pv[1] = ld_own<NT>(P1, o); pv[2] = ld_own<NT>(P2, o);
-    if (z0 + 1 < z1) { pn[0] = ld_own<NT>(P0, o + plane4); pn[1] = ld_own<NT>(P1, o + plane4); pn[2] = ld_own<NT>(P2, o + plane4); }
+    pv[0] = ld_own<NT>(V0, o); pv[1] = ld_own<NT>(V1, o); pv[2] = ld_own<NT>(V2, o);
+    if (z0 + 1 < z1) { pn[0] = ld_own<NT>(V0, o + plane4); pn[1] = ld_own<NT>(V1, o + plane4); pn[2] = ld_own<NT>(V2, o + plane4); }
   }
   if (h_role) {
     const uint32_t o = (uint32_t)z0 * plane4 + hcol4;
@@ -186,7 +198,7 @@ __device__ __forceinline__ void fd_tile(const FdArgs& a, const int b) {
     }
     if (z + 2 < z1) {
       const uint32_t o = zo + 2 * plane4 + col4;
-      pn2[0] = ld_own<NT>(P0, o); pn2[1] = ld_own<NT>(P1, o); pn2[2] = ld_own<NT>(P2, o);
+      pn2[0] = ld_own<NT>(V0, o); pn2[1] = ld_own<NT>(V1, o); pn2[2] = ld_own<NT>(V2, o);
       if (h_role) {
         const uint32_t oh = zo + 2 * plane4 + hcol4;
         hn2[0] = ld_at(X0, oh); hn2[1] = ld_at(X1, oh); hn2[2] = ld_at(X2, oh);
@@ -215,7 +227,7 @@ __device__ __forceinline__ void fd_tile(const FdArgs& a, const int b) {
       const float wy = (byl || byh) ? 2.f : 1.f;
       const float wz = (bzl || bzh) ? 2.f : 1.f;
       const uint32_t idx4 = zo + col4;
-      float L[3];
+      float S[3];
 #pragma unroll
       for (int c = 0; c < 3; ++c) {
         const float xc = q1[c];
@@ -223,7 +235,7 @@ __device__ __forceinline__ void fd_tile(const FdArgs& a, const int b) {
         const float sx = (bxl ? 0.f : xc - p[-1]) + (bxh ? 0.f : xc - p[1]);
         const float sy = (byl ? 0.f : xc - p[-SW]) + (byh ? 0.f : xc - p[SW]);
         const float sz = (bzl ? 0.f : xc - q0[c]) + (bzh ? 0.f : xc - q2[c]);
-        L[c] = a.nu2 * (wx * sx + wy * sy + wz * sz);
+        S[c] = __builtin_fmaf(wz, sz, __builtin_fmaf(wy, sy, wx * sx));
       }
       const bool on_bnd = bxl || bxh || byl || byh || bzl || bzh;
       float src[3] = {0.f, 0.f, 0.f};
@@ -272,12 +284,12 @@ __device__ __forceinline__ void fd_tile(const FdArgs& a, const int b) {
       float out[3], xn[3];
       if (na == 0 && nb == 0) {
 #pragma unroll
-        for (int c = 0; c < 3; ++c) out[c] = (q1[c] - pv[c]) - L[c] + src[c];
+        for (int c = 0; c < 3; ++c) out[c] = __builtin_fmaf(-a.nu2, S[c], q1[c] - pv[c]) + src[c];
       } else {
         const float ba = a.nu * (float)na, bb = a.nu * (float)nb;
 #pragma unroll
         for (int c = 0; c < 3; ++c)
-          out[c] = ((1.f - bb) * (q1[c] - pv[c]) - L[c] + src[c] - (ba - bb) * q1[c]) / (1.f + ba);
+          out[c] = ((1.f - bb) * (q1[c] - pv[c]) - a.nu2 * S[c] + src[c] - (ba - bb) * q1[c]) / (1.f + ba);
       }
 #pragma unroll
       for (int c = 0; c < 3; ++c) xn[c] = q1[c] + out[c];
@@ -293,7 +305,7 @@ __device__ __forceinline__ void fd_tile(const FdArgs& a, const int b) {
       if (ENERGY) {
         double e_node = 0.0;
 #pragma unroll
-        for (int c = 0; c < 3; ++c) e_node += (double)out[c] * (double)out[c] + (double)xn[c] * (double)L[c];
+        for (int c = 0; c < 3; ++c) e_node += (double)out[c] * (double)out[c] + (double)xn[c] * (double)(a.nu2 * S[c]);
         eacc += a.e_coef * ldexp(1.0, -bcount) * e_node;
       }
     }
@@ -854,6 +866,383 @@ __global__ __launch_bounds__(FD_THREADS) void step_kernel(FdArgs fa, FemArgs ea,
   fd_tile<ENERGY, NT, OBL>(fa, b - fem_blocks);
 }
 
+// ---------------------------------------------------------------------------------------
+// Temporal blocking of the finite-difference region: two steps per launch.
+// A far tile (no node of the closed FEM box among its own) advances its 32 x 8 columns over a
+// z-chunk of tb_zc planes from level n to n+2.  Per plane it recomputes level n+1 on the tile
+// plus a one-node ring, from level n on the tile plus two rings; one plane behind, it forms
+// level n+2 on the tile from those values.  A level-n+1 value on the ring is the FD update
+// of a node outside the open FEM box (at most a layer-0 node, whose stencil reads the
+// layer-1 value of level n that the FEM wrote into the grid), so nothing it needs comes from
+// this launch's FEM partitions.  Levels n-1 and n are read, n+1 and n+2 written, in four
+// distinct buffers, so no tile reads a value another tile writes in the same launch.  The
+// FD fields then move 24 B per node and step instead of 36.  Near tiles, and the second
+// launch of a pair, take one step with the same code (ONE).
+// Lanes: the tile node (tid % 32, tid / 32); lanes [0, TB_RING1) also a ring-1 node (rows y0-1
+// and y0+8, then columns x0-1 and x0+32).  The level-n planes z-1 .. z+2 (tile plus two rings,
+// loaded by all lanes, one plane ahead) and the level-n+1 planes z-2 .. z (tile plus one ring)
+// sit in LDS; two barriers per plane (after the level-n plane is in, after level n+1 is).
+// Measured on MI355X the one-step launches are faster (the grids whose fields the last-level
+// cache holds are not bandwidth-bound, and the recomputed ring and end planes cost a third
+// more node updates), so the two-step launches are an option (DD_TB=1 at dd_create).
+// ---------------------------------------------------------------------------------------
+
+// Per-column data of a node: its (x, y), the outer-face flags of x and y, and whether the
+// column holds the dipole node.
+struct FdCol {
+  int x, y;
+  bool bxl, bxh, byl, byh, dip;
+};
+__device__ __forceinline__ FdCol fd_col(const FdArgs& a, int x, int y, int dip_x, int dip_y) {
+  FdCol c;
+  c.x = x; c.y = y;
+  c.bxl = x == 0; c.bxh = x == a.nx - 1; c.byl = y == 0; c.byh = y == a.ny - 1;
+  c.dip = x == dip_x && y == dip_y;
+  return c;
+}
+
+// One node's three-level update (the arithmetic of fd_tile, in the same order, so that both
+// paths round alike): xc its level-n value, xm / xp, ym / yp, zm / zp the neighbours (ignored
+// across the outer box's faces), pv the previous level; the next level in xn and the node's
+// detector index (or -1) in det.  INT: a node with no outer face and no dipole, where the
+// mirror weights are 1 and there is no forcing, damping or detector.
+template <bool OBL, bool INT>
+__device__ __forceinline__ void fd_point(const FdArgs& a, const FdStepData& sd, const FdCol& cl, int z, int dip_z,
+                                         const float xc[3], const float xm[3], const float xp[3], const float ym[3],
+                                         const float yp[3], const float zm[3], const float zp[3], const float pv[3],
+                                         float xn[3], int64_t& det) {
+#pragma clang fp contract(off)
+  det = -1;
+  if (INT) {
+#pragma unroll
+    for (int c = 0; c < 3; ++c) {
+      const float v = xc[c];
+      const float sx = (v - xm[c]) + (v - xp[c]);
+      const float sy = (v - ym[c]) + (v - yp[c]);
+      const float sz = (v - zm[c]) + (v - zp[c]);
+      const float S = (sx + sy) + sz;
+      xn[c] = v + __builtin_fmaf(-a.nu2, S, v - pv[c]);
+    }
+    return;
+  }
+  const int nz = a.nz;
+  const bool bxl = cl.bxl, bxh = cl.bxh, byl = cl.byl, byh = cl.byh, bzl = z == 0, bzh = z == nz - 1;
+  const float wx = (bxl || bxh) ? 2.f : 1.f;
+  const float wy = (byl || byh) ? 2.f : 1.f;
+  const float wz = (bzl || bzh) ? 2.f : 1.f;
+  float S[3];
+#pragma unroll
+  for (int c = 0; c < 3; ++c) {
+    const float v = xc[c];
+    const float sx = (bxl ? 0.f : v - xm[c]) + (bxh ? 0.f : v - xp[c]);
+    const float sy = (byl ? 0.f : v - ym[c]) + (byh ? 0.f : v - yp[c]);
+    const float sz = (bzl ? 0.f : v - zm[c]) + (bzh ? 0.f : v - zp[c]);
+    S[c] = __builtin_fmaf(wz, sz, __builtin_fmaf(wy, sy, wx * sx));
+  }
+  float src[3] = {0.f, 0.f, 0.f};
+  int na = 0, nb = 0;
+  if (bxl || bxh || byl || byh || bzl || bzh) {
+    const int bcount = (int)(bxl || bxh) + (int)(byl || byh) + (int)(bzl || bzh);
+    const unsigned am = a.abs_mask;
+    const int fixed = ((am & DD_FACE_BOTTOM) && bzl) + ((am & DD_FACE_XMIN) && bxl) + ((am & DD_FACE_XMAX) && bxh) +
+                      ((am & DD_FACE_YMIN) && byl) + ((am & DD_FACE_YMAX) && byh);
+    const int top = (am & DD_FACE_TOP) && bzh;
+    na = fixed + top * sd.top_a;
+    nb = fixed + top * sd.top_b;
+    if (bzh) {
+      src[0] += sd.pw[0];
+      src[1] += sd.pw[1];
+      src[2] += sd.pw[2];
+      if (OBL && sd.pw_kind) {
+        const float pvl = oblique_pulse_at(a, sd.pw_kind, sd.pw_t, cl.x, cl.y);
+        src[0] += a.pw_amp[0] * pvl;
+        src[1] += a.pw_amp[1] * pvl;
+        src[2] += a.pw_amp[2] * pvl;
+      }
+    }
+    if (a.det_mask) det = face_lex_index(cl.x, cl.y, z, a.nx, a.ny, nz, a.det_mask);
+    if (det >= 0 && sd.cot_in) {
+      const float sc2 = a.dt2_h3 * (float)(1 << bcount);
+#pragma unroll
+      for (int c = 0; c < 3; ++c) {
+        const float r = sd.obs_in ? sd.cot_in[det * 3 + c] - sd.obs_in[det * 3 + c] : sd.cot_in[det * 3 + c];
+        src[c] -= r * sc2;
+      }
+    }
+  }
+  if (cl.dip && z == dip_z) {
+#pragma unroll
+    for (int c = 0; c < 3; ++c) src[c] += sd.dip[c];
+  }
+  float out[3];
+  if (na == 0 && nb == 0) {
+#pragma unroll
+    for (int c = 0; c < 3; ++c) out[c] = __builtin_fmaf(-a.nu2, S[c], xc[c] - pv[c]) + src[c];
+  } else {
+    const float ba = a.nu * (float)na, bb = a.nu * (float)nb;
+#pragma unroll
+    for (int c = 0; c < 3; ++c)
+      out[c] = ((1.f - bb) * (xc[c] - pv[c]) - a.nu2 * S[c] + src[c] - (ba - bb) * xc[c]) / (1.f + ba);
+  }
+#pragma unroll
+  for (int c = 0; c < 3; ++c) xn[c] = xc[c] + out[c];
+}
+
+__device__ __forceinline__ bool fd_fem_owned(const FdArgs& a, int x, int y, int z) {
+  return x > a.blo[0] && x < a.bhi[0] && y > a.blo[1] && y < a.bhi[1] && z > a.blo[2] && z < a.bhi[2];
+}
+
+// LDS of a one-step tile (ONE): the level-n planes only
+constexpr size_t TB_LDS_ONE_BYTES = (size_t)4 * 3 * TB_LX * TB_LY * 4;
+
+// The march of one tile (see above); INT (two steps only): the level-n+1 region touches no
+// outer face and holds no dipole node, so every node takes the interior update.
+template <bool ONE, bool NT, bool OBL, bool INT>
+__device__ __forceinline__ void fd_tile2_march(const FdArgs& a, const int t) {
+#pragma clang fp contract(off)
+  constexpr int ZC = tb_zc(NT);
+  constexpr int CN = TB_LX * TB_LY, CU = TB_EX * TB_EY;   // component strides of the LDS planes
+  constexpr int NL = (CN + FD_THREADS - 1) / FD_THREADS;  // level-n plane nodes per lane (2)
+  extern __shared__ __align__(16) unsigned char lds[];
+  float* sN = reinterpret_cast<float*>(lds);            // [4][3][TB_LY][TB_LX]: level n, planes z-1..z+2
+  float* sU = sN + 4 * 3 * CN;                          // [3][3][TB_EY][TB_EX]: level n+1, planes z-2..z
+  const int nx = a.nx, ny = a.ny, nz = a.nz;
+  const int bx = t % a.nbx, by = (t / a.nbx) % a.nby, bz = t / (a.nbx * a.nby);
+  const int x0 = bx * FD_TX, y0 = by * FD_TY, z0 = bz * ZC;
+  const int z1 = min(z0 + ZC, nz);
+  const int tid = threadIdx.x;
+  const int tx = tid % FD_TX, ty = tid / FD_TX;
+  const int ox = x0 + tx, oy = y0 + ty;                 // the lane's tile node
+  const bool o_col = ox < nx && oy < ny;
+  // the lane's ring-1 node (lanes [0, TB_RING1)), in level-n plane coordinates
+  int alx = 1, aly = 1;
+  const bool ring1 = !ONE && tid < TB_RING1;
+  if (ring1) {
+    const int r = tid;
+    if (r < TB_EX) { alx = r + 1; aly = 1; }
+    else if (r < 2 * TB_EX) { alx = r - TB_EX + 1; aly = TB_EY; }
+    else if (r < 2 * TB_EX + FD_TY) { alx = 1; aly = 2 + r - 2 * TB_EX; }
+    else { alx = TB_EX; aly = 2 + r - 2 * TB_EX - FD_TY; }
+  }
+  const int ax = x0 - 2 + alx, ay = y0 - 2 + aly;
+  const bool a_col = ring1 && ax >= 0 && ax < nx && ay >= 0 && ay < ny;
+  int dip_x = -1, dip_y = -1, dip_z = -1;
+  if (!INT && a.dip_idx >= 0) {
+    dip_x = (int)(a.dip_idx % nx);
+    dip_y = (int)((a.dip_idx / nx) % ny);
+    dip_z = (int)(a.dip_idx / ((int64_t)nx * ny));
+  }
+  const FdCol co = fd_col(a, ox, oy, dip_x, dip_y), ca = fd_col(a, ax, ay, dip_x, dip_y);
+  const bool o_box = ox > a.blo[0] && ox < a.bhi[0] && oy > a.blo[1] && oy < a.bhi[1];
+  const uint32_t plane4 = 4u * (uint32_t)(nx * ny);
+  const uint32_t oc4 = o_col ? 4u * (uint32_t)(oy * nx + ox) : 0u;
+  const uint32_t ac4 = a_col ? 4u * (uint32_t)(ay * nx + ax) : 0u;
+  // the level-n plane nodes this lane loads: plane positions tid and tid + FD_THREADS
+  uint32_t lc4[NL];
+  bool l_ok[NL];
+#pragma unroll
+  for (int q = 0; q < NL; ++q) {
+    const int i = tid + q * FD_THREADS;
+    const int gx = x0 - 2 + i % TB_LX, gy = y0 - 2 + i / TB_LX;
+    l_ok[q] = i < CN && gx >= 0 && gx < nx && gy >= 0 && gy < ny;
+    lc4[q] = l_ok[q] ? 4u * (uint32_t)(gy * nx + gx) : 0u;
+  }
+  const size_t comp = (size_t)a.N * 4;
+  const char* X0 = reinterpret_cast<const char*>(a.X_in);
+  const char* Q0 = reinterpret_cast<const char*>(a.X_prev ? a.X_prev : a.X_out);
+  char* P0 = reinterpret_cast<char*>(a.X_out);
+  char* R0 = reinterpret_cast<char*>(a.X_out2);
+  FdStepData s1;
+#pragma unroll
+  for (int c = 0; c < 3; ++c) {
+    s1.pw[c] = a.pw[c];
+    s1.dip[c] = a.dip[c];
+  }
+  s1.top_a = a.top_a; s1.top_b = a.top_b; s1.pw_kind = a.pw_kind; s1.pw_t = a.pw_t;
+  s1.tr_out = a.tr_out; s1.cot_in = a.cot_in; s1.obs_in = a.obs_in;
+
+  // level n+1 is formed on planes [zs, ze); level n is read on [zs - 1, ze]
+  const int zs = ONE ? z0 : z0 - 1, ze = ONE ? z1 : z1 + 1;
+  float ln[NL][3], lp[3], la[3];   // loads in flight: level n (plane z+3), level n-1 (plane z+1)
+  auto load_n = [&](int z) {
+#pragma unroll
+    for (int q = 0; q < NL; ++q) {
+      const bool ok = l_ok[q] && z >= 0 && z < nz && z <= ze;
+      const uint32_t o = (uint32_t)z * plane4 + lc4[q];
+#pragma unroll
+      for (int c = 0; c < 3; ++c) ln[q][c] = ok ? ld_at(X0 + c * comp, o) : 0.f;
+    }
+  };
+  auto store_n = [&](int z) {
+    float* sn = sN + (z & 3) * 3 * CN;
+#pragma unroll
+    for (int q = 0; q < NL; ++q) {
+      const int i = tid + q * FD_THREADS;
+      if (i < CN) {
+#pragma unroll
+        for (int c = 0; c < 3; ++c) sn[c * CN + i] = ln[q][c];
+      }
+    }
+  };
+  auto load_p = [&](int z) {
+    const bool ok = o_col && z >= 0 && z < nz && z < ze;
+    const bool oka = a_col && z >= 0 && z < nz && z < ze;
+    const uint32_t o = (uint32_t)z * plane4;
+#pragma unroll
+    for (int c = 0; c < 3; ++c) {
+      lp[c] = ok ? ld_own<NT>(Q0 + c * comp, o + oc4) : 0.f;
+      la[c] = oka ? ld_at(Q0 + c * comp, o + ac4) : 0.f;
+    }
+  };
+  const int oq = (ty + 2) * TB_LX + tx + 2, aq = aly * TB_LX + alx;
+  const int ou = (ty + 1) * TB_EX + tx + 1, au = (aly - 1) * TB_EX + (alx - 1);
+  load_n(zs - 1);
+  store_n(zs - 1);
+  load_n(zs);
+  store_n(zs);
+  load_n(zs + 1);
+  store_n(zs + 1);
+  load_n(zs + 2);   // in flight for a whole iteration: stored at the end of the first one
+  load_p(zs);
+#pragma unroll 1
+  for (int z = zs; z < ze; ++z) {
+    float pv[3], pa[3];
+#pragma unroll
+    for (int c = 0; c < 3; ++c) { pv[c] = lp[c]; pa[c] = la[c]; }
+    load_p(z + 1);
+    __syncthreads();
+    // level n+1 at the tile node, then (two steps) at the ring-1 node; one node at a time, which
+    // keeps a single node's operands live.  A two-step tile holds no FEM-owned node.
+    float* su = sU + ((z + 3) % 3) * 3 * CU;   // z >= -1: a non-negative slot
+    const float* sm = sN + ((z - 1) & 3) * 3 * CN;
+    const float* sc = sN + (z & 3) * 3 * CN;
+    const float* sp = sN + ((z + 1) & 3) * 3 * CN;
+#pragma unroll 1
+    for (int r = 0; r < (ONE ? 1 : 2); ++r) {
+      const bool tile = r == 0;
+      if (!tile && !ring1) break;
+      float xn[3] = {0.f, 0.f, 0.f};
+      const bool ok = (tile ? o_col : a_col) && z >= 0 && z < nz && (!ONE || !(o_box && z > a.blo[2] && z < a.bhi[2]));
+      if (ok) {
+        const int q = tile ? oq : aq;
+        float xc[3], xm[3], xp[3], ym[3], yp[3], zm[3], zp[3], pp[3];
+#pragma unroll
+        for (int c = 0; c < 3; ++c) {
+          const float* cc = sc + c * CN + q;
+          xc[c] = cc[0]; xm[c] = cc[-1]; xp[c] = cc[1]; ym[c] = cc[-TB_LX]; yp[c] = cc[TB_LX];
+          zm[c] = sm[c * CN + q]; zp[c] = sp[c * CN + q];
+          pp[c] = tile ? pv[c] : pa[c];
+        }
+        int64_t det;
+        fd_point<OBL, INT>(a, s1, tile ? co : ca, z, dip_z, xc, xm, xp, ym, yp, zm, zp, pp, xn, det);
+        if (tile && z >= z0 && z < z1) {
+          const uint32_t o = (uint32_t)z * plane4 + oc4;
+#pragma unroll
+          for (int c = 0; c < 3; ++c) st_own<NT>(P0 + c * comp, o, xn[c]);
+          if (!INT && det >= 0 && s1.tr_out) {
+#pragma unroll
+            for (int c = 0; c < 3; ++c) s1.tr_out[det * 3 + c] = xn[c];
+          }
+          if (ONE && a.iface_out && ox >= a.blo[0] && ox <= a.bhi[0] && oy >= a.blo[1] && oy <= a.bhi[1] &&
+              z >= a.blo[2] && z <= a.bhi[2]) {
+            const int64_t l0 = face_lex_index(ox - a.blo[0], oy - a.blo[1], z - a.blo[2], a.fs[0], a.fs[1], a.fs[2], 63u);
+            if (l0 >= 0) {
+#pragma unroll
+              for (int c = 0; c < 3; ++c) a.iface_out[c * a.n_l0 + l0] = xn[c];
+            }
+          }
+        }
+      }
+      if (!ONE) {
+        const int u = tile ? ou : au;
+#pragma unroll
+        for (int c = 0; c < 3; ++c) su[c * CU + u] = xn[c];
+      }
+    }
+    // the level-n plane z + 2 (loaded one iteration ago) for the next iterations (its slot, that
+    // of plane z - 2, was last read before this iteration's first barrier), then plane z + 3
+    store_n(z + 2);
+    load_n(z + 3);
+    if (!ONE) {
+      __syncthreads();
+      // level n+2 at the tile node, one plane behind
+      const int zb = z - 1;
+      if (zb >= z0 && zb < z1 && o_col) {
+        const float* um = sU + ((zb + 2) % 3) * 3 * CU + ou;   // plane zb - 1 (zb >= 0)
+        const float* uc = sU + (zb % 3) * 3 * CU + ou;
+        const float* up = sU + ((z + 3) % 3) * 3 * CU + ou;
+        float xc[3], xm[3], xp[3], ym[3], yp[3], zm[3], zp[3], pv2[3], x2[3];
+#pragma unroll
+        for (int c = 0; c < 3; ++c) {
+          const float* cc = uc + c * CU;
+          xc[c] = cc[0]; xm[c] = cc[-1]; xp[c] = cc[1]; ym[c] = cc[-TB_EX]; yp[c] = cc[TB_EX];
+          zm[c] = um[c * CU]; zp[c] = up[c * CU];
+          pv2[c] = sm[c * CN + oq];   // level n at plane zb
+        }
+        int64_t det;
+        fd_point<OBL, INT>(a, a.s2, co, zb, dip_z, xc, xm, xp, ym, yp, zm, zp, pv2, x2, det);
+        const uint32_t o = (uint32_t)zb * plane4 + oc4;
+#pragma unroll
+        for (int c = 0; c < 3; ++c) st_own<NT>(R0 + c * comp, o, x2[c]);
+        if (!INT && det >= 0 && a.s2.tr_out) {
+#pragma unroll
+          for (int c = 0; c < 3; ++c) a.s2.tr_out[det * 3 + c] = x2[c];
+        }
+      }
+    }
+  }
+}
+
+// A tile of a two-step launch: ONE, one step (near tiles); else two, by the interior update
+// where the tile's level-n+1 region (the tile, a one-node ring and one plane beyond each end
+// of its chunk) touches no outer face and holds no dipole node.
+template <bool ONE, bool NT, bool OBL>
+__device__ __forceinline__ void fd_tile2(const FdArgs& a, const int t) {
+  if (ONE) {
+    fd_tile2_march<true, NT, OBL, false>(a, t);
+    return;
+  }
+  constexpr int ZC = tb_zc(NT);
+  const int bx = t % a.nbx, by = (t / a.nbx) % a.nby, bz = t / (a.nbx * a.nby);
+  const int x0 = bx * FD_TX, y0 = by * FD_TY, z0 = bz * ZC;
+  const int z1 = min(z0 + ZC, a.nz);
+  bool in = x0 - 1 >= 1 && x0 + FD_TX <= a.nx - 2 && y0 - 1 >= 1 && y0 + FD_TY <= a.ny - 2 && z0 - 1 >= 1 &&
+            z1 <= a.nz - 2;
+  if (in && a.dip_idx >= 0) {
+    const int dx = (int)(a.dip_idx % a.nx), dy = (int)((a.dip_idx / a.nx) % a.ny);
+    const int dz = (int)(a.dip_idx / ((int64_t)a.nx * a.ny));
+    in = !(dx >= x0 - 1 && dx <= x0 + FD_TX && dy >= y0 - 1 && dy <= y0 + FD_TY && dz >= z0 - 1 && dz <= z1);
+  }
+  if (in)
+    fd_tile2_march<false, NT, OBL, true>(a, t);
+  else
+    fd_tile2_march<false, NT, OBL, false>(a, t);
+}
+
+// Two-step launches (temporal blocking).  pair_a = 1: blocks [0, fem_blocks) the FEM
+// partitions' step n, then the two-step tile grid: far tiles steps n and n+1, near tiles step
+// n.  pair_a = 0: the FEM partitions' step n+1 and the near tiles (fa.tb_list) step n+1.
+template <bool ADJ, bool NT, bool OBL>
+__global__ __launch_bounds__(FD_THREADS) void step_pair_kernel(FdArgs fa, FemArgs ea, int fem_blocks, int pair_a) {
+  const int b = blockIdx.x;
+  if (b < fem_blocks) {
+    const int p = fem_part_of_block(b, fem_blocks, ea.rev);
+    if (p < ea.n_part) fem_stencil_part<ADJ, false>(ea, p);
+    return;
+  }
+  const int f = b - fem_blocks;
+  if (pair_a) {
+    const int kx = fa.rev ? fa.tb_per_xcd - 1 - f / N_XCD : f / N_XCD;
+    const int t = (f % N_XCD) * fa.tb_per_xcd + kx;
+    if (t >= fa.tb_ntiles) return;
+    const int c = tb_tile_class(t, fa.nbx, fa.nby, fa.nx, fa.ny, fa.nz, tb_zc(NT), fa.blo, fa.bhi);
+    if (c == 2) fd_tile2<false, NT, OBL>(fa, t);
+    else if (c == 1) fd_tile2<true, NT, OBL>(fa, t);
+  } else if (f < fa.tb_nlist) {
+    fd_tile2<true, NT, OBL>(fa, fa.tb_list[f]);
+  }
+}
+
 // The adjoint step of the form R1 with the paper-formula variant on: it also carries the
 // variant's div-div gradient terms of its input level (blocks [fem_blocks, fem_blocks +
 // pg_blocks), pg_tile), which read lambda^k and the saved E^k that the step does not write.
@@ -1208,6 +1597,29 @@ static void launch_step_t(const FdArgs& fa, const FemArgs& ea, hipStream_t s, bo
     hipLaunchKernelGGL((step_kernel<false, true, NT>), grid, dim3(FD_THREADS), lds, s, fa, ea, fem_blocks);
   else
     hipLaunchKernelGGL((step_kernel<false, false, NT>), grid, dim3(FD_THREADS), lds, s, fa, ea, fem_blocks);
+}
+
+template <bool NT>
+static void launch_pair_t(const FdArgs& fa, const FemArgs& ea, hipStream_t s, bool adj, int pair_a) {
+  const int fem_blocks = (ea.n_part + N_XCD - 1) / N_XCD * N_XCD;
+  const int fd_blocks = pair_a ? fa.tb_per_xcd * N_XCD : fa.tb_nlist;
+  if (fem_blocks + fd_blocks == 0) return;
+  const dim3 grid(fem_blocks + fd_blocks);
+  const size_t lds = std::max(stencil_lds_bytes(ea), pair_a ? TB_LDS_BYTES : TB_LDS_ONE_BYTES);
+  if (adj)
+    hipLaunchKernelGGL((step_pair_kernel<true, NT, false>), grid, dim3(FD_THREADS), lds, s, fa, ea, fem_blocks, pair_a);
+  else if (fa.pw_kind || fa.s2.pw_kind)
+    hipLaunchKernelGGL((step_pair_kernel<false, NT, true>), grid, dim3(FD_THREADS), lds, s, fa, ea, fem_blocks, pair_a);
+  else
+    hipLaunchKernelGGL((step_pair_kernel<false, NT, false>), grid, dim3(FD_THREADS), lds, s, fa, ea, fem_blocks,
+                       pair_a);
+}
+
+void launch_step_pair(const FdArgs& fa, const FemArgs& ea, hipStream_t s, bool adj, bool nt, int pair_a) {
+  if (nt)
+    launch_pair_t<true>(fa, ea, s, adj, pair_a);
+  else
+    launch_pair_t<false>(fa, ea, s, adj, pair_a);
 }
 
 void launch_step(const FdArgs& fa, const FemArgs& ea, hipStream_t s, bool adj, bool energy, bool nt,

@@ -12,5 +12,5 @@ from .configs import (  # noqa: F401
     ProblemDesc, Source, Workload,
     fem_layers, fem_node_coords,
     c1, c2, c3, probe288, stream224, small, batch_mix, noise, initial_pulses, with_steps, gauss_sine, oblique_wave,
-    plane_wave_switch, Request, serving_requests, meshref_marks, refined_mesh, refined_values,
+    plane_wave_switch, Request, serving_requests, meshref_marks, refined_mesh, refined_values, aligned_box,
 )

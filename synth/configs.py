@@ -358,6 +358,22 @@ def small(name: str, seed_offset: int = 0) -> Workload:
     return Workload(name, desc, eps, sig, [src], seed, eps_true=eps, sigma_true=sig)
 
 
+def aligned_box(n_steps=96, ckpt_every=16, seed=SEED_BASE + 8) -> Workload:
+    """A grid whose FEM box starts on a 32-node boundary in x and on 16-node boundaries in y and
+    z (outer 64 x 40 x 41, box 16 x 12 x 12 cells at (32, 16, 16)), random media: the finite-
+    difference tiles next to the box end one node short of its faces."""
+    h = 0.03
+    n_outer = (64, 40, 41)
+    desc = ProblemDesc(n_outer=n_outer, h=h, origin=(-0.5 * h * (n_outer[0] - 1),) * 3, fem_lo=(32, 16, 16),
+                       fem_cells=(16, 12, 12), dt=0.5 * h / math.sqrt(3.0), n_steps=n_steps, ckpt_every=ckpt_every,
+                       detector_faces=FACE_TOP | FACE_XMIN | FACE_YMAX)
+    src = gauss_sine(2.0 * math.pi / (12.0 * h), pol=(0.3, 1.0, -0.2))
+    desc.t_switch = src.support_end()
+    rng = np.random.Generator(np.random.PCG64(seed))
+    eps, sig = random_media(desc, rng)
+    return Workload("aligned", desc, eps, sig, [src], seed, eps_true=eps, sigma_true=sig)
+
+
 def batch_mix(n_problems=16, seed=SEED_BASE + 4, ckpt_every=64):
     """Uneven multi-problem mix: outer 96..224 nodes, FEM 32..96 cells (valid pairs), 1000-2500
     steps, layered-skin media; even problems get a plane wave of seeded incidence (theta ~
