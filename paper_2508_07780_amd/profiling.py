@@ -4,6 +4,7 @@
   python -m paper_2508_07780_amd.profiling stats CSV          kernel-trace stats -> markdown table
   python -m paper_2508_07780_amd.profiling pmc DIR COUNTER    average counter per dispatch per kernel
   python -m paper_2508_07780_amd.profiling hash               hash of the kernel sources
+  python -m paper_2508_07780_amd.profiling batch [STEPS]      two small mix problems batched, then alone
 
 The committed summaries under profiles/ record the HBM traffic of the fused step
 kernel together with the hash of the kernel sources it was measured on; bench.py
@@ -38,6 +39,43 @@ def copy_probe(mib=1024, reps=5):
         torch.mul(x, 1.0, out=y)
     torch.cuda.synchronize()
     print(f"copied {mib} MiB x {reps} with an elementwise kernel", flush=True)
+
+
+def batch_probe(steps=400):
+    """Two small problems of the 16-problem mix (outer 112^3 / FEM 64^3 hexes, and 96^3 / 48^3),
+    `steps` steps each, forward + misfit adjoint + gradient: first as one batch, whose steps
+    share batched launches (batch_step_kernel), then one problem at a time (step_kernel), so
+    that one kernel trace or counter run holds both."""
+    import torch
+    import synth
+    from . import Problem
+    from .batch import Batch
+    mix = synth.batch_mix()
+    ws = [synth.with_steps(mix[i], steps) for i in (2, 11)]
+
+    def setup(w):
+        p = Problem(w.desc)
+        p.set_coefficients(torch.tensor(w.eps_true, dtype=torch.float32, device="cuda"),
+                           torch.tensor(w.sigma_true, dtype=torch.float32, device="cuda"))
+        obs = torch.zeros((len(w.sources), steps, p.n_det, 3), dtype=torch.float32, device="cuda")
+        return p, obs
+
+    probs = [setup(w) for w in ws]
+    b = Batch(4)
+    for (p, obs), w in zip(probs, ws):
+        b.submit(p, w.sources, obs=obs)
+    b.run_to_completion(chunk=64)
+    torch.cuda.synchronize()
+    b.close()
+    print(f"batched: {[w.name for w in ws]}, {steps} steps", flush=True)
+    for (p, obs), w in zip(probs, ws):
+        tr = p.forward(w.sources, save=True)
+        p.adjoint_misfit(tr, obs)
+        p.gradient()
+    torch.cuda.synchronize()
+    print("one at a time", flush=True)
+    for p, _ in probs:
+        p.close()
 
 
 def _rows(path_or_dir, suffix):
@@ -94,6 +132,8 @@ def main(argv):
             print(f"{k}\t{argv[2]}\t{v:.1f}\tdispatches={n}")
     elif cmd == "hash":
         print(kernel_source_hash())
+    elif cmd == "batch":
+        batch_probe(int(argv[1]) if len(argv) > 1 else 400)
     else:
         print(__doc__)
         return 1
