@@ -799,15 +799,34 @@ int dd_detector_nodes(const dd_problem_desc* desc, int64_t* out, int64_t capacit
   return DD_OK;
 }
 
+}  // extern "C"
+
+namespace {
+// FEM partition block of the Kuhn split: 8^3 owned nodes, or 8 x 4 x 4 when an 8^3 split leaves
+// fewer than 128 partitions (small boxes: the FEM partitions are the longest blocks of a step,
+// and more, shorter ones finish sooner; measured on a 32^3-hex box: 10.1 -> 7.5 us per step,
+// while from 48^3 hexes up the 8^3 blocks are faster).
+void fem_block(const dd_problem_desc* d, int pb[3]) {
+  int64_t n8 = 1;
+  for (int a = 0; a < 3; ++a) n8 *= (d->fem_cells[a] - 1 + FEM_PB - 1) / FEM_PB;
+  pb[0] = FEM_PB;
+  pb[1] = pb[2] = n8 < 128 ? FEM_PB / 2 : FEM_PB;
+}
+}  // namespace
+
+extern "C" {
+
 size_t dd_footprint_bytes(const dd_problem_desc* desc, int32_t n_src) {
   if (!check_desc(desc).empty() || n_src < 0) return 0;
   const int64_t N = (int64_t)desc->n_outer[0] * desc->n_outer[1] * desc->n_outer[2];
   const int64_t fs[3] = {desc->fem_cells[0] + 1, desc->fem_cells[1] + 1, desc->fem_cells[2] + 1};
   const int64_t n_fem = fs[0] * fs[1] * fs[2];
+  int pb[3];
+  fem_block(desc, pb);
   int64_t n_own = 1, n_part = 1;
   for (int a = 0; a < 3; ++a) {
     n_own *= desc->fem_cells[a] - 1;
-    n_part *= (desc->fem_cells[a] - 1 + FEM_PB - 1) / FEM_PB;
+    n_part *= (desc->fem_cells[a] - 1 + pb[a] - 1) / pb[a];
   }
   const int64_t n_l0 = face_lex_count((int)fs[0], (int)fs[1], (int)fs[2], 63u);
   const int64_t nt = desc->n_steps, K = effective_ckpt_every(desc);
@@ -816,10 +835,10 @@ size_t dd_footprint_bytes(const dd_problem_desc* desc, int32_t n_src) {
   // tile count of the variant with the most tiles (short z-chunks)
   int nbx, nby, nbz, ntiles, per_xcd;
   fd_tile_grid(desc->n_outer[0], desc->n_outer[1], desc->n_outer[2], false, nbx, nby, nbz, ntiles, per_xcd);
-  // per partition of at most FEM_PB^3 owned nodes: a staging box / halo list of at most
-  // (FEM_PB + 2)^3 codes, at most 6 (FEM_PB + 1)^3 elements, at most FEM_COLORS_MAX colours
-  constexpr int64_t box = (FEM_PB + 2) * (FEM_PB + 2) * (FEM_PB + 2);
-  constexpr int64_t elem = 6 * (FEM_PB + 1) * (FEM_PB + 1) * (FEM_PB + 1);
+  // per partition of at most pb0 x pb1 x pb2 owned nodes: a staging box / halo list of at
+  // most (pb + 2)^3 codes, at most 6 (pb + 1)^3 elements, at most FEM_COLORS_MAX colours
+  const int64_t box = (int64_t)(pb[0] + 2) * (pb[1] + 2) * (pb[2] + 2);
+  const int64_t elem = 6ll * (pb[0] + 1) * (pb[1] + 1) * (pb[2] + 1);
   int64_t b = 0;
   // topology: partition offsets, colours, halo lists, elements, geometry, index maps, masses,
   // stencil boxes and slots
@@ -874,7 +893,8 @@ int create_problem(const dd_problem_desc* desc, const MeshInput* gm, dd_alloc_fn
   for (int a = 0; a < 3; ++a) p->fs[a] = desc->fem_cells[a] + 1;
   p->n_det = face_lex_count(p->nx, p->ny, p->nz, desc->detector_faces);
   HostMesh m;
-  int pb[3] = {FEM_PB, FEM_PB, FEM_PB};
+  int pb[3];
+  fem_block(desc, pb);
   if (const char* e = std::getenv("DD_FEM_PB")) {
     int x = 0, y = 0, z = 0;
     if (std::sscanf(e, "%d,%d,%d", &x, &y, &z) == 3) { pb[0] = x; pb[1] = y; pb[2] = z; }
