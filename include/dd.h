@@ -152,8 +152,9 @@ int dd_create(const dd_problem_desc* desc, dd_alloc_fn alloc_fn, dd_free_fn free
  * nodes of layers 0 and 1 keep their roles (finite-difference data; the dual-written layer) and
  * the extra nodes are free.  FEM-node arrays (coefficients, gradients) then hold n_fem_nodes =
  * (fem_cells + 1)^3 + n_extra entries.  The FEM rows run on the element-coloured kernel with
- * the div-div form R1; the form R2, the paper-formula gradient, initial data, dd_cga runs and
- * batched jobs report DD_ERR_UNSUPPORTED for such a problem.  The arrays are read during the
+ * the div-div form R1 (and a dd_cga run weighs each free node by its lumped mass); the form R2,
+ * the paper-formula gradient, initial data and batched jobs report DD_ERR_UNSUPPORTED for such
+ * a problem.  The arrays are read during the
  * call only.  The explicit step is stable for dt up to 2 / sqrt(lambda_max(M_eps^-1 A)),
  * which a refined mesh lowers: the caller chooses dt accordingly.
  * Errors: DD_ERR_INVALID_ARG (descriptor, or a mesh that breaks the rules above),
@@ -161,6 +162,27 @@ int dd_create(const dd_problem_desc* desc, dd_alloc_fn alloc_fn, dd_free_fn free
  * at most 512 owned / 1024 local nodes and 4608 elements), DD_ERR_OOM, DD_ERR_HIP. */
 int dd_create_mesh(const dd_problem_desc* desc, int64_t n_extra, const double* extra_xyz, int64_t n_tets,
                    const int32_t* tets, dd_alloc_fn alloc_fn, dd_free_fn free_fn, void* ctx, dd_problem** out);
+
+/* ---- Local refinement of the Kuhn split (box "ACGA", eq. meshref), host only -------------
+ * dd_meshref_marks: marks (host, fem_cells[0] * fem_cells[1] * fem_cells[2] entries, cells
+ * lexicographic, x fastest) = 1 for a cell one of whose corners has |eps| >= beta_eps max|eps|
+ * and |sigma| >= beta_sig max|sigma| (maxima over the FEM lattice; the mesh function h is
+ * the same on every element of the uniform mesh), among cells whose eight corners are all
+ * FEM-owned (layer >= 1); else 0.  eps, sigma: host FEM-lattice arrays ((fem_cells + 1)^3).
+ * beta in [0, 1].  Returns the number of marked cells, or DD_ERR_INVALID_ARG.
+ * dd_meshref_mesh: the refined mesh for dd_create_mesh.  extra_xyz (host, [n_marked][3]; may
+ * be NULL when nothing is marked): the marked cells' centres in cell order; tets (host,
+ * [6 n_cells + 6 n_marked][4]): per cell in order its six Kuhn tetrahedra (lowest corner,
+ * then one axis step at a time along x y z, x z y, y x z, y z x, z x y, z y x, to the highest
+ * corner), each of a marked cell bisected across the cell's main diagonal into (v0, v1, v2,
+ * centre) and (centre, v1, v2, v3).  The refinement is conforming.
+ * dd_meshref_values: a FEM-lattice array (host) on the refined mesh's nodes (host, lattice
+ * nodes then centres): the lattice values, then at each centre the mean of its cell's eight
+ * corners (the trilinear interpolant there), rounded once. */
+int64_t dd_meshref_marks(const dd_problem_desc* desc, const float* eps, const float* sigma, double beta_eps,
+                         double beta_sig, uint8_t* marks);
+int dd_meshref_mesh(const dd_problem_desc* desc, const uint8_t* marks, double* extra_xyz, int32_t* tets);
+int dd_meshref_values(const dd_problem_desc* desc, const uint8_t* marks, const float* lattice, float* out);
 /* Releases the problem.  With hipMalloc memory the device is synchronised first; with a
  * caller allocator only the library's own second stream is, and each buffer goes back
  * through free_fn while the caller's stream may still hold queued work that reads it: the
@@ -331,7 +353,7 @@ int dd_gradient_paper(dd_problem* p, double* g_eps_dev, double* g_sigma_dev, voi
  * dd_adjoint_misfit, dd_gradient (step 1), then dd_cga_update (steps 2-6), which turns
  * the gradient of J into the gradient functions of eq. gradeps,
  *     g_i = (dJ/dc_i) / m_i + gamma^m (c_i - c^0_i)   on free nodes (layer >= 2),
- * with m_i = h^3 the lumped mass and c^0 the initial guess (the Tikhonov centre of
+ * with m_i the lumped mass of node i and c^0 the initial guess (the Tikhonov centre of
  * eq. tikhonov_functional), and updates the coefficients in place:
  *     beta^m = |g^m|^2 / |g^{m-1}|^2 (0 at m = 0 or when |g^{m-1}| = 0),
  *     d^m = -g^m + beta^m d^{m-1},
@@ -339,8 +361,9 @@ int dd_gradient_paper(dd_problem* p, double* g_eps_dev, double* g_sigma_dev, voi
  *               of eq. epsilon_sigma_constraint,
  *     alpha^{m+1} = -(g^m, d^m) / (gamma^m (d^m, d^m)) (alpha^m kept when d^m = 0),
  *     gamma^{m+1} = gamma^0 / (m + 1)^p,
- * where (u, v) = h^3 sum over free nodes of u_i v_i (lumped-mass L2 inner product) and
- * |u| = (u, u)^{1/2}; eps and sigma are updated independently with their own scalars.
+ * where (u, v) = sum over free nodes of m_i u_i v_i (lumped-mass L2 inner product: m_i = h^3
+ * on the Kuhn split; on a mesh of dd_create_mesh each node's own mass, and its extra nodes are
+ * free) and |u| = (u, u)^{1/2}; eps and sigma are updated independently with their own scalars.
  * The stop test of step 6 holds when (|eps^{m+1} - eps^m| < eta1_eps or
  * |sigma^{m+1} - sigma^m| < eta1_sig) and (|g_eps^m| < eta2_eps or |g_sig^m| < eta2_sig).
  * All of it runs on the device, with deterministic FP64 sums. */
@@ -369,12 +392,13 @@ typedef struct {
  * float32, copied: they are the Tikhonov centres).  The initial guess must satisfy the
  * coefficient constraint and the box (else DD_ERR_CONSTRAINT); parameters out of range
  * give DD_ERR_INVALID_ARG.  Synchronises `stream`.  The run keeps only the lattice sizes
- * of p and may outlive it; release it with dd_cga_destroy. */
+ * of p (and, on a mesh of dd_create_mesh, its own copy of the lumped masses) and may outlive
+ * it; release it with dd_cga_destroy. */
 int dd_cga_create(dd_problem* p, const dd_cga_params* prm, const float* eps0_dev, const float* sig0_dev, void* stream,
                   dd_cga** out);
 int dd_cga_destroy(dd_cga* c);
 /* Step sizes of a run from the gradient of J at the initial guess, on the device (no host
- * read): with G = max over the free nodes of |dJ/dc_i| / h^3 (at least 1e-30), per field,
+ * read): with G = max over the free nodes of |dJ/dc_i| / m_i (at least 1e-30), per field,
  * gamma^0 = gamma^m = G / step and alpha^m = step / G, so that the first update moves eps by at
  * most step_eps and sigma by at most step_sig.  Call before the first dd_cga_update; replaces
  * those values of the parameters given to dd_cga_create.  Asynchronous. */

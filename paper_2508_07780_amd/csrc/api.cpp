@@ -27,6 +27,7 @@ struct dd_problem {
   int64_t n_fem = 0, n_own = 0, n_l0 = 0, n_det = 0;
   bool general = false;   // a caller mesh (dd_create_mesh): n_extra nodes beyond the lattice
   int64_t n_extra = 0;
+  double* mass_api = nullptr;   // a caller mesh's lumped masses per FEM node (API order; 0 off the owned set)
   int n_part = 0, n_geom = 0;
   int lds_loc = 0, lds_own = 0, lds_elem = 0, lds_box = 0;
   bool use_stencil = false;             // assembled-stencil FEM kernel instead of the element kernel
@@ -985,6 +986,11 @@ int create_problem(const dd_problem_desc* desc, const MeshInput* gm, dd_alloc_fn
   chk(upload(p, &p->elems, m.elems));
   chk(upload(p, &p->geom, m.geom));
   chk(upload(p, &p->mass_d, m.mass));
+  if (gm) {
+    std::vector<double> wa((size_t)m.n_fem, 0.0);
+    for (int64_t id = 0; id < m.n_own; ++id) wa[m.own_api[id]] = m.mass[id];
+    chk(upload(p, &p->mass_api, wa));
+  }
   if (m.stencil_ok) {
     chk(upload(p, &p->part_dims, m.part_dims));
     chk(upload(p, &p->box_codes, m.box_codes));
@@ -1398,7 +1404,7 @@ int dd_set_initial_data(dd_problem* p, const float* f0_dev, const float* f1_dev,
 // Conjugate gradient reconstruction (box "CGA"): device state of one run.
 // ---------------------------------------------------------------------------------------
 struct dd_cga {
-  int fs[3] = {0, 0, 0};
+  CgaMesh mesh{};
   int64_t n = 0;
   dd_free_fn free_fn = nullptr;   // the allocator of the problem the run started on
   void* actx = nullptr;
@@ -1406,6 +1412,7 @@ struct dd_cga {
   double* d = nullptr;      // [2][n]: previous directions d^{m-1}
   double* part = nullptr;   // [CGA_MAX_BLOCKS][6] block partials
   CgaDev* st = nullptr;
+  double* w = nullptr;      // [n]: a general mesh's lumped masses (own copy; null on the Kuhn split)
 };
 
 namespace {
@@ -1431,6 +1438,7 @@ void cga_free(dd_cga* c) {
   raw_free(c->free_fn, c->actx, c->d);
   raw_free(c->free_fn, c->actx, c->part);
   raw_free(c->free_fn, c->actx, c->st);
+  raw_free(c->free_fn, c->actx, c->w);
   delete c;
 }
 }  // namespace
@@ -1441,7 +1449,6 @@ int dd_cga_create(dd_problem* p, const dd_cga_params* prm, const float* eps0_dev
                   dd_cga** out) {
   if (!p) return DD_ERR_INVALID_ARG;
   if (!prm || !eps0_dev || !sig0_dev || !out) return fail(p, DD_ERR_INVALID_ARG, "null CGA argument");
-  if (p->general) return fail(p, DD_ERR_UNSUPPORTED, "CGA runs on the Kuhn split of the FEM box");
   *out = nullptr;
   std::string why;
   if (!cga_params_ok(*prm, why)) return fail(p, DD_ERR_INVALID_ARG, why);
@@ -1463,7 +1470,8 @@ int dd_cga_create(dd_problem* p, const dd_cga_params* prm, const float* eps0_dev
     return fail(p, DD_ERR_CONSTRAINT, std::to_string(h_err[0] + h_err[1]) +
                                           " FEM nodes of the initial guess violate the coefficient box");
   dd_cga* c = new dd_cga();
-  for (int a = 0; a < 3; ++a) c->fs[a] = p->fs[a];
+  for (int a = 0; a < 3; ++a) c->mesh.fs[a] = p->fs[a];
+  c->mesh.n_extra = p->n_extra;
   c->n = p->n_fem;
   c->free_fn = p->free_fn;
   c->actx = p->actx;
@@ -1471,10 +1479,18 @@ int dd_cga_create(dd_problem* p, const dd_cga_params* prm, const float* eps0_dev
   c->d = static_cast<double*>(raw_alloc(p->alloc_fn, p->actx, 2 * c->n * sizeof(double)));
   c->part = static_cast<double*>(raw_alloc(p->alloc_fn, p->actx, (size_t)CGA_MAX_BLOCKS * 6 * sizeof(double)));
   c->st = static_cast<CgaDev*>(raw_alloc(p->alloc_fn, p->actx, sizeof(CgaDev)));
-  if (!c->c0 || !c->d || !c->part || !c->st) {
+  if (p->mass_api) c->w = static_cast<double*>(raw_alloc(p->alloc_fn, p->actx, c->n * sizeof(double)));
+  if (!c->c0 || !c->d || !c->part || !c->st || (p->mass_api && !c->w)) {
     cga_free(c);
     return fail(p, DD_ERR_OOM, "CGA state allocation failed");
   }
+  // a general mesh's masses are copied so that the run keeps nothing of p; on the Kuhn split
+  // every free node weighs h^3
+  if (c->w && hipMemcpyAsync(c->w, p->mass_api, c->n * sizeof(double), hipMemcpyDeviceToDevice, st) != hipSuccess) {
+    cga_free(c);
+    return fail(p, DD_ERR_HIP, "copy of the lumped masses failed");
+  }
+  c->mesh.w = c->w;
   CgaDev h{};
   h.gamma0[0] = h.gamma[0] = prm->gamma_eps;
   h.gamma0[1] = h.gamma[1] = prm->gamma_sig;
@@ -1510,7 +1526,7 @@ int dd_cga_steps_from_gradient(dd_cga* c, const double* g_eps_dev, const double*
   if (!c || !g_eps_dev || !g_sigma_dev || !(step_eps > 0.0) || !(step_sig > 0.0) || !std::isfinite(step_eps) ||
       !std::isfinite(step_sig))
     return DD_ERR_INVALID_ARG;
-  launch_cga_steps(g_eps_dev, g_sigma_dev, c->fs, step_eps, step_sig, c->st, c->part, (hipStream_t)stream);
+  launch_cga_steps(g_eps_dev, g_sigma_dev, c->mesh, step_eps, step_sig, c->st, c->part, (hipStream_t)stream);
   return hipGetLastError() == hipSuccess ? DD_OK : DD_ERR_HIP;
 }
 
@@ -1523,8 +1539,8 @@ int dd_cga_destroy(dd_cga* c) {
 int dd_cga_update(dd_cga* c, const double* g_eps_dev, const double* g_sigma_dev, float* eps_dev, float* sigma_dev,
                   void* stream) {
   if (!c || !g_eps_dev || !g_sigma_dev || !eps_dev || !sigma_dev) return DD_ERR_INVALID_ARG;
-  launch_cga_update(g_eps_dev, g_sigma_dev, eps_dev, sigma_dev, c->c0, c->c0 + c->n, c->d, c->d + c->n, c->fs, c->st,
-                    c->part, (hipStream_t)stream);
+  launch_cga_update(g_eps_dev, g_sigma_dev, eps_dev, sigma_dev, c->c0, c->c0 + c->n, c->d, c->d + c->n, c->mesh,
+                    c->st, c->part, (hipStream_t)stream);
   return hipGetLastError() == hipSuccess ? DD_OK : DD_ERR_HIP;
 }
 

@@ -1,8 +1,9 @@
 // Conjugate gradient update of the coefficients eps and sigma (box "CGA", steps 2-6) on
 // the FEM lattice, after the forward / adjoint / gradient solves of step 1.
 //
-// With the lumped-mass L2 inner product (u, v) = sum_i m_i u_i v_i (m_i = h^3 on every
-// free node, i.e. layer >= 2) the gradient function of eq. gradeps at a free node is
+// With the lumped-mass L2 inner product (u, v) = sum_i m_i u_i v_i (m_i = h^3 on every free
+// node of the Kuhn split, i.e. layer >= 2; on a general mesh each free node's lumped mass, and
+// its extra nodes are free) the gradient function of eq. gradeps at a free node is
 //     g_i = (dJ/dc_i) / m_i + gamma^m (c_i - c^0_i),
 // the nodal derivative of the trace misfit turned into a function, plus the Tikhonov term
 // of eq. tikhonov_functional (centre = the initial guess).  One update then takes
@@ -33,7 +34,9 @@ namespace {
 
 constexpr int CGA_THREADS = 256;
 
+// Free FEM node: lattice layer >= 2, or one of a general mesh's extra nodes (after the lattice).
 __device__ inline bool cga_free(int64_t i, int fsx, int fsy, int fsz) {
+  if (i >= (int64_t)fsx * fsy * fsz) return true;
   const int lx = (int)(i % fsx);
   const int64_t r = i / fsx;
   const int ly = (int)(r % fsy);
@@ -84,16 +87,18 @@ __device__ inline void sum_partials(const double* part, int nb, double* out) {
 __global__ __launch_bounds__(CGA_THREADS) void cga_norm_kernel(
     const double* __restrict__ gJe, const double* __restrict__ gJs, const float* __restrict__ eps,
     const float* __restrict__ sig, const float* __restrict__ eps0, const float* __restrict__ sig0, int fsx, int fsy,
-    int fsz, const CgaDev* __restrict__ st, double* __restrict__ part) {
-  const int64_t n = (int64_t)fsx * fsy * fsz;
-  const double w = st->w, gam_e = st->gamma[0], gam_s = st->gamma[1];
+    int fsz, int64_t n_extra, const double* __restrict__ wn, const CgaDev* __restrict__ st,
+    double* __restrict__ part) {
+  const int64_t n = (int64_t)fsx * fsy * fsz + n_extra;
+  const double gam_e = st->gamma[0], gam_s = st->gamma[1];
   double acc[2] = {0.0, 0.0};
   for (int64_t i = (int64_t)blockIdx.x * CGA_THREADS + threadIdx.x; i < n; i += (int64_t)gridDim.x * CGA_THREADS) {
     if (!cga_free(i, fsx, fsy, fsz)) continue;
+    const double w = wn ? wn[i] : st->w;
     const double ge = cga_g(gJe[i], w, eps[i], eps0[i], gam_e);
     const double gs = cga_g(gJs[i], w, sig[i], sig0[i], gam_s);
-    acc[0] += ge * ge;
-    acc[1] += gs * gs;
+    acc[0] += w * ge * ge;
+    acc[1] += w * gs * gs;
   }
   block_sums<2>(acc, part + (int64_t)blockIdx.x * 2);
 }
@@ -106,7 +111,7 @@ __global__ __launch_bounds__(CGA_THREADS) void cga_beta_kernel(const double* __r
   __syncthreads();
   if (threadIdx.x == 0) {
     for (int f = 0; f < 2; ++f) {
-      const double gn2 = st->w * tot[f];
+      const double gn2 = tot[f];
       st->gn2[f] = gn2;
       st->beta[f] = (st->m > 0 && st->gn2_prev[f] > 0.0) ? gn2 / st->gn2_prev[f] : 0.0;
     }
@@ -117,9 +122,9 @@ __global__ __launch_bounds__(CGA_THREADS) void cga_beta_kernel(const double* __r
 __global__ __launch_bounds__(CGA_THREADS) void cga_step_kernel(
     const double* __restrict__ gJe, const double* __restrict__ gJs, float* __restrict__ eps, float* __restrict__ sig,
     const float* __restrict__ eps0, const float* __restrict__ sig0, double* __restrict__ d_eps,
-    double* __restrict__ d_sig, int fsx, int fsy, int fsz, const CgaDev* __restrict__ st, double* __restrict__ part) {
-  const int64_t n = (int64_t)fsx * fsy * fsz;
-  const double w = st->w;
+    double* __restrict__ d_sig, int fsx, int fsy, int fsz, int64_t n_extra, const double* __restrict__ wn,
+    const CgaDev* __restrict__ st, double* __restrict__ part) {
+  const int64_t n = (int64_t)fsx * fsy * fsz + n_extra;
   const double gam[2] = {st->gamma[0], st->gamma[1]};
   const double beta[2] = {st->beta[0], st->beta[1]};
   const double alpha[2] = {st->alpha[0], st->alpha[1]};
@@ -127,6 +132,7 @@ __global__ __launch_bounds__(CGA_THREADS) void cga_step_kernel(
   double acc[6] = {0.0, 0.0, 0.0, 0.0, 0.0, 0.0};
   for (int64_t i = (int64_t)blockIdx.x * CGA_THREADS + threadIdx.x; i < n; i += (int64_t)gridDim.x * CGA_THREADS) {
     if (!cga_free(i, fsx, fsy, fsz)) continue;
+    const double w = wn ? wn[i] : st->w;
     {
       const float c = eps[i];
       const double g = cga_g(gJe[i], w, c, eps0[i], gam[0]);
@@ -135,9 +141,9 @@ __global__ __launch_bounds__(CGA_THREADS) void cga_step_kernel(
       d_eps[i] = d;
       eps[i] = cn;
       const double dc = (double)cn - (double)c;
-      acc[0] += g * d;
-      acc[1] += d * d;
-      acc[2] += dc * dc;
+      acc[0] += w * g * d;
+      acc[1] += w * d * d;
+      acc[2] += w * dc * dc;
     }
     {
       const float c = sig[i];
@@ -147,9 +153,9 @@ __global__ __launch_bounds__(CGA_THREADS) void cga_step_kernel(
       d_sig[i] = d;
       sig[i] = cn;
       const double dc = (double)cn - (double)c;
-      acc[3] += g * d;
-      acc[4] += d * d;
-      acc[5] += dc * dc;
+      acc[3] += w * g * d;
+      acc[4] += w * d * d;
+      acc[5] += w * dc * dc;
     }
   }
   block_sums<6>(acc, part + (int64_t)blockIdx.x * 6);
@@ -164,7 +170,7 @@ __global__ __launch_bounds__(CGA_THREADS) void cga_finish_kernel(const double* _
   if (threadIdx.x == 0) {
     bool small_step = false, small_grad = false;
     for (int f = 0; f < 2; ++f) {
-      const double gd = st->w * tot[3 * f], dd = st->w * tot[3 * f + 1], step2 = st->w * tot[3 * f + 2];
+      const double gd = tot[3 * f], dd = tot[3 * f + 1], step2 = tot[3 * f + 2];
       st->gd[f] = gd;
       st->dd[f] = dd;
       st->step2[f] = step2;
@@ -234,14 +240,16 @@ __global__ void cga_upper_check_kernel(const float* __restrict__ eps, const floa
 // the free nodes of eps and of sigma.
 __global__ __launch_bounds__(CGA_THREADS) void cga_gmax_kernel(const double* __restrict__ gJe,
                                                                const double* __restrict__ gJs, int fsx, int fsy,
-                                                               int fsz, double* __restrict__ part) {
+                                                               int fsz, int64_t n_extra, const double* __restrict__ wn,
+                                                               const CgaDev* __restrict__ st, double* __restrict__ part) {
   __shared__ double red[2][CGA_THREADS];
-  const int64_t n = (int64_t)fsx * fsy * fsz;
+  const int64_t n = (int64_t)fsx * fsy * fsz + n_extra;
   double m[2] = {0.0, 0.0};
   for (int64_t i = (int64_t)blockIdx.x * CGA_THREADS + threadIdx.x; i < n; i += (int64_t)gridDim.x * CGA_THREADS) {
     if (!cga_free(i, fsx, fsy, fsz)) continue;
-    m[0] = fmax(m[0], fabs(gJe[i]));
-    m[1] = fmax(m[1], fabs(gJs[i]));
+    const double w = wn ? wn[i] : st->w;
+    m[0] = fmax(m[0], fabs(gJe[i]) / w);
+    m[1] = fmax(m[1], fabs(gJs[i]) / w);
   }
   const int t = threadIdx.x;
   red[0][t] = m[0];
@@ -260,8 +268,8 @@ __global__ __launch_bounds__(CGA_THREADS) void cga_gmax_kernel(const double* __r
   }
 }
 
-// gamma^0 = gamma^m = G / step and alpha^m = step / G per field, G = max(max|dJ/dc| / w, 1e-30)
-// (w: the lumped mass of a free node): the first update then moves the field by at most `step`.
+// gamma^0 = gamma^m = G / step and alpha^m = step / G per field, G = max(max |dJ/dc_i| / w_i, 1e-30)
+// (w_i: the lumped mass of free node i): the first update then moves the field by at most `step`.
 __global__ __launch_bounds__(CGA_THREADS) void cga_steps_finish_kernel(const double* __restrict__ part, int nb,
                                                                        double step_e, double step_s,
                                                                        CgaDev* __restrict__ st) {
@@ -285,7 +293,7 @@ __global__ __launch_bounds__(CGA_THREADS) void cga_steps_finish_kernel(const dou
   if (t == 0) {
     const double step[2] = {step_e, step_s};
     for (int f = 0; f < 2; ++f) {
-      const double g = fmax(red[f][0] / st->w, 1e-30);
+      const double g = fmax(red[f][0], 1e-30);
       st->gamma0[f] = st->gamma[f] = g / step[f];
       st->alpha[f] = step[f] / g;
     }
@@ -294,10 +302,11 @@ __global__ __launch_bounds__(CGA_THREADS) void cga_steps_finish_kernel(const dou
 
 }  // namespace
 
-void launch_cga_steps(const double* gJe, const double* gJs, const int fs[3], double step_eps, double step_sig,
+void launch_cga_steps(const double* gJe, const double* gJs, const CgaMesh& g, double step_eps, double step_sig,
                       CgaDev* st, double* part, hipStream_t s) {
-  const int nb = cga_blocks((int64_t)fs[0] * fs[1] * fs[2]);
-  hipLaunchKernelGGL(cga_gmax_kernel, dim3(nb), dim3(CGA_THREADS), 0, s, gJe, gJs, fs[0], fs[1], fs[2], part);
+  const int nb = cga_blocks((int64_t)g.fs[0] * g.fs[1] * g.fs[2] + g.n_extra);
+  hipLaunchKernelGGL(cga_gmax_kernel, dim3(nb), dim3(CGA_THREADS), 0, s, gJe, gJs, g.fs[0], g.fs[1], g.fs[2], g.n_extra,
+                     g.w, st, part);
   hipLaunchKernelGGL(cga_steps_finish_kernel, dim3(1), dim3(CGA_THREADS), 0, s, part, nb, step_eps, step_sig, st);
 }
 
@@ -307,14 +316,14 @@ int cga_blocks(int64_t n_fem) {
 }
 
 void launch_cga_update(const double* gJe, const double* gJs, float* eps, float* sig, const float* eps0,
-                       const float* sig0, double* d_eps, double* d_sig, const int fs[3], CgaDev* st,
+                       const float* sig0, double* d_eps, double* d_sig, const CgaMesh& g, CgaDev* st,
                        double* part, hipStream_t s) {
-  const int nb = cga_blocks((int64_t)fs[0] * fs[1] * fs[2]);
-  hipLaunchKernelGGL(cga_norm_kernel, dim3(nb), dim3(CGA_THREADS), 0, s, gJe, gJs, eps, sig, eps0, sig0, fs[0],
-                     fs[1], fs[2], st, part);
+  const int nb = cga_blocks((int64_t)g.fs[0] * g.fs[1] * g.fs[2] + g.n_extra);
+  hipLaunchKernelGGL(cga_norm_kernel, dim3(nb), dim3(CGA_THREADS), 0, s, gJe, gJs, eps, sig, eps0, sig0, g.fs[0],
+                     g.fs[1], g.fs[2], g.n_extra, g.w, st, part);
   hipLaunchKernelGGL(cga_beta_kernel, dim3(1), dim3(CGA_THREADS), 0, s, part, nb, st);
   hipLaunchKernelGGL(cga_step_kernel, dim3(nb), dim3(CGA_THREADS), 0, s, gJe, gJs, eps, sig, eps0, sig0, d_eps,
-                     d_sig, fs[0], fs[1], fs[2], st, part);
+                     d_sig, g.fs[0], g.fs[1], g.fs[2], g.n_extra, g.w, st, part);
   hipLaunchKernelGGL(cga_finish_kernel, dim3(1), dim3(CGA_THREADS), 0, s, part, nb, st);
 }
 

@@ -11,23 +11,31 @@ namespace dd {
 struct CgaDev {
   // parameters
   double gamma0[2], p, lo[2], hi[2], eta1[2], eta2[2];
-  double w;                  // lumped mass of a free node (h^3): weight of the L2 inner product
+  double w;                  // lumped mass of a free lattice node (h^3): the L2 weight when the
+                             // FEM nodes carry no mass array (the Kuhn split)
   // iteration state: gamma^m, alpha^m, |g^{m-1}|^2, m
   double gamma[2], alpha[2], gn2_prev[2];
   int m, converged;
   // results of the last update
   double gn2[2], beta[2], gd[2], dd[2], step2[2], alpha_used[2], gamma_used[2];
 };
+// The FEM nodes of a run: the (fs[0] x fs[1] x fs[2]) lattice, then n_extra nodes of a general
+// mesh (free); w: FP64 lumped mass per FEM node (API order) or null for h^3 on every free node.
+struct CgaMesh {
+  int fs[3];
+  int64_t n_extra;
+  const double* w;
+};
 constexpr int CGA_MAX_BLOCKS = 1024;
 int cga_blocks(int64_t n_fem);
 // Four launches: gradient-function norms, beta, direction / update / projection, step sizes.
 // part holds CGA_MAX_BLOCKS x 6 doubles.
 void launch_cga_update(const double* gJe, const double* gJs, float* eps, float* sig, const float* eps0,
-                       const float* sig0, double* d_eps, double* d_sig, const int fs[3], CgaDev* st,
+                       const float* sig0, double* d_eps, double* d_sig, const CgaMesh& g, CgaDev* st,
                        double* part, hipStream_t s);
-// gamma^0 = gamma^m = G / step and alpha^m = step / G for eps and sigma, G = max|dJ/dc| / h^3 over
+// gamma^0 = gamma^m = G / step and alpha^m = step / G for eps and sigma, G = max |dJ/dc_i| / w_i over
 // the free nodes (two launches; part holds CGA_MAX_BLOCKS x 2 doubles).
-void launch_cga_steps(const double* gJe, const double* gJs, const int fs[3], double step_eps, double step_sig,
+void launch_cga_steps(const double* gJe, const double* gJs, const CgaMesh& g, double step_eps, double step_sig,
                       CgaDev* st, double* part, hipStream_t s);
 // Counts FEM nodes with eps > eps_max or sigma > sig_max into *err.
 void launch_cga_upper_check(const float* eps, const float* sig, int64_t n, double eps_max, double sig_max, int* err,

@@ -769,3 +769,114 @@ std::string build_mesh_general(const dd_problem_desc& d, int64_t n_extra, const 
 }
 
 }  // namespace dd
+
+// ---------------------------------------------------------------------------------------
+// Local refinement of the Kuhn split (box "ACGA", eq. meshref), host only.
+// A cell is marked when one of its corners has |eps| >= beta_eps max|eps| and |sigma| >=
+// beta_sig max|sigma| (maxima over the FEM lattice; the mesh function h is the same on every
+// element of the uniform starting mesh, so it cancels), among cells whose corners are all
+// FEM-owned (layer >= 1), so that the overlap layers keep their lattice elements.  A marked
+// cell gets its centre as a node, and each of its six Kuhn tetrahedra (lowest corner, then one
+// axis step at a time, to the highest corner) is bisected across the cell's main diagonal,
+// which the centre halves: (v0, v1, v2, centre) and (centre, v1, v2, v3).  The cell's faces
+// are not split, so unmarked neighbours stay conforming.  Values at a centre: the mean of the
+// cell's eight corners (the trilinear interpolant there).
+// ---------------------------------------------------------------------------------------
+namespace {
+// Kuhn tetrahedron q of cell (i, j, k): its four vertices as lattice coordinates.
+void kuhn_tet(int i, int j, int k, int q, int v[4][3]) {
+  static const int perm[6][3] = {{0, 1, 2}, {0, 2, 1}, {1, 0, 2}, {1, 2, 0}, {2, 0, 1}, {2, 1, 0}};
+  v[0][0] = i; v[0][1] = j; v[0][2] = k;
+  for (int s = 1; s < 4; ++s) {
+    for (int a = 0; a < 3; ++a) v[s][a] = v[s - 1][a];
+    ++v[s][perm[q][s - 1]];
+  }
+}
+}  // namespace
+
+extern "C" int64_t dd_meshref_marks(const dd_problem_desc* d, const float* eps, const float* sig, double beta_eps,
+                                    double beta_sig, uint8_t* marks) {
+  if (!d || !eps || !sig || !marks || !(beta_eps >= 0.0 && beta_eps <= 1.0) || !(beta_sig >= 0.0 && beta_sig <= 1.0))
+    return DD_ERR_INVALID_ARG;
+  const int c[3] = {d->fem_cells[0], d->fem_cells[1], d->fem_cells[2]};
+  if (c[0] < 2 || c[1] < 2 || c[2] < 2) return DD_ERR_INVALID_ARG;
+  const int s0 = c[0] + 1, s1 = c[1] + 1, s2 = c[2] + 1;
+  const int64_t n = (int64_t)s0 * s1 * s2;
+  double me = 0.0, ms = 0.0;
+  for (int64_t i = 0; i < n; ++i) {
+    me = std::max(me, std::fabs((double)eps[i]));
+    ms = std::max(ms, std::fabs((double)sig[i]));
+  }
+  const double te = beta_eps * me, ts = beta_sig * ms;
+  int64_t count = 0;
+  for (int k = 0; k < c[2]; ++k)
+    for (int j = 0; j < c[1]; ++j)
+      for (int i = 0; i < c[0]; ++i) {
+        const bool owned = i >= 1 && j >= 1 && k >= 1 && i + 1 <= c[0] - 1 && j + 1 <= c[1] - 1 && k + 1 <= c[2] - 1;
+        bool hit = false;
+        for (int q = 0; q < 8 && owned && !hit; ++q) {
+          const int64_t v = (i + (q & 1)) + (int64_t)s0 * ((j + ((q >> 1) & 1)) + (int64_t)s1 * (k + (q >> 2)));
+          hit = std::fabs((double)eps[v]) >= te && std::fabs((double)sig[v]) >= ts;
+        }
+        marks[i + (int64_t)c[0] * (j + (int64_t)c[1] * k)] = hit ? 1 : 0;
+        count += hit;
+      }
+  return count;
+}
+
+extern "C" int dd_meshref_mesh(const dd_problem_desc* d, const uint8_t* marks, double* extra_xyz, int32_t* tets) {
+  if (!d || !marks || !tets) return DD_ERR_INVALID_ARG;
+  const int c[3] = {d->fem_cells[0], d->fem_cells[1], d->fem_cells[2]};
+  const int s0 = c[0] + 1, s1 = c[1] + 1;
+  const int64_t n_lat = (int64_t)s0 * s1 * (c[2] + 1);
+  int64_t e = 0, t = 0;
+  for (int k = 0; k < c[2]; ++k)
+    for (int j = 0; j < c[1]; ++j)
+      for (int i = 0; i < c[0]; ++i) {
+        const bool m = marks[i + (int64_t)c[0] * (j + (int64_t)c[1] * k)] != 0;
+        int64_t centre = -1;
+        if (m) {
+          if (!extra_xyz) return DD_ERR_INVALID_ARG;
+          centre = n_lat + e;
+          const double g[3] = {d->fem_lo[0] + i + 0.5, d->fem_lo[1] + j + 0.5, d->fem_lo[2] + k + 0.5};
+          for (int a = 0; a < 3; ++a) extra_xyz[3 * e + a] = d->origin[a] + d->h * g[a];
+          ++e;
+        }
+        for (int q = 0; q < 6; ++q) {
+          int v[4][3];
+          kuhn_tet(i, j, k, q, v);
+          int64_t id[4];
+          for (int s = 0; s < 4; ++s) id[s] = v[s][0] + (int64_t)s0 * (v[s][1] + (int64_t)s1 * v[s][2]);
+          if (!m) {
+            for (int s = 0; s < 4; ++s) tets[4 * t + s] = (int32_t)id[s];
+            ++t;
+          } else {
+            const int64_t a[4] = {id[0], id[1], id[2], centre}, b[4] = {centre, id[1], id[2], id[3]};
+            for (int s = 0; s < 4; ++s) tets[4 * t + s] = (int32_t)a[s];
+            ++t;
+            for (int s = 0; s < 4; ++s) tets[4 * t + s] = (int32_t)b[s];
+            ++t;
+          }
+        }
+      }
+  return DD_OK;
+}
+
+extern "C" int dd_meshref_values(const dd_problem_desc* d, const uint8_t* marks, const float* lattice, float* out) {
+  if (!d || !marks || !lattice || !out) return DD_ERR_INVALID_ARG;
+  const int c[3] = {d->fem_cells[0], d->fem_cells[1], d->fem_cells[2]};
+  const int s0 = c[0] + 1, s1 = c[1] + 1;
+  const int64_t n_lat = (int64_t)s0 * s1 * (c[2] + 1);
+  for (int64_t i = 0; i < n_lat; ++i) out[i] = lattice[i];
+  int64_t e = 0;
+  for (int k = 0; k < c[2]; ++k)
+    for (int j = 0; j < c[1]; ++j)
+      for (int i = 0; i < c[0]; ++i) {
+        if (!marks[i + (int64_t)c[0] * (j + (int64_t)c[1] * k)]) continue;
+        double sum = 0.0;
+        for (int q = 0; q < 8; ++q)
+          sum += (double)lattice[(i + (q & 1)) + (int64_t)s0 * ((j + ((q >> 1) & 1)) + (int64_t)s1 * (k + (q >> 2)))];
+        out[n_lat + e++] = (float)(sum / 8.0);
+      }
+  return DD_OK;
+}

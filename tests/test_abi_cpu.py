@@ -295,3 +295,28 @@ def test_malformed_general_meshes_are_refused(lib):
                               t.ctypes.data_as(ctypes.POINTER(ctypes.c_int32)), _lib.ALLOC_FN(), _lib.FREE_FN(),
                               None, ctypes.byref(h)) == -1
     assert not h.value
+
+
+@pytest.mark.parametrize("name,be,bs", [("skinlet", 0.3, 0.0), ("ragged", 0.5, 0.2), ("tiny", 0.0, 0.0),
+                                        ("skinlet", 0.9, 0.9)])
+def test_library_refinement_equals_the_oracle(lib, name, be, bs):
+    """dd_meshref_marks / _mesh / _values (the library's host refinement of box "ACGA") against
+    the oracle's independent marking, mesh and interpolation on the same float32 values:
+    marks and tetrahedra bit for bit, centres to 1e-15, interpolated values within one float32
+    rounding of the FP64 mean."""
+    from oracle import acga as oacga
+    from paper_2508_07780_amd import acga
+    w = synth.small(name)
+    eps = np.asarray(w.eps, dtype=np.float32)
+    sig = np.asarray(w.sigma + 0.01 * np.random.default_rng(9).random(w.sigma.size) * (w.sigma > 0),
+                     dtype=np.float32)
+    marks, (xyz, tets) = acga.meshref(w.desc, eps, sig, be, bs)
+    om = oacga.marks(w.desc, eps.astype(np.float64), sig.astype(np.float64), be, bs)
+    assert np.array_equal(marks.astype(bool), om)
+    oxyz, otets = oacga.refine(w.desc, om)
+    assert np.array_equal(tets, otets.astype(np.int32))
+    assert xyz.shape == oxyz.shape and (len(xyz) == 0 or np.abs(xyz - oxyz).max() <= 1e-15)
+    v = acga.interpolate(w.desc, marks, eps)
+    ov = oacga.interpolate(w.desc, om, eps.astype(np.float64))
+    assert np.array_equal(v[:eps.size], eps)
+    assert np.all(v[eps.size:] == ov[eps.size:].astype(np.float32))

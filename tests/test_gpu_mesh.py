@@ -122,11 +122,10 @@ def test_kuhn_split_as_a_general_mesh_matches_the_default_path():
 
 def test_constraints_and_refused_forms_on_a_general_mesh():
     """Extra nodes are free (eps > 1 accepted there); layer-1 lattice nodes still must hold
-    eps = 1.  R2, the paper-formula gradient, initial data, CGA and batched jobs are refused."""
+    eps = 1.  R2, the paper-formula gradient, initial data and batched jobs are refused."""
     import torch
     from paper_2508_07780_amd import DDError
     from paper_2508_07780_amd.batch import Batch
-    from paper_2508_07780_amd.cga import CGA, CGAParams
     w, marks, mesh, eps, sig = _refined("tiny", 0.5)
     p = _problem(torch, w, mesh, eps, sig)
     n_lat = int(np.prod(np.asarray(w.desc.fem_cells) + 1))
@@ -148,11 +147,6 @@ def test_constraints_and_refused_forms_on_a_general_mesh():
             call()
         assert e.value.code == -7
     obs = torch.zeros((1, w.desc.n_steps, p.n_det, 3), dtype=torch.float32, device="cuda")
-    with pytest.raises(DDError) as e:
-        CGA(p, w.sources, obs, torch.tensor(eps, dtype=torch.float32, device="cuda"),
-            torch.tensor(sig, dtype=torch.float32, device="cuda"),
-            CGAParams(gamma_eps=1.0, gamma_sig=1.0, p=0.5, alpha_eps=1.0, alpha_sig=1.0, eps_max=10.0, sig_max=1.0))
-    assert e.value.code == -7
     b = Batch(2)
     with pytest.raises(DDError) as e:
         b.submit(p, w.sources, obs=obs)
