@@ -10,7 +10,10 @@ the refined mesh and the interpolation onto it.
   and on the box surface), non-degenerate, fills the box, and a marked cell's twelve
   tetrahedra have volume h^3/12 each;
 * interpolation: exact (to rounding) for trilinear functions, whose value at a cell centre
-  is the mean of the corners; old nodes keep their values.
+  is the mean of the corners; old nodes keep their values;
+* the loop's stitching: with nothing marked its second level is the CGA on the uniform mesh
+  from the first level's result (the CGA itself is pinned in tests/test_oracle_cga.py, the
+  solves on refined meshes in tests/test_oracle_mesh.py).
 """
 
 import itertools
@@ -117,3 +120,25 @@ def test_interpolation_is_exact_for_trilinear_functions():
     cz, cy, cx = np.nonzero(m.reshape(tuple(int(c) for c in w.desc.fem_cells)[::-1]))
     exact = f(cx + 0.5, cy + 0.5, cz + 0.5)
     assert np.abs(out[vals.size:] - exact).max() <= 1e-12 * np.abs(exact).max()
+
+
+def test_loop_with_nothing_marked_continues_on_the_uniform_mesh():
+    """The stitching of the loop: with beta_eps > 1 no cell is marked, so the second level must
+    be the CGA on the (uniform) mesh started from, and centred on, the first level's result,
+    with the same observations."""
+    from oracle.cga import cga
+    from oracle.solver import forward
+    w = synth.small("tiny")
+    d = Discretization(w.desc).set_coefficients(w.eps, w.sigma)
+    src = w.sources[0]
+    eobs = forward(d, src)["traces"][None]
+    n = d.n_fem
+    prm = dict(gamma_eps=0.5, gamma_sig=0.5, p=0.5, alpha_eps=0.5, alpha_sig=0.05, eps_max=8.0, sig_max=2.0)
+    r = acga.acga(w.desc, [src], eobs, np.ones(n), np.zeros(n), prm, 2, 1.5, 0.0)
+    assert not r["marks"].any() and len(r["mesh"][0]) == 0
+    h1 = cga(Discretization(w.desc), [src], eobs, r["eps_coarse"], r["sig_coarse"], prm, 2)
+    assert r["eps_coarse"] is not None and np.any(r["eps_coarse"] != 1.0)
+    for a, b in zip(r["fine"], h1):
+        for f in ("eps", "sig"):
+            assert a[f]["grad_norm"] == pytest.approx(b[f]["grad_norm"], rel=1e-12)
+            assert np.allclose(a[f]["coef"], b[f]["coef"], rtol=1e-12, atol=1e-14)
