@@ -384,7 +384,7 @@ def main():
     ap.add_argument("--ckpt-every", type=int, default=0,
                     help="forward checkpoint interval K for the adjoint; 0 = store every FEM level "
                          "(no recompute; 12.6 GB for the default workload)")
-    ap.add_argument("--cpu-sample-steps", type=int, default=8, help="0 skips the oracle baseline")
+    ap.add_argument("--cpu-sample-steps", type=int, default=20, help="0 skips the oracle baseline")
     ap.add_argument("--no-profile", action="store_true", help="skip the HIP-event kernel timing")
     ap.add_argument("--serving", type=int, default=1, help="0 skips the batched / serving comparison")
     ap.add_argument("--serving-jobs", type=int, default=24, help="requests of the serving comparison")
