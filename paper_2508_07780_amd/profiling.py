@@ -3,7 +3,8 @@
   python -m paper_2508_07780_amd.profiling copy [MiB]        plain device copy of a known size
   python -m paper_2508_07780_amd.profiling stats CSV          kernel-trace stats -> markdown table
   python -m paper_2508_07780_amd.profiling pmc DIR COUNTER    average counter per dispatch per kernel
-  python -m paper_2508_07780_amd.profiling hash               hash of the kernel sources
+  python -m paper_2508_07780_amd.profiling hash [FILE ...]    hash of the step kernel sources (or of
+                                                             the named files under csrc/)
   python -m paper_2508_07780_amd.profiling batch [STEPS]      two small mix problems batched, then alone
 
 The committed summaries under profiles/ record the HBM traffic of the fused step
@@ -21,9 +22,9 @@ import sys
 HERE = os.path.dirname(os.path.abspath(__file__))
 
 
-def kernel_source_hash():
+def kernel_source_hash(names=("kernels.hip", "dd_common.hpp")):
     h = hashlib.sha256()
-    for name in ("kernels.hip", "dd_common.hpp"):
+    for name in names:
         with open(os.path.join(HERE, "csrc", name), "rb") as f:
             h.update(f.read())
     return h.hexdigest()[:16]
@@ -131,7 +132,7 @@ def main(argv):
         for k, (v, n) in sorted(pmc_average(argv[1], argv[2], argv[3] if len(argv) > 3 else "").items()):
             print(f"{k}\t{argv[2]}\t{v:.1f}\tdispatches={n}")
     elif cmd == "hash":
-        print(kernel_source_hash())
+        print(kernel_source_hash(argv[1:]) if len(argv) > 1 else kernel_source_hash())
     elif cmd == "batch":
         batch_probe(int(argv[1]) if len(argv) > 1 else 400)
     else:
