@@ -163,26 +163,53 @@ int dd_create(const dd_problem_desc* desc, dd_alloc_fn alloc_fn, dd_free_fn free
 int dd_create_mesh(const dd_problem_desc* desc, int64_t n_extra, const double* extra_xyz, int64_t n_tets,
                    const int32_t* tets, dd_alloc_fn alloc_fn, dd_free_fn free_fn, void* ctx, dd_problem** out);
 
-/* ---- Local refinement of the Kuhn split (box "ACGA", eq. meshref), host only -------------
- * dd_meshref_marks: marks (host, fem_cells[0] * fem_cells[1] * fem_cells[2] entries, cells
- * lexicographic, x fastest) = 1 for a cell one of whose corners has |eps| >= beta_eps max|eps|
- * and |sigma| >= beta_sig max|sigma| (maxima over the FEM lattice; the mesh function h is
- * the same on every element of the uniform mesh), among cells whose eight corners are all
- * FEM-owned (layer >= 1); else 0.  eps, sigma: host FEM-lattice arrays ((fem_cells + 1)^3).
- * beta in [0, 1].  Returns the number of marked cells, or DD_ERR_INVALID_ARG.
- * dd_meshref_mesh: the refined mesh for dd_create_mesh.  extra_xyz (host, [n_marked][3]; may
- * be NULL when nothing is marked): the marked cells' centres in cell order; tets (host,
- * [6 n_cells + 6 n_marked][4]): per cell in order its six Kuhn tetrahedra (lowest corner,
- * then one axis step at a time along x y z, x z y, y x z, y z x, z x y, z y x, to the highest
- * corner), each of a marked cell bisected across the cell's main diagonal into (v0, v1, v2,
- * centre) and (centre, v1, v2, v3).  The refinement is conforming.
- * dd_meshref_values: a FEM-lattice array (host) on the refined mesh's nodes (host, lattice
- * nodes then centres): the lattice values, then at each centre the mean of its cell's eight
- * corners (the trilinear interpolant there), rounded once. */
-int64_t dd_meshref_marks(const dd_problem_desc* desc, const float* eps, const float* sigma, double beta_eps,
-                         double beta_sig, uint8_t* marks);
-int dd_meshref_mesh(const dd_problem_desc* desc, const uint8_t* marks, double* extra_xyz, int32_t* tets);
-int dd_meshref_values(const dd_problem_desc* desc, const uint8_t* marks, const float* lattice, float* out);
+/* ---- Local mesh refinement (box "ACGA", steps 2 and 3; eq. meshref, eq. meshfunction) ----
+ * Host only; no device work.  dd_meshref_create marks the elements of a mesh of the FEM box and
+ * refines them.  The mesh: n_tets = 0 (tets and extra_xyz NULL, n_extra = 0) for the uniform
+ * Kuhn split (per cell, lexicographic with x fastest, its six tetrahedra from the lowest corner
+ * one axis step at a time along x y z, x z y, y x z, y z x, z x y, z y x), or extra nodes and
+ * tetrahedra as dd_create_mesh takes them (host arrays, read during the call only).
+ * eps, sigma: host float32 values at the mesh's FEM nodes (lattice nodes, then extra nodes).
+ * Marking: with h_K the diameter (longest edge) of element K, K is marked when at one of its
+ * vertices v both h_K |eps(v)| >= beta_eps M_eps and h_K |sigma(v)| >= beta_sig M_sig hold
+ * (M: the largest such product over all elements and their vertices; beta in [0, 1]).
+ * Refining: longest-edge bisection with propagation.  A marked element is bisected at its
+ * longest edge (ties within 1e-9 relative: the edge with the smaller (low, high) pair of node
+ * ids), together with every element around that edge, at the edge's midpoint, after every
+ * element around the edge whose own longest edge is another one has been bisected the same
+ * way (recursively, in increasing element id; an element split at (a, b), a < b, becomes
+ * its half with b replaced by the midpoint and then its half with a replaced by it, with ids
+ * after all existing ones).  So every element is split at its longest edge and the mesh stays
+ * conforming.  An edge is bisected only when every element around it has all its vertices
+ * FEM-owned (lattice layer >= 1): the elements touching layer 0 are never split, and a marked
+ * element whose propagation reaches such an edge stays as it is.  Marked elements are taken in
+ * element order, skipping those already split; the k-th bisection's midpoint becomes FEM node
+ * n_old + k.  On the Kuhn split this inserts the centre of every cell one of whose corners meets
+ * the rule (and whose corners are all FEM-owned) and bisects its six tetrahedra across its
+ * main diagonal.
+ * out: a host handle (release with dd_meshref_destroy).
+ * Errors: DD_ERR_INVALID_ARG (null arguments, beta outside [0, 1], an index out of range, an
+ * extra node outside the box's interior, a descriptor with fewer than 2 FEM cells per axis). */
+typedef struct dd_refinement dd_refinement;
+int dd_meshref_create(const dd_problem_desc* desc, int64_t n_extra, const double* extra_xyz, int64_t n_tets,
+                      const int32_t* tets, const float* eps, const float* sigma, double beta_eps, double beta_sig,
+                      dd_refinement** out);
+/* Sizes of the result: marked input elements, bisected edges (= new nodes), extra nodes of the
+ * refined mesh (the input's extra nodes, then the midpoints) and its elements.  Any pointer may
+ * be NULL. */
+int dd_meshref_sizes(const dd_refinement* r, int64_t* n_marked, int64_t* n_bisected, int64_t* n_extra,
+                     int64_t* n_tets);
+/* Copies the result into host arrays: marks [input elements] (1 = marked; may be NULL),
+ * extra_xyz [n_extra][3] (physical coordinates; may be NULL when n_extra = 0), tets
+ * [n_tets][4] (FEM-node ids; elements in the order of the input's, each replaced in place by
+ * its pieces), ready for dd_create_mesh. */
+int dd_meshref_result(const dd_refinement* r, uint8_t* marks, double* extra_xyz, int32_t* tets);
+/* A nodal function of the input mesh (host, n_old entries) on the refined mesh's nodes (host,
+ * n_old + n_bisected entries): old nodes keep their values, each midpoint in bisection order
+ * takes the mean of its edge's endpoints (the refined mesh carries the same piecewise-linear
+ * function); computed in FP64 and rounded once. */
+int dd_meshref_interpolate(const dd_refinement* r, const float* in, float* out);
+int dd_meshref_destroy(dd_refinement* r);
 /* Releases the problem.  With hipMalloc memory the device is synchronised first; with a
  * caller allocator only the library's own second stream is, and each buffer goes back
  * through free_fn while the caller's stream may still hold queued work that reads it: the
@@ -386,6 +413,7 @@ typedef struct {
   double alpha_next[2];          /* alpha^{m+1} */
   double gamma_used[2];          /* gamma^m */
   double gamma_next[2];          /* gamma^{m+1} */
+  double change_norm[2];         /* |c^{m+1} - c^0|: distance from the initial guess */
 } dd_cga_info;
 
 /* Start a run on problem p from the initial guess eps0_dev, sig0_dev (FEM-node arrays,

@@ -130,7 +130,8 @@ def cga_update(state, dJ, coef, coef0, w, free):
         alpha_next = next_alpha(w, g, d, gamma, state.alpha[f])
         step = c - coef[f]
         info[f] = dict(grad_norm=math.sqrt(gn2), beta=beta, alpha_used=state.alpha[f], alpha_next=alpha_next,
-                       step_norm=math.sqrt(inner(w, step, step)), gamma_used=gamma)
+                       step_norm=math.sqrt(inner(w, step, step)), gamma_used=gamma,
+                       change_norm=math.sqrt(inner(w, c - coef0[f], c - coef0[f])))
         new[f] = c
         state.d[f] = d
         state.gn2_prev[f] = gn2

@@ -20,8 +20,8 @@ EXPORTS = [
     "dd_adjoint_misfit", "dd_cga_create", "dd_cga_destroy", "dd_cga_update", "dd_cga_get_info",
     "dd_paper_gradient_enable", "dd_gradient_paper", "dd_misfit", "dd_set_divdiv_form", "dd_set_initial_data", "dd_check_finite", "dd_batch_set_fill",
     "dd_misfit_noalloc", "dd_misfit_taper", "dd_set_coefficients_async", "dd_coefficients_status",
-    "dd_cga_steps_from_gradient", "dd_create_mesh", "dd_debug_fem_apply_mesh", "dd_meshref_marks",
-    "dd_meshref_mesh", "dd_meshref_values",
+    "dd_cga_steps_from_gradient", "dd_create_mesh", "dd_debug_fem_apply_mesh", "dd_meshref_create",
+    "dd_meshref_sizes", "dd_meshref_result", "dd_meshref_interpolate", "dd_meshref_destroy",
 ]
 
 (PROF_FD_FWD, PROF_FEM_FWD, PROF_FD_ADJ, PROF_FEM_ADJ, PROF_FEM_RECOMPUTE, PROF_STEP_FWD, PROF_STEP_ADJ,
@@ -87,7 +87,8 @@ class CgaParams(ctypes.Structure):
 class CgaInfo(ctypes.Structure):
     _fields_ = [("iterations", ctypes.c_int32), ("converged", ctypes.c_int32)] + [
         (name, ctypes.c_double * 2) for name in (
-            "grad_norm", "step_norm", "beta", "alpha_used", "alpha_next", "gamma_used", "gamma_next")]
+            "grad_norm", "step_norm", "beta", "alpha_used", "alpha_next", "gamma_used", "gamma_next",
+            "change_norm")]
 
 
 class DDError(RuntimeError):
@@ -137,10 +138,12 @@ def load():
     lib.dd_debug_fem_apply.argtypes = [ctypes.POINTER(ProblemDesc), P, P, ctypes.c_int32, P, P]
     lib.dd_debug_fem_apply_mesh.argtypes = [ctypes.POINTER(ProblemDesc), ctypes.c_int64, P, ctypes.c_int64, P, P, P,
                                             ctypes.c_int32, P, P]
-    lib.dd_meshref_marks.argtypes = [ctypes.POINTER(ProblemDesc), P, P, ctypes.c_double, ctypes.c_double, P]
-    lib.dd_meshref_marks.restype = ctypes.c_int64
-    lib.dd_meshref_mesh.argtypes = [ctypes.POINTER(ProblemDesc), P, P, P]
-    lib.dd_meshref_values.argtypes = [ctypes.POINTER(ProblemDesc), P, P, P]
+    lib.dd_meshref_create.argtypes = [ctypes.POINTER(ProblemDesc), ctypes.c_int64, P, ctypes.c_int64, P, P, P,
+                                      ctypes.c_double, ctypes.c_double, ctypes.POINTER(P)]
+    lib.dd_meshref_sizes.argtypes = [P] + [ctypes.POINTER(ctypes.c_int64)] * 4
+    lib.dd_meshref_result.argtypes = [P, P, P, P]
+    lib.dd_meshref_interpolate.argtypes = [P, P, P]
+    lib.dd_meshref_destroy.argtypes = [P]
     lib.dd_batch_create.argtypes = [ctypes.c_int32, ctypes.c_size_t, ctypes.POINTER(P)]
     lib.dd_batch_destroy.argtypes = [P]
     lib.dd_batch_submit.argtypes = [P, P, ctypes.POINTER(Source), ctypes.c_int32, P, P, P, P,

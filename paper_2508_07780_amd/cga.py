@@ -149,7 +149,8 @@ class CGA:
         out = {"iterations": c.iterations, "converged": bool(c.converged)}
         if self.track_loss and self.J is not None:
             out["J"] = float(self.J.item())     # J at the iterate the last update started from
-        for name in ("grad_norm", "step_norm", "beta", "alpha_used", "alpha_next", "gamma_used", "gamma_next"):
+        for name in ("grad_norm", "step_norm", "beta", "alpha_used", "alpha_next", "gamma_used", "gamma_next",
+                     "change_norm"):
             arr = getattr(c, name)
             out[name] = {"eps": arr[0], "sig": arr[1]}
         return out

@@ -1477,7 +1477,7 @@ int dd_cga_create(dd_problem* p, const dd_cga_params* prm, const float* eps0_dev
   c->actx = p->actx;
   c->c0 = static_cast<float*>(raw_alloc(p->alloc_fn, p->actx, 2 * c->n * sizeof(float)));
   c->d = static_cast<double*>(raw_alloc(p->alloc_fn, p->actx, 2 * c->n * sizeof(double)));
-  c->part = static_cast<double*>(raw_alloc(p->alloc_fn, p->actx, (size_t)CGA_MAX_BLOCKS * 6 * sizeof(double)));
+  c->part = static_cast<double*>(raw_alloc(p->alloc_fn, p->actx, (size_t)CGA_MAX_BLOCKS * CGA_SUMS * sizeof(double)));
   c->st = static_cast<CgaDev*>(raw_alloc(p->alloc_fn, p->actx, sizeof(CgaDev)));
   if (p->mass_api) c->w = static_cast<double*>(raw_alloc(p->alloc_fn, p->actx, c->n * sizeof(double)));
   if (!c->c0 || !c->d || !c->part || !c->st || (p->mass_api && !c->w)) {
@@ -1560,6 +1560,7 @@ int dd_cga_get_info(dd_cga* c, dd_cga_info* out, void* stream) {
     out->alpha_next[f] = h.alpha[f];
     out->gamma_used[f] = h.gamma_used[f];
     out->gamma_next[f] = h.gamma[f];
+    out->change_norm[f] = std::sqrt(h.change2[f]);
   }
   return DD_OK;
 }

@@ -129,7 +129,7 @@ __global__ __launch_bounds__(CGA_THREADS) void cga_step_kernel(
   const double beta[2] = {st->beta[0], st->beta[1]};
   const double alpha[2] = {st->alpha[0], st->alpha[1]};
   const double lo[2] = {st->lo[0], st->lo[1]}, hi[2] = {st->hi[0], st->hi[1]};
-  double acc[6] = {0.0, 0.0, 0.0, 0.0, 0.0, 0.0};
+  double acc[CGA_SUMS] = {0.0, 0.0, 0.0, 0.0, 0.0, 0.0, 0.0, 0.0};
   for (int64_t i = (int64_t)blockIdx.x * CGA_THREADS + threadIdx.x; i < n; i += (int64_t)gridDim.x * CGA_THREADS) {
     if (!cga_free(i, fsx, fsy, fsz)) continue;
     const double w = wn ? wn[i] : st->w;
@@ -140,10 +140,11 @@ __global__ __launch_bounds__(CGA_THREADS) void cga_step_kernel(
       const float cn = (float)fmin(fmax((double)c + alpha[0] * d, lo[0]), hi[0]);
       d_eps[i] = d;
       eps[i] = cn;
-      const double dc = (double)cn - (double)c;
+      const double dc = (double)cn - (double)c, dc0 = (double)cn - (double)eps0[i];
       acc[0] += w * g * d;
       acc[1] += w * d * d;
       acc[2] += w * dc * dc;
+      acc[6] += w * dc0 * dc0;
     }
     {
       const float c = sig[i];
@@ -152,20 +153,21 @@ __global__ __launch_bounds__(CGA_THREADS) void cga_step_kernel(
       const float cn = (float)fmin(fmax((double)c + alpha[1] * d, lo[1]), hi[1]);
       d_sig[i] = d;
       sig[i] = cn;
-      const double dc = (double)cn - (double)c;
+      const double dc = (double)cn - (double)c, dc0 = (double)cn - (double)sig0[i];
       acc[3] += w * g * d;
       acc[4] += w * d * d;
       acc[5] += w * dc * dc;
+      acc[7] += w * dc0 * dc0;
     }
   }
-  block_sums<6>(acc, part + (int64_t)blockIdx.x * 6);
+  block_sums<CGA_SUMS>(acc, part + (int64_t)blockIdx.x * CGA_SUMS);
 }
 
 // alpha^{m+1}, gamma^{m+1}, the stop test, m -> m + 1 (one block).
 __global__ __launch_bounds__(CGA_THREADS) void cga_finish_kernel(const double* __restrict__ part, int nb,
                                                                  CgaDev* __restrict__ st) {
-  __shared__ double tot[6];
-  sum_partials<6>(part, nb, tot);
+  __shared__ double tot[CGA_SUMS];
+  sum_partials<CGA_SUMS>(part, nb, tot);
   __syncthreads();
   if (threadIdx.x == 0) {
     bool small_step = false, small_grad = false;
@@ -174,6 +176,7 @@ __global__ __launch_bounds__(CGA_THREADS) void cga_finish_kernel(const double* _
       st->gd[f] = gd;
       st->dd[f] = dd;
       st->step2[f] = step2;
+      st->change2[f] = tot[6 + f];
       st->alpha_used[f] = st->alpha[f];
       st->gamma_used[f] = st->gamma[f];
       if (dd > 0.0) st->alpha[f] = -gd / (st->gamma[f] * dd);

@@ -18,6 +18,7 @@ struct CgaDev {
   int m, converged;
   // results of the last update
   double gn2[2], beta[2], gd[2], dd[2], step2[2], alpha_used[2], gamma_used[2];
+  double change2[2];         // |c^{m+1} - c^0|^2: the distance from the initial guess
 };
 // The FEM nodes of a run: the (fs[0] x fs[1] x fs[2]) lattice, then n_extra nodes of a general
 // mesh (free); w: FP64 lumped mass per FEM node (API order) or null for h^3 on every free node.
@@ -27,9 +28,11 @@ struct CgaMesh {
   const double* w;
 };
 constexpr int CGA_MAX_BLOCKS = 1024;
+// FP64 sums per block of an update: (g, d), (d, d), |step|^2 per field, then |c - c^0|^2 per field
+constexpr int CGA_SUMS = 8;
 int cga_blocks(int64_t n_fem);
 // Four launches: gradient-function norms, beta, direction / update / projection, step sizes.
-// part holds CGA_MAX_BLOCKS x 6 doubles.
+// part holds CGA_MAX_BLOCKS x CGA_SUMS doubles.
 void launch_cga_update(const double* gJe, const double* gJs, float* eps, float* sig, const float* eps0,
                        const float* sig0, double* d_eps, double* d_sig, const CgaMesh& g, CgaDev* st,
                        double* part, hipStream_t s);

@@ -19,7 +19,10 @@
 #include <array>
 #include <cmath>
 #include <cstring>
+#include <climits>
 #include <map>
+#include <set>
+#include <vector>
 
 #include "dd_common.hpp"
 
@@ -771,17 +774,36 @@ std::string build_mesh_general(const dd_problem_desc& d, int64_t n_extra, const 
 }  // namespace dd
 
 // ---------------------------------------------------------------------------------------
-// Local refinement of the Kuhn split (box "ACGA", eq. meshref), host only.
-// A cell is marked when one of its corners has |eps| >= beta_eps max|eps| and |sigma| >=
-// beta_sig max|sigma| (maxima over the FEM lattice; the mesh function h is the same on every
-// element of the uniform starting mesh, so it cancels), among cells whose corners are all
-// FEM-owned (layer >= 1), so that the overlap layers keep their lattice elements.  A marked
-// cell gets its centre as a node, and each of its six Kuhn tetrahedra (lowest corner, then one
-// axis step at a time, to the highest corner) is bisected across the cell's main diagonal,
-// which the centre halves: (v0, v1, v2, centre) and (centre, v1, v2, v3).  The cell's faces
-// are not split, so unmarked neighbours stay conforming.  Values at a centre: the mean of the
-// cell's eight corners (the trilinear interpolant there).
+// Local refinement of a FEM mesh (box "ACGA", steps 2 and 3, eq. meshref), host only.
+//
+// Marking: h_K is an element's diameter (its longest edge) and eps, sigma are nodal; element K
+// is marked when at one of its vertices v both h_K |eps(v)| >= beta_eps M_eps and
+// h_K |sigma(v)| >= beta_sig M_sig hold, M the largest such product over all elements and
+// their vertices.
+//
+// Refining: longest-edge bisection with propagation.  Element K is bisected at its longest
+// edge e (ties within 1e-9: the smaller (low, high) pair of node ids), together with every
+// element around e, at e's midpoint; any element around e whose own longest edge is another
+// one is bisected first, the same way (recursively, in increasing element id), so that every
+// element is split at its longest edge and the shapes do not degenerate.  An edge is bisected
+// only when every element around it has all four vertices FEM-owned (lattice layer >= 1), so
+// the overlap layers keep their lattice elements; a marked element whose propagation reaches
+// another edge is left as it is.  Marked elements are taken in element order; the k-th
+// bisection's midpoint becomes node n + k; an element split at (a, b), a < b, becomes its half
+// with b replaced by the midpoint and its half with a replaced by it, in that order in the
+// element list (children take ids after all existing ones).  Interpolation: each midpoint, in
+// bisection order, takes the mean of its edge's endpoints (so the refined mesh carries the
+// same piecewise-linear function), in FP64, rounded once to float32.
 // ---------------------------------------------------------------------------------------
+struct dd_refinement {
+  int64_t n_old = 0;                           // FEM nodes of the input mesh
+  int64_t n_tets_in = 0, n_marked = 0;
+  std::vector<uint8_t> marks;                  // per input element
+  std::vector<std::array<int64_t, 2>> split;   // bisected edges, in order
+  std::vector<double> xyz;                     // extra nodes of the refined mesh (old, then new)
+  std::vector<int32_t> tets;                   // refined elements
+};
+
 namespace {
 // Kuhn tetrahedron q of cell (i, j, k): its four vertices as lattice coordinates.
 void kuhn_tet(int i, int j, int k, int q, int v[4][3]) {
@@ -792,91 +814,238 @@ void kuhn_tet(int i, int j, int k, int q, int v[4][3]) {
     ++v[s][perm[q][s - 1]];
   }
 }
+
+using Edge = std::pair<int64_t, int64_t>;
+inline Edge edge_of(int64_t a, int64_t b) { return a < b ? Edge(a, b) : Edge(b, a); }
+constexpr double TIE = 1e-9;
+
+struct Refiner {
+  std::vector<std::array<double, 3>> P;        // node positions in units of h from the box corner
+  std::vector<int> layer;                      // lattice layer; midpoints and extra nodes: free
+  std::vector<std::array<int64_t, 4>> verts;   // element id -> vertices (leaves: the current mesh)
+  std::vector<std::array<int64_t, 2>> kids;    // {-1, -1} for a leaf
+  std::map<Edge, std::set<int64_t>> around;    // edge -> current elements that contain it
+  std::vector<Edge> split;
+
+  double len2(const Edge& e) const {
+    double s = 0.0;
+    for (int a = 0; a < 3; ++a) {
+      const double d = P[e.first][a] - P[e.second][a];
+      s += d * d;
+    }
+    return s;
+  }
+  Edge longest(int64_t t) const {
+    const auto& v = verts[t];
+    Edge es[6];
+    double l2[6], top = 0.0;
+    int n = 0;
+    for (int a = 0; a < 4; ++a)
+      for (int b = a + 1; b < 4; ++b) {
+        es[n] = edge_of(v[a], v[b]);
+        l2[n] = len2(es[n]);
+        top = std::max(top, l2[n]);
+        ++n;
+      }
+    Edge best(INT64_MAX, INT64_MAX);
+    for (int i = 0; i < 6; ++i)
+      if (l2[i] >= (1.0 - TIE) * top && es[i] < best) best = es[i];
+    return best;
+  }
+  void add(int64_t t) {
+    const auto& v = verts[t];
+    for (int a = 0; a < 4; ++a)
+      for (int b = a + 1; b < 4; ++b) around[edge_of(v[a], v[b])].insert(t);
+  }
+  bool eligible(const Edge& e) const {
+    auto it = around.find(e);
+    if (it == around.end()) return false;
+    for (int64_t t : it->second)
+      for (int64_t v : verts[t])
+        if (layer[v] < 1) return false;
+    return true;
+  }
+  void bisect(const Edge& e) {
+    const int64_t m = (int64_t)P.size();
+    std::array<double, 3> q;
+    for (int a = 0; a < 3; ++a) q[a] = 0.5 * (P[e.first][a] + P[e.second][a]);
+    P.push_back(q);
+    layer.push_back(1 << 30);
+    split.push_back(e);
+    auto node = around.extract(e);
+    for (int64_t t : node.mapped()) {   // increasing id
+      const auto v = verts[t];
+      for (int a = 0; a < 4; ++a)
+        for (int b = a + 1; b < 4; ++b) {
+          const Edge f = edge_of(v[a], v[b]);
+          if (f != e) around[f].erase(t);
+        }
+      std::array<int64_t, 4> h0 = v, h1 = v;
+      for (int a = 0; a < 4; ++a) {
+        if (h0[a] == e.second) h0[a] = m;
+        if (h1[a] == e.first) h1[a] = m;
+      }
+      const int64_t c0 = (int64_t)verts.size();
+      verts.push_back(h0);
+      kids.push_back({-1, -1});
+      add(c0);
+      verts.push_back(h1);
+      kids.push_back({-1, -1});
+      add(c0 + 1);
+      kids[t] = {c0, c0 + 1};
+    }
+  }
+  bool refine_element(int64_t t) {
+    while (kids[t][0] < 0) {
+      const Edge e = longest(t);
+      if (!eligible(e)) return false;
+      std::vector<int64_t> others;
+      for (int64_t u : around[e])
+        if (longest(u) != e) others.push_back(u);   // std::set: increasing id
+      if (others.empty()) {
+        bisect(e);
+        return true;
+      }
+      for (int64_t u : others)
+        if (kids[u][0] < 0 && !refine_element(u)) return false;
+    }
+    return true;
+  }
+  void emit(int64_t t, std::vector<int32_t>& out) const {
+    if (kids[t][0] >= 0) {
+      emit(kids[t][0], out);
+      emit(kids[t][1], out);
+    } else {
+      for (int64_t v : verts[t]) out.push_back((int32_t)v);
+    }
+  }
+};
 }  // namespace
 
-extern "C" int64_t dd_meshref_marks(const dd_problem_desc* d, const float* eps, const float* sig, double beta_eps,
-                                    double beta_sig, uint8_t* marks) {
-  if (!d || !eps || !sig || !marks || !(beta_eps >= 0.0 && beta_eps <= 1.0) || !(beta_sig >= 0.0 && beta_sig <= 1.0))
+extern "C" int dd_meshref_create(const dd_problem_desc* d, int64_t n_extra, const double* extra_xyz, int64_t n_tets,
+                                 const int32_t* tets, const float* eps, const float* sig, double beta_eps,
+                                 double beta_sig, dd_refinement** out) {
+  if (!out) return DD_ERR_INVALID_ARG;
+  *out = nullptr;
+  if (!d || !eps || !sig || !(beta_eps >= 0.0 && beta_eps <= 1.0) || !(beta_sig >= 0.0 && beta_sig <= 1.0) ||
+      n_extra < 0 || n_tets < 0 || (n_extra > 0 && !extra_xyz) || (n_tets > 0 && !tets) || (n_tets == 0 && n_extra))
     return DD_ERR_INVALID_ARG;
   const int c[3] = {d->fem_cells[0], d->fem_cells[1], d->fem_cells[2]};
-  if (c[0] < 2 || c[1] < 2 || c[2] < 2) return DD_ERR_INVALID_ARG;
+  if (c[0] < 2 || c[1] < 2 || c[2] < 2 || !(d->h > 0.0)) return DD_ERR_INVALID_ARG;
   const int s0 = c[0] + 1, s1 = c[1] + 1, s2 = c[2] + 1;
-  const int64_t n = (int64_t)s0 * s1 * s2;
-  double me = 0.0, ms = 0.0;
-  for (int64_t i = 0; i < n; ++i) {
-    me = std::max(me, std::fabs((double)eps[i]));
-    ms = std::max(ms, std::fabs((double)sig[i]));
+  const int64_t n_lat = (int64_t)s0 * s1 * s2;
+  const int64_t n_old = n_lat + n_extra;
+  if (n_old >= (1ll << 31)) return DD_ERR_INVALID_ARG;
+  Refiner R;
+  R.P.resize(n_old);
+  R.layer.resize(n_old);
+  for (int z = 0; z < s2; ++z)
+    for (int y = 0; y < s1; ++y)
+      for (int x = 0; x < s0; ++x) {
+        const int64_t i = x + (int64_t)s0 * (y + (int64_t)s1 * z);
+        R.P[i] = {(double)x, (double)y, (double)z};
+        R.layer[i] = std::min({x, c[0] - x, y, c[1] - y, z, c[2] - z});
+      }
+  for (int64_t e = 0; e < n_extra; ++e) {
+    for (int a = 0; a < 3; ++a) {
+      const double u = (extra_xyz[3 * e + a] - d->origin[a]) / d->h - d->fem_lo[a];
+      if (!(u > 0.0 && u < c[a])) return DD_ERR_INVALID_ARG;
+      R.P[n_lat + e][a] = u;
+    }
+    R.layer[n_lat + e] = 1 << 30;
   }
-  const double te = beta_eps * me, ts = beta_sig * ms;
-  int64_t count = 0;
-  for (int k = 0; k < c[2]; ++k)
-    for (int j = 0; j < c[1]; ++j)
-      for (int i = 0; i < c[0]; ++i) {
-        const bool owned = i >= 1 && j >= 1 && k >= 1 && i + 1 <= c[0] - 1 && j + 1 <= c[1] - 1 && k + 1 <= c[2] - 1;
-        bool hit = false;
-        for (int q = 0; q < 8 && owned && !hit; ++q) {
-          const int64_t v = (i + (q & 1)) + (int64_t)s0 * ((j + ((q >> 1) & 1)) + (int64_t)s1 * (k + (q >> 2)));
-          hit = std::fabs((double)eps[v]) >= te && std::fabs((double)sig[v]) >= ts;
-        }
-        marks[i + (int64_t)c[0] * (j + (int64_t)c[1] * k)] = hit ? 1 : 0;
-        count += hit;
-      }
-  return count;
-}
-
-extern "C" int dd_meshref_mesh(const dd_problem_desc* d, const uint8_t* marks, double* extra_xyz, int32_t* tets) {
-  if (!d || !marks || !tets) return DD_ERR_INVALID_ARG;
-  const int c[3] = {d->fem_cells[0], d->fem_cells[1], d->fem_cells[2]};
-  const int s0 = c[0] + 1, s1 = c[1] + 1;
-  const int64_t n_lat = (int64_t)s0 * s1 * (c[2] + 1);
-  int64_t e = 0, t = 0;
-  for (int k = 0; k < c[2]; ++k)
-    for (int j = 0; j < c[1]; ++j)
-      for (int i = 0; i < c[0]; ++i) {
-        const bool m = marks[i + (int64_t)c[0] * (j + (int64_t)c[1] * k)] != 0;
-        int64_t centre = -1;
-        if (m) {
-          if (!extra_xyz) return DD_ERR_INVALID_ARG;
-          centre = n_lat + e;
-          const double g[3] = {d->fem_lo[0] + i + 0.5, d->fem_lo[1] + j + 0.5, d->fem_lo[2] + k + 0.5};
-          for (int a = 0; a < 3; ++a) extra_xyz[3 * e + a] = d->origin[a] + d->h * g[a];
-          ++e;
-        }
-        for (int q = 0; q < 6; ++q) {
-          int v[4][3];
-          kuhn_tet(i, j, k, q, v);
-          int64_t id[4];
-          for (int s = 0; s < 4; ++s) id[s] = v[s][0] + (int64_t)s0 * (v[s][1] + (int64_t)s1 * v[s][2]);
-          if (!m) {
-            for (int s = 0; s < 4; ++s) tets[4 * t + s] = (int32_t)id[s];
-            ++t;
-          } else {
-            const int64_t a[4] = {id[0], id[1], id[2], centre}, b[4] = {centre, id[1], id[2], id[3]};
-            for (int s = 0; s < 4; ++s) tets[4 * t + s] = (int32_t)a[s];
-            ++t;
-            for (int s = 0; s < 4; ++s) tets[4 * t + s] = (int32_t)b[s];
-            ++t;
+  if (n_tets == 0) {
+    for (int k = 0; k < c[2]; ++k)
+      for (int j = 0; j < c[1]; ++j)
+        for (int i = 0; i < c[0]; ++i)
+          for (int q = 0; q < 6; ++q) {
+            int v[4][3];
+            kuhn_tet(i, j, k, q, v);
+            std::array<int64_t, 4> id;
+            for (int s = 0; s < 4; ++s) id[s] = v[s][0] + (int64_t)s0 * (v[s][1] + (int64_t)s1 * v[s][2]);
+            R.verts.push_back(id);
           }
-        }
+  } else {
+    for (int64_t t = 0; t < n_tets; ++t) {
+      std::array<int64_t, 4> id;
+      for (int s = 0; s < 4; ++s) {
+        id[s] = tets[4 * t + s];
+        if (id[s] < 0 || id[s] >= n_old) return DD_ERR_INVALID_ARG;
       }
+      R.verts.push_back(id);
+    }
+  }
+  const int64_t nt = (int64_t)R.verts.size();
+  R.kids.assign(nt, {-1, -1});
+  // step 2: marks
+  std::vector<double> hk(nt);
+  double me = 0.0, ms = 0.0;
+  for (int64_t t = 0; t < nt; ++t) {
+    double top = 0.0;
+    for (int a = 0; a < 4; ++a)
+      for (int b = a + 1; b < 4; ++b) top = std::max(top, R.len2(edge_of(R.verts[t][a], R.verts[t][b])));
+    hk[t] = std::sqrt(top);
+    for (int64_t v : R.verts[t]) {
+      me = std::max(me, hk[t] * std::fabs((double)eps[v]));
+      ms = std::max(ms, hk[t] * std::fabs((double)sig[v]));
+    }
+  }
+  auto* r = new dd_refinement();
+  r->n_old = n_old;
+  r->n_tets_in = nt;
+  r->marks.assign(nt, 0);
+  const double te = beta_eps * me, ts = beta_sig * ms;
+  for (int64_t t = 0; t < nt; ++t)
+    for (int64_t v : R.verts[t])
+      if (hk[t] * std::fabs((double)eps[v]) >= te && hk[t] * std::fabs((double)sig[v]) >= ts) {
+        r->marks[t] = 1;
+        ++r->n_marked;
+        break;
+      }
+  // step 3: bisection
+  for (int64_t t = 0; t < nt; ++t) R.add(t);
+  for (int64_t t = 0; t < nt; ++t)
+    if (r->marks[t] && R.kids[t][0] < 0) R.refine_element(t);
+  for (int64_t t = 0; t < nt; ++t) R.emit(t, r->tets);
+  r->split.reserve(R.split.size());
+  for (const Edge& e : R.split) r->split.push_back({e.first, e.second});
+  r->xyz.assign(extra_xyz, extra_xyz + 3 * n_extra);
+  for (size_t k = 0; k < R.split.size(); ++k) {
+    const auto& q = R.P[n_old + k];
+    for (int a = 0; a < 3; ++a) r->xyz.push_back(d->origin[a] + d->h * (d->fem_lo[a] + q[a]));
+  }
+  *out = r;
   return DD_OK;
 }
 
-extern "C" int dd_meshref_values(const dd_problem_desc* d, const uint8_t* marks, const float* lattice, float* out) {
-  if (!d || !marks || !lattice || !out) return DD_ERR_INVALID_ARG;
-  const int c[3] = {d->fem_cells[0], d->fem_cells[1], d->fem_cells[2]};
-  const int s0 = c[0] + 1, s1 = c[1] + 1;
-  const int64_t n_lat = (int64_t)s0 * s1 * (c[2] + 1);
-  for (int64_t i = 0; i < n_lat; ++i) out[i] = lattice[i];
-  int64_t e = 0;
-  for (int k = 0; k < c[2]; ++k)
-    for (int j = 0; j < c[1]; ++j)
-      for (int i = 0; i < c[0]; ++i) {
-        if (!marks[i + (int64_t)c[0] * (j + (int64_t)c[1] * k)]) continue;
-        double sum = 0.0;
-        for (int q = 0; q < 8; ++q)
-          sum += (double)lattice[(i + (q & 1)) + (int64_t)s0 * ((j + ((q >> 1) & 1)) + (int64_t)s1 * (k + (q >> 2)))];
-        out[n_lat + e++] = (float)(sum / 8.0);
-      }
+extern "C" int dd_meshref_sizes(const dd_refinement* r, int64_t* n_marked, int64_t* n_bisected, int64_t* n_extra,
+                                int64_t* n_tets) {
+  if (!r) return DD_ERR_INVALID_ARG;
+  if (n_marked) *n_marked = r->n_marked;
+  if (n_bisected) *n_bisected = (int64_t)r->split.size();
+  if (n_extra) *n_extra = (int64_t)r->xyz.size() / 3;
+  if (n_tets) *n_tets = (int64_t)r->tets.size() / 4;
+  return DD_OK;
+}
+
+extern "C" int dd_meshref_result(const dd_refinement* r, uint8_t* marks, double* extra_xyz, int32_t* tets) {
+  if (!r || (!extra_xyz && !r->xyz.empty()) || !tets) return DD_ERR_INVALID_ARG;
+  if (marks) std::memcpy(marks, r->marks.data(), r->marks.size());
+  if (!r->xyz.empty()) std::memcpy(extra_xyz, r->xyz.data(), r->xyz.size() * sizeof(double));
+  std::memcpy(tets, r->tets.data(), r->tets.size() * sizeof(int32_t));
+  return DD_OK;
+}
+
+extern "C" int dd_meshref_interpolate(const dd_refinement* r, const float* in, float* out) {
+  if (!r || !in || !out) return DD_ERR_INVALID_ARG;
+  std::vector<double> v(in, in + r->n_old);
+  v.reserve(r->n_old + r->split.size());
+  for (const auto& e : r->split) v.push_back(0.5 * (v[e[0]] + v[e[1]]));
+  for (size_t i = 0; i < v.size(); ++i) out[i] = (float)v[i];
+  return DD_OK;
+}
+
+extern "C" int dd_meshref_destroy(dd_refinement* r) {
+  delete r;
   return DD_OK;
 }

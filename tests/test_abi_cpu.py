@@ -223,17 +223,32 @@ def test_footprint_covers_store_all_and_the_defaults_of_zeroed_fields(lib):
 
 def _refined_case(name, beta=0.5):
     w = synth.small(name)
+    if beta is None:
+        # three successive longest-edge refinements (the oracle's) around a smooth bump
+        from oracle import acga as oacga
+        mesh = None
+        c = np.asarray(w.desc.fem_cells, dtype=np.float64)
+        for _ in range(3):
+            P = oacga.node_coords(w.desc, np.zeros((0, 3)) if mesh is None else mesh[0])
+            f = np.exp(-np.sum((P - 0.45 * c) ** 2, axis=1) / (0.08 * c.min() ** 2))
+            mesh = oacga.refine(w.desc, mesh, oacga.marks(w.desc, mesh, f, f, 0.5, 0.0))["mesh"]
+        n = int(np.prod(c + 1)) + len(mesh[0])
+        eps = 1.0 + np.random.default_rng(4).random(n)
+        lay = oacga.node_layers(w.desc, n)
+        eps[lay <= 1] = 1.0
+        return w, np.ones(1, dtype=bool), mesh, eps
     marks = synth.meshref_marks(w.desc, w.eps, beta)
     mesh = synth.refined_mesh(w.desc, marks)
     eps = synth.refined_values(w.desc, marks, w.eps)
     return w, marks, mesh, eps
 
 
-@pytest.mark.parametrize("name,beta", [("tiny", 0.5), ("skinlet", 0.3), ("ragged", 0.0)])
+@pytest.mark.parametrize("name,beta", [("tiny", 0.5), ("skinlet", 0.3), ("ragged", 0.0), ("ragged", None)])
 def test_general_mesh_data_path_reproduces_oracle_operator(lib, name, beta):
     """The element data dd_create_mesh builds from a refined mesh (eq. meshref: marked cells get
-    their centre and bisected Kuhn tetrahedra) reproduce the oracle's FEM rows of A and A^T on
-    that mesh; beta = 0 marks every cell whose corners are FEM-owned."""
+    their centre and bisected Kuhn tetrahedra; beta = 0 marks every cell whose corners are
+    FEM-owned; None: three successive longest-edge refinements) reproduce the oracle's FEM rows
+    of A and A^T on that mesh."""
     from paper_2508_07780_amd import _lib
     w, marks, (xyz, tets), eps = _refined_case(name, beta)
     assert marks.sum() > 0
@@ -297,26 +312,68 @@ def test_malformed_general_meshes_are_refused(lib):
     assert not h.value
 
 
-@pytest.mark.parametrize("name,be,bs", [("skinlet", 0.3, 0.0), ("ragged", 0.5, 0.2), ("tiny", 0.0, 0.0),
-                                        ("skinlet", 0.9, 0.9)])
-def test_library_refinement_equals_the_oracle(lib, name, be, bs):
-    """dd_meshref_marks / _mesh / _values (the library's host refinement of box "ACGA") against
-    the oracle's independent marking, mesh and interpolation on the same float32 values:
-    marks and tetrahedra bit for bit, centres to 1e-15, interpolated values within one float32
-    rounding of the FP64 mean."""
+def _bump(desc, ext, centre, width):
+    """A smooth seeded-free test field on the nodes (lattice, then extra), float32."""
+    from oracle import acga as oacga
+    P = oacga.node_coords(desc, ext)
+    c = np.asarray(desc.fem_cells, dtype=np.float64)
+    return np.exp(-np.sum((P - centre * c) ** 2, axis=1) / (width * c.min() ** 2)).astype(np.float32)
+
+
+@pytest.mark.parametrize("name,be,bs,levels", [("skinlet", 0.3, 0.0, 1), ("ragged", 0.5, 0.2, 3), ("tiny", 0.0, 0.0, 1),
+                                               ("skinlet", 0.9, 0.9, 1), ("tiny", 0.5, 0.3, 4)])
+def test_library_refinement_equals_the_oracle(lib, name, be, bs, levels):
+    """dd_meshref_create / _result / _interpolate (the library's host refinement of box "ACGA")
+    against the oracle's independent marking, bisection and interpolation on the same float32
+    values, over successive refinements: marks and elements bit for bit, midpoints to 1e-14 of
+    the box's scale, interpolated values equal to the oracle's FP64 means rounded once."""
     from oracle import acga as oacga
     from paper_2508_07780_amd import acga
     w = synth.small(name)
-    eps = np.asarray(w.eps, dtype=np.float32)
-    sig = np.asarray(w.sigma + 0.01 * np.random.default_rng(9).random(w.sigma.size) * (w.sigma > 0),
-                     dtype=np.float32)
-    marks, (xyz, tets) = acga.meshref(w.desc, eps, sig, be, bs)
-    om = oacga.marks(w.desc, eps.astype(np.float64), sig.astype(np.float64), be, bs)
-    assert np.array_equal(marks.astype(bool), om)
-    oxyz, otets = oacga.refine(w.desc, om)
-    assert np.array_equal(tets, otets.astype(np.int32))
-    assert xyz.shape == oxyz.shape and (len(xyz) == 0 or np.abs(xyz - oxyz).max() <= 1e-15)
-    v = acga.interpolate(w.desc, marks, eps)
-    ov = oacga.interpolate(w.desc, om, eps.astype(np.float64))
-    assert np.array_equal(v[:eps.size], eps)
-    assert np.all(v[eps.size:] == ov[eps.size:].astype(np.float32))
+    mesh = None
+    n_lat = int(np.prod(np.asarray(w.desc.fem_cells) + 1))
+    for level in range(levels):
+        ext = np.zeros((0, 3)) if mesh is None else mesh[0]
+        if level == 0 and name != "tiny":
+            eps = np.asarray(w.eps, dtype=np.float32)
+            sig = np.asarray(w.sigma + 0.01 * np.random.default_rng(9).random(w.sigma.size) * (w.sigma > 0),
+                             dtype=np.float32)
+        else:
+            eps = 1.0 + _bump(w.desc, ext, 0.45, 0.1)
+            sig = _bump(w.desc, ext, 0.55, 0.2)
+        r = acga.Refinement(w.desc, mesh, eps, sig, be, bs)
+        om = oacga.marks(w.desc, mesh, eps.astype(np.float64), sig.astype(np.float64), be, bs)
+        assert np.array_equal(r.marks.astype(bool), om)
+        oref = oacga.refine(w.desc, mesh, om)
+        oxyz, otets = oref["mesh"]
+        assert r.n_bisected == len(oref["edges"])
+        assert np.array_equal(r.mesh[1], otets.astype(np.int32))
+        assert r.mesh[0].shape == oxyz.shape
+        scale = max(1.0, float(np.abs(oxyz).max())) if len(oxyz) else 1.0
+        assert len(oxyz) == 0 or np.abs(r.mesh[0] - oxyz).max() <= 1e-14 * scale
+        v = r.interpolate(eps)
+        ov = oacga.interpolate(oref, eps.astype(np.float64))
+        assert np.array_equal(v[:eps.size], eps)
+        assert np.array_equal(v, ov.astype(np.float32))
+        mesh = r.mesh
+        r.close()
+        if be == 0.0 and bs == 0.0:
+            assert len(mesh[0]) > 0
+    assert len(mesh[1]) >= 6 * np.prod(w.desc.fem_cells) and n_lat > 0
+
+
+def test_refinement_rejects_bad_input(lib):
+    from paper_2508_07780_amd import acga, _lib as L
+    w = synth.small("tiny")
+    n = int(np.prod(np.asarray(w.desc.fem_cells) + 1))
+    e = np.ones(n, dtype=np.float32)
+    with pytest.raises(L.DDError):
+        acga.Refinement(w.desc, None, e, e, 1.5, 0.0)
+    ext = np.asarray([w.desc.origin], dtype=np.float64)      # the box's corner region: outside its interior
+    _, tets = synth.refined_mesh(w.desc, np.zeros(int(np.prod(w.desc.fem_cells)), dtype=bool))
+    with pytest.raises(L.DDError):
+        acga.Refinement(w.desc, (ext, tets), np.ones(n + 1), np.ones(n + 1), 0.5, 0.0)
+    bad = tets.copy()
+    bad[0, 0] = n + 5
+    with pytest.raises(L.DDError):
+        acga.Refinement(w.desc, (np.zeros((0, 3)), bad), e, e, 0.5, 0.0)

@@ -7,7 +7,8 @@
   C-ABI), so the oracle's iterate is rounded to float32 after each update before the next
   one.  Bars: iterates within one float32 ulp (1e-12 absolute where the update cancels to
   almost zero); scalars (norms, beta, alpha, gamma) rel 1e-12
-  (FP64 sums in another order).
+  (FP64 sums in another order); the step and the distance from the initial guess rel 1e-6
+  (the product measures them on the float32 iterate, the oracle on its FP64 value).
 * The degenerate cases: a zero gradient (beta guarded, alpha kept, no movement), steps
   that leave the box (clamped to 1 / eps_max and 0 / sig_max), layers 0-1 never written.
 * The misfit adjoint (cotangent traces - obs formed in the kernels) against the oracle's
@@ -81,6 +82,7 @@ def _run_update_parity(desc, params, n_updates=4, seed=1, zero_sig_from=None):
             for k in ("grad_norm", "beta", "alpha_used", "alpha_next", "gamma_used", "gamma_next"):
                 assert info[k][f] == pytest.approx(oi[f][k], rel=1e-12, abs=1e-300), (m, f, k)
             assert info["step_norm"][f] == pytest.approx(oi[f]["step_norm"], rel=1e-6, abs=1e-300), (m, f)
+            assert info["change_norm"][f] == pytest.approx(oi[f]["change_norm"], rel=1e-6, abs=1e-300), (m, f)
         assert info["iterations"] == m + 1 and info["converged"] == oi["converged"]
     c.close()
     p.close()

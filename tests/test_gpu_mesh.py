@@ -2,7 +2,9 @@
 
 The meshes are those of eq. meshref after one refinement of the uniform starting mesh: cells
 where |eps| >= beta max |eps| at a corner get their centre as a node and their six Kuhn
-tetrahedra bisected across the main diagonal (synth.refined_mesh).  The FEM rows then run on
+tetrahedra bisected across the main diagonal (synth.refined_mesh); and meshes after three
+successive longest-edge refinements of the elements where eps is largest (the oracle's step 3
+of box "ACGA").  The FEM rows then run on
 the element-coloured kernel with the library's partitions of the caller's tetrahedra; dt is
 0.8 times the explicit scheme's limit on the refined mesh (power iteration on the oracle's
 operator), which the refined cells push below the uniform mesh's h / sqrt(3).  Bars as everywhere: traces rel L2 <= 1e-4, gradient rel L2 <= 1e-3 (over every FEM
@@ -45,10 +47,21 @@ def step_limit(d, iters=300, seed=0):
 
 def _refined(name, beta):
     w = synth.small(name)
-    marks = synth.meshref_marks(w.desc, w.eps, beta)
-    mesh = synth.refined_mesh(w.desc, marks)
-    eps = _f32(synth.refined_values(w.desc, marks, w.eps))
-    sig = _f32(synth.refined_values(w.desc, marks, w.sigma))
+    if beta is None:
+        # three successive longest-edge refinements (the oracle's ACGA step 3) around the
+        # largest eps; values interpolated level by level
+        from oracle import acga as oacga
+        mesh, eps, sig = None, np.asarray(w.eps, dtype=np.float64), np.asarray(w.sigma, dtype=np.float64)
+        for _ in range(3):
+            ref = oacga.refine(w.desc, mesh, oacga.marks(w.desc, mesh, eps, sig, 0.7, 0.0))
+            mesh, eps, sig = ref["mesh"], oacga.interpolate(ref, eps), oacga.interpolate(ref, sig)
+        marks = np.ones(len(mesh[0]), dtype=bool)
+        eps, sig = _f32(eps), _f32(sig)
+    else:
+        marks = synth.meshref_marks(w.desc, w.eps, beta)
+        mesh = synth.refined_mesh(w.desc, marks)
+        eps = _f32(synth.refined_values(w.desc, marks, w.eps))
+        sig = _f32(synth.refined_values(w.desc, marks, w.sigma))
     # the refined cells lower the limit below the uniform mesh's h / sqrt(3): they set dt
     lim = step_limit(Discretization(w.desc, mesh=mesh).set_coefficients(eps, sig))
     assert lim < w.desc.h / math.sqrt(3.0)
@@ -64,12 +77,13 @@ def _problem(torch, w, mesh, eps, sig):
     return p
 
 
-@pytest.mark.parametrize("name,beta", [("tiny", 0.5), ("skinlet", 0.3), ("ragged", 0.6)])
+@pytest.mark.parametrize("name,beta", [("tiny", 0.5), ("skinlet", 0.3), ("ragged", 0.6), ("ragged", None),
+                                       ("skinlet", None)])
 def test_refined_mesh_matches_oracle(name, beta):
     import torch
     w, marks, mesh, eps, sig = _refined(name, beta)
-    print(f"[gpu] refined mesh {name} beta {beta}: {int(marks.sum())} cells refined, "
-          f"{len(mesh[0])} centres, {len(mesh[1])} tets, dt {w.desc.dt:.4g}, steps {w.desc.n_steps}", flush=True)
+    print(f"[gpu] refined mesh {name} beta {beta}: {len(mesh[0])} extra nodes, {len(mesh[1])} tets, "
+          f"dt {w.desc.dt:.4g}, steps {w.desc.n_steps}", flush=True)
     d = Discretization(w.desc, mesh=mesh).set_coefficients(eps, sig)
     fw = forward(d, w.sources[0])
     eobs = (0.6 * fw["traces"]).astype(np.float32)
