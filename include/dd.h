@@ -159,7 +159,9 @@ int dd_create(const dd_problem_desc* desc, dd_alloc_fn alloc_fn, dd_free_fn free
  * which a refined mesh lowers: the caller chooses dt accordingly.
  * Errors: DD_ERR_INVALID_ARG (descriptor, or a mesh that breaks the rules above),
  * DD_ERR_UNSUPPORTED (as dd_create, or a mesh too dense for the kernel's partitions of
- * at most 512 owned / 1024 local nodes and 4608 elements), DD_ERR_OOM, DD_ERR_HIP. */
+ * at most 512 owned / 1024 local nodes, 4608 elements and 64 element colours: lattice blocks
+ * of 8^3 owned nodes are cut at their median until they fit, so only a node with more than
+ * 64 elements around it, or a single node over the limits, is refused), DD_ERR_OOM, DD_ERR_HIP. */
 int dd_create_mesh(const dd_problem_desc* desc, int64_t n_extra, const double* extra_xyz, int64_t n_tets,
                    const int32_t* tets, dd_alloc_fn alloc_fn, dd_free_fn free_fn, void* ctx, dd_problem** out);
 

@@ -522,9 +522,10 @@ namespace dd {
 
 // General tetrahedral mesh of the FEM box: the box's lattice nodes (lexicographic) and n_extra
 // extra nodes strictly inside it, and n_tets tetrahedra in those node indices.  Owned nodes
-// (lattice layer >= 1, every extra node) are grouped by lattice blocks of pb^3 (an extra node
-// joins the block of the cell it lies in); the block edge shrinks until every partition fits
-// the element kernel's limits.  Everything else is built as for the Kuhn split's element path.
+// (lattice layer >= 1, every extra node) are grouped by lattice blocks of 8^3 (an extra node
+// joins the block of the cell it lies in); a block that does not fit the element kernel's
+// limits is cut at the median of its nodes, recursively.  Everything else is built as for the
+// Kuhn split's element path.
 std::string build_mesh_general(const dd_problem_desc& d, int64_t n_extra, const double* xyz, int64_t n_tets,
                                const int32_t* tv, HostMesh& m) {
   Lattice L;
@@ -611,25 +612,107 @@ std::string build_mesh_general(const dd_problem_desc& d, int64_t n_extra, const 
   m.stencil_ok = false;
   m.n_slots = 0;
 
-  // partitions: owned nodes by lattice block; try block edges 8, 6, 4, 3, 2
-  for (int pb : {8, 6, 4, 3, 2}) {
+  // partitions: owned nodes by lattice blocks of 8^3 (an extra node joins the block of the
+  // cell it lies in, by its cell's lower corner); a block that exceeds the element kernel's
+  // limits (owned, local nodes, elements, colours) is cut in two at the median of its nodes
+  // along its longest extent, recursively, lower half first
+  std::vector<std::vector<int64_t>> members;
+  {
+    constexpr int pb = FEM_PB;
     const int ow[3] = {L.c[0] - 1, L.c[1] - 1, L.c[2] - 1};
     int npb[3];
     for (int a = 0; a < 3; ++a) npb[a] = (ow[a] + pb - 1) / pb;
-    const int n_part = npb[0] * npb[1] * npb[2];
     auto block_of = [&](const std::array<double, 3>& q) {
       int b[3];
       for (int a = 0; a < 3; ++a) {
-        // lattice owned coordinate 1..c-1 -> block; an extra node takes its cell's lower corner
         int c = (int)std::floor(q[a]);
         c = std::min(std::max(c, 1), L.c[a] - 1);
         b[a] = (c - 1) / pb;
       }
       return b[0] + npb[0] * (b[1] + npb[1] * b[2]);
     };
-    std::vector<std::vector<int64_t>> members(n_part);
+    std::vector<std::vector<int64_t>> blocks(npb[0] * npb[1] * npb[2]);
     for (int64_t i = 0; i < n_fem; ++i)
-      if (layer_of(i) >= 1) members[block_of(P[i])].push_back(i);   // lattice first, then extra: index order
+      if (layer_of(i) >= 1) blocks[block_of(P[i])].push_back(i);   // lattice first, then extra: index order
+    std::vector<int> mark(n_fem, -1), tstamp(n_tets, -1);
+    int call = 0;
+    // does a partition of these owned nodes fit (the same counts and greedy colouring as below)?
+    auto fits_part = [&](const std::vector<int64_t>& own) {
+      const int id = call++;
+      for (size_t k = 0; k < own.size(); ++k) mark[own[k]] = id;
+      std::vector<int> els;
+      for (int64_t i : own)
+        for (int a = adj_off[i]; a < adj_off[i + 1]; ++a)
+          if (tstamp[adj[a]] != id) {
+            tstamp[adj[a]] = id;
+            els.push_back(adj[a]);
+          }
+      if ((int)own.size() > FEM_OWN_MAX || (int)els.size() > FEM_ELEM_MAX) return false;
+      std::sort(els.begin(), els.end());
+      std::vector<int64_t> halo;
+      for (int t : els)
+        for (int k = 0; k < 4; ++k)
+          if (mark[tv[4 * t + k]] != id) halo.push_back(tv[4 * t + k]);
+      std::sort(halo.begin(), halo.end());
+      halo.erase(std::unique(halo.begin(), halo.end()), halo.end());
+      if ((int)(own.size() + halo.size()) > FEM_LOC_MAX) return false;
+      std::map<int64_t, int> loc;
+      for (size_t k = 0; k < own.size(); ++k) loc[own[k]] = (int)k;
+      std::vector<uint64_t> used(own.size(), 0);
+      for (int t : els) {
+        uint64_t forbid = 0;
+        for (int k = 0; k < 4; ++k) {
+          auto it = loc.find(tv[4 * t + k]);
+          if (it != loc.end()) forbid |= used[it->second];
+        }
+        if (forbid == ~0ull) return false;
+        int c = 0;
+        while (forbid & (1ull << c)) ++c;
+        for (int k = 0; k < 4; ++k) {
+          auto it = loc.find(tv[4 * t + k]);
+          if (it != loc.end()) used[it->second] |= (1ull << c);
+        }
+      }
+      return true;
+    };
+    std::vector<std::vector<int64_t>> stack;
+    for (auto& b : blocks) {
+      if (b.empty()) continue;
+      stack.push_back(std::move(b));
+      while (!stack.empty()) {
+        std::vector<int64_t> v = std::move(stack.back());
+        stack.pop_back();
+        if (fits_part(v)) {
+          members.push_back(std::move(v));
+          continue;
+        }
+        if (v.size() < 2) return "the mesh is too dense for the FEM kernel's partitions";
+        int ax = 0;
+        double ext = -1.0;
+        for (int a = 0; a < 3; ++a) {
+          double lo = 1e300, hi = -1e300;
+          for (int64_t i : v) {
+            lo = std::min(lo, P[i][a]);
+            hi = std::max(hi, P[i][a]);
+          }
+          if (hi - lo > ext) {
+            ext = hi - lo;
+            ax = a;
+          }
+        }
+        std::vector<int64_t> w = v;
+        std::stable_sort(w.begin(), w.end(), [&](int64_t a, int64_t b) { return P[a][ax] < P[b][ax]; });
+        const size_t half = w.size() / 2;
+        std::vector<int64_t> lo(w.begin(), w.begin() + half), hi(w.begin() + half, w.end());
+        std::sort(lo.begin(), lo.end());
+        std::sort(hi.begin(), hi.end());
+        stack.push_back(std::move(hi));   // the lower half is taken first
+        stack.push_back(std::move(lo));
+      }
+    }
+  }
+  {
+    const int n_part = (int)members.size();
     // internal numbering: partition-major
     std::vector<int> code(n_fem);
     for (int z = 0; z < L.s[2]; ++z)
@@ -760,7 +843,7 @@ std::string build_mesh_general(const dd_problem_desc& d, int64_t n_extra, const 
         q.elems.push_back(w);
       }
     }
-    if (!fits) continue;
+    if (!fits) return "the mesh is too dense for the FEM kernel's partitions";
     q.halo_off[n_part] = (int)q.halo.size();
     q.geom.swap(m.geom);
     q.n_geom = m.n_geom;
@@ -768,7 +851,6 @@ std::string build_mesh_general(const dd_problem_desc& d, int64_t n_extra, const 
     m = std::move(q);
     return std::string();
   }
-  return "the mesh is too dense for the FEM kernel's partitions";
 }
 
 }  // namespace dd

@@ -223,14 +223,16 @@ def test_footprint_covers_store_all_and_the_defaults_of_zeroed_fields(lib):
 
 def _refined_case(name, beta=0.5):
     w = synth.small(name)
-    if beta is None:
-        # three successive longest-edge refinements (the oracle's) around a smooth bump
+    if beta in (None, "deep"):
+        # three successive longest-edge refinements (the oracle's) around a smooth bump, or six
+        # around a narrow one (blocks of the mesh then exceed the partition limits and are cut)
         from oracle import acga as oacga
         mesh = None
         c = np.asarray(w.desc.fem_cells, dtype=np.float64)
-        for _ in range(3):
+        levels, width = (3, 0.08) if beta is None else (6, 0.02)
+        for _ in range(levels):
             P = oacga.node_coords(w.desc, np.zeros((0, 3)) if mesh is None else mesh[0])
-            f = np.exp(-np.sum((P - 0.45 * c) ** 2, axis=1) / (0.08 * c.min() ** 2))
+            f = np.exp(-np.sum((P - 0.45 * c) ** 2, axis=1) / (width * c.min() ** 2))
             mesh = oacga.refine(w.desc, mesh, oacga.marks(w.desc, mesh, f, f, 0.5, 0.0))["mesh"]
         n = int(np.prod(c + 1)) + len(mesh[0])
         eps = 1.0 + np.random.default_rng(4).random(n)
@@ -243,12 +245,14 @@ def _refined_case(name, beta=0.5):
     return w, marks, mesh, eps
 
 
-@pytest.mark.parametrize("name,beta", [("tiny", 0.5), ("skinlet", 0.3), ("ragged", 0.0), ("ragged", None)])
+@pytest.mark.parametrize("name,beta", [("tiny", 0.5), ("skinlet", 0.3), ("ragged", 0.0), ("ragged", None),
+                                       ("ragged", "deep")])
 def test_general_mesh_data_path_reproduces_oracle_operator(lib, name, beta):
     """The element data dd_create_mesh builds from a refined mesh (eq. meshref: marked cells get
     their centre and bisected Kuhn tetrahedra; beta = 0 marks every cell whose corners are
-    FEM-owned; None: three successive longest-edge refinements) reproduce the oracle's FEM rows
-    of A and A^T on that mesh."""
+    FEM-owned; None: three successive longest-edge refinements; "deep": six, whose densest lattice
+    blocks are cut into smaller partitions) reproduce the oracle's FEM rows of A and A^T on that
+    mesh."""
     from paper_2508_07780_amd import _lib
     w, marks, (xyz, tets), eps = _refined_case(name, beta)
     assert marks.sum() > 0
