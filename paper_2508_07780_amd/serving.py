@@ -8,9 +8,11 @@ when a batch slot is free and its device footprint (dd_footprint_bytes plus its 
 observation and gradient buffers) fits in the HBM budget; admitted solves join the
 running batch at the next launch, so work of jobs of different sizes overlaps on the
 device.  A job whose single step already fills the GPU (at least `solo_cells` cells per
-step) gains nothing from sharing launches and is slower through the batch kernel: it waits
-until the batch is empty and then runs alone through the single-problem calls, in arrival
-order like every other job.  The one-at-a-time server runs the same jobs in arrival order through the
+step) gains nothing from sharing launches and is slower through the batch kernel: it runs
+through the single-problem calls instead, on a stream of its own, issued by a host thread of
+its own, so that it overlaps the batch on the device; two such jobs run at a time by default
+(two large solves side by side fill each other's launch tails), and jobs are admitted in
+arrival order.  The one-at-a-time server runs the same jobs in arrival order through the
 single-problem calls, for comparison.
 
 The device never waits for the host at a job boundary: admission (mesh set-up, the first
@@ -31,6 +33,7 @@ host array [n_src][n_steps][n_det][3]).  Otherwise observations are seeded synth
 traces' shape: the cost of a solve does not depend on their values.
 """
 
+import threading
 import time
 
 import numpy as np
@@ -179,12 +182,14 @@ class _Finisher:
 
 
 def serve_batched(requests, max_slots=16, hbm_budget=None, chunk=256, time_fn=time.perf_counter, keep=False,
-                  solo_cells=3_000_000, fill_cells=None, retries=1):
+                  solo_cells=3_000_000, fill_cells=None, retries=1, solo_overlap=True, solo_slots=2):
     """Continuous batching: returns a summary dict and per-job records (with each job's final
-    eps and sigma when keep is set).  Jobs of at least solo_cells cells per step run alone
-    through the single-problem calls (None: every job is batched).  fill_cells: the batch's
-    fill target per launch (None: the library's default).  retries: how often a failed job is
-    queued again before it is rejected."""
+    eps and sigma when keep is set).  Jobs of at least solo_cells cells per step run through
+    the single-problem calls (None: every job is batched): beside the batch on a stream and a
+    host thread of their own (solo_overlap; up to solo_slots such jobs at once, each on its
+    own stream), or alone once the batch has drained.
+    fill_cells: the batch's fill target per launch (None: the library's default).  retries:
+    how often a failed job is queued again before it is rejected."""
     dev = torch.device("cuda", torch.cuda.current_device())
     if hbm_budget is None:
         free, _ = torch.cuda.mem_get_info()
@@ -192,6 +197,10 @@ def serve_batched(requests, max_slots=16, hbm_budget=None, chunk=256, time_fn=ti
     pending = sorted(requests, key=lambda r: r.arrival)
     admit = torch.cuda.current_stream()
     run = torch.cuda.Stream(device=dev)
+    if not solo_overlap:
+        solo_slots = 1
+    slots = [{"stream": torch.cuda.Stream(device=dev) if solo_overlap else run, "thread": None, "job": None,
+              "error": None} for _ in range(solo_slots)]
     batch = Batch(max_slots, fill_cells=fill_cells)
     active = {}           # job id in the batch -> _Job
     in_use = 0
@@ -209,13 +218,13 @@ def serve_batched(requests, max_slots=16, hbm_budget=None, chunk=256, time_fn=ti
 
     fin = _Finisher(t0, keep, release)
 
-    def fail(req, job, err):
+    def fail(req, job, err, stream=None):
         """Release the job's slot and budget, then queue it again or reject it."""
         nonlocal in_use
         if job is not None:
             in_use -= job.footprint
             fin_ev = torch.cuda.Event()
-            fin_ev.record(run)
+            fin_ev.record(run if stream is None else stream)
             fin_ev.synchronize()            # nothing of it may still run when its memory goes
             job.close()
         n = failures.get(req.rid, 0) + 1
@@ -226,17 +235,46 @@ def serve_batched(requests, max_slots=16, hbm_budget=None, chunk=256, time_fn=ti
         else:
             rejected.append({"rid": req.rid, "arrival": req.arrival, "error": str(err)})
 
-    while pending or active:
+    def solo_worker(slot, job):
+        try:
+            with torch.cuda.stream(slot["stream"]):
+                _run_alone(job)
+        except DDError as e:
+            slot["error"] = e
+
+    def solo_finished():
+        """Account for each thread's job once its launches are all issued."""
+        nonlocal solves, work
+        for slot in slots:
+            th, job = slot["thread"], slot["job"]
+            if th is None or th.is_alive():
+                continue
+            th.join()
+            slot["thread"] = slot["job"] = None
+            if slot["error"] is not None:
+                err, slot["error"] = slot["error"], None
+                fail(job.req, job, err, slot["stream"])
+                continue
+            solves += job.req.iterations
+            work += cell_steps(job.req.workload.desc, len(job.req.workload.sources)) * job.req.iterations
+            fin.add(job, slot["stream"])
+
+    def solo_busy():
+        return [sl for sl in slots if sl["thread"] is not None]
+
+    while pending or active or solo_busy():
         fin.sweep()
+        solo_finished()
         now = time_fn() - t0
         # admission: arrived, a slot free, the footprint fits
         while pending and pending[0].arrival <= now and len(active) < max_slots:
             fp = job_footprint(pending[0])
             if fp > hbm_budget:
                 raise ValueError(f"request {pending[0].rid} needs {fp} bytes, over the HBM budget of {hbm_budget}")
-            solo = solo_cells is not None and step_cells(pending[0].workload.desc) >= solo_cells
-            if solo and active:
-                break                    # the batch drains first (arrival order is kept)
+            alone = solo_cells is not None and step_cells(pending[0].workload.desc) >= solo_cells
+            free_slot = next((sl for sl in slots if sl["thread"] is None), None)
+            if alone and (free_slot is None or (active and not solo_overlap)):
+                break                    # solo_slots such jobs at a time (arrival order is kept)
             if in_use + fp > hbm_budget:
                 break                    # room comes back as finished jobs are released
             req = pending.pop(0)
@@ -248,18 +286,15 @@ def serve_batched(requests, max_slots=16, hbm_budget=None, chunk=256, time_fn=ti
             job.footprint = fp
             in_use += fp
             peak_bytes = max(peak_bytes, in_use)
-            if solo:
-                peak_jobs = max(peak_jobs, 1)
-                try:
-                    run.wait_stream(admit)
-                    with torch.cuda.stream(run):
-                        _run_alone(job)
-                except DDError as e:
-                    fail(req, job, e)
-                    continue
-                solves += req.iterations
-                work += cell_steps(req.workload.desc, len(req.workload.sources)) * req.iterations
-                fin.add(job, run)
+            if alone:
+                peak_jobs = max(peak_jobs, len(active) + len(solo_busy()) + 1)
+                free_slot["stream"].wait_stream(admit)
+                free_slot["job"] = job
+                free_slot["thread"] = threading.Thread(target=solo_worker, args=(free_slot, job), daemon=True)
+                free_slot["thread"].start()
+                if not solo_overlap:
+                    free_slot["thread"].join()
+                    solo_finished()
                 now = time_fn() - t0
                 continue
             try:
@@ -272,10 +307,16 @@ def serve_batched(requests, max_slots=16, hbm_budget=None, chunk=256, time_fn=ti
             active[jid] = job
             peak_jobs = max(peak_jobs, len(active))
         if not active:
-            if not pending:
+            busy = solo_busy()
+            if not pending and not busy:
                 break            # the last jobs ran alone
-            # idle until the next arrival, or until finished jobs free room
-            time.sleep(max(0.0005, min(0.01, pending[0].arrival - now)))
+            # idle until the next arrival, until finished jobs free room, or until a job
+            # beside the batch has issued its work
+            wait = 0.01 if not pending else min(0.01, pending[0].arrival - now)
+            if busy:
+                busy[0]["thread"].join(timeout=max(0.0005, wait))
+            else:
+                time.sleep(max(0.0005, wait))
             continue
         try:
             with torch.cuda.stream(run):
@@ -306,6 +347,8 @@ def serve_batched(requests, max_slots=16, hbm_budget=None, chunk=256, time_fn=ti
                 continue
             fin.add(job, run)
     run.synchronize()
+    for sl in slots:
+        sl["stream"].synchronize()
     fin.sweep(wait=True)
     makespan = time_fn() - t0
     batch.close()

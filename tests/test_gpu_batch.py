@@ -155,10 +155,12 @@ def test_serving_completes_and_respects_budget():
             assert float(torch.linalg.norm(a - b)) <= 1e-4 * float(torch.linalg.norm(b)), (r["rid"], f)
 
 
-def test_serving_runs_large_jobs_alone():
-    """Jobs at or above the solo threshold wait for the batch to drain and run alone through
-    the single-problem calls (the one-at-a-time server's calls: the same reconstruction bit
-    for bit); the others are batched; every job completes in arrival order of admission."""
+@pytest.mark.parametrize("overlap,slots", [(True, 2), (True, 1), (False, 1)])
+def test_serving_runs_large_jobs_alone(overlap, slots):
+    """Jobs at or above the solo threshold run through the single-problem calls (the
+    one-at-a-time server's calls: the same reconstruction bit for bit), on streams and host
+    threads of their own beside the batch (two or one at a time), or after the batch has
+    drained; the others are batched; every job completes."""
     import torch
     from paper_2508_07780_amd import serving
     reqs = synth.serving_requests(6, 20.0, outer=(40, 48), fem=(16, 24), sources=(1, 3), steps=(40, 90),
@@ -167,7 +169,9 @@ def test_serving_runs_large_jobs_alone():
     thr = cells[len(cells) // 2]
     solo = {r.rid for r in reqs if serving.step_cells(r.workload.desc) >= thr}
     assert 0 < len(solo) < len(reqs)
-    s_b, rec_b = serving.serve_batched(reqs, max_slots=4, chunk=16, keep=True, solo_cells=thr)
+    s_b, rec_b = serving.serve_batched(reqs, max_slots=4, chunk=16, keep=True, solo_cells=thr,
+                                       solo_overlap=overlap, solo_slots=slots)
+    assert s_b["in_use_end_bytes"] == 0
     s_s, rec_s = serving.serve_serial(reqs, keep=True)
     print(f"[gpu] serving with {len(solo)} solo jobs: {s_b}", flush=True)
     assert s_b["jobs"] == len(reqs) and s_b["solves"] == s_s["solves"]
@@ -236,6 +240,31 @@ def test_serving_failures_release_budget_and_requeue_or_reject(monkeypatch):
     done = {r["rid"] for r in rec if not r.get("rejected")}
     assert reqs[1].rid not in done and reqs[3].rid in done
     assert s["solves"] == sum(r.iterations for r in reqs if r.rid != reqs[1].rid)
+
+
+def test_serving_solo_failure_is_requeued(monkeypatch):
+    """A job beside the batch whose solve fails once (injected on the host, in its thread) is
+    released, queued again and completes; the budget comes back."""
+    from paper_2508_07780_amd import DDError, serving
+    reqs = synth.serving_requests(4, 20.0, outer=(40, 48), fem=(16, 24), sources=(1, 2), steps=(40, 60),
+                                  iterations=(2, 2))
+    cells = sorted(serving.step_cells(r.workload.desc) for r in reqs)
+    thr = cells[-1]
+    big = [r for r in reqs if serving.step_cells(r.workload.desc) >= thr][0]
+    real = serving._run_alone
+    calls = {"n": 0}
+
+    def run_alone(job):
+        if job.req.rid == big.rid and calls["n"] == 0:
+            calls["n"] += 1
+            raise DDError(-4, "injected")
+        return real(job)
+
+    monkeypatch.setattr(serving, "_run_alone", run_alone)
+    s, rec = serving.serve_batched(reqs, max_slots=4, chunk=16, solo_cells=thr)
+    print(f"[gpu] serving with an injected solo failure: {s}", flush=True)
+    assert calls["n"] == 1 and s["rejected"] == 0 and s["jobs"] == len(reqs)
+    assert s["in_use_end_bytes"] == 0 and s["retried"] == 1
 
 
 def test_served_job_matches_the_oracle_cga():
