@@ -1982,9 +1982,18 @@ int dd_batch_step(dd_batch* b, int32_t max_steps, void* stream) {
     }
     if (m) {
       const size_t off = (size_t)b->pos * b->width;
-      if (hipMemcpyAsync(b->dev + off, b->host + off, sizeof(BatchItem) * b->width * m, hipMemcpyHostToDevice,
-                         st) != hipSuccess ||
-          hipEventRecord(b->ev[g], st) != hipSuccess) {
+      // a launch of a single forward or adjoint step, or of one job's adjoint step with its
+      // recompute step, passes its arguments by value; only the others read the uploaded items
+      auto by_value = [&](int k) {
+        const BatchItem& one = b->host[off + (size_t)k * b->width];
+        const BatchItem& two = b->host[off + (size_t)k * b->width + 1];
+        return (bases[k].n == 1 && one.kind != 2) || (bases[k].n == 2 && one.kind == 1 && two.kind == 2 && !obl[k]);
+      };
+      bool upload = false;
+      for (int k = 0; k < m; ++k) upload = upload || (bases[k].n && !by_value(k));
+      if (upload && (hipMemcpyAsync(b->dev + off, b->host + off, sizeof(BatchItem) * b->width * m,
+                                    hipMemcpyHostToDevice, st) != hipSuccess ||
+                     hipEventRecord(b->ev[g], st) != hipSuccess)) {
         b->err = "batch upload failed";
         return DD_ERR_HIP;
       }
