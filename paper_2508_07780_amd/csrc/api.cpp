@@ -1785,7 +1785,11 @@ struct dd_batch {
   int next_id = 1;
   BatchItem* host = nullptr;    // pinned [ring][width]
   BatchItem* dev = nullptr;     // device [ring][width]
-  std::vector<hipEvent_t> ev;   // per ring segment: its upload has been consumed
+  // Items go up on a copy stream of their own, so that an upload runs while the kernels before
+  // it are still running instead of waiting its turn between them on the launch stream.
+  hipStream_t copy = nullptr;
+  std::vector<hipEvent_t> ev;       // per ring segment: its upload is done (host and launches wait)
+  std::vector<hipEvent_t> ev_used;  // per ring segment: the launches that read it are done
   // The ring holds the items of `ring` launches in segments of `seg` launches; the items of
   // the launches of one segment are uploaded with one copy.
   static constexpr int seg = 16;
@@ -1828,11 +1832,18 @@ int dd_batch_create(int32_t max_slots, size_t hbm_budget, dd_batch** out) {
     return DD_ERR_OOM;
   }
   b->ev.resize(b->ring / b->seg, nullptr);
-  for (auto& e : b->ev)
-    if (hipEventCreateWithFlags(&e, hipEventDisableTiming) != hipSuccess) {
-      dd_batch_destroy(b);
-      return DD_ERR_HIP;
-    }
+  b->ev_used.resize(b->ring / b->seg, nullptr);
+  for (auto* v : {&b->ev, &b->ev_used})
+    for (auto& e : *v)
+      if (hipEventCreateWithFlags(&e, hipEventDisableTiming) != hipSuccess) {
+        dd_batch_destroy(b);
+        return DD_ERR_HIP;
+      }
+  if (hipStreamCreateWithFlags(&b->copy, hipStreamNonBlocking) != hipSuccess) {
+    b->copy = nullptr;
+    dd_batch_destroy(b);
+    return DD_ERR_HIP;
+  }
   *out = b;
   return DD_OK;
 }
@@ -1840,8 +1851,10 @@ int dd_batch_create(int32_t max_slots, size_t hbm_budget, dd_batch** out) {
 int dd_batch_destroy(dd_batch* b) {
   if (!b) return DD_ERR_INVALID_ARG;
   (void)hipDeviceSynchronize();
-  for (auto e : b->ev)
-    if (e) (void)hipEventDestroy(e);
+  for (auto* v : {&b->ev, &b->ev_used})
+    for (auto e : *v)
+      if (e) (void)hipEventDestroy(e);
+  if (b->copy) (void)hipStreamDestroy(b->copy);
   if (b->dev) (void)hipFree(b->dev);
   if (b->host) (void)hipHostFree(b->host);
   delete b;
@@ -1991,9 +2004,13 @@ int dd_batch_step(dd_batch* b, int32_t max_steps, void* stream) {
       };
       bool upload = false;
       for (int k = 0; k < m; ++k) upload = upload || (bases[k].n && !by_value(k));
-      if (upload && (hipMemcpyAsync(b->dev + off, b->host + off, sizeof(BatchItem) * b->width * m,
-                                    hipMemcpyHostToDevice, st) != hipSuccess ||
-                     hipEventRecord(b->ev[g], st) != hipSuccess)) {
+      // the copy overwrites the device segment once the launches that read it last are done,
+      // and the launches below read it once the copy is done
+      if (upload && (hipStreamWaitEvent(b->copy, b->ev_used[g], 0) != hipSuccess ||
+                     hipMemcpyAsync(b->dev + off, b->host + off, sizeof(BatchItem) * b->width * m,
+                                    hipMemcpyHostToDevice, b->copy) != hipSuccess ||
+                     hipEventRecord(b->ev[g], b->copy) != hipSuccess ||
+                     hipStreamWaitEvent(st, b->ev[g], 0) != hipSuccess)) {
         b->err = "batch upload failed";
         return DD_ERR_HIP;
       }
@@ -2010,6 +2027,10 @@ int dd_batch_step(dd_batch* b, int32_t max_steps, void* stream) {
           launch_step_rec(one.fa, one.ea, two.ea, st, nt[k]);
         else
           launch_batch(b->dev + off + (size_t)k * b->width, bases[k], lds[k], st, nt[k], obl[k]);
+      }
+      if (upload && hipEventRecord(b->ev_used[g], st) != hipSuccess) {
+        b->err = "batch event record failed";
+        return DD_ERR_HIP;
       }
       hipError_t e = hipGetLastError();
       if (e != hipSuccess) {
