@@ -155,6 +155,68 @@ def batch_comparison():
             "sources": "even problems: Gaussian-sine plane waves of seeded incidence (0-30 degrees), odd: point dipoles"}
 
 
+def refined_mesh_measure(w, stride=16):
+    """The main workload's solve (forward with saving, adjoint, gradient) on a locally refined
+    FEM mesh of box "ACGA": the elements where the true eps is largest (beta_eps 0.6) refined
+    once by longest-edge bisection (the library's refinement), eps and sigma interpolated.  The
+    FEM rows then run on the element-coloured kernel (FD tiles and FEM partitions in launches of
+    their own).  dt is 0.7 of the uniform mesh's (the refined elements lower the step limit);
+    the per-step cost does not depend on it.  For comparison the uniform mesh through the same
+    element-coloured path."""
+    import numpy as np
+    import torch
+    from paper_2508_07780_amd import Problem, _lib
+    from paper_2508_07780_amd.acga import Refinement
+    from dataclasses import replace
+    dev = torch.device("cuda", 0)
+    desc = replace(w.desc, dt=0.7 * w.desc.dt)
+    ref = Refinement(desc, None, w.eps_true, w.sigma_true, 0.6, 0.0)
+    eps = torch.tensor(ref.interpolate(w.eps_true), device=dev)
+    sig = torch.tensor(ref.interpolate(w.sigma_true), device=dev)
+    out = {"workload": f"layered skin, outer {desc.n_outer[0]}^3, FEM {desc.fem_cells[0]}^3 hexes, "
+                       f"{desc.n_steps} steps; {ref.n_marked} elements marked, {ref.n_bisected} bisected, "
+                       f"{len(ref.mesh[1])} tetrahedra (uniform: {6 * int(np.prod(desc.fem_cells))})"}
+    prev = os.environ.get("DD_FEM_PATH")
+    os.environ["DD_FEM_PATH"] = "element"
+    try:
+        for name, mesh, e, sg in (("refined", ref.mesh, eps, sig),
+                                  ("uniform_element_path", None,
+                                   torch.tensor(w.eps_true, dtype=torch.float32, device=dev),
+                                   torch.tensor(w.sigma_true, dtype=torch.float32, device=dev))):
+            p = Problem(desc, mesh=mesh)
+            p.set_coefficients(e, sg)
+            tr = p.forward(w.sources, save=True)
+            cot = (1e-3 * tr).contiguous()
+            p.adjoint(cot)
+            p.gradient()
+            torch.cuda.synchronize()
+            p.profile(stride)
+            for k in range(len(_lib.PROF_NAMES)):
+                p.profile_read(k, reset=True)
+            t0 = time.perf_counter()
+            tr = p.forward(w.sources, save=True)
+            p.adjoint(cot)
+            ge, gs = p.gradient()
+            torch.cuda.synchronize()
+            wall = time.perf_counter() - t0
+            cells = (desc.n_grid() + desc.n_fem_owned()) * 2 * desc.n_steps * len(w.sources)
+            r = {"solve_ms": round(wall * 1e3, 2), "gcell_steps_s": round(cells / wall / 1e9, 3),
+                 "gradient_finite": bool(torch.isfinite(ge).all() and torch.isfinite(gs).all())}
+            for kind in ("fd_step_fwd", "fem_step_fwd", "fd_step_adj", "fem_step_adj"):
+                ms, n = p.profile_read(_lib.PROF_NAMES.index(kind), reset=True)
+                if n:
+                    r[kind + "_us"] = round(ms / n * 1e3, 2)
+            out[name] = r
+            p.close()
+    finally:
+        if prev is None:
+            os.environ.pop("DD_FEM_PATH", None)
+        else:
+            os.environ["DD_FEM_PATH"] = prev
+    ref.close()
+    return out
+
+
 def large_probe(n_steps=300, stride=16):
     """The fused step kernels on a 288^3 outer grid (96^3 FEM hexes, layered skin), whose
     per-step field set (860 MB) exceeds the 256 MB last-level cache, so that the achieved
@@ -400,6 +462,7 @@ def main():
     ap.add_argument("--cga", type=int, default=3, help="CGA iterations to time on the main workload (0 skips)")
     ap.add_argument("--paper-gradient", type=int, default=1,
                     help="0 skips the paper-formula gradient variant's measurement")
+    ap.add_argument("--refined", type=int, default=1, help="0 skips the solve on a locally refined mesh")
     ap.add_argument("--profile-stride", type=int, default=64,
                     help="time every k-th step launch with HIP events (k >= 16 barely perturbs the run)")
     args = ap.parse_args()
@@ -527,6 +590,9 @@ def main():
     if args.cga:
         out["cga"] = cga_measure(prob, w, eobs, args.cga)
     del prob
+    if args.refined:
+        out["refined_mesh"] = refined_mesh_measure(w)
+        progress("refined mesh")
     progress("main workload")
     if args.probe:
         out["hbm_probe"] = large_probe(args.probe_steps)

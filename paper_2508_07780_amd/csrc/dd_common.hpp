@@ -229,7 +229,7 @@ struct FemArgs {
 };
 
 void launch_fd(const FdArgs& a, hipStream_t s, bool energy, bool nt);
-size_t fem_lds_bytes(const FemArgs& a, bool adj);
+size_t fem_lds_bytes(const FemArgs& a, bool adj, bool stage);
 void launch_fem_fwd(const FemArgs& a, int n_part, hipStream_t s, bool energy);
 void launch_fem_adj(const FemArgs& a, int n_part, hipStream_t s);
 void launch_fem_stencil_fwd(const FemArgs& a, int n_part, hipStream_t s, bool energy);

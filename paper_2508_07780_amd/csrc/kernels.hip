@@ -351,19 +351,21 @@ __global__ __launch_bounds__(FD_THREADS) void fd_step_kernel(FdArgs a) {
 // Layer-0 values come from the interface buffer written by the finite-difference kernel;
 // layer-1 results are also written into the finite-difference grid (the two-node overlap).
 // ---------------------------------------------------------------------------------------
-template <bool ADJ, bool ENERGY, bool GEOM_LDS>
+template <bool ADJ, bool ENERGY, bool GEOM_LDS, bool STAGE>
 __global__ __launch_bounds__(FEM_THREADS) void fem_step_kernel(FemArgs a) {
   constexpr int NPT = FEM_OWN_MAX / FEM_THREADS;   // owned nodes per thread in the update
   constexpr int NA4 = ADJ ? 2 : 1;                 // float4 accumulators per owned node
   // Dynamic LDS sized from the mesh.  One float4 per node (E_x, E_y, E_z, eps - 1) and per
   // accumulator, so a node is gathered or scattered with a single 16-byte access; each
-  // accumulator row has 32 trash slots that absorb the contributions to halo nodes.
+  // accumulator row has 32 trash slots that absorb the contributions to halo nodes.  STAGE:
+  // the packed elements are staged in LDS too (8 B each); otherwise each colour reads them
+  // from global memory, and a block needs less LDS, so that more blocks share a CU.
   extern __shared__ __align__(16) unsigned char lds[];
   const int LOC = a.lds_loc, ROW = a.lds_own + 32;
   float4* sX = reinterpret_cast<float4*>(lds);                // [LOC]
   float4* sA = sX + LOC;                                      // [NA4][ROW]
-  uint64_t* sE = reinterpret_cast<uint64_t*>(sA + NA4 * ROW);  // [lds_elem] (even)
-  float* sG = reinterpret_cast<float*>(sE + a.lds_elem);       // [n_geom][GEOM_STRIDE]
+  uint64_t* sE = reinterpret_cast<uint64_t*>(sA + NA4 * ROW);  // [lds_elem] (even), if STAGE
+  float* sG = reinterpret_cast<float*>(sE + (STAGE ? a.lds_elem : 0));   // [n_geom][GEOM_STRIDE]
   int* sC = reinterpret_cast<int*>(sG + (GEOM_LDS ? a.n_geom * GEOM_STRIDE : 0));   // [ncl + 1]
   __shared__ double red[ENERGY ? FEM_THREADS : 1];
   const int p = blockIdx.x;
@@ -375,23 +377,26 @@ __global__ __launch_bounds__(FEM_THREADS) void fem_step_kernel(FemArgs a) {
   const int e_beg = a.col_off[cb], ne = a.col_off[cb + ncl] - e_beg;
   const int64_t n_own = a.n_own, n_l0 = a.n_l0;
 
-  // ---- stage: elements, colour offsets, geometry, node values.  Loads are issued in
-  // unrolled batches so that one batch costs one memory latency, not one per iteration.
+  // ---- stage: colour offsets, geometry, node values.  Loads are issued in unrolled
+  // batches so that one batch costs one memory latency, not one per iteration.
   if (tid <= ncl) sC[tid] = a.col_off[cb + tid] - e_beg;
-  constexpr int EB = 8;
-  for (int base = 0; base < ne; base += EB * FEM_THREADS) {
-    uint64_t tmp[EB];
+  if (STAGE) {
+    constexpr int EB = 8;
+    for (int base = 0; base < ne; base += EB * FEM_THREADS) {
+      uint64_t tmp[EB];
 #pragma unroll
-    for (int k = 0; k < EB; ++k) {
-      const int i = base + k * FEM_THREADS + tid;
-      tmp[k] = i < ne ? a.elems[e_beg + i] : 0ull;
-    }
+      for (int k = 0; k < EB; ++k) {
+        const int i = base + k * FEM_THREADS + tid;
+        tmp[k] = i < ne ? a.elems[e_beg + i] : 0ull;
+      }
 #pragma unroll
-    for (int k = 0; k < EB; ++k) {
-      const int i = base + k * FEM_THREADS + tid;
-      if (i < ne) sE[i] = tmp[k];
+      for (int k = 0; k < EB; ++k) {
+        const int i = base + k * FEM_THREADS + tid;
+        if (i < ne) sE[i] = tmp[k];
+      }
     }
   }
+  const uint64_t* __restrict__ gE = STAGE ? sE : a.elems + e_beg;
   if (GEOM_LDS)
     for (int i = tid; i < a.n_geom * GEOM_STRIDE; i += FEM_THREADS) sG[i] = a.geom[i];
   constexpr int NB = 4;
@@ -461,7 +466,7 @@ __global__ __launch_bounds__(FEM_THREADS) void fem_step_kernel(FemArgs a) {
   for (int c = 0; c < ncl; ++c) {
     const int e0 = sC[c], e1 = sC[c + 1];
     for (int e = e0 + tid; e < e1; e += FEM_THREADS) {
-      const uint64_t w = sE[e];
+      const uint64_t w = gE[e];
       int v[4], t[4];
 #pragma unroll
       for (int k = 0; k < 4; ++k) {
@@ -1492,27 +1497,48 @@ void launch_fd(const FdArgs& a, hipStream_t s, bool energy, bool nt) {
     launch_fd_t<false>(a, s, energy);
 }
 
-size_t fem_lds_bytes(const FemArgs& a, bool adj) {
+size_t fem_lds_bytes(const FemArgs& a, bool adj, bool stage) {
   const bool geom_lds = a.n_geom <= FEM_GEOM_LDS;
   size_t f = (size_t)a.lds_loc * 4 + (size_t)(adj ? 8 : 4) * (a.lds_own + 32);
-  f += (size_t)a.lds_elem * 2 + (geom_lds ? (size_t)a.n_geom * GEOM_STRIDE : 0);
+  f += (stage ? (size_t)a.lds_elem * 2 : 0) + (geom_lds ? (size_t)a.n_geom * GEOM_STRIDE : 0);
   f += FEM_COLORS_MAX + 1;   // colour offsets
   return f * 4;
 }
 
+namespace {
+int device_cus() {
+  static int cus = 0;
+  if (!cus) {
+    int dev = 0;
+    if (hipGetDevice(&dev) != hipSuccess || hipDeviceGetAttribute(&cus, hipDeviceAttributeMultiprocessorCount, dev) !=
+                                                 hipSuccess || cus <= 0)
+      cus = 256;
+  }
+  return cus;
+}
+
+template <bool ADJ, bool ENERGY, bool GEOM, bool STAGE>
+void launch_fem_v(const FemArgs& a, int n_part, size_t lds, hipStream_t s) {
+  if (lds > 65536)
+    (void)hipFuncSetAttribute((const void*)fem_step_kernel<ADJ, ENERGY, GEOM, STAGE>,
+                              hipFuncAttributeMaxDynamicSharedMemorySize, (int)lds);
+  hipLaunchKernelGGL((fem_step_kernel<ADJ, ENERGY, GEOM, STAGE>), dim3(n_part), dim3(FEM_THREADS), lds, s, a);
+}
+}  // namespace
+
+// The elements are staged in LDS when the partitions then still run in one round of blocks
+// (160 KB of LDS per CU); otherwise they are read from global memory and more blocks share a CU.
 template <bool ADJ, bool ENERGY>
 static void launch_fem_t(const FemArgs& a, int n_part, hipStream_t s) {
-  const size_t lds = fem_lds_bytes(a, ADJ);
-  if (lds > 65536) {
-    (void)hipFuncSetAttribute((const void*)fem_step_kernel<ADJ, ENERGY, true>,
-                              hipFuncAttributeMaxDynamicSharedMemorySize, (int)lds);
-    (void)hipFuncSetAttribute((const void*)fem_step_kernel<ADJ, ENERGY, false>,
-                              hipFuncAttributeMaxDynamicSharedMemorySize, (int)lds);
-  }
-  if (a.n_geom <= FEM_GEOM_LDS)
-    hipLaunchKernelGGL((fem_step_kernel<ADJ, ENERGY, true>), dim3(n_part), dim3(FEM_THREADS), lds, s, a);
-  else
-    hipLaunchKernelGGL((fem_step_kernel<ADJ, ENERGY, false>), dim3(n_part), dim3(FEM_THREADS), lds, s, a);
+  constexpr size_t LDS_CU = 160 * 1024;
+  const size_t staged = fem_lds_bytes(a, ADJ, true);
+  const bool stage = (int64_t)n_part <= (int64_t)(LDS_CU / staged) * device_cus();
+  const size_t lds = stage ? staged : fem_lds_bytes(a, ADJ, false);
+  const bool geom = a.n_geom <= FEM_GEOM_LDS;
+  if (geom && stage) launch_fem_v<ADJ, ENERGY, true, true>(a, n_part, lds, s);
+  else if (geom) launch_fem_v<ADJ, ENERGY, true, false>(a, n_part, lds, s);
+  else if (stage) launch_fem_v<ADJ, ENERGY, false, true>(a, n_part, lds, s);
+  else launch_fem_v<ADJ, ENERGY, false, false>(a, n_part, lds, s);
 }
 
 void launch_fem_fwd(const FemArgs& a, int n_part, hipStream_t s, bool energy) {
