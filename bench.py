@@ -159,8 +159,9 @@ def refined_mesh_measure(w, stride=16):
     """The main workload's solve (forward with saving, adjoint, gradient) on a locally refined
     FEM mesh of box "ACGA": the elements where the true eps is largest (beta_eps 0.6) refined
     once by longest-edge bisection (the library's refinement), eps and sigma interpolated.  The
-    FEM rows then run on the element-coloured kernel (FD tiles and FEM partitions in launches of
-    their own).  dt is 0.7 of the uniform mesh's (the refined elements lower the step limit);
+    FEM rows then run on the element-coloured kernel, fused with the FD tiles in one launch per
+    step (forward and adjoint).  dt is 0.7 of the uniform mesh's (the refined elements lower the
+    step limit);
     the per-step cost does not depend on it.  For comparison the uniform mesh through the same
     element-coloured path."""
     import numpy as np
@@ -202,7 +203,7 @@ def refined_mesh_measure(w, stride=16):
             cells = (desc.n_grid() + desc.n_fem_owned()) * 2 * desc.n_steps * len(w.sources)
             r = {"solve_ms": round(wall * 1e3, 2), "gcell_steps_s": round(cells / wall / 1e9, 3),
                  "gradient_finite": bool(torch.isfinite(ge).all() and torch.isfinite(gs).all())}
-            for kind in ("fd_step_fwd", "fem_step_fwd", "fd_step_adj", "fem_step_adj"):
+            for kind in ("step_fwd", "step_adj", "fd_step_fwd", "fem_step_fwd", "fd_step_adj", "fem_step_adj"):
                 ms, n = p.profile_read(_lib.PROF_NAMES.index(kind), reset=True)
                 if n:
                     r[kind + "_us"] = round(ms / n * 1e3, 2)

@@ -596,6 +596,8 @@ int run_forward(dd_problem* p, const dd_source& src, int s, float* traces, bool 
   fa.epart = energy ? p->epart : nullptr;
   ea.epart = energy ? p->epart : nullptr;
   const bool fused = p->use_stencil && p->fused;
+  // the element-coloured FEM path (general meshes) fuses its forward step too
+  const bool el_fused = !p->use_stencil && p->fused && !p->overlap;
   const bool tb = tb_forward(p, energy != nullptr);
   for (int64_t n = 0; n < nt; ++n) {
     fwd_step_args(p, src, sp, s, n, traces, save, fa, ea);
@@ -625,6 +627,10 @@ int run_forward(dd_problem* p, const dd_source& src, int s, float* traces, bool 
     } else if (fused) {
       ps = prof_begin(p, DD_PROF_STEP_FWD, st);
       launch_step(fa, ea, st, false, energy != nullptr, p->fd_nt);
+      prof_end(p, DD_PROF_STEP_FWD, ps, st);
+    } else if (el_fused) {
+      ps = prof_begin(p, DD_PROF_STEP_FWD, st);
+      launch_step_el(fa, ea, st, false, energy != nullptr, p->fd_nt);
       prof_end(p, DD_PROF_STEP_FWD, ps, st);
     } else {
       ps = prof_begin(p, DD_PROF_FD_FWD, st);
@@ -724,6 +730,11 @@ int run_adjoint(dd_problem* p, int s, const float* cot, const float* obs, hipStr
         }
         ps = prof_begin(p, DD_PROF_STEP_ADJ, st);
         launch_step(fa, ea, st, true, false, p->fd_nt, pg_fused ? &pga : nullptr);
+        prof_end(p, DD_PROF_STEP_ADJ, ps, st);
+      } else if (!p->use_stencil && p->fused && !p->overlap && !p->r2 && !p->pg_on) {
+        // a general mesh: element-coloured FEM partitions and FD tiles in one launch
+        ps = prof_begin(p, DD_PROF_STEP_ADJ, st);
+        launch_step_el(fa, ea, st, true, false, p->fd_nt);
         prof_end(p, DD_PROF_STEP_ADJ, ps, st);
       } else {
         ps = prof_begin(p, DD_PROF_FD_ADJ, st);

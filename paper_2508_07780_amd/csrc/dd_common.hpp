@@ -230,6 +230,8 @@ struct FemArgs {
 
 void launch_fd(const FdArgs& a, hipStream_t s, bool energy, bool nt);
 size_t fem_lds_bytes(const FemArgs& a, bool adj, bool stage);
+// One fused step on a general mesh: element-coloured FEM partitions and the FD tiles.
+void launch_step_el(const FdArgs& fa, const FemArgs& ea, hipStream_t s, bool adj, bool energy, bool nt);
 void launch_fem_fwd(const FemArgs& a, int n_part, hipStream_t s, bool energy);
 void launch_fem_adj(const FemArgs& a, int n_part, hipStream_t s);
 void launch_fem_stencil_fwd(const FemArgs& a, int n_part, hipStream_t s, bool energy);

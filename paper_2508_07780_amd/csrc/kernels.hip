@@ -351,8 +351,9 @@ __global__ __launch_bounds__(FD_THREADS) void fd_step_kernel(FdArgs a) {
 // Layer-0 values come from the interface buffer written by the finite-difference kernel;
 // layer-1 results are also written into the finite-difference grid (the two-node overlap).
 // ---------------------------------------------------------------------------------------
+// One FEM partition p of the element-coloured step, by a block of FEM_THREADS threads.
 template <bool ADJ, bool ENERGY, bool GEOM_LDS, bool STAGE>
-__global__ __launch_bounds__(FEM_THREADS) void fem_step_kernel(FemArgs a) {
+__device__ __forceinline__ void fem_el_part(const FemArgs& a, const int p) {
   constexpr int NPT = FEM_OWN_MAX / FEM_THREADS;   // owned nodes per thread in the update
   constexpr int NA4 = ADJ ? 2 : 1;                 // float4 accumulators per owned node
   // Dynamic LDS sized from the mesh.  One float4 per node (E_x, E_y, E_z, eps - 1) and per
@@ -368,7 +369,6 @@ __global__ __launch_bounds__(FEM_THREADS) void fem_step_kernel(FemArgs a) {
   float* sG = reinterpret_cast<float*>(sE + (STAGE ? a.lds_elem : 0));   // [n_geom][GEOM_STRIDE]
   int* sC = reinterpret_cast<int*>(sG + (GEOM_LDS ? a.n_geom * GEOM_STRIDE : 0));   // [ncl + 1]
   __shared__ double red[ENERGY ? FEM_THREADS : 1];
-  const int p = blockIdx.x;
   const int tid = threadIdx.x;
   const int o0 = a.own_off[p], no = a.own_off[p + 1] - o0;
   const int h0 = a.halo_off[p], nh = a.halo_off[p + 1] - h0;
@@ -611,6 +611,11 @@ __global__ __launch_bounds__(FEM_THREADS) void fem_step_kernel(FemArgs a) {
     }
     if (tid == 0) a.epart[a.epart_off + p] = red[0];
   }
+}
+
+template <bool ADJ, bool ENERGY, bool GEOM_LDS, bool STAGE>
+__global__ __launch_bounds__(FEM_THREADS) void fem_step_kernel(FemArgs a) {
+  fem_el_part<ADJ, ENERGY, GEOM_LDS, STAGE>(a, blockIdx.x);
 }
 
 // ---------------------------------------------------------------------------------------
@@ -866,6 +871,21 @@ __global__ __launch_bounds__(FD_THREADS) void step_kernel(FdArgs fa, FemArgs ea,
   if (b < fem_blocks) {
     const int p = fem_part_of_block(b, fem_blocks, ea.rev);
     if (p < ea.n_part) fem_stencil_part<ADJ, ENERGY>(ea, p);
+    return;
+  }
+  fd_tile<ENERGY, NT, OBL>(fa, b - fem_blocks);
+}
+
+// The same fused step on a general mesh: the FEM partitions run the element-coloured code
+// (elements read from global memory, so that a block's LDS stays small enough for the
+// finite-difference tiles of the same launch to share the CUs).
+template <bool ADJ, bool ENERGY, bool NT, bool OBL, bool GEOM_LDS>
+__global__ __launch_bounds__(FD_THREADS) void step_kernel_el(FdArgs fa, FemArgs ea, int fem_blocks) {
+  static_assert(FD_THREADS == FEM_THREADS, "one block size for both parts");
+  const int b = blockIdx.x;
+  if (b < fem_blocks) {
+    const int p = fem_part_of_block(b, fem_blocks, ea.rev);
+    if (p < ea.n_part) fem_el_part<ADJ, ENERGY, GEOM_LDS, false>(ea, p);
     return;
   }
   fd_tile<ENERGY, NT, OBL>(fa, b - fem_blocks);
@@ -1654,6 +1674,36 @@ void launch_step(const FdArgs& fa, const FemArgs& ea, hipStream_t s, bool adj, b
     launch_step_t<true>(fa, ea, s, adj, energy, pg);
   else
     launch_step_t<false>(fa, ea, s, adj, energy, pg);
+}
+
+template <bool NT, bool GEOM>
+static void launch_step_el_t(const FdArgs& fa, const FemArgs& ea, hipStream_t s, bool adj, bool energy) {
+  const int fem_blocks = (ea.n_part + N_XCD - 1) / N_XCD * N_XCD;   // keeps FD blocks XCD-aligned
+  const dim3 grid(fem_blocks + fa.per_xcd * N_XCD);
+  const size_t lds = fem_lds_bytes(ea, adj, false);
+  if (adj)
+    hipLaunchKernelGGL((step_kernel_el<true, false, NT, false, GEOM>), grid, dim3(FD_THREADS), lds, s, fa, ea,
+                       fem_blocks);
+  else if (fa.pw_kind && energy)
+    hipLaunchKernelGGL((step_kernel_el<false, true, NT, true, GEOM>), grid, dim3(FD_THREADS), lds, s, fa, ea,
+                       fem_blocks);
+  else if (fa.pw_kind)
+    hipLaunchKernelGGL((step_kernel_el<false, false, NT, true, GEOM>), grid, dim3(FD_THREADS), lds, s, fa, ea,
+                       fem_blocks);
+  else if (energy)
+    hipLaunchKernelGGL((step_kernel_el<false, true, NT, false, GEOM>), grid, dim3(FD_THREADS), lds, s, fa, ea,
+                       fem_blocks);
+  else
+    hipLaunchKernelGGL((step_kernel_el<false, false, NT, false, GEOM>), grid, dim3(FD_THREADS), lds, s, fa, ea,
+                       fem_blocks);
+}
+
+void launch_step_el(const FdArgs& fa, const FemArgs& ea, hipStream_t s, bool adj, bool energy, bool nt) {
+  const bool geom = ea.n_geom <= FEM_GEOM_LDS;
+  if (nt && geom) launch_step_el_t<true, true>(fa, ea, s, adj, energy);
+  else if (nt) launch_step_el_t<true, false>(fa, ea, s, adj, energy);
+  else if (geom) launch_step_el_t<false, true>(fa, ea, s, adj, energy);
+  else launch_step_el_t<false, false>(fa, ea, s, adj, energy);
 }
 
 void launch_energy_reduce(const double* part, int n, double* out, hipStream_t s) {
