@@ -185,13 +185,14 @@ def loss_and_cotangent(traces, eobs, z=None):
     return 0.5 * float(np.sum(w * r * r)), w * r
 
 
-def adjoint_gradient(d, cot, fwd, keep_lambda=False):
+def adjoint_gradient(d, cot, fwd, keep_lambda=False, sbp=True):
     """Adjoint recursion backward in time and the eps / sigma gradient.
 
     ``cot`` is dJ/dT with the shape of the traces; ``fwd`` the forward result
     (its FEM history).  Returns dict(g_eps, g_sigma) over the FEM lattice, the
-    mass term in both the plain and the summed-by-parts form, and optionally
-    lambda^n (n = 0..N_t-1) on the whole grid.
+    mass term in both the plain and the summed-by-parts form (the latter, and the
+    sigma term summed by parts, only with ``sbp``: they keep lambda^n on the FEM nodes
+    for every n), and optionally lambda^n (n = 0..N_t-1) on the whole grid.
     """
     nt = cot.shape[0]
     dt = d.dt
@@ -204,7 +205,7 @@ def adjoint_gradient(d, cot, fwd, keep_lambda=False):
     g_dd = np.zeros(d.n_fem)
     g_dd_paper = np.zeros(d.n_fem)
     g_sig = np.zeros(d.n_fem)
-    lam_f = np.zeros((nt + 1, d.n_fem, 3))   # lambda^n on FEM nodes, n = 0..N_t
+    lam_f = np.zeros((nt + 1, d.n_fem, 3)) if sbp else None   # lambda^n on FEM nodes, n = 0..N_t
     lams = np.zeros((nt, d.N, 3)) if keep_lambda else None
     for k in range(nt, 0, -1):
         r = np.zeros((d.N, 3))
@@ -215,7 +216,8 @@ def adjoint_gradient(d, cot, fwd, keep_lambda=False):
         lam_prev = rhs / (Me / dt ** 2 + Cm / (2 * dt))
         n = k - 1
         lf = lam_prev[d.fem_grid]
-        lam_f[n] = lf
+        if sbp:
+            lam_f[n] = lf
         e_p, e_c, e_m = Eh[n + 2], Eh[n + 1], Eh[n]
         g_mass += m * np.sum(lf * (e_p - 2.0 * e_c + e_m), axis=1) / dt ** 2
         g_sig += m * np.sum(lf * (e_p - e_m), axis=1) / (2.0 * dt)
@@ -235,15 +237,17 @@ def adjoint_gradient(d, cot, fwd, keep_lambda=False):
     # summation by parts of the mass term: -sum_n m (lambda^{n+1} - lambda^n) . (E^{n+1} - E^n) / dt^2
     # plus the boundary term -m lambda^0 . V^0 / dt^2 of the starting levels (zero from rest)
     g_mass_sbp = np.zeros(d.n_fem)
-    for n in range(nt):
+    g_sig_sbp = np.zeros(d.n_fem)
+    for n in range(nt if sbp else 0):
         g_mass_sbp -= m * np.sum((lam_f[n + 1] - lam_f[n]) * (Eh[n + 2] - Eh[n + 1]), axis=1) / dt ** 2
-    g_mass_sbp -= m * np.sum(lam_f[0] * (Eh[1] - Eh[0]), axis=1) / dt ** 2
+    if sbp:
+        g_mass_sbp -= m * np.sum(lam_f[0] * (Eh[1] - Eh[0]), axis=1) / dt ** 2
     # the sigma term summed by parts: sum_n m (lambda^n + lambda^{n+1}) . (E^{n+1} - E^n) / (2 dt)
     # plus the boundary row m lambda^0 . V^0 / (2 dt) of the starting levels (zero from rest)
-    g_sig_sbp = np.zeros(d.n_fem)
-    for n in range(nt):
+    for n in range(nt if sbp else 0):
         g_sig_sbp += m * np.sum((lam_f[n] + lam_f[n + 1]) * (Eh[n + 2] - Eh[n + 1]), axis=1) / (2.0 * dt)
-    g_sig_sbp += m * np.sum(lam_f[0] * (Eh[1] - Eh[0]), axis=1) / (2.0 * dt)
+    if sbp:
+        g_sig_sbp += m * np.sum(lam_f[0] * (Eh[1] - Eh[0]), axis=1) / (2.0 * dt)
     free = d.fem_free
     g_eps_paper = np.where(free, g_mass + g_dd_paper, 0.0)
     if getattr(d, "divdiv_form", "R1") == "R2":

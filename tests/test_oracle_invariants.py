@@ -233,3 +233,20 @@ def test_mirror_symmetry():
     sig2 = np.where(d0.fem_free, synth.noise(d0.n_fem, 14) ** 2, 0.0)
     tr2 = forward(Discretization(desc).set_coefficients(np.ones(d0.n_fem), sig2), w.sources[0])["traces"]
     assert np.abs(tr2[:, perm, :] - tr2).max() > 1e-6 * np.abs(tr2).max()
+
+
+def test_adjoint_without_the_lambda_history_gives_the_same_gradient():
+    """sbp=False only skips the summed-by-parts diagnostics (and the lambda history they need):
+    the gradient is the same, bit for bit."""
+    import numpy as np
+    import synth
+    from oracle.discretization import Discretization
+    from oracle.solver import adjoint_gradient, forward
+    w = synth.small("tiny")
+    d = Discretization(w.desc).set_coefficients(w.eps, w.sigma)
+    fw = forward(d, w.sources[0], n_steps=30)
+    cot = np.random.default_rng(4).standard_normal(fw["traces"].shape)
+    a = adjoint_gradient(d, cot, fw)
+    b = adjoint_gradient(d, cot, fw, sbp=False)
+    for k in ("g_eps", "g_sigma", "g_eps_paper", "g_mass", "g_divdiv"):
+        assert np.array_equal(a[k], b[k]), k
