@@ -22,6 +22,7 @@
 #include <climits>
 #include <map>
 #include <set>
+#include <unordered_map>
 #include <vector>
 
 #include "dd_common.hpp"
@@ -906,7 +907,10 @@ struct Refiner {
   std::vector<int> layer;                      // lattice layer; midpoints and extra nodes: free
   std::vector<std::array<int64_t, 4>> verts;   // element id -> vertices (leaves: the current mesh)
   std::vector<std::array<int64_t, 2>> kids;    // {-1, -1} for a leaf
-  std::map<Edge, std::set<int64_t>> around;    // edge -> current elements that contain it
+  // edge (low << 32 | high) -> current elements that contain it, in increasing id (elements
+  // are added in id order and children take new, larger ids, so appending keeps the order)
+  std::unordered_map<uint64_t, std::vector<int64_t>> around;
+  static uint64_t key(const Edge& e) { return ((uint64_t)e.first << 32) | (uint64_t)e.second; }
   std::vector<Edge> split;
 
   double len2(const Edge& e) const {
@@ -937,10 +941,10 @@ struct Refiner {
   void add(int64_t t) {
     const auto& v = verts[t];
     for (int a = 0; a < 4; ++a)
-      for (int b = a + 1; b < 4; ++b) around[edge_of(v[a], v[b])].insert(t);
+      for (int b = a + 1; b < 4; ++b) around[key(edge_of(v[a], v[b]))].push_back(t);
   }
   bool eligible(const Edge& e) const {
-    auto it = around.find(e);
+    auto it = around.find(key(e));
     if (it == around.end()) return false;
     for (int64_t t : it->second)
       for (int64_t v : verts[t])
@@ -954,13 +958,16 @@ struct Refiner {
     P.push_back(q);
     layer.push_back(1 << 30);
     split.push_back(e);
-    auto node = around.extract(e);
+    auto node = around.extract(key(e));
     for (int64_t t : node.mapped()) {   // increasing id
       const auto v = verts[t];
       for (int a = 0; a < 4; ++a)
         for (int b = a + 1; b < 4; ++b) {
           const Edge f = edge_of(v[a], v[b]);
-          if (f != e) around[f].erase(t);
+          if (f != e) {
+            auto& l = around[key(f)];
+            l.erase(std::find(l.begin(), l.end(), t));
+          }
         }
       std::array<int64_t, 4> h0 = v, h1 = v;
       for (int a = 0; a < 4; ++a) {
@@ -982,7 +989,7 @@ struct Refiner {
       const Edge e = longest(t);
       if (!eligible(e)) return false;
       std::vector<int64_t> others;
-      for (int64_t u : around[e])
+      for (int64_t u : around[key(e)])
         if (longest(u) != e) others.push_back(u);   // std::set: increasing id
       if (others.empty()) {
         bisect(e);
@@ -1085,6 +1092,7 @@ extern "C" int dd_meshref_create(const dd_problem_desc* d, int64_t n_extra, cons
         break;
       }
   // step 3: bisection
+  R.around.reserve((size_t)(2 * nt));
   for (int64_t t = 0; t < nt; ++t) R.add(t);
   for (int64_t t = 0; t < nt; ++t)
     if (r->marks[t] && R.kids[t][0] < 0) R.refine_element(t);
