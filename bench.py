@@ -218,6 +218,48 @@ def refined_mesh_measure(w, stride=16):
     return out
 
 
+def acga_measure(w, n_iter=2, n_refine=2, beta_eps=0.9):
+    """Box "ACGA" on the main workload from eps = 1, sigma = 0: n_iter CGA iterations per mesh,
+    n_refine refinements (longest-edge bisection where h_K |eps| >= beta_eps of its largest
+    value, in the library's host code) with the interpolated reconstruction as the next start;
+    dt 0.7 of the uniform mesh's (the refined meshes' step limit is lower).  The step sizes come
+    from the gradient at the initial guess (setup, not timed)."""
+    import numpy as np
+    import torch
+    from dataclasses import replace
+    from paper_2508_07780_amd import CGAParams, Problem
+    from paper_2508_07780_amd.acga import acga
+    dev = torch.device("cuda", 0)
+    desc = replace(w.desc, dt=0.7 * w.desc.dt)
+    p = Problem(desc)
+    p.set_coefficients(torch.tensor(w.eps_true, dtype=torch.float32, device=dev),
+                       torch.tensor(w.sigma_true, dtype=torch.float32, device=dev))
+    obs = p.forward(w.sources, save=False).clone()
+    n = p.n_fem
+    eps0 = torch.ones(n, dtype=torch.float32, device=dev)
+    sig0 = torch.zeros(n, dtype=torch.float32, device=dev)
+    p.set_coefficients(eps0, sig0)
+    p.adjoint_misfit(p.forward(w.sources, save=True), obs)
+    ge, gs = p.gradient()
+    prm = CGAParams.from_gradient(ge, gs, desc.h, eps_max=20.0, sig_max=3.0)
+    p.close()
+    torch.cuda.synchronize()
+    t0 = time.perf_counter()
+    out = acga(desc, w.sources, obs, eps0, sig0, prm, n_iter, beta_eps, 0.0, n_refine=n_refine)
+    torch.cuda.synchronize()
+    wall = time.perf_counter() - t0
+    lv = out["levels"]
+    return {"workload": f"layered skin, outer {desc.n_outer[0]}^3, FEM {desc.fem_cells[0]}^3 hexes, "
+                        f"{desc.n_steps} steps; {n_iter} CGA iterations per mesh, {n_refine} refinements "
+                        f"(beta_eps {beta_eps})",
+            "wall_s": round(wall, 2), "meshes": len(lv),
+            "bisections": [l.get("n_bisected") for l in lv[:-1]],
+            "final_extra_nodes": len(out["mesh"][0]) if out["mesh"] is not None else 0,
+            "final_tets": len(out["mesh"][1]) if out["mesh"] is not None else 6 * int(np.prod(desc.fem_cells)),
+            "grad_norm_eps": [[round(h["grad_norm"]["eps"], 1) for h in l["history"]] for l in lv],
+            "finite": bool(torch.isfinite(out["eps"]).all() and torch.isfinite(out["sigma"]).all())}
+
+
 def large_probe(n_steps=300, stride=16):
     """The fused step kernels on a 288^3 outer grid (96^3 FEM hexes, layered skin), whose
     per-step field set (860 MB) exceeds the 256 MB last-level cache, so that the achieved
@@ -464,6 +506,7 @@ def main():
     ap.add_argument("--paper-gradient", type=int, default=1,
                     help="0 skips the paper-formula gradient variant's measurement")
     ap.add_argument("--refined", type=int, default=1, help="0 skips the solve on a locally refined mesh")
+    ap.add_argument("--acga", type=int, default=1, help="0 skips the adaptive reconstruction (box ACGA)")
     ap.add_argument("--profile-stride", type=int, default=64,
                     help="time every k-th step launch with HIP events (k >= 16 barely perturbs the run)")
     args = ap.parse_args()
@@ -594,6 +637,9 @@ def main():
     if args.refined:
         out["refined_mesh"] = refined_mesh_measure(w)
         progress("refined mesh")
+    if args.acga:
+        out["acga"] = acga_measure(w)
+        progress("adaptive reconstruction")
     progress("main workload")
     if args.probe:
         out["hbm_probe"] = large_probe(args.probe_steps)
