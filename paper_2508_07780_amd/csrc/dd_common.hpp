@@ -39,6 +39,8 @@ __host__ __device__ constexpr int fd_zc(bool nt) { return nt ? FD_ZC_STREAM : FD
 constexpr int FD_ZGROUP = DD_FD_ZGROUP;
 __host__ __device__ constexpr int fd_zgroup(bool nt) { return nt ? FD_ZGROUP : 1; }
 constexpr int FD_THREADS = FD_TX * FD_TY;
+// the FD tile's two LDS planes of three components (when they sit in the dynamic LDS)
+constexpr size_t FD_DYN_LDS_BYTES = sizeof(float) * 2 * 3 * (FD_TY + 2) * (FD_TX + 2);
 // Last-level cache (MI355X Infinity Cache).  A grid whose two levels of E exceed it streams
 // each node's own previous and new level with non-temporal accesses.
 constexpr double LLC_BYTES = 256.0 * 1024 * 1024;

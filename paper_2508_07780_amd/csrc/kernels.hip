@@ -77,14 +77,19 @@ __device__ __forceinline__ float oblique_pulse(const FdArgs& a, int x, int y) {
 // and no other contraction, so every path rounds alike: S = wz sz + (wy sy + wx sx) (mirror
 // weights 1 inside), E^{n+1} = E^n + [(E^n - E^{n-1}) - nu^2 S + F] (damped faces: the divided
 // form).  With unit weights and no forcing it is the interior update of the two-step tiles.
-template <bool ENERGY, bool NT, bool OBL = false>
+// DYN: the two planes live at the start of the launch's dynamic LDS instead of a static array
+// (a launch whose other blocks need more dynamic LDS then holds one buffer, not both).
+template <bool ENERGY, bool NT, bool OBL = false, bool DYN = false>
 __device__ __forceinline__ void fd_tile(const FdArgs& a, const int b) {
 #pragma clang fp contract(off)
   constexpr int ZC = fd_zc(NT);
   // two LDS planes: plane z is written while plane z-1 may still be read by slower waves,
   // so one barrier per plane suffices
   constexpr int SW = FD_TX + 2, SC = (FD_TY + 2) * SW;   // row and component strides
-  __shared__ float s[2][3 * SC];
+  __shared__ float s_static[DYN ? 1 : 2][DYN ? 1 : 3 * SC];
+  extern __shared__ __align__(16) unsigned char fd_dyn[];
+  float (*s)[3 * SC] = DYN ? reinterpret_cast<float (*)[3 * SC]>(fd_dyn)
+                           : reinterpret_cast<float (*)[3 * SC]>(&s_static[0][0]);
   __shared__ double red[ENERGY ? FD_THREADS : 1];
   // consecutive tiles share an XCD's L2; on alternate steps each XCD sweeps its tiles in
   // reverse, starting where the previous step ended, whose fields are still in the caches
@@ -888,7 +893,7 @@ __global__ __launch_bounds__(FD_THREADS) void step_kernel_el(FdArgs fa, FemArgs 
     if (p < ea.n_part) fem_el_part<ADJ, ENERGY, GEOM_LDS, false>(ea, p);
     return;
   }
-  fd_tile<ENERGY, NT, OBL>(fa, b - fem_blocks);
+  fd_tile<ENERGY, NT, OBL, true>(fa, b - fem_blocks);
 }
 
 // ---------------------------------------------------------------------------------------
@@ -1680,7 +1685,7 @@ template <bool NT, bool GEOM>
 static void launch_step_el_t(const FdArgs& fa, const FemArgs& ea, hipStream_t s, bool adj, bool energy) {
   const int fem_blocks = (ea.n_part + N_XCD - 1) / N_XCD * N_XCD;   // keeps FD blocks XCD-aligned
   const dim3 grid(fem_blocks + fa.per_xcd * N_XCD);
-  const size_t lds = fem_lds_bytes(ea, adj, false);
+  const size_t lds = std::max(fem_lds_bytes(ea, adj, false), FD_DYN_LDS_BYTES);
   if (adj)
     hipLaunchKernelGGL((step_kernel_el<true, false, NT, false, GEOM>), grid, dim3(FD_THREADS), lds, s, fa, ea,
                        fem_blocks);
