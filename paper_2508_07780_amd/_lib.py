@@ -18,7 +18,7 @@ EXPORTS = [
     "dd_profile_enable", "dd_profile_read", "dd_algorithmic_bytes", "dd_debug_fem_apply",
     "dd_batch_create", "dd_batch_destroy", "dd_batch_submit", "dd_batch_step", "dd_batch_poll",
     "dd_adjoint_misfit", "dd_cga_create", "dd_cga_destroy", "dd_cga_update", "dd_cga_get_info",
-    "dd_paper_gradient_enable", "dd_gradient_paper", "dd_misfit", "dd_set_divdiv_form", "dd_set_initial_data", "dd_check_finite", "dd_batch_set_fill",
+    "dd_paper_gradient_enable", "dd_gradient_paper", "dd_misfit", "dd_set_divdiv_form", "dd_set_graph", "dd_graph_stats", "dd_set_initial_data", "dd_check_finite", "dd_batch_set_fill",
     "dd_misfit_noalloc", "dd_misfit_taper", "dd_set_coefficients_async", "dd_coefficients_status",
     "dd_cga_steps_from_gradient", "dd_create_mesh", "dd_debug_fem_apply_mesh", "dd_meshref_create",
     "dd_meshref_sizes", "dd_meshref_result", "dd_meshref_interpolate", "dd_meshref_destroy",
@@ -157,6 +157,8 @@ def load():
     lib.dd_misfit_noalloc.argtypes = [P, P, P, ctypes.c_int32, P, P, P, P]
     lib.dd_misfit_taper.argtypes = [ctypes.c_int32, ctypes.c_double, ctypes.c_double, P]
     lib.dd_set_divdiv_form.argtypes = [P, ctypes.c_int32]
+    lib.dd_set_graph.argtypes = [P, ctypes.c_int32]
+    lib.dd_graph_stats.argtypes = [P, ctypes.c_void_p, ctypes.c_void_p]
     lib.dd_gradient_paper.argtypes = [P, P, P, P]
     lib.dd_set_initial_data.argtypes = [P, P, P, P]
     lib.dd_check_finite.argtypes = [P, P]

@@ -239,6 +239,18 @@ class Problem:
         self.generation += 1
         _lib.check(_lib.load().dd_set_divdiv_form(self._h, code), self._h)
 
+    def set_graph(self, mode):
+        """Forward launches replayed as a HIP graph: "off", "on" or "auto" (the default: small
+        grids, from the second call in a row with the same arguments)."""
+        code = {"off": 0, "on": 1, "auto": 2}[mode]
+        _lib.check(_lib.load().dd_set_graph(self._h, code), self._h)
+
+    def graph_stats(self):
+        """(graphs captured, forward calls replayed as a graph) so far."""
+        c, r = ctypes.c_int64(), ctypes.c_int64()
+        _lib.check(_lib.load().dd_graph_stats(self._h, ctypes.byref(c), ctypes.byref(r)), self._h)
+        return c.value, r.value
+
     def check_finite(self):
         """Raise DDError (DD_ERR_UNSTABLE) if the current fields hold non-finite values."""
         _lib.check(_lib.load().dd_check_finite(self._h, _stream()), self._h)
