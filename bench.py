@@ -439,7 +439,7 @@ def cga_measure(prob, w, eobs, n_iter):
     }
 
 
-def serving_comparison(n_jobs=24, ranges="small"):
+def serving_comparison(n_jobs=48, ranges="small"):
     """Continuous batching vs one solve at a time on the same uneven request stream.
 
     Requests (seeded), ranges "small": outer grids {64, 96, 128}^3, FEM boxes {32, 48}^3 hexes,
@@ -492,7 +492,7 @@ def main():
     ap.add_argument("--cpu-sample-steps", type=int, default=20, help="0 skips the oracle baseline")
     ap.add_argument("--no-profile", action="store_true", help="skip the HIP-event kernel timing")
     ap.add_argument("--serving", type=int, default=1, help="0 skips the batched / serving comparison")
-    ap.add_argument("--serving-jobs", type=int, default=24, help="requests of the serving comparison")
+    ap.add_argument("--serving-jobs", type=int, default=48, help="requests of the serving comparison")
     ap.add_argument("--serving-ranges", choices=("small", "full"), default="small",
                     help="request size ranges of the serving comparison")
     ap.add_argument("--serving-full-jobs", type=int, default=6,
