@@ -348,23 +348,28 @@ enum { DD_MISFIT_NOALLOC_MAX_STEPS = 65536 };
 int dd_misfit_noalloc(dd_problem* p, const float* traces_dev, const float* obs_dev, int32_t n_src, const double* z_host,
                       float* cot_dev, double* j_dev, void* stream);
 
-/* Forward launches as a HIP graph.  A step of a small grid takes a few microseconds, a good
- * part of it the dispatch of its launch; replaying the forward's launches as one graph
- * (hipGraphLaunch on the caller's stream) cuts that part.  DD_GRAPH_ON: every dd_forward call
- * replays a graph, captured on the first call and again whenever the call's sources, trace /
- * energy buffers, save flag, div-div form or initial-data state differ from the captured
- * ones (a capture takes about as long as queuing the launches one by one); the graph reads the coefficients,
- * initial data and saved-forward buffers the problem owns, so it follows dd_set_coefficients.
- * DD_GRAPH_AUTO (default): as ON on grids of at most 2^19 nodes, from the second call in a row
- * with the same arguments; the first of them runs launch by launch.  DD_GRAPH_OFF: launch by
- * launch.  Results are bitwise those of the launch-by-launch forward.  Not while kernel
- * timing (dd_profile_enable) is on, nor with the two-stream step order; the adjoint runs
- * launch by launch.  A re-capture waits for the previous replay to finish.  The environment
- * variable DD_GRAPH (0, 1, 2) sets the mode of problems created after it. */
+/* Solves as HIP graphs.  A step of a small grid takes a few microseconds, a good part of it the
+ * dispatch of its launch; replaying a call's launches as one graph (hipGraphLaunch on the
+ * caller's stream) cuts that part.  The forward (dd_forward) and the adjoint (dd_adjoint,
+ * dd_adjoint_misfit) each keep one graph.  DD_GRAPH_ON: every such call replays its graph,
+ * captured on the first call and again whenever the call's arguments (forward: sources,
+ * trace / energy buffers, save flag; adjoint: cotangent / observation buffers, saved source
+ * count) or the problem's options (div-div form, initial data, paper-formula variant) differ
+ * from the captured ones; a capture takes about as long as queuing the launches one by one.
+ * The graphs read the coefficients, initial data and saved-forward buffers the problem owns,
+ * so they follow dd_set_coefficients.  DD_GRAPH_AUTO (default): as ON on grids of at most
+ * 2^19 nodes, from the second call in a row with the same arguments; the first of them runs
+ * launch by launch.  DD_GRAPH_OFF: launch by launch.  Results are bitwise those of the
+ * launch-by-launch calls.  Not while kernel timing (dd_profile_enable) is on, nor with the
+ * two-stream step order.  A re-capture waits for the previous replay of that graph to
+ * finish.  The environment variable DD_GRAPH (0, 1, 2) sets the mode of problems created
+ * after it. */
 enum { DD_GRAPH_OFF = 0, DD_GRAPH_ON = 1, DD_GRAPH_AUTO = 2 };
 int dd_set_graph(dd_problem* p, int32_t mode);
-/* Graphs captured and forward calls replayed as a graph so far (either pointer may be NULL). */
-int dd_graph_stats(const dd_problem* p, int64_t* captures, int64_t* replays);
+/* Graphs captured and calls replayed as a graph so far, for which = DD_GRAPH_FORWARD or
+ * DD_GRAPH_ADJOINT (either pointer may be NULL). */
+enum { DD_GRAPH_FORWARD = 0, DD_GRAPH_ADJOINT = 1 };
+int dd_graph_stats(const dd_problem* p, int32_t which, int64_t* captures, int64_t* replays);
 
 /* Div-div form of the FEM rows.  DD_DIVDIV_R1 (default): the nodal product (eps - 1) E inside
  * the element divergence, as eq. forward_prob writes it.  DD_DIVDIV_R2: the element mean of

@@ -158,7 +158,7 @@ def load():
     lib.dd_misfit_taper.argtypes = [ctypes.c_int32, ctypes.c_double, ctypes.c_double, P]
     lib.dd_set_divdiv_form.argtypes = [P, ctypes.c_int32]
     lib.dd_set_graph.argtypes = [P, ctypes.c_int32]
-    lib.dd_graph_stats.argtypes = [P, ctypes.c_void_p, ctypes.c_void_p]
+    lib.dd_graph_stats.argtypes = [P, ctypes.c_int32, ctypes.c_void_p, ctypes.c_void_p]
     lib.dd_gradient_paper.argtypes = [P, P, P, P]
     lib.dd_set_initial_data.argtypes = [P, P, P, P]
     lib.dd_check_finite.argtypes = [P, P]

@@ -19,6 +19,16 @@
 
 using namespace dd;
 
+// One replayable graph of a problem's launches (the forward's or the adjoint's): the executable
+// graph, the key of the call it was captured for, the key of the last call, the number of
+// captures and replays, and an event marking the end of the last replay.
+struct GraphCache {
+  hipGraphExec_t exec = nullptr;
+  hipEvent_t done = nullptr;
+  std::vector<unsigned char> key, last;
+  int64_t captures = 0, replays = 0;
+};
+
 struct dd_problem {
   dd_problem_desc d{};
   int nx = 0, ny = 0, nz = 0;
@@ -74,17 +84,13 @@ struct dd_problem {
   // steps (on the caller's stream) are done
   hipEvent_t ev_rec[2] = {nullptr, nullptr}, ev_adj = nullptr;
   bool overlap = false;   // measured slower than one stream (cross-stream waits per step)
-  // forward graphs: the launches of a dd_forward call captured once into a HIP graph (on the
-  // capture stream `cap`) and replayed while the call's arguments and the problem's launch
-  // options stay the same (`gkey`); `gdone` marks the end of the last replay
-  // (DD_GRAPH_AUTO: on grids of at most kGraphAutoNodes nodes, from the second call in a row
-  // with the same key, `glast` being the last call's key)
+  // graphs: the launches of a dd_forward / dd_adjoint call captured once into a HIP graph (on
+  // the capture stream `cap`) and replayed while the call's arguments and the problem's launch
+  // options stay the same (DD_GRAPH_AUTO: on grids of at most kGraphAutoNodes nodes, from the
+  // second call in a row with the same key)
   int graph = DD_GRAPH_AUTO;
   hipStream_t cap = nullptr;
-  hipGraphExec_t gexec = nullptr;
-  hipEvent_t gdone = nullptr;
-  std::vector<unsigned char> gkey, glast;
-  int64_t g_captures = 0, g_replays = 0;
+  GraphCache gfwd, gadj;
   bool fused = true;      // one launch per step (FD tiles + stencil FEM partitions)
   bool saved = false;
   int saved_n_src = 0;
@@ -811,52 +817,59 @@ std::vector<unsigned char> forward_key(const dd_problem* p, const dd_source* src
   return key;
 }
 
-// Whether this dd_forward call replays a graph (and records the call for DD_GRAPH_AUTO).
-bool forward_graph_wanted(dd_problem* p, const std::vector<unsigned char>& key) {
+// Whether a call with this key replays the graph of `g` (and records the call for
+// DD_GRAPH_AUTO).
+bool graph_wanted(dd_problem* p, GraphCache& g, const std::vector<unsigned char>& key) {
   if (p->graph == DD_GRAPH_OFF || p->overlap || p->prof_stride > 0) return false;
   if (p->graph == DD_GRAPH_ON) return true;
   if (p->N > kGraphAutoNodes) return false;
-  const bool repeat = (p->gexec && key == p->gkey) || key == p->glast;
-  p->glast = key;
+  const bool repeat = (g.exec && key == g.key) || key == g.last;
+  g.last = key;
   return repeat;
 }
 
-// The forward's launches as one HIP graph: captured on the problem's capture stream (whose
-// captured work never runs there), instantiated, and launched on the caller's stream.  The
-// graph is kept and replayed while the call's key stays the same; a new key captures anew.
-int forward_graph(dd_problem* p, const std::vector<unsigned char>& key, const dd_source* src, int32_t n_src,
-                  float* traces, bool save, double* energy, hipStream_t st) {
-  if (!p->gexec || key != p->gkey) {
-    if (p->gexec) {
+// The launches `queue` issues on a stream, as one HIP graph: captured on the problem's capture
+// stream (whose captured work never runs there; streams that join the capture through events
+// rejoin it before its end), instantiated, and launched on the caller's stream.  The graph is
+// kept and replayed while the key stays the same; a new key captures anew.
+template <class Queue>
+int graph_run(dd_problem* p, GraphCache& g, const std::vector<unsigned char>& key, hipStream_t st, Queue&& queue) {
+  if (!g.exec || key != g.key) {
+    if (g.exec) {
       // the last replay may still run
-      if (hipEventSynchronize(p->gdone) != hipSuccess) return fail(p, DD_ERR_HIP, "graph wait failed");
-      (void)hipGraphExecDestroy(p->gexec);
-      p->gexec = nullptr;
+      if (hipEventSynchronize(g.done) != hipSuccess) return fail(p, DD_ERR_HIP, "graph wait failed");
+      (void)hipGraphExecDestroy(g.exec);
+      g.exec = nullptr;
     }
     if (!p->cap && hipStreamCreateWithFlags(&p->cap, hipStreamNonBlocking) != hipSuccess)
       return fail(p, DD_ERR_HIP, "capture stream creation failed");
-    if (!p->gdone && hipEventCreateWithFlags(&p->gdone, hipEventDisableTiming) != hipSuccess)
+    if (!g.done && hipEventCreateWithFlags(&g.done, hipEventDisableTiming) != hipSuccess)
       return fail(p, DD_ERR_HIP, "event creation failed");
     if (hipStreamBeginCapture(p->cap, hipStreamCaptureModeThreadLocal) != hipSuccess)
       return fail(p, DD_ERR_HIP, "stream capture failed to start");
-    int rc = DD_OK;
-    for (int s = 0; s < n_src && !rc; ++s) rc = run_forward(p, src[s], s, traces, save, energy, p->cap);
-    hipGraph_t g = nullptr;
-    const hipError_t e = hipStreamEndCapture(p->cap, &g);
-    if (!rc && (e != hipSuccess || !g)) rc = fail(p, DD_ERR_HIP, "stream capture failed");
-    if (!rc && hipGraphInstantiate(&p->gexec, g, nullptr, nullptr, 0) != hipSuccess) {
-      p->gexec = nullptr;
+    int rc = queue(p->cap);
+    hipGraph_t graph = nullptr;
+    const hipError_t e = hipStreamEndCapture(p->cap, &graph);
+    if (!rc && (e != hipSuccess || !graph)) rc = fail(p, DD_ERR_HIP, "stream capture failed");
+    if (!rc && hipGraphInstantiate(&g.exec, graph, nullptr, nullptr, 0) != hipSuccess) {
+      g.exec = nullptr;
       rc = fail(p, DD_ERR_HIP, "graph instantiation failed");
     }
-    if (g) (void)hipGraphDestroy(g);
+    if (graph) (void)hipGraphDestroy(graph);
     if (rc) return rc;
-    p->gkey = key;
-    ++p->g_captures;
+    g.key = key;
+    ++g.captures;
   }
-  if (hipGraphLaunch(p->gexec, st) != hipSuccess || hipEventRecord(p->gdone, st) != hipSuccess)
+  if (hipGraphLaunch(g.exec, st) != hipSuccess || hipEventRecord(g.done, st) != hipSuccess)
     return fail(p, DD_ERR_HIP, "graph launch failed");
-  ++p->g_replays;
+  ++g.replays;
   return DD_OK;
+}
+
+void graph_free(GraphCache& g) {
+  if (g.exec) (void)hipGraphExecDestroy(g.exec);
+  if (g.done) (void)hipEventDestroy(g.done);
+  g = GraphCache();
 }
 }  // namespace
 
@@ -1168,8 +1181,8 @@ int dd_destroy(dd_problem* p) {
   for (hipEvent_t e : {p->ev_rec[0], p->ev_rec[1], p->ev_adj})
     if (e) (void)hipEventDestroy(e);
   if (p->aux) (void)hipStreamDestroy(p->aux);
-  if (p->gexec) (void)hipGraphExecDestroy(p->gexec);
-  if (p->gdone) (void)hipEventDestroy(p->gdone);
+  graph_free(p->gfwd);
+  graph_free(p->gadj);
   if (p->cap) (void)hipStreamDestroy(p->cap);
   for (void* q : p->allocs) raw_free(p->free_fn, p->actx, q);
   delete p;
@@ -1249,8 +1262,12 @@ int dd_forward(dd_problem* p, const dd_source* src, int32_t n_src, float* traces
     if (rc) return rc;
   }
   const std::vector<unsigned char> key = forward_key(p, src, n_src, traces_dev, save != 0, energy_dev);
-  if (forward_graph_wanted(p, key)) {
-    int rc = forward_graph(p, key, src, n_src, traces_dev, save != 0, energy_dev, st);
+  if (graph_wanted(p, p->gfwd, key)) {
+    int rc = graph_run(p, p->gfwd, key, st, [&](hipStream_t cs) {
+      int r = DD_OK;
+      for (int s = 0; s < n_src && !r; ++s) r = run_forward(p, src[s], s, traces_dev, save != 0, energy_dev, cs);
+      return r;
+    });
     if (rc) return rc;
   } else {
     for (int s = 0; s < n_src; ++s) {
@@ -1266,15 +1283,38 @@ int dd_forward(dd_problem* p, const dd_source* src, int32_t n_src, float* traces
 }
 
 namespace {
-int adjoint_all(dd_problem* p, const float* cot, const float* obs, hipStream_t st) {
+// The adjoint sweeps of every saved source with their gradient sums cleared first.
+int adjoint_launches(dd_problem* p, const float* cot, const float* obs, hipStream_t st) {
   launch_fill_f64(p->g_eps, p->n_own, 0.0, st);
   launch_fill_f64(p->g_sig, p->n_own, 0.0, st);
   if (p->pg_on || p->r2) launch_fill_f64(p->pg_acc, p->n_fem, 0.0, st);
-  p->ic_used = p->init_on && !p->r2;
   if (p->ic_used) launch_fill_f64(p->ic_acc, p->n_fem, 0.0, st);
-  p->adj_obs = obs != nullptr;
   for (int s = 0; s < p->saved_n_src; ++s) {
     int rc = run_adjoint(p, s, cot, obs, st);
+    if (rc) return rc;
+  }
+  return DD_OK;
+}
+
+int adjoint_all(dd_problem* p, const float* cot, const float* obs, hipStream_t st) {
+  p->ic_used = p->init_on && !p->r2;
+  p->adj_obs = obs != nullptr;
+  std::vector<unsigned char> key;
+  key_put(key, cot); key_put(key, obs); key_put(key, p->saved_n_src);
+  key_put(key, p->pg_on); key_put(key, p->r2); key_put(key, p->init_on); key_put(key, p->tb); key_put(key, p->fd_nt);
+  key_put(key, p->fused);
+  if (graph_wanted(p, p->gadj, key)) {
+    int rc = graph_run(p, p->gadj, key, st, [&](hipStream_t cs) {
+      int r = adjoint_launches(p, cot, obs, cs);
+      // the segment recompute stream rejoins the capture (it already has, unless one
+      // segment left it nothing to do)
+      if (!r && (hipEventRecord(p->ev_fem, p->aux) != hipSuccess || hipStreamWaitEvent(cs, p->ev_fem, 0) != hipSuccess))
+        r = fail(p, DD_ERR_HIP, "stream join failed");
+      return r;
+    });
+    if (rc) return rc;
+  } else {
+    int rc = adjoint_launches(p, cot, obs, st);
     if (rc) return rc;
   }
   p->have_grad = true;
@@ -1420,14 +1460,17 @@ int dd_set_graph(dd_problem* p, int32_t mode) {
   if (mode != DD_GRAPH_OFF && mode != DD_GRAPH_ON && mode != DD_GRAPH_AUTO)
     return fail(p, DD_ERR_INVALID_ARG, "unknown graph mode");
   p->graph = mode;
-  p->glast.clear();
+  p->gfwd.last.clear();
+  p->gadj.last.clear();
   return DD_OK;
 }
 
-int dd_graph_stats(const dd_problem* p, int64_t* captures, int64_t* replays) {
+int dd_graph_stats(const dd_problem* p, int32_t which, int64_t* captures, int64_t* replays) {
   if (!p) return DD_ERR_INVALID_ARG;
-  if (captures) *captures = p->g_captures;
-  if (replays) *replays = p->g_replays;
+  if (which != DD_GRAPH_FORWARD && which != DD_GRAPH_ADJOINT) return DD_ERR_INVALID_ARG;
+  const GraphCache& g = which == DD_GRAPH_FORWARD ? p->gfwd : p->gadj;
+  if (captures) *captures = g.captures;
+  if (replays) *replays = g.replays;
   return DD_OK;
 }
 

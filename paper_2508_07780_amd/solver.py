@@ -240,15 +240,16 @@ class Problem:
         _lib.check(_lib.load().dd_set_divdiv_form(self._h, code), self._h)
 
     def set_graph(self, mode):
-        """Forward launches replayed as a HIP graph: "off", "on" or "auto" (the default: small
-        grids, from the second call in a row with the same arguments)."""
+        """Forward and adjoint launches replayed as HIP graphs: "off", "on" or "auto" (the
+        default: small grids, from the second call in a row with the same arguments)."""
         code = {"off": 0, "on": 1, "auto": 2}[mode]
         _lib.check(_lib.load().dd_set_graph(self._h, code), self._h)
 
-    def graph_stats(self):
-        """(graphs captured, forward calls replayed as a graph) so far."""
+    def graph_stats(self, which="forward"):
+        """(graphs captured, calls replayed as a graph) so far, of "forward" or "adjoint"."""
         c, r = ctypes.c_int64(), ctypes.c_int64()
-        _lib.check(_lib.load().dd_graph_stats(self._h, ctypes.byref(c), ctypes.byref(r)), self._h)
+        code = {"forward": 0, "adjoint": 1}[which]
+        _lib.check(_lib.load().dd_graph_stats(self._h, code, ctypes.byref(c), ctypes.byref(r)), self._h)
         return c.value, r.value
 
     def check_finite(self):

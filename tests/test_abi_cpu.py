@@ -74,7 +74,7 @@ def test_null_handles_rejected_without_device_work(lib):
     assert L.dd_batch_set_fill(None, 0) == -1
     assert L.dd_set_divdiv_form(None, 2) == -1
     assert L.dd_set_graph(None, 1) == -1
-    assert L.dd_graph_stats(None, None, None) == -1
+    assert L.dd_graph_stats(None, 0, None, None) == -1
     assert L.dd_misfit(None, None, None, 1, None, None, None, None) == -1
 
 

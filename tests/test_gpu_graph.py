@@ -1,12 +1,14 @@
-"""Forward launches replayed as a HIP graph (dd_set_graph) against launch by launch.
+"""Forward and adjoint launches replayed as HIP graphs (dd_set_graph) against launch by launch.
 
-The graph holds the same kernels with the same arguments as the launch-by-launch forward, so
-the bar is bit-for-bit: traces, energy, and the gradient of an adjoint that reads the saved
-forward the graph wrote.  Each graph is replayed several times, with other work queued and
-the device synchronised between replays; a change of the call's sources, buffers or save flag,
-of the div-div form or of the initial data captures anew.  One case is also held to the FP64
-oracle at the bar of every parity test (traces 1e-4).  The automatic mode replays only on a
-repeated call on a small grid, and never while kernel timing is on.
+A graph holds the same kernels with the same arguments as the launch-by-launch call, so the
+bar is bit-for-bit: traces, energy, and gradients (an adjoint graph reads the saved forward a
+forward graph wrote).  Each graph is replayed several times, with other work queued and the
+device synchronised between replays; a change of the call's sources, buffers or save flag, of
+the div-div form or of the initial data captures anew.  The adjoint runs with one, two and
+several checkpoint segments (its segment recompute on a second stream joins the capture).
+One case is also held to the FP64 oracle at the bar of every parity test (traces 1e-4).  The
+automatic mode replays only on a repeated call on a small grid, and never while kernel timing
+is on.
 """
 
 import dataclasses
@@ -41,10 +43,14 @@ def _grad(torch, p, traces, obs):
     return [g.clone() for g in p.gradient()]
 
 
-@pytest.mark.parametrize("name", ["tiny", "ragged"])
-def test_graph_replays_equal_launch_by_launch(name):
+@pytest.mark.parametrize("name,segments", [("tiny", "many"), ("ragged", "many"), ("tiny", "one"), ("tiny", "two")])
+def test_graph_replays_equal_launch_by_launch(name, segments):
     import torch
     w = synth.small(name)
+    nt = w.desc.n_steps
+    if segments != "many":
+        ck = nt if segments == "one" else (nt + 1) // 2
+        w = dataclasses.replace(w, desc=dataclasses.replace(w.desc, ckpt_every=ck))
     pe, pg = _problem(torch, w, "off"), _problem(torch, w, "on")
     dip = _dipole(w, (1, 1, 1))
     ref = pe.forward(w.sources, save=True).clone()
@@ -59,9 +65,13 @@ def test_graph_replays_equal_launch_by_launch(name):
         torch.cuda.synchronize()
         assert torch.equal(buf, ref), f"replay {r}"
     assert pg.graph_stats() == (1, 4)
-    g = _grad(torch, pg, buf, obs)
-    for a, b in zip(g, g_ref):
-        assert torch.equal(a, b)
+    for r in range(3):
+        g = _grad(torch, pg, buf, obs)
+        for a, b in zip(g, g_ref):
+            assert torch.equal(a, b), f"adjoint replay {r}"
+        pe.forward([dip], save=False)
+        torch.cuda.synchronize()
+    assert pg.graph_stats("adjoint") == (1, 3)
 
     # a new source, the save flag, energy: captured anew, still bitwise
     te = pe.forward([dip], save=True).clone()
@@ -97,6 +107,7 @@ def test_graph_replays_equal_launch_by_launch(name):
     for a, b in zip(g, g_ref):
         assert torch.equal(a, b)
     assert pg.graph_stats() == (6, 10)
+    assert pg.graph_stats("adjoint") == (3, 5)
     pe.close()
     pg.close()
 
@@ -136,6 +147,13 @@ def test_auto_mode_replays_repeated_calls_on_small_grids():
     assert torch.equal(buf, ref_d) and pa.graph_stats() == (2, 3)
     pa.forward(w.sources, save=True, out=buf)      # back to the first call: launch by launch
     assert torch.equal(buf, ref) and pa.graph_stats() == (2, 3)
+    obs = torch.tensor(1e-3 * synth.noise(tuple(ref.shape), 5), dtype=torch.float32, device="cuda")
+    pe.forward(w.sources, save=True)
+    g_ref = _grad(torch, pe, ref, obs)
+    for want in [(0, 0), (1, 1), (1, 2)]:
+        for a, b in zip(_grad(torch, pa, buf, obs), g_ref):
+            assert torch.equal(a, b)
+        assert pa.graph_stats("adjoint") == want
     # kernel timing on: launch by launch
     pa.profile(1)
     for _ in range(2):
