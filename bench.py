@@ -218,6 +218,66 @@ def refined_mesh_measure(w, stride=16):
     return out
 
 
+def small_graphs_measure(reps=20):
+    """The plain forward config (25^3 outer nodes, 8^3 FEM hexes, 300 steps), whose steps are
+    bound by launch latency: per-step times of the forward (with saving) and of the misfit
+    adjoint, and the whole solve (forward, adjoint, gradient), launch by launch and replayed
+    as HIP graphs, with the configured checkpoint interval (K = 64) and with one segment."""
+    import torch
+    import synth
+    from dataclasses import replace
+    from paper_2508_07780_amd import Problem
+    w = synth.c1()
+    nt = w.desc.n_steps
+    out = {"workload": "plain forward config: outer 25^3, FEM 8^3 hexes, 300 steps, one source"}
+
+    def timed(fn):
+        for _ in range(3):
+            fn()
+        torch.cuda.synchronize()
+        t0 = time.perf_counter()
+        for _ in range(reps):
+            fn()
+        torch.cuda.synchronize()
+        return (time.perf_counter() - t0) / reps
+
+    for label, desc in (("k64", w.desc), ("one_segment", replace(w.desc, ckpt_every=nt))):
+        res, grads = {}, {}
+        for mode in ("off", "on"):
+            p = Problem(desc)
+            p.set_graph(mode)
+            p.set_coefficients(torch.tensor(w.eps, dtype=torch.float32, device="cuda"),
+                               torch.tensor(w.sigma, dtype=torch.float32, device="cuda"))
+            tr = p.forward(w.sources, save=True)
+            obs = torch.full_like(tr, 1e-3)
+            ge = torch.empty(p.n_fem, dtype=torch.float64, device="cuda")
+            gs = torch.empty_like(ge)
+
+            def fwd():
+                p.forward(w.sources, save=True, out=tr)
+
+            def adj():
+                p.adjoint_misfit(tr, obs)
+
+            def solve():
+                fwd()
+                adj()
+                p.gradient(out=(ge, gs))
+
+            tf, ta, ts = timed(fwd), timed(adj), timed(solve)
+            r = {"forward_us_per_step": round(tf / nt * 1e6, 2), "adjoint_us_per_step": round(ta / nt * 1e6, 2),
+                 "solve_ms": round(ts * 1e3, 3)}
+            if mode == "on":
+                r["graphs_captured_replayed"] = {"forward": p.graph_stats("forward"),
+                                                 "adjoint": p.graph_stats("adjoint")}
+            res["launch_by_launch" if mode == "off" else "graphs"] = r
+            grads[mode] = ge.clone()
+            p.close()
+        res["gradient_bitwise_equal"] = bool(torch.equal(grads["off"], grads["on"]))
+        out[label] = res
+    return out
+
+
 def acga_measure(w, n_iter=2, n_refine=2, beta_eps=0.9):
     """Box "ACGA" on the main workload from eps = 1, sigma = 0: n_iter CGA iterations per mesh,
     n_refine refinements (longest-edge bisection where h_K |eps| >= beta_eps of its largest
@@ -507,6 +567,8 @@ def main():
                     help="0 skips the paper-formula gradient variant's measurement")
     ap.add_argument("--refined", type=int, default=1, help="0 skips the solve on a locally refined mesh")
     ap.add_argument("--acga", type=int, default=1, help="0 skips the adaptive reconstruction (box ACGA)")
+    ap.add_argument("--small", type=int, default=1,
+                    help="0 skips the plain forward config's launch-by-launch / graph comparison")
     ap.add_argument("--profile-stride", type=int, default=64,
                     help="time every k-th step launch with HIP events (k >= 16 barely perturbs the run)")
     args = ap.parse_args()
@@ -640,6 +702,9 @@ def main():
     if args.acga:
         out["acga"] = acga_measure(w)
         progress("adaptive reconstruction")
+    if args.small:
+        out["small_graphs"] = small_graphs_measure()
+        progress("plain forward config, graphs")
     progress("main workload")
     if args.probe:
         out["hbm_probe"] = large_probe(args.probe_steps)

@@ -6,6 +6,8 @@
   python -m paper_2508_07780_amd.profiling hash [FILE ...]    hash of the step kernel sources (or of
                                                              the named files under csrc/)
   python -m paper_2508_07780_amd.profiling batch [STEPS]      two small mix problems batched, then alone
+  python -m paper_2508_07780_amd.profiling grid DIR [GRID...]  kernel-trace durations per kernel and
+                                                             grid size (only the given grid sizes)
 
 The committed summaries under profiles/ record the HBM traffic of the fused step
 kernel together with the hash of the kernel sources it was measured on; bench.py
@@ -104,6 +106,21 @@ def stats_table(path):
     return "\n".join(out)
 
 
+def grid_table(path, grids=()):
+    """Average / min / max duration per (kernel, grid size) of a kernel trace: launches of one
+    kernel on problems of different sizes apart."""
+    dur = collections.defaultdict(list)
+    for r in _rows(path, "kernel_trace.csv"):
+        g = r["Grid_Size_X"]
+        if grids and g not in grids:
+            continue
+        dur[(_short(r["Kernel_Name"]), g)].append((int(r["End_Timestamp"]) - int(r["Start_Timestamp"])) / 1e3)
+    out = ["| kernel | grid size (work-items) | calls | average us | min us | max us |", "|---|---|---|---|---|---|"]
+    for (k, g), v in sorted(dur.items(), key=lambda kv: -sum(kv[1])):
+        out.append("| %s | %s | %d | %.2f | %.2f | %.2f |" % (k, g, len(v), sum(v) / len(v), min(v), max(v)))
+    return "\n".join(out)
+
+
 def pmc_average(path, counter, pattern=""):
     rows = _rows(path, "counter_collection.csv")
     tot = collections.defaultdict(float)
@@ -133,6 +150,8 @@ def main(argv):
             print(f"{k}\t{argv[2]}\t{v:.1f}\tdispatches={n}")
     elif cmd == "hash":
         print(kernel_source_hash(argv[1:]) if len(argv) > 1 else kernel_source_hash())
+    elif cmd == "grid":
+        print(grid_table(argv[1], tuple(argv[2:])))
     elif cmd == "batch":
         batch_probe(int(argv[1]) if len(argv) > 1 else 400)
     else:
