@@ -867,6 +867,8 @@ int graph_run(dd_problem* p, GraphCache& g, const std::vector<unsigned char>& ke
 }
 
 void graph_free(GraphCache& g) {
+  // the last replay may still run
+  if (g.exec && g.done) (void)hipEventSynchronize(g.done);
   if (g.exec) (void)hipGraphExecDestroy(g.exec);
   if (g.done) (void)hipEventDestroy(g.done);
   g = GraphCache();
