@@ -362,7 +362,7 @@ int dd_misfit_noalloc(dd_problem* p, const float* traces_dev, const float* obs_d
  * launch by launch.  DD_GRAPH_OFF: launch by launch.  Results are bitwise those of the
  * launch-by-launch calls.  Not while kernel timing (dd_profile_enable) is on, nor with the
  * two-stream step order.  A re-capture waits for the previous replay of that graph to
- * finish.  The environment variable DD_GRAPH (0, 1, 2) sets the mode of problems created
+ * finish, and dd_destroy for the last replays of the problem's graphs.  The environment variable DD_GRAPH (0, 1, 2) sets the mode of problems created
  * after it. */
 enum { DD_GRAPH_OFF = 0, DD_GRAPH_ON = 1, DD_GRAPH_AUTO = 2 };
 int dd_set_graph(dd_problem* p, int32_t mode);
