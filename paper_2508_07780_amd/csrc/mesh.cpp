@@ -907,10 +907,46 @@ struct Refiner {
   std::vector<int> layer;                      // lattice layer; midpoints and extra nodes: free
   std::vector<std::array<int64_t, 4>> verts;   // element id -> vertices (leaves: the current mesh)
   std::vector<std::array<int64_t, 2>> kids;    // {-1, -1} for a leaf
-  // edge (low << 32 | high) -> current elements that contain it, in increasing id (elements
-  // are added in id order and children take new, larger ids, so appending keeps the order)
-  std::unordered_map<uint64_t, std::vector<int64_t>> around;
+  // Elements around each edge.  The input elements' edges are indexed once: grouped by their
+  // low vertex (off / ent), each group sorted by (high vertex, element).  Elements created by
+  // bisection are appended to `added` under their edges.  A lookup returns the leaves among
+  // them: an element stops containing its edges when it is bisected, and its children take
+  // new, larger ids, so the input entries followed by the added ones are in increasing id.
+  int64_t n_in = 0;
+  std::vector<int64_t> off;
+  std::vector<std::pair<int32_t, int32_t>> ent;
+  std::unordered_map<uint64_t, std::vector<int64_t>> added;
   static uint64_t key(const Edge& e) { return ((uint64_t)e.first << 32) | (uint64_t)e.second; }
+  void index_input() {
+    n_in = (int64_t)verts.size();
+    off.assign(P.size() + 1, 0);
+    for (int64_t t = 0; t < n_in; ++t)
+      for (int a = 0; a < 4; ++a)
+        for (int b = a + 1; b < 4; ++b) ++off[edge_of(verts[t][a], verts[t][b]).first + 1];
+    for (size_t i = 1; i < off.size(); ++i) off[i] += off[i - 1];
+    ent.resize((size_t)off.back());
+    std::vector<int64_t> pos(off.begin(), off.end() - 1);
+    for (int64_t t = 0; t < n_in; ++t)
+      for (int a = 0; a < 4; ++a)
+        for (int b = a + 1; b < 4; ++b) {
+          const Edge e = edge_of(verts[t][a], verts[t][b]);
+          ent[(size_t)pos[e.first]++] = {(int32_t)e.second, (int32_t)t};
+        }
+    for (size_t i = 0; i + 1 < off.size(); ++i) std::sort(ent.begin() + off[i], ent.begin() + off[i + 1]);
+  }
+  bool leaf(int64_t t) const { return kids[t][0] < 0; }
+  std::vector<int64_t> around(const Edge& e) const {
+    std::vector<int64_t> res;
+    const auto b = ent.begin() + off[e.first], en = ent.begin() + off[e.first + 1];
+    for (auto it = std::lower_bound(b, en, std::make_pair((int32_t)e.second, INT32_MIN));
+         it != en && it->first == (int32_t)e.second; ++it)
+      if (leaf(it->second)) res.push_back(it->second);
+    const auto o = added.find(key(e));
+    if (o != added.end())
+      for (int64_t t : o->second)
+        if (leaf(t)) res.push_back(t);
+    return res;
+  }
   std::vector<Edge> split;
 
   double len2(const Edge& e) const {
@@ -941,12 +977,12 @@ struct Refiner {
   void add(int64_t t) {
     const auto& v = verts[t];
     for (int a = 0; a < 4; ++a)
-      for (int b = a + 1; b < 4; ++b) around[key(edge_of(v[a], v[b]))].push_back(t);
+      for (int b = a + 1; b < 4; ++b) added[key(edge_of(v[a], v[b]))].push_back(t);
   }
   bool eligible(const Edge& e) const {
-    auto it = around.find(key(e));
-    if (it == around.end()) return false;
-    for (int64_t t : it->second)
+    const std::vector<int64_t> ts = around(e);
+    if (ts.empty()) return false;
+    for (int64_t t : ts)
       for (int64_t v : verts[t])
         if (layer[v] < 1) return false;
     return true;
@@ -958,17 +994,8 @@ struct Refiner {
     P.push_back(q);
     layer.push_back(1 << 30);
     split.push_back(e);
-    auto node = around.extract(key(e));
-    for (int64_t t : node.mapped()) {   // increasing id
+    for (int64_t t : around(e)) {   // increasing id; each becomes a non-leaf below
       const auto v = verts[t];
-      for (int a = 0; a < 4; ++a)
-        for (int b = a + 1; b < 4; ++b) {
-          const Edge f = edge_of(v[a], v[b]);
-          if (f != e) {
-            auto& l = around[key(f)];
-            l.erase(std::find(l.begin(), l.end(), t));
-          }
-        }
       std::array<int64_t, 4> h0 = v, h1 = v;
       for (int a = 0; a < 4; ++a) {
         if (h0[a] == e.second) h0[a] = m;
@@ -989,8 +1016,8 @@ struct Refiner {
       const Edge e = longest(t);
       if (!eligible(e)) return false;
       std::vector<int64_t> others;
-      for (int64_t u : around[key(e)])
-        if (longest(u) != e) others.push_back(u);   // std::set: increasing id
+      for (int64_t u : around(e))
+        if (longest(u) != e) others.push_back(u);   // increasing id
       if (others.empty()) {
         bisect(e);
         return true;
@@ -1065,6 +1092,7 @@ extern "C" int dd_meshref_create(const dd_problem_desc* d, int64_t n_extra, cons
     }
   }
   const int64_t nt = (int64_t)R.verts.size();
+  if (nt >= (1ll << 31)) return DD_ERR_INVALID_ARG;   // element ids are indexed as 32-bit values
   R.kids.assign(nt, {-1, -1});
   // step 2: marks
   std::vector<double> hk(nt);
@@ -1092,8 +1120,7 @@ extern "C" int dd_meshref_create(const dd_problem_desc* d, int64_t n_extra, cons
         break;
       }
   // step 3: bisection
-  R.around.reserve((size_t)(2 * nt));
-  for (int64_t t = 0; t < nt; ++t) R.add(t);
+  R.index_input();
   for (int64_t t = 0; t < nt; ++t)
     if (r->marks[t] && R.kids[t][0] < 0) R.refine_element(t);
   for (int64_t t = 0; t < nt; ++t) R.emit(t, r->tets);
