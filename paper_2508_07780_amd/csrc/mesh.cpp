@@ -556,16 +556,19 @@ std::string build_mesh_general(const dd_problem_desc& d, int64_t n_extra, const 
   };
   // geometry (FP64, lengths in h scaled back to physical units), volumes, node -> tets
   std::vector<int> deg(n_fem + 1, 0);
+  std::vector<double> tvol(n_tets);
   double vol_sum = 0.0;
   for (int64_t t = 0; t < n_tets; ++t) {
     double p[4][3], g[4][3], vol;
     for (int k = 0; k < 4; ++k) {
       const int64_t v = tv[4 * t + k];
       if (v < 0 || v >= n_fem) return "a tetrahedron references a node that does not exist";
-      for (int a = 0; a < 3; ++a) p[k][a] = d.h * (P[v][a] - P[tv[4 * t]][a]);
       ++deg[v];
     }
+    for (int k = 0; k < 4; ++k)
+      for (int a = 0; a < 3; ++a) p[k][a] = d.h * (P[tv[4 * t + k]][a] - P[tv[4 * t]][a]);
     if (!tet_geometry(p, g, &vol)) return "degenerate tetrahedron";
+    tvol[t] = vol;
     vol_sum += vol;
   }
   const double box = d.h * d.h * d.h * (double)L.c[0] * L.c[1] * L.c[2];
@@ -635,7 +638,7 @@ std::string build_mesh_general(const dd_problem_desc& d, int64_t n_extra, const 
     std::vector<std::vector<int64_t>> blocks(npb[0] * npb[1] * npb[2]);
     for (int64_t i = 0; i < n_fem; ++i)
       if (layer_of(i) >= 1) blocks[block_of(P[i])].push_back(i);   // lattice first, then extra: index order
-    std::vector<int> mark(n_fem, -1), tstamp(n_tets, -1);
+    std::vector<int> mark(n_fem, -1), tstamp(n_tets, -1), lpos(n_fem, 0);
     int call = 0;
     // does a partition of these owned nodes fit (the same counts and greedy colouring as below)?
     auto fits_part = [&](const std::vector<int64_t>& own) {
@@ -657,21 +660,20 @@ std::string build_mesh_general(const dd_problem_desc& d, int64_t n_extra, const 
       std::sort(halo.begin(), halo.end());
       halo.erase(std::unique(halo.begin(), halo.end()), halo.end());
       if ((int)(own.size() + halo.size()) > FEM_LOC_MAX) return false;
-      std::map<int64_t, int> loc;
-      for (size_t k = 0; k < own.size(); ++k) loc[own[k]] = (int)k;
+      for (size_t k = 0; k < own.size(); ++k) lpos[own[k]] = (int)k;   // valid where mark == id
       std::vector<uint64_t> used(own.size(), 0);
       for (int t : els) {
         uint64_t forbid = 0;
         for (int k = 0; k < 4; ++k) {
-          auto it = loc.find(tv[4 * t + k]);
-          if (it != loc.end()) forbid |= used[it->second];
+          const int64_t v = tv[4 * t + k];
+          if (mark[v] == id) forbid |= used[lpos[v]];
         }
         if (forbid == ~0ull) return false;
         int c = 0;
         while (forbid & (1ull << c)) ++c;
         for (int k = 0; k < 4; ++k) {
-          auto it = loc.find(tv[4 * t + k]);
-          if (it != loc.end()) used[it->second] |= (1ull << c);
+          const int64_t v = tv[4 * t + k];
+          if (mark[v] == id) used[lpos[v]] |= (1ull << c);
         }
       }
       return true;
@@ -746,14 +748,7 @@ std::string build_mesh_general(const dd_problem_desc& d, int64_t n_extra, const 
           q.own_grid[id] = (int)(gx + (int64_t)d.n_outer[0] * (gy + (int64_t)d.n_outer[1] * gz));
         }
         double ms = 0.0;   // lumped mass: |K| / 4 over the incident tetrahedra, in index order
-        for (int a = adj_off[i]; a < adj_off[i + 1]; ++a) {
-          const int t = adj[a];
-          double pp[4][3], g[4][3], vol;
-          for (int k = 0; k < 4; ++k)
-            for (int c = 0; c < 3; ++c) pp[k][c] = d.h * (P[tv[4 * t + k]][c] - P[tv[4 * t]][c]);
-          tet_geometry(pp, g, &vol);
-          ms += vol / 4.0;
-        }
+        for (int a = adj_off[i]; a < adj_off[i + 1]; ++a) ms += tvol[adj[a]] / 4.0;
         q.mass[id] = ms;
       }
     q.halo_off.assign(n_part + 1, 0);
