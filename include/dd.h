@@ -351,7 +351,8 @@ int dd_misfit_noalloc(dd_problem* p, const float* traces_dev, const float* obs_d
 /* Solves as HIP graphs.  A step of a small grid takes a few microseconds, a good part of it the
  * dispatch of its launch; replaying a call's launches as one graph (hipGraphLaunch on the
  * caller's stream) cuts that part.  The forward (dd_forward) and the adjoint (dd_adjoint,
- * dd_adjoint_misfit) each keep one graph.  DD_GRAPH_ON: every such call replays its graph,
+ * dd_adjoint_misfit; only for problems whose adjoint has one checkpoint segment, i.e.
+ * ckpt_every >= n_steps or DD_CKPT_STORE_ALL) each keep one graph.  DD_GRAPH_ON: every such call replays its graph,
  * captured on the first call and again whenever the call's arguments (forward: sources,
  * trace / energy buffers, save flag; adjoint: cotangent / observation buffers, saved source
  * count) or the problem's options (div-div form, initial data, paper-formula variant) differ

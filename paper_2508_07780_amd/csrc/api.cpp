@@ -1305,11 +1305,14 @@ int adjoint_all(dd_problem* p, const float* cot, const float* obs, hipStream_t s
   key_put(key, cot); key_put(key, obs); key_put(key, p->saved_n_src);
   key_put(key, p->pg_on); key_put(key, p->r2); key_put(key, p->init_on); key_put(key, p->tb); key_put(key, p->fd_nt);
   key_put(key, p->fused);
-  if (graph_wanted(p, p->gadj, key)) {
+  // one checkpoint segment only: with several, the recompute runs on a second stream, and a
+  // graph with that parallel branch gained nothing and its launch held the host until the
+  // stream had drained
+  if (n_segments(p) == 1 && graph_wanted(p, p->gadj, key)) {
     int rc = graph_run(p, p->gadj, key, st, [&](hipStream_t cs) {
       int r = adjoint_launches(p, cot, obs, cs);
-      // the segment recompute stream rejoins the capture (it already has, unless one
-      // segment left it nothing to do)
+      // the segment recompute stream joined the capture through the sweep's first event
+      // wait, with nothing to do in one segment: it rejoins here
       if (!r && (hipEventRecord(p->ev_fem, p->aux) != hipSuccess || hipStreamWaitEvent(cs, p->ev_fem, 0) != hipSuccess))
         r = fail(p, DD_ERR_HIP, "stream join failed");
       return r;

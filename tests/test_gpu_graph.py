@@ -5,10 +5,11 @@ bar is bit-for-bit: traces, energy, and gradients (an adjoint graph reads the sa
 forward graph wrote).  Each graph is replayed several times, with other work queued and the
 device synchronised between replays; a change of the call's sources, buffers or save flag, of
 the div-div form or of the initial data captures anew.  The adjoint runs with one, two and
-several checkpoint segments (its segment recompute on a second stream joins the capture).
-One case is also held to the FP64 oracle at the bar of every parity test (traces 1e-4).  The
-automatic mode replays only on a repeated call on a small grid, and never while kernel timing
-is on.
+several checkpoint segments; only an adjoint of one segment is captured (with several, its
+recompute stream's branch made the graph's launch hold the host), the others run launch by
+launch and must give the same gradients.  One case is also held to the FP64 oracle at the bar
+of every parity test (traces 1e-4).  The automatic mode replays only on a repeated call on a
+small grid, and never while kernel timing is on.
 """
 
 import dataclasses
@@ -71,7 +72,8 @@ def test_graph_replays_equal_launch_by_launch(name, segments):
             assert torch.equal(a, b), f"adjoint replay {r}"
         pe.forward([dip], save=False)
         torch.cuda.synchronize()
-    assert pg.graph_stats("adjoint") == (1, 3)
+    one = segments == "one"
+    assert pg.graph_stats("adjoint") == ((1, 3) if one else (0, 0))
 
     # a new source, the save flag, energy: captured anew, still bitwise
     te = pe.forward([dip], save=True).clone()
@@ -107,7 +109,7 @@ def test_graph_replays_equal_launch_by_launch(name, segments):
     for a, b in zip(g, g_ref):
         assert torch.equal(a, b)
     assert pg.graph_stats() == (6, 10)
-    assert pg.graph_stats("adjoint") == (3, 5)
+    assert pg.graph_stats("adjoint") == ((3, 5) if one else (0, 0))
     pe.close()
     pg.close()
 
@@ -131,6 +133,7 @@ def test_graph_forward_matches_oracle():
 def test_auto_mode_replays_repeated_calls_on_small_grids():
     import torch
     w = synth.small("tiny")
+    w = dataclasses.replace(w, desc=dataclasses.replace(w.desc, ckpt_every=w.desc.n_steps))   # one segment
     pe, pa = _problem(torch, w, "off"), _problem(torch, w, "auto")
     dip = _dipole(w, (1, 1, 1))
     ref = pe.forward(w.sources, save=True).clone()
