@@ -50,6 +50,10 @@ struct dd_problem {
   int *own_off = nullptr, *halo_off = nullptr, *halo = nullptr, *col_base = nullptr, *ncol = nullptr,
       *col_off = nullptr, *own_grid = nullptr, *own_api = nullptr;
   uint64_t* elems = nullptr;
+  // incidence lists of the element kernel's gather form (FemArgs::inc); fem_gather selects it
+  uint16_t* inc = nullptr;
+  int *inc_off = nullptr, *inc_n = nullptr;
+  bool fem_gather = true;
   float* geom = nullptr;
   double* mass_d = nullptr;
   float *em1 = nullptr, *c1 = nullptr, *c2 = nullptr;
@@ -304,6 +308,8 @@ FemArgs fem_base(const dd_problem* p) {
   a.col_base = p->col_base; a.ncol = p->ncol; a.col_off = p->col_off;
   a.elems = p->elems; a.geom = p->geom; a.n_geom = p->n_geom; a.own_grid = p->own_grid;
   a.lds_loc = p->lds_loc; a.lds_own = p->lds_own; a.lds_elem = p->lds_elem;
+  a.inc = p->inc; a.inc_off = p->inc_off; a.inc_n = p->inc_n;
+  a.gather = p->fem_gather && p->inc ? 1 : 0;
   a.part_dims = p->part_dims; a.box_codes = p->box_codes; a.slot_off = p->slot_off;
   a.slot_k = p->slot_k; a.slot_b = p->slot_b; a.n_slots = p->n_slots; a.lds_box = p->lds_box;
   a.n_part = p->n_part;
@@ -923,6 +929,45 @@ void fem_block(const dd_problem_desc* d, int pb[3]) {
   pb[0] = FEM_PB;
   pb[1] = pb[2] = n8 < 128 ? FEM_PB / 2 : FEM_PB;
 }
+
+// Incidence lists of the element kernel's gather form: per partition, the elements incident to
+// each owned node in the partition's colour order (its element order), entry i of owned node l
+// at off[p] + i * no + l (element index within the partition << 2 | the node's slot), each list
+// padded with 0xFFFF to cnt[p] entries.
+std::string build_incidence(const HostMesh& m, std::vector<uint16_t>& inc, std::vector<int>& off,
+                            std::vector<int>& cnt) {
+  off.assign(m.n_part + 1, 0);
+  cnt.assign(m.n_part, 0);
+  inc.clear();
+  std::vector<std::vector<uint16_t>> lists;
+  for (int p = 0; p < m.n_part; ++p) {
+    const int o0 = m.own_off[p], no = m.own_off[p + 1] - o0;
+    const int cb = m.col_base[p];
+    const int e_beg = m.col_off[cb], e_end = m.col_off[cb + m.ncol[p]];
+    if (e_end - e_beg > (0xFFFF >> 2)) return "too many elements in a partition for the gather form";
+    lists.assign(no, {});
+    size_t mx = 0;
+    for (int e = e_beg; e < e_end; ++e) {
+      const uint64_t w = m.elems[e];
+      for (int k = 0; k < 4; ++k) {
+        const int loc = (int)((w >> (11 * k)) & 0x7FFu);
+        if (loc < no) {
+          lists[loc].push_back((uint16_t)(((e - e_beg) << 2) | k));
+          mx = std::max(mx, lists[loc].size());
+        }
+      }
+    }
+    if (inc.size() + mx * no > (size_t)INT32_MAX) return "incidence lists exceed 2^31 entries";
+    off[p] = (int)inc.size();
+    cnt[p] = (int)mx;
+    inc.resize(inc.size() + mx * no, 0xFFFF);
+    for (int l = 0; l < no; ++l)
+      for (size_t i = 0; i < lists[l].size(); ++i) inc[off[p] + i * no + l] = lists[l][i];
+  }
+  off[m.n_part] = (int)inc.size();
+  return std::string();
+}
+
 }  // namespace
 
 extern "C" {
@@ -955,6 +1000,9 @@ size_t dd_footprint_bytes(const dd_problem_desc* desc, int32_t n_src) {
   // stencil boxes and slots
   b += 4 * (5 * n_part + 2 + n_part * (FEM_COLORS_MAX + 1) + n_part * box) + 8 * n_part * elem;
   b += 4 * 64 * GEOM_STRIDE + 4 * 2 * n_own + 8 * n_own;
+  // the element kernel's incidence lists: an owned node of the Kuhn split lies in at most 24
+  // tetrahedra (2-byte entries, padded per partition), offsets and counts
+  b += 2 * 24 * n_part * (int64_t)pb[0] * pb[1] * pb[2] + 4 * (2 * n_part + 1);
   b += 4 * (4 * n_part + n_part * box) + 4 * STENCIL_SLOTS_MAX * 14;
   b += 4 * 4 * n_own;                     // eps - 1, c1, c2, sigma
   b += 4 * 6 * N;                         // E (2 levels) on the grid
@@ -1095,6 +1143,17 @@ int create_problem(const dd_problem_desc* desc, const MeshInput* gm, dd_alloc_fn
   chk(upload(p, &p->own_grid, m.own_grid));
   chk(upload(p, &p->own_api, m.own_api));
   chk(upload(p, &p->elems, m.elems));
+  if (!p->use_stencil) {
+    // the element kernel's gather form (DD_FEM_GATHER=0: the colour-by-colour scatter)
+    if (const char* e = std::getenv("DD_FEM_GATHER")) p->fem_gather = std::atoi(e) != 0;
+    std::vector<uint16_t> inc;
+    std::vector<int> inc_off, inc_n;
+    if (p->fem_gather && build_incidence(m, inc, inc_off, inc_n).empty()) {
+      chk(upload(p, &p->inc, inc));
+      chk(upload(p, &p->inc_off, inc_off));
+      chk(upload(p, &p->inc_n, inc_n));
+    }
+  }
   chk(upload(p, &p->geom, m.geom));
   chk(upload(p, &p->mass_d, m.mass));
   if (gm) {

@@ -48,6 +48,10 @@ constexpr double LLC_BYTES = 256.0 * 1024 * 1024;
 // FEM partition: a block of at most FEM_PB^3 owned nodes plus its halo.
 constexpr int FEM_PB = 8;          // default block edge; DD_FEM_PB="x,y,z" overrides
 constexpr int FEM_THREADS = 256;
+// gather form of the element kernel: list entries (and their element words) loaded per batch
+#ifndef DD_FEM_GB
+#define DD_FEM_GB 8
+#endif
 // the assembled-stencil FEM part shares launches with the FD tiles: same block size
 constexpr int STENCIL_THREADS = FD_THREADS;
 constexpr int FEM_LOC_MAX = 1024;  // owned + halo nodes per partition (11-bit local ids)
@@ -205,6 +209,12 @@ struct FemArgs {
   const float* geom;    // [n_geom][GEOM_STRIDE]
   int n_geom;
   int lds_loc, lds_own, lds_elem;  // LDS sizing: max local nodes, owned nodes, elements (even)
+  // node-gather form of the element loop: per partition, the elements incident to each owned
+  // node in colour order, entry i of owned node l at inc[inc_off[p] + i * no + l] (element
+  // index within the partition << 2 | the node's slot in it), lists padded with 0xFFFF to
+  // inc_n[p] entries; gather = 1 selects this form, 0 the colour-by-colour scatter
+  const uint16_t* inc; const int* inc_off; const int* inc_n;
+  int gather;
   const int* own_grid;  // grid index for layer-1 owned nodes, -1 otherwise (free)
   const float* em1;     // eps - 1
   const float* c1;      // (a - b) / (a + b)

@@ -345,8 +345,11 @@ __global__ __launch_bounds__(FD_THREADS) void fd_step_kernel(FdArgs a) {
 // ---------------------------------------------------------------------------------------
 // FEM region: lumped-mass P1 on tetrahedra (stiffness + div-div stabiliser of eq.
 // lagrangian_weak).  One workgroup per partition: the partition's owned and halo node
-// values are staged in LDS, elements are evaluated colour by colour and scattered into
-// LDS accumulators of the owned nodes, then owned nodes are advanced.
+// values are staged in LDS, the element terms are summed per owned node, then owned nodes
+// are advanced.  Two forms of the sums: colour by colour, each element scattered into LDS
+// accumulators of its owned nodes with a barrier between colours, or gathered per owned node
+// over its incident elements in the same colour order, in registers and with no barrier (the
+// same sums, bit for bit; faster on the measured meshes, the default).
 //   forward:  (A E)_i = sum_K |K| [grad phi_i . grad(E_c)|_K + d_c phi_i div_K((eps-1) E)]
 //   adjoint:  (A^T l)_i = sum_K |K| grad phi_i . grad(l_c)|_K + (eps_i - 1) q_i,
 //             q_i = sum_K |K| grad phi_i div_K(l)
@@ -356,9 +359,84 @@ __global__ __launch_bounds__(FD_THREADS) void fd_step_kernel(FdArgs a) {
 // Layer-0 values come from the interface buffer written by the finite-difference kernel;
 // layer-1 results are also written into the finite-difference grid (the two-node overlap).
 // ---------------------------------------------------------------------------------------
-// One FEM partition p of the element-coloured step, by a block of FEM_THREADS threads.
-template <bool ADJ, bool ENERGY, bool GEOM_LDS, bool STAGE>
+// Row of owned node l (local id) of a partition's element sums in the gather form: the terms of
+// the elements incident to the node, in the partition's colour order, so that they are the
+// terms of the colour-by-colour scatter added in the same order.  Forward: acc = the node's
+// row of K E + the div-div row of (eps - 1) E; adjoint: acc = the row of K^T lambda without
+// the div-div part, acd = sum over K of |K| grad phi_l div_K lambda (scaled by eps_l - 1 later).
+template <bool ADJ>
+__device__ __forceinline__ void fem_gather_row(const uint16_t* __restrict__ inc, const int ni, const int no,
+                                               const int l, const uint64_t* __restrict__ gE,
+                                               const float* __restrict__ G, const float4* sX, float4& acc,
+                                               float4& acd) {
+  acc = make_float4(0.f, 0.f, 0.f, 0.f);
+  acd = acc;
+  // GB entries and their element words are loaded before the arithmetic of any of them, so
+  // that one batch waits for two memory latencies, not two per element
+  constexpr int GB = DD_FEM_GB;
+  for (int i0 = 0; i0 < ni; i0 += GB) {
+    unsigned ub[GB];
+#pragma unroll
+    for (int b = 0; b < GB; ++b) ub[b] = i0 + b < ni ? (unsigned)inc[(i0 + b) * no + l] : 0xFFFFu;
+    uint64_t wb[GB];
+#pragma unroll
+    for (int b = 0; b < GB; ++b) wb[b] = ub[b] != 0xFFFFu ? gE[ub[b] >> 2] : 0ull;
+#pragma unroll
+    for (int b = 0; b < GB; ++b) {
+      const unsigned u = ub[b];
+      if (u == 0xFFFFu) break;   // a node's list is padded at its end
+      const uint64_t w = wb[b];
+      const int k = (int)(u & 3u);
+      const float* g = G + (int)(w >> 44) * GEOM_STRIDE;
+      const float4* g4 = reinterpret_cast<const float4*>(g);
+      float gr[12];
+#pragma unroll
+      for (int q = 0; q < 3; ++q) {
+        const float4 a4 = g4[q];
+        gr[4 * q] = a4.x; gr[4 * q + 1] = a4.y; gr[4 * q + 2] = a4.z; gr[4 * q + 3] = a4.w;
+      }
+      // |K| grad phi_k of the node's slot
+      const float a0 = g[12 + 3 * k], a1 = g[13 + 3 * k], a2 = g[14 + 3 * k];
+      float Gm[3][3];
+#pragma unroll
+      for (int q = 0; q < 3; ++q)
+#pragma unroll
+        for (int d = 0; d < 3; ++d) Gm[q][d] = 0.f;
+      float dv = 0.f;
+#pragma unroll
+      for (int j = 0; j < 4; ++j) {
+        const float4 x = sX[(int)((w >> (11 * j)) & 0x7FFu)];
+#pragma unroll
+        for (int d = 0; d < 3; ++d) {
+          Gm[0][d] += x.x * gr[3 * j + d];
+          Gm[1][d] += x.y * gr[3 * j + d];
+          Gm[2][d] += x.z * gr[3 * j + d];
+        }
+        const float dj = x.x * gr[3 * j] + x.y * gr[3 * j + 1] + x.z * gr[3 * j + 2];
+        dv += ADJ ? dj : x.w * dj;
+      }
+      if (!ADJ) {
+#pragma unroll
+        for (int q = 0; q < 3; ++q) Gm[q][q] += dv;
+      }
+      acc.x += a0 * Gm[0][0] + a1 * Gm[0][1] + a2 * Gm[0][2];
+      acc.y += a0 * Gm[1][0] + a1 * Gm[1][1] + a2 * Gm[1][2];
+      acc.z += a0 * Gm[2][0] + a1 * Gm[2][1] + a2 * Gm[2][2];
+      if (ADJ) {
+        acd.x += a0 * dv;
+        acd.y += a1 * dv;
+        acd.z += a2 * dv;
+      }
+    }
+    if (ub[GB - 1] == 0xFFFFu) break;
+  }
+}
+
+// One FEM partition p of the element-coloured step, by a block of FEM_THREADS threads
+// (GATHER: the gather form of the element sums).
+template <bool ADJ, bool ENERGY, bool GEOM_LDS, bool STAGE, bool GATHER = false>
 __device__ __forceinline__ void fem_el_part(const FemArgs& a, const int p) {
+  static_assert(!(GATHER && STAGE), "the gather form reads the elements from global memory");
   constexpr int NPT = FEM_OWN_MAX / FEM_THREADS;   // owned nodes per thread in the update
   constexpr int NA4 = ADJ ? 2 : 1;                 // float4 accumulators per owned node
   // Dynamic LDS sized from the mesh.  One float4 per node (E_x, E_y, E_z, eps - 1) and per
@@ -367,7 +445,8 @@ __device__ __forceinline__ void fem_el_part(const FemArgs& a, const int p) {
   // the packed elements are staged in LDS too (8 B each); otherwise each colour reads them
   // from global memory, and a block needs less LDS, so that more blocks share a CU.
   extern __shared__ __align__(16) unsigned char lds[];
-  const int LOC = a.lds_loc, ROW = a.lds_own + 32;
+  // GATHER: the sums stay in registers, no accumulator rows
+  const int LOC = a.lds_loc, ROW = GATHER ? 0 : a.lds_own + 32;
   float4* sX = reinterpret_cast<float4*>(lds);                // [LOC]
   float4* sA = sX + LOC;                                      // [NA4][ROW]
   uint64_t* sE = reinterpret_cast<uint64_t*>(sA + NA4 * ROW);  // [lds_elem] (even), if STAGE
@@ -436,7 +515,7 @@ __device__ __forceinline__ void fem_el_part(const FemArgs& a, const int p) {
       if (l < nl) sX[l] = xv[k];
     }
   }
-  for (int l = tid; l < ROW; l += FEM_THREADS) {
+  for (int l = tid; l < ROW; l += FEM_THREADS) {   // (no rows in the gather form)
 #pragma unroll
     for (int c = 0; c < NA4; ++c) sA[c * ROW + l] = make_float4(0.f, 0.f, 0.f, 0.f);
   }
@@ -468,7 +547,7 @@ __device__ __forceinline__ void fem_el_part(const FemArgs& a, const int p) {
   // ---- elements, colour by colour (no two elements of a colour share an owned node)
   const float* __restrict__ G = GEOM_LDS ? sG : a.geom;
   const int trash = a.lds_own + (tid & 31);
-  for (int c = 0; c < ncl; ++c) {
+  for (int c = 0; c < (GATHER ? 0 : ncl); ++c) {
     const int e0 = sC[c], e1 = sC[c + 1];
     for (int e = e0 + tid; e < e1; e += FEM_THREADS) {
       const uint64_t w = gE[e];
@@ -550,8 +629,14 @@ __device__ __forceinline__ void fem_el_part(const FemArgs& a, const int p) {
     const int l = tid + j * FEM_THREADS;
     if (l >= no) continue;
     const int id = o0 + l;
-    const float4 x4 = sX[l], s4 = sA[l];
-    const float4 d4 = ADJ ? sA[ROW + l] : make_float4(0.f, 0.f, 0.f, 0.f);
+    const float4 x4 = sX[l];
+    float4 s4, d4;
+    if (GATHER) {
+      fem_gather_row<ADJ>(a.inc + a.inc_off[p], a.inc_n[p], no, l, a.elems + e_beg, G, sX, s4, d4);
+    } else {
+      s4 = sA[l];
+      d4 = ADJ ? sA[ROW + l] : make_float4(0.f, 0.f, 0.f, 0.f);
+    }
     const float xo[3] = {x4.x, x4.y, x4.z};
     const float q[3] = {d4.x, d4.y, d4.z};
     float r[3] = {s4.x, s4.y, s4.z};
@@ -618,9 +703,9 @@ __device__ __forceinline__ void fem_el_part(const FemArgs& a, const int p) {
   }
 }
 
-template <bool ADJ, bool ENERGY, bool GEOM_LDS, bool STAGE>
+template <bool ADJ, bool ENERGY, bool GEOM_LDS, bool STAGE, bool GATHER>
 __global__ __launch_bounds__(FEM_THREADS) void fem_step_kernel(FemArgs a) {
-  fem_el_part<ADJ, ENERGY, GEOM_LDS, STAGE>(a, blockIdx.x);
+  fem_el_part<ADJ, ENERGY, GEOM_LDS, STAGE, GATHER>(a, blockIdx.x);
 }
 
 // ---------------------------------------------------------------------------------------
@@ -883,14 +968,14 @@ __global__ __launch_bounds__(FD_THREADS) void step_kernel(FdArgs fa, FemArgs ea,
 
 // The same fused step on a general mesh: the FEM partitions run the element-coloured code
 // (elements read from global memory, so that a block's LDS stays small enough for the
-// finite-difference tiles of the same launch to share the CUs).
-template <bool ADJ, bool ENERGY, bool NT, bool OBL, bool GEOM_LDS>
+// finite-difference tiles of the same launch to share the CUs; GATHER: the gather form).
+template <bool ADJ, bool ENERGY, bool NT, bool OBL, bool GEOM_LDS, bool GATHER>
 __global__ __launch_bounds__(FD_THREADS) void step_kernel_el(FdArgs fa, FemArgs ea, int fem_blocks) {
   static_assert(FD_THREADS == FEM_THREADS, "one block size for both parts");
   const int b = blockIdx.x;
   if (b < fem_blocks) {
     const int p = fem_part_of_block(b, fem_blocks, ea.rev);
-    if (p < ea.n_part) fem_el_part<ADJ, ENERGY, GEOM_LDS, false>(ea, p);
+    if (p < ea.n_part) fem_el_part<ADJ, ENERGY, GEOM_LDS, false, GATHER>(ea, p);
     return;
   }
   fd_tile<ENERGY, NT, OBL, true>(fa, b - fem_blocks);
@@ -1524,7 +1609,8 @@ void launch_fd(const FdArgs& a, hipStream_t s, bool energy, bool nt) {
 
 size_t fem_lds_bytes(const FemArgs& a, bool adj, bool stage) {
   const bool geom_lds = a.n_geom <= FEM_GEOM_LDS;
-  size_t f = (size_t)a.lds_loc * 4 + (size_t)(adj ? 8 : 4) * (a.lds_own + 32);
+  // node values; the scatter form's accumulator rows (the gather form sums in registers)
+  size_t f = (size_t)a.lds_loc * 4 + (a.gather ? 0 : (size_t)(adj ? 8 : 4) * (a.lds_own + 32));
   f += (stage ? (size_t)a.lds_elem * 2 : 0) + (geom_lds ? (size_t)a.n_geom * GEOM_STRIDE : 0);
   f += FEM_COLORS_MAX + 1;   // colour offsets
   return f * 4;
@@ -1542,19 +1628,27 @@ int device_cus() {
   return cus;
 }
 
-template <bool ADJ, bool ENERGY, bool GEOM, bool STAGE>
+template <bool ADJ, bool ENERGY, bool GEOM, bool STAGE, bool GATHER = false>
 void launch_fem_v(const FemArgs& a, int n_part, size_t lds, hipStream_t s) {
   if (lds > 65536)
-    (void)hipFuncSetAttribute((const void*)fem_step_kernel<ADJ, ENERGY, GEOM, STAGE>,
+    (void)hipFuncSetAttribute((const void*)fem_step_kernel<ADJ, ENERGY, GEOM, STAGE, GATHER>,
                               hipFuncAttributeMaxDynamicSharedMemorySize, (int)lds);
-  hipLaunchKernelGGL((fem_step_kernel<ADJ, ENERGY, GEOM, STAGE>), dim3(n_part), dim3(FEM_THREADS), lds, s, a);
+  hipLaunchKernelGGL((fem_step_kernel<ADJ, ENERGY, GEOM, STAGE, GATHER>), dim3(n_part), dim3(FEM_THREADS), lds, s,
+                     a);
 }
 }  // namespace
 
 // The elements are staged in LDS when the partitions then still run in one round of blocks
 // (160 KB of LDS per CU); otherwise they are read from global memory and more blocks share a CU.
+// The gather form reads the elements from global memory.
 template <bool ADJ, bool ENERGY>
 static void launch_fem_t(const FemArgs& a, int n_part, hipStream_t s) {
+  if (a.gather) {
+    const size_t lds = fem_lds_bytes(a, ADJ, false);
+    if (a.n_geom <= FEM_GEOM_LDS) launch_fem_v<ADJ, ENERGY, true, false, true>(a, n_part, lds, s);
+    else launch_fem_v<ADJ, ENERGY, false, false, true>(a, n_part, lds, s);
+    return;
+  }
   constexpr size_t LDS_CU = 160 * 1024;
   const size_t staged = fem_lds_bytes(a, ADJ, true);
   const bool stage = (int64_t)n_part <= (int64_t)(LDS_CU / staged) * device_cus();
@@ -1681,34 +1775,42 @@ void launch_step(const FdArgs& fa, const FemArgs& ea, hipStream_t s, bool adj, b
     launch_step_t<false>(fa, ea, s, adj, energy, pg);
 }
 
-template <bool NT, bool GEOM>
+template <bool NT, bool GEOM, bool GATHER>
 static void launch_step_el_t(const FdArgs& fa, const FemArgs& ea, hipStream_t s, bool adj, bool energy) {
   const int fem_blocks = (ea.n_part + N_XCD - 1) / N_XCD * N_XCD;   // keeps FD blocks XCD-aligned
   const dim3 grid(fem_blocks + fa.per_xcd * N_XCD);
   const size_t lds = std::max(fem_lds_bytes(ea, adj, false), FD_DYN_LDS_BYTES);
   if (adj)
-    hipLaunchKernelGGL((step_kernel_el<true, false, NT, false, GEOM>), grid, dim3(FD_THREADS), lds, s, fa, ea,
+    hipLaunchKernelGGL((step_kernel_el<true, false, NT, false, GEOM, GATHER>), grid, dim3(FD_THREADS), lds, s, fa, ea,
                        fem_blocks);
   else if (fa.pw_kind && energy)
-    hipLaunchKernelGGL((step_kernel_el<false, true, NT, true, GEOM>), grid, dim3(FD_THREADS), lds, s, fa, ea,
+    hipLaunchKernelGGL((step_kernel_el<false, true, NT, true, GEOM, GATHER>), grid, dim3(FD_THREADS), lds, s, fa, ea,
                        fem_blocks);
   else if (fa.pw_kind)
-    hipLaunchKernelGGL((step_kernel_el<false, false, NT, true, GEOM>), grid, dim3(FD_THREADS), lds, s, fa, ea,
+    hipLaunchKernelGGL((step_kernel_el<false, false, NT, true, GEOM, GATHER>), grid, dim3(FD_THREADS), lds, s, fa, ea,
                        fem_blocks);
   else if (energy)
-    hipLaunchKernelGGL((step_kernel_el<false, true, NT, false, GEOM>), grid, dim3(FD_THREADS), lds, s, fa, ea,
+    hipLaunchKernelGGL((step_kernel_el<false, true, NT, false, GEOM, GATHER>), grid, dim3(FD_THREADS), lds, s, fa, ea,
                        fem_blocks);
   else
-    hipLaunchKernelGGL((step_kernel_el<false, false, NT, false, GEOM>), grid, dim3(FD_THREADS), lds, s, fa, ea,
+    hipLaunchKernelGGL((step_kernel_el<false, false, NT, false, GEOM, GATHER>), grid, dim3(FD_THREADS), lds, s, fa, ea,
                        fem_blocks);
 }
 
-void launch_step_el(const FdArgs& fa, const FemArgs& ea, hipStream_t s, bool adj, bool energy, bool nt) {
+template <bool GATHER>
+static void launch_step_el_g(const FdArgs& fa, const FemArgs& ea, hipStream_t s, bool adj, bool energy, bool nt) {
   const bool geom = ea.n_geom <= FEM_GEOM_LDS;
-  if (nt && geom) launch_step_el_t<true, true>(fa, ea, s, adj, energy);
-  else if (nt) launch_step_el_t<true, false>(fa, ea, s, adj, energy);
-  else if (geom) launch_step_el_t<false, true>(fa, ea, s, adj, energy);
-  else launch_step_el_t<false, false>(fa, ea, s, adj, energy);
+  if (nt && geom) launch_step_el_t<true, true, GATHER>(fa, ea, s, adj, energy);
+  else if (nt) launch_step_el_t<true, false, GATHER>(fa, ea, s, adj, energy);
+  else if (geom) launch_step_el_t<false, true, GATHER>(fa, ea, s, adj, energy);
+  else launch_step_el_t<false, false, GATHER>(fa, ea, s, adj, energy);
+}
+
+void launch_step_el(const FdArgs& fa, const FemArgs& ea, hipStream_t s, bool adj, bool energy, bool nt) {
+  if (ea.gather)
+    launch_step_el_g<true>(fa, ea, s, adj, energy, nt);
+  else
+    launch_step_el_g<false>(fa, ea, s, adj, energy, nt);
 }
 
 void launch_energy_reduce(const double* part, int n, double* out, hipStream_t s) {

@@ -107,6 +107,38 @@ def test_refined_mesh_matches_oracle(name, beta):
     p.close()
 
 
+@pytest.mark.parametrize("name,beta,fused", [("ragged", 0.6, "1"), ("ragged", 0.6, "0"), ("skinlet", 0.3, "1")])
+def test_gather_form_equals_the_colour_scatter(name, beta, fused, monkeypatch):
+    """The element kernel's node-gather form sums, per owned node, the same element terms in the
+    same (colour) order as the colour-by-colour scatter, so traces, energies and gradients agree
+    to the rounding of the two codes' multiply-add contractions.  Fused steps and separate FEM
+    launches; K = 7 so that the adjoint recomputes segments with the FEM-only launches."""
+    import torch
+    w, marks, mesh, eps, sig = _refined(name, beta)
+    w.desc.ckpt_every = 7
+    monkeypatch.setenv("DD_FUSED", fused)
+    out = []
+    for g in ("0", "1"):
+        monkeypatch.setenv("DD_FEM_GATHER", g)
+        print(f"[gpu] gather {g} against scatter: {name} beta {beta} fused {fused}", flush=True)
+        p = _problem(torch, w, mesh, eps, sig)
+        if not out:
+            obs = torch.tensor(1e-3 * synth.noise((1, w.desc.n_steps, p.n_det, 3), 5), dtype=torch.float32,
+                               device="cuda")
+        tr = p.forward(w.sources, save=True).clone()
+        p.adjoint_misfit(tr, obs)
+        ge, gs = (g_.cpu().numpy() for g_ in p.gradient())
+        _, en = p.forward(w.sources, save=False, energy=True)
+        out.append((tr.cpu().numpy(), en.cpu().numpy(), ge, gs))
+        p.close()
+    errs = [_rel(b, a) for a, b in zip(*out)]
+    same = [bool(np.array_equal(a, b)) for a, b in zip(*out)]
+    print(f"[gpu]   traces {errs[0]:.2e} energy {errs[1]:.2e} g_eps {errs[2]:.2e} g_sigma {errs[3]:.2e}; "
+          f"bit-identical {same}", flush=True)
+    assert errs[0] <= 1e-6 and errs[1] <= 1e-6
+    assert errs[2] <= 1e-5 and errs[3] <= 1e-5
+
+
 def test_kuhn_split_as_a_general_mesh_matches_the_default_path():
     """No cell marked: the caller's mesh is the Kuhn split, so traces and gradient equal those of
     the default problem up to the order of the float32 sums (other partitions and colours)."""

@@ -302,13 +302,16 @@ def test_autograd_refuses_a_stale_saved_forward(torch_cuda):
     assert torch.allclose(sig.grad, 2 * sig1.grad, rtol=1e-6, atol=0)
 
 
+@pytest.mark.parametrize("gather", ["1", "0"])
 @pytest.mark.parametrize("name", ["ragged", "skinlet"])
-def test_element_colored_fem_path(torch_cuda, name, monkeypatch):
-    """The element-colored FEM kernel (general tetrahedral meshes) against the oracle."""
+def test_element_colored_fem_path(torch_cuda, name, gather, monkeypatch):
+    """The element-colored FEM kernel (general tetrahedral meshes) against the oracle, in its
+    node-gather form (default) and its colour-by-colour scatter form."""
     torch = torch_cuda
     monkeypatch.setenv("DD_FEM_PATH", "element")
+    monkeypatch.setenv("DD_FEM_GATHER", gather)
     w = synth.small(name)
-    print(f"[gpu] element path {name}", flush=True)
+    print(f"[gpu] element path {name} gather {gather}", flush=True)
     d = _oracle(w)
     fw = forward(d, w.sources[0])
     cot = (0.3 * fw["traces"]).astype(np.float32)
