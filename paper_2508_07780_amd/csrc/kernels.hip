@@ -349,7 +349,7 @@ __global__ __launch_bounds__(FD_THREADS) void fd_step_kernel(FdArgs a) {
 // are advanced.  Two forms of the sums: colour by colour, each element scattered into LDS
 // accumulators of its owned nodes with a barrier between colours, or gathered per owned node
 // over its incident elements in the same colour order, in registers and with no barrier (the
-// same sums, bit for bit; faster on the measured meshes, the default).
+// same sums up to rounding; faster on the measured meshes, the default).
 //   forward:  (A E)_i = sum_K |K| [grad phi_i . grad(E_c)|_K + d_c phi_i div_K((eps-1) E)]
 //   adjoint:  (A^T l)_i = sum_K |K| grad phi_i . grad(l_c)|_K + (eps_i - 1) q_i,
 //             q_i = sum_K |K| grad phi_i div_K(l)
@@ -360,8 +360,9 @@ __global__ __launch_bounds__(FD_THREADS) void fd_step_kernel(FdArgs a) {
 // layer-1 results are also written into the finite-difference grid (the two-node overlap).
 // ---------------------------------------------------------------------------------------
 // Row of owned node l (local id) of a partition's element sums in the gather form: the terms of
-// the elements incident to the node, in the partition's colour order, so that they are the
-// terms of the colour-by-colour scatter added in the same order.  Forward: acc = the node's
+// the elements incident to the node, in the partition's colour order (the scatter's order; each
+// term is formed through the element's stiffness entries of the node's row instead of the
+// element's full gradient, so the two forms agree to rounding).  Forward: acc = the node's
 // row of K E + the div-div row of (eps - 1) E; adjoint: acc = the row of K^T lambda without
 // the div-div part, acd = sum over K of |K| grad phi_l div_K lambda (scaled by eps_l - 1 later).
 template <bool ADJ>
@@ -397,31 +398,27 @@ __device__ __forceinline__ void fem_gather_row(const uint16_t* __restrict__ inc,
       }
       // |K| grad phi_k of the node's slot
       const float a0 = g[12 + 3 * k], a1 = g[13 + 3 * k], a2 = g[14 + 3 * k];
-      float Gm[3][3];
-#pragma unroll
-      for (int q = 0; q < 3; ++q)
-#pragma unroll
-        for (int d = 0; d < 3; ++d) Gm[q][d] = 0.f;
-      float dv = 0.f;
+      // the node's row through the element's stiffness entries s_j = |K| grad phi_k . grad phi_j:
+      // sum_j s_j E_j (+ |K| grad phi_k div_K((eps - 1) E) forward); dv = div_K of (eps-1)E or lambda
+      float c0 = 0.f, c1 = 0.f, c2 = 0.f, dv = 0.f;
 #pragma unroll
       for (int j = 0; j < 4; ++j) {
         const float4 x = sX[(int)((w >> (11 * j)) & 0x7FFu)];
-#pragma unroll
-        for (int d = 0; d < 3; ++d) {
-          Gm[0][d] += x.x * gr[3 * j + d];
-          Gm[1][d] += x.y * gr[3 * j + d];
-          Gm[2][d] += x.z * gr[3 * j + d];
-        }
+        const float sj = a0 * gr[3 * j] + a1 * gr[3 * j + 1] + a2 * gr[3 * j + 2];
+        c0 += sj * x.x;
+        c1 += sj * x.y;
+        c2 += sj * x.z;
         const float dj = x.x * gr[3 * j] + x.y * gr[3 * j + 1] + x.z * gr[3 * j + 2];
         dv += ADJ ? dj : x.w * dj;
       }
       if (!ADJ) {
-#pragma unroll
-        for (int q = 0; q < 3; ++q) Gm[q][q] += dv;
+        c0 += a0 * dv;
+        c1 += a1 * dv;
+        c2 += a2 * dv;
       }
-      acc.x += a0 * Gm[0][0] + a1 * Gm[0][1] + a2 * Gm[0][2];
-      acc.y += a0 * Gm[1][0] + a1 * Gm[1][1] + a2 * Gm[1][2];
-      acc.z += a0 * Gm[2][0] + a1 * Gm[2][1] + a2 * Gm[2][2];
+      acc.x += c0;
+      acc.y += c1;
+      acc.z += c2;
       if (ADJ) {
         acd.x += a0 * dv;
         acd.y += a1 * dv;

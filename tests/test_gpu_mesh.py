@@ -110,8 +110,10 @@ def test_refined_mesh_matches_oracle(name, beta):
 @pytest.mark.parametrize("name,beta,fused", [("ragged", 0.6, "1"), ("ragged", 0.6, "0"), ("skinlet", 0.3, "1")])
 def test_gather_form_equals_the_colour_scatter(name, beta, fused, monkeypatch):
     """The element kernel's node-gather form sums, per owned node, the same element terms in the
-    same (colour) order as the colour-by-colour scatter, so traces, energies and gradients agree
-    to the rounding of the two codes' multiply-add contractions.  Fused steps and separate FEM
+    same (colour) order as the colour-by-colour scatter, each term formed through the element's
+    stiffness entries of the node's row rather than its full gradient: traces, energies and
+    gradients agree to FP32 rounding, bounded here by twice what either form shows against the
+    FP64 oracle on these meshes (traces 1.4e-6, gradients 9.5e-6).  Fused steps and separate FEM
     launches; K = 7 so that the adjoint recomputes segments with the FEM-only launches."""
     import torch
     w, marks, mesh, eps, sig = _refined(name, beta)
@@ -135,8 +137,8 @@ def test_gather_form_equals_the_colour_scatter(name, beta, fused, monkeypatch):
     same = [bool(np.array_equal(a, b)) for a, b in zip(*out)]
     print(f"[gpu]   traces {errs[0]:.2e} energy {errs[1]:.2e} g_eps {errs[2]:.2e} g_sigma {errs[3]:.2e}; "
           f"bit-identical {same}", flush=True)
-    assert errs[0] <= 1e-6 and errs[1] <= 1e-6
-    assert errs[2] <= 1e-5 and errs[3] <= 1e-5
+    assert errs[0] <= 3e-6 and errs[1] <= 3e-6
+    assert errs[2] <= 2e-5 and errs[3] <= 2e-5
 
 
 def test_kuhn_split_as_a_general_mesh_matches_the_default_path():
