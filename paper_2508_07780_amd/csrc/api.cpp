@@ -1054,6 +1054,7 @@ int create_problem(const dd_problem_desc* desc, const MeshInput* gm, dd_alloc_fn
   HostMesh m;
   int pb[3];
   fem_block(desc, pb);
+  if (gm) pb[0] = pb[1] = pb[2] = FEM_PB;   // a caller mesh: lattice blocks of 8^3 cells by default
   if (const char* e = std::getenv("DD_FEM_PB")) {
     int x = 0, y = 0, z = 0;
     if (std::sscanf(e, "%d,%d,%d", &x, &y, &z) == 3) { pb[0] = x; pb[1] = y; pb[2] = z; }
@@ -1061,7 +1062,7 @@ int create_problem(const dd_problem_desc* desc, const MeshInput* gm, dd_alloc_fn
   bool element_path = gm != nullptr;   // the element-coloured FEM kernel instead of the assembled stencil
   if (const char* e = std::getenv("DD_FEM_PATH"))
     if (std::strcmp(e, "element") == 0) element_path = true;
-  const std::string me = gm ? build_mesh_general(*desc, gm->n_extra, gm->xyz, gm->n_tets, gm->tets, m)
+  const std::string me = gm ? build_mesh_general(*desc, gm->n_extra, gm->xyz, gm->n_tets, gm->tets, m, pb)
                             : build_mesh(*desc, m, pb, element_path);
   if (!me.empty()) {
     delete p;

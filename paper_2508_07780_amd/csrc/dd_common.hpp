@@ -333,9 +333,10 @@ struct HostMesh {
 // the error text.
 std::string build_mesh(const dd_problem_desc& d, HostMesh& m, const int pb[3], bool elements);
 // General tetrahedral mesh of the FEM box (lattice nodes, then n_extra nodes at xyz strictly
-// inside the box; n_tets tetrahedra in those indices), for the element kernel.  Empty string on
-// success, else the error text.
+// inside the box; n_tets tetrahedra in those indices), for the element kernel, its owned nodes
+// grouped by lattice blocks of pb[0] x pb[1] x pb[2] cells.  Empty string on success, else the
+// error text.
 std::string build_mesh_general(const dd_problem_desc& d, int64_t n_extra, const double* xyz, int64_t n_tets,
-                               const int32_t* tets, HostMesh& m);
+                               const int32_t* tets, HostMesh& m, const int pb[3]);
 
 }  // namespace dd

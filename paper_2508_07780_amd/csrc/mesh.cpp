@@ -515,7 +515,8 @@ extern "C" int dd_debug_fem_apply_mesh(const dd_problem_desc* d, int64_t n_extra
                                        int flags, double* out, int64_t* stats) {
   if (!d || !eps || !E || !out || (flags & 2)) return DD_ERR_INVALID_ARG;
   dd::HostMesh m;
-  if (!dd::build_mesh_general(*d, n_extra, extra_xyz, n_tets, tets, m).empty()) return DD_ERR_UNSUPPORTED;
+  const int pb[3] = {dd::FEM_PB, dd::FEM_PB, dd::FEM_PB};
+  if (!dd::build_mesh_general(*d, n_extra, extra_xyz, n_tets, tets, m, pb).empty()) return DD_ERR_UNSUPPORTED;
   return debug_apply(d, m, eps, E, flags, out, stats);
 }
 
@@ -528,7 +529,7 @@ namespace dd {
 // limits is cut at the median of its nodes, recursively.  Everything else is built as for the
 // Kuhn split's element path.
 std::string build_mesh_general(const dd_problem_desc& d, int64_t n_extra, const double* xyz, int64_t n_tets,
-                               const int32_t* tv, HostMesh& m) {
+                               const int32_t* tv, HostMesh& m, const int pb[3]) {
   Lattice L;
   for (int a = 0; a < 3; ++a) {
     L.c[a] = d.fem_cells[a];
@@ -616,22 +617,21 @@ std::string build_mesh_general(const dd_problem_desc& d, int64_t n_extra, const 
   m.stencil_ok = false;
   m.n_slots = 0;
 
-  // partitions: owned nodes by lattice blocks of 8^3 (an extra node joins the block of the
+  // partitions: owned nodes by lattice blocks of pb cells (an extra node joins the block of the
   // cell it lies in, by its cell's lower corner); a block that exceeds the element kernel's
   // limits (owned, local nodes, elements, colours) is cut in two at the median of its nodes
   // along its longest extent, recursively, lower half first
   std::vector<std::vector<int64_t>> members;
   {
-    constexpr int pb = FEM_PB;
     const int ow[3] = {L.c[0] - 1, L.c[1] - 1, L.c[2] - 1};
     int npb[3];
-    for (int a = 0; a < 3; ++a) npb[a] = (ow[a] + pb - 1) / pb;
+    for (int a = 0; a < 3; ++a) npb[a] = (ow[a] + pb[a] - 1) / pb[a];
     auto block_of = [&](const std::array<double, 3>& q) {
       int b[3];
       for (int a = 0; a < 3; ++a) {
         int c = (int)std::floor(q[a]);
         c = std::min(std::max(c, 1), L.c[a] - 1);
-        b[a] = (c - 1) / pb;
+        b[a] = (c - 1) / pb[a];
       }
       return b[0] + npb[0] * (b[1] + npb[1] * b[2]);
     };
