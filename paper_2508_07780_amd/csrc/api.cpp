@@ -1000,9 +1000,11 @@ size_t dd_footprint_bytes(const dd_problem_desc* desc, int32_t n_src) {
   // stencil boxes and slots
   b += 4 * (5 * n_part + 2 + n_part * (FEM_COLORS_MAX + 1) + n_part * box) + 8 * n_part * elem;
   b += 4 * 64 * GEOM_STRIDE + 4 * 2 * n_own + 8 * n_own;
-  // the element kernel's incidence lists: an owned node of the Kuhn split lies in at most 24
-  // tetrahedra (2-byte entries, padded per partition), offsets and counts
-  b += 2 * 24 * n_part * (int64_t)pb[0] * pb[1] * pb[2] + 4 * (2 * n_part + 1);
+  // the element kernel's incidence lists, on the element path only (DD_FEM_PATH=element, as
+  // dd_create reads it): an owned node of the Kuhn split lies in at most 24 tetrahedra (2-byte
+  // entries, padded per partition), offsets and counts
+  if (const char* e = std::getenv("DD_FEM_PATH"))
+    if (std::strcmp(e, "element") == 0) b += 2 * 24 * n_part * (int64_t)pb[0] * pb[1] * pb[2] + 4 * (2 * n_part + 1);
   b += 4 * (4 * n_part + n_part * box) + 4 * STENCIL_SLOTS_MAX * 14;
   b += 4 * 4 * n_own;                     // eps - 1, c1, c2, sigma
   b += 4 * 6 * N;                         // E (2 levels) on the grid
