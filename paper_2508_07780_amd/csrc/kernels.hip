@@ -966,8 +966,10 @@ __global__ __launch_bounds__(FD_THREADS) void step_kernel(FdArgs fa, FemArgs ea,
 // The same fused step on a general mesh: the FEM partitions run the element-coloured code
 // (elements read from global memory, so that a block's LDS stays small enough for the
 // finite-difference tiles of the same launch to share the CUs; GATHER: the gather form).
+// Held to 5 waves per SIMD (at most 96 VGPRs): the adjoint's element sums would otherwise take
+// about 105 and leave the FD tiles of the same launch 4 waves.
 template <bool ADJ, bool ENERGY, bool NT, bool OBL, bool GEOM_LDS, bool GATHER>
-__global__ __launch_bounds__(FD_THREADS) void step_kernel_el(FdArgs fa, FemArgs ea, int fem_blocks) {
+__global__ __launch_bounds__(FD_THREADS, 5) void step_kernel_el(FdArgs fa, FemArgs ea, int fem_blocks) {
   static_assert(FD_THREADS == FEM_THREADS, "one block size for both parts");
   const int b = blockIdx.x;
   if (b < fem_blocks) {
